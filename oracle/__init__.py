@@ -1,0 +1,254 @@
+"""ctypes front end of the FP64 CPU oracle (``oracle/obk_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+CPU-baseline leg of ``bench.py``; never by the library.  It shares no code
+with the HIP path.  Each function states the step of the paper it follows;
+the C file carries the details of every step.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "obk_oracle.c")
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f64 = ctypes.c_double
+_p = ctypes.c_void_p
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    from .build import build as _b
+    return _b(force=force)
+
+
+def lib():
+    """The compiled oracle.  OBK_ORACLE_LIB names another build of the same
+    source (the mutation tests load deliberately broken copies this way)."""
+    global _lib
+    if _lib is None:
+        path = os.environ.get("OBK_ORACLE_LIB", LIB_PATH)
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(path)
+        L.orc_validate.restype = ctypes.c_int
+        L.orc_validate.argtypes = [_i64, _p, _p, _p, _p]
+        L.orc_rcm.restype = ctypes.c_int
+        L.orc_rcm.argtypes = [_i64, _p, _p, _p]
+        L.orc_permute.restype = ctypes.c_int
+        L.orc_permute.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_norms.restype = None
+        L.orc_norms.argtypes = [_i64, _p, _p, _p, _p]
+        L.orc_cosine.restype = _f64
+        L.orc_cosine.argtypes = [_i64, _i64, _p, _p, _p, _p]
+        L.orc_conflicts.restype = _i64
+        L.orc_conflicts.argtypes = [_i64, _p, _p, _p, _p, _f64, _p, _p]
+        L.orc_groups.restype = _i32
+        L.orc_groups.argtypes = [_i64, _p, _p, _p, _p]
+        L.orc_pairs.restype = ctypes.c_int
+        L.orc_pairs.argtypes = [_i64, _p, _p, _p, _p, _f64, _p]
+        L.orc_sweep.restype = ctypes.c_int
+        L.orc_sweep.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64]
+        L.orc_rowwise.restype = None
+        L.orc_rowwise.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i64, _p]
+        L.orc_relres.restype = _f64
+        L.orc_relres.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
+        L.orc_unpermute.restype = None
+        L.orc_unpermute.argtypes = [_i64, _p, _p, _p]
+        L.orc_permute_vec.restype = None
+        L.orc_permute_vec.argtypes = [_i64, _p, _p, _p]
+        L.orc_refine.restype = _i64
+        L.orc_refine.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64, _i64, _f64, _p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def validate(n, rp, ci, v, f=None) -> int:
+    """O1 (square CSR, columns in range, no duplicates, finite). 0 = valid."""
+    rp, ci, v = _c(rp, np.int64), _c(ci, np.int32), _c(v, np.float64)
+    f = None if f is None else _c(f, np.float64)
+    return lib().orc_validate(n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(f))
+
+
+def rcm(n, rp, ci) -> np.ndarray:
+    """O2-O3: reverse Cuthill-McKee permutation p (new -> old), Section 3.2."""
+    rp, ci = _c(rp, np.int64), _c(ci, np.int32)
+    p = np.empty(n, dtype=np.int32)
+    rc = lib().orc_rcm(n, _ptr(rp), _ptr(ci), _ptr(p))
+    if rc != 0:
+        raise RuntimeError(f"orc_rcm failed: {rc}")
+    return p
+
+
+def permute(n, rp, ci, v, f, p):
+    """O4: A~ = P A P^T with sorted rows, f~ = P f (eqs. 3.1-3.2)."""
+    rp, ci, v = _c(rp, np.int64), _c(ci, np.int32), _c(v, np.float64)
+    f = _c(f, np.float64)
+    p = _c(p, np.int32)
+    nnz = int(rp[n])
+    trp = np.empty(n + 1, np.int64)
+    tci = np.empty(nnz, np.int32)
+    tv = np.empty(nnz, np.float64)
+    tf = np.empty(n, np.float64)
+    rc = lib().orc_permute(n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(f), _ptr(p), _ptr(trp), _ptr(tci),
+                           _ptr(tv), _ptr(tf))
+    if rc != 0:
+        raise RuntimeError(f"orc_permute failed: {rc}")
+    return trp, tci, tv, tf
+
+
+def norms(n, rp, v):
+    """O5: nu_i = ||a_i||^2 (denominator of eq. 1.2), inv_i = 1/nu_i."""
+    rp, v = _c(rp, np.int64), _c(v, np.float64)
+    nu = np.empty(n, np.float64)
+    inv = np.empty(n, np.float64)
+    lib().orc_norms(n, _ptr(rp), _ptr(v), _ptr(nu), _ptr(inv))
+    return nu, inv
+
+
+def cosine(i, j, rp, ci, v, nu) -> float:
+    """O6: |cos| of the angle between rows i and j (cosine table of Section 3.3)."""
+    return lib().orc_cosine(int(i), int(j), _ptr(rp), _ptr(ci), _ptr(v), _ptr(nu))
+
+
+def conflicts(n, rp, ci, v, nu, delta):
+    """O6: for each row i the rows j < i with |cos_ij| >= delta (CSR form)."""
+    rp, ci, v, nu = _c(rp, np.int64), _c(ci, np.int32), _c(v, np.float64), _c(nu, np.float64)
+    cptr = np.empty(n + 1, np.int64)
+    total = lib().orc_conflicts(n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(nu), float(delta), _ptr(cptr), None)
+    if total < 0:
+        raise RuntimeError(f"orc_conflicts failed: {total}")
+    cidx = np.empty(max(total, 1), np.int32)
+    total2 = lib().orc_conflicts(n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(nu), float(delta), _ptr(cptr),
+                                 _ptr(cidx))
+    assert total2 == total
+    return cptr, cidx[:total]
+
+
+def groups(n, nu, cptr, cidx):
+    """O7: first-fit grouping (maximal Oclass/Nclass of Section 3.3)."""
+    nu, cptr, cidx = _c(nu, np.float64), _c(cptr, np.int64), _c(cidx, np.int32)
+    if cidx.size == 0:
+        cidx = np.zeros(1, np.int32)
+    g = np.empty(n, np.int32)
+    ng = lib().orc_groups(n, _ptr(nu), _ptr(cptr), _ptr(cidx), _ptr(g))
+    if ng < 0:
+        raise RuntimeError(f"orc_groups failed: {ng}")
+    return g, int(ng)
+
+
+def pairs(n, rp, ci, v, nu, delta):
+    """Literal pair rule of Section 3.3: partner of each row, -1 Nclass, -2 zero row."""
+    rp, ci, v, nu = _c(rp, np.int64), _c(ci, np.int32), _c(v, np.float64), _c(nu, np.float64)
+    out = np.empty(n, np.int32)
+    lib().orc_pairs(n, _ptr(rp), _ptr(ci), _ptr(v), _ptr(nu), float(delta), _ptr(out))
+    return out
+
+
+@dataclasses.dataclass
+class Plan:
+    n: int
+    p: np.ndarray          # new -> old
+    rp: np.ndarray
+    ci: np.ndarray
+    v: np.ndarray
+    f: np.ndarray          # permuted right-hand side
+    nu: np.ndarray
+    inv: np.ndarray
+    cptr: np.ndarray
+    cidx: np.ndarray
+    group: np.ndarray      # group of each reordered row (-1: zero row)
+    ngroups: int
+
+
+def plan(n, rp, ci, v, f, delta, *, use_rcm: bool = True) -> Plan:
+    """Algorithm 4, first four steps, with one-row blocks: RCM, reorder,
+    norms, cosine conflicts, grouping."""
+    if validate(n, rp, ci, v, f) != 0:
+        raise ValueError("invalid system")
+    p = rcm(n, rp, ci) if use_rcm else np.arange(n, dtype=np.int32)
+    trp, tci, tv, tf = permute(n, rp, ci, v, f, p)
+    nu, inv = norms(n, trp, tv)
+    cptr, cidx = conflicts(n, trp, tci, tv, nu, delta)
+    g, ng = groups(n, nu, cptr, cidx)
+    return Plan(n, p, trp, tci, tv, tf, nu, inv, cptr, cidx, g, ng)
+
+
+def plan_system(s, delta, **kw) -> Plan:
+    return plan(s.n, s.row_ptr, s.col, s.val, s.f, delta, **kw)
+
+
+def sweep(pl: Plan, xt: np.ndarray, sweeps: int, f: np.ndarray | None = None) -> np.ndarray:
+    """O8: `sweeps` OBK sweeps in reordered coordinates; returns a new array."""
+    x = np.array(xt, dtype=np.float64, copy=True)
+    ff = pl.f if f is None else _c(f, np.float64)
+    rc = lib().orc_sweep(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(ff), _ptr(pl.inv),
+                         _ptr(pl.group), pl.ngroups, _ptr(x), int(sweeps))
+    if rc != 0:
+        raise RuntimeError(f"orc_sweep failed: {rc}")
+    return x
+
+
+def rowwise(n, rp, ci, v, f, inv, rows, x):
+    """Sequential eq. (1.2) projections over `rows` in the given order."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    rows = _c(rows, np.int32)
+    lib().orc_rowwise(n, _ptr(_c(rp, np.int64)), _ptr(_c(ci, np.int32)), _ptr(_c(v, np.float64)),
+                      _ptr(_c(f, np.float64)), _ptr(_c(inv, np.float64)), _ptr(rows), rows.size,
+                      _ptr(x))
+    return x
+
+
+def relres(n, rp, ci, v, f, x, want_r: bool = False):
+    """O9: ||f - A x|| / ||f||."""
+    r = np.empty(n, np.float64) if want_r else None
+    rho = lib().orc_relres(n, _ptr(_c(rp, np.int64)), _ptr(_c(ci, np.int32)), _ptr(_c(v, np.float64)),
+                           _ptr(_c(f, np.float64)), _ptr(_c(x, np.float64)), _ptr(r))
+    return (rho, r) if want_r else rho
+
+
+def unpermute(p, xt):
+    """O10: x = P^T x~."""
+    xt = _c(xt, np.float64)
+    x = np.empty_like(xt)
+    lib().orc_unpermute(xt.size, _ptr(_c(p, np.int32)), _ptr(xt), _ptr(x))
+    return x
+
+
+def permute_vec(p, x):
+    x = _c(x, np.float64)
+    xt = np.empty_like(x)
+    lib().orc_permute_vec(x.size, _ptr(_c(p, np.int32)), _ptr(x), _ptr(xt))
+    return xt
+
+
+def solve(pl: Plan, sweeps: int, x0: np.ndarray | None = None) -> np.ndarray:
+    """Plan + `sweeps` sweeps from x0 (default 0, Section 3.5), original ordering."""
+    xt = np.zeros(pl.n) if x0 is None else permute_vec(pl.p, x0)
+    return unpermute(pl.p, sweep(pl, xt, sweeps))
+
+
+def refine(pl: Plan, inner: int, outer: int, tol: float, x0t: np.ndarray | None = None):
+    """O11 iterative refinement schedule in FP64; returns (x~, steps, relres)."""
+    x = np.zeros(pl.n) if x0t is None else np.array(x0t, dtype=np.float64, copy=True)
+    rho = ctypes.c_double(0.0)
+    steps = lib().orc_refine(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(pl.f), _ptr(pl.inv),
+                             _ptr(pl.group), pl.ngroups, _ptr(x), int(inner), int(outer), float(tol),
+                             ctypes.byref(rho))
+    return x, int(steps), float(rho.value)

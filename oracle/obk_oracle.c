@@ -1,0 +1,518 @@
+/*
+ * FP64 CPU oracle for OBK-RCM (Liang & Li, "OBK-RCM: Accelerated Orthogonal
+ * Block Kaczmarz Algorithm via RCM Reordering and Dynamic Grouping").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the GPU library computes.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, table or helper with the HIP library.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Every floating-point sum below runs sequentially in the stated order; every
+ * + - * / sqrt is a single IEEE-754 round-to-nearest operation (no FMA
+ * contraction), which is what makes bit-exact plan parity well defined.
+ *
+ * Readings of the paper that this file fixes (where the text is silent):
+ *  - one block = one row of the reordered matrix, so a block's centroid is the
+ *    row itself and the cosine table becomes exact row cosines (Section 3.3);
+ *  - |cos| is compared with the threshold, a pair is near-orthogonal iff
+ *    |cos| < delta (strict, as written in Section 3.3);
+ *  - classes are maximal: first-fit greedy colouring in reordered row order
+ *    (the pair rule of Section 3.3 is kept as orc_pairs for tests);
+ *  - RCM tie-break: start at the unvisited vertex of least (degree, index),
+ *    visit unvisited neighbours by ascending (degree, index), reverse the
+ *    whole Cuthill-McKee sequence (Section 3.2 gives no tie-break);
+ *  - one sweep projects every group once in ascending group id, all rows of a
+ *    group from the same iterate (simultaneous form of eq. 3.3).
+ *
+ * Status: every function is pinned by the CPU test-suite (pseudo-inverse block
+ * projection, sequential Kaczmarz, dense Gram cosines, hand-worked RCM orders,
+ * closed forms).  The iterate after K sweeps on near-orthogonal (not exactly
+ * orthogonal) groups is pinned only through convergence and non-expansiveness:
+ * the paper prints no iterate values.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_CSR (-2)
+#define ORC_E_NONFINITE (-4)
+#define ORC_E_NOMEM (-5)
+
+/* ---------------------------------------------------------------- O1 ----
+ * Validate a square CSR (the method needs m = n, Section 4 opening).
+ * Columns in range, no duplicate (row, col), values and f finite.
+ * Rows need not be sorted.                                                  */
+int orc_validate(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                 const double *f)
+{
+    if (n < 0 || !rp) return ORC_E_ARG;
+    if (rp[0] != 0) return ORC_E_CSR;
+    for (int64_t i = 0; i < n; i++)
+        if (rp[i + 1] < rp[i]) return ORC_E_CSR;
+    int64_t nnz = rp[n];
+    for (int64_t k = 0; k < nnz; k++)
+        if (ci[k] < 0 || (int64_t)ci[k] >= n) return ORC_E_CSR;
+    /* duplicates: mark columns of each row in a scratch array */
+    int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!seen) return ORC_E_NOMEM;
+    for (int64_t c = 0; c < n; c++) seen[c] = -1;
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < n && rc == ORC_OK; i++)
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+            if (seen[ci[k]] == i) { rc = ORC_E_CSR; break; }
+            seen[ci[k]] = i;
+        }
+    free(seen);
+    if (rc != ORC_OK) return rc;
+    for (int64_t k = 0; k < nnz; k++)
+        if (!isfinite(v[k])) return ORC_E_NONFINITE;
+    if (f)
+        for (int64_t i = 0; i < n; i++)
+            if (!isfinite(f[i])) return ORC_E_NONFINITE;
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- O2 ----
+ * Undirected simple graph of the pattern of A + A^T without the diagonal:
+ * edge {u,v} iff u != v and (u,v) or (v,u) is stored.  Built as a sorted,
+ * de-duplicated list of directed pairs (both directions).                   */
+typedef struct { int32_t a, b; } orc_pair;
+
+static int cmp_pair(const void *x, const void *y)
+{
+    const orc_pair *p = (const orc_pair *)x, *q = (const orc_pair *)y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    return 0;
+}
+
+/* adjacency in CSR form: gp[n+1], gi[gp[n]]; returns number of entries or <0 */
+static int64_t build_graph(int64_t n, const int64_t *rp, const int32_t *ci,
+                           int64_t **gp_out, int32_t **gi_out)
+{
+    int64_t nnz = rp[n];
+    orc_pair *e = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(2 * nnz + 1));
+    if (!e) return ORC_E_NOMEM;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t j = ci[k];
+            if (j == (int32_t)i) continue;
+            e[m].a = (int32_t)i; e[m].b = j; m++;
+            e[m].a = j; e[m].b = (int32_t)i; m++;
+        }
+    qsort(e, (size_t)m, sizeof(orc_pair), cmp_pair);
+    int64_t u = 0;
+    for (int64_t t = 0; t < m; t++)
+        if (t == 0 || cmp_pair(&e[t], &e[t - 1]) != 0) e[u++] = e[t];
+    int64_t *gp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *gi = (int32_t *)malloc(sizeof(int32_t) * (size_t)(u + 1));
+    if (!gp || !gi) { free(e); free(gp); free(gi); return ORC_E_NOMEM; }
+    for (int64_t t = 0; t < u; t++) gp[e[t].a + 1]++;
+    for (int64_t i = 0; i < n; i++) gp[i + 1] += gp[i];
+    for (int64_t t = 0; t < u; t++) gi[t] = e[t].b;   /* already grouped by a */
+    free(e);
+    *gp_out = gp; *gi_out = gi;
+    return u;
+}
+
+/* ---------------------------------------------------------------- O3 ----
+ * Reverse Cuthill-McKee (Section 3.2; Algorithm 4, first step).
+ * Cuthill-McKee: while a vertex is unvisited, start a breadth-first search at
+ * the unvisited vertex of least (degree, index); a dequeued vertex is appended
+ * to the order and its unvisited neighbours, sorted by (degree, index), are
+ * marked visited and enqueued.  The concatenated order is then reversed.
+ * Output p[t] = old index of new row t (new -> old).                        */
+static const int64_t *g_deg_for_sort;
+static int cmp_deg_idx(const void *x, const void *y)
+{
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    int64_t da = g_deg_for_sort[a], db = g_deg_for_sort[b];
+    if (da != db) return da < db ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+int orc_rcm(int64_t n, const int64_t *rp, const int32_t *ci, int32_t *p)
+{
+    if (n == 0) return ORC_OK;
+    int64_t *gp; int32_t *gi;
+    int64_t ne = build_graph(n, rp, ci, &gp, &gi);
+    if (ne < 0) return (int)ne;
+    int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *byrank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    char *visited = (char *)calloc((size_t)n, 1);
+    if (!deg || !byrank || !queue || !order || !nb || !visited) {
+        free(gp); free(gi); free(deg); free(byrank); free(queue); free(order); free(nb); free(visited);
+        return ORC_E_NOMEM;
+    }
+    for (int64_t v = 0; v < n; v++) { deg[v] = gp[v + 1] - gp[v]; byrank[v] = (int32_t)v; }
+    /* all vertices sorted by (degree, index): the first unvisited entry of this
+     * list is the argmin over unvisited vertices */
+    g_deg_for_sort = deg;
+    qsort(byrank, (size_t)n, sizeof(int32_t), cmp_deg_idx);
+    int64_t cursor = 0, norder = 0;
+    while (norder < n) {
+        while (visited[byrank[cursor]]) cursor++;
+        int32_t s = byrank[cursor];
+        int64_t head = 0, tail = 0;
+        visited[s] = 1;
+        queue[tail++] = s;
+        while (head < tail) {
+            int32_t v = queue[head++];
+            order[norder++] = v;
+            int64_t cnt = 0;
+            for (int64_t k = gp[v]; k < gp[v + 1]; k++)
+                if (!visited[gi[k]]) nb[cnt++] = gi[k];
+            qsort(nb, (size_t)cnt, sizeof(int32_t), cmp_deg_idx);
+            for (int64_t t = 0; t < cnt; t++) { visited[nb[t]] = 1; queue[tail++] = nb[t]; }
+        }
+    }
+    for (int64_t t = 0; t < n; t++) p[t] = order[n - 1 - t];
+    free(gp); free(gi); free(deg); free(byrank); free(queue); free(order); free(nb); free(visited);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- O4 ----
+ * Symmetric permutation, eqs. (3.1)-(3.2): row t of A~ = P A P^T is row p[t]
+ * of A with every column c renamed q[c] (q = inverse of p) and the row sorted
+ * ascending by the new column; f~_t = f_{p[t]}.                              */
+typedef struct { int32_t c; double v; } orc_entry;
+static int cmp_entry(const void *x, const void *y)
+{
+    int32_t a = ((const orc_entry *)x)->c, b = ((const orc_entry *)y)->c;
+    return (a > b) - (a < b);
+}
+
+int orc_permute(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                const double *f, const int32_t *p, int64_t *trp, int32_t *tci, double *tv,
+                double *tf)
+{
+    int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    orc_entry *buf = (orc_entry *)malloc(sizeof(orc_entry) * (size_t)(n > 0 ? n : 1));
+    if (!q || !buf) { free(q); free(buf); return ORC_E_NOMEM; }
+    for (int64_t t = 0; t < n; t++) q[p[t]] = (int32_t)t;
+    trp[0] = 0;
+    for (int64_t t = 0; t < n; t++) {
+        int32_t old = p[t];
+        int64_t len = rp[old + 1] - rp[old];
+        for (int64_t k = 0; k < len; k++) {
+            buf[k].c = q[ci[rp[old] + k]];
+            buf[k].v = v[rp[old] + k];
+        }
+        qsort(buf, (size_t)len, sizeof(orc_entry), cmp_entry);
+        for (int64_t k = 0; k < len; k++) {
+            tci[trp[t] + k] = buf[k].c;
+            tv[trp[t] + k] = buf[k].v;
+        }
+        trp[t + 1] = trp[t] + len;
+        if (tf && f) tf[t] = f[old];
+    }
+    free(q); free(buf);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- O5 ----
+ * Squared row norms, the denominator of eq. (1.2): nu_i = sum_k a_ik^2 in
+ * ascending k; inv_i = 1/nu_i (0 for an all-zero row, which is never
+ * projected).                                                               */
+void orc_norms(int64_t n, const int64_t *rp, const double *v, double *nu, double *inv)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * v[k];
+        nu[i] = s;
+        inv[i] = (s != 0.0) ? 1.0 / s : 0.0;
+    }
+}
+
+/* ---------------------------------------------------------------- O6 ----
+ * Row cosines (the cosine table C of Section 3.3 with one-row blocks).
+ * For rows i, j sharing at least one column: d = sum over the common columns
+ * in ascending order of a_ic * a_jc; cos_ij = |d| / sqrt(nu_i * nu_j)
+ * (product rounded, then sqrt, then the division).  Rows sharing no column are
+ * exactly orthogonal.  The pair conflicts (is NOT near-orthogonal) iff
+ * cos_ij >= delta.  Zero rows take part in nothing.
+ * Rows must be sorted ascending (O4 output).
+ *
+ * Output, for each i, the conflicting j < i in ascending order:
+ *   cptr[n+1], cidx[cptr[n]].  With cidx == NULL only cptr is filled.       */
+static double sparse_dot_sorted(const int32_t *ca, const double *va, int64_t la,
+                                const int32_t *cb, const double *vb, int64_t lb, int *shared)
+{
+    double d = 0.0;
+    int64_t a = 0, b = 0;
+    *shared = 0;
+    while (a < la && b < lb) {
+        if (ca[a] < cb[b]) a++;
+        else if (ca[a] > cb[b]) b++;
+        else { d = d + va[a] * vb[b]; *shared = 1; a++; b++; }
+    }
+    return d;
+}
+
+double orc_cosine(int64_t i, int64_t j, const int64_t *rp, const int32_t *ci, const double *v,
+                  const double *nu)
+{
+    int shared;
+    double d = sparse_dot_sorted(ci + rp[i], v + rp[i], rp[i + 1] - rp[i],
+                                 ci + rp[j], v + rp[j], rp[j + 1] - rp[j], &shared);
+    if (!shared || nu[i] == 0.0 || nu[j] == 0.0) return 0.0;
+    return fabs(d) / sqrt(nu[i] * nu[j]);
+}
+
+static int cmp_i32(const void *x, const void *y)
+{
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    return (a > b) - (a < b);
+}
+
+int64_t orc_conflicts(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                      const double *nu, double delta, int64_t *cptr, int32_t *cidx)
+{
+    /* column -> rows (CSC of the pattern) */
+    int64_t nnz = rp[n];
+    int64_t *cp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *cr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!cp || !cr || !fill || !mark || !cand) {
+        free(cp); free(cr); free(fill); free(mark); free(cand); return ORC_E_NOMEM;
+    }
+    for (int64_t k = 0; k < nnz; k++) cp[ci[k] + 1]++;
+    for (int64_t c = 0; c < n; c++) cp[c + 1] += cp[c];
+    for (int64_t c = 0; c < n; c++) fill[c] = cp[c];
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) cr[fill[ci[k]]++] = (int32_t)i;
+    for (int64_t j = 0; j < n; j++) mark[j] = -1;
+
+    int64_t total = 0;
+    cptr[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t ncand = 0;
+        if (nu[i] != 0.0) {
+            for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                int32_t c = ci[k];
+                for (int64_t t = cp[c]; t < cp[c + 1]; t++) {
+                    int32_t j = cr[t];
+                    if (j < i && mark[j] != i) { mark[j] = i; cand[ncand++] = j; }
+                }
+            }
+        }
+        qsort(cand, (size_t)ncand, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < ncand; t++) {
+            int32_t j = cand[t];
+            if (nu[j] == 0.0) continue;
+            if (orc_cosine(i, j, rp, ci, v, nu) >= delta) {
+                if (cidx) cidx[total] = j;
+                total++;
+            }
+        }
+        cptr[i + 1] = total;
+    }
+    free(cp); free(cr); free(fill); free(mark); free(cand);
+    return total;
+}
+
+/* ---------------------------------------------------------------- O7 ----
+ * Grouping (Section 3.3, class{i}, Oclass/Nclass; Algorithm 4, fourth step).
+ * Taking "the first later block orthogonal to A_i" to its maximal form: rows
+ * are visited in reordered order and row i joins the lowest-numbered group
+ * that holds no row conflicting with it (first-fit greedy colouring of the
+ * conflict graph).  A zero row joins no group (group -1).
+ * Returns the number of groups.                                             */
+int32_t orc_groups(int64_t n, const double *nu, const int64_t *cptr, const int32_t *cidx,
+                   int32_t *group)
+{
+    char *used = (char *)calloc((size_t)n + 2, 1);
+    if (!used) return ORC_E_NOMEM;
+    int32_t ngroups = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (nu[i] == 0.0) { group[i] = -1; continue; }
+        for (int64_t t = cptr[i]; t < cptr[i + 1]; t++)
+            if (group[cidx[t]] >= 0) used[group[cidx[t]]] = 1;
+        int32_t g = 0;
+        while (used[g]) g++;
+        group[i] = g;
+        if (g + 1 > ngroups) ngroups = g + 1;
+        for (int64_t t = cptr[i]; t < cptr[i + 1]; t++)
+            if (group[cidx[t]] >= 0) used[group[cidx[t]]] = 0;
+    }
+    free(used);
+    return ngroups;
+}
+
+/* The literal pair rule of Section 3.3: for each unassigned row i (ascending),
+ * the first unassigned later row j with cos_ij < delta forms class{i} = {i, j};
+ * a row that finds no partner goes to Nclass.  Output: pair_of[i] = partner
+ * (or -1 for an Nclass row, -2 for a zero row).  Quadratic; tiny inputs.     */
+int orc_pairs(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              const double *nu, double delta, int32_t *pair_of)
+{
+    for (int64_t i = 0; i < n; i++) pair_of[i] = (nu[i] == 0.0) ? -2 : -3;   /* -3: unassigned */
+    for (int64_t i = 0; i < n; i++) {
+        if (pair_of[i] != -3) continue;
+        pair_of[i] = -1;
+        for (int64_t j = i + 1; j < n; j++) {
+            if (pair_of[j] != -3) continue;
+            if (orc_cosine(i, j, rp, ci, v, nu) < delta) {
+                pair_of[i] = (int32_t)j; pair_of[j] = (int32_t)i; break;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- O8 ----
+ * One OBK sweep (eq. 3.3 with one-row blocks; eq. 1.2 per row).
+ * For g = 0 .. ngroups-1:
+ *   (i)  for every row i of group g, from the same iterate x:
+ *          s = sum_k a_ik x_k (ascending k);  w_i = (f_i - s) * inv_i
+ *   (ii) for every column c touched by group g:
+ *          t = sum over rows i of group g holding c, ascending i, of w_i a_ic;
+ *          x_c = x_c + t
+ * For exactly orthogonal rows this is the pseudo-inverse projection of eq.
+ * (1.3); for near-orthogonal rows it defines the step.  `sweeps` sweeps run.
+ * T = double (FP64).                                                         */
+int orc_sweep(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              const double *f, const double *inv, const int32_t *group, int32_t ngroups,
+              double *x, int64_t sweeps)
+{
+    /* rows of each group in ascending order */
+    int64_t *gp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
+    int32_t *gr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ngroups + 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *t = (double *)calloc((size_t)n + 1, sizeof(double));
+    char *touched = (char *)calloc((size_t)n + 1, 1);
+    int32_t *tlist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!gp || !gr || !fill || !w || !t || !touched || !tlist) {
+        free(gp); free(gr); free(fill); free(w); free(t); free(touched); free(tlist);
+        return ORC_E_NOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) gp[group[i] + 1]++;
+    for (int32_t g = 0; g < ngroups; g++) gp[g + 1] += gp[g];
+    for (int32_t g = 0; g < ngroups; g++) fill[g] = gp[g];
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) gr[fill[group[i]]++] = (int32_t)i;
+
+    for (int64_t it = 0; it < sweeps; it++) {
+        for (int32_t g = 0; g < ngroups; g++) {
+            /* (i) residual weights from the same iterate */
+            for (int64_t a = gp[g]; a < gp[g + 1]; a++) {
+                int32_t i = gr[a];
+                double s = 0.0;
+                for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
+                w[i] = (f[i] - s) * inv[i];
+            }
+            /* (ii) per touched column, the sum over the group's rows in
+             * ascending row order, then one update of x_c */
+            int64_t nt = 0;
+            for (int64_t a = gp[g]; a < gp[g + 1]; a++) {
+                int32_t i = gr[a];
+                for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                    int32_t c = ci[k];
+                    if (!touched[c]) { touched[c] = 1; t[c] = 0.0; tlist[nt++] = c; }
+                    t[c] = t[c] + w[i] * v[k];
+                }
+            }
+            for (int64_t a = 0; a < nt; a++) {
+                int32_t c = tlist[a];
+                x[c] = x[c] + t[c];
+                touched[c] = 0;
+            }
+        }
+    }
+    free(gp); free(gr); free(fill); free(w); free(t); free(touched); free(tlist);
+    return ORC_OK;
+}
+
+/* Sequential row projections in a given row order (eq. 1.2 applied row by
+ * row, each from the latest iterate).  Used to pin O8 (P3) and the pair mode
+ * of Algorithm 4, where the two blocks of a class are projected one after the
+ * other.                                                                     */
+void orc_rowwise(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                 const double *f, const double *inv, const int32_t *rows, int64_t nrows,
+                 double *x)
+{
+    (void)n;
+    for (int64_t a = 0; a < nrows; a++) {
+        int32_t i = rows[a];
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
+        double w = (f[i] - s) * inv[i];
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) x[ci[k]] = x[ci[k]] + w * v[k];
+    }
+}
+
+/* ---------------------------------------------------------------- O9 ----
+ * Residual r = f - A x (ascending k per row) and the relative residual
+ * ||r||_2 / ||f||_2, each norm the sqrt of an ascending-index sum of squares.
+ * r may be NULL.  Returns -1 if ||f|| = 0 and ||r|| > 0, 0 if both are 0.     */
+double orc_relres(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                  const double *f, const double *x, double *r)
+{
+    double rr = 0.0, ff = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
+        double ri = f[i] - s;
+        if (r) r[i] = ri;
+        rr = rr + ri * ri;
+        ff = ff + f[i] * f[i];
+    }
+    if (ff == 0.0) return rr == 0.0 ? 0.0 : -1.0;
+    return sqrt(rr) / sqrt(ff);
+}
+
+/* --------------------------------------------------------------- O10 ----
+ * Back-permutation x = P^T x~ (Algorithm 4, last step): x[p[t]] = xt[t].    */
+void orc_unpermute(int64_t n, const int32_t *p, const double *xt, double *x)
+{
+    for (int64_t t = 0; t < n; t++) x[p[t]] = xt[t];
+}
+
+/* Forward permutation of a vector: xt[t] = x[p[t]].                          */
+void orc_permute_vec(int64_t n, const int32_t *p, const double *x, double *xt)
+{
+    for (int64_t t = 0; t < n; t++) xt[t] = x[p[t]];
+}
+
+/* --------------------------------------------------------------- O11 ----
+ * Iterative refinement around the sweep (not in the paper): with x~ in FP64,
+ *   r = f - A x;  stop if ||r||/||f|| <= tol or `outer` steps are done;
+ *   sigma = max_i |r_i|;  b = r / sigma;
+ *   d = 0;  `inner` sweeps of O8 on A d = b (same groups and order);
+ *   x = x + sigma * d.
+ * The oracle runs this schedule in FP64 throughout, so a GPU run of the same
+ * schedule with an FP32 inner sweep differs only by the FP32 inner arithmetic.
+ * Returns the number of outer steps taken; *relres gets the last residual.  */
+int64_t orc_refine(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                   const double *f, const double *inv, const int32_t *group, int32_t ngroups,
+                   double *x, int64_t inner, int64_t outer, double tol, double *relres)
+{
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    if (!r || !d) { free(r); free(d); return ORC_E_NOMEM; }
+    int64_t steps = 0;
+    double rho = orc_relres(n, rp, ci, v, f, x, r);
+    while (!(rho <= tol) && steps < outer) {
+        double sigma = 0.0;
+        for (int64_t i = 0; i < n; i++) if (fabs(r[i]) > sigma) sigma = fabs(r[i]);
+        if (sigma == 0.0) break;
+        for (int64_t i = 0; i < n; i++) { r[i] = r[i] / sigma; d[i] = 0.0; }
+        orc_sweep(n, rp, ci, v, r, inv, group, ngroups, d, inner);
+        for (int64_t i = 0; i < n; i++) x[i] = x[i] + sigma * d[i];
+        steps++;
+        rho = orc_relres(n, rp, ci, v, f, x, r);
+    }
+    if (relres) *relres = rho;
+    free(r); free(d);
+    return steps;
+}

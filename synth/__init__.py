@@ -1,0 +1,247 @@
+"""Seeded synthetic sparse systems ``A x = f`` (problem statement, eq. 1.1).
+
+This module only draws random inputs; it holds none of the solver's
+arithmetic.  Both the FP64 CPU oracle and the HIP path are fed from here,
+so that the two see bit-identical CSR matrices and right-hand sides.
+
+The paper evaluates on SuiteSparse matrices (Section 3.5, Table 3) that are
+not available here; the families below stand in for them:
+
+* ``c1``        2,000 rows, diagonal U(1,2) plus 4 off-diagonal N(0,1) entries
+                per row at distinct uniform columns, then a random symmetric
+                permutation (scattered pattern).
+* ``c2``        2-D 5-point stencil on a 1024x1024 grid (diagonal 4+U(0,0.1),
+                -1 to each N/S/E/W neighbour, Dirichlet), random symmetric
+                permutation.  ``grid`` sets the side for smaller cases.
+* ``c3``        2,000,000 rows, diagonal U(1,2) plus 11 distinct uniform
+                off-diagonal N(0,1) entries per row (12 nnz/row).
+* ``c4``        512 systems, n log-uniform in [1e3, 2e5], 4..16 nnz per row
+                including the diagonal.
+* ``c5``        serving requests, n log-uniform in [500, 5e5], 4..16 nnz/row.
+* ``companion=True`` replaces the diagonal by U(1,2) + sum_j |a_ij| (row
+  diagonal dominance), keeping pattern, off-diagonal values and seeds.
+
+Conventions: ``numpy.random.Generator(PCG64(seed))`` with
+``seed = 1000*config + system_index``.  Draw order per system: per-row nnz
+(families with variable rows), off-diagonal columns, off-diagonal values,
+diagonal values, symmetric permutation (where used), x* ~ N(0,1).
+f = A x* is formed in FP64 by scipy's CSR product.
+
+CSR layout everywhere: int64 ``row_ptr[n+1]``, int32 ``col[nnz]`` sorted
+ascending within each row, float64 ``val[nnz]``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "System", "seed_for", "random_rows", "stencil", "c1", "c2", "c3",
+    "c4_sizes", "c4_system", "c5_sizes", "c5_system", "c5_arrivals",
+    "from_dense", "from_scipy",
+]
+
+
+@dataclasses.dataclass
+class System:
+    """A square sparse system in CSR form with its generating solution."""
+    n: int
+    row_ptr: np.ndarray      # int64 [n+1]
+    col: np.ndarray          # int32 [nnz]
+    val: np.ndarray          # float64 [nnz]
+    f: np.ndarray            # float64 [n]
+    x_star: np.ndarray       # float64 [n]
+    name: str = ""
+    seed: int = -1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def seed_for(config: int, index: int = 0) -> int:
+    return 1000 * int(config) + int(index)
+
+
+def _pack(A: sp.spmatrix, x_star: np.ndarray, name: str, seed: int) -> System:
+    A = sp.csr_matrix(A)
+    A.sum_duplicates()
+    A.sort_indices()
+    f = A @ x_star
+    return System(
+        n=A.shape[0],
+        row_ptr=np.ascontiguousarray(A.indptr, dtype=np.int64),
+        col=np.ascontiguousarray(A.indices, dtype=np.int32),
+        val=np.ascontiguousarray(A.data, dtype=np.float64),
+        f=np.ascontiguousarray(f, dtype=np.float64),
+        x_star=np.ascontiguousarray(x_star, dtype=np.float64),
+        name=name, seed=seed)
+
+
+def from_scipy(A: sp.spmatrix, x_star: np.ndarray | None = None, f: np.ndarray | None = None,
+               name: str = "custom") -> System:
+    """Wrap an explicit matrix.  If ``f`` is given it is kept as-is."""
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    n = A.shape[0]
+    if x_star is None:
+        x_star = np.zeros(n)
+    s = _pack(A, np.asarray(x_star, dtype=np.float64), name, -1)
+    if f is not None:
+        s.f = np.ascontiguousarray(f, dtype=np.float64)
+    return s
+
+
+def from_dense(M: np.ndarray, x_star: np.ndarray | None = None, f: np.ndarray | None = None,
+               name: str = "dense") -> System:
+    """CSR of a small dense matrix; exact zeros are not stored."""
+    return from_scipy(sp.csr_matrix(np.asarray(M, dtype=np.float64)), x_star, f, name)
+
+
+def _distinct_offdiag_columns(rng: np.random.Generator, n: int, k: np.ndarray):
+    """Per row i, k[i] distinct columns uniform over {0..n-1} minus {i}.
+
+    Rows are drawn as a batch of k_max candidates with replacement from
+    {0..n-2}; a row whose first k[i] candidates repeat is redrawn whole
+    (rejection keeps the subset uniform).  Candidates v >= i map to v+1.
+    Returns the candidate matrix and the mask of its used entries.
+    """
+    kmax = int(k.max()) if len(k) else 0
+    if kmax > n - 1:
+        raise ValueError("more off-diagonals than columns")
+    cand = rng.integers(0, max(n - 1, 1), size=(n, kmax), dtype=np.int64)
+    mask = np.arange(kmax)[None, :] < k[:, None]
+    filler = (n + 7 + np.arange(kmax, dtype=np.int64))[None, :]
+
+    def dup_rows(c: np.ndarray, m: np.ndarray) -> np.ndarray:
+        if kmax < 2:
+            return np.zeros(0, dtype=np.int64)
+        s = np.sort(np.where(m, c, filler), axis=1)
+        return np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
+
+    bad = dup_rows(cand, mask)
+    while bad.size:
+        cand[bad] = rng.integers(0, n - 1, size=(bad.size, kmax), dtype=np.int64)
+        bad = bad[dup_rows(cand[bad], mask[bad])]
+    rows = np.arange(n, dtype=np.int64)
+    cand = np.where(cand >= rows[:, None], cand + 1, cand)
+    return cand, mask
+
+
+def _random_rows_from(rng: np.random.Generator, n: int, k: np.ndarray, *, permute: bool,
+                      companion: bool, name: str, seed: int) -> System:
+    cols, mask = _distinct_offdiag_columns(rng, n, k)
+    offv = rng.standard_normal(size=cols.shape)
+    diag = rng.uniform(1.0, 2.0, size=n)
+    rr = np.repeat(np.arange(n, dtype=np.int64), k)
+    cc = cols[mask]
+    vv = offv[mask]
+    if companion:
+        diag = diag + np.bincount(rr, weights=np.abs(vv), minlength=n)
+    r_all = np.concatenate([rr, np.arange(n, dtype=np.int64)])
+    c_all = np.concatenate([cc, np.arange(n, dtype=np.int64)])
+    v_all = np.concatenate([vv, diag])
+    A = sp.csr_matrix((v_all, (r_all, c_all)), shape=(n, n))
+    if permute:
+        perm = rng.permutation(n)          # new -> old
+        A = A[perm][:, perm]
+    x_star = rng.standard_normal(n)
+    return _pack(A, x_star, name + ("-companion" if companion else ""), seed)
+
+
+def random_rows(n: int, k_off: int, seed: int, *, permute: bool = False, companion: bool = False,
+                name: str = "random") -> System:
+    """Diagonal U(1,2) plus ``k_off`` off-diagonal N(0,1) entries on every row."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = np.full(n, int(k_off), dtype=np.int64)
+    return _random_rows_from(rng, n, k, permute=permute, companion=companion, name=name, seed=seed)
+
+
+def stencil(grid: int, seed: int, *, permute: bool = True, name: str = "stencil") -> System:
+    """5-point stencil on a grid x grid mesh, natural index r*grid + c.
+
+    Diagonal 4 + U(0, 0.1); -1 to each existing N/S/E/W neighbour.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = grid * grid
+    idx = np.arange(n, dtype=np.int64).reshape(grid, grid)
+    rows, cols = [], []
+    for dr, dc in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        r0, r1 = max(0, -dr), grid - max(0, dr)
+        c0, c1 = max(0, -dc), grid - max(0, dc)
+        src = idx[r0:r1, c0:c1].ravel()
+        dst = idx[r0 + dr:r1 + dr, c0 + dc:c1 + dc].ravel()
+        rows.append(src)
+        cols.append(dst)
+    rr = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    diag = 4.0 + rng.uniform(0.0, 0.1, size=n)
+    A = sp.csr_matrix((np.concatenate([-np.ones(rr.size), diag]),
+                       (np.concatenate([rr, np.arange(n)]), np.concatenate([cc, np.arange(n)]))),
+                      shape=(n, n))
+    if permute:
+        perm = rng.permutation(n)
+        A = A[perm][:, perm]
+    x_star = rng.standard_normal(n)
+    return _pack(A, x_star, f"{name}{grid}", seed)
+
+
+def c1(index: int = 0, *, n: int = 2000, companion: bool = False) -> System:
+    """2,000 rows, 4 off-diagonals per row, scattered by a symmetric permutation."""
+    return random_rows(n, 4, seed_for(1, index), permute=True, companion=companion, name=f"c1-n{n}")
+
+
+def c2(index: int = 0, *, grid: int = 1024) -> System:
+    """1024x1024 5-point stencil under a random symmetric permutation."""
+    return stencil(grid, seed_for(2, index), permute=True, name="c2-grid")
+
+
+def c3(index: int = 0, *, n: int = 2_000_000, companion: bool = False) -> System:
+    """n rows, 12 nnz per row (diagonal plus 11 uniform off-diagonals)."""
+    return random_rows(n, 11, seed_for(3, index), permute=False, companion=companion, name=f"c3-n{n}")
+
+
+def _loguniform_sizes(rng: np.random.Generator, count: int, lo: float, hi: float) -> np.ndarray:
+    return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+
+
+def c4_sizes(count: int = 512, lo: float = 1e3, hi: float = 2e5) -> np.ndarray:
+    """System sizes of the batched family (drawn from seed 4000)."""
+    return _loguniform_sizes(np.random.Generator(np.random.PCG64(seed_for(4, 0))), count, lo, hi)
+
+
+def _variable_rows(n: int, seed: int, companion: bool, name: str) -> System:
+    """4..16 nnz per row including the diagonal; the per-row count is drawn first."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nnz_row = rng.integers(4, 17, size=n)
+    k_off = np.minimum(nnz_row - 1, n - 1).astype(np.int64)
+    return _random_rows_from(rng, n, k_off, permute=False, companion=companion, name=name, seed=seed)
+
+
+def c4_system(index: int, n: int | None = None, *, companion: bool = False) -> System:
+    """System ``index`` of the batched family (seed 4000 + 1 + index)."""
+    if n is None:
+        n = int(c4_sizes()[index])
+    return _variable_rows(n, seed_for(4, 1 + index), companion, f"c4-{index}-n{n}")
+
+
+def c5_sizes(count: int = 8192, lo: float = 500, hi: float = 5e5) -> np.ndarray:
+    return _loguniform_sizes(np.random.Generator(np.random.PCG64(seed_for(5, 0))), count, lo, hi)
+
+
+def c5_system(index: int, n: int | None = None, *, companion: bool = True) -> System:
+    if n is None:
+        n = int(c5_sizes()[index])
+    return _variable_rows(n, seed_for(5, 1 + index), companion, f"c5-{index}-n{n}")
+
+
+def c5_arrivals(count: int, rate_per_s: float) -> np.ndarray:
+    """Poisson arrival times (seconds) at ``rate_per_s``, from seed 5000."""
+    rng = np.random.Generator(np.random.PCG64(5000))
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))

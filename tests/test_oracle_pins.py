@@ -1,0 +1,488 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside it.
+
+Each test names what it pins: a hand-worked case, a closed form, a textbook
+routine (numpy pseudo-inverse, dense Gram matrix, classic row Kaczmarz) or an
+invariant the paper states.  None of them re-types the oracle's own formula.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import oracle
+import synth
+from conftest import parse_golden
+
+
+def _csr(M):
+    A = sp.csr_matrix(np.asarray(M, dtype=np.float64))
+    A.sort_indices()
+    return (np.ascontiguousarray(A.indptr, np.int64), np.ascontiguousarray(A.indices, np.int32),
+            np.ascontiguousarray(A.data, np.float64))
+
+
+def _identity_plan(M, f, delta):
+    """Plan steps O5-O7 on a matrix taken as already reordered (P = I)."""
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[0]
+    rp, ci, v = _csr(M)
+    nu, inv = oracle.norms(n, rp, v)
+    cptr, cidx = oracle.conflicts(n, rp, ci, v, nu, delta)
+    g, ng = oracle.groups(n, nu, cptr, cidx)
+    return oracle.Plan(n, np.arange(n, dtype=np.int32), rp, ci, v, np.asarray(f, np.float64),
+                       nu, inv, cptr, cidx, g, ng)
+
+
+def _bandwidth(rp, ci):
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    return int(np.abs(rows - ci).max()) if ci.size else 0
+
+
+def _kaczmarz_textbook(M, f, x, order):
+    """Classic row Kaczmarz, eq. (1.2), dense, one row after another."""
+    x = np.array(x, dtype=np.float64)
+    for i in order:
+        a = M[i]
+        x = x + (f[i] - a @ x) / (a @ a) * a
+    return x
+
+
+# ----------------------------------------------------------------- P8: RCM
+@pytest.mark.parametrize("case", parse_golden("rcm_hand.txt"), ids=lambda c: c["name"])
+def test_rcm_hand_worked(case):
+    """O3 against orders worked by hand from the tie-break rule (Section 3.2)."""
+    n = int(case["n"])
+    M = np.eye(n)
+    for e in case["stored"].split():
+        r, c = map(int, e.split("-"))
+        M[r, c] = 1.0
+    rp, ci, v = _csr(M)
+    p = oracle.rcm(n, rp, ci)
+    assert p.tolist() == [int(t) for t in case["p"].split()]
+    assert p[::-1].tolist() == [int(t) for t in case["cm"].split()]
+
+
+def test_rcm_scrambled_path_has_bandwidth_one():
+    """A randomly labelled path is a band of width 1 after RCM."""
+    n = 500
+    perm = np.random.default_rng(7).permutation(n)
+    M = sp.lil_matrix((n, n))
+    for t in range(n):
+        M[perm[t], perm[t]] = 2.0
+        if t + 1 < n:
+            M[perm[t], perm[t + 1]] = -1.0
+            M[perm[t + 1], perm[t]] = -1.0
+    s = synth.from_scipy(M.tocsr())
+    pl = oracle.plan_system(s, 0.1)
+    assert _bandwidth(pl.rp, pl.ci) == 1
+
+
+@pytest.mark.parametrize("grid", [8, 32, 64])
+def test_rcm_grid_bandwidth(grid):
+    """A scrambled N x N grid comes back with bandwidth N (a level-set band;
+    Table 1 and Fig. 2 show RCM restoring a band)."""
+    s = synth.c2(grid=grid)
+    before = _bandwidth(s.row_ptr, s.col)
+    pl = oracle.plan_system(s, 0.1)
+    after = _bandwidth(pl.rp, pl.ci)
+    assert after <= 2 * grid - 1
+    assert after == grid
+    assert before > 4 * grid
+
+
+def test_rcm_is_a_permutation_and_close_to_scipy():
+    """Sanity against scipy's RCM (different tie-break, so not parity)."""
+    for s in (synth.c1(), synth.c2(grid=48)):
+        p = oracle.rcm(s.n, s.row_ptr, s.col)
+        assert np.array_equal(np.sort(p), np.arange(s.n))
+        A = s.scipy()
+        pat = ((A + A.T) != 0).astype(np.int8).tocsr()
+        ps = csg.reverse_cuthill_mckee(pat, symmetric_mode=True)
+        bw_o = _bandwidth(*_csr_perm(A, p))
+        bw_s = _bandwidth(*_csr_perm(A, ps))
+        assert bw_o <= 1.5 * bw_s
+
+
+def _csr_perm(A, p):
+    B = A[p][:, p].tocsr()
+    B.sort_indices()
+    return B.indptr.astype(np.int64), B.indices.astype(np.int32)
+
+
+# ------------------------------------------------------------- O4 permute
+def test_permute_matches_dense_symmetric_permutation():
+    """A~ = P A P^T, f~ = P f (eqs. 3.1-3.2) against dense fancy indexing."""
+    s = synth.c1(n=300)
+    p = oracle.rcm(s.n, s.row_ptr, s.col)
+    trp, tci, tv, tf = oracle.permute(s.n, s.row_ptr, s.col, s.val, s.f, p)
+    D = s.scipy().toarray()
+    Dt = D[p][:, p]
+    got = sp.csr_matrix((tv, tci, trp), shape=(s.n, s.n)).toarray()
+    assert np.array_equal(got, Dt)
+    assert np.array_equal(tf, s.f[p])
+    for i in range(s.n):
+        row = tci[trp[i]:trp[i + 1]]
+        assert np.all(np.diff(row) > 0)
+
+
+def test_error_norm_invariant_under_permutation():
+    """eq. (3.4): ||x_j - x*|| is the same in reordered and original coordinates."""
+    s = synth.c1(n=400)
+    pl = oracle.plan_system(s, 0.1)
+    xt = oracle.sweep(pl, np.zeros(s.n), 7)
+    xs_t = oracle.permute_vec(pl.p, s.x_star)
+    x = oracle.unpermute(pl.p, xt)
+    assert np.linalg.norm(xt - xs_t) == np.linalg.norm(x - s.x_star)
+    assert np.array_equal(oracle.permute_vec(pl.p, x), xt)
+
+
+# ------------------------------------------------- P9: norms and cosines
+def test_cosines_against_dense_gram():
+    """O5-O6 against |D^-1/2 A A^T D^-1/2| from a dense Gram matrix."""
+    for s in (synth.c1(n=250), synth.c2(grid=12), synth.c1(n=200, companion=True)):
+        n = s.n
+        rp, ci, v = s.row_ptr, s.col, s.val
+        nu, inv = oracle.norms(n, rp, v)
+        D = s.scipy().toarray()
+        assert np.allclose(nu, (D * D).sum(1), rtol=4e-16 * 16, atol=0)
+        G = D @ D.T
+        C = np.abs(G) / np.sqrt(np.outer(nu, nu))
+        pattern = ((np.abs(D) > 0).astype(float) @ (np.abs(D) > 0).T.astype(float)) > 0
+        for delta in (0.02, 0.1, 0.3):
+            cptr, cidx = oracle.conflicts(n, rp, ci, v, nu, delta)
+            got = set()
+            for i in range(n):
+                for j in cidx[cptr[i]:cptr[i + 1]]:
+                    got.add((i, int(j)))
+            near = np.abs(C - delta) < 1e-12
+            want = set()
+            for i in range(n):
+                for j in range(i):
+                    if pattern[i, j] and C[i, j] >= delta:
+                        want.add((i, j))
+            ambiguous = {(i, j) for i in range(n) for j in range(i) if near[i, j]}
+            assert got - ambiguous == want - ambiguous
+        # individual cosines within a few ulp of the dense value
+        rng = np.random.default_rng(1)
+        for _ in range(200):
+            i, j = rng.integers(0, n, 2)
+            c = oracle.cosine(i, j, rp, ci, v, nu)
+            if pattern[i, j]:
+                assert abs(c - C[i, j]) <= 8 * np.finfo(float).eps * max(C[i, j], 1e-300) + 1e-17
+            else:
+                assert c == 0.0
+
+
+@pytest.mark.parametrize("case", [c for c in parse_golden("hand_cases.txt") if "conflicts" in c],
+                         ids=lambda c: c["name"])
+def test_conflicts_groups_pairs_hand_worked(case):
+    """O6, O7 and the literal pair rule of Section 3.3 on cases worked by hand."""
+    M = np.array(case["row"])
+    n = M.shape[0]
+    delta = float(case["delta"])
+    pl = _identity_plan(M, np.zeros(n), delta)
+    want = {}
+    for tok in case["conflicts"].split():
+        i, js = tok.split(":")
+        want[int(i)] = [int(j) for j in js.split(",")]
+    for i in range(n):
+        assert pl.cidx[pl.cptr[i]:pl.cptr[i + 1]].tolist() == want.get(i, [])
+    assert pl.group.tolist() == [int(t) for t in case["groups"].split()]
+    got_pairs = oracle.pairs(n, pl.rp, pl.ci, pl.v, pl.nu, delta)
+    assert got_pairs.tolist() == [int(t) for t in case["pairs"].split()]
+
+
+# --------------------------------------------------------- P10: groups
+def _mis_peeling(n, conflict_sets):
+    """Independent statement of the class{i} rule taken to maximal classes:
+    repeatedly open a class at the first unassigned row and add every later
+    unassigned row that conflicts with none of the class so far."""
+    group = [-1] * n
+    g = 0
+    while True:
+        members = []
+        for i in range(n):
+            if group[i] != -1:
+                continue
+            if all(j not in conflict_sets[i] for j in members):
+                members.append(i)
+        if not members:
+            break
+        for i in members:
+            group[i] = g
+        g += 1
+        if all(x != -1 for x in group):
+            break
+    return group
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.c1(n=600), lambda: synth.c2(grid=20),
+                                   lambda: synth.c1(n=300, companion=True)])
+def test_groups_valid_first_fit_and_peeling(maker):
+    s = maker()
+    pl = oracle.plan_system(s, 0.1)
+    n = s.n
+    conf = [set() for _ in range(n)]
+    for i in range(n):
+        for j in pl.cidx[pl.cptr[i]:pl.cptr[i + 1]]:
+            conf[i].add(int(j))
+            conf[int(j)].add(i)
+    g = pl.group
+    # validity: no conflict inside a group
+    for i in range(n):
+        for j in conf[i]:
+            assert g[i] != g[j]
+    # first-fit property: a row of group c has an earlier conflicting row in every group < c
+    for i in range(n):
+        earlier = {int(g[j]) for j in conf[i] if j < i}
+        assert set(range(g[i])) <= earlier
+    # equality with the peeling statement of the class rule
+    assert _mis_peeling(n, conf) == g.tolist()
+
+
+# --------------------------------------- P1/P4: hand-worked sweeps (Fig. 1)
+@pytest.mark.parametrize("case", [c for c in parse_golden("hand_cases.txt") if "x1" in c],
+                         ids=lambda c: c["name"])
+def test_sweep_hand_worked(case):
+    M = np.array(case["row"])
+    f = np.array([float(t) for t in case["f"].split()])
+    xs = np.array([float(t) for t in case["xstar"].split()])
+    s = synth.from_dense(M, xs, f)
+    pl = oracle.plan_system(s, float(case["delta"]))
+    if "p" in case:
+        assert pl.p.tolist() == [int(t) for t in case["p"].split()]
+    assert pl.group.tolist() == [int(t) for t in case["groups"].split()]
+    x1 = oracle.solve(pl, 1)
+    np.testing.assert_allclose(x1, [float(t) for t in case["x1"].split()], rtol=0, atol=4e-16)
+    if "x2" in case:
+        x2 = oracle.solve(pl, 2)
+        np.testing.assert_allclose(x2, [float(t) for t in case["x2"].split()], rtol=0, atol=4e-16)
+    if "rate" in case:
+        # eq. (3.15): each projection multiplies the error by cos(theta)
+        errs = [np.linalg.norm(oracle.solve(pl, k) - xs) for k in range(1, 8)]
+        ratios = np.array(errs[1:]) / np.array(errs[:-1])
+        np.testing.assert_allclose(ratios, float(case["rate"]), rtol=1e-10)
+
+
+def test_single_row_projection_lands_on_hyperplane():
+    """eq. (1.2): after projecting row i, a_i x = f_i (to rounding)."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        M = np.diag(rng.uniform(1, 2, 4))
+        M[0] = rng.standard_normal(4)
+        M[0, 0] = 3.0
+        f = rng.standard_normal(4)
+        pl = _identity_plan(M, f, 0.1)
+        x0 = rng.standard_normal(4)
+        rows = np.array([0], np.int32)
+        x = oracle.rowwise(4, pl.rp, pl.ci, pl.v, f, pl.inv, rows, x0)
+        assert abs(M[0] @ x - f[0]) <= 8e-16 * (np.abs(M[0]) @ np.abs(x) + abs(f[0]))
+        np.testing.assert_allclose(x, _kaczmarz_textbook(M, f, x0, [0]), rtol=1e-15, atol=1e-15)
+
+
+# ---------------------------------- P2/P3/P5: exactly orthogonal groups
+def _hadamard(k):
+    H = np.array([[1.0]])
+    while H.shape[0] < k:
+        H = np.block([[H, H], [H, -H]])
+    return H
+
+
+def _one_group_plan(M, f, rows):
+    """A plan whose only group is `rows` (other rows left out)."""
+    pl = _identity_plan(M, f, 0.1)
+    g = np.full(M.shape[0], -1, np.int32)
+    g[np.asarray(rows)] = 0
+    pl.group = g
+    pl.ngroups = 1
+    return pl
+
+
+@pytest.mark.parametrize("kind", ["hadamard", "disjoint", "orthogonal_dense"])
+def test_group_step_equals_pseudoinverse_projection(kind):
+    """O8 on an exactly orthogonal group equals eq. (1.3) with numpy's pinv,
+    equals sequential eq. (1.2) in any order (P3), and obeys the Pythagorean
+    identity of eq. (3.8) (P5)."""
+    rng = np.random.default_rng({"hadamard": 1, "disjoint": 2, "orthogonal_dense": 3}[kind])
+    n = 8
+    M = np.diag(rng.uniform(1, 2, n))
+    if kind == "hadamard":
+        rows = [0, 2, 5, 7]
+        H = _hadamard(8)
+        for t, r in enumerate(rows):
+            M[r] = H[t] * rng.choice([1.0, 2.0, 0.5])
+    elif kind == "disjoint":
+        rows = [0, 1, 2]
+        M[0] = 0; M[1] = 0; M[2] = 0
+        M[0, [0, 3]] = rng.standard_normal(2)
+        M[1, [1, 4, 6]] = rng.standard_normal(3)
+        M[2, [2, 5, 7]] = rng.standard_normal(3)
+    else:
+        rows = [1, 3, 4, 6]
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        for t, r in enumerate(rows):
+            M[r] = Q[t] * rng.uniform(0.5, 2)
+    f = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    pl = _one_group_plan(M, f, rows)
+    x1 = oracle.sweep(pl, x0, 1)
+    Ag = M[rows]
+    want = x0 + np.linalg.pinv(Ag) @ (f[rows] - Ag @ x0)
+    np.testing.assert_allclose(x1, want, rtol=1e-14, atol=1e-14 * np.abs(want).max())
+    for order in (rows, rows[::-1], list(rng.permutation(rows))):
+        np.testing.assert_allclose(x1, _kaczmarz_textbook(M, f, x0, order), rtol=1e-14,
+                                   atol=1e-14 * np.abs(want).max())
+    # eq. (3.8) with x* any point on all the group's hyperplanes
+    xs = rng.standard_normal(n)
+    f2 = f.copy()
+    f2[rows] = Ag @ xs
+    pl2 = _one_group_plan(M, f2, rows)
+    x1 = oracle.sweep(pl2, x0, 1)
+    lhs = np.linalg.norm(x1 - xs) ** 2
+    rhs = np.linalg.norm(x0 - xs) ** 2 - np.linalg.norm(x1 - x0) ** 2
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x0 - xs) ** 2
+
+
+def test_all_orthogonal_rows_solve_in_one_sweep():
+    """Fig. 1 (right) and bcsstm39's IT = 1 (Table 4; nnz = rows, Table 3):
+    mutually orthogonal rows form one group and one sweep is exact."""
+    rng = np.random.default_rng(5)
+    n = 64
+    cases = []
+    cases.append(np.diag(rng.uniform(0.5, 3, n)))                      # diagonal
+    P = np.eye(n)[rng.permutation(n)] * rng.uniform(0.5, 3, n)[:, None]  # scaled permutation
+    cases.append(P)
+    Q, _ = np.linalg.qr(rng.standard_normal((16, 16)))                   # dense orthogonal
+    cases.append(Q)
+    for M in cases:
+        xs = rng.standard_normal(M.shape[0])
+        s = synth.from_dense(M, xs)
+        pl = oracle.plan_system(s, 0.1)
+        assert pl.ngroups == 1
+        x = oracle.solve(pl, 1)
+        np.testing.assert_allclose(x, xs, rtol=0, atol=1e-13 * np.abs(xs).max())
+
+
+def test_identity_gives_f_after_one_sweep():
+    """Identity: one group, x = f after one sweep (exactly)."""
+    n = 50
+    f = np.random.default_rng(8).standard_normal(n)
+    s = synth.from_dense(np.eye(n), f=f)
+    pl = oracle.plan_system(s, 0.1)
+    assert pl.ngroups == 1
+    assert np.array_equal(oracle.solve(pl, 1), f)
+
+
+def test_identical_rows_are_singletons_and_sequential():
+    """All rows identical: every pair has |cos| = 1, so n singleton groups and
+    the sweep is classic sequential Kaczmarz; a consistent f is met after one
+    sweep."""
+    n = 12
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(n)
+    M = np.tile(a, (n, 1))
+    xs = rng.standard_normal(n)
+    f = M @ xs
+    pl = _identity_plan(M, f, 0.1)
+    assert pl.ngroups == n
+    assert sorted(pl.group.tolist()) == list(range(n))
+    x0 = rng.standard_normal(n)
+    x = oracle.sweep(pl, x0, 1)
+    np.testing.assert_allclose(x, _kaczmarz_textbook(M, f, x0, list(range(n))), rtol=1e-13, atol=1e-13)
+    assert np.abs(M @ x - f).max() < 1e-12 * np.abs(f).max()
+
+
+def test_threshold_above_one_gives_single_simultaneous_step():
+    """delta > 1: no pair can conflict (|cos| <= 1), one group, and one sweep is
+    the simultaneous step x + A^T D^-1 (f - A x) of all rows."""
+    s = synth.c1(n=150)
+    pl = oracle.plan_system(s, 1.5)
+    assert pl.ngroups == 1
+    D = sp.csr_matrix((pl.v, pl.ci, pl.rp), shape=(s.n, s.n)).toarray()
+    x0 = np.random.default_rng(2).standard_normal(s.n)
+    want = x0 + D.T @ ((pl.f - D @ x0) / (D * D).sum(1))
+    np.testing.assert_allclose(oracle.sweep(pl, x0, 1), want, rtol=1e-12, atol=1e-12)
+
+
+# -------------------------------------------- P7: convergence (Theorem 1)
+def test_converges_to_generating_solution():
+    """Theorem 1: consistent systems converge to x* (= A^+ f, A nonsingular)."""
+    s = synth.c1(companion=True)
+    pl = oracle.plan_system(s, 0.1)
+    x = oracle.solve(pl, 60)
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) < 1e-10
+    s = synth.c2(grid=16)
+    pl = oracle.plan_system(s, 0.1)
+    x = oracle.solve(pl, 20000)
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) < 1e-10
+
+
+def test_minimum_norm_limit_for_singular_consistent_system():
+    """Theorem 1: from x0 = 0 the limit is the minimum-norm solution A^+ f."""
+    rng = np.random.default_rng(11)
+    n = 30
+    B = sp.random(n, n, density=0.15, random_state=3).toarray() + np.diag(rng.uniform(1, 2, n))
+    B[5] = B[3] + B[7]              # rank deficient, still consistent
+    B[20] = 0.0                     # a zero row, left out of every group
+    xs = rng.standard_normal(n)
+    f = B @ xs
+    s = synth.from_dense(B, f=f)
+    pl = oracle.plan_system(s, 0.1)
+    assert pl.group[np.nonzero(pl.p == 20)[0][0]] == -1
+    x = oracle.solve(pl, 40000)
+    want = np.linalg.pinv(B) @ f
+    np.testing.assert_allclose(x, want, rtol=0, atol=1e-7 * np.abs(want).max())
+
+
+def test_error_non_increasing_each_sweep():
+    """Every group step is non-expansive in the error when the group's unit rows
+    have lambda_max < 2 (Gershgorin bound checked here); the error norm then
+    never grows from sweep to sweep (eq. 3.8 for exact groups)."""
+    s = synth.c1()
+    pl = oracle.plan_system(s, 0.1)
+    D = sp.csr_matrix((pl.v, pl.ci, pl.rp), shape=(s.n, s.n))
+    B = sp.diags(1 / np.sqrt(pl.nu)) @ D
+    for g in range(pl.ngroups):
+        rows = np.nonzero(pl.group == g)[0]
+        Bg = B[rows]
+        G = abs(Bg @ Bg.T)
+        assert G.sum(1).max() < 2.0
+    xs_t = oracle.permute_vec(pl.p, s.x_star)
+    x = np.zeros(s.n)
+    e_prev = np.linalg.norm(x - xs_t)
+    for _ in range(30):
+        x = oracle.sweep(pl, x, 1)
+        e = np.linalg.norm(x - xs_t)
+        assert e <= e_prev * (1 + 1e-14)
+        e_prev = e
+
+
+# ---------------------------------------------- O9 residual, O11 refine
+def test_relres_against_scipy():
+    s = synth.c1(n=500)
+    x = np.random.default_rng(4).standard_normal(s.n)
+    r = s.f - s.scipy() @ x
+    np.testing.assert_allclose(oracle.relres(s.n, s.row_ptr, s.col, s.val, s.f, x),
+                               np.linalg.norm(r) / np.linalg.norm(s.f), rtol=1e-13)
+
+
+def test_refinement_reaches_tolerance():
+    """Iterative refinement around the sweep reaches relative residual 1e-10."""
+    s = synth.c1(companion=True)
+    pl = oracle.plan_system(s, 0.1)
+    xt, steps, rho = oracle.refine(pl, inner=8, outer=50, tol=1e-10)
+    assert rho <= 1e-10
+    assert steps >= 2
+    x = oracle.unpermute(pl.p, xt)
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) < 1e-9
+
+
+# ---------------------------------------------------------- O1 validate
+def test_validate_rejects_bad_input():
+    rp = np.array([0, 2, 3], np.int64)
+    assert oracle.validate(2, rp, np.array([0, 1, 1], np.int32), np.ones(3)) == 0
+    assert oracle.validate(2, rp, np.array([0, 0, 1], np.int32), np.ones(3)) == -2       # duplicate
+    assert oracle.validate(2, rp, np.array([0, 2, 1], np.int32), np.ones(3)) == -2       # out of range
+    assert oracle.validate(2, rp, np.array([0, 1, 1], np.int32), np.array([1, np.nan, 1])) == -4
+    assert oracle.validate(2, rp, np.array([0, 1, 1], np.int32), np.ones(3), np.array([1, np.inf])) == -4
+    assert oracle.validate(2, np.array([0, 3, 2], np.int64), np.array([0, 1, 1], np.int32), np.ones(3)) == -2
