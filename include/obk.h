@@ -1,0 +1,196 @@
+/*
+ * obk.h -- C ABI of libobk, an MI355X (gfx950) implementation of the hot path
+ * of OBK-RCM (Liang & Li, "OBK-RCM: Accelerated Orthogonal Block Kaczmarz
+ * Algorithm via RCM Reordering and Dynamic Grouping for Sparse Linear
+ * Systems").
+ *
+ * The library solves the square sparse system A x = f (eq. 1.1) as follows:
+ *   obk_plan   RCM reordering A~ = P A P^T, f~ = P f (Section 3.2, eqs.
+ *              3.1-3.2), squared row norms (denominator of eq. 1.2), the row
+ *              cosine table thresholded at delta (Section 3.3, one-row blocks)
+ *              and the grouping of mutually near-orthogonal rows (the
+ *              Oclass/Nclass rule of Section 3.3 taken to maximal classes:
+ *              first-fit in reordered row order);
+ *   obk_solve  sweeps of the orthogonal-group block Kaczmarz step: for each
+ *              group in ascending id, w_i = (f_i - a_i x) / ||a_i||^2 for all
+ *              rows of the group from the same x, then x += sum_i w_i a_i^T
+ *              (eq. 3.3; eq. 1.3 when the rows are exactly orthogonal), and
+ *              finally x = P^T x~ (Algorithm 4, last step).
+ *
+ * Conventions shared by every entry point:
+ *  - CSR: int64 row_ptr[n+1] (row_ptr[0] = 0), int32 col[nnz], double
+ *    val[nnz].  Rows may be unsorted; a repeated (row, col) is an error;
+ *    explicit zeros are kept as structure.  Only square matrices are accepted.
+ *  - Memory spaces: obk_csr.on_device says whether the CSR arrays and f are
+ *    host or device pointers.  x0 and x of obk_solve live in the same space
+ *    as the CSR given to obk_plan.  The caller owns every pointer it passes;
+ *    obk_plan copies what it needs, so the inputs may be freed once it
+ *    returns.
+ *  - Streams: all device work is enqueued on the given hipStream_t (0 = the
+ *    null stream); calls return after synchronising that stream.
+ *  - Errors: each call returns an obk_status; a message for the last error
+ *    of the calling thread is available from obk_last_error().  On error no
+ *    output handle is produced and nothing leaks.  No exception crosses the
+ *    ABI.
+ *  - A plan is immutable after obk_plan and owns its device workspace; one
+ *    solve per plan may run at a time (a second concurrent solve on the same
+ *    plan returns OBK_E_BUSY).
+ */
+#ifndef OBK_H
+#define OBK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define OBK_API __attribute__((visibility("default")))
+#else
+#define OBK_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *obk_stream_t;   /* the same type as hipStream_t */
+typedef struct obk_plan_s *obk_plan_t;
+
+typedef enum {
+    OBK_OK = 0,
+    OBK_E_ARG = -1,         /* bad argument (null pointer, negative size, bad option) */
+    OBK_E_CSR = -2,         /* malformed CSR: row_ptr not monotone, column out of range, duplicate */
+    OBK_E_NOT_SQUARE = -3,  /* n_rows != n_cols */
+    OBK_E_NONFINITE = -4,   /* NaN or Inf in val or f */
+    OBK_E_NOMEM = -5,       /* device or host allocation failed, or over opts.hbm_budget */
+    OBK_E_HIP = -6,         /* a HIP runtime call failed */
+    OBK_E_BUSY = -7,        /* a solve on this plan is already running */
+    OBK_E_INCONSISTENT = -8 /* a zero row with f_i != 0 (reported by obk_plan only when
+                               opts.reject_inconsistent is set) */
+} obk_status;
+
+/* Solve outcome written to obk_info.status. */
+enum {
+    OBK_CONVERGED = 0,      /* relative residual <= tol */
+    OBK_MAXIT = 1,          /* maxit sweeps done (always the outcome when tol <= 0) */
+    OBK_DIVERGED = 2,       /* relative residual grew above 1e3 x its initial value */
+    OBK_NONFINITE_ITERATE = 3
+};
+
+/* Arithmetic of the sweep. */
+enum {
+    OBK_FP64 = 0,           /* plain FP64 sweeps */
+    OBK_FP32_IR = 1         /* FP32 sweeps inside FP64 iterative refinement (residual,
+                               norms, scaling and the update stay FP64) */
+};
+
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    const int64_t *row_ptr;  /* [n_rows+1] */
+    const int32_t *col;      /* [nnz] */
+    const double *val;       /* [nnz] */
+    int on_device;           /* 1: the three arrays (and f, x0, x) are device pointers */
+} obk_csr;
+
+typedef struct {
+    int use_rcm;             /* 1 (default): reverse Cuthill-McKee; 0: identity ordering */
+    int precision;           /* OBK_FP64 (default) or OBK_FP32_IR */
+    int inner_sweeps;        /* OBK_FP32_IR: FP32 sweeps per refinement step (default 8) */
+    int check_every;         /* sweeps between residual checks when tol > 0 (default 1) */
+    int reject_inconsistent; /* 1: obk_plan fails with OBK_E_INCONSISTENT on a zero row
+                                with f_i != 0; 0 (default): such rows are skipped */
+    size_t hbm_budget;       /* 0: unlimited; else obk_plan fails with OBK_E_NOMEM when the
+                                plan's device footprint would exceed it */
+} obk_opts;
+
+typedef struct {
+    int64_t sweeps;          /* sweeps performed (FP32 inner sweeps in OBK_FP32_IR) */
+    int64_t outer_steps;     /* refinement steps (OBK_FP32_IR), else residual checks */
+    double relres0;          /* ||f~ - A~ x~0|| / ||f~|| */
+    double relres;           /* last computed relative residual (-1 if never computed) */
+    double seconds;          /* wall time of the solve, host clock */
+    int status;              /* OBK_CONVERGED | OBK_MAXIT | OBK_DIVERGED | OBK_NONFINITE_ITERATE */
+} obk_info;
+
+/* Fill *opts with the defaults listed above. */
+OBK_API obk_status obk_opts_default(obk_opts *opts);
+
+/*
+ * Build a plan for A x = f (Algorithm 4, first four steps, with one-row
+ * blocks; Sections 3.2-3.3).  delta is the cosine threshold: rows i, j are
+ * near-orthogonal iff |cos(a_i, a_j)| < delta (|cos| = |a_i . a_j| /
+ * sqrt(||a_i||^2 ||a_j||^2), computed in FP64 with sums in ascending column
+ * order).  opts may be NULL (defaults).  On success *out receives a plan that
+ * owns device copies of the reordered, grouped system.
+ * Errors: OBK_E_ARG, OBK_E_NOT_SQUARE, OBK_E_CSR, OBK_E_NONFINITE,
+ * OBK_E_NOMEM, OBK_E_HIP, OBK_E_INCONSISTENT.
+ */
+OBK_API obk_status obk_plan(const obk_csr *A, const double *f, double delta, const obk_opts *opts,
+                    obk_stream_t stream, obk_plan_t *out);
+
+/*
+ * Run sweeps from x0 (NULL: x0 = 0, the paper's start, Section 3.5) and write
+ * the result in the original ordering to x.  With tol > 0 the relative
+ * residual ||f - A x|| / ||f|| is checked every opts.check_every sweeps (each
+ * refinement step in OBK_FP32_IR) and the solve stops once it is <= tol; with
+ * tol <= 0 exactly maxit sweeps run (refinement steps for OBK_FP32_IR) and no
+ * residual is computed except relres0/relres in info.  info may be NULL.
+ * Errors: OBK_E_ARG, OBK_E_BUSY, OBK_E_HIP.
+ */
+OBK_API obk_status obk_solve(obk_plan_t plan, const double *x0, double tol, int64_t maxit, double *x,
+                     obk_info *info, obk_stream_t stream);
+
+/* Release a plan and its device memory.  NULL is a no-op. */
+OBK_API void obk_free(obk_plan_t plan);
+
+/* Introspection (host outputs). */
+/* p_host[t] = original index of reordered row t (new -> old), n entries. */
+OBK_API obk_status obk_plan_perm(obk_plan_t plan, int32_t *p_host);
+/* group_of_row_host[t] = group of reordered row t (-1 for an all-zero row);
+ * *n_groups = number of groups.  Either output may be NULL. */
+OBK_API obk_status obk_plan_groups(obk_plan_t plan, int32_t *group_of_row_host, int32_t *n_groups);
+/* Device bytes owned by the plan (for admission against an HBM budget). */
+OBK_API obk_status obk_plan_bytes(obk_plan_t plan, size_t *device_bytes);
+/* Sizes: n, nnz, number of groups, bandwidth of A~, number of conflicting pairs. */
+OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int32_t *n_groups,
+                          int64_t *bandwidth, int64_t *n_conflicts);
+
+/*
+ * Sweeps on a plan with device-resident iterates, no host synchronisation and
+ * no residual (the form a benchmark or a batched driver times): x~ (device,
+ * reordered coordinates, n entries) is updated in place by `sweeps` sweeps.
+ * Enqueued on stream; returns without waiting.
+ */
+OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_t sweeps,
+                            obk_stream_t stream);
+
+/*
+ * Host stages of obk_plan, exported so that they can be used and tested
+ * without a GPU.
+ *
+ * obk_rcm_host: reverse Cuthill-McKee order (Section 3.2) of an undirected
+ * graph given as a symmetric adjacency structure without self loops:
+ * gptr[n+1] (int64 offsets), gadj[gptr[n]] (neighbours).  Tie-break: each
+ * breadth-first search starts at the unvisited vertex of least (degree,
+ * index); unvisited neighbours are visited by ascending (degree, index); the
+ * whole Cuthill-McKee sequence is reversed.  perm[t] (caller-allocated, n) =
+ * vertex placed at position t.
+ *
+ * obk_first_fit_host: grouping of Section 3.3 in its maximal form: rows in
+ * ascending order; row i joins the least group holding no row j < i that
+ * conflicts with it.  cptr[n+1], cidx: for each row the conflicting rows
+ * j < i (any order).  active[i] = 0 marks a row that joins no group (-1).
+ * group[n] and *n_groups are outputs.
+ * Errors: OBK_E_ARG for NULL pointers or negative n.
+ */
+OBK_API obk_status obk_rcm_host(int64_t n, const int64_t *gptr, const int32_t *gadj, int32_t *perm);
+OBK_API obk_status obk_first_fit_host(int64_t n, const int64_t *cptr, const int32_t *cidx,
+                                      const uint8_t *active, int32_t *group, int32_t *n_groups);
+
+/* Thread-local message for the last failing call of this thread ("" if none). */
+OBK_API const char *obk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OBK_H */

@@ -1,0 +1,280 @@
+"""Python binding of libobk (ctypes): argument marshalling only.
+
+Every step of the plan and the sweep runs inside ``libobk.so`` (HIP kernels
+for gfx950 plus the host graph passes).  There is no fallback: if the library
+is not built, importing works but the first call raises ``ObkError``.
+
+Inputs are numpy arrays (host memory) or torch CUDA tensors (device memory,
+``on_device``); torch is used only for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Any
+
+import numpy as np
+
+__all__ = ["ObkError", "Plan", "plan", "plan_system", "rcm_host", "first_fit_host", "lib", "LIB_PATH", "STATUS", "FP64", "FP32_IR"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libobk.so")
+
+FP64, FP32_IR = 0, 1
+STATUS = {0: "converged", 1: "maxit", 2: "diverged", 3: "nonfinite"}
+ERRORS = {-1: "OBK_E_ARG", -2: "OBK_E_CSR", -3: "OBK_E_NOT_SQUARE", -4: "OBK_E_NONFINITE",
+          -5: "OBK_E_NOMEM", -6: "OBK_E_HIP", -7: "OBK_E_BUSY", -8: "OBK_E_INCONSISTENT"}
+
+
+class ObkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("on_device", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("use_rcm", ctypes.c_int), ("precision", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("reject_inconsistent", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("outer_steps", ctypes.c_int64), ("relres0", ctypes.c_double),
+                ("relres", ctypes.c_double), ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+@dataclasses.dataclass
+class Info:
+    sweeps: int
+    outer_steps: int
+    relres0: float
+    relres: float
+    seconds: float
+    status: str
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ObkError(-6, f"{LIB_PATH} is not built (run __graft_entry__.build() or "
+                               "python paper_2401_00672_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.obk_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+        L.obk_plan.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
+                               ctypes.POINTER(_P)]
+        L.obk_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.POINTER(_Info), _P]
+        L.obk_free.argtypes = [_P]
+        L.obk_free.restype = None
+        L.obk_plan_perm.argtypes = [_P, _P]
+        L.obk_plan_groups.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int32)]
+        L.obk_plan_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
+        L.obk_plan_stats.argtypes = [_P] + [ctypes.POINTER(ctypes.c_int64)] * 2 + \
+            [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_int64)] * 2
+        L.obk_sweep_device.argtypes = [_P, _P, ctypes.c_int64, _P]
+        L.obk_last_error.restype = ctypes.c_char_p
+        L.obk_rcm_host.argtypes = [ctypes.c_int64, _P, _P, _P]
+        L.obk_first_fit_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]
+        for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
+                     "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_rcm_host",
+                     "obk_first_fit_host"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> None:
+    if code != 0:
+        raise ObkError(code, lib().obk_last_error().decode(errors="replace"))
+
+
+def _is_torch(a: Any) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _dev_ptr(t, dtype_name: str) -> int:
+    import torch
+    want = {"int64": torch.int64, "int32": torch.int32, "float64": torch.float64}[dtype_name]
+    if not t.is_cuda or t.dtype != want or not t.is_contiguous():
+        raise ObkError(-1, f"expected a contiguous CUDA tensor of {dtype_name}")
+    return t.data_ptr()
+
+
+def _host(a, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stream(stream) -> int | None:
+    if stream is not None:
+        return int(stream)
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Plan:
+    """A device-resident OBK-RCM plan (reordered, grouped system + workspace)."""
+
+    def __init__(self, handle: int, n: int, nnz: int, on_device: bool):
+        self._h = handle
+        self.n = n
+        self.nnz = nnz
+        self.on_device = on_device
+
+    # -- lifetime
+    def free(self) -> None:
+        if self._h:
+            lib().obk_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ObkError(-1, "plan has been freed")
+        return self._h
+
+    # -- solve
+    def solve(self, x0=None, tol: float = 0.0, maxit: int = 100, out=None, stream=None):
+        """Sweeps from x0 (None = 0); returns (x, Info).  x is a numpy array for a
+        host plan and a torch CUDA tensor for a device plan."""
+        info = _Info()
+        if self.on_device:
+            import torch
+            x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+            px = _dev_ptr(x, "float64")
+            p0 = None if x0 is None else _dev_ptr(x0, "float64")
+            st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+        else:
+            x = out if out is not None else np.empty(self.n, dtype=np.float64)
+            px = x.ctypes.data
+            x0h = None if x0 is None else _host(x0, np.float64)
+            p0 = None if x0h is None else x0h.ctypes.data
+            st = _stream(stream)
+        _check(lib().obk_solve(self.handle, p0, float(tol), int(maxit), px, ctypes.byref(info), st))
+        return x, Info(info.sweeps, info.outer_steps, info.relres0, info.relres, info.seconds,
+                       STATUS.get(info.status, str(info.status)))
+
+    def sweep_device(self, x_tilde, sweeps: int, stream=None) -> None:
+        """Enqueue `sweeps` sweeps on a device iterate in reordered coordinates."""
+        import torch
+        st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+        _check(lib().obk_sweep_device(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st))
+
+    # -- introspection
+    def perm(self) -> np.ndarray:
+        p = np.empty(self.n, dtype=np.int32)
+        _check(lib().obk_plan_perm(self.handle, p.ctypes.data))
+        return p
+
+    def groups(self):
+        g = np.empty(self.n, dtype=np.int32)
+        ng = ctypes.c_int32(0)
+        _check(lib().obk_plan_groups(self.handle, g.ctypes.data, ctypes.byref(ng)))
+        return g, int(ng.value)
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t(0)
+        _check(lib().obk_plan_bytes(self.handle, ctypes.byref(b)))
+        return int(b.value)
+
+    def stats(self) -> dict:
+        n, nnz, bw, nc = (ctypes.c_int64() for _ in range(4))
+        ng = ctypes.c_int32()
+        _check(lib().obk_plan_stats(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(ng),
+                                    ctypes.byref(bw), ctypes.byref(nc)))
+        return {"n": n.value, "nnz": nnz.value, "groups": ng.value, "bandwidth": bw.value,
+                "conflicts": nc.value}
+
+
+def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: int | None = None,
+         use_rcm: bool = True, precision: int = FP64, inner_sweeps: int = 8, check_every: int = 1,
+         reject_inconsistent: bool = False, hbm_budget: int = 0, stream=None) -> Plan:
+    """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device)."""
+    on_device = _is_torch(row_ptr)
+    if on_device:
+        nrows = int(row_ptr.numel()) - 1 if n is None else int(n)
+        nnz = int(col.numel())
+        keep = (row_ptr, col, val, f)
+        ptrs = (_dev_ptr(row_ptr, "int64"), _dev_ptr(col, "int32"), _dev_ptr(val, "float64"),
+                _dev_ptr(f, "float64"))
+        import torch
+        st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+    else:
+        rp, ci, v, ff = _host(row_ptr, np.int64), _host(col, np.int32), _host(val, np.float64), \
+            _host(f, np.float64)
+        nrows = len(rp) - 1 if n is None else int(n)
+        nnz = len(ci)
+        keep = (rp, ci, v, ff)
+        ptrs = (rp.ctypes.data, ci.ctypes.data if nnz else None, v.ctypes.data if nnz else None,
+                ff.ctypes.data)
+        st = _stream(stream)
+    csr = _Csr(nrows, nrows if n_cols is None else int(n_cols), nnz, ptrs[0], ptrs[1], ptrs[2],
+               1 if on_device else 0)
+    opts = _Opts()
+    lib().obk_opts_default(ctypes.byref(opts))
+    opts.use_rcm = 1 if use_rcm else 0
+    opts.precision = int(precision)
+    opts.inner_sweeps = int(inner_sweeps)
+    opts.check_every = int(check_every)
+    opts.reject_inconsistent = 1 if reject_inconsistent else 0
+    opts.hbm_budget = int(hbm_budget)
+    h = _P()
+    _check(lib().obk_plan(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
+    del keep
+    return Plan(h.value, nrows, nnz, on_device)
+
+
+def rcm_host(gptr, gadj) -> np.ndarray:
+    """obk_rcm_host: RCM order of a symmetric adjacency structure (no GPU needed)."""
+    gptr = _host(gptr, np.int64)
+    gadj = _host(gadj, np.int32)
+    n = len(gptr) - 1
+    perm = np.empty(max(n, 0), dtype=np.int32)
+    _check(lib().obk_rcm_host(n, gptr.ctypes.data, gadj.ctypes.data if gadj.size else None,
+                              perm.ctypes.data if n else None))
+    return perm
+
+
+def first_fit_host(cptr, cidx, active):
+    """obk_first_fit_host: first-fit grouping from conflict lists (no GPU needed)."""
+    cptr = _host(cptr, np.int64)
+    cidx = _host(cidx, np.int32)
+    active = _host(active, np.uint8)
+    n = len(cptr) - 1
+    g = np.empty(max(n, 0), dtype=np.int32)
+    ng = ctypes.c_int32(0)
+    _check(lib().obk_first_fit_host(n, cptr.ctypes.data, cidx.ctypes.data if cidx.size else None,
+                                    active.ctypes.data, g.ctypes.data if n else None, ctypes.byref(ng)))
+    return g, int(ng.value)
+
+
+def plan_system(s, delta: float, **kw) -> Plan:
+    """obk_plan on a ``synth.System`` (host arrays)."""
+    return plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)

@@ -1,0 +1,142 @@
+// Host parts of the plan: the two inherently sequential graph passes (reverse
+// Cuthill-McKee, first-fit grouping), the sweep tile schedule, errors and
+// device-memory bookkeeping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "obk_internal.h"
+
+namespace obk {
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+void fail(obk_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        obk_status code = (e == hipErrorOutOfMemory) ? OBK_E_NOMEM : OBK_E_HIP;
+        fail(code, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void DevMem::alloc(size_t b) {
+    release();
+    if (b == 0) b = 16;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(OBK_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+    }
+    ptr = p;
+    bytes = b;
+}
+
+void DevMem::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// --------------------------------------------------------------------- RCM
+// Section 3.2 names reverse Cuthill-McKee without a tie-break; this file
+// fixes one (stated in obk.h and below) so that the order is unique.
+void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm) {
+    if (n <= 0) return;
+    // Vertices ordered by (degree, index): counting sort on the degree keeps
+    // ascending index within a degree.
+    int64_t maxdeg = 0;
+    for (int64_t v = 0; v < n; v++) maxdeg = std::max(maxdeg, gptr[v + 1] - gptr[v]);
+    std::vector<int64_t> bucket(maxdeg + 2, 0);
+    for (int64_t v = 0; v < n; v++) bucket[gptr[v + 1] - gptr[v] + 1]++;
+    for (int64_t d = 0; d <= maxdeg; d++) bucket[d + 1] += bucket[d];
+    std::vector<int32_t> by_degree(n);
+    for (int64_t v = 0; v < n; v++) by_degree[bucket[gptr[v + 1] - gptr[v]]++] = (int32_t)v;
+
+    std::vector<uint8_t> seen(n, 0);
+    std::vector<int32_t> cm(n);          // Cuthill-McKee sequence, doubles as the FIFO
+    std::vector<int32_t> fresh;
+    fresh.reserve(256);
+    int64_t head = 0, tail = 0, next_start = 0;
+    auto deg = [&](int32_t v) { return gptr[v + 1] - gptr[v]; };
+    auto before = [&](int32_t a, int32_t b) {
+        int64_t da = deg(a), db = deg(b);
+        return da != db ? da < db : a < b;
+    };
+    while (tail < n) {
+        if (head == tail) {               // new component
+            while (seen[by_degree[next_start]]) next_start++;
+            int32_t s = by_degree[next_start];
+            seen[s] = 1;
+            cm[tail++] = s;
+        }
+        int32_t v = cm[head++];
+        fresh.clear();
+        for (int64_t k = gptr[v]; k < gptr[v + 1]; k++) {
+            int32_t u = gadj[k];
+            if (!seen[u]) { seen[u] = 1; fresh.push_back(u); }
+        }
+        // neighbour lists are short: insertion sort by (degree, index)
+        for (size_t a = 1; a < fresh.size(); a++) {
+            int32_t key = fresh[a];
+            size_t b = a;
+            while (b > 0 && before(key, fresh[b - 1])) { fresh[b] = fresh[b - 1]; b--; }
+            fresh[b] = key;
+        }
+        for (int32_t u : fresh) cm[tail++] = u;
+    }
+    for (int64_t t = 0; t < n; t++) perm[t] = cm[n - 1 - t];
+}
+
+// -------------------------------------------------------- first-fit groups
+// Section 3.3 puts each block with the first later block it is (near-)
+// orthogonal to; taken to maximal classes this is first-fit colouring in
+// row order.
+int32_t host_first_fit(int64_t n, const int64_t* cptr, const int32_t* cidx, const uint8_t* active,
+                       int32_t* colour) {
+    std::vector<int64_t> stamp;   // stamp[c] == i: colour c is taken by a conflicting row of i
+    int32_t ncol = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!active[i]) { colour[i] = -1; continue; }
+        for (int64_t t = cptr[i]; t < cptr[i + 1]; t++) {
+            int32_t c = colour[cidx[t]];
+            if (c >= 0) {
+                if ((size_t)c >= stamp.size()) stamp.resize((size_t)c + 1, -1);
+                stamp[c] = i;
+            }
+        }
+        int32_t c = 0;
+        while ((size_t)c < stamp.size() && stamp[c] == i) c++;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+// ---------------------------------------------------------------- tiles
+void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Tile>& out) {
+    int64_t s = seg0;
+    while (s < seg1) {
+        int64_t e = s + 1;
+        while (e < seg1 && e - s < kTileThreads && off[e + 1] - off[s] <= kTileEntries) e++;
+        Tile t;
+        t.seg_begin = (int32_t)s;
+        t.seg_end = (int32_t)e;
+        t.ent_begin = off[s];
+        t.ent_end = off[e];
+        out.push_back(t);
+        s = e;
+    }
+}
+
+}  // namespace obk

@@ -1,0 +1,140 @@
+// Internal declarations of libobk (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/obk.h"
+
+namespace obk {
+
+// ---------------------------------------------------------------- errors
+// Thrown inside the library only; every ABI entry point catches and converts.
+struct Error {
+    obk_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(obk_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+#define OBK_HIP(call) ::obk::check_hip((call), #call)
+void set_last_error(const std::string& msg);
+
+// ------------------------------------------------------- device memory
+// Owning device buffer; all plan memory goes through it so that the plan
+// can report its footprint.
+struct DevMem {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DevMem& operator=(DevMem&& o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevMem() { release(); }
+    void alloc(size_t b);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+template <class T> struct DevArray {
+    DevMem mem;
+    size_t count = 0;
+    void alloc(size_t n) { mem.alloc(n * sizeof(T) + (n == 0 ? sizeof(T) : 0)); count = n; }
+    T* get() const { return mem.as<T>(); }
+    size_t bytes() const { return mem.bytes; }
+};
+
+// ------------------------------------------------------- device primitives
+// Exclusive prefix sum of n int64 values (in -> out, may alias); returns the
+// total on the host (synchronises the stream).
+int64_t scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+// Same for int32 counts producing int64 offsets.
+int64_t scan_counts_i32(const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs by the low `key_bits` bits of
+// the uint32 keys.  keys/vals are sorted in place (scratch of equal size is
+// allocated internally).  vals may be null (keys only).
+void radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int key_bits, hipStream_t s);
+int bits_for(uint64_t max_value);
+
+// ----------------------------------------------------------- host graph
+// Reverse Cuthill-McKee order of an undirected graph given as a symmetric
+// adjacency structure without self loops (gptr[n+1], gadj[gptr[n]]).
+// Tie-break: start at the unvisited vertex of least (degree, index); visit
+// unvisited neighbours by ascending (degree, index); reverse the whole
+// Cuthill-McKee sequence.  perm[t] = old index of new position t.
+void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm);
+// First-fit colouring in row order: row i takes the least colour not used
+// by any conflicting row j < i (conflict lists cptr[n+1], cidx).  Rows with
+// active[i] == 0 get colour -1.  Returns the number of colours.
+int32_t host_first_fit(int64_t n, const int64_t* cptr, const int32_t* cidx, const uint8_t* active,
+                       int32_t* colour);
+
+// --------------------------------------------------------- sweep schedule
+// A tile is a contiguous range of "segments" (rows of a group in phase R,
+// touched columns of a group in phase S) whose entries are reduced by one
+// workgroup.  seg_begin/seg_end index segments, ent_begin/ent_end entries.
+struct Tile {
+    int32_t seg_begin, seg_end;
+    int64_t ent_begin, ent_end;
+};
+constexpr int kTileThreads = 256;        // threads per sweep workgroup
+constexpr int kTileEntries = 2048;       // entries staged per chunk (8 per thread)
+// Split segments [0, nseg) with offsets off[nseg+1] into tiles of at most
+// kTileThreads segments and (unless a single segment is longer) at most
+// kTileEntries entries.
+void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Tile>& out);
+
+}  // namespace obk
+
+// --------------------------------------------------------------- the plan
+struct obk_plan_s {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    int64_t m = 0;              // rows that take part in a group (nonzero rows)
+    int32_t ngroups = 0;
+    int64_t bandwidth = 0;
+    int64_t nconflicts = 0;
+    obk_opts opts{};
+    double delta = 0;
+    bool input_on_device = false;
+    bool busy = false;
+
+    // host copies (introspection, schedule)
+    std::vector<int32_t> h_perm;       // new -> old
+    std::vector<int32_t> h_group;      // group of each reordered row (-1 zero row)
+    std::vector<int64_t> h_gptr;       // group g = group-major rows [gptr[g], gptr[g+1])
+    std::vector<int64_t> h_tptr;       // touched columns of group g: [tptr[g], tptr[g+1])
+    std::vector<obk::Tile> h_rtiles, h_stiles;
+    std::vector<int32_t> h_rtile_ptr, h_stile_ptr;   // tiles of group g
+
+    // device: permutation
+    obk::DevArray<int32_t> perm;       // new -> old
+    // device: group-major CSR of A~ (columns in reordered numbering, rows sorted)
+    obk::DevArray<int64_t> rptr;       // [m+1]
+    obk::DevArray<int32_t> rcol;       // [nnz]
+    obk::DevArray<double> rval;        // [nnz]
+    obk::DevArray<double> rf;          // f~ in group-major order [m]
+    obk::DevArray<double> rinv;        // 1/||a||^2 in group-major order [m]
+    // device: per-group CSC (scatter-owner lists)
+    obk::DevArray<int32_t> tcol;       // touched column of each segment [T]
+    obk::DevArray<int64_t> sptr;       // [T+1]
+    obk::DevArray<int32_t> srow;       // group-major row of each entry [nnz]
+    obk::DevArray<double> sval;        // [nnz]
+    // device: tiles
+    obk::DevArray<obk::Tile> rtiles, stiles;
+    // device: workspace
+    obk::DevArray<double> x;           // reordered iterate [n]
+    obk::DevArray<double> w;           // group weights [m]
+    obk::DevArray<double> red;         // reduction scratch
+    double fnorm2 = 0;                 // ||f~||^2
+    double zero_rows_f2 = 0;           // sum of f_i^2 over all-zero rows
+
+    size_t device_bytes() const;
+};

@@ -1,0 +1,594 @@
+// obk_plan: RCM reordering, row norms, row-cosine conflicts, grouping and the
+// group-major relayout (Algorithm 4, first four steps, with one-row blocks).
+//
+// Built with -ffp-contract=off: the norms and cosines decide the grouping,
+// which must come out identical to any other IEEE-754 evaluation of the same
+// sums in the same (ascending column) order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "obk_internal.h"
+
+namespace obk {
+namespace {
+
+constexpr int kT = 256;
+inline unsigned nblk(int64_t n, int t = kT) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+enum : int { BAD_ROWPTR = 1, BAD_COL = 2, BAD_VAL = 4, BAD_F = 8, DUPLICATE = 16 };
+
+// ---------------------------------------------------------------- ingest
+__global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, const double* __restrict__ f, int* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (i <= n) {
+        int64_t r = rp[i];
+        if ((i == 0 && r != 0) || (i == n && r != nnz) || r < 0 || r > nnz) bad |= BAD_ROWPTR;
+        if (i < n && rp[i + 1] < r) bad |= BAD_ROWPTR;
+        if (i < n && !isfinite(f[i])) bad |= BAD_F;
+    }
+    if (i < nnz) {
+        if (ci[i] < 0 || (int64_t)ci[i] >= n) bad |= BAD_COL;
+        if (!isfinite(v[i])) bad |= BAD_VAL;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// row id of every entry of a CSR
+__global__ void k_row_of(int64_t n, const int64_t* __restrict__ rp, int32_t* __restrict__ row) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t k = rp[i]; k < rp[i + 1]; k++) row[k] = (int32_t)i;
+}
+
+// ----------------------------------------------------- graph of A + A^T
+__global__ void k_offdiag_flag(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ ci,
+                               int64_t* __restrict__ flag) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) flag[k] = (row[k] != ci[k]) ? 2 : 0;
+}
+
+__global__ void k_offdiag_emit(int64_t nnz, const int32_t* __restrict__ row, const int32_t* __restrict__ ci,
+                               const int64_t* __restrict__ pos, uint32_t* __restrict__ ra, uint32_t* __restrict__ cb) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    int32_t r = row[k], c = ci[k];
+    if (r == c) return;
+    int64_t p = pos[k];
+    ra[p] = (uint32_t)r; cb[p] = (uint32_t)c;
+    ra[p + 1] = (uint32_t)c; cb[p + 1] = (uint32_t)r;
+}
+
+// after sorting by (r, c): keep the first of each run of equal pairs
+__global__ void k_unique_flag(int64_t m, const uint32_t* __restrict__ ra, const uint32_t* __restrict__ cb,
+                              int64_t* __restrict__ flag) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) flag[k] = (k == 0 || ra[k] != ra[k - 1] || cb[k] != cb[k - 1]) ? 1 : 0;
+}
+
+__global__ void k_unique_emit(int64_t m, const uint32_t* __restrict__ ra, const uint32_t* __restrict__ cb,
+                              const int64_t* __restrict__ pos, int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    if (k == 0 || ra[k] != ra[k - 1] || cb[k] != cb[k - 1]) {
+        adj[pos[k]] = (int32_t)cb[k];
+        atomicAdd(&deg[ra[k]], 1);
+    }
+}
+
+// --------------------------------------------------- symmetric permutation
+__global__ void k_inverse_perm(int64_t n, const int32_t* __restrict__ p, int32_t* __restrict__ q) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) q[p[t]] = (int32_t)t;
+}
+
+__global__ void k_perm_lengths(int64_t n, const int32_t* __restrict__ p, const int64_t* __restrict__ rp,
+                               int64_t* __restrict__ len) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) len[t] = rp[p[t] + 1] - rp[p[t]];
+}
+
+// gather row p[t] into new row t, relabel columns through q
+__global__ void k_perm_gather(int64_t n, const int32_t* __restrict__ p, const int32_t* __restrict__ q,
+                              const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const int64_t* __restrict__ trp, uint32_t* __restrict__ key_col,
+                              uint32_t* __restrict__ entry, int32_t* __restrict__ trow,
+                              const double* __restrict__ f, double* __restrict__ tf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int64_t src = rp[p[t]], dst = trp[t], len = trp[t + 1] - trp[t];
+    for (int64_t k = 0; k < len; k++) {
+        key_col[dst + k] = (uint32_t)q[ci[src + k]];
+        entry[dst + k] = (uint32_t)(src + k);
+        trow[dst + k] = (int32_t)t;
+    }
+    tf[t] = f[p[t]];
+}
+
+__global__ void k_gather_u32_by(int64_t m, const uint32_t* __restrict__ idx, const int32_t* __restrict__ src,
+                                uint32_t* __restrict__ dst) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) dst[k] = (uint32_t)src[idx[k]];
+}
+
+// final permuted CSR entries: order[] lists original entry ids in (row, col) order
+__global__ void k_perm_finish(int64_t nnz, const uint32_t* __restrict__ order, const int32_t* __restrict__ ci,
+                              const int32_t* __restrict__ q, const double* __restrict__ v,
+                              const int32_t* __restrict__ trow, int32_t* __restrict__ tci,
+                              double* __restrict__ tv, int* flags, unsigned long long* bw) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    uint32_t e = order[k];
+    int32_t c = q[ci[e]];
+    tci[k] = c;
+    tv[k] = v[e];
+    int32_t r = trow[k];
+    unsigned long long d = (unsigned long long)(r > c ? r - c : c - r);
+    atomicMax(bw, d);
+    (void)flags;
+}
+
+__global__ void k_dup_check(int64_t nnz, const int32_t* __restrict__ trow, const int32_t* __restrict__ tci,
+                            int* flags) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > 0 && k < nnz && trow[k] == trow[k - 1] && tci[k] == tci[k - 1]) atomicOr(flags, DUPLICATE);
+}
+
+// --------------------------------------------------------------- norms
+// nu_i = sum_k a_ik^2 in ascending k; inv_i = 1/nu_i (denominator of eq. 1.2)
+__global__ void k_norms(int64_t n, const int64_t* __restrict__ trp, const double* __restrict__ tv,
+                        double* __restrict__ nu, double* __restrict__ inv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t k = trp[i]; k < trp[i + 1]; k++) s = s + tv[k] * tv[k];
+    nu[i] = s;
+    inv[i] = (s != 0.0) ? 1.0 / s : 0.0;
+}
+
+// ------------------------------------------------------------------ CSC
+__global__ void k_hist_i32(int64_t m, const uint32_t* __restrict__ key, int64_t* __restrict__ cnt) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) atomicAdd((unsigned long long*)&cnt[key[k]], 1ull);
+}
+
+__global__ void k_csc_fill(int64_t nnz, const uint32_t* __restrict__ order, const int32_t* __restrict__ trow,
+                           int32_t* __restrict__ crow) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) crow[k] = trow[order[k]];
+}
+
+// --------------------------------------------------------- cosine pass
+// One thread per entry (i, c) of A~.  For every row j < i stored in column c,
+// the sparse dot a_i . a_j is taken over the common columns in ascending
+// order; the pair is handled only by the entry of its first common column,
+// so each pair is evaluated once.  |cos| = |d| / sqrt(nu_i * nu_j) (Section
+// 3.3, one-row blocks); the pair conflicts iff |cos| >= delta.
+template <bool kFill>
+__global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
+                            const double* __restrict__ tv, const int32_t* __restrict__ trow,
+                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ crow,
+                            const double* __restrict__ nu, double delta, int64_t* __restrict__ count,
+                            const int64_t* __restrict__ out_pos, int32_t* __restrict__ out_idx) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t i = trow[e];
+    const int32_t c = tci[e];
+    const double nui = nu[i];
+    int64_t found = 0;
+    int64_t wpos = kFill ? out_pos[e] : 0;
+    if (nui != 0.0) {
+        const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+        for (int64_t s = cptr[c]; s < cptr[c + 1]; s++) {
+            const int32_t j = crow[s];
+            if (j >= i) break;                  // rows ascending within the column
+            const double nuj = nu[j];
+            if (nuj == 0.0) continue;
+            int64_t a = ia0, b = trp[j];
+            const int64_t b1 = trp[j + 1];
+            int32_t first = -1;
+            double d = 0.0;
+            while (a < ia1 && b < b1) {
+                const int32_t ca = tci[a], cb = tci[b];
+                if (ca < cb) a++;
+                else if (ca > cb) b++;
+                else {
+                    if (first < 0) first = ca;
+                    d = d + tv[a] * tv[b];
+                    a++; b++;
+                }
+            }
+            if (first != c) continue;
+            const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
+            if (cs >= delta) {
+                if (kFill) out_idx[wpos++] = j;
+                found++;
+            }
+        }
+    }
+    if (!kFill) count[e] = found;
+}
+
+// --------------------------------------------------------------- relayout
+__global__ void k_gm_lengths(int64_t m, const int32_t* __restrict__ grow, const int64_t* __restrict__ trp,
+                             int64_t* __restrict__ len) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < m) len[a] = trp[grow[a] + 1] - trp[grow[a]];
+}
+
+__global__ void k_gm_gather(int64_t m, const int32_t* __restrict__ grow, const int64_t* __restrict__ trp,
+                            const int32_t* __restrict__ tci, const double* __restrict__ tv,
+                            const double* __restrict__ tf, const double* __restrict__ inv,
+                            const int64_t* __restrict__ rptr, int32_t* __restrict__ rcol, double* __restrict__ rval,
+                            double* __restrict__ rf, double* __restrict__ rinv) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    int32_t t = grow[a];
+    int64_t src = trp[t], dst = rptr[a], len = rptr[a + 1] - rptr[a];
+    for (int64_t k = 0; k < len; k++) {
+        rcol[dst + k] = tci[src + k];
+        rval[dst + k] = tv[src + k];
+    }
+    rf[a] = tf[t];
+    rinv[a] = inv[t];
+}
+
+// CSC entries of active rows, keyed by the group of their row
+__global__ void k_csc_group_keys(int64_t nnz, const int32_t* __restrict__ crow, const int32_t* __restrict__ group,
+                                 int64_t* __restrict__ keep) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) keep[k] = group[crow[k]] >= 0 ? 1 : 0;
+}
+
+__global__ void k_csc_group_emit(int64_t nnz, const int32_t* __restrict__ crow, const int32_t* __restrict__ group,
+                                 const int64_t* __restrict__ pos, uint32_t* __restrict__ gkey,
+                                 uint32_t* __restrict__ cidx) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    int32_t g = group[crow[k]];
+    if (g < 0) return;
+    gkey[pos[k]] = (uint32_t)g;
+    cidx[pos[k]] = (uint32_t)k;
+}
+
+// column of each CSC position: from the CSC column pointers
+__global__ void k_csc_col_of(int64_t n, const int64_t* __restrict__ cptr, int32_t* __restrict__ ccol) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int64_t k = cptr[c]; k < cptr[c + 1]; k++) ccol[k] = (int32_t)c;
+}
+
+// after the stable sort by group: entries are in (group, column, row) order
+__global__ void k_seg_flag(int64_t me, const uint32_t* __restrict__ gkey, const uint32_t* __restrict__ cidx,
+                           const int32_t* __restrict__ ccol, int64_t* __restrict__ flag) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= me) return;
+    flag[k] = (k == 0 || gkey[k] != gkey[k - 1] || ccol[cidx[k]] != ccol[cidx[k - 1]]) ? 1 : 0;
+}
+
+__global__ void k_seg_emit(int64_t me, const uint32_t* __restrict__ gkey, const uint32_t* __restrict__ cidx,
+                           const int32_t* __restrict__ ccol, const int32_t* __restrict__ crow,
+                           const double* __restrict__ cval, const int32_t* __restrict__ pos_of_row,
+                           const int64_t* __restrict__ segpos, int32_t* __restrict__ tcol,
+                           int64_t* __restrict__ sptr, int32_t* __restrict__ srow, double* __restrict__ sval,
+                           int64_t* __restrict__ segs_per_group) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= me) return;
+    uint32_t e = cidx[k];
+    bool head = (k == 0 || gkey[k] != gkey[k - 1] || ccol[e] != ccol[cidx[k - 1]]);
+    if (head) {
+        int64_t s = segpos[k];
+        tcol[s] = ccol[e];
+        sptr[s] = k;
+        atomicAdd((unsigned long long*)&segs_per_group[gkey[k]], 1ull);
+    }
+    srow[k] = pos_of_row[crow[e]];
+    sval[k] = cval[e];
+}
+
+__global__ void k_gather_f64(int64_t m, const uint32_t* __restrict__ idx, const double* __restrict__ src,
+                             double* __restrict__ dst) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) dst[k] = src[idx[k]];
+}
+
+__global__ void k_sumsq_rows(int64_t n, const double* __restrict__ f, const double* __restrict__ nu,
+                             int only_zero_rows, double* __restrict__ partial) {
+    __shared__ double red[kT];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n && (!only_zero_rows || nu[i] == 0.0)) v = f[i] * f[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+template <class T> void to_device(DevArray<T>& d, const T* h, size_t n, hipStream_t s) {
+    d.alloc(n);
+    if (n) OBK_HIP(hipMemcpyAsync(d.get(), h, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T> void copy_in(DevArray<T>& d, const T* src, size_t n, bool on_dev, hipStream_t s) {
+    d.alloc(n);
+    if (n) OBK_HIP(hipMemcpyAsync(d.get(), src, n * sizeof(T), on_dev ? hipMemcpyDeviceToDevice
+                                                                      : hipMemcpyHostToDevice, s));
+}
+template <class T> std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) OBK_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+double host_sum_ordered(const std::vector<double>& v) {
+    double s = 0.0;
+    for (double x : v) s = s + x;
+    return s;
+}
+
+}  // namespace
+
+// Deterministic sum of f_i^2 (all rows, or only rows with nu_i = 0).
+double sum_squares(const double* f, const double* nu, int64_t n, bool only_zero_rows, hipStream_t s) {
+    if (n <= 0) return 0.0;
+    DevArray<double> part;
+    part.alloc(nblk(n));
+    k_sumsq_rows<<<nblk(n), kT, 0, s>>>(n, f, nu, only_zero_rows ? 1 : 0, part.get());
+    OBK_HIP(hipGetLastError());
+    return host_sum_ordered(to_host(part.get(), nblk(n), s));
+}
+
+// ---------------------------------------------------------------------------
+void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s) {
+    const int64_t n = A.n_rows, nnz = A.nnz;
+    const bool dev = A.on_device != 0;
+    P.n = n; P.nnz = nnz; P.delta = delta; P.input_on_device = dev;
+    OBK_HIP(hipGetDevice(&P.device));
+
+    // ---- a1: ingest and validate (square checked by the caller)
+    DevArray<int64_t> rp; DevArray<int32_t> ci; DevArray<double> v, fd;
+    copy_in(rp, A.row_ptr, n + 1, dev, s);
+    copy_in(ci, A.col, nnz, dev, s);
+    copy_in(v, A.val, nnz, dev, s);
+    copy_in(fd, f, n, dev, s);
+    DevArray<int> flags; flags.alloc(1);
+    OBK_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
+    k_validate<<<nblk(std::max(n + 1, nnz)), kT, 0, s>>>(n, nnz, rp.get(), ci.get(), v.get(), fd.get(), flags.get());
+    OBK_HIP(hipGetLastError());
+    int hflags = to_host(flags.get(), 1, s)[0];
+    if (hflags & BAD_ROWPTR) fail(OBK_E_CSR, "row_ptr is not a monotone offset array from 0 to nnz");
+    if (hflags & BAD_COL) fail(OBK_E_CSR, "column index out of range");
+    if (hflags & (BAD_VAL | BAD_F)) fail(OBK_E_NONFINITE, "NaN or Inf in the matrix values or in f");
+
+    DevArray<int32_t> row; row.alloc(nnz);
+    k_row_of<<<nblk(n), kT, 0, s>>>(n, rp.get(), row.get());
+    OBK_HIP(hipGetLastError());
+    const int nbits = bits_for((uint64_t)std::max<int64_t>(n - 1, 0));
+
+    // ---- a2: RCM on the pattern of A + A^T without the diagonal
+    std::vector<int32_t> perm(n);
+    if (P.opts.use_rcm && n > 0) {
+        DevArray<int64_t> flag; flag.alloc(nnz + 1);
+        k_offdiag_flag<<<nblk(nnz), kT, 0, s>>>(nnz, row.get(), ci.get(), flag.get());
+        OBK_HIP(hipGetLastError());
+        int64_t m2 = scan_exclusive_i64(flag.get(), flag.get(), nnz, s);
+        DevArray<uint32_t> ra, cb; ra.alloc(m2); cb.alloc(m2);
+        k_offdiag_emit<<<nblk(nnz), kT, 0, s>>>(nnz, row.get(), ci.get(), flag.get(), ra.get(), cb.get());
+        OBK_HIP(hipGetLastError());
+        // (r, c) order: stable by c, then stable by r
+        radix_sort_pairs(cb.get(), ra.get(), m2, nbits, s);
+        radix_sort_pairs(ra.get(), cb.get(), m2, nbits, s);
+        DevArray<int64_t> uflag; uflag.alloc(m2 + 1);
+        k_unique_flag<<<nblk(m2), kT, 0, s>>>(m2, ra.get(), cb.get(), uflag.get());
+        OBK_HIP(hipGetLastError());
+        int64_t mu = scan_exclusive_i64(uflag.get(), uflag.get(), m2, s);
+        DevArray<int32_t> adj, deg; adj.alloc(mu); deg.alloc(n);
+        OBK_HIP(hipMemsetAsync(deg.get(), 0, n * sizeof(int32_t), s));
+        k_unique_emit<<<nblk(m2), kT, 0, s>>>(m2, ra.get(), cb.get(), uflag.get(), adj.get(), deg.get());
+        OBK_HIP(hipGetLastError());
+        std::vector<int32_t> hdeg = to_host(deg.get(), n, s);
+        std::vector<int32_t> hadj = to_host(adj.get(), mu, s);
+        std::vector<int64_t> gptr(n + 1, 0);
+        for (int64_t i = 0; i < n; i++) gptr[i + 1] = gptr[i] + hdeg[i];
+        host_rcm(n, gptr.data(), hadj.data(), perm.data());
+    } else {
+        for (int64_t t = 0; t < n; t++) perm[t] = (int32_t)t;
+    }
+    P.h_perm = perm;
+    to_device(P.perm, perm.data(), n, s);
+
+    // ---- a3: A~ = P A P^T with rows sorted by the new column index
+    DevArray<int32_t> q; q.alloc(n);
+    k_inverse_perm<<<nblk(n), kT, 0, s>>>(n, P.perm.get(), q.get());
+    DevArray<int64_t> trp; trp.alloc(n + 1);
+    k_perm_lengths<<<nblk(n), kT, 0, s>>>(n, P.perm.get(), rp.get(), trp.get());
+    OBK_HIP(hipGetLastError());
+    int64_t tot = scan_exclusive_i64(trp.get(), trp.get(), n, s);
+    OBK_HIP(hipMemcpyAsync(trp.get() + n, &tot, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevArray<uint32_t> kcol, entry, krow; kcol.alloc(nnz); entry.alloc(nnz); krow.alloc(nnz);
+    DevArray<int32_t> trow; trow.alloc(nnz);
+    DevArray<double> tf; tf.alloc(n);
+    k_perm_gather<<<nblk(n), kT, 0, s>>>(n, P.perm.get(), q.get(), rp.get(), ci.get(), trp.get(), kcol.get(),
+                                          entry.get(), trow.get(), fd.get(), tf.get());
+    OBK_HIP(hipGetLastError());
+    // sort entries by (new row, new column): stable by column, then by row
+    radix_sort_pairs(kcol.get(), entry.get(), nnz, nbits, s);
+    // row of each entry in the current order: the new row of the original entry
+    {
+        k_gather_u32_by<<<nblk(nnz), kT, 0, s>>>(nnz, entry.get(), row.get(), krow.get());   // old row ids
+        OBK_HIP(hipGetLastError());
+        // map old row -> new row through q
+        DevArray<uint32_t> tmp; tmp.alloc(nnz);
+        k_gather_u32_by<<<nblk(nnz), kT, 0, s>>>(nnz, krow.get(), q.get(), tmp.get());
+        OBK_HIP(hipGetLastError());
+        OBK_HIP(hipMemcpyAsync(krow.get(), tmp.get(), nnz * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        OBK_HIP(hipStreamSynchronize(s));
+    }
+    radix_sort_pairs(krow.get(), entry.get(), nnz, nbits, s);
+    DevArray<int32_t> tci; DevArray<double> tv; tci.alloc(nnz); tv.alloc(nnz);
+    DevArray<unsigned long long> bw; bw.alloc(1);
+    OBK_HIP(hipMemsetAsync(bw.get(), 0, sizeof(unsigned long long), s));
+    k_perm_finish<<<nblk(nnz), kT, 0, s>>>(nnz, entry.get(), ci.get(), q.get(), v.get(), trow.get(), tci.get(),
+                                           tv.get(), flags.get(), bw.get());
+    OBK_HIP(hipGetLastError());
+    k_dup_check<<<nblk(nnz), kT, 0, s>>>(nnz, trow.get(), tci.get(), flags.get());
+    OBK_HIP(hipGetLastError());
+    hflags = to_host(flags.get(), 1, s)[0];
+    if (hflags & DUPLICATE) fail(OBK_E_CSR, "duplicate (row, col) entry");
+    P.bandwidth = (int64_t)to_host(bw.get(), 1, s)[0];
+    // free what the rest of the plan no longer needs
+    rp = DevArray<int64_t>(); ci = DevArray<int32_t>(); v = DevArray<double>(); fd = DevArray<double>();
+    row = DevArray<int32_t>(); kcol = DevArray<uint32_t>(); krow = DevArray<uint32_t>();
+    entry = DevArray<uint32_t>();
+
+    // ---- a4: row norms
+    DevArray<double> nu, inv; nu.alloc(n); inv.alloc(n);
+    k_norms<<<nblk(n), kT, 0, s>>>(n, trp.get(), tv.get(), nu.get(), inv.get());
+    OBK_HIP(hipGetLastError());
+    P.fnorm2 = sum_squares(tf.get(), nu.get(), n, false, s);
+    P.zero_rows_f2 = sum_squares(tf.get(), nu.get(), n, true, s);
+    if (P.opts.reject_inconsistent && P.zero_rows_f2 != 0.0)
+        fail(OBK_E_INCONSISTENT, "an all-zero row has a nonzero right-hand side");
+
+    // ---- a5: CSC of A~ (rows ascending within a column), then conflicts
+    DevArray<int64_t> cptr; cptr.alloc(n + 1);
+    DevArray<int32_t> crow; crow.alloc(nnz);
+    DevArray<double> cval; cval.alloc(nnz);
+    DevArray<uint32_t> order; order.alloc(nnz);
+    {
+        DevArray<uint32_t> ckey; ckey.alloc(nnz);
+        OBK_HIP(hipMemcpyAsync(ckey.get(), tci.get(), nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        std::vector<uint32_t> iota(nnz);
+        for (int64_t k = 0; k < nnz; k++) iota[k] = (uint32_t)k;
+        OBK_HIP(hipMemcpyAsync(order.get(), iota.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        OBK_HIP(hipStreamSynchronize(s));
+        radix_sort_pairs(ckey.get(), order.get(), nnz, nbits, s);
+        OBK_HIP(hipMemsetAsync(cptr.get(), 0, (n + 1) * sizeof(int64_t), s));
+        k_hist_i32<<<nblk(nnz), kT, 0, s>>>(nnz, ckey.get(), cptr.get());
+        OBK_HIP(hipGetLastError());
+        int64_t t2 = scan_exclusive_i64(cptr.get(), cptr.get(), n, s);
+        OBK_HIP(hipMemcpyAsync(cptr.get() + n, &t2, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        k_csc_fill<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), trow.get(), crow.get());
+        OBK_HIP(hipGetLastError());
+        k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());
+        OBK_HIP(hipGetLastError());
+    }
+    DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
+    k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                                crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
+    OBK_HIP(hipGetLastError());
+    int64_t nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
+    P.nconflicts = nconf;
+    DevArray<int32_t> cidx; cidx.alloc(nconf);
+    k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                               crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get());
+    OBK_HIP(hipGetLastError());
+
+    // ---- a6: first-fit grouping on the host
+    std::vector<int64_t> htrp = to_host(trp.get(), n + 1, s);
+    std::vector<int64_t> hcc = to_host(ccount.get(), nnz, s);
+    std::vector<int32_t> hcidx = to_host(cidx.get(), nconf, s);
+    std::vector<double> hnu = to_host(nu.get(), n, s);
+    std::vector<int64_t> hcptr(n + 1);
+    for (int64_t i = 0; i < n; i++) hcptr[i] = (htrp[i] < nnz) ? hcc[htrp[i]] : nconf;
+    hcptr[n] = nconf;
+    // rows with no entries start where the next row starts
+    for (int64_t i = n - 1; i >= 0; i--) if (htrp[i] == htrp[i + 1]) hcptr[i] = hcptr[i + 1];
+    std::vector<uint8_t> active(n);
+    for (int64_t i = 0; i < n; i++) active[i] = hnu[i] != 0.0;
+    std::vector<int32_t> group(n);
+    P.ngroups = host_first_fit(n, hcptr.data(), hcidx.data(), active.data(), group.data());
+    P.h_group = group;
+    ccount = DevArray<int64_t>(); cidx = DevArray<int32_t>();
+
+    // ---- a7: group-major relayout
+    const int32_t G = P.ngroups;
+    std::vector<int64_t> gsize(G + 1, 0);
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) gsize[group[i] + 1]++;
+    P.h_gptr.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) P.h_gptr[g + 1] = P.h_gptr[g] + gsize[g + 1];
+    const int64_t m = P.h_gptr[G];
+    P.m = m;
+    std::vector<int32_t> grow(m), pos_of_row(n, -1);
+    {
+        std::vector<int64_t> fill(P.h_gptr.begin(), P.h_gptr.end());
+        for (int64_t i = 0; i < n; i++)
+            if (group[i] >= 0) { int64_t a = fill[group[i]]++; grow[a] = (int32_t)i; pos_of_row[i] = (int32_t)a; }
+    }
+    // device footprint check before the persistent arrays are allocated
+    {
+        int64_t me_est = nnz;
+        size_t est = (size_t)(m + 1) * 8 + (size_t)nnz * 12 + (size_t)m * 24 + (size_t)nnz * 12 +
+                     (size_t)std::min<int64_t>(me_est, (int64_t)G * n + 1) * 12 + (size_t)n * 12;
+        if (P.opts.hbm_budget && est > P.opts.hbm_budget)
+            fail(OBK_E_NOMEM, "plan footprint " + std::to_string(est) + " B exceeds hbm_budget");
+    }
+    DevArray<int32_t> dgrow; to_device(dgrow, grow.data(), m, s);
+    DevArray<int32_t> dpos; to_device(dpos, pos_of_row.data(), n, s);
+    DevArray<int32_t> dgroup; to_device(dgroup, group.data(), n, s);
+    P.rptr.alloc(m + 1);
+    k_gm_lengths<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), P.rptr.get());
+    OBK_HIP(hipGetLastError());
+    int64_t nnz_act = scan_exclusive_i64(P.rptr.get(), P.rptr.get(), m, s);
+    OBK_HIP(hipMemcpyAsync(P.rptr.get() + m, &nnz_act, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    P.rcol.alloc(nnz_act); P.rval.alloc(nnz_act); P.rf.alloc(m); P.rinv.alloc(m);
+    k_gm_gather<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), tci.get(), tv.get(), tf.get(), inv.get(),
+                                        P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.rinv.get());
+    OBK_HIP(hipGetLastError());
+
+    // per-group CSC: CSC entries of active rows, stable-sorted by group
+    DevArray<int64_t> keep; keep.alloc(nnz + 1);
+    k_csc_group_keys<<<nblk(nnz), kT, 0, s>>>(nnz, crow.get(), dgroup.get(), keep.get());
+    OBK_HIP(hipGetLastError());
+    int64_t me = scan_exclusive_i64(keep.get(), keep.get(), nnz, s);
+    DevArray<uint32_t> gkey, gidx; gkey.alloc(me); gidx.alloc(me);
+    k_csc_group_emit<<<nblk(nnz), kT, 0, s>>>(nnz, crow.get(), dgroup.get(), keep.get(), gkey.get(), gidx.get());
+    OBK_HIP(hipGetLastError());
+    radix_sort_pairs(gkey.get(), gidx.get(), me, bits_for((uint64_t)std::max(G - 1, 0)), s);
+    DevArray<int32_t> ccol; ccol.alloc(nnz);
+    k_csc_col_of<<<nblk(n), kT, 0, s>>>(n, cptr.get(), ccol.get());
+    OBK_HIP(hipGetLastError());
+    DevArray<int64_t> segflag; segflag.alloc(me + 1);
+    k_seg_flag<<<nblk(me), kT, 0, s>>>(me, gkey.get(), gidx.get(), ccol.get(), segflag.get());
+    OBK_HIP(hipGetLastError());
+    int64_t T = scan_exclusive_i64(segflag.get(), segflag.get(), me, s);
+    P.tcol.alloc(T); P.sptr.alloc(T + 1); P.srow.alloc(me); P.sval.alloc(me);
+    DevArray<int64_t> segs_g; segs_g.alloc(std::max(G, 1));
+    OBK_HIP(hipMemsetAsync(segs_g.get(), 0, std::max(G, 1) * sizeof(int64_t), s));
+    k_seg_emit<<<nblk(me), kT, 0, s>>>(me, gkey.get(), gidx.get(), ccol.get(), crow.get(), cval.get(), dpos.get(),
+                                        segflag.get(), P.tcol.get(), P.sptr.get(), P.srow.get(), P.sval.get(),
+                                        segs_g.get());
+    OBK_HIP(hipGetLastError());
+    OBK_HIP(hipMemcpyAsync(P.sptr.get() + T, &me, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    std::vector<int64_t> hsegs = to_host(segs_g.get(), std::max(G, 1), s);
+    P.h_tptr.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) P.h_tptr[g + 1] = P.h_tptr[g] + hsegs[g];
+
+    // ---- sweep schedule: tiles per group for both phases
+    std::vector<int64_t> hrptr = to_host(P.rptr.get(), m + 1, s);
+    std::vector<int64_t> hsptr = to_host(P.sptr.get(), T + 1, s);
+    P.h_rtile_ptr.assign(G + 1, 0);
+    P.h_stile_ptr.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; g++) {
+        build_tiles(P.h_gptr[g], P.h_gptr[g + 1], hrptr.data(), P.h_rtiles);
+        P.h_rtile_ptr[g + 1] = (int32_t)P.h_rtiles.size();
+        build_tiles(P.h_tptr[g], P.h_tptr[g + 1], hsptr.data(), P.h_stiles);
+        P.h_stile_ptr[g + 1] = (int32_t)P.h_stiles.size();
+    }
+    to_device(P.rtiles, P.h_rtiles.data(), P.h_rtiles.size(), s);
+    to_device(P.stiles, P.h_stiles.data(), P.h_stiles.size(), s);
+
+    // ---- workspace
+    P.x.alloc(n);
+    P.w.alloc(m);
+    P.red.alloc(std::max<int64_t>(nblk(std::max<int64_t>(m, 1)), 1) + 16);
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace obk

@@ -1,0 +1,118 @@
+"""CPU checks of libobk: it loads, exports every declared entry point, rejects
+bad arguments before touching a GPU, and its host plan stages (RCM order,
+first-fit grouping) are bit-exact with the oracle's independent code."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+import paper_2401_00672_amd as obk
+from conftest import ROOT, parse_golden
+
+HEADER = os.path.join(ROOT, "include", "obk.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"OBK_API[^;(]*?\b(obk_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 12
+    L = obk.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_opts_default_and_free_null():
+    L = obk.lib()
+    o = obk._Opts()
+    assert L.obk_opts_default(o) == 0
+    assert (o.use_rcm, o.precision, o.inner_sweeps, o.check_every, o.reject_inconsistent, o.hbm_budget) == \
+        (1, 0, 8, 1, 0, 0)
+    L.obk_free(None)
+    assert L.obk_opts_default(None) == -1
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_cols=5), -3),               # not square (Section 4: the method needs m = n)
+    (dict(delta=0.0), -1),              # delta must be > 0
+    (dict(delta=float("nan")), -1),
+    (dict(precision=7), -1),
+    (dict(check_every=0), -1),
+])
+def test_plan_rejects_bad_arguments_before_any_gpu_work(kw, code):
+    s = synth.c1(n=6)
+    delta = kw.pop("delta", 0.1)
+    with pytest.raises(obk.ObkError) as ei:
+        obk.plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)
+    assert ei.value.code == code
+    assert obk.lib().obk_last_error().decode() != ""
+
+
+def _graph(s):
+    A = s.scipy()
+    G = ((A + A.T) != 0).astype(np.int8).tolil()
+    G.setdiag(0)
+    G = sp.csr_matrix(G)
+    G.eliminate_zeros()
+    G.sort_indices()
+    return G.indptr.astype(np.int64), G.indices.astype(np.int32)
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.c1(), lambda: synth.c2(grid=64), lambda: synth.c1(n=37),
+                                   lambda: synth.c4_system(3, n=3000),
+                                   lambda: synth.from_dense(np.eye(9))])
+def test_host_rcm_bit_exact_with_oracle(maker):
+    s = maker()
+    gptr, gadj = _graph(s)
+    assert np.array_equal(obk.rcm_host(gptr, gadj), oracle.rcm(s.n, s.row_ptr, s.col))
+
+
+@pytest.mark.parametrize("case", parse_golden("rcm_hand.txt"), ids=lambda c: c["name"])
+def test_host_rcm_hand_worked(case):
+    n = int(case["n"])
+    M = np.eye(n)
+    for e in case["stored"].split():
+        r, c = map(int, e.split("-"))
+        M[r, c] = 1.0
+    gptr, gadj = _graph(synth.from_dense(M))
+    assert obk.rcm_host(gptr, gadj).tolist() == [int(t) for t in case["p"].split()]
+
+
+def test_host_rcm_random_graphs():
+    rng = np.random.default_rng(0)
+    for trial in range(30):
+        n = int(rng.integers(1, 80))
+        M = sp.random(n, n, density=float(rng.uniform(0, 0.15)), random_state=trial, format="csr")
+        M = M + sp.eye(n)
+        s = synth.from_scipy(M)
+        gptr, gadj = _graph(s)
+        assert np.array_equal(obk.rcm_host(gptr, gadj), oracle.rcm(s.n, s.row_ptr, s.col))
+
+
+@pytest.mark.parametrize("maker,delta", [(lambda: synth.c1(), 0.1), (lambda: synth.c2(grid=64), 0.1),
+                                         (lambda: synth.c1(n=500), 0.02), (lambda: synth.c1(n=300), 0.5)])
+def test_host_first_fit_bit_exact_with_oracle(maker, delta):
+    s = maker()
+    pl = oracle.plan_system(s, delta)
+    rng = np.random.default_rng(5)
+    # conflict lists in scrambled order: the grouping must not depend on it
+    cidx = pl.cidx.copy()
+    for i in range(s.n):
+        seg = cidx[pl.cptr[i]:pl.cptr[i + 1]]
+        rng.shuffle(seg)
+    g, ng = obk.first_fit_host(pl.cptr, cidx, (pl.nu != 0).astype(np.uint8))
+    assert ng == pl.ngroups
+    assert np.array_equal(g, pl.group)
+
+
+def test_host_stage_argument_errors():
+    assert obk.lib().obk_rcm_host(-1, None, None, None) == -1
+    assert obk.lib().obk_first_fit_host(3, None, None, None, None, None) == -1
+    assert obk.rcm_host(np.zeros(1, np.int64), np.zeros(0, np.int32)).size == 0

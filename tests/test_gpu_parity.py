@@ -1,0 +1,191 @@
+"""GPU parity of libobk against the FP64 CPU oracle (through the C ABI).
+
+Bar: the RCM permutation and the group of every row are bit-exact; the
+iterate after K FP64 sweeps is within 1e-10 relative (2-norm) of the oracle's.
+Both sides sum every row and column in ascending order without FMA
+contraction, so the iterates are expected to agree to the last bit; the
+tolerance is the stated contract, the bitwise result is reported.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+import paper_2401_00672_amd as obk
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.init()
+
+
+def _arrow(n=3000, seed=3):
+    """Diagonal plus one dense row and one dense column: a row of n entries
+    spans several LDS chunks of a sweep tile."""
+    rng = np.random.default_rng(seed)
+    A = sp.lil_matrix((n, n))
+    A.setdiag(rng.uniform(1, 2, n) + n ** 0.5)
+    A[0, :] = rng.standard_normal(n)
+    A[:, 0] = rng.standard_normal((n, 1))
+    A[0, 0] = n
+    return synth.from_scipy(A.tocsr(), rng.standard_normal(n), name="arrow")
+
+
+def _zero_rows():
+    s = synth.c1(n=300)
+    A = s.scipy().tolil()
+    A[7, :] = 0          # all-zero row (skipped, f = 0 keeps it consistent)
+    A[11, 3] = 0.0       # explicit zero kept as structure
+    A = A.tocsr()
+    A[11, 3] = 0.0
+    xs = s.x_star
+    return synth.from_scipy(A, xs, name="zero-rows")
+
+
+CASES = [
+    ("c1-n2000", lambda: synth.c1(), 0.1, 200),
+    ("c1-companion", lambda: synth.c1(companion=True), 0.1, 40),
+    ("c1-delta0.02", lambda: synth.c1(), 0.02, 50),
+    ("c1-delta1.5-single-group", lambda: synth.c1(), 1.5, 10),
+    ("stencil16", lambda: synth.c2(grid=16), 0.1, 300),
+    ("stencil64", lambda: synth.c2(grid=64), 0.1, 100),
+    ("stencil200-ragged", lambda: synth.c2(grid=200), 0.1, 20),
+    ("c3-family-n20000", lambda: synth.c3(n=20000), 0.1, 10),
+    ("c4-family-n7001", lambda: synth.c4_system(5, n=7001), 0.1, 10),
+    ("arrow-long-row", _arrow, 0.1, 5),
+    ("zero-rows-explicit-zeros", _zero_rows, 0.1, 30),
+    ("identity", lambda: synth.from_dense(np.eye(33), f=np.arange(33.0)), 0.1, 1),
+    ("n1", lambda: synth.from_dense(np.array([[2.0]]), f=np.array([6.0])), 0.1, 3),
+    ("identical-rows", lambda: synth.from_dense(np.tile(np.arange(1.0, 9.0), (8, 1)), f=np.full(8, 3.0)), 0.1, 2),
+    ("no-rcm", lambda: synth.c1(n=500), 0.1, 20),
+]
+
+
+@pytest.mark.parametrize("name,maker,delta,K", CASES, ids=[c[0] for c in CASES])
+def test_plan_and_sweeps_match_oracle(name, maker, delta, K):
+    s = maker()
+    use_rcm = name != "no-rcm"
+    _say(f"[parity] {name}: n={s.n} nnz={s.nnz} delta={delta} K={K}")
+    pl_o = oracle.plan_system(s, delta, use_rcm=use_rcm)
+    with obk.plan_system(s, delta, use_rcm=use_rcm) as P:
+        assert np.array_equal(P.perm(), pl_o.p), "RCM permutation differs"
+        g, ng = P.groups()
+        assert ng == pl_o.ngroups
+        assert np.array_equal(g, pl_o.group), "group assignment differs"
+        st = P.stats()
+        assert st["conflicts"] == pl_o.cidx.size
+        x, info = P.solve(maxit=K, tol=0.0)
+    xo = oracle.solve(pl_o, K)
+    den = max(np.linalg.norm(xo), 1e-300)
+    rel = np.linalg.norm(x - xo) / den
+    _say(f"[parity] {name}: groups={ng} relerr={rel:.3e} maxabs={np.abs(x - xo).max():.3e} "
+         f"bitwise={np.array_equal(x, xo)} relres={info.relres:.3e}")
+    assert info.sweeps == K and info.status == "maxit"
+    assert rel <= TOL_X
+
+
+def test_full_size_stencil_parity():
+    """The 1024x1024 stencil (1,048,576 rows) at its full size: bit-exact plan,
+    x after 3 sweeps within 1e-10."""
+    s = synth.c2()
+    _say(f"[parity] c2 full: n={s.n} nnz={s.nnz}")
+    pl_o = oracle.plan_system(s, 0.1)
+    with obk.plan_system(s, 0.1) as P:
+        assert np.array_equal(P.perm(), pl_o.p)
+        g, ng = P.groups()
+        assert ng == pl_o.ngroups and np.array_equal(g, pl_o.group)
+        assert P.stats()["bandwidth"] == 1024
+        x, _ = P.solve(maxit=3)
+    xo = oracle.solve(pl_o, 3)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"[parity] c2 full: relerr={rel:.3e} bitwise={np.array_equal(x, xo)}")
+    assert rel <= TOL_X
+
+
+def test_device_inputs_and_resume():
+    """Device-resident inputs give the same plan and iterate as host inputs;
+    K1 then K2 sweeps (resuming from x0) equal K1 + K2 sweeps."""
+    import torch
+    s = synth.c1(n=1500)
+    _say("[parity] device inputs")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with obk.plan(d(s.row_ptr), d(s.col), d(s.val), d(s.f), 0.1) as Pd, obk.plan_system(s, 0.1) as Ph:
+        assert np.array_equal(Pd.perm(), Ph.perm())
+        assert np.array_equal(Pd.groups()[0], Ph.groups()[0])
+        xd, _ = Pd.solve(maxit=30)
+        xh, _ = Ph.solve(maxit=30)
+        assert np.array_equal(xd.cpu().numpy(), xh)
+        x10, _ = Ph.solve(maxit=10)
+        x30, _ = Ph.solve(x0=x10, maxit=20)
+        assert np.array_equal(x30, xh)
+
+
+def test_run_twice_bitwise():
+    s = synth.c2(grid=128)
+    _say("[parity] determinism")
+    with obk.plan_system(s, 0.1) as P:
+        a, _ = P.solve(maxit=50)
+        b, _ = P.solve(maxit=50)
+    assert np.array_equal(a, b)
+
+
+def test_converges_with_tolerance():
+    """tol > 0: stops at relative residual <= tol (Theorem 1 convergence)."""
+    s = synth.c1(companion=True)
+    _say("[parity] tol stop")
+    with obk.plan_system(s, 0.1) as P:
+        x, info = P.solve(maxit=500, tol=1e-10)
+    assert info.status == "converged" and info.relres <= 1e-10
+    assert info.sweeps < 500
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) < 1e-8
+    r = s.f - s.scipy() @ x
+    assert abs(np.linalg.norm(r) / np.linalg.norm(s.f) - info.relres) <= 1e-3 * info.relres + 1e-15
+
+
+@pytest.mark.parametrize("kind,code", [("col_out_of_range", -2), ("duplicate", -2), ("nan", -4),
+                                       ("bad_rowptr", -2), ("budget", -5), ("inconsistent", -8)])
+def test_plan_errors(kind, code):
+    s = synth.c1(n=50)
+    rp, ci, v, f = s.row_ptr.copy(), s.col.copy(), s.val.copy(), s.f.copy()
+    kw = {}
+    if kind == "col_out_of_range":
+        ci[5] = 50
+    elif kind == "duplicate":
+        ci[1] = ci[0]
+    elif kind == "nan":
+        v[3] = np.nan
+    elif kind == "bad_rowptr":
+        rp[10] = rp[11] + 1
+    elif kind == "budget":
+        kw["hbm_budget"] = 1000
+    elif kind == "inconsistent":
+        ci = np.delete(ci, np.arange(rp[4], rp[5]))
+        v = np.delete(v, np.arange(rp[4], rp[5]))
+        rp[5:] -= rp[5] - rp[4]
+        f[4] = 1.0
+        kw["reject_inconsistent"] = True
+    _say(f"[errors] {kind}")
+    with pytest.raises(obk.ObkError) as ei:
+        obk.plan(rp, ci, v, f, 0.1, **kw)
+    assert ei.value.code == code
+
+
+def test_empty_system():
+    s = synth.from_scipy(sp.csr_matrix((0, 0)))
+    with obk.plan_system(s, 0.1) as P:
+        x, info = P.solve(maxit=3)
+    assert x.size == 0
