@@ -66,16 +66,27 @@ __global__ void k_offdiag_emit(int64_t nnz, const int32_t* __restrict__ row, con
 __global__ void k_unique_flag(int64_t m, const uint32_t* __restrict__ ra, const uint32_t* __restrict__ cb,
                               int64_t* __restrict__ flag) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) flag[k] = (k == 0 || ra[k] != ra[k - 1] || cb[k] != cb[k - 1]) ? 1 : 0;
+    if (k >= m) return;
+    const int64_t kp = k > 0 ? k - 1 : 0;
+    const uint32_t r = ra[k], c = cb[k], rp = ra[kp], cp = cb[kp];
+    flag[k] = ((k == 0) | (r != rp) | (c != cp)) ? 1 : 0;
 }
 
+// Written without short-circuit branches around loads: every load is issued
+// unconditionally at an in-range index and the condition is combined with
+// bitwise operators (the HIP compiler of ROCm 7.2 miscompiles some
+// short-circuit forms; see the design notes).
 __global__ void k_unique_emit(int64_t m, const uint32_t* __restrict__ ra, const uint32_t* __restrict__ cb,
                               const int64_t* __restrict__ pos, int32_t* __restrict__ adj, int32_t* __restrict__ deg) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
-    if (k == 0 || ra[k] != ra[k - 1] || cb[k] != cb[k - 1]) {
-        adj[pos[k]] = (int32_t)cb[k];
-        atomicAdd(&deg[ra[k]], 1);
+    const int64_t kp = k > 0 ? k - 1 : 0;
+    const uint32_t r = ra[k], c = cb[k], rp = ra[kp], cp = cb[kp];
+    const int64_t p = pos[k];
+    const bool head = (k == 0) | (r != rp) | (c != cp);
+    if (head) {
+        adj[p] = (int32_t)c;
+        atomicAdd(&deg[r], 1);
     }
 }
 
@@ -134,7 +145,10 @@ __global__ void k_perm_finish(int64_t nnz, const uint32_t* __restrict__ order, c
 __global__ void k_dup_check(int64_t nnz, const int32_t* __restrict__ trow, const int32_t* __restrict__ tci,
                             int* flags) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > 0 && k < nnz && trow[k] == trow[k - 1] && tci[k] == tci[k - 1]) atomicOr(flags, DUPLICATE);
+    if (k >= nnz) return;
+    const int64_t kp = k > 0 ? k - 1 : 0;
+    const int32_t r = trow[k], c = tci[k], rp = trow[kp], cp = tci[kp];
+    if ((k > 0) & (r == rp) & (c == cp)) atomicOr(flags, DUPLICATE);
 }
 
 // --------------------------------------------------------------- norms
@@ -178,36 +192,36 @@ __global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const 
     const int32_t i = trow[e];
     const int32_t c = tci[e];
     const double nui = nu[i];
+    const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+    const int64_t s0 = cptr[c], s1 = cptr[c + 1];
+    // rows of column c are ascending: those below i are a prefix
+    int64_t s_end = s0;
+    for (int64_t s = s0; s < s1; s++) s_end += (crow[s] < i) ? 1 : 0;
+    if (nui == 0.0) s_end = s0;
     int64_t found = 0;
-    int64_t wpos = kFill ? out_pos[e] : 0;
-    if (nui != 0.0) {
-        const int64_t ia0 = trp[i], ia1 = trp[i + 1];
-        for (int64_t s = cptr[c]; s < cptr[c + 1]; s++) {
-            const int32_t j = crow[s];
-            if (j >= i) break;                  // rows ascending within the column
-            const double nuj = nu[j];
-            if (nuj == 0.0) continue;
-            int64_t a = ia0, b = trp[j];
-            const int64_t b1 = trp[j + 1];
-            int32_t first = -1;
-            double d = 0.0;
-            while (a < ia1 && b < b1) {
-                const int32_t ca = tci[a], cb = tci[b];
-                if (ca < cb) a++;
-                else if (ca > cb) b++;
-                else {
-                    if (first < 0) first = ca;
-                    d = d + tv[a] * tv[b];
-                    a++; b++;
-                }
-            }
-            if (first != c) continue;
-            const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
-            if (cs >= delta) {
-                if (kFill) out_idx[wpos++] = j;
-                found++;
-            }
+    int64_t wpos = 0;
+    if (kFill) wpos = out_pos[e];
+    for (int64_t s = s0; s < s_end; s++) {
+        const int32_t j = crow[s];
+        const double nuj = nu[j];
+        int64_t a = ia0, b = trp[j];
+        const int64_t b1 = trp[j + 1];
+        int32_t first = -1;
+        double d = 0.0;
+        while ((a < ia1) & (b < b1)) {
+            const int32_t ca = tci[a], cb = tci[b];
+            const double va = tv[a], vb = tv[b];
+            const bool eq = (ca == cb);
+            if (eq) d = d + va * vb;
+            first = (eq & (first < 0)) ? ca : first;
+            a += (ca <= cb) ? 1 : 0;
+            b += (cb <= ca) ? 1 : 0;
         }
+        const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
+        const bool conflict = (first == c) & (nuj != 0.0) & (cs >= delta);
+        if (kFill && conflict) out_idx[wpos] = j;
+        wpos += conflict ? 1 : 0;
+        found += conflict ? 1 : 0;
     }
     if (!kFill) count[e] = found;
 }
@@ -266,7 +280,10 @@ __global__ void k_seg_flag(int64_t me, const uint32_t* __restrict__ gkey, const 
                            const int32_t* __restrict__ ccol, int64_t* __restrict__ flag) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= me) return;
-    flag[k] = (k == 0 || gkey[k] != gkey[k - 1] || ccol[cidx[k]] != ccol[cidx[k - 1]]) ? 1 : 0;
+    const int64_t kp = k > 0 ? k - 1 : 0;
+    const uint32_t g = gkey[k], gp = gkey[kp];
+    const int32_t c = ccol[cidx[k]], cp = ccol[cidx[kp]];
+    flag[k] = ((k == 0) | (g != gp) | (c != cp)) ? 1 : 0;
 }
 
 __global__ void k_seg_emit(int64_t me, const uint32_t* __restrict__ gkey, const uint32_t* __restrict__ cidx,
@@ -277,16 +294,21 @@ __global__ void k_seg_emit(int64_t me, const uint32_t* __restrict__ gkey, const 
                            int64_t* __restrict__ segs_per_group) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= me) return;
-    uint32_t e = cidx[k];
-    bool head = (k == 0 || gkey[k] != gkey[k - 1] || ccol[e] != ccol[cidx[k - 1]]);
+    const int64_t kp = k > 0 ? k - 1 : 0;
+    const uint32_t e = cidx[k], ep = cidx[kp];
+    const uint32_t g = gkey[k], gp = gkey[kp];
+    const int32_t c = ccol[e], cp = ccol[ep];
+    const int64_t sidx = segpos[k];
+    const int32_t row_pos = pos_of_row[crow[e]];
+    const double val = cval[e];
+    const bool head = (k == 0) | (g != gp) | (c != cp);
     if (head) {
-        int64_t s = segpos[k];
-        tcol[s] = ccol[e];
-        sptr[s] = k;
-        atomicAdd((unsigned long long*)&segs_per_group[gkey[k]], 1ull);
+        tcol[sidx] = c;
+        sptr[sidx] = k;
+        atomicAdd((unsigned long long*)&segs_per_group[g], 1ull);
     }
-    srow[k] = pos_of_row[crow[e]];
-    sval[k] = cval[e];
+    srow[k] = row_pos;
+    sval[k] = val;
 }
 
 __global__ void k_gather_f64(int64_t m, const uint32_t* __restrict__ idx, const double* __restrict__ src,
@@ -461,19 +483,21 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     DevArray<int32_t> crow; crow.alloc(nnz);
     DevArray<double> cval; cval.alloc(nnz);
     DevArray<uint32_t> order; order.alloc(nnz);
+    int64_t csc_total = 0;
     {
         DevArray<uint32_t> ckey; ckey.alloc(nnz);
         OBK_HIP(hipMemcpyAsync(ckey.get(), tci.get(), nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         std::vector<uint32_t> iota(nnz);
         for (int64_t k = 0; k < nnz; k++) iota[k] = (uint32_t)k;
-        OBK_HIP(hipMemcpyAsync(order.get(), iota.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        if (nnz) OBK_HIP(hipMemcpyAsync(order.get(), iota.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         OBK_HIP(hipStreamSynchronize(s));
         radix_sort_pairs(ckey.get(), order.get(), nnz, nbits, s);
         OBK_HIP(hipMemsetAsync(cptr.get(), 0, (n + 1) * sizeof(int64_t), s));
         k_hist_i32<<<nblk(nnz), kT, 0, s>>>(nnz, ckey.get(), cptr.get());
         OBK_HIP(hipGetLastError());
-        int64_t t2 = scan_exclusive_i64(cptr.get(), cptr.get(), n, s);
-        OBK_HIP(hipMemcpyAsync(cptr.get() + n, &t2, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        csc_total = scan_exclusive_i64(cptr.get(), cptr.get(), n, s);
+        OBK_HIP(hipMemcpyAsync(cptr.get() + n, &csc_total, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        OBK_HIP(hipStreamSynchronize(s));
         k_csc_fill<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), trow.get(), crow.get());
         OBK_HIP(hipGetLastError());
         k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());

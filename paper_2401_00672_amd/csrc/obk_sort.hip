@@ -120,18 +120,21 @@ __global__ void k_digit_scatter(const uint32_t* __restrict__ keys_in, const uint
                                 int shift, int64_t nblocks, const int64_t* __restrict__ offsets) {
     __shared__ uint64_t lw[kSortThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    // loads are unconditional at clamped in-range indices (predicated form)
     uint32_t k[kSortItems];
+    uint32_t v[kSortItems];
     int dig[kSortItems];
     uint64_t packed[kBins / 4] = {0, 0, 0, 0};
     for (int j = 0; j < kSortItems; j++) {
-        int64_t i = base + j;
-        if (i < n) {
-            k[j] = keys_in[i];
-            dig[j] = (k[j] >> shift) & (kBins - 1);
-            packed[dig[j] >> 2] += (uint64_t)1 << (16 * (dig[j] & 3));
-        } else {
-            dig[j] = -1;
-        }
+        const int64_t i = base + j;
+        const int64_t ic = i < n ? i : n - 1;
+        k[j] = keys_in[ic];
+        v[j] = vals_in ? vals_in[ic] : 0u;
+        const int d = (int)((k[j] >> shift) & (kBins - 1));
+        dig[j] = i < n ? d : -1;
+        const uint64_t one = i < n ? 1ull : 0ull;
+        for (int q = 0; q < kBins / 4; q++)
+            packed[q] += (q == (d >> 2)) ? (one << (16 * (d & 3))) : 0ull;
     }
     uint64_t excl[kBins / 4];
     for (int q = 0; q < kBins / 4; q++) {
@@ -139,16 +142,20 @@ __global__ void k_digit_scatter(const uint32_t* __restrict__ keys_in, const uint
         uint64_t incl = block_inclusive_scan<uint64_t>(packed[q], lw, &tot);
         excl[q] = incl - packed[q];
     }
-    int run[kBins];
-    for (int d = 0; d < kBins; d++)
-        run[d] = (int)((excl[d >> 2] >> (16 * (d & 3))) & 0xFFFF);
     for (int j = 0; j < kSortItems; j++) {
-        if (dig[j] < 0) continue;
-        int d = dig[j];
-        int64_t pos = offsets[(int64_t)d * nblocks + blockIdx.x] + run[d];
-        run[d]++;
-        keys_out[pos] = k[j];
-        if (vals_in) vals_out[pos] = vals_in[base + j];
+        const int d = dig[j];
+        const int dd = d < 0 ? 0 : d;
+        // running count of digit dd among this thread's earlier items
+        int before = 0;
+        for (int t = 0; t < j; t++) before += (dig[t] == dd) ? 1 : 0;
+        uint64_t ex = 0;
+        for (int q = 0; q < kBins / 4; q++) ex = (q == (dd >> 2)) ? excl[q] : ex;
+        const int64_t pos = offsets[(int64_t)dd * nblocks + blockIdx.x] +
+                            (int64_t)((ex >> (16 * (dd & 3))) & 0xFFFF) + before;
+        if (d >= 0) {
+            keys_out[pos] = k[j];
+            if (vals_in) vals_out[pos] = v[j];
+        }
     }
 }
 

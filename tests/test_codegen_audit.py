@@ -1,0 +1,43 @@
+"""Guard against a code-generation hazard of the ROCm 7.2 HIP compiler.
+
+The control-flow structurizer of this toolchain turned a kernel with a
+short-circuit condition over loads (`k == 0 || a[k] != a[k-1] || ...`) into
+IR where a PHI takes `poison` on a path that still uses the value; the
+register allocator then reused that register and lanes at a group boundary
+computed a wild address.  The kernels are written in predicated form
+(unconditional loads at clamped in-range indices, conditions combined with
+bitwise operators).  This test compiles every HIP source for gfx950 and
+fails if any PHI with a poison/undef input survives structurization.
+"""
+import glob
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2401_00672_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+SOURCES = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
+@pytest.mark.parametrize("src", SOURCES, ids=[os.path.basename(s) for s in SOURCES])
+def test_no_poison_phi_after_structurization(src, tmp_path):
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+           "-I", os.path.join(ROOT, "include"), "--cuda-device-only", "-S", "-o", str(tmp_path / "out.s"), src,
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-print-after=amdgpu-annotate-uniform"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    bad = []
+    for dump in r.stderr.split("*** IR Dump After")[1:]:
+        m = re.search(r"define [^@]*@(\S+)\(", dump)
+        fn = m.group(1) if m else "?"
+        for line in dump.splitlines():
+            if re.search(r"= phi .*\b(poison|undef)\b", line):
+                bad.append(f"{fn}: {line.strip()}")
+    assert not bad, "structurized IR with poison PHI inputs:\n" + "\n".join(bad[:20])
