@@ -15,12 +15,15 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
 void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                 hipStream_t s);
 void enqueue_sweeps(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
+                   hipStream_t s);
 }  // namespace obk
 
 size_t obk_plan_s::device_bytes() const {
     return perm.bytes() + rptr.bytes() + rcol.bytes() + rval.bytes() + rf.bytes() + rinv.bytes() +
            tcol.bytes() + sptr.bytes() + srow.bytes() + sval.bytes() + rtiles.bytes() + stiles.bytes() +
-           x.bytes() + w.bytes() + red.bytes();
+           x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
+           b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes();
 }
 
 namespace {
@@ -107,8 +110,10 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
         if (maxit < 0 || std::isnan(tol)) obk::fail(OBK_E_ARG, "maxit must be >= 0 and tol a number");
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
-        if (plan->opts.precision != OBK_FP64) obk::fail(OBK_E_ARG, "precision not available");
-        obk::solve_fp64(*plan, x0, tol, maxit, x, info, as_hip(stream));
+        if (plan->opts.precision == OBK_FP32_IR)
+            obk::solve_fp32_ir(*plan, x0, tol, maxit, x, info, as_hip(stream));
+        else
+            obk::solve_fp64(*plan, x0, tol, maxit, x, info, as_hip(stream));
     });
 }
 

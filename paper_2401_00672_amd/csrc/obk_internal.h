@@ -135,6 +135,17 @@ struct obk_plan_s {
     obk::DevArray<double> red;         // reduction scratch
     double fnorm2 = 0;                 // ||f~||^2
     double zero_rows_f2 = 0;           // sum of f_i^2 over all-zero rows
+    double zero_rows_fmax = 0;         // max |f_i| over all-zero rows
+
+    // FP32 copies and workspace for iterative refinement (precision OBK_FP32_IR)
+    obk::DevArray<float> rval32;       // [nnz]
+    obk::DevArray<float> rinv32;       // [m]
+    obk::DevArray<float> sval32;       // [nnz]
+    obk::DevArray<float> b32;          // scaled residual, group-major [m]
+    obk::DevArray<float> d32;          // correction, reordered [n]
+    obk::DevArray<float> w32;          // group weights [m]
+    obk::DevArray<double> r64;         // FP64 residual, group-major [m]
 
     size_t device_bytes() const;
+    bool has_fp32() const { return opts.precision == OBK_FP32_IR; }
 };

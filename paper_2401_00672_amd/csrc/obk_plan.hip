@@ -332,6 +332,11 @@ __global__ void k_sumsq_rows(int64_t n, const double* __restrict__ f, const doub
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+__global__ void k_to_f32(int64_t m, const double* __restrict__ src, float* __restrict__ dst) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) dst[k] = (float)src[k];
+}
+
 template <class T> void to_device(DevArray<T>& d, const T* h, size_t n, hipStream_t s) {
     d.alloc(n);
     if (n) OBK_HIP(hipMemcpyAsync(d.get(), h, n * sizeof(T), hipMemcpyHostToDevice, s));
@@ -475,6 +480,12 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     OBK_HIP(hipGetLastError());
     P.fnorm2 = sum_squares(tf.get(), nu.get(), n, false, s);
     P.zero_rows_f2 = sum_squares(tf.get(), nu.get(), n, true, s);
+    {
+        std::vector<double> hf = to_host(tf.get(), n, s), hn = to_host(nu.get(), n, s);
+        double mx = 0.0;
+        for (int64_t i = 0; i < n; i++) if (hn[i] == 0.0) mx = std::max(mx, std::fabs(hf[i]));
+        P.zero_rows_fmax = mx;
+    }
     if (P.opts.reject_inconsistent && P.zero_rows_f2 != 0.0)
         fail(OBK_E_INCONSISTENT, "an all-zero row has a nonzero right-hand side");
 
@@ -607,6 +618,16 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     }
     to_device(P.rtiles, P.h_rtiles.data(), P.h_rtiles.size(), s);
     to_device(P.stiles, P.h_stiles.data(), P.h_stiles.size(), s);
+
+    // ---- FP32 copies for the refinement mode
+    if (P.has_fp32()) {
+        P.rval32.alloc(nnz_act); P.rinv32.alloc(m); P.sval32.alloc(me);
+        k_to_f32<<<nblk(nnz_act), kT, 0, s>>>(nnz_act, P.rval.get(), P.rval32.get());
+        k_to_f32<<<nblk(m), kT, 0, s>>>(m, P.rinv.get(), P.rinv32.get());
+        k_to_f32<<<nblk(me), kT, 0, s>>>(me, P.sval.get(), P.sval32.get());
+        OBK_HIP(hipGetLastError());
+        P.b32.alloc(m); P.d32.alloc(n); P.w32.alloc(m); P.r64.alloc(m);
+    }
 
     // ---- workspace
     P.x.alloc(n);

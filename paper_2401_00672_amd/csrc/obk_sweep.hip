@@ -24,60 +24,58 @@ namespace {
 constexpr int kT = kTileThreads;
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-// Phase R over the tiles of one group.
+// Phase R over the tiles of one group (T = double, or float in the inner
+// sweeps of iterative refinement).
+template <class T>
 __global__ __launch_bounds__(kT) void k_phase_r(const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr,
-                                                const int32_t* __restrict__ rcol, const double* __restrict__ rval,
-                                                const double* __restrict__ rf, const double* __restrict__ rinv,
-                                                const double* __restrict__ x, double* __restrict__ w) {
-    __shared__ double prod[kTileEntries];
+                                                const int32_t* __restrict__ rcol, const T* __restrict__ rval,
+                                                const T* __restrict__ rf, const T* __restrict__ rinv,
+                                                const T* __restrict__ x, T* __restrict__ w) {
+    __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
     const int nseg = t.seg_end - t.seg_begin;
     const int me = threadIdx.x;
-    int64_t k0 = 0, k1 = 0;
-    if (me < nseg) { k0 = rptr[t.seg_begin + me]; k1 = rptr[t.seg_begin + me + 1]; }
-    double acc = 0.0;
+    const bool owner = me < nseg;
+    const int64_t a = t.seg_begin + (owner ? me : 0);
+    const int64_t k0 = rptr[a], k1 = rptr[a + 1];
+    T acc = T(0);
     for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
         const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
         for (int q = me; q < len; q += kT) prod[q] = rval[base + q] * x[rcol[base + q]];
         __syncthreads();
-        if (me < nseg) {
-            const int64_t lo = max(k0, base), hi = min(k1, base + len);
-            for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
-        }
+        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
+        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
         __syncthreads();
     }
-    if (me < nseg) {
-        const int64_t a = t.seg_begin + me;
-        w[a] = (rf[a] - acc) * rinv[a];
-    }
+    const T fa = rf[a], ia = rinv[a];
+    if (owner) w[a] = (fa - acc) * ia;
 }
 
 // Phase S over the tiles of one group's touched columns.
+template <class T>
 __global__ __launch_bounds__(kT) void k_phase_s(const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr,
-                                                const int32_t* __restrict__ srow, const double* __restrict__ sval,
-                                                const int32_t* __restrict__ tcol, const double* __restrict__ w,
-                                                double* __restrict__ x) {
-    __shared__ double prod[kTileEntries];
+                                                const int32_t* __restrict__ srow, const T* __restrict__ sval,
+                                                const int32_t* __restrict__ tcol, const T* __restrict__ w,
+                                                T* __restrict__ x) {
+    __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
     const int nseg = t.seg_end - t.seg_begin;
     const int me = threadIdx.x;
-    int64_t k0 = 0, k1 = 0;
-    if (me < nseg) { k0 = sptr[t.seg_begin + me]; k1 = sptr[t.seg_begin + me + 1]; }
-    double acc = 0.0;
+    const bool owner = me < nseg;
+    const int64_t sg = t.seg_begin + (owner ? me : 0);
+    const int64_t k0 = sptr[sg], k1 = sptr[sg + 1];
+    T acc = T(0);
     for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
         const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
         for (int q = me; q < len; q += kT) prod[q] = w[srow[base + q]] * sval[base + q];
         __syncthreads();
-        if (me < nseg) {
-            const int64_t lo = max(k0, base), hi = min(k1, base + len);
-            for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
-        }
+        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
+        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
         __syncthreads();
     }
-    if (me < nseg) {
-        const int32_t c = tcol[t.seg_begin + me];
-        x[c] = x[c] + acc;
-    }
+    const int32_t c = tcol[sg];
+    const T xc = x[c];
+    if (owner) x[c] = xc + acc;
 }
 
 // r_a = f_a - a_a . x over the group-major rows; per-block sums of r_a^2
@@ -130,23 +128,95 @@ __global__ void k_permute_out(int64_t n, const int32_t* __restrict__ p, const do
     if (t < n) x[p[t]] = xt[t];
 }
 
+// FP64 residual of the refinement loop, kept per row: r_a = f_a - a_a . x;
+// per-block sums of r_a^2 and maxima of |r_a|
+__global__ __launch_bounds__(256) void k_resid_keep(int64_t m, const int64_t* __restrict__ rptr,
+                                                    const int32_t* __restrict__ rcol, const double* __restrict__ rval,
+                                                    const double* __restrict__ rf, const double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ psum,
+                                                    double* __restrict__ pmax, int* __restrict__ nonfinite) {
+    __shared__ double red[256];
+    __shared__ double mx[256];
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double r2 = 0.0, ra = 0.0;
+    if (a < m) {
+        double s = 0.0;
+        for (int64_t k = rptr[a]; k < rptr[a + 1]; k++) s = s + rval[k] * x[rcol[k]];
+        const double ri = rf[a] - s;
+        r[a] = ri;
+        if (!isfinite(ri)) atomicOr(nonfinite, 1);
+        r2 = ri * ri;
+        ra = fabs(ri);
+    }
+    red[threadIdx.x] = r2;
+    mx[threadIdx.x] = ra;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { psum[blockIdx.x] = red[0]; pmax[blockIdx.x] = mx[0]; }
+}
+
+__global__ void k_sum_max_partials(int64_t np, const double* __restrict__ psum, const double* __restrict__ pmax,
+                                   double* __restrict__ out) {
+    __shared__ double red[256];
+    __shared__ double mx[256];
+    double s = 0.0, m = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += 256) { s = s + psum[i]; m = fmax(m, pmax[i]); }
+    red[threadIdx.x] = s;
+    mx[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = red[0]; out[1] = mx[0]; }
+}
+
+// right-hand side of the correction system, b = (float)(r / sigma), and d = 0
+__global__ void k_make_rhs(int64_t m, int64_t n, const double* __restrict__ r, double sigma,
+                           float* __restrict__ b, float* __restrict__ d) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) b[i] = (float)(r[i] / sigma);
+    if (i < n) d[i] = 0.0f;
+}
+
+// x += sigma * d (FP64)
+__global__ void k_update_x(int64_t n, double sigma, const float* __restrict__ d, double* __restrict__ x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] + sigma * (double)d[i];
+}
+
 }  // namespace
 
-// enqueue `sweeps` sweeps on x (device, reordered coordinates)
-void enqueue_sweeps(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
+template <class T>
+static void enqueue_sweeps_t(const obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval,
+                             T* x, T* w, int64_t sweeps, hipStream_t s) {
     for (int64_t it = 0; it < sweeps; it++) {
         for (int32_t g = 0; g < P.ngroups; g++) {
             const int32_t r0 = P.h_rtile_ptr[g], r1 = P.h_rtile_ptr[g + 1];
             const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
             if (r1 > r0)
-                k_phase_r<<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, P.rptr.get(), P.rcol.get(), P.rval.get(),
-                                                  P.rf.get(), P.rinv.get(), x, P.w.get());
+                k_phase_r<T><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, P.rptr.get(), P.rcol.get(), rval, rf,
+                                                     rinv, x, w);
             if (s1 > s0)
-                k_phase_s<<<s1 - s0, kT, 0, s>>>(P.stiles.get() + s0, P.sptr.get(), P.srow.get(), P.sval.get(),
-                                                  P.tcol.get(), P.w.get(), x);
+                k_phase_s<T><<<s1 - s0, kT, 0, s>>>(P.stiles.get() + s0, P.sptr.get(), P.srow.get(), sval,
+                                                     P.tcol.get(), w, x);
         }
     }
     OBK_HIP(hipGetLastError());
+}
+
+// enqueue `sweeps` sweeps on x (device, reordered coordinates)
+void enqueue_sweeps(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
+    enqueue_sweeps_t<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), x, P.w.get(), sweeps, s);
 }
 
 // relative residual ||f~ - A~ x|| / ||f~|| (synchronises the stream); sets *nonfinite
@@ -213,6 +283,82 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
     if (tol <= 0) inf.relres = relres(P, P.x.get(), s, &nf);
     inf.sweeps = done;
     // x = P^T x~ (Algorithm 4, last step)
+    double* xout = x;
+    if (!dev) { xd.alloc(n); xout = xd.get(); }
+    k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), P.x.get(), xout);
+    OBK_HIP(hipGetLastError());
+    if (!dev) OBK_HIP(hipMemcpyAsync(x, xd.get(), n * sizeof(double), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+}
+
+// Iterative refinement with FP32 inner sweeps (residual, norms, scale and
+// update in FP64): r = f - A x; sigma = max |r_i|; `inner_sweeps` FP32
+// sweeps on A d = r / sigma from d = 0; x += sigma d.  Stops when
+// ||r|| / ||f|| <= tol or after maxit refinement steps.
+void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
+                   hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = P.n, m = P.m;
+    const bool dev = P.input_on_device;
+    obk_info inf{};
+    DevArray<double> x0d, xd;
+    const double* x0dev = nullptr;
+    if (x0) {
+        if (dev) x0dev = x0;
+        else {
+            x0d.alloc(n);
+            OBK_HIP(hipMemcpyAsync(x0d.get(), x0, n * sizeof(double), hipMemcpyHostToDevice, s));
+            x0dev = x0d.get();
+        }
+    }
+    k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), x0dev, P.x.get());
+    OBK_HIP(hipGetLastError());
+    const unsigned nb = nblk(m);
+    double* psum = P.red.get();
+    DevArray<double> pmax; pmax.alloc(nb + 4);
+    int* flag = reinterpret_cast<int*>(psum + nb + 8);
+    auto residual = [&](double* rho, double* sigma, bool* nonfinite) {
+        OBK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+        k_resid_keep<<<nb, 256, 0, s>>>(m, P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(),
+                                        P.r64.get(), psum, pmax.get(), flag);
+        k_sum_max_partials<<<1, 256, 0, s>>>(nb, psum, pmax.get(), pmax.get() + nb);
+        OBK_HIP(hipGetLastError());
+        double out[2] = {0, 0};
+        int nf = 0;
+        OBK_HIP(hipMemcpyAsync(out, pmax.get() + nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipMemcpyAsync(&nf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipStreamSynchronize(s));
+        const double r2 = out[0] + P.zero_rows_f2;
+        *sigma = std::max(out[1], P.zero_rows_fmax);
+        *nonfinite = nf != 0 || !std::isfinite(r2);
+        *rho = (P.fnorm2 == 0.0) ? (r2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(r2) / std::sqrt(P.fnorm2);
+    };
+    double rho = 0, sigma = 0;
+    bool nf = false;
+    residual(&rho, &sigma, &nf);
+    inf.relres0 = rho;
+    inf.relres = rho;
+    inf.status = OBK_MAXIT;
+    if (nf) inf.status = OBK_NONFINITE_ITERATE;
+    else if (tol > 0 && rho <= tol) inf.status = OBK_CONVERGED;
+    const int inner = std::max(1, P.opts.inner_sweeps);
+    while (inf.status == OBK_MAXIT && inf.outer_steps < maxit && sigma > 0.0) {
+        k_make_rhs<<<nblk(std::max(m, n)), 256, 0, s>>>(m, n, P.r64.get(), sigma, P.b32.get(), P.d32.get());
+        enqueue_sweeps_t<float>(P, P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sval32.get(), P.d32.get(),
+                                P.w32.get(), inner, s);
+        k_update_x<<<nblk(n), 256, 0, s>>>(n, sigma, P.d32.get(), P.x.get());
+        OBK_HIP(hipGetLastError());
+        inf.outer_steps++;
+        inf.sweeps += inner;
+        residual(&rho, &sigma, &nf);
+        inf.relres = rho;
+        if (nf) inf.status = OBK_NONFINITE_ITERATE;
+        else if (tol > 0 && rho <= tol) inf.status = OBK_CONVERGED;
+        else if (rho > 1e3 * inf.relres0 && inf.relres0 > 0) inf.status = OBK_DIVERGED;
+    }
+    if (inf.status == OBK_MAXIT && sigma == 0.0) inf.status = OBK_CONVERGED;
     double* xout = x;
     if (!dev) { xd.alloc(n); xout = xd.get(); }
     k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), P.x.get(), xout);
