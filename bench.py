@@ -67,13 +67,12 @@ def bench_stencil(args) -> dict:
     m = int((g >= 0).sum())
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(max(args.warmup, 0)):
-        P.sweep_device(x, 1)
+    if args.warmup > 0:
+        P.sweep_device(x, args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
-        P.sweep_device(x, 1)
+    P.sweep_device(x, args.steps)          # the K timed sweeps, replayed from captured graphs
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
@@ -107,6 +106,21 @@ def bench_stencil(args) -> dict:
     return res
 
 
+def copy_calibration(mib: int = 256, reps: int = 5) -> dict:
+    """A plain device copy of known size, for scaling the HBM byte counters
+    (FETCH_SIZE / WRITE_SIZE) that a profiler reports per dispatch."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"calibration": "copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+            "kib_per_copy": n * 8 / 1024, "reps": reps}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +130,12 @@ def main() -> int:
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design note, not a measured path.", file=sys.stderr)

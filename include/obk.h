@@ -158,7 +158,10 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  * Sweeps on a plan with device-resident iterates, no host synchronisation and
  * no residual (the form a benchmark or a batched driver times): x~ (device,
  * reordered coordinates, n entries) is updated in place by `sweeps` sweeps.
- * Enqueued on stream; returns without waiting.
+ * Enqueued on stream; returns without waiting.  The sweeps are replayed from
+ * graphs captured on first use for this x~ pointer (the plan keeps them until
+ * obk_free).  Sweeps on one plan share its workspace: calls on the same plan
+ * must be ordered (one stream, or explicit synchronisation).
  */
 OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_t sweeps,
                             obk_stream_t stream);

@@ -14,7 +14,7 @@ const char* last_error_cstr();
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s);
 void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                 hipStream_t s);
-void enqueue_sweeps(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                    hipStream_t s);
 }  // namespace obk

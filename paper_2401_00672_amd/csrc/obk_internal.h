@@ -146,6 +146,22 @@ struct obk_plan_s {
     obk::DevArray<float> w32;          // group weights [m]
     obk::DevArray<double> r64;         // FP64 residual, group-major [m]
 
+    // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
+    // count and element size; replayed on the caller's stream
+    struct SweepGraph {
+        const void* x = nullptr;
+        int64_t sweeps = 0;
+        int elem = 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<SweepGraph> graphs;
+    hipStream_t capture_stream = nullptr;
+
+    obk_plan_s() = default;
+    obk_plan_s(const obk_plan_s&) = delete;
+    obk_plan_s& operator=(const obk_plan_s&) = delete;
+    ~obk_plan_s();
     size_t device_bytes() const;
     bool has_fp32() const { return opts.precision == OBK_FP32_IR; }
 };

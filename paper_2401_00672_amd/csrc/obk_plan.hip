@@ -291,7 +291,7 @@ __global__ void k_seg_emit(int64_t me, const uint32_t* __restrict__ gkey, const 
                            const double* __restrict__ cval, const int32_t* __restrict__ pos_of_row,
                            const int64_t* __restrict__ segpos, int32_t* __restrict__ tcol,
                            int64_t* __restrict__ sptr, int32_t* __restrict__ srow, double* __restrict__ sval,
-                           int64_t* __restrict__ segs_per_group) {
+                           int64_t* __restrict__ group_first_seg) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= me) return;
     const int64_t kp = k > 0 ? k - 1 : 0;
@@ -305,8 +305,9 @@ __global__ void k_seg_emit(int64_t me, const uint32_t* __restrict__ gkey, const 
     if (head) {
         tcol[sidx] = c;
         sptr[sidx] = k;
-        atomicAdd((unsigned long long*)&segs_per_group[g], 1ull);
     }
+    // the first entry of a group opens the group's first segment (one writer per group)
+    if ((k == 0) | (g != gp)) group_first_seg[g] = sidx;
     srow[k] = row_pos;
     sval[k] = val;
 }
@@ -595,15 +596,19 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     int64_t T = scan_exclusive_i64(segflag.get(), segflag.get(), me, s);
     P.tcol.alloc(T); P.sptr.alloc(T + 1); P.srow.alloc(me); P.sval.alloc(me);
     DevArray<int64_t> segs_g; segs_g.alloc(std::max(G, 1));
-    OBK_HIP(hipMemsetAsync(segs_g.get(), 0, std::max(G, 1) * sizeof(int64_t), s));
     k_seg_emit<<<nblk(me), kT, 0, s>>>(me, gkey.get(), gidx.get(), ccol.get(), crow.get(), cval.get(), dpos.get(),
                                         segflag.get(), P.tcol.get(), P.sptr.get(), P.srow.get(), P.sval.get(),
                                         segs_g.get());
     OBK_HIP(hipGetLastError());
     OBK_HIP(hipMemcpyAsync(P.sptr.get() + T, &me, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    std::vector<int64_t> hsegs = to_host(segs_g.get(), std::max(G, 1), s);
+    std::vector<int64_t> hfirst = to_host(segs_g.get(), std::max(G, 1), s);
+    // every group has at least one row with a nonzero entry, hence a segment
     P.h_tptr.assign(G + 1, 0);
-    for (int32_t g = 0; g < G; g++) P.h_tptr[g + 1] = P.h_tptr[g] + hsegs[g];
+    for (int32_t g = 0; g < G; g++) P.h_tptr[g] = hfirst[g];
+    P.h_tptr[G] = T;
+    for (int32_t g = 0; g < G; g++)
+        if (P.h_tptr[g] > P.h_tptr[g + 1] || P.h_tptr[g] < 0)
+            fail(OBK_E_HIP, "inconsistent per-group column segments");
 
     // ---- sweep schedule: tiles per group for both phases
     std::vector<int64_t> hrptr = to_host(P.rptr.get(), m + 1, s);

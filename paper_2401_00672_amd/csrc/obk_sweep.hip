@@ -214,10 +214,66 @@ static void enqueue_sweeps_t(const obk_plan_s& P, const T* rval, const T* rf, co
     OBK_HIP(hipGetLastError());
 }
 
-// enqueue `sweeps` sweeps on x (device, reordered coordinates)
-void enqueue_sweeps(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
-    enqueue_sweeps_t<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), x, P.w.get(), sweeps, s);
+// Sweeps are replayed from captured graphs: one graph per (iterate, sweep
+// count, precision) holding kChunk (or 1) whole sweeps as kernel nodes; the
+// host then launches ceil(sweeps / kChunk) graphs instead of 2 G kernels per
+// sweep.
+constexpr int64_t kChunk = 8;
+
+template <class T>
+static hipGraphExec_t sweep_graph(obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval, T* x,
+                                  T* w, int64_t sweeps) {
+    for (auto& g : P.graphs)
+        if (g.x == (const void*)x && g.sweeps == sweeps && g.elem == (int)sizeof(T) && g.exec) return g.exec;
+    if (!P.capture_stream) OBK_HIP(hipStreamCreateWithFlags(&P.capture_stream, hipStreamNonBlocking));
+    obk_plan_s::SweepGraph sg;
+    sg.x = x; sg.sweeps = sweeps; sg.elem = (int)sizeof(T);
+    OBK_HIP(hipStreamBeginCapture(P.capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_sweeps_t<T>(P, rval, rf, rinv, sval, x, w, sweeps, P.capture_stream);
+    } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(P.capture_stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+    }
+    OBK_HIP(hipStreamEndCapture(P.capture_stream, &sg.graph));
+    OBK_HIP(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+    P.graphs.push_back(sg);
+    return sg.exec;
 }
+
+template <class T>
+static void run_sweeps(obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval, T* x, T* w,
+                       int64_t sweeps, hipStream_t s) {
+    if (sweeps <= 0 || P.ngroups == 0) return;
+    if (sweeps >= kChunk) {
+        hipGraphExec_t ex = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, kChunk);
+        for (int64_t i = 0; i + kChunk <= sweeps; i += kChunk) OBK_HIP(hipGraphLaunch(ex, s));
+    }
+    const int64_t rest = sweeps % kChunk;
+    if (rest) {
+        hipGraphExec_t ex = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, 1);
+        for (int64_t i = 0; i < rest; i++) OBK_HIP(hipGraphLaunch(ex, s));
+    }
+}
+
+// enqueue `sweeps` sweeps on x (device, reordered coordinates)
+void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
+    run_sweeps<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), x, P.w.get(), sweeps, s);
+}
+
+}  // namespace obk
+
+obk_plan_s::~obk_plan_s() {
+    for (auto& g : graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+namespace obk {
 
 // relative residual ||f~ - A~ x|| / ||f~|| (synchronises the stream); sets *nonfinite
 double relres(const obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
@@ -346,8 +402,8 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     const int inner = std::max(1, P.opts.inner_sweeps);
     while (inf.status == OBK_MAXIT && inf.outer_steps < maxit && sigma > 0.0) {
         k_make_rhs<<<nblk(std::max(m, n)), 256, 0, s>>>(m, n, P.r64.get(), sigma, P.b32.get(), P.d32.get());
-        enqueue_sweeps_t<float>(P, P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sval32.get(), P.d32.get(),
-                                P.w32.get(), inner, s);
+        run_sweeps<float>(P, P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sval32.get(), P.d32.get(),
+                          P.w32.get(), inner, s);
         k_update_x<<<nblk(n), 256, 0, s>>>(n, sigma, P.d32.get(), P.x.get());
         OBK_HIP(hipGetLastError());
         inf.outer_steps++;
