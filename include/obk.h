@@ -142,6 +142,15 @@ OBK_API obk_status obk_solve(obk_plan_t plan, const double *x0, double tol, int6
 /* Release a plan and its device memory.  NULL is a no-op. */
 OBK_API void obk_free(obk_plan_t plan);
 
+/*
+ * Change a plan's solve options (precision, inner_sweeps, check_every) without
+ * replanning; switching to OBK_FP32_IR allocates the FP32 copies (checked
+ * against opts->hbm_budget when nonzero).  use_rcm and reject_inconsistent are
+ * plan-time options and are ignored here.  Errors: OBK_E_ARG, OBK_E_NOMEM,
+ * OBK_E_BUSY.
+ */
+OBK_API obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts *opts);
+
 /* Introspection (host outputs). */
 /* p_host[t] = original index of reordered row t (new -> old), n entries. */
 OBK_API obk_status obk_plan_perm(obk_plan_t plan, int32_t *p_host);
@@ -165,6 +174,56 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  */
 OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_t sweeps,
                             obk_stream_t stream);
+
+/*
+ * Batched solves: several plans advanced together in shared launches (one
+ * persistent launch per step runs the sweeps of every system).  All plans of
+ * a batch must share one precision and live on the current device; a plan may
+ * belong to several batch objects but only one may run at a time.
+ *
+ * A step is, for OBK_FP32_IR plans, one iterative-refinement step (FP64
+ * residual, scale sigma = max|r_i|, opts.inner_sweeps FP32 sweeps on the
+ * scaled correction system, FP64 update) and, for OBK_FP64 plans,
+ * opts.check_every FP64 sweeps after an FP64 residual.  A system takes part
+ * in a step while it is enabled, its relative residual at the start of the
+ * step is above tol (tol <= 0: always) and finite, and sigma > 0.
+ *
+ * Tunables (0 = default): wgs_per_cu workgroups per compute unit in the
+ * persistent launch (default 4, clamped to occupancy); team_work, the entries
+ * per sweep one workgroup of a system's team should carry (default 131072);
+ * max_team, the largest team (default 16).  obk_batch_tune times candidate
+ * settings on the given plans and returns the fastest.
+ */
+typedef struct obk_batch_s *obk_batch_t;
+typedef struct {
+    int wgs_per_cu;
+    int64_t team_work;
+    int max_team;
+} obk_batch_opts;
+
+/* Build the launch schedule for `count` plans (the handles must outlive the batch). */
+OBK_API obk_status obk_batch_create(const obk_plan_t *plans, int count, const obk_batch_opts *opts,
+                                    obk_batch_t *out);
+/* x~_i = P_i x0_i for every system (x0 NULL, or x0[i] NULL: zeros); re-enables all systems. */
+OBK_API obk_status obk_batch_begin(obk_batch_t batch, const double *const *x0, obk_stream_t stream);
+/* One step for all systems.  relres[i] (host, may be NULL) receives system i's
+ * relative residual at the start of the step, active[i] (host, may be NULL)
+ * whether the step advanced it. */
+OBK_API obk_status obk_batch_step(obk_batch_t batch, double tol, double *relres, int32_t *active,
+                                  obk_stream_t stream);
+/* enabled[i] = 0 removes system i from later steps until obk_batch_begin. */
+OBK_API obk_status obk_batch_enable(obk_batch_t batch, const int32_t *enabled, obk_stream_t stream);
+/* x = P^T x~ of system `index`, in the plan's input memory space. */
+OBK_API obk_status obk_batch_result(obk_batch_t batch, int index, double *x, obk_stream_t stream);
+OBK_API void obk_batch_free(obk_batch_t batch);
+/* Solve every system to tol (or maxit steps): x0/x are arrays of `count`
+ * pointers (x0 may be NULL); infos (may be NULL) gets one obk_info each. */
+OBK_API obk_status obk_solve_batch(const obk_plan_t *plans, int count, const double *const *x0, double tol,
+                                   int64_t maxit, double *const *x, obk_info *infos, const obk_batch_opts *opts,
+                                   obk_stream_t stream);
+/* Autotuner: times candidate tunables on these plans (iterates are reset to 0)
+ * and writes the fastest to *best and its time per step to *seconds. */
+OBK_API obk_status obk_batch_tune(const obk_plan_t *plans, int count, obk_batch_opts *best, double *seconds);
 
 /*
  * Host stages of obk_plan, exported so that they can be used and tested

@@ -16,7 +16,8 @@ from typing import Any
 
 import numpy as np
 
-__all__ = ["ObkError", "Plan", "plan", "plan_system", "rcm_host", "first_fit_host", "lib", "LIB_PATH", "STATUS", "FP64", "FP32_IR"]
+__all__ = ["ObkError", "Plan", "plan", "plan_system", "rcm_host", "first_fit_host", "solve_batch",
+           "batch_tune", "Batch", "lib", "LIB_PATH", "STATUS", "FP64", "FP32_IR"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libobk.so")
@@ -43,6 +44,10 @@ class _Opts(ctypes.Structure):
     _fields_ = [("use_rcm", ctypes.c_int), ("precision", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("reject_inconsistent", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("wgs_per_cu", ctypes.c_int), ("team_work", ctypes.c_int64), ("max_team", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -83,12 +88,25 @@ def lib() -> ctypes.CDLL:
         L.obk_plan_stats.argtypes = [_P] + [ctypes.POINTER(ctypes.c_int64)] * 2 + \
             [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_int64)] * 2
         L.obk_sweep_device.argtypes = [_P, _P, ctypes.c_int64, _P]
+        L.obk_plan_set_opts.argtypes = [_P, ctypes.POINTER(_Opts)]
+        L.obk_plan_set_opts.restype = ctypes.c_int
         L.obk_last_error.restype = ctypes.c_char_p
         L.obk_rcm_host.argtypes = [ctypes.c_int64, _P, _P, _P]
         L.obk_first_fit_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]
+        L.obk_batch_create.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_P)]
+        L.obk_batch_begin.argtypes = [_P, _P, _P]
+        L.obk_batch_step.argtypes = [_P, ctypes.c_double, _P, _P, _P]
+        L.obk_batch_enable.argtypes = [_P, _P, _P]
+        L.obk_batch_result.argtypes = [_P, ctypes.c_int, _P, _P]
+        L.obk_batch_free.argtypes = [_P]
+        L.obk_batch_free.restype = None
+        L.obk_solve_batch.argtypes = [_P, ctypes.c_int, _P, ctypes.c_double, ctypes.c_int64, _P, _P,
+                                      ctypes.POINTER(_BatchOpts), _P]
+        L.obk_batch_tune.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_BatchOpts), ctypes.POINTER(ctypes.c_double)]
         for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_rcm_host",
-                     "obk_first_fit_host"):
+                     "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
+                     "obk_batch_enable", "obk_batch_result", "obk_solve_batch", "obk_batch_tune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -130,7 +148,8 @@ def _stream(stream) -> int | None:
 class Plan:
     """A device-resident OBK-RCM plan (reordered, grouped system + workspace)."""
 
-    def __init__(self, handle: int, n: int, nnz: int, on_device: bool):
+    def __init__(self, handle: int, n: int, nnz: int, on_device: bool, opts: dict | None = None):
+        self._opts = dict(opts or {})
         self._h = handle
         self.n = n
         self.nnz = nnz
@@ -186,6 +205,17 @@ class Plan:
         import torch
         st = _stream(stream) or torch.cuda.current_stream().cuda_stream
         _check(lib().obk_sweep_device(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st))
+
+    def set_opts(self, precision: int | None = None, inner_sweeps: int | None = None,
+                 check_every: int | None = None) -> None:
+        """obk_plan_set_opts: change solve options without replanning."""
+        o = _Opts()
+        lib().obk_opts_default(ctypes.byref(o))
+        o.precision = self._opts.get("precision", FP64) if precision is None else int(precision)
+        o.inner_sweeps = self._opts.get("inner_sweeps", 8) if inner_sweeps is None else int(inner_sweeps)
+        o.check_every = self._opts.get("check_every", 1) if check_every is None else int(check_every)
+        _check(lib().obk_plan_set_opts(self.handle, ctypes.byref(o)))
+        self._opts.update(precision=o.precision, inner_sweeps=o.inner_sweeps, check_every=o.check_every)
 
     # -- introspection
     def perm(self) -> np.ndarray:
@@ -248,7 +278,8 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     h = _P()
     _check(lib().obk_plan(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
     del keep
-    return Plan(h.value, nrows, nnz, on_device)
+    return Plan(h.value, nrows, nnz, on_device,
+                {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every)})
 
 
 def rcm_host(gptr, gadj) -> np.ndarray:
@@ -278,3 +309,117 @@ def first_fit_host(cptr, cidx, active):
 def plan_system(s, delta: float, **kw) -> Plan:
     """obk_plan on a ``synth.System`` (host arrays)."""
     return plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)
+
+
+# ------------------------------------------------------------------ batches
+def _handles(plans):
+    arr = (_P * len(plans))(*[p.handle for p in plans])
+    return arr
+
+
+def _batch_opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, _BatchOpts):
+        return opts
+    return _BatchOpts(int(opts.get("wgs_per_cu", 0)), int(opts.get("team_work", 0)), int(opts.get("max_team", 0)))
+
+
+def _ptr_array(arrays, on_device, dtype_name="float64"):
+    if arrays is None:
+        return None, []
+    keep, ptrs = [], []
+    for a in arrays:
+        if a is None:
+            ptrs.append(None)
+        elif on_device:
+            ptrs.append(_dev_ptr(a, dtype_name))
+        else:
+            h = _host(a, np.float64)
+            keep.append(h)
+            ptrs.append(h.ctypes.data)
+    return (_P * len(ptrs))(*ptrs), keep
+
+
+def solve_batch(plans, x0=None, tol: float = 1e-10, maxit: int = 100, opts=None, stream=None):
+    """obk_solve_batch: solve all plans together; returns (list of x, list of Info)."""
+    plans = list(plans)
+    on_dev = bool(plans) and plans[0].on_device
+    if on_dev:
+        import torch
+        xs = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p in plans]
+        st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+    else:
+        xs = [np.empty(p.n, dtype=np.float64) for p in plans]
+        st = _stream(stream)
+    x0arr, keep0 = _ptr_array(x0, on_dev)
+    xarr, keep1 = _ptr_array(xs, on_dev) if not on_dev else ((_P * len(xs))(*[x.data_ptr() for x in xs]), [])
+    if not on_dev:
+        xarr = (_P * len(xs))(*[x.ctypes.data for x in xs])
+    infos = (_Info * max(len(plans), 1))()
+    o = _batch_opts(opts)
+    _check(lib().obk_solve_batch(_handles(plans), len(plans), x0arr, float(tol), int(maxit), xarr, infos,
+                                 ctypes.byref(o) if o is not None else None, st))
+    out = [Info(i.sweeps, i.outer_steps, i.relres0, i.relres, i.seconds, STATUS.get(i.status, str(i.status)))
+           for i in list(infos)[:len(plans)]]
+    return xs, out
+
+
+def batch_tune(plans):
+    """obk_batch_tune: returns (dict of the fastest tunables, seconds per step)."""
+    plans = list(plans)
+    best = _BatchOpts()
+    sec = ctypes.c_double(0)
+    _check(lib().obk_batch_tune(_handles(plans), len(plans), ctypes.byref(best), ctypes.byref(sec)))
+    return {"wgs_per_cu": best.wgs_per_cu, "team_work": best.team_work, "max_team": best.max_team}, sec.value
+
+
+class Batch:
+    """A batch of plans advanced in shared launches (obk_batch_*)."""
+
+    def __init__(self, plans, opts=None):
+        self.plans = list(plans)
+        self._keep = _handles(self.plans)
+        h = _P()
+        o = _batch_opts(opts)
+        _check(lib().obk_batch_create(self._keep, len(self.plans), ctypes.byref(o) if o is not None else None,
+                                      ctypes.byref(h)))
+        self._h = h.value
+
+    def begin(self, x0=None, stream=None):
+        on_dev = bool(self.plans) and self.plans[0].on_device
+        arr, keep = _ptr_array(x0, on_dev)
+        _check(lib().obk_batch_begin(self._h, arr, _stream(stream)))
+
+    def step(self, tol: float, stream=None):
+        n = len(self.plans)
+        rr = np.empty(max(n, 1), np.float64)
+        act = np.empty(max(n, 1), np.int32)
+        _check(lib().obk_batch_step(self._h, float(tol), rr.ctypes.data, act.ctypes.data, _stream(stream)))
+        return rr[:n], act[:n].astype(bool)
+
+    def enable(self, enabled, stream=None):
+        e = np.ascontiguousarray(enabled, dtype=np.int32)
+        _check(lib().obk_batch_enable(self._h, e.ctypes.data, _stream(stream)))
+
+    def result(self, i: int, stream=None):
+        p = self.plans[i]
+        if p.on_device:
+            import torch
+            x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+            _check(lib().obk_batch_result(self._h, int(i), x.data_ptr(), _stream(stream)))
+        else:
+            x = np.empty(p.n, np.float64)
+            _check(lib().obk_batch_result(self._h, int(i), x.ctypes.data, _stream(stream)))
+        return x
+
+    def free(self):
+        if self._h:
+            lib().obk_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

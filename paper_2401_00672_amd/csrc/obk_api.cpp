@@ -1,11 +1,13 @@
 // The C ABI of libobk: argument checks, error conversion, plan lifecycle.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <limits>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "obk_internal.h"
 
@@ -17,11 +19,25 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
 void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                    hipStream_t s);
+void ensure_fp32(obk_plan_s& P, hipStream_t s);
+void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts);
+void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s);
+void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s);
+void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s);
+void batch_set_enabled(obk_batch_s& B, const int32_t* enabled, hipStream_t s);
 }  // namespace obk
+
+// the batch object is defined with its kernels; only pointers cross here
+struct obk_batch_s;
+obk_batch_s* obk_batch_new();
+void obk_batch_delete(obk_batch_s*);
+bool* obk_batch_busy(obk_batch_s*);
+int obk_batch_count(obk_batch_s*);
 
 size_t obk_plan_s::device_bytes() const {
     return perm.bytes() + rptr.bytes() + rcol.bytes() + rval.bytes() + rf.bytes() + rinv.bytes() +
            tcol.bytes() + sptr.bytes() + srow.bytes() + sval.bytes() + rtiles.bytes() + stiles.bytes() +
+           d_rtile_ptr.bytes() + d_stile_ptr.bytes() +
            x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
            b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes();
 }
@@ -117,6 +133,21 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
     });
 }
 
+obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts* opts) {
+    return guarded([&] {
+        if (!plan || !opts) obk::fail(OBK_E_ARG, "NULL argument");
+        if (opts->precision != OBK_FP64 && opts->precision != OBK_FP32_IR) obk::fail(OBK_E_ARG, "unknown precision");
+        if (opts->inner_sweeps < 1 || opts->check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
+        BusyGuard busy(plan);
+        OBK_HIP(hipSetDevice(plan->device));
+        plan->opts.precision = opts->precision;
+        plan->opts.inner_sweeps = opts->inner_sweeps;
+        plan->opts.check_every = opts->check_every;
+        plan->opts.hbm_budget = opts->hbm_budget;
+        if (plan->has_fp32()) obk::ensure_fp32(*plan, nullptr);
+    });
+}
+
 obk_status obk_sweep_device(obk_plan_t plan, double* x_tilde_dev, int64_t sweeps, obk_stream_t stream) {
     return guarded([&] {
         if (!plan || !x_tilde_dev) obk::fail(OBK_E_ARG, "plan and x_tilde_dev must not be NULL");
@@ -183,6 +214,147 @@ obk_status obk_first_fit_host(int64_t n, const int64_t* cptr, const int32_t* cid
         if (n > 0 && cptr[n] > 0 && !cidx) obk::fail(OBK_E_ARG, "cidx is NULL");
         int32_t ng = obk::host_first_fit(n, cptr, cidx, active, group);
         if (n_groups) *n_groups = ng;
+    });
+}
+
+obk_status obk_batch_create(const obk_plan_t* plans, int count, const obk_batch_opts* opts, obk_batch_t* out) {
+    if (out) *out = nullptr;
+    obk_batch_s* B = nullptr;
+    obk_status st = guarded([&] {
+        if (!out || count < 0 || (count > 0 && !plans)) obk::fail(OBK_E_ARG, "bad argument");
+        B = obk_batch_new();
+        obk::batch_create(*B, plans, count, opts);
+    });
+    if (st != OBK_OK) { obk_batch_delete(B); return st; }
+    *out = B;
+    return OBK_OK;
+}
+
+obk_status obk_batch_begin(obk_batch_t batch, const double* const* x0, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch) obk::fail(OBK_E_ARG, "NULL batch");
+        obk::batch_begin(*batch, x0, as_hip(stream));
+    });
+}
+
+obk_status obk_batch_step(obk_batch_t batch, double tol, double* relres, int32_t* active, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch || std::isnan(tol)) obk::fail(OBK_E_ARG, "bad argument");
+        bool* busy = obk_batch_busy(batch);
+        if (__atomic_exchange_n(busy, true, __ATOMIC_ACQ_REL)) obk::fail(OBK_E_BUSY, "a step on this batch is running");
+        try {
+            obk::batch_step(*batch, tol, relres, active, as_hip(stream));
+        } catch (...) {
+            __atomic_store_n(busy, false, __ATOMIC_RELEASE);
+            throw;
+        }
+        __atomic_store_n(busy, false, __ATOMIC_RELEASE);
+    });
+}
+
+obk_status obk_batch_enable(obk_batch_t batch, const int32_t* enabled, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch || (!enabled && obk_batch_count(batch) > 0)) obk::fail(OBK_E_ARG, "bad argument");
+        obk::batch_set_enabled(*batch, enabled, as_hip(stream));
+    });
+}
+
+obk_status obk_batch_result(obk_batch_t batch, int index, double* x, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch || !x || index < 0 || index >= obk_batch_count(batch)) obk::fail(OBK_E_ARG, "bad argument");
+        obk::batch_result(*batch, index, x, as_hip(stream));
+    });
+}
+
+void obk_batch_free(obk_batch_t batch) {
+    if (!batch) return;
+    (void)hipDeviceSynchronize();
+    obk_batch_delete(batch);
+}
+
+obk_status obk_solve_batch(const obk_plan_t* plans, int count, const double* const* x0, double tol, int64_t maxit,
+                           double* const* x, obk_info* infos, const obk_batch_opts* opts, obk_stream_t stream) {
+    return guarded([&] {
+        if (count < 0 || (count > 0 && (!plans || !x)) || maxit < 0 || std::isnan(tol))
+            obk::fail(OBK_E_ARG, "bad argument");
+        auto t0 = std::chrono::steady_clock::now();
+        obk_batch_s* B = obk_batch_new();
+        struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};
+        obk::batch_create(*B, plans, count, opts);
+        hipStream_t s = as_hip(stream);
+        obk::batch_begin(*B, x0, s);
+        std::vector<double> rr(count), first(count, -1.0);
+        std::vector<int32_t> act(count), done(count, 0), steps(count, 0);
+        std::vector<obk_info> inf(count);
+        int remaining = count;
+        for (int64_t it = 0; it < maxit && remaining > 0; it++) {
+            obk::batch_step(*B, tol, rr.data(), act.data(), s);
+            for (int i = 0; i < count; i++) {
+                if (done[i]) continue;
+                if (first[i] < 0) first[i] = rr[i];
+                if (!act[i]) {
+                    done[i] = 1;
+                    remaining--;
+                    inf[i].relres = rr[i];
+                    inf[i].status = !std::isfinite(rr[i]) ? OBK_NONFINITE_ITERATE : OBK_CONVERGED;
+                } else {
+                    steps[i]++;
+                }
+            }
+        }
+        if (remaining > 0) {     // residual of the systems still running (no further update)
+            obk::batch_step(*B, INFINITY, rr.data(), act.data(), s);
+            for (int i = 0; i < count; i++)
+                if (!done[i]) {
+                    inf[i].relres = rr[i];
+                    inf[i].status = !std::isfinite(rr[i]) ? OBK_NONFINITE_ITERATE
+                                    : (tol > 0 && rr[i] <= tol) ? OBK_CONVERGED : OBK_MAXIT;
+                    if (first[i] < 0) first[i] = rr[i];
+                }
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < count; i++) {
+            obk::batch_result(*B, i, x[i], s);
+            const bool ir = plans[i]->opts.precision == OBK_FP32_IR;
+            inf[i].outer_steps = steps[i];
+            inf[i].sweeps = steps[i] * (ir ? plans[i]->opts.inner_sweeps : plans[i]->opts.check_every);
+            inf[i].relres0 = first[i];
+            inf[i].seconds = secs;
+            if (infos) infos[i] = inf[i];
+        }
+    });
+}
+
+obk_status obk_batch_tune(const obk_plan_t* plans, int count, obk_batch_opts* best, double* seconds) {
+    return guarded([&] {
+        if (count <= 0 || !plans || !best) obk::fail(OBK_E_ARG, "bad argument");
+        hipStream_t s = nullptr;
+        OBK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        struct SD { hipStream_t s; ~SD() { (void)hipStreamDestroy(s); } } sd{s};
+        double best_t = INFINITY;
+        obk_batch_opts best_o{};
+        for (int per_cu : {2, 4, 8}) {
+            for (int64_t tw : {int64_t(1) << 15, int64_t(1) << 17, int64_t(1) << 19, int64_t(1) << 30}) {
+                obk_batch_opts o{per_cu, tw, 16};
+                obk_batch_s* B = obk_batch_new();
+                struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};
+                obk::batch_create(*B, plans, count, &o);
+                obk::batch_begin(*B, nullptr, s);
+                obk::batch_step(*B, -1.0, nullptr, nullptr, s);            // warm-up
+                auto t0 = std::chrono::steady_clock::now();
+                for (int r = 0; r < 2; r++) obk::batch_step(*B, -1.0, nullptr, nullptr, s);
+                const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / 2;
+                if (t < best_t) { best_t = t; best_o = o; }
+            }
+        }
+        *best = best_o;
+        if (seconds) *seconds = best_t;
+        for (int i = 0; i < count; i++) {     // leave the iterates at zero
+            obk_batch_s* B = obk_batch_new();
+            struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};
+            obk::batch_create(*B, plans + i, 1, &best_o);
+            obk::batch_begin(*B, nullptr, s);
+        }
     });
 }
 

@@ -1,0 +1,518 @@
+// Batched solves: many independent plans advanced in shared launches.
+//
+// A refinement step over a batch (all plans OBK_FP32_IR):
+//   1. one launch computes r = f~ - A~ x~ in FP64 for every system (row blocks
+//      of all systems) with per-block sums of r^2 and maxima of |r|;
+//   2. one launch reduces them per system (fixed order): relres, sigma and the
+//      system's active flag (relres > tol, sigma > 0, finite);
+//   3. one launch forms b = (float)(r / sigma) and d = 0 for active systems;
+//   4. ONE persistent launch runs the inner FP32 sweeps of every active
+//      system: each system is owned by a team of workgroups placed on one XCD
+//      (team size from the system's work), teams synchronise only among
+//      themselves between the phases of a sweep;
+//   5. one launch applies x~ += sigma d in FP64.
+// With OBK_FP64 plans, step 4 runs check_every FP64 sweeps on x~ directly and
+// steps 3 and 5 are skipped.
+//
+// Team barriers are generation barriers in device memory (agent-scope
+// release/acquire); a workgroup's task list is ordered by team id, so a team
+// can always complete once its lowest-numbered members arrive.  Every wait is
+// bounded: past the bound the kernel records an error and leaves, and the host
+// reports OBK_E_HIP.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "obk_internal.h"
+#include "obk_sweep_tiles.h"
+
+namespace obk {
+
+void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+
+namespace {
+
+constexpr long kSpinLimit = 1L << 22;
+
+template <class T> struct BatchSys {
+    const Tile* rtiles;
+    const Tile* stiles;
+    const int32_t* rtile_ptr;
+    const int32_t* stile_ptr;
+    const int64_t* rptr;
+    const int32_t* rcol;
+    const T* rval;
+    const T* rf;
+    const T* rinv;
+    const int64_t* sptr;
+    const int32_t* srow;
+    const T* sval;
+    const int32_t* tcol;
+    T* x;
+    T* w;
+    int32_t ngroups;
+    int32_t team;
+    uint32_t* bar;           // [0] arrivals, [1] generation
+};
+
+struct TeamTask {
+    int32_t sys;
+    int32_t rank;
+};
+
+struct Block {               // a range of rows or columns of one system
+    int32_t sys;
+    int32_t begin;
+    int32_t end;
+};
+
+struct ResSys {              // FP64 arrays for residual, scaling and update
+    const int64_t* rptr;
+    const int32_t* rcol;
+    const double* rval;
+    const double* rf;
+    double* x;
+    double* r;
+    float* b;
+    float* d;
+    double fnorm2, zero_f2, zero_fmax;
+};
+
+__device__ __forceinline__ void team_barrier(uint32_t* bar, int team, int* err) {
+    __syncthreads();
+    if (team > 1) {
+        if (threadIdx.x == 0) {
+            const uint32_t gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t arrived =
+                __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == (uint32_t)team - 1) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                // bounded wait for the generation to move on
+                uint32_t cur = gen;
+                long spins = 0;
+#pragma clang loop unroll(disable)
+                do {
+                    __builtin_amdgcn_s_sleep(1);
+                    cur = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    spins++;
+                } while ((cur == gen) & (spins <= kSpinLimit));
+                if (cur == gen) atomicOr(err, 1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kTileThreads) void k_batch_sweeps(const BatchSys<T>* __restrict__ systems,
+                                                               const int32_t* __restrict__ task_ptr,
+                                                               const TeamTask* __restrict__ tasks,
+                                                               const uint8_t* __restrict__ active, int sweeps,
+                                                               int* err) {
+    __shared__ T prod[kTileEntries];
+    const int32_t t0 = task_ptr[blockIdx.x], t1 = task_ptr[blockIdx.x + 1];
+    for (int32_t ti = t0; ti < t1; ti++) {
+        const TeamTask tk = tasks[ti];
+        if (!active[tk.sys]) continue;
+        const BatchSys<T> S = systems[tk.sys];
+        for (int sw = 0; sw < sweeps; sw++) {
+            for (int32_t g = 0; g < S.ngroups; g++) {
+                const int32_t r0 = S.rtile_ptr[g], r1 = S.rtile_ptr[g + 1];
+                for (int32_t t = r0 + tk.rank; t < r1; t += S.team) {
+                    const Tile tl = S.rtiles[t];
+                    tile_phase_r<T>(tl, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
+                }
+                team_barrier(S.bar, S.team, err);
+                const int32_t s0 = S.stile_ptr[g], s1 = S.stile_ptr[g + 1];
+                for (int32_t t = s0 + tk.rank; t < s1; t += S.team) {
+                    const Tile tl = S.stiles[t];
+                    tile_phase_s<T>(tl, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
+                }
+                team_barrier(S.bar, S.team, err);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_resid(const ResSys* __restrict__ sys, const Block* __restrict__ blocks,
+                                                     double* __restrict__ psum, double* __restrict__ pmax,
+                                                     int* __restrict__ nonfinite) {
+    __shared__ double red[256];
+    __shared__ double mx[256];
+    const Block bk = blocks[blockIdx.x];
+    const ResSys S = sys[bk.sys];
+    const int64_t a = bk.begin + (int64_t)threadIdx.x;
+    const bool valid = a < bk.end;
+    const int64_t ac = valid ? a : bk.begin;
+    const int64_t k0 = S.rptr[ac], k1 = valid ? S.rptr[ac + 1] : k0;
+    double s = 0.0;
+    for (int64_t k = k0; k < k1; k++) s = s + S.rval[k] * S.x[S.rcol[k]];
+    const double ri = S.rf[ac] - s;
+    if (valid) {
+        if (S.r) S.r[a] = ri;      // FP64 plans keep no residual vector
+        if (!isfinite(ri)) atomicOr(nonfinite, 1);
+    }
+    red[threadIdx.x] = valid ? ri * ri : 0.0;
+    mx[threadIdx.x] = valid ? fabs(ri) : 0.0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { psum[blockIdx.x] = red[0]; pmax[blockIdx.x] = mx[0]; }
+}
+
+// one block per system: ordered reduction of its row blocks
+__global__ __launch_bounds__(256) void k_batch_reduce(const ResSys* __restrict__ sys,
+                                                      const int32_t* __restrict__ blk_ptr,
+                                                      const double* __restrict__ psum,
+                                                      const double* __restrict__ pmax, double tol,
+                                                      const uint8_t* __restrict__ enabled,
+                                                      double* __restrict__ relres, double* __restrict__ sigma,
+                                                      uint8_t* __restrict__ active) {
+    __shared__ double red[256];
+    __shared__ double mx[256];
+    const int s = blockIdx.x;
+    const int32_t b0 = blk_ptr[s], b1 = blk_ptr[s + 1];
+    double acc = 0.0, m = 0.0;
+    for (int32_t b = b0 + threadIdx.x; b < b1; b += 256) { acc = acc + psum[b]; m = fmax(m, pmax[b]); }
+    red[threadIdx.x] = acc;
+    mx[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    // every thread derives the (uniform) results; thread 0 stores them
+    const ResSys S = sys[s];
+    const double r2 = red[0] + S.zero_f2;
+    const double sg = fmax(mx[0], S.zero_fmax);
+    const double denom = (S.fnorm2 == 0.0) ? 1.0 : S.fnorm2;
+    const double q = sqrt(r2) / sqrt(denom);
+    const double rho = (S.fnorm2 == 0.0) ? ((r2 == 0.0) ? 0.0 : INFINITY) : q;
+    const bool go = enabled[s] && isfinite(rho) && (rho > tol) && (sg > 0.0);
+    if (threadIdx.x == 0) {
+        relres[s] = rho;
+        sigma[s] = sg;
+        active[s] = go ? 1 : 0;
+    }
+}
+
+__global__ void k_batch_rhs(const ResSys* __restrict__ sys, const Block* __restrict__ rows,
+                            const double* __restrict__ sigma, const uint8_t* __restrict__ active) {
+    const Block bk = rows[blockIdx.x];
+    const int64_t a = bk.begin + (int64_t)threadIdx.x;
+    if (a >= bk.end || !active[bk.sys]) return;
+    const ResSys S = sys[bk.sys];
+    S.b[a] = (float)(S.r[a] / sigma[bk.sys]);
+}
+
+__global__ void k_batch_cols(const ResSys* __restrict__ sys, const Block* __restrict__ cols,
+                             const double* __restrict__ sigma, const uint8_t* __restrict__ active, int update) {
+    const Block bk = cols[blockIdx.x];
+    const int64_t c = bk.begin + (int64_t)threadIdx.x;
+    if (c >= bk.end || !active[bk.sys]) return;
+    const ResSys S = sys[bk.sys];
+    if (update) S.x[c] = S.x[c] + sigma[bk.sys] * (double)S.d[c];
+    else S.d[c] = 0.0f;
+}
+
+__global__ void k_batch_permute_in(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ x0,
+                                   double* __restrict__ xt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) xt[t] = x0 ? x0[p[t]] : 0.0;
+}
+
+__global__ void k_batch_permute_out(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ xt,
+                                    double* __restrict__ x) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[p[t]] = xt[t];
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+template <class T> BatchSys<T> sys_view(obk_plan_s& P, uint32_t* bar, int team);
+template <> BatchSys<float> sys_view<float>(obk_plan_s& P, uint32_t* bar, int team) {
+    return BatchSys<float>{P.rtiles.get(), P.stiles.get(), P.d_rtile_ptr.get(), P.d_stile_ptr.get(), P.rptr.get(),
+                           P.rcol.get(), P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sptr.get(), P.srow.get(),
+                           P.sval32.get(), P.tcol.get(), P.d32.get(), P.w32.get(), P.ngroups, team, bar};
+}
+template <> BatchSys<double> sys_view<double>(obk_plan_s& P, uint32_t* bar, int team) {
+    return BatchSys<double>{P.rtiles.get(), P.stiles.get(), P.d_rtile_ptr.get(), P.d_stile_ptr.get(), P.rptr.get(),
+                            P.rcol.get(), P.rval.get(), P.rf.get(), P.rinv.get(), P.sptr.get(), P.srow.get(),
+                            P.sval.get(), P.tcol.get(), P.x.get(), P.w.get(), P.ngroups, team, bar};
+}
+
+}  // namespace
+}  // namespace obk
+
+// ------------------------------------------------------------------ engine
+struct obk_batch_s {
+    std::vector<obk_plan_s*> plans;
+    obk_batch_opts opts{};
+    bool fp32 = false;
+    int device = 0;
+    int nwg = 0;
+    std::vector<int32_t> team;               // team size per system
+    obk::DevArray<uint8_t> enabled, active;  // per system
+    obk::DevArray<double> relres, sigma;     // per system
+    obk::DevArray<uint32_t> bars;            // 2 per system
+    obk::DevArray<int32_t> task_ptr;
+    obk::DevArray<char> tasks, sys_sweep, sys_res;
+    obk::DevArray<char> rowblocks, colblocks;
+    obk::DevArray<int32_t> rowblk_ptr;
+    obk::DevArray<double> psum, pmax;
+    obk::DevArray<int> err;
+    int64_t n_rowblocks = 0, n_colblocks = 0;
+    std::vector<uint8_t> h_enabled;
+    bool busy = false;
+};
+
+namespace obk {
+namespace {
+
+template <class T> void upload(DevArray<char>& d, const std::vector<T>& h) {
+    d.alloc(std::max<size_t>(h.size() * sizeof(T), 1));
+    if (!h.empty()) OBK_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Team sizing and placement.  Work of a system per sweep ~ its entries in
+// both phases; a system gets ceil(work / team_work) workgroups (at most
+// max_team), all on one XCD (workgroup b runs on XCD b % 8).  Single-workgroup
+// teams are packed onto the least-loaded workgroups.  Each workgroup's task
+// list is ordered by system id.
+void build_schedule(obk_batch_s& B) {
+    const int count = (int)B.plans.size();
+    int dev = 0, cus = 256;
+    OBK_HIP(hipGetDevice(&dev));
+    OBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = B.opts.wgs_per_cu > 0 ? B.opts.wgs_per_cu : 4;
+    // every workgroup of the persistent launch must be resident at once
+    int occ = 0;
+    if (B.fp32)
+        OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float>, kTileThreads, 0));
+    else
+        OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double>, kTileThreads, 0));
+    per_cu = std::max(1, std::min(per_cu, occ));
+    const int nxcd = 8;
+    int nwg = std::max(nxcd, cus * per_cu);
+    nwg -= nwg % nxcd;
+    B.nwg = nwg;
+    const int64_t team_work = B.opts.team_work > 0 ? B.opts.team_work : (1 << 17);
+    const int max_team = std::max(1, std::min(B.opts.max_team > 0 ? B.opts.max_team : 16, nwg / nxcd));
+    std::vector<int64_t> work(count);
+    for (int s = 0; s < count; s++) work[s] = 2 * B.plans[s]->nnz + 2 * B.plans[s]->m;
+    B.team.assign(count, 1);
+    std::vector<std::vector<TeamTask>> per_wg(nwg);
+    std::vector<int64_t> load(nwg, 0);
+    // large systems first
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    const int slots = nwg / nxcd;
+    for (int s : order) {
+        int k = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (work[s] + team_work - 1) / team_work));
+        B.team[s] = k;
+        if (k == 1) {
+            int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            per_wg[best].push_back(TeamTask{s, 0});
+            load[best] += work[s];
+        } else {
+            // the XCD whose k least-loaded slots carry the least total load
+            int best_x = 0;
+            int64_t best_l = INT64_MAX;
+            std::vector<int> pick, best_pick;
+            for (int x = 0; x < nxcd; x++) {
+                pick.clear();
+                std::vector<int> ids(slots);
+                for (int j = 0; j < slots; j++) ids[j] = x + nxcd * j;
+                std::partial_sort(ids.begin(), ids.begin() + k, ids.end(),
+                                  [&](int a, int b) { return load[a] < load[b]; });
+                int64_t l = 0;
+                for (int j = 0; j < k; j++) l = std::max(l, load[ids[j]]);
+                if (l < best_l) { best_l = l; best_x = x; best_pick.assign(ids.begin(), ids.begin() + k); }
+            }
+            (void)best_x;
+            for (int j = 0; j < k; j++) {
+                per_wg[best_pick[j]].push_back(TeamTask{s, j});
+                load[best_pick[j]] = best_l + (work[s] + k - 1) / k;
+            }
+        }
+    }
+    std::vector<int32_t> tptr(nwg + 1, 0);
+    std::vector<TeamTask> flat;
+    for (int b = 0; b < nwg; b++) {
+        std::sort(per_wg[b].begin(), per_wg[b].end(), [](const TeamTask& a, const TeamTask& c) { return a.sys < c.sys; });
+        for (auto& t : per_wg[b]) flat.push_back(t);
+        tptr[b + 1] = (int32_t)flat.size();
+    }
+    B.task_ptr.alloc(nwg + 1);
+    OBK_HIP(hipMemcpy(B.task_ptr.get(), tptr.data(), (nwg + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    upload(B.tasks, flat);
+    B.bars.alloc(2 * (size_t)std::max(count, 1));
+    OBK_HIP(hipMemset(B.bars.get(), 0, 2 * sizeof(uint32_t) * std::max(count, 1)));
+    if (B.fp32) {
+        std::vector<BatchSys<float>> v;
+        for (int s = 0; s < count; s++) v.push_back(sys_view<float>(*B.plans[s], B.bars.get() + 2 * s, B.team[s]));
+        upload(B.sys_sweep, v);
+    } else {
+        std::vector<BatchSys<double>> v;
+        for (int s = 0; s < count; s++) v.push_back(sys_view<double>(*B.plans[s], B.bars.get() + 2 * s, B.team[s]));
+        upload(B.sys_sweep, v);
+    }
+    std::vector<ResSys> rs;
+    std::vector<Block> rows, cols;
+    std::vector<int32_t> rptr(count + 1, 0);
+    for (int s = 0; s < count; s++) {
+        obk_plan_s& P = *B.plans[s];
+        rs.push_back(ResSys{P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(), P.r64.get(),
+                            P.b32.get(), P.d32.get(), P.fnorm2, P.zero_rows_f2, P.zero_rows_fmax});
+        for (int64_t a = 0; a < std::max<int64_t>(P.m, 1); a += 256)
+            rows.push_back(Block{s, (int32_t)a, (int32_t)std::min<int64_t>(a + 256, P.m)});
+        rptr[s + 1] = (int32_t)rows.size();
+        for (int64_t c = 0; c < P.n; c += 256)
+            cols.push_back(Block{s, (int32_t)c, (int32_t)std::min<int64_t>(c + 256, P.n)});
+    }
+    upload(B.sys_res, rs);
+    upload(B.rowblocks, rows);
+    upload(B.colblocks, cols);
+    B.n_rowblocks = (int64_t)rows.size();
+    B.n_colblocks = (int64_t)cols.size();
+    B.rowblk_ptr.alloc(count + 1);
+    OBK_HIP(hipMemcpy(B.rowblk_ptr.get(), rptr.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    B.psum.alloc(std::max<int64_t>(B.n_rowblocks, 1));
+    B.pmax.alloc(std::max<int64_t>(B.n_rowblocks, 1));
+    B.relres.alloc(std::max(count, 1));
+    B.sigma.alloc(std::max(count, 1));
+    B.active.alloc(std::max(count, 1));
+    B.enabled.alloc(std::max(count, 1));
+    B.h_enabled.assign(count, 1);
+    OBK_HIP(hipMemcpy(B.enabled.get(), B.h_enabled.data(), count, hipMemcpyHostToDevice));
+    B.err.alloc(1);
+    OBK_HIP(hipMemset(B.err.get(), 0, sizeof(int)));
+}
+
+}  // namespace
+
+void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts) {
+    B.plans.assign(plans, plans + count);
+    if (opts) B.opts = *opts;
+    OBK_HIP(hipGetDevice(&B.device));
+    for (int s = 0; s < count; s++) {
+        if (!plans[s]) fail(OBK_E_ARG, "NULL plan in batch");
+        if (plans[s]->device != B.device) fail(OBK_E_ARG, "plans of a batch must live on the current device");
+        if (s > 0 && plans[s]->opts.precision != plans[0]->opts.precision)
+            fail(OBK_E_ARG, "plans of a batch must share one precision");
+        for (int t = 0; t < s; t++)
+            if (plans[t] == plans[s]) fail(OBK_E_ARG, "a plan appears twice in a batch");
+    }
+    B.fp32 = count > 0 && plans[0]->opts.precision == OBK_FP32_IR;
+    build_schedule(B);
+}
+
+// x~ = P x0 for every system (x0 entries may be NULL: 0)
+void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s) {
+    for (size_t i = 0; i < B.plans.size(); i++) {
+        obk_plan_s& P = *B.plans[i];
+        const double* src = x0 ? x0[i] : nullptr;
+        DevArray<double> tmp;
+        if (src && !P.input_on_device) {
+            tmp.alloc(P.n);
+            OBK_HIP(hipMemcpyAsync(tmp.get(), src, P.n * sizeof(double), hipMemcpyHostToDevice, s));
+            src = tmp.get();
+        }
+        k_batch_permute_in<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), src, P.x.get());
+        OBK_HIP(hipGetLastError());
+        if (tmp.get()) OBK_HIP(hipStreamSynchronize(s));
+    }
+    B.h_enabled.assign(B.plans.size(), 1);
+    if (!B.plans.empty())
+        OBK_HIP(hipMemcpyAsync(B.enabled.get(), B.h_enabled.data(), B.plans.size(), hipMemcpyHostToDevice, s));
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+// One step for all enabled systems; relres/active (host, may be NULL) receive
+// each system's relative residual at the start of the step and whether the
+// step advanced it.
+void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s) {
+    const int count = (int)B.plans.size();
+    if (count == 0) return;
+    k_batch_resid<<<(unsigned)B.n_rowblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
+                                                          (const Block*)B.rowblocks.get(), B.psum.get(),
+                                                          B.pmax.get(), B.err.get());
+    k_batch_reduce<<<count, 256, 0, s>>>((const ResSys*)B.sys_res.get(), B.rowblk_ptr.get(), B.psum.get(),
+                                         B.pmax.get(), tol > 0 ? tol : -1.0, B.enabled.get(), B.relres.get(),
+                                         B.sigma.get(), B.active.get());
+    OBK_HIP(hipGetLastError());
+    if (B.fp32) {
+        k_batch_rhs<<<(unsigned)B.n_rowblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
+                                                            (const Block*)B.rowblocks.get(), B.sigma.get(),
+                                                            B.active.get());
+        if (B.n_colblocks)
+            k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
+                                                                 (const Block*)B.colblocks.get(), B.sigma.get(),
+                                                                 B.active.get(), 0);
+        k_batch_sweeps<float><<<B.nwg, kTileThreads, 0, s>>>((const BatchSys<float>*)B.sys_sweep.get(),
+                                                             B.task_ptr.get(), (const TeamTask*)B.tasks.get(),
+                                                             B.active.get(), std::max(1, B.plans[0]->opts.inner_sweeps),
+                                                             B.err.get());
+        if (B.n_colblocks)
+            k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
+                                                                 (const Block*)B.colblocks.get(), B.sigma.get(),
+                                                                 B.active.get(), 1);
+    } else {
+        k_batch_sweeps<double><<<B.nwg, kTileThreads, 0, s>>>((const BatchSys<double>*)B.sys_sweep.get(),
+                                                              B.task_ptr.get(), (const TeamTask*)B.tasks.get(),
+                                                              B.active.get(),
+                                                              std::max(1, B.plans[0]->opts.check_every), B.err.get());
+    }
+    OBK_HIP(hipGetLastError());
+    std::vector<double> rr(count);
+    std::vector<uint8_t> act(count);
+    int herr = 0;
+    OBK_HIP(hipMemcpyAsync(rr.data(), B.relres.get(), count * sizeof(double), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipMemcpyAsync(act.data(), B.active.get(), count, hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipMemcpyAsync(&herr, B.err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+    if (herr & 1) fail(OBK_E_HIP, "a team barrier of the batched sweep timed out");
+    for (int i = 0; i < count; i++) {
+        if (relres_out) relres_out[i] = rr[i];
+        if (active_out) active_out[i] = act[i];
+    }
+}
+
+void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s) {
+    obk_plan_s& P = *B.plans[index];
+    DevArray<double> tmp;
+    double* dst = x;
+    if (!P.input_on_device) { tmp.alloc(P.n); dst = tmp.get(); }
+    k_batch_permute_out<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), P.x.get(), dst);
+    OBK_HIP(hipGetLastError());
+    if (!P.input_on_device) OBK_HIP(hipMemcpyAsync(x, tmp.get(), P.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+// Disable systems from further steps (e.g. after they converged).
+void batch_set_enabled(obk_batch_s& B, const int32_t* enabled, hipStream_t s) {
+    for (size_t i = 0; i < B.plans.size(); i++) B.h_enabled[i] = enabled[i] ? 1 : 0;
+    OBK_HIP(hipMemcpyAsync(B.enabled.get(), B.h_enabled.data(), B.plans.size(), hipMemcpyHostToDevice, s));
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace obk
+
+obk_batch_s* obk_batch_new() { return new obk_batch_s(); }
+void obk_batch_delete(obk_batch_s* b) { delete b; }
+bool* obk_batch_busy(obk_batch_s* b) { return &b->busy; }
+int obk_batch_count(obk_batch_s* b) { return (int)b->plans.size(); }

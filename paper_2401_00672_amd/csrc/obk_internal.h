@@ -127,8 +127,9 @@ struct obk_plan_s {
     obk::DevArray<int64_t> sptr;       // [T+1]
     obk::DevArray<int32_t> srow;       // group-major row of each entry [nnz]
     obk::DevArray<double> sval;        // [nnz]
-    // device: tiles
+    // device: tiles, and the tile range of each group
     obk::DevArray<obk::Tile> rtiles, stiles;
+    obk::DevArray<int32_t> d_rtile_ptr, d_stile_ptr;   // [G+1]
     // device: workspace
     obk::DevArray<double> x;           // reordered iterate [n]
     obk::DevArray<double> w;           // group weights [m]

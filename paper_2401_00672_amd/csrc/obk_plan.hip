@@ -372,6 +372,22 @@ double sum_squares(const double* f, const double* nu, int64_t n, bool only_zero_
     return host_sum_ordered(to_host(part.get(), nblk(n), s));
 }
 
+// FP32 copies of the values, 1/||a||^2 and the workspace of the refinement mode
+void ensure_fp32(obk_plan_s& P, hipStream_t s) {
+    if (P.rval32.get()) return;
+    const int64_t nnz_act = (int64_t)P.rval.count, me = (int64_t)P.sval.count, m = P.m, n = P.n;
+    const size_t extra = (size_t)(nnz_act + me) * 4 + (size_t)m * 16 + (size_t)n * 4 + (size_t)m * 8;
+    if (P.opts.hbm_budget && P.device_bytes() + extra > P.opts.hbm_budget)
+        fail(OBK_E_NOMEM, "FP32 copies would exceed hbm_budget");
+    P.rval32.alloc(nnz_act); P.rinv32.alloc(m); P.sval32.alloc(me);
+    k_to_f32<<<nblk(nnz_act), kT, 0, s>>>(nnz_act, P.rval.get(), P.rval32.get());
+    k_to_f32<<<nblk(m), kT, 0, s>>>(m, P.rinv.get(), P.rinv32.get());
+    k_to_f32<<<nblk(me), kT, 0, s>>>(me, P.sval.get(), P.sval32.get());
+    OBK_HIP(hipGetLastError());
+    P.b32.alloc(m); P.d32.alloc(n); P.w32.alloc(m); P.r64.alloc(m);
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
 // ---------------------------------------------------------------------------
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s) {
     const int64_t n = A.n_rows, nnz = A.nnz;
@@ -623,16 +639,11 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     }
     to_device(P.rtiles, P.h_rtiles.data(), P.h_rtiles.size(), s);
     to_device(P.stiles, P.h_stiles.data(), P.h_stiles.size(), s);
+    to_device(P.d_rtile_ptr, P.h_rtile_ptr.data(), P.h_rtile_ptr.size(), s);
+    to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
     // ---- FP32 copies for the refinement mode
-    if (P.has_fp32()) {
-        P.rval32.alloc(nnz_act); P.rinv32.alloc(m); P.sval32.alloc(me);
-        k_to_f32<<<nblk(nnz_act), kT, 0, s>>>(nnz_act, P.rval.get(), P.rval32.get());
-        k_to_f32<<<nblk(m), kT, 0, s>>>(m, P.rinv.get(), P.rinv32.get());
-        k_to_f32<<<nblk(me), kT, 0, s>>>(me, P.sval.get(), P.sval32.get());
-        OBK_HIP(hipGetLastError());
-        P.b32.alloc(m); P.d32.alloc(n); P.w32.alloc(m); P.r64.alloc(m);
-    }
+    if (P.has_fp32()) ensure_fp32(P, s);
 
     // ---- workspace
     P.x.alloc(n);

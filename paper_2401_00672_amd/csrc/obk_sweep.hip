@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "obk_internal.h"
+#include "obk_sweep_tiles.h"
 
 namespace obk {
 
@@ -24,8 +25,7 @@ namespace {
 constexpr int kT = kTileThreads;
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-// Phase R over the tiles of one group (T = double, or float in the inner
-// sweeps of iterative refinement).
+// Phase R / phase S over the tiles of one group (bodies in obk_sweep_tiles.h).
 template <class T>
 __global__ __launch_bounds__(kT) void k_phase_r(const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr,
                                                 const int32_t* __restrict__ rcol, const T* __restrict__ rval,
@@ -33,25 +33,9 @@ __global__ __launch_bounds__(kT) void k_phase_r(const Tile* __restrict__ tiles, 
                                                 const T* __restrict__ x, T* __restrict__ w) {
     __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    const int nseg = t.seg_end - t.seg_begin;
-    const int me = threadIdx.x;
-    const bool owner = me < nseg;
-    const int64_t a = t.seg_begin + (owner ? me : 0);
-    const int64_t k0 = rptr[a], k1 = rptr[a + 1];
-    T acc = T(0);
-    for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
-        const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
-        for (int q = me; q < len; q += kT) prod[q] = rval[base + q] * x[rcol[base + q]];
-        __syncthreads();
-        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
-        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
-        __syncthreads();
-    }
-    const T fa = rf[a], ia = rinv[a];
-    if (owner) w[a] = (fa - acc) * ia;
+    tile_phase_r<T>(t, prod, rptr, rcol, rval, rf, rinv, x, w);
 }
 
-// Phase S over the tiles of one group's touched columns.
 template <class T>
 __global__ __launch_bounds__(kT) void k_phase_s(const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr,
                                                 const int32_t* __restrict__ srow, const T* __restrict__ sval,
@@ -59,23 +43,7 @@ __global__ __launch_bounds__(kT) void k_phase_s(const Tile* __restrict__ tiles, 
                                                 T* __restrict__ x) {
     __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    const int nseg = t.seg_end - t.seg_begin;
-    const int me = threadIdx.x;
-    const bool owner = me < nseg;
-    const int64_t sg = t.seg_begin + (owner ? me : 0);
-    const int64_t k0 = sptr[sg], k1 = sptr[sg + 1];
-    T acc = T(0);
-    for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
-        const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
-        for (int q = me; q < len; q += kT) prod[q] = w[srow[base + q]] * sval[base + q];
-        __syncthreads();
-        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
-        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
-        __syncthreads();
-    }
-    const int32_t c = tcol[sg];
-    const T xc = x[c];
-    if (owner) x[c] = xc + acc;
+    tile_phase_s<T>(t, prod, sptr, srow, sval, tcol, w, x);
 }
 
 // r_a = f_a - a_a . x over the group-major rows; per-block sums of r_a^2

@@ -37,7 +37,34 @@ def test_no_poison_phi_after_structurization(src, tmp_path):
     for dump in r.stderr.split("*** IR Dump After")[1:]:
         m = re.search(r"define [^@]*@(\S+)\(", dump)
         fn = m.group(1) if m else "?"
-        for line in dump.splitlines():
-            if re.search(r"= phi .*\b(poison|undef)\b", line):
-                bad.append(f"{fn}: {line.strip()}")
-    assert not bad, "structurized IR with poison PHI inputs:\n" + "\n".join(bad[:20])
+        bad += [f"{fn}: {p}" for p in divergent_poison_phis(dump)]
+    assert not bad, "structurized IR with poison PHI inputs on divergent edges:\n" + "\n".join(bad[:20])
+
+
+def divergent_poison_phis(ir: str):
+    """PHIs with a poison/undef input whose incoming edge leaves a block whose
+    branch is not marked uniform.  (In uniform control flow the wave-level and
+    thread-level CFGs coincide, so such inputs are harmless.)"""
+    blocks, label, lines = {}, "entry", []
+    for line in ir.splitlines():
+        mm = re.match(r"^(\d+|[A-Za-z_.][\w.]*):", line)
+        if mm:
+            blocks[label] = lines
+            label, lines = mm.group(1), []
+        else:
+            lines.append(line)
+    blocks[label] = lines
+    uniform_term = {}
+    for lab, body in blocks.items():
+        term = [l for l in body if l.strip().startswith("br ") or l.strip().startswith("switch ")]
+        uniform_term[lab] = bool(term) and "!amdgpu.uniform" in term[-1]
+    out = []
+    for lab, body in blocks.items():
+        for line in body:
+            if not re.search(r"= phi ", line):
+                continue
+            for val, pred in re.findall(r"\[\s*([^,\]]+),\s*%([\w.]+)\s*\]", line):
+                if val.strip() in ("poison", "undef") and not uniform_term.get(pred, False):
+                    out.append(line.strip())
+                    break
+    return out
