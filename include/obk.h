@@ -189,9 +189,10 @@ OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_
  * step is above tol (tol <= 0: always) and finite, and sigma > 0.
  *
  * Tunables (0 = default): wgs_per_cu workgroups per compute unit in the
- * persistent launch (default 4, clamped to occupancy); team_work, the entries
- * per sweep one workgroup of a system's team should carry (default 131072);
- * max_team, the largest team (default 16).  obk_batch_tune times candidate
+ * persistent launch (default 2, clamped to occupancy); team_work, the entries
+ * per sweep one workgroup of a system's team should carry (default 262144);
+ * max_team, the largest team (default 16); tiles_per_wg, how many tiles of
+ * 256 rows (columns) a workgroup keeps in flight (default 4).  obk_batch_tune times candidate
  * settings on the given plans and returns the fastest.
  */
 typedef struct obk_batch_s *obk_batch_t;
@@ -199,6 +200,7 @@ typedef struct {
     int wgs_per_cu;
     int64_t team_work;
     int max_team;
+    int tiles_per_wg;        /* tiles a workgroup works on at once: 1, 2 or 4 (default 4) */
 } obk_batch_opts;
 
 /* Build the launch schedule for `count` plans (the handles must outlive the batch). */

@@ -47,7 +47,8 @@ class _Opts(ctypes.Structure):
 
 
 class _BatchOpts(ctypes.Structure):
-    _fields_ = [("wgs_per_cu", ctypes.c_int), ("team_work", ctypes.c_int64), ("max_team", ctypes.c_int)]
+    _fields_ = [("wgs_per_cu", ctypes.c_int), ("team_work", ctypes.c_int64), ("max_team", ctypes.c_int),
+                ("tiles_per_wg", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -322,7 +323,8 @@ def _batch_opts(opts):
         return None
     if isinstance(opts, _BatchOpts):
         return opts
-    return _BatchOpts(int(opts.get("wgs_per_cu", 0)), int(opts.get("team_work", 0)), int(opts.get("max_team", 0)))
+    return _BatchOpts(int(opts.get("wgs_per_cu", 0)), int(opts.get("team_work", 0)), int(opts.get("max_team", 0)),
+                      int(opts.get("tiles_per_wg", 0)))
 
 
 def _ptr_array(arrays, on_device, dtype_name="float64"):
@@ -371,7 +373,8 @@ def batch_tune(plans):
     best = _BatchOpts()
     sec = ctypes.c_double(0)
     _check(lib().obk_batch_tune(_handles(plans), len(plans), ctypes.byref(best), ctypes.byref(sec)))
-    return {"wgs_per_cu": best.wgs_per_cu, "team_work": best.team_work, "max_team": best.max_team}, sec.value
+    return ({"wgs_per_cu": best.wgs_per_cu, "team_work": best.team_work, "max_team": best.max_team,
+             "tiles_per_wg": best.tiles_per_wg}, sec.value)
 
 
 class Batch:

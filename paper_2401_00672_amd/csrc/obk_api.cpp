@@ -333,18 +333,21 @@ obk_status obk_batch_tune(const obk_plan_t* plans, int count, obk_batch_opts* be
         struct SD { hipStream_t s; ~SD() { (void)hipStreamDestroy(s); } } sd{s};
         double best_t = INFINITY;
         obk_batch_opts best_o{};
-        for (int per_cu : {2, 4, 8}) {
-            for (int64_t tw : {int64_t(1) << 15, int64_t(1) << 17, int64_t(1) << 19, int64_t(1) << 30}) {
-                obk_batch_opts o{per_cu, tw, 16};
-                obk_batch_s* B = obk_batch_new();
-                struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};
-                obk::batch_create(*B, plans, count, &o);
-                obk::batch_begin(*B, nullptr, s);
-                obk::batch_step(*B, -1.0, nullptr, nullptr, s);            // warm-up
-                auto t0 = std::chrono::steady_clock::now();
-                for (int r = 0; r < 2; r++) obk::batch_step(*B, -1.0, nullptr, nullptr, s);
-                const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / 2;
-                if (t < best_t) { best_t = t; best_o = o; }
+        for (int sub : {1, 2, 4}) {
+            for (int per_cu : {1, 2, 4, 8}) {
+                if (sub * per_cu > 16) continue;
+                for (int64_t tw : {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 30}) {
+                    obk_batch_opts o{per_cu, tw, 16, sub};
+                    obk_batch_s* B = obk_batch_new();
+                    struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};
+                    obk::batch_create(*B, plans, count, &o);
+                    obk::batch_begin(*B, nullptr, s);
+                    obk::batch_step(*B, -1.0, nullptr, nullptr, s);            // warm-up
+                    auto t0 = std::chrono::steady_clock::now();
+                    for (int r = 0; r < 2; r++) obk::batch_step(*B, -1.0, nullptr, nullptr, s);
+                    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / 2;
+                    if (t < best_t) { best_t = t; best_o = o; }
+                }
             }
         }
         *best = best_o;

@@ -20,6 +20,8 @@
 // bounded: past the bound the kernel records an error and leaves, and the host
 // reports OBK_E_HIP.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <numeric>
@@ -108,35 +110,62 @@ __device__ __forceinline__ void team_barrier(uint32_t* bar, int team, int* err) 
     }
 }
 
-template <class T>
-__global__ __launch_bounds__(kTileThreads) void k_batch_sweeps(const BatchSys<T>* __restrict__ systems,
-                                                               const int32_t* __restrict__ task_ptr,
-                                                               const TeamTask* __restrict__ tasks,
-                                                               const uint8_t* __restrict__ active, int sweeps,
-                                                               int* err) {
-    __shared__ T prod[kTileEntries];
+// Tiles of one phase handled by team member `rank`: r0 + rank + j * team for
+// j = 0, 1, ...; a workgroup takes SUB of them per pass, one per sub-block.
+template <class T, int SUB, bool kR>
+__device__ __forceinline__ void team_phase(const BatchSys<T>& S, int32_t g, int32_t rank, T* prod) {
+    const Tile* tiles = kR ? S.rtiles : S.stiles;
+    const int32_t r0 = kR ? S.rtile_ptr[g] : S.stile_ptr[g];
+    const int32_t r1 = kR ? S.rtile_ptr[g + 1] : S.stile_ptr[g + 1];
+    const int32_t mine = (r1 - r0 > rank) ? (r1 - r0 - rank + S.team - 1) / S.team : 0;
+    const int32_t passes = (mine + SUB - 1) / SUB;
+    const int sb = threadIdx.x / kTileThreads;
+    __shared__ int chunks[SUB];
+    for (int32_t p = 0; p < passes; p++) {
+        // each sub-block loads its own tile (clamped index: pass p always has j = p * SUB < mine)
+        const int32_t j = p * SUB + sb;
+        const bool ok = j < mine;
+        const Tile tb = tiles[r0 + rank + (ok ? j : p * SUB) * S.team];
+        Tile mt;
+        mt.seg_begin = ok ? tb.seg_begin : 0;
+        mt.seg_end = ok ? tb.seg_end : 0;
+        mt.ent_begin = ok ? tb.ent_begin : 0;
+        mt.ent_end = ok ? tb.ent_end : 0;
+        if ((threadIdx.x & (kTileThreads - 1)) == 0) chunks[sb] = tile_chunks(mt);
+        __syncthreads();
+        int nchunks = 0;
+        for (int b = 0; b < SUB; b++) nchunks = max(nchunks, chunks[b]);
+        if (kR)
+            tile_phase_r<T>(mt, nchunks, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
+        else
+            tile_phase_s<T>(mt, nchunks, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
+    }
+}
+
+template <class T, int SUB>
+__global__ __launch_bounds__(kTileThreads * SUB) void k_batch_sweeps(const BatchSys<T>* __restrict__ systems,
+                                                                     const int32_t* __restrict__ task_ptr,
+                                                                     const TeamTask* __restrict__ tasks,
+                                                                     const uint8_t* __restrict__ active, int sweeps,
+                                                                     int* err, uint64_t* __restrict__ trace) {
+    __shared__ T prod_all[SUB * kTileEntries];
+    T* prod = prod_all + (threadIdx.x / kTileThreads) * kTileEntries;
     const int32_t t0 = task_ptr[blockIdx.x], t1 = task_ptr[blockIdx.x + 1];
+    if (trace && threadIdx.x == 0) trace[2 * blockIdx.x] = wall_clock64();
     for (int32_t ti = t0; ti < t1; ti++) {
         const TeamTask tk = tasks[ti];
         if (!active[tk.sys]) continue;
         const BatchSys<T> S = systems[tk.sys];
         for (int sw = 0; sw < sweeps; sw++) {
             for (int32_t g = 0; g < S.ngroups; g++) {
-                const int32_t r0 = S.rtile_ptr[g], r1 = S.rtile_ptr[g + 1];
-                for (int32_t t = r0 + tk.rank; t < r1; t += S.team) {
-                    const Tile tl = S.rtiles[t];
-                    tile_phase_r<T>(tl, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
-                }
+                team_phase<T, SUB, true>(S, g, tk.rank, prod);
                 team_barrier(S.bar, S.team, err);
-                const int32_t s0 = S.stile_ptr[g], s1 = S.stile_ptr[g + 1];
-                for (int32_t t = s0 + tk.rank; t < s1; t += S.team) {
-                    const Tile tl = S.stiles[t];
-                    tile_phase_s<T>(tl, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
-                }
+                team_phase<T, SUB, false>(S, g, tk.rank, prod);
                 team_barrier(S.bar, S.team, err);
             }
         }
     }
+    if (trace && threadIdx.x == 0) trace[2 * blockIdx.x + 1] = wall_clock64();
 }
 
 __global__ __launch_bounds__(256) void k_batch_resid(const ResSys* __restrict__ sys, const Block* __restrict__ blocks,
@@ -277,6 +306,8 @@ struct obk_batch_s {
     int64_t n_rowblocks = 0, n_colblocks = 0;
     std::vector<uint8_t> h_enabled;
     bool busy = false;
+    obk::DevArray<uint64_t> trace;       // per workgroup start/end (OBK_TRACE=1)
+    int sub = 4;                         // tiles in flight per workgroup
 };
 
 namespace obk {
@@ -297,19 +328,25 @@ void build_schedule(obk_batch_s& B) {
     int dev = 0, cus = 256;
     OBK_HIP(hipGetDevice(&dev));
     OBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = B.opts.wgs_per_cu > 0 ? B.opts.wgs_per_cu : 4;
+    int per_cu = B.opts.wgs_per_cu > 0 ? B.opts.wgs_per_cu : 2;
     // every workgroup of the persistent launch must be resident at once
+    const int sub = B.sub;
     int occ = 0;
-    if (B.fp32)
-        OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float>, kTileThreads, 0));
-    else
-        OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double>, kTileThreads, 0));
+    if (B.fp32) {
+        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 1>, kTileThreads, 0));
+        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 2>, 2 * kTileThreads, 0));
+        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 4>, 4 * kTileThreads, 0));
+    } else {
+        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 1>, kTileThreads, 0));
+        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 2>, 2 * kTileThreads, 0));
+        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 4>, 4 * kTileThreads, 0));
+    }
     per_cu = std::max(1, std::min(per_cu, occ));
     const int nxcd = 8;
     int nwg = std::max(nxcd, cus * per_cu);
     nwg -= nwg % nxcd;
     B.nwg = nwg;
-    const int64_t team_work = B.opts.team_work > 0 ? B.opts.team_work : (1 << 17);
+    const int64_t team_work = B.opts.team_work > 0 ? B.opts.team_work : (1 << 18);
     const int max_team = std::max(1, std::min(B.opts.max_team > 0 ? B.opts.max_team : 16, nwg / nxcd));
     std::vector<int64_t> work(count);
     for (int s = 0; s < count; s++) work[s] = 2 * B.plans[s]->nnz + 2 * B.plans[s]->m;
@@ -353,7 +390,11 @@ void build_schedule(obk_batch_s& B) {
     std::vector<int32_t> tptr(nwg + 1, 0);
     std::vector<TeamTask> flat;
     for (int b = 0; b < nwg; b++) {
-        std::sort(per_wg[b].begin(), per_wg[b].end(), [](const TeamTask& a, const TeamTask& c) { return a.sys < c.sys; });
+        // one global order for all workgroups: larger teams first, then system id
+        std::sort(per_wg[b].begin(), per_wg[b].end(), [&](const TeamTask& a, const TeamTask& c) {
+            if (B.team[a.sys] != B.team[c.sys]) return B.team[a.sys] > B.team[c.sys];
+            return a.sys < c.sys;
+        });
         for (auto& t : per_wg[b]) flat.push_back(t);
         tptr[b + 1] = (int32_t)flat.size();
     }
@@ -405,9 +446,67 @@ void build_schedule(obk_batch_s& B) {
 
 }  // namespace
 
+namespace {
+// OBK_TRACE=1: per-workgroup wall-clock spans of the persistent launch and the
+// event time of the launch, summarised on stderr after each step
+bool trace_enabled() {
+    const char* v = std::getenv("OBK_TRACE");
+    return v && v[0] && v[0] != '0';
+}
+
+hipEvent_t g_ev[2] = {nullptr, nullptr};
+
+void ev_record(obk_batch_s& B, int which, hipStream_t s) {
+    if (!B.trace.get()) return;
+    if (!g_ev[which]) OBK_HIP(hipEventCreate(&g_ev[which]));
+    OBK_HIP(hipEventRecord(g_ev[which], s));
+}
+
+void trace_report(obk_batch_s& B) {
+    std::vector<uint64_t> t(2 * (size_t)B.nwg);
+    OBK_HIP(hipMemcpy(t.data(), B.trace.get(), t.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    int rate_khz = 100000;
+    (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, B.device);
+    const double us = 1e3 / (double)rate_khz;
+    uint64_t t0 = UINT64_MAX, t1 = 0;
+    std::vector<double> dur;
+    for (int b = 0; b < B.nwg; b++) {
+        t0 = std::min(t0, t[2 * b]);
+        t1 = std::max(t1, t[2 * b + 1]);
+        dur.push_back((double)(t[2 * b + 1] - t[2 * b]) * us);
+    }
+    std::vector<double> sd = dur;
+    std::sort(sd.begin(), sd.end());
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, g_ev[0], g_ev[1]);
+    std::fprintf(stderr, "[obk-trace] batched launch: %.1f us (event), span %.1f us, per-WG us: min %.1f "
+                         "median %.1f p90 %.1f max %.1f over %d WGs\n",
+                 ms * 1e3, (double)(t1 - t0) * us, sd.front(), sd[sd.size() / 2], sd[sd.size() * 9 / 10],
+                 sd.back(), B.nwg);
+}
+}  // namespace
+
+template <class T>
+void launch_sweeps(obk_batch_s& B, int sweeps, hipStream_t s) {
+    const BatchSys<T>* sys = (const BatchSys<T>*)B.sys_sweep.get();
+    const TeamTask* tasks = (const TeamTask*)B.tasks.get();
+    if (B.sub == 1)
+        k_batch_sweeps<T, 1><<<B.nwg, kTileThreads, 0, s>>>(sys, B.task_ptr.get(), tasks, B.active.get(), sweeps,
+                                                             B.err.get(), B.trace.get());
+    else if (B.sub == 2)
+        k_batch_sweeps<T, 2><<<B.nwg, 2 * kTileThreads, 0, s>>>(sys, B.task_ptr.get(), tasks, B.active.get(),
+                                                                 sweeps, B.err.get(), B.trace.get());
+    else
+        k_batch_sweeps<T, 4><<<B.nwg, 4 * kTileThreads, 0, s>>>(sys, B.task_ptr.get(), tasks, B.active.get(),
+                                                                 sweeps, B.err.get(), B.trace.get());
+    OBK_HIP(hipGetLastError());
+}
+
 void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts) {
     B.plans.assign(plans, plans + count);
     if (opts) B.opts = *opts;
+    B.sub = B.opts.tiles_per_wg > 0 ? B.opts.tiles_per_wg : 4;
+    if (B.sub != 1 && B.sub != 2 && B.sub != 4) fail(OBK_E_ARG, "tiles_per_wg must be 1, 2 or 4");
     OBK_HIP(hipGetDevice(&B.device));
     for (int s = 0; s < count; s++) {
         if (!plans[s]) fail(OBK_E_ARG, "NULL plan in batch");
@@ -419,6 +518,10 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
     }
     B.fp32 = count > 0 && plans[0]->opts.precision == OBK_FP32_IR;
     build_schedule(B);
+    if (trace_enabled()) {
+        B.trace.alloc(2 * (size_t)B.nwg);
+        OBK_HIP(hipMemset(B.trace.get(), 0, 2 * sizeof(uint64_t) * B.nwg));
+    }
 }
 
 // x~ = P x0 for every system (x0 entries may be NULL: 0)
@@ -463,19 +566,17 @@ void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_
             k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
                                                                  (const Block*)B.colblocks.get(), B.sigma.get(),
                                                                  B.active.get(), 0);
-        k_batch_sweeps<float><<<B.nwg, kTileThreads, 0, s>>>((const BatchSys<float>*)B.sys_sweep.get(),
-                                                             B.task_ptr.get(), (const TeamTask*)B.tasks.get(),
-                                                             B.active.get(), std::max(1, B.plans[0]->opts.inner_sweeps),
-                                                             B.err.get());
+        ev_record(B, 0, s);
+        launch_sweeps<float>(B, std::max(1, B.plans[0]->opts.inner_sweeps), s);
+        ev_record(B, 1, s);
         if (B.n_colblocks)
             k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
                                                                  (const Block*)B.colblocks.get(), B.sigma.get(),
                                                                  B.active.get(), 1);
     } else {
-        k_batch_sweeps<double><<<B.nwg, kTileThreads, 0, s>>>((const BatchSys<double>*)B.sys_sweep.get(),
-                                                              B.task_ptr.get(), (const TeamTask*)B.tasks.get(),
-                                                              B.active.get(),
-                                                              std::max(1, B.plans[0]->opts.check_every), B.err.get());
+        ev_record(B, 0, s);
+        launch_sweeps<double>(B, std::max(1, B.plans[0]->opts.check_every), s);
+        ev_record(B, 1, s);
     }
     OBK_HIP(hipGetLastError());
     std::vector<double> rr(count);
@@ -486,6 +587,7 @@ void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_
     OBK_HIP(hipMemcpyAsync(&herr, B.err.get(), sizeof(int), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
     if (herr & 1) fail(OBK_E_HIP, "a team barrier of the batched sweep timed out");
+    if (B.trace.get()) trace_report(B);
     for (int i = 0; i < count; i++) {
         if (relres_out) relres_out[i] = rr[i];
         if (active_out) active_out[i] = act[i];

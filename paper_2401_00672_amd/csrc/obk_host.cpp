@@ -128,7 +128,7 @@ void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Til
     int64_t s = seg0;
     while (s < seg1) {
         int64_t e = s + 1;
-        while (e < seg1 && e - s < kTileThreads && off[e + 1] - off[s] <= kTileEntries) e++;
+        while (e < seg1 && e - s < kTileSegs && off[e + 1] - off[s] <= kTileEntries) e++;
         Tile t;
         t.seg_begin = (int32_t)s;
         t.seg_end = (int32_t)e;

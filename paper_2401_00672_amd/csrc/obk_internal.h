@@ -84,10 +84,11 @@ struct Tile {
     int32_t seg_begin, seg_end;
     int64_t ent_begin, ent_end;
 };
-constexpr int kTileThreads = 256;        // threads per sweep workgroup
+constexpr int kTileThreads = 256;        // threads per tile (one sub-block)
+constexpr int kTileSegs = 256;           // rows (columns) per tile, 1 per thread
 constexpr int kTileEntries = 2048;       // entries staged per chunk (8 per thread)
 // Split segments [0, nseg) with offsets off[nseg+1] into tiles of at most
-// kTileThreads segments and (unless a single segment is longer) at most
+// kTileSegs segments and (unless a single segment is longer) at most
 // kTileEntries entries.
 void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Tile>& out);
 

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kT) void k_phase_r(const Tile* __restrict__ tiles, 
                                                 const T* __restrict__ x, T* __restrict__ w) {
     __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    tile_phase_r<T>(t, prod, rptr, rcol, rval, rf, rinv, x, w);
+    tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
 }
 
 template <class T>
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kT) void k_phase_s(const Tile* __restrict__ tiles, 
                                                 T* __restrict__ x) {
     __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    tile_phase_s<T>(t, prod, sptr, srow, sval, tcol, w, x);
+    tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
 }
 
 // r_a = f_a - a_a . x over the group-major rows; per-block sums of r_a^2

@@ -1,65 +1,174 @@
-// Device bodies of the two sweep phases over one tile, shared by the
-// per-group kernels and the batched team kernel.  T is the arithmetic type
-// (double, or float in the inner sweeps of iterative refinement).
+// Device bodies of the two sweep phases over tiles, shared by the per-group
+// kernels and the batched team kernel.  T is the arithmetic type (double, or
+// float in the inner sweeps of iterative refinement).
 //
 // phase R (one group): for each row a of the tile, from the same x,
 //   w_a = (f_a - sum_k a_ak x_k) * inv_a
 // phase S (one group): for each touched column c of the tile,
 //   x_c = x_c + sum over the group's rows a holding c of w_a a_ac
-// Entries are staged through LDS in chunks of kTileEntries; each row (column)
-// is then reduced by one thread in ascending entry order.  Written in
-// predicated form: every load is issued at an in-range index.
+//
+// A workgroup of 256*SUB threads works on SUB tiles at once, one per
+// 256-thread sub-block, each with its own LDS slice of kTileEntries values.
+// A tile holds up to kTileSegs rows (columns): thread t owns segments
+// t, t + 256, ... (one segment per thread at kTileSegs = 256, which keeps
+// enough tiles per phase to fill the chip).
+// Entries are staged through LDS in chunks; each row (column) is then reduced
+// by one thread in ascending entry order, so the result does not depend on
+// SUB or on the tile schedule.  Every load that depends only on the tile
+// (row bounds, f, 1/||a||^2, the column owned) is issued before the entry
+// loads, which shortens the chain of dependent memory round trips.  Written
+// in predicated form: every load is issued at an in-range index.  An empty
+// tile {0,0,0,0} may be passed for an idle sub-block (segment 0 must exist).
 #pragma once
 
 #include "obk_internal.h"
 
 namespace obk {
 
+__device__ __forceinline__ int tile_chunks(const Tile& t) {
+    return (int)((t.ent_end - t.ent_begin + kTileEntries - 1) / kTileEntries);
+}
+
+// Stage one chunk of products into LDS: prod[q] = val[q] * v[idx[q]] for
+// q < len.  All index and value loads of the thread are issued first, then all
+// gathers, so a chunk costs two dependent memory round trips, not one pair per
+// entry.  Loads are exec-masked (q < len), never issued out of range.
+constexpr int kPerThread = kTileEntries / kTileThreads;
+
 template <class T>
-__device__ __forceinline__ void tile_phase_r(const Tile& t, T* prod, const int64_t* __restrict__ rptr,
-                                             const int32_t* __restrict__ rcol, const T* __restrict__ rval,
-                                             const T* __restrict__ rf, const T* __restrict__ rinv,
-                                             const T* __restrict__ x, T* __restrict__ w) {
-    const int nseg = t.seg_end - t.seg_begin;
-    const int me = threadIdx.x;
-    const bool owner = me < nseg;
-    const int64_t a = t.seg_begin + (owner ? me : 0);
-    const int64_t k0 = rptr[a], k1 = rptr[a + 1];
-    T acc = T(0);
-    for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
-        const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
-        for (int q = me; q < len; q += kTileThreads) prod[q] = rval[base + q] * x[rcol[base + q]];
-        __syncthreads();
-        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
-        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
-        __syncthreads();
+__device__ __forceinline__ void stage_r(T* prod, int me, int len, const int32_t* __restrict__ idx,
+                                        const T* __restrict__ val, const T* __restrict__ v) {
+    int32_t ix[kPerThread];
+    T va[kPerThread], g[kPerThread];
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        ix[e] = 0;
+        va[e] = T(0);
+        if (q < len) {
+            ix[e] = idx[q];
+            va[e] = val[q];
+        }
     }
-    const T fa = rf[a], ia = rinv[a];
-    if (owner) w[a] = (fa - acc) * ia;
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        g[e] = T(0);
+        if (q < len) g[e] = v[ix[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        if (q < len) prod[q] = va[e] * g[e];
+    }
+}
+
+// Same for phase S, where the product is w[row] * val (operand order kept).
+template <class T>
+__device__ __forceinline__ void stage_s(T* prod, int me, int len, const int32_t* __restrict__ idx,
+                                        const T* __restrict__ val, const T* __restrict__ v) {
+    int32_t ix[kPerThread];
+    T va[kPerThread], g[kPerThread];
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        ix[e] = 0;
+        va[e] = T(0);
+        if (q < len) {
+            ix[e] = idx[q];
+            va[e] = val[q];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        g[e] = T(0);
+        if (q < len) g[e] = v[ix[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < kPerThread; e++) {
+        const int q = me + e * kTileThreads;
+        if (q < len) prod[q] = g[e] * va[e];
+    }
 }
 
 template <class T>
-__device__ __forceinline__ void tile_phase_s(const Tile& t, T* prod, const int64_t* __restrict__ sptr,
+__device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod, const int64_t* __restrict__ rptr,
+                                             const int32_t* __restrict__ rcol, const T* __restrict__ rval,
+                                             const T* __restrict__ rf, const T* __restrict__ rinv,
+                                             const T* __restrict__ x, T* __restrict__ w) {
+    constexpr int Q = kTileSegs / kTileThreads;      // rows owned per thread
+    const int nseg = t.seg_end - t.seg_begin;
+    const int me = threadIdx.x & (kTileThreads - 1);
+    bool own[Q];
+    int64_t a[Q], k0[Q], k1[Q];
+    T fa[Q], ia[Q], acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int sg = me + q * kTileThreads;
+        own[q] = sg < nseg;
+        a[q] = t.seg_begin + (own[q] ? sg : 0);
+        k0[q] = rptr[a[q]];
+        k1[q] = rptr[a[q] + 1];
+        fa[q] = rf[a[q]];
+        ia[q] = rinv[a[q]];
+        acc[q] = T(0);
+    }
+    for (int c = 0; c < nchunks; c++) {
+        const int64_t base = t.ent_begin + (int64_t)c * kTileEntries;
+        const int len = (int)max<int64_t>(0, min<int64_t>(kTileEntries, t.ent_end - base));
+        stage_r(prod, me, len, rcol + base, rval + base, x);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int64_t lo = max(k0[q], base), hi = own[q] ? min(k1[q], base + len) : lo;
+            for (int64_t k = lo; k < hi; k++) acc[q] = acc[q] + prod[k - base];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+        if (own[q]) w[a[q]] = (fa[q] - acc[q]) * ia[q];
+}
+
+template <class T>
+__device__ __forceinline__ void tile_phase_s(const Tile& t, int nchunks, T* prod, const int64_t* __restrict__ sptr,
                                              const int32_t* __restrict__ srow, const T* __restrict__ sval,
                                              const int32_t* __restrict__ tcol, const T* __restrict__ w,
                                              T* __restrict__ x) {
+    constexpr int Q = kTileSegs / kTileThreads;      // columns owned per thread
     const int nseg = t.seg_end - t.seg_begin;
-    const int me = threadIdx.x;
-    const bool owner = me < nseg;
-    const int64_t sg = t.seg_begin + (owner ? me : 0);
-    const int64_t k0 = sptr[sg], k1 = sptr[sg + 1];
-    T acc = T(0);
-    for (int64_t base = t.ent_begin; base < t.ent_end; base += kTileEntries) {
-        const int len = (int)min<int64_t>(kTileEntries, t.ent_end - base);
-        for (int q = me; q < len; q += kTileThreads) prod[q] = w[srow[base + q]] * sval[base + q];
+    const int me = threadIdx.x & (kTileThreads - 1);
+    bool own[Q];
+    int64_t k0[Q], k1[Q];
+    int32_t col[Q];
+    T xc[Q], acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+        const int sg = me + q * kTileThreads;
+        own[q] = sg < nseg;
+        const int64_t s = t.seg_begin + (own[q] ? sg : 0);
+        k0[q] = sptr[s];
+        k1[q] = sptr[s + 1];
+        col[q] = tcol[s];
+        xc[q] = x[col[q]];      // each column has one owner in the phase
+        acc[q] = T(0);
+    }
+    for (int c = 0; c < nchunks; c++) {
+        const int64_t base = t.ent_begin + (int64_t)c * kTileEntries;
+        const int len = (int)max<int64_t>(0, min<int64_t>(kTileEntries, t.ent_end - base));
+        stage_s(prod, me, len, srow + base, sval + base, w);
         __syncthreads();
-        const int64_t lo = max(k0, base), hi = owner ? min(k1, base + len) : lo;
-        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+            const int64_t lo = max(k0[q], base), hi = own[q] ? min(k1[q], base + len) : lo;
+            for (int64_t k = lo; k < hi; k++) acc[q] = acc[q] + prod[k - base];
+        }
         __syncthreads();
     }
-    const int32_t c = tcol[sg];
-    const T xc = x[c];
-    if (owner) x[c] = xc + acc;
+#pragma unroll
+    for (int q = 0; q < Q; q++)
+        if (own[q]) x[col[q]] = xc[q] + acc[q];
 }
 
 }  // namespace obk
