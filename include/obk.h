@@ -176,6 +176,35 @@ OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_
                             obk_stream_t stream);
 
 /*
+ * Per-kernel timing of FP64 sweeps (the device-side roofline measurement):
+ * `sweeps` sweeps on x~ (device, reordered coordinates, updated in place as
+ * by obk_sweep_device) are launched eagerly -- not from a graph -- with a HIP
+ * event recorded on `stream` before and after every kernel launch.  For each
+ * distinct sweep kernel, out[k] receives its name, the number of launches,
+ * the summed event time and the summed algorithmic bytes of those launches.
+ * Algorithmic bytes of one launch over group g (n_g rows, e_g entries, t_g
+ * touched columns, element size s = 8, offsets counted at 4 bytes):
+ *   phase R: e_g (s + 4) + n_g (4 + 3 s) + t_g s
+ *            (values and columns; row offset, f~, 1/||a||^2 and w per row;
+ *            each touched x read once)
+ *   phase S: e_g (s + 4) + t_g (8 + 2 s) + n_g s
+ *            (values and row ids; column offset, column id, x read and
+ *            written per touched column; w read once per row)
+ * Synchronises the stream.  *n_out receives the number of kernels reported
+ * (at most max_out).  sweeps must be in [1, 4096].
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double seconds;
+    double bytes;
+} obk_kernel_profile;
+
+OBK_API obk_status obk_sweep_profile(obk_plan_t plan, double *x_tilde_dev, int64_t sweeps,
+                             obk_stream_t stream, obk_kernel_profile *out, int32_t max_out,
+                             int32_t *n_out);
+
+/*
  * Batched solves: several plans advanced together in shared launches (one
  * persistent launch per step runs the sweeps of every system).  All plans of
  * a batch must share one precision and live on the current device; a plan may

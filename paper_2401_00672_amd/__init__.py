@@ -51,6 +51,11 @@ class _BatchOpts(ctypes.Structure):
                 ("tiles_per_wg", ctypes.c_int)]
 
 
+class _KernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("outer_steps", ctypes.c_int64), ("relres0", ctypes.c_double),
                 ("relres", ctypes.c_double), ("seconds", ctypes.c_double), ("status", ctypes.c_int)]
@@ -89,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.obk_plan_stats.argtypes = [_P] + [ctypes.POINTER(ctypes.c_int64)] * 2 + \
             [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_int64)] * 2
         L.obk_sweep_device.argtypes = [_P, _P, ctypes.c_int64, _P]
+        L.obk_sweep_profile.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(_KernelProfile),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_set_opts.argtypes = [_P, ctypes.POINTER(_Opts)]
         L.obk_plan_set_opts.restype = ctypes.c_int
         L.obk_last_error.restype = ctypes.c_char_p
@@ -105,7 +112,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(_BatchOpts), _P]
         L.obk_batch_tune.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_BatchOpts), ctypes.POINTER(ctypes.c_double)]
         for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
-                     "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_rcm_host",
+                     "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_result", "obk_solve_batch", "obk_batch_tune"):
             getattr(L, name).restype = ctypes.c_int
@@ -206,6 +213,18 @@ class Plan:
         import torch
         st = _stream(stream) or torch.cuda.current_stream().cuda_stream
         _check(lib().obk_sweep_device(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st))
+
+    def sweep_profile(self, x_tilde, sweeps: int, stream=None) -> list[dict]:
+        """obk_sweep_profile: eager FP64 sweeps with HIP events around every
+        launch; per kernel the launches, event seconds and algorithmic bytes."""
+        import torch
+        st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+        out = (_KernelProfile * 8)()
+        n = ctypes.c_int32()
+        _check(lib().obk_sweep_profile(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st, out, 8,
+                                       ctypes.byref(n)))
+        return [{"name": out[i].name.decode(), "launches": out[i].launches, "seconds": out[i].seconds,
+                 "bytes": out[i].bytes} for i in range(n.value)]
 
     def set_opts(self, precision: int | None = None, inner_sweeps: int | None = None,
                  check_every: int | None = None) -> None:

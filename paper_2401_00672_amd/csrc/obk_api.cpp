@@ -17,6 +17,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
 void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                 hipStream_t s);
 void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
+                       int32_t max_out);
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                    hipStream_t s);
 void ensure_fp32(obk_plan_s& P, hipStream_t s);
@@ -154,6 +156,18 @@ obk_status obk_sweep_device(obk_plan_t plan, double* x_tilde_dev, int64_t sweeps
         if (sweeps < 0) obk::fail(OBK_E_ARG, "sweeps must be >= 0");
         OBK_HIP(hipSetDevice(plan->device));
         obk::enqueue_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream));
+    });
+}
+
+obk_status obk_sweep_profile(obk_plan_t plan, double* x_tilde_dev, int64_t sweeps, obk_stream_t stream,
+                             obk_kernel_profile* out, int32_t max_out, int32_t* n_out) {
+    return guarded([&] {
+        if (!plan || !x_tilde_dev || !out || !n_out) obk::fail(OBK_E_ARG, "NULL argument");
+        if (sweeps < 1 || sweeps > 4096) obk::fail(OBK_E_ARG, "sweeps must be in [1, 4096]");
+        if (max_out < 1) obk::fail(OBK_E_ARG, "max_out must be >= 1");
+        OBK_HIP(hipSetDevice(plan->device));
+        BusyGuard busy(plan);
+        *n_out = obk::profile_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out);
     });
 }
 

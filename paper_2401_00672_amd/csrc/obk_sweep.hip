@@ -9,8 +9,11 @@
 //            exactly one thread (the group's CSC), so no atomics are needed.
 // Both phases stream their entries through LDS in tiles and reduce each row
 // (column) sequentially in ascending entry order.
+#include <hip/hip_ext.h>
+
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "obk_internal.h"
@@ -18,33 +21,13 @@
 
 namespace obk {
 
+constexpr int kT = kTileThreads;
+
 double sum_squares(const double* f, const double* nu, int64_t n, bool only_zero_rows, hipStream_t s);
 
 namespace {
 
-constexpr int kT = kTileThreads;
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
-
-// Phase R / phase S over the tiles of one group (bodies in obk_sweep_tiles.h).
-template <class T>
-__global__ __launch_bounds__(kT) void k_phase_r(const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr,
-                                                const int32_t* __restrict__ rcol, const T* __restrict__ rval,
-                                                const T* __restrict__ rf, const T* __restrict__ rinv,
-                                                const T* __restrict__ x, T* __restrict__ w) {
-    __shared__ T prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
-    tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
-}
-
-template <class T>
-__global__ __launch_bounds__(kT) void k_phase_s(const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr,
-                                                const int32_t* __restrict__ srow, const T* __restrict__ sval,
-                                                const int32_t* __restrict__ tcol, const T* __restrict__ w,
-                                                T* __restrict__ x) {
-    __shared__ T prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
-    tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
-}
 
 // r_a = f_a - a_a . x over the group-major rows; per-block sums of r_a^2
 __global__ __launch_bounds__(256) void k_resid(int64_t m, const int64_t* __restrict__ rptr,
@@ -229,6 +212,81 @@ static void run_sweeps(obk_plan_s& P, const T* rval, const T* rf, const T* rinv,
 // enqueue `sweeps` sweeps on x (device, reordered coordinates)
 void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
     run_sweeps<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), x, P.w.get(), sweeps, s);
+}
+
+// Eager FP64 sweeps with an event pair around every launch; per-kernel sums
+// of event time and algorithmic bytes (formulas in obk.h).
+int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
+                       int32_t max_out) {
+    const int32_t G = P.ngroups;
+    struct Launch { int kind; double bytes; };
+    std::vector<Launch> plan_launches;
+    const double sv = 8, so = 4;
+    for (int32_t g = 0; g < G; g++) {
+        const int32_t r0 = P.h_rtile_ptr[g], r1 = P.h_rtile_ptr[g + 1];
+        const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
+        double ng = 0, eg = 0, tg = 0;
+        for (int32_t t = r0; t < r1; t++) {
+            ng += P.h_rtiles[t].seg_end - P.h_rtiles[t].seg_begin;
+            eg += (double)(P.h_rtiles[t].ent_end - P.h_rtiles[t].ent_begin);
+        }
+        for (int32_t t = s0; t < s1; t++) tg += P.h_stiles[t].seg_end - P.h_stiles[t].seg_begin;
+        if (r1 > r0) plan_launches.push_back({0, eg * (sv + so) + ng * (so + 3 * sv) + tg * sv});
+        if (s1 > s0) plan_launches.push_back({1, eg * (sv + so) + tg * (2 * so + 2 * sv) + ng * sv});
+    }
+    const size_t nl = plan_launches.size() * (size_t)sweeps;
+    std::vector<hipEvent_t> ev(2 * nl, nullptr);
+    struct EvGuard {
+        std::vector<hipEvent_t>& e;
+        ~EvGuard() { for (auto x : e) if (x) (void)hipEventDestroy(x); }
+    } guard{ev};
+    for (auto& e : ev) OBK_HIP(hipEventCreate(&e));
+    size_t k = 0;
+    for (int64_t it = 0; it < sweeps; it++) {
+        size_t li = 0;
+        for (int32_t g = 0; g < G; g++) {
+            const int32_t r0 = P.h_rtile_ptr[g], r1 = P.h_rtile_ptr[g + 1];
+            const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
+            // the events ride on the kernel's own dispatch packet: they time the
+            // kernel, not the packets around it
+            if (r1 > r0) {
+                hipExtLaunchKernelGGL(k_phase_r<double>, dim3(r1 - r0), dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
+                                      (const Tile*)(P.rtiles.get() + r0), (const int64_t*)P.rptr.get(),
+                                      (const int32_t*)P.rcol.get(), (const double*)P.rval.get(),
+                                      (const double*)P.rf.get(), (const double*)P.rinv.get(), (const double*)x,
+                                      P.w.get());
+                k++, li++;
+            }
+            if (s1 > s0) {
+                hipExtLaunchKernelGGL(k_phase_s<double>, dim3(s1 - s0), dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
+                                      (const Tile*)(P.stiles.get() + s0), (const int64_t*)P.sptr.get(),
+                                      (const int32_t*)P.srow.get(), (const double*)P.sval.get(),
+                                      (const int32_t*)P.tcol.get(), (const double*)P.w.get(), x);
+                k++, li++;
+            }
+        }
+        (void)li;
+    }
+    OBK_HIP(hipGetLastError());
+    OBK_HIP(hipStreamSynchronize(s));
+    const char* names[2] = {"k_phase_r<double>", "k_phase_s<double>"};
+    obk_kernel_profile acc[2];
+    for (int j = 0; j < 2; j++) {
+        std::memset(&acc[j], 0, sizeof(acc[j]));
+        std::strncpy(acc[j].name, names[j], sizeof(acc[j].name) - 1);
+    }
+    for (size_t i = 0; i < nl; i++) {
+        const Launch& L = plan_launches[i % plan_launches.size()];
+        float ms = 0;
+        OBK_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+        acc[L.kind].launches++;
+        acc[L.kind].seconds += ms * 1e-3;
+        acc[L.kind].bytes += L.bytes;
+    }
+    int32_t n = 0;
+    for (int j = 0; j < 2 && n < max_out; j++)
+        if (acc[j].launches) out[n++] = acc[j];
+    return n;
 }
 
 }  // namespace obk

@@ -1,5 +1,5 @@
 // Device bodies of the two sweep phases over tiles, shared by the per-group
-// kernels and the batched team kernel.  T is the arithmetic type (double, or
+// kernels (defined at the end of this file) and the batched team kernel.  T is the arithmetic type (double, or
 // float in the inner sweeps of iterative refinement).
 //
 // phase R (one group): for each row a of the tile, from the same x,
@@ -170,5 +170,30 @@ __device__ __forceinline__ void tile_phase_s(const Tile& t, int nchunks, T* prod
     for (int q = 0; q < Q; q++)
         if (own[q]) x[col[q]] = xc[q] + acc[q];
 }
+
+namespace {
+
+// Phase R / phase S kernels over the tiles of one group: one tile per
+// 256-thread workgroup.
+template <class T>
+__global__ __launch_bounds__(kTileThreads) void k_phase_r(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+    const T* __restrict__ rval, const T* __restrict__ rf, const T* __restrict__ rinv, const T* __restrict__ x,
+    T* __restrict__ w) {
+    __shared__ T prod[kTileEntries];
+    const Tile t = tiles[blockIdx.x];
+    tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
+}
+
+template <class T>
+__global__ __launch_bounds__(kTileThreads) void k_phase_s(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr, const int32_t* __restrict__ srow,
+    const T* __restrict__ sval, const int32_t* __restrict__ tcol, const T* __restrict__ w, T* __restrict__ x) {
+    __shared__ T prod[kTileEntries];
+    const Tile t = tiles[blockIdx.x];
+    tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
+}
+
+}  // namespace
 
 }  // namespace obk

@@ -134,6 +134,40 @@ def test_device_inputs_and_resume():
         assert np.array_equal(x30, xh)
 
 
+def test_sweep_device_and_profile_match_oracle():
+    """obk_sweep_device (graph replays) and obk_sweep_profile (eager launches
+    with events) both advance x~ in reordered coordinates exactly as the
+    oracle's sweeps; the profile's byte sums follow the per-launch formulas."""
+    import torch
+    s = synth.c2(grid=200)
+    _say("[parity] sweep_device / sweep_profile")
+    pl_o = oracle.plan_system(s, 0.1)
+    rng = np.random.default_rng(11)
+    x0 = rng.standard_normal(s.n)
+    with obk.plan_system(s, 0.1) as P:
+        xa = torch.from_numpy(x0.copy()).cuda()
+        P.sweep_device(xa, 13)
+        xb = torch.from_numpy(x0.copy()).cuda()
+        prof = P.sweep_profile(xb, 13)
+        torch.cuda.synchronize()
+        xa, xb = xa.cpu().numpy(), xb.cpu().numpy()
+    xo = oracle.sweep(pl_o, x0, 13)
+    assert np.array_equal(xa, xb)
+    assert np.linalg.norm(xa - xo) / np.linalg.norm(xo) <= TOL_X
+    names = {k["name"]: k for k in prof}
+    assert set(names) == {"k_phase_r<double>", "k_phase_s<double>"}
+    G = pl_o.ngroups
+    assert all(k["launches"] == 13 * G and k["seconds"] > 0 for k in prof)
+    # phase R bytes: e (8 + 4) + n (4 + 24) + t 8 per sweep, t = touched columns summed over groups
+    A = sp.csr_matrix((pl_o.v, pl_o.ci, pl_o.rp), shape=(s.n, s.n))
+    touched = sum(len(np.unique(A[pl_o.group == g].indices)) for g in range(G))
+    rows = int((pl_o.group >= 0).sum())
+    want_r = 13 * (A.nnz * 12 + rows * 28 + touched * 8)
+    want_s = 13 * (A.nnz * 12 + touched * 24 + rows * 8)
+    assert names["k_phase_r<double>"]["bytes"] == pytest.approx(want_r, rel=1e-12)
+    assert names["k_phase_s<double>"]["bytes"] == pytest.approx(want_s, rel=1e-12)
+
+
 def test_run_twice_bitwise():
     s = synth.c2(grid=128)
     _say("[parity] determinism")
