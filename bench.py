@@ -222,6 +222,91 @@ def bench_batched(args) -> dict:
     return res
 
 
+def bench_serving(args) -> dict:
+    """Continuous batching of single-system requests: n log-uniform in
+    [500, 5e5], 4..16 nnz/row (companion family, to relative residual 1e-10),
+    Poisson arrivals.  A first run with every request arriving at t = 0 gives
+    the capacity; the reported run uses arrivals at 0.7 x that capacity.  The
+    baseline serves the same requests one at a time, first in first out, with
+    a plain FP64 plan + solve each (service times measured; queueing computed
+    on the same arrival times)."""
+    import torch
+    import synth
+    import paper_2401_00672_amd as obk
+    from paper_2401_00672_amd.serve import LibobkBackend, Request, Server, latency_summary
+
+    count = args.requests
+    sizes = synth.c5_sizes(count)
+    t0 = time.perf_counter()
+    systems = [synth.c5_system(i, n=int(n)) for i, n in enumerate(sizes)]
+    _log(f"[c5] generated {count} requests in {time.perf_counter() - t0:.1f} s "
+         f"(mean n {sizes.mean():.0f}, total nnz {sum(s.nnz for s in systems)})")
+    budget = int(args.budget_gib * (1 << 30))
+    be = LibobkBackend(delta=args.delta, inner_sweeps=args.inner, planners=args.planners)
+    warm = Server(be, budget, tol=1e-10, planners=args.planners)
+    warm.run([Request(0, 0.0, systems[0])])
+    torch.cuda.synchronize()
+
+    def serve(arrivals):
+        reqs = [Request(i, float(arrivals[i]), systems[i]) for i in range(count)]
+        srv = Server(be, budget, tol=1e-10, max_steps=args.max_steps, planners=args.planners)
+        ts = time.perf_counter()
+        res = srv.run(reqs)
+        span = time.perf_counter() - ts
+        return res, srv.stats, span
+
+    sat, sat_stats, sat_span = serve(np.zeros(count))
+    capacity = count / sat_span
+    _log(f"[c5] saturation: {capacity:.1f} solves/s, {sat_stats}")
+    rate = 0.7 * capacity
+    arrivals = synth.c5_arrivals(count, rate)
+    res, stats, span = serve(arrivals)
+    makespan = max(r.finished for r in res)
+    lat = latency_summary(res)
+    conv = sum(r.status == "converged" for r in res)
+    worst = 0.0
+    for i in range(0, count, max(1, count // 16)):
+        s = systems[i]
+        worst = max(worst, float(np.linalg.norm(s.f - s.scipy() @ res[i].x) / np.linalg.norm(s.f)))
+    _log(f"[c5] poisson {rate:.1f}/s: {count / makespan:.1f} solves/s, latency {lat}, {stats}")
+    # baseline: FIFO, one request at a time, plain FP64 plan + solve
+    service = []
+    base_conv = 0
+    for i, s in enumerate(systems):
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        with obk.plan_system(s, args.delta, check_every=args.check_every) as P:
+            _, inf = P.solve(maxit=20000, tol=1e-10)
+        service.append(time.perf_counter() - tb)
+        base_conv += inf.status == "converged"
+    free_at, base_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        start = max(a, free_at)
+        free_at = start + sv
+        base_lat.append(free_at - a)
+    base_lat = np.array(base_lat)
+    return {
+        "metric": "solves/s and p50/p99 latency to rel. residual 1e-10 (continuous batching)",
+        "value": count / makespan,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": stats["steps"], "warmup": 1, "ms_per_step": stats["step_seconds"] * 1e3 / max(1, stats["steps"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 sweeps + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"serving-{count}-requests-n-loguniform-500-5e5-4to16nnz-companion-poisson",
+                   "requests": count, "arrival_rate_per_s": rate, "budget_bytes": budget,
+                   "planners": args.planners, "inner_sweeps": args.inner},
+        "latency_s": lat,
+        "converged": conv,
+        "worst_sampled_relres": worst,
+        "saturation": {"solves_per_s": capacity, "latency_s": latency_summary(sat), "stats": sat_stats},
+        "server_stats": stats,
+        "baseline_fifo_plain_fp64": {"solves_per_s": count / float(free_at), "converged": base_conv,
+                                     "p50_s": float(np.percentile(base_lat, 50)),
+                                     "p99_s": float(np.percentile(base_lat, 99)),
+                                     "mean_service_s": float(np.mean(service))},
+    }
+
+
 def bench_c3(args) -> dict:
     """2,000,000 rows, 12 nnz/row.  Literal family: FP32 inner-sweep throughput
     (sweeps/s, GB/s) and the residual reached after a sweep cap.  Companion
@@ -299,13 +384,18 @@ def main() -> int:
                     help="eager sweeps timed per launch for the dominant-kernel roofline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4"],
-                    help="c2: 1024^2 stencil sweeps (default line); c3: 2M-row FP32+IR; c4: 512 batched systems")
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: 1024^2 stencil sweeps (default line); c3: 2M-row FP32+IR; c4: 512 batched systems; "
+                         "c5: continuous-batching server")
     ap.add_argument("--systems", type=int, default=512)
     ap.add_argument("--inner", type=int, default=8)
     ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--n3", type=int, default=2_000_000)
     ap.add_argument("--ir-steps", type=int, default=20)
+    ap.add_argument("--requests", type=int, default=512, help="c5: requests in the sample")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: device-memory admission budget")
+    ap.add_argument("--planners", type=int, default=4, help="c5: planner threads")
+    ap.add_argument("--max-steps", type=int, default=200, help="c5: refinement steps before a request gives up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -320,6 +410,8 @@ def main() -> int:
         res = bench_batched(args)
     elif args.config == "c3":
         res = bench_c3(args)
+    elif args.config == "c5":
+        res = bench_serving(args)
     else:
         res = bench_stencil(args)
     print(json.dumps(res), flush=True)

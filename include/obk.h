@@ -242,6 +242,12 @@ OBK_API obk_status obk_batch_begin(obk_batch_t batch, const double *const *x0, o
  * whether the step advanced it. */
 OBK_API obk_status obk_batch_step(obk_batch_t batch, double tol, double *relres, int32_t *active,
                                   obk_stream_t stream);
+/* x~_index = P x0 for system `index` alone (x0 NULL: zeros) and enable it;
+ * the other systems keep their iterates and flags.  Iterates live in each
+ * plan's workspace, so a system moved into a new batch object (continuous
+ * batching: members admitted and retired between steps) continues from where
+ * it stopped, and only newly admitted members need obk_batch_start. */
+OBK_API obk_status obk_batch_start(obk_batch_t batch, int index, const double *x0, obk_stream_t stream);
 /* enabled[i] = 0 removes system i from later steps until obk_batch_begin. */
 OBK_API obk_status obk_batch_enable(obk_batch_t batch, const int32_t *enabled, obk_stream_t stream);
 /* x = P^T x~ of system `index`, in the plan's input memory space. */

@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
         L.obk_batch_begin.argtypes = [_P, _P, _P]
         L.obk_batch_step.argtypes = [_P, ctypes.c_double, _P, _P, _P]
         L.obk_batch_enable.argtypes = [_P, _P, _P]
+        L.obk_batch_start.argtypes = [_P, ctypes.c_int, _P, _P]
         L.obk_batch_result.argtypes = [_P, ctypes.c_int, _P, _P]
         L.obk_batch_free.argtypes = [_P]
         L.obk_batch_free.restype = None
@@ -114,7 +115,7 @@ def lib() -> ctypes.CDLL:
         for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
-                     "obk_batch_enable", "obk_batch_result", "obk_solve_batch", "obk_batch_tune"):
+                     "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -412,6 +413,18 @@ class Batch:
         on_dev = bool(self.plans) and self.plans[0].on_device
         arr, keep = _ptr_array(x0, on_dev)
         _check(lib().obk_batch_begin(self._h, arr, _stream(stream)))
+
+    def start(self, i: int, x0=None, stream=None):
+        """obk_batch_start: initialise system i alone (x0 None: zeros)."""
+        ptr = None
+        keep = None
+        if x0 is not None:
+            if self.plans[i].on_device:
+                ptr = _dev_ptr(x0, "float64")
+            else:
+                keep = np.ascontiguousarray(x0, dtype=np.float64)
+                ptr = keep.ctypes.data
+        _check(lib().obk_batch_start(self._h, int(i), ptr, _stream(stream)))
 
     def step(self, tol: float, stream=None):
         n = len(self.plans)

@@ -27,6 +27,7 @@ void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s);
 void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s);
 void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s);
 void batch_set_enabled(obk_batch_s& B, const int32_t* enabled, hipStream_t s);
+void batch_start(obk_batch_s& B, int index, const double* x0, hipStream_t s);
 }  // namespace obk
 
 // the batch object is defined with its kernels; only pointers cross here
@@ -248,6 +249,13 @@ obk_status obk_batch_begin(obk_batch_t batch, const double* const* x0, obk_strea
     return guarded([&] {
         if (!batch) obk::fail(OBK_E_ARG, "NULL batch");
         obk::batch_begin(*batch, x0, as_hip(stream));
+    });
+}
+
+obk_status obk_batch_start(obk_batch_t batch, int index, const double* x0, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch || index < 0 || index >= obk_batch_count(batch)) obk::fail(OBK_E_ARG, "bad argument");
+        obk::batch_start(*batch, index, x0, as_hip(stream));
     });
 }
 

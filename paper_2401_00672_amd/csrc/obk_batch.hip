@@ -524,21 +524,23 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
     }
 }
 
+// x~ = P x0 for one system (x0 NULL: 0)
+static void start_one(obk_plan_s& P, const double* x0, hipStream_t s) {
+    const double* src = x0;
+    DevArray<double> tmp;
+    if (src && !P.input_on_device) {
+        tmp.alloc(P.n);
+        OBK_HIP(hipMemcpyAsync(tmp.get(), src, P.n * sizeof(double), hipMemcpyHostToDevice, s));
+        src = tmp.get();
+    }
+    k_batch_permute_in<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), src, P.x.get());
+    OBK_HIP(hipGetLastError());
+    if (tmp.get()) OBK_HIP(hipStreamSynchronize(s));
+}
+
 // x~ = P x0 for every system (x0 entries may be NULL: 0)
 void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s) {
-    for (size_t i = 0; i < B.plans.size(); i++) {
-        obk_plan_s& P = *B.plans[i];
-        const double* src = x0 ? x0[i] : nullptr;
-        DevArray<double> tmp;
-        if (src && !P.input_on_device) {
-            tmp.alloc(P.n);
-            OBK_HIP(hipMemcpyAsync(tmp.get(), src, P.n * sizeof(double), hipMemcpyHostToDevice, s));
-            src = tmp.get();
-        }
-        k_batch_permute_in<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), src, P.x.get());
-        OBK_HIP(hipGetLastError());
-        if (tmp.get()) OBK_HIP(hipStreamSynchronize(s));
-    }
+    for (size_t i = 0; i < B.plans.size(); i++) start_one(*B.plans[i], x0 ? x0[i] : nullptr, s);
     B.h_enabled.assign(B.plans.size(), 1);
     if (!B.plans.empty())
         OBK_HIP(hipMemcpyAsync(B.enabled.get(), B.h_enabled.data(), B.plans.size(), hipMemcpyHostToDevice, s));
@@ -602,6 +604,14 @@ void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s) {
     k_batch_permute_out<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), P.x.get(), dst);
     OBK_HIP(hipGetLastError());
     if (!P.input_on_device) OBK_HIP(hipMemcpyAsync(x, tmp.get(), P.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+// Start one system (continuous batching); the others are untouched.
+void batch_start(obk_batch_s& B, int index, const double* x0, hipStream_t s) {
+    start_one(*B.plans[index], x0, s);
+    B.h_enabled[index] = 1;
+    OBK_HIP(hipMemcpyAsync(B.enabled.get() + index, &B.h_enabled[index], 1, hipMemcpyHostToDevice, s));
     OBK_HIP(hipStreamSynchronize(s));
 }
 
