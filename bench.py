@@ -321,6 +321,7 @@ def bench_c3(args) -> dict:
     P = obk.plan_system(s, args.delta, precision=obk.FP32_IR, inner_sweeps=args.inner)
     plan_s = time.perf_counter() - t0
     st = P.stats()
+    P.solve(maxit=1, tol=0.0)               # warm-up: captures the sweep graphs
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     x, info = P.solve(maxit=args.ir_steps, tol=0.0)
@@ -331,12 +332,15 @@ def bench_c3(args) -> dict:
     P.free()
     sc = synth.c3(n=n, companion=True)
     Pc = obk.plan_system(sc, args.delta, precision=obk.FP32_IR, inner_sweeps=args.inner)
+    Pc.solve(maxit=1, tol=0.0)              # warm-up: captures the sweep graphs
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     xc, ic = Pc.solve(maxit=100, tol=1e-10)
     torch.cuda.synchronize()
     t_comp = time.perf_counter() - t2
     Pc.set_opts(precision=obk.FP64, check_every=args.check_every)
+    Pc.solve(maxit=args.check_every, tol=0.0)
+    torch.cuda.synchronize()
     t3 = time.perf_counter()
     x64, i64 = Pc.solve(maxit=5000, tol=1e-10)
     t_64 = time.perf_counter() - t3

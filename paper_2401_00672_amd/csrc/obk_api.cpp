@@ -115,6 +115,10 @@ obk_status obk_plan(const obk_csr* A, const double* f, double delta, const obk_o
         obk::build_plan(*P, *A, f, delta, as_hip(stream));
     });
     if (st != OBK_OK) {
+        if (P) {
+            (void)hipStreamSynchronize(as_hip(stream));   // no kernel may still use the plan's buffers
+            (void)hipGetLastError();
+        }
         delete P;
         return st;
     }

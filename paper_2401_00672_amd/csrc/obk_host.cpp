@@ -29,23 +29,73 @@ void check_hip(hipError_t e, const char* what) {
     }
 }
 
+namespace {
+thread_local hipStream_t g_alloc_stream = nullptr;
+thread_local bool g_alloc_scoped = false;
+}  // namespace
+
+AllocScope::AllocScope(hipStream_t s) : prev_stream(g_alloc_stream), prev_on(g_alloc_scoped) {
+    g_alloc_stream = s;
+    g_alloc_scoped = true;
+}
+
+AllocScope::~AllocScope() {
+    g_alloc_stream = prev_stream;
+    g_alloc_scoped = prev_on;
+}
+
+bool alloc_scoped() { return g_alloc_scoped; }
+
+void sync_for_free(hipStream_t s) {
+    if (!g_alloc_scoped) OBK_HIP(hipStreamSynchronize(s));
+}
+
+namespace {
+struct PinnedStage {
+    void* p = nullptr;
+    size_t cap = 0;
+    ~PinnedStage() { if (p) (void)hipHostFree(p); }
+};
+thread_local PinnedStage g_stage;
+}  // namespace
+
+void* pinned_stage(size_t bytes) {
+    if (bytes > g_stage.cap) {
+        if (g_stage.p) (void)hipHostFree(g_stage.p);
+        g_stage.p = nullptr;
+        g_stage.cap = 0;
+        const size_t want = std::max<size_t>(bytes, (size_t)1 << 20);
+        OBK_HIP(hipHostMalloc(&g_stage.p, want, hipHostMallocDefault));
+        g_stage.cap = want;
+    }
+    return g_stage.p;
+}
+
 void DevMem::alloc(size_t b) {
     release();
     if (b == 0) b = 16;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, b);
+    const bool use_pool = g_alloc_scoped;
+    hipError_t e = use_pool ? hipMallocAsync(&p, b, g_alloc_stream) : hipMalloc(&p, b);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        fail(OBK_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+        fail(OBK_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
     }
     ptr = p;
     bytes = b;
+    pooled = use_pool;
 }
 
 void DevMem::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        if (pooled)
+            (void)hipFreeAsync(ptr, g_alloc_scoped ? g_alloc_stream : nullptr);
+        else
+            (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
+    pooled = false;
 }
 
 // --------------------------------------------------------------------- RCM
@@ -53,26 +103,27 @@ void DevMem::release() {
 // fixes one (stated in obk.h and below) so that the order is unique.
 void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm) {
     if (n <= 0) return;
+    // Degrees once; neighbours are then ordered by the 64-bit key
+    // (degree << 32 | index), which is the (degree, index) order.
+    std::vector<uint32_t> deg(n);
+    uint32_t maxdeg = 0;
+    for (int64_t v = 0; v < n; v++) {
+        deg[v] = (uint32_t)(gptr[v + 1] - gptr[v]);
+        maxdeg = std::max(maxdeg, deg[v]);
+    }
     // Vertices ordered by (degree, index): counting sort on the degree keeps
     // ascending index within a degree.
-    int64_t maxdeg = 0;
-    for (int64_t v = 0; v < n; v++) maxdeg = std::max(maxdeg, gptr[v + 1] - gptr[v]);
-    std::vector<int64_t> bucket(maxdeg + 2, 0);
-    for (int64_t v = 0; v < n; v++) bucket[gptr[v + 1] - gptr[v] + 1]++;
-    for (int64_t d = 0; d <= maxdeg; d++) bucket[d + 1] += bucket[d];
+    std::vector<int64_t> bucket((size_t)maxdeg + 2, 0);
+    for (int64_t v = 0; v < n; v++) bucket[deg[v] + 1]++;
+    for (uint32_t d = 0; d <= maxdeg; d++) bucket[d + 1] += bucket[d];
     std::vector<int32_t> by_degree(n);
-    for (int64_t v = 0; v < n; v++) by_degree[bucket[gptr[v + 1] - gptr[v]]++] = (int32_t)v;
+    for (int64_t v = 0; v < n; v++) by_degree[bucket[deg[v]]++] = (int32_t)v;
 
     std::vector<uint8_t> seen(n, 0);
     std::vector<int32_t> cm(n);          // Cuthill-McKee sequence, doubles as the FIFO
-    std::vector<int32_t> fresh;
+    std::vector<uint64_t> fresh;
     fresh.reserve(256);
     int64_t head = 0, tail = 0, next_start = 0;
-    auto deg = [&](int32_t v) { return gptr[v + 1] - gptr[v]; };
-    auto before = [&](int32_t a, int32_t b) {
-        int64_t da = deg(a), db = deg(b);
-        return da != db ? da < db : a < b;
-    };
     while (tail < n) {
         if (head == tail) {               // new component
             while (seen[by_degree[next_start]]) next_start++;
@@ -84,16 +135,22 @@ void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm
         fresh.clear();
         for (int64_t k = gptr[v]; k < gptr[v + 1]; k++) {
             int32_t u = gadj[k];
-            if (!seen[u]) { seen[u] = 1; fresh.push_back(u); }
+            if (!seen[u]) {
+                seen[u] = 1;
+                fresh.push_back(((uint64_t)deg[u] << 32) | (uint32_t)u);
+            }
         }
-        // neighbour lists are short: insertion sort by (degree, index)
-        for (size_t a = 1; a < fresh.size(); a++) {
-            int32_t key = fresh[a];
-            size_t b = a;
-            while (b > 0 && before(key, fresh[b - 1])) { fresh[b] = fresh[b - 1]; b--; }
-            fresh[b] = key;
+        if (fresh.size() <= 32) {          // short lists: insertion sort
+            for (size_t a = 1; a < fresh.size(); a++) {
+                uint64_t key = fresh[a];
+                size_t b = a;
+                while (b > 0 && key < fresh[b - 1]) { fresh[b] = fresh[b - 1]; b--; }
+                fresh[b] = key;
+            }
+        } else {
+            std::sort(fresh.begin(), fresh.end());
         }
-        for (int32_t u : fresh) cm[tail++] = u;
+        for (uint64_t key : fresh) cm[tail++] = (int32_t)(key & 0xffffffffu);
     }
     for (int64_t t = 0; t < n; t++) perm[t] = cm[n - 1 - t];
 }

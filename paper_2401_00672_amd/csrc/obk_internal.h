@@ -26,15 +26,44 @@ void set_last_error(const std::string& msg);
 // ------------------------------------------------------- device memory
 // Owning device buffer; all plan memory goes through it so that the plan
 // can report its footprint.
+//
+// While an AllocScope is active on the calling thread, buffers are taken from
+// the device's stream-ordered pool (hipMallocAsync on the scope's stream) and
+// returned with hipFreeAsync: on the scope's stream while it is active, else on
+// the null stream, after the owner has synchronised the device (obk_free
+// does).  Plan building on one thread then never waits for work that other
+// threads run on the device, as a synchronous hipFree may.
+struct AllocScope {
+    hipStream_t prev_stream;
+    bool prev_on;
+    explicit AllocScope(hipStream_t s);
+    ~AllocScope();
+};
+// True while an AllocScope is active on this thread: temporaries are then
+// freed in stream order and need no synchronisation before they go.
+bool alloc_scoped();
+// Synchronise s unless temporaries are freed in stream order.
+void sync_for_free(hipStream_t s);
+// Pinned host staging buffer of the calling thread (grown on demand, kept
+// until the thread ends); every user completes its copy before returning.
+void* pinned_stage(size_t bytes);
+
 struct DevMem {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool pooled = false;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
-    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes), pooled(o.pooled) {
+        o.ptr = nullptr; o.bytes = 0; o.pooled = false;
+    }
     DevMem& operator=(DevMem&& o) noexcept {
-        if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            ptr = o.ptr; bytes = o.bytes; pooled = o.pooled;
+            o.ptr = nullptr; o.bytes = 0; o.pooled = false;
+        }
         return *this;
     }
     ~DevMem() { release(); }

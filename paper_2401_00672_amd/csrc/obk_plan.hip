@@ -5,7 +5,10 @@
 // which must come out identical to any other IEEE-754 evaluation of the same
 // sums in the same (ascending column) order.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -18,6 +21,14 @@ constexpr int kT = 256;
 inline unsigned nblk(int64_t n, int t = kT) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
 enum : int { BAD_ROWPTR = 1, BAD_COL = 2, BAD_VAL = 4, BAD_F = 8, DUPLICATE = 16 };
+
+// ------------------------------------------------------------- small helpers
+__global__ void k_iota_u32(int64_t n, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (uint32_t)i;
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
 // ---------------------------------------------------------------- ingest
 __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -338,19 +349,38 @@ __global__ void k_to_f32(int64_t m, const double* __restrict__ src, float* __res
     if (k < m) dst[k] = (float)src[k];
 }
 
+// Host <-> device copies of the plan go through the calling thread's pinned
+// staging buffer, so that concurrent plan builds on several threads do not
+// share the runtime's pageable-copy path.
+template <class T> void h2d(T* d, const T* h, size_t n, hipStream_t s) {
+    if (!n) return;
+    void* st = pinned_stage(n * sizeof(T));
+    std::memcpy(st, h, n * sizeof(T));
+    OBK_HIP(hipMemcpyAsync(d, st, n * sizeof(T), hipMemcpyHostToDevice, s));
+    OBK_HIP(hipStreamSynchronize(s));     // the stage is reused by the next copy
+}
 template <class T> void to_device(DevArray<T>& d, const T* h, size_t n, hipStream_t s) {
     d.alloc(n);
-    if (n) OBK_HIP(hipMemcpyAsync(d.get(), h, n * sizeof(T), hipMemcpyHostToDevice, s));
+    h2d(d.get(), h, n, s);
 }
 template <class T> void copy_in(DevArray<T>& d, const T* src, size_t n, bool on_dev, hipStream_t s) {
     d.alloc(n);
-    if (n) OBK_HIP(hipMemcpyAsync(d.get(), src, n * sizeof(T), on_dev ? hipMemcpyDeviceToDevice
-                                                                      : hipMemcpyHostToDevice, s));
+    if (!n) return;
+    if (on_dev)
+        OBK_HIP(hipMemcpyAsync(d.get(), src, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    else
+        h2d(d.get(), src, n, s);
 }
 template <class T> std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
     std::vector<T> h(n);
-    if (n) OBK_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-    OBK_HIP(hipStreamSynchronize(s));
+    if (n) {
+        void* st = pinned_stage(n * sizeof(T));
+        OBK_HIP(hipMemcpyAsync(st, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipStreamSynchronize(s));
+        std::memcpy(h.data(), st, n * sizeof(T));
+    } else {
+        OBK_HIP(hipStreamSynchronize(s));
+    }
     return h;
 }
 
@@ -389,11 +419,42 @@ void ensure_fp32(obk_plan_s& P, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Optional stage timing of the plan (OBK_PLAN_TRACE=1 in the environment):
+// the stream is synchronised at each stage boundary and the wall time of each
+// stage is printed to stderr when the plan is complete.
+struct PlanTrace {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::chrono::steady_clock::time_point t0, last;
+    std::vector<std::pair<const char*, double>> marks;
+    explicit PlanTrace(hipStream_t st) : s(st) {
+        const char* e = std::getenv("OBK_PLAN_TRACE");
+        on = e && e[0] && e[0] != '0';
+        if (on) t0 = last = std::chrono::steady_clock::now();
+    }
+    void mark(const char* what) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        auto now = std::chrono::steady_clock::now();
+        marks.emplace_back(what, std::chrono::duration<double, std::milli>(now - last).count());
+        last = now;
+    }
+    void report(int64_t n, int64_t nnz) {
+        if (!on) return;
+        double tot = std::chrono::duration<double, std::milli>(last - t0).count();
+        std::fprintf(stderr, "[obk-plan] n=%lld nnz=%lld total %.2f ms:", (long long)n, (long long)nnz, tot);
+        for (auto& m : marks) std::fprintf(stderr, " %s %.2f", m.first, m.second);
+        std::fprintf(stderr, "\n");
+    }
+};
+
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s) {
     const int64_t n = A.n_rows, nnz = A.nnz;
     const bool dev = A.on_device != 0;
     P.n = n; P.nnz = nnz; P.delta = delta; P.input_on_device = dev;
     OBK_HIP(hipGetDevice(&P.device));
+    AllocScope pool(s);
+    PlanTrace tr(s);
 
     // ---- a1: ingest and validate (square checked by the caller)
     DevArray<int64_t> rp; DevArray<int32_t> ci; DevArray<double> v, fd;
@@ -415,6 +476,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     OBK_HIP(hipGetLastError());
     const int nbits = bits_for((uint64_t)std::max<int64_t>(n - 1, 0));
 
+    tr.mark("ingest");
     // ---- a2: RCM on the pattern of A + A^T without the diagonal
     std::vector<int32_t> perm(n);
     if (P.opts.use_rcm && n > 0) {
@@ -447,6 +509,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     P.h_perm = perm;
     to_device(P.perm, perm.data(), n, s);
 
+    tr.mark("rcm");
     // ---- a3: A~ = P A P^T with rows sorted by the new column index
     DevArray<int32_t> q; q.alloc(n);
     k_inverse_perm<<<nblk(n), kT, 0, s>>>(n, P.perm.get(), q.get());
@@ -454,7 +517,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     k_perm_lengths<<<nblk(n), kT, 0, s>>>(n, P.perm.get(), rp.get(), trp.get());
     OBK_HIP(hipGetLastError());
     int64_t tot = scan_exclusive_i64(trp.get(), trp.get(), n, s);
-    OBK_HIP(hipMemcpyAsync(trp.get() + n, &tot, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_set_i64<<<1, 1, 0, s>>>(trp.get() + n, tot);
     DevArray<uint32_t> kcol, entry, krow; kcol.alloc(nnz); entry.alloc(nnz); krow.alloc(nnz);
     DevArray<int32_t> trow; trow.alloc(nnz);
     DevArray<double> tf; tf.alloc(n);
@@ -472,7 +535,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         k_gather_u32_by<<<nblk(nnz), kT, 0, s>>>(nnz, krow.get(), q.get(), tmp.get());
         OBK_HIP(hipGetLastError());
         OBK_HIP(hipMemcpyAsync(krow.get(), tmp.get(), nnz * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-        OBK_HIP(hipStreamSynchronize(s));
+        sync_for_free(s);   // tmp is freed here
     }
     radix_sort_pairs(krow.get(), entry.get(), nnz, nbits, s);
     DevArray<int32_t> tci; DevArray<double> tv; tci.alloc(nnz); tv.alloc(nnz);
@@ -491,6 +554,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     row = DevArray<int32_t>(); kcol = DevArray<uint32_t>(); krow = DevArray<uint32_t>();
     entry = DevArray<uint32_t>();
 
+    tr.mark("permute");
     // ---- a4: row norms
     DevArray<double> nu, inv; nu.alloc(n); inv.alloc(n);
     k_norms<<<nblk(n), kT, 0, s>>>(n, trp.get(), tv.get(), nu.get(), inv.get());
@@ -506,6 +570,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     if (P.opts.reject_inconsistent && P.zero_rows_f2 != 0.0)
         fail(OBK_E_INCONSISTENT, "an all-zero row has a nonzero right-hand side");
 
+    tr.mark("norms");
     // ---- a5: CSC of A~ (rows ascending within a column), then conflicts
     DevArray<int64_t> cptr; cptr.alloc(n + 1);
     DevArray<int32_t> crow; crow.alloc(nnz);
@@ -515,17 +580,14 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     {
         DevArray<uint32_t> ckey; ckey.alloc(nnz);
         OBK_HIP(hipMemcpyAsync(ckey.get(), tci.get(), nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        std::vector<uint32_t> iota(nnz);
-        for (int64_t k = 0; k < nnz; k++) iota[k] = (uint32_t)k;
-        if (nnz) OBK_HIP(hipMemcpyAsync(order.get(), iota.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        OBK_HIP(hipStreamSynchronize(s));
+        k_iota_u32<<<nblk(nnz), kT, 0, s>>>(nnz, order.get());
+        OBK_HIP(hipGetLastError());
         radix_sort_pairs(ckey.get(), order.get(), nnz, nbits, s);
         OBK_HIP(hipMemsetAsync(cptr.get(), 0, (n + 1) * sizeof(int64_t), s));
         k_hist_i32<<<nblk(nnz), kT, 0, s>>>(nnz, ckey.get(), cptr.get());
         OBK_HIP(hipGetLastError());
         csc_total = scan_exclusive_i64(cptr.get(), cptr.get(), n, s);
-        OBK_HIP(hipMemcpyAsync(cptr.get() + n, &csc_total, sizeof(int64_t), hipMemcpyHostToDevice, s));
-        OBK_HIP(hipStreamSynchronize(s));
+        k_set_i64<<<1, 1, 0, s>>>(cptr.get() + n, csc_total);
         k_csc_fill<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), trow.get(), crow.get());
         OBK_HIP(hipGetLastError());
         k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());
@@ -542,6 +604,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
                                                crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get());
     OBK_HIP(hipGetLastError());
 
+    tr.mark("conflicts");
     // ---- a6: first-fit grouping on the host
     std::vector<int64_t> htrp = to_host(trp.get(), n + 1, s);
     std::vector<int64_t> hcc = to_host(ccount.get(), nnz, s);
@@ -559,6 +622,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     P.h_group = group;
     ccount = DevArray<int64_t>(); cidx = DevArray<int32_t>();
 
+    tr.mark("groups");
     // ---- a7: group-major relayout
     const int32_t G = P.ngroups;
     std::vector<int64_t> gsize(G + 1, 0);
@@ -588,12 +652,13 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     k_gm_lengths<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), P.rptr.get());
     OBK_HIP(hipGetLastError());
     int64_t nnz_act = scan_exclusive_i64(P.rptr.get(), P.rptr.get(), m, s);
-    OBK_HIP(hipMemcpyAsync(P.rptr.get() + m, &nnz_act, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_set_i64<<<1, 1, 0, s>>>(P.rptr.get() + m, nnz_act);
     P.rcol.alloc(nnz_act); P.rval.alloc(nnz_act); P.rf.alloc(m); P.rinv.alloc(m);
     k_gm_gather<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), tci.get(), tv.get(), tf.get(), inv.get(),
                                         P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.rinv.get());
     OBK_HIP(hipGetLastError());
 
+    tr.mark("relayout");
     // per-group CSC: CSC entries of active rows, stable-sorted by group
     DevArray<int64_t> keep; keep.alloc(nnz + 1);
     k_csc_group_keys<<<nblk(nnz), kT, 0, s>>>(nnz, crow.get(), dgroup.get(), keep.get());
@@ -616,7 +681,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
                                         segflag.get(), P.tcol.get(), P.sptr.get(), P.srow.get(), P.sval.get(),
                                         segs_g.get());
     OBK_HIP(hipGetLastError());
-    OBK_HIP(hipMemcpyAsync(P.sptr.get() + T, &me, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_set_i64<<<1, 1, 0, s>>>(P.sptr.get() + T, me);
     std::vector<int64_t> hfirst = to_host(segs_g.get(), std::max(G, 1), s);
     // every group has at least one row with a nonzero entry, hence a segment
     P.h_tptr.assign(G + 1, 0);
@@ -626,6 +691,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         if (P.h_tptr[g] > P.h_tptr[g + 1] || P.h_tptr[g] < 0)
             fail(OBK_E_HIP, "inconsistent per-group column segments");
 
+    tr.mark("group_csc");
     // ---- sweep schedule: tiles per group for both phases
     std::vector<int64_t> hrptr = to_host(P.rptr.get(), m + 1, s);
     std::vector<int64_t> hsptr = to_host(P.sptr.get(), T + 1, s);
@@ -642,6 +708,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     to_device(P.d_rtile_ptr, P.h_rtile_ptr.data(), P.h_rtile_ptr.size(), s);
     to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
+    tr.mark("tiles");
     // ---- FP32 copies for the refinement mode
     if (P.has_fp32()) ensure_fp32(P, s);
 
@@ -650,6 +717,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     P.w.alloc(m);
     P.red.alloc(std::max<int64_t>(nblk(std::max<int64_t>(m, 1)), 1) + 16);
     OBK_HIP(hipStreamSynchronize(s));
+    tr.mark("fp32_workspace");
+    tr.report(n, nnz);
 }
 
 }  // namespace obk

@@ -88,7 +88,13 @@ void scan_rec(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
     scan_rec(sums.get(), sums.get(), nb, s);
     k_tile_scan<<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, sums.get(), out);
     OBK_HIP(hipGetLastError());
-    OBK_HIP(hipStreamSynchronize(s));   // sums is freed on return
+    sync_for_free(s);   // sums is freed on return
+}
+
+// *out = *a (+ *b when b is given); one thread
+__global__ void k_total(const int64_t* a, const int64_t* b, int64_t* out) {
+    const int64_t v = *a;
+    *out = b ? v + *b : v;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -169,13 +175,18 @@ int bits_for(uint64_t max_value) {
 
 int64_t scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
     if (n <= 0) return 0;
-    int64_t last_in = 0, last_out = 0;
-    OBK_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    OBK_HIP(hipStreamSynchronize(s));
+    // total = in[n-1] + out[n-1], formed on the device (in may alias out)
+    DevArray<int64_t> last;
+    last.alloc(1);
+    k_total<<<1, 1, 0, s>>>(in + n - 1, nullptr, last.get());
+    OBK_HIP(hipGetLastError());
     scan_rec(in, out, n, s);
-    OBK_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    k_total<<<1, 1, 0, s>>>(last.get(), out + n - 1, last.get());
+    OBK_HIP(hipGetLastError());
+    int64_t* h = static_cast<int64_t*>(pinned_stage(sizeof(int64_t)));
+    OBK_HIP(hipMemcpyAsync(h, last.get(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
-    return last_in + last_out;
+    return *h;
 }
 
 int64_t scan_counts_i32(const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {
@@ -210,7 +221,7 @@ void radix_sort_pairs(uint32_t* keys, uint32_t* vals, int64_t n, int key_bits, h
         OBK_HIP(hipMemcpyAsync(keys, ki, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         if (vals) OBK_HIP(hipMemcpyAsync(vals, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
-    OBK_HIP(hipStreamSynchronize(s));
+    sync_for_free(s);   // k2, v2 and counts are freed on return
 }
 
 }  // namespace obk
