@@ -71,6 +71,7 @@ struct Block {               // a range of rows or columns of one system
 };
 
 struct ResSys {              // FP64 arrays for residual, scaling and update
+    const Tile* rtiles;
     const int64_t* rptr;
     const int32_t* rcol;
     const double* rval;
@@ -168,38 +169,22 @@ __global__ __launch_bounds__(kTileThreads * SUB) void k_batch_sweeps(const Batch
     if (trace && threadIdx.x == 0) trace[2 * blockIdx.x + 1] = wall_clock64();
 }
 
-__global__ __launch_bounds__(256) void k_batch_resid(const ResSys* __restrict__ sys, const Block* __restrict__ blocks,
-                                                     double* __restrict__ psum, double* __restrict__ pmax,
-                                                     int* __restrict__ nonfinite) {
-    __shared__ double red[256];
-    __shared__ double mx[256];
+// FP64 residual of one R tile of one system per workgroup (block = {system,
+// tile}); the per-tile partials are those of the single-system solve, so the
+// per-system reduction in k_batch_reduce gives the same relative residual.
+__global__ __launch_bounds__(kTileThreads) void k_batch_resid(const ResSys* __restrict__ sys,
+                                                              const Block* __restrict__ blocks,
+                                                              double* __restrict__ psum, double* __restrict__ pmax,
+                                                              int* __restrict__ nonfinite) {
+    __shared__ double prod[kTileEntries];
     const Block bk = blocks[blockIdx.x];
     const ResSys S = sys[bk.sys];
-    const int64_t a = bk.begin + (int64_t)threadIdx.x;
-    const bool valid = a < bk.end;
-    const int64_t ac = valid ? a : bk.begin;
-    const int64_t k0 = S.rptr[ac], k1 = valid ? S.rptr[ac + 1] : k0;
-    double s = 0.0;
-    for (int64_t k = k0; k < k1; k++) s = s + S.rval[k] * S.x[S.rcol[k]];
-    const double ri = S.rf[ac] - s;
-    if (valid) {
-        if (S.r) S.r[a] = ri;      // FP64 plans keep no residual vector
-        if (!isfinite(ri)) atomicOr(nonfinite, 1);
-    }
-    red[threadIdx.x] = valid ? ri * ri : 0.0;
-    mx[threadIdx.x] = valid ? fabs(ri) : 0.0;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
-            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) { psum[blockIdx.x] = red[0]; pmax[blockIdx.x] = mx[0]; }
+    const Tile t = S.rtiles[bk.begin];
+    double s2, mx;
+    tile_resid(t, tile_chunks(t), prod, S.rptr, S.rcol, S.rval, S.rf, S.x, S.r, nonfinite, s2, mx);
+    if (threadIdx.x == 0) { psum[blockIdx.x] = s2; pmax[blockIdx.x] = mx; }
 }
 
-// one block per system: ordered reduction of its row blocks
 __global__ __launch_bounds__(256) void k_batch_reduce(const ResSys* __restrict__ sys,
                                                       const int32_t* __restrict__ blk_ptr,
                                                       const double* __restrict__ psum,
@@ -299,11 +284,11 @@ struct obk_batch_s {
     obk::DevArray<uint32_t> bars;            // 2 per system
     obk::DevArray<int32_t> task_ptr;
     obk::DevArray<char> tasks, sys_sweep, sys_res;
-    obk::DevArray<char> rowblocks, colblocks;
+    obk::DevArray<char> rowblocks, colblocks, resblocks;
     obk::DevArray<int32_t> rowblk_ptr;
     obk::DevArray<double> psum, pmax;
     obk::DevArray<int> err;
-    int64_t n_rowblocks = 0, n_colblocks = 0;
+    int64_t n_rowblocks = 0, n_colblocks = 0, n_resblocks = 0;
     std::vector<uint8_t> h_enabled;
     bool busy = false;
     obk::DevArray<uint64_t> trace;       // per workgroup start/end (OBK_TRACE=1)
@@ -413,35 +398,39 @@ void build_schedule(obk_batch_s& B) {
         upload(B.sys_sweep, v);
     }
     std::vector<ResSys> rs;
-    std::vector<Block> rows, cols;
+    std::vector<Block> rows, cols, res;
     std::vector<int32_t> rptr(count + 1, 0);
     for (int s = 0; s < count; s++) {
         obk_plan_s& P = *B.plans[s];
-        rs.push_back(ResSys{P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(), P.r64.get(),
-                            P.b32.get(), P.d32.get(), P.fnorm2, P.zero_rows_f2, P.zero_rows_fmax});
+        rs.push_back(ResSys{P.rtiles.get(), P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(),
+                            P.r64.get(), P.b32.get(), P.d32.get(), P.fnorm2, P.zero_rows_f2, P.zero_rows_fmax});
         for (int64_t a = 0; a < std::max<int64_t>(P.m, 1); a += 256)
             rows.push_back(Block{s, (int32_t)a, (int32_t)std::min<int64_t>(a + 256, P.m)});
-        rptr[s + 1] = (int32_t)rows.size();
+        // residual blocks: the system's R tiles in plan order (all groups)
+        for (size_t k = 0; k < P.h_rtiles.size(); k++) res.push_back(Block{s, (int32_t)k, 0});
+        rptr[s + 1] = (int32_t)res.size();
         for (int64_t c = 0; c < P.n; c += 256)
             cols.push_back(Block{s, (int32_t)c, (int32_t)std::min<int64_t>(c + 256, P.n)});
     }
     upload(B.sys_res, rs);
     upload(B.rowblocks, rows);
     upload(B.colblocks, cols);
+    upload(B.resblocks, res);
     B.n_rowblocks = (int64_t)rows.size();
     B.n_colblocks = (int64_t)cols.size();
+    B.n_resblocks = (int64_t)res.size();
     B.rowblk_ptr.alloc(count + 1);
     OBK_HIP(hipMemcpy(B.rowblk_ptr.get(), rptr.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    B.psum.alloc(std::max<int64_t>(B.n_rowblocks, 1));
-    B.pmax.alloc(std::max<int64_t>(B.n_rowblocks, 1));
+    B.psum.alloc(std::max<int64_t>(B.n_resblocks, 1));
+    B.pmax.alloc(std::max<int64_t>(B.n_resblocks, 1));
     B.relres.alloc(std::max(count, 1));
     B.sigma.alloc(std::max(count, 1));
     B.active.alloc(std::max(count, 1));
     B.enabled.alloc(std::max(count, 1));
     B.h_enabled.assign(count, 1);
     OBK_HIP(hipMemcpy(B.enabled.get(), B.h_enabled.data(), count, hipMemcpyHostToDevice));
-    B.err.alloc(1);
-    OBK_HIP(hipMemset(B.err.get(), 0, sizeof(int)));
+    B.err.alloc(2);   // [0]: a team barrier timed out; [1]: a residual was not finite (per system in relres)
+    OBK_HIP(hipMemset(B.err.get(), 0, 2 * sizeof(int)));
 }
 
 }  // namespace
@@ -553,9 +542,10 @@ void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s) {
 void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s) {
     const int count = (int)B.plans.size();
     if (count == 0) return;
-    k_batch_resid<<<(unsigned)B.n_rowblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
-                                                          (const Block*)B.rowblocks.get(), B.psum.get(),
-                                                          B.pmax.get(), B.err.get());
+    if (B.n_resblocks)
+        k_batch_resid<<<(unsigned)B.n_resblocks, kTileThreads, 0, s>>>((const ResSys*)B.sys_res.get(),
+                                                                       (const Block*)B.resblocks.get(), B.psum.get(),
+                                                                       B.pmax.get(), B.err.get() + 1);
     k_batch_reduce<<<count, 256, 0, s>>>((const ResSys*)B.sys_res.get(), B.rowblk_ptr.get(), B.psum.get(),
                                          B.pmax.get(), tol > 0 ? tol : -1.0, B.enabled.get(), B.relres.get(),
                                          B.sigma.get(), B.active.get());

@@ -715,7 +715,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     // ---- workspace
     P.x.alloc(n);
     P.w.alloc(m);
-    P.red.alloc(std::max<int64_t>(nblk(std::max<int64_t>(m, 1)), 1) + 16);
+    P.red.alloc(2 * std::max<size_t>(P.h_rtiles.size(), 1) + 16);   // residual partials per R tile
     OBK_HIP(hipStreamSynchronize(s));
     tr.mark("fp32_workspace");
     tr.report(n, nnz);

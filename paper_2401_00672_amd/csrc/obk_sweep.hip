@@ -29,44 +29,6 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-// r_a = f_a - a_a . x over the group-major rows; per-block sums of r_a^2
-__global__ __launch_bounds__(256) void k_resid(int64_t m, const int64_t* __restrict__ rptr,
-                                               const int32_t* __restrict__ rcol, const double* __restrict__ rval,
-                                               const double* __restrict__ rf, const double* __restrict__ x,
-                                               double* __restrict__ partial, int* __restrict__ nonfinite) {
-    __shared__ double red[256];
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r2 = 0.0;
-    if (a < m) {
-        double s = 0.0;
-        for (int64_t k = rptr[a]; k < rptr[a + 1]; k++) s = s + rval[k] * x[rcol[k]];
-        double r = rf[a] - s;
-        if (!isfinite(r)) atomicOr(nonfinite, 1);
-        r2 = r * r;
-    }
-    red[threadIdx.x] = r2;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// ordered sum of the partials by one block (deterministic)
-__global__ void k_sum_partials(int64_t np, const double* __restrict__ partial, double* __restrict__ out) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < np; i += 256) s = s + partial[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0];
-}
-
 __global__ void k_permute_in(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ x0,
                              double* __restrict__ xt) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -79,39 +41,8 @@ __global__ void k_permute_out(int64_t n, const int32_t* __restrict__ p, const do
     if (t < n) x[p[t]] = xt[t];
 }
 
-// FP64 residual of the refinement loop, kept per row: r_a = f_a - a_a . x;
-// per-block sums of r_a^2 and maxima of |r_a|
-__global__ __launch_bounds__(256) void k_resid_keep(int64_t m, const int64_t* __restrict__ rptr,
-                                                    const int32_t* __restrict__ rcol, const double* __restrict__ rval,
-                                                    const double* __restrict__ rf, const double* __restrict__ x,
-                                                    double* __restrict__ r, double* __restrict__ psum,
-                                                    double* __restrict__ pmax, int* __restrict__ nonfinite) {
-    __shared__ double red[256];
-    __shared__ double mx[256];
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double r2 = 0.0, ra = 0.0;
-    if (a < m) {
-        double s = 0.0;
-        for (int64_t k = rptr[a]; k < rptr[a + 1]; k++) s = s + rval[k] * x[rcol[k]];
-        const double ri = rf[a] - s;
-        r[a] = ri;
-        if (!isfinite(ri)) atomicOr(nonfinite, 1);
-        r2 = ri * ri;
-        ra = fabs(ri);
-    }
-    red[threadIdx.x] = r2;
-    mx[threadIdx.x] = ra;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + st];
-            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + st]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) { psum[blockIdx.x] = red[0]; pmax[blockIdx.x] = mx[0]; }
-}
-
+// ordered reduction of the per-tile partials by one block (deterministic; the
+// batched engine reduces each system's partials in the same order)
 __global__ void k_sum_max_partials(int64_t np, const double* __restrict__ psum, const double* __restrict__ pmax,
                                    double* __restrict__ out) {
     __shared__ double red[256];
@@ -301,23 +232,40 @@ obk_plan_s::~obk_plan_s() {
 
 namespace obk {
 
+// FP64 residual over the plan's R tiles (every active row): r (may be null)
+// receives r_a; *sum_sq gets sum r_a^2 over the active rows, *max_abs max |r_a|,
+// *nonfinite whether any r_a is not finite.  Synchronises the stream.
+static void resid_tiles(const obk_plan_s& P, const double* x, double* r, hipStream_t s, double* sum_sq,
+                        double* max_abs, bool* nonfinite) {
+    const int64_t nt = (int64_t)P.h_rtiles.size();
+    double* psum = P.red.get();
+    double* pmax = psum + std::max<int64_t>(nt, 1);
+    double* out = pmax + std::max<int64_t>(nt, 1);
+    int* flag = reinterpret_cast<int*>(out + 4);
+    OBK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    if (nt)
+        k_resid_tiles<<<(unsigned)nt, kT, 0, s>>>(P.rtiles.get(), P.rptr.get(), P.rcol.get(), P.rval.get(),
+                                                  P.rf.get(), x, r, psum, pmax, flag);
+    k_sum_max_partials<<<1, 256, 0, s>>>(nt, psum, pmax, out);
+    OBK_HIP(hipGetLastError());
+    auto* h = static_cast<double*>(pinned_stage(4 * sizeof(double)));
+    OBK_HIP(hipMemcpyAsync(h, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipMemcpyAsync(h + 2, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    OBK_HIP(hipStreamSynchronize(s));
+    int nf = 0;
+    std::memcpy(&nf, h + 2, sizeof(int));
+    *sum_sq = h[0];
+    *max_abs = h[1];
+    *nonfinite = nf != 0;
+}
+
 // relative residual ||f~ - A~ x|| / ||f~|| (synchronises the stream); sets *nonfinite
 double relres(const obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
-    const int64_t m = P.m;
-    const unsigned nb = nblk(m);
-    double* part = P.red.get();
-    int* flag = reinterpret_cast<int*>(part + nb + 8);
-    OBK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    k_resid<<<nb, 256, 0, s>>>(m, P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), x, part, flag);
-    k_sum_partials<<<1, 256, 0, s>>>(nb, part, part + nb);
-    OBK_HIP(hipGetLastError());
-    double r2 = 0;
-    int nf = 0;
-    OBK_HIP(hipMemcpyAsync(&r2, part + nb, sizeof(double), hipMemcpyDeviceToHost, s));
-    OBK_HIP(hipMemcpyAsync(&nf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    OBK_HIP(hipStreamSynchronize(s));
+    double r2 = 0, mx = 0;
+    bool nf = false;
+    resid_tiles(P, x, nullptr, s, &r2, &mx, &nf);
     r2 = r2 + P.zero_rows_f2;
-    if (nonfinite) *nonfinite = (nf != 0) || !std::isfinite(r2);
+    if (nonfinite) *nonfinite = nf || !std::isfinite(r2);
     if (P.fnorm2 == 0.0) return r2 == 0.0 ? 0.0 : INFINITY;
     return std::sqrt(r2) / std::sqrt(P.fnorm2);
 }
@@ -397,24 +345,13 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     }
     k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), x0dev, P.x.get());
     OBK_HIP(hipGetLastError());
-    const unsigned nb = nblk(m);
-    double* psum = P.red.get();
-    DevArray<double> pmax; pmax.alloc(nb + 4);
-    int* flag = reinterpret_cast<int*>(psum + nb + 8);
     auto residual = [&](double* rho, double* sigma, bool* nonfinite) {
-        OBK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-        k_resid_keep<<<nb, 256, 0, s>>>(m, P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(),
-                                        P.r64.get(), psum, pmax.get(), flag);
-        k_sum_max_partials<<<1, 256, 0, s>>>(nb, psum, pmax.get(), pmax.get() + nb);
-        OBK_HIP(hipGetLastError());
-        double out[2] = {0, 0};
-        int nf = 0;
-        OBK_HIP(hipMemcpyAsync(out, pmax.get() + nb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        OBK_HIP(hipMemcpyAsync(&nf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-        OBK_HIP(hipStreamSynchronize(s));
-        const double r2 = out[0] + P.zero_rows_f2;
-        *sigma = std::max(out[1], P.zero_rows_fmax);
-        *nonfinite = nf != 0 || !std::isfinite(r2);
+        double r2 = 0, mx = 0;
+        bool nf = false;
+        resid_tiles(P, P.x.get(), P.r64.get(), s, &r2, &mx, &nf);
+        r2 = r2 + P.zero_rows_f2;
+        *sigma = std::max(mx, P.zero_rows_fmax);
+        *nonfinite = nf || !std::isfinite(r2);
         *rho = (P.fnorm2 == 0.0) ? (r2 == 0.0 ? 0.0 : INFINITY) : std::sqrt(r2) / std::sqrt(P.fnorm2);
     };
     double rho = 0, sigma = 0;

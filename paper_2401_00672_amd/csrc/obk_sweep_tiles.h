@@ -171,6 +171,56 @@ __device__ __forceinline__ void tile_phase_s(const Tile& t, int nchunks, T* prod
         if (own[q]) x[col[q]] = xc[q] + acc[q];
 }
 
+// FP64 residual of one R tile: r_a = f_a - a_a . x for each row of the tile,
+// each row summed in ascending entry order exactly as in phase R.  r (may be
+// null) receives r_a.  The tile's sum of r_a^2 and maximum of |r_a| are formed
+// by a fixed tree over the row slots and returned to every thread of the
+// sub-block (prod is reused as the tree's scratch).  A nonfinite r_a sets
+// *nonfinite.
+__device__ __forceinline__ void tile_resid(const Tile& t, int nchunks, double* prod,
+                                           const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                           const double* __restrict__ rval, const double* __restrict__ rf,
+                                           const double* __restrict__ x, double* __restrict__ r,
+                                           int* __restrict__ nonfinite, double& sum_sq, double& max_abs) {
+    static_assert(kTileSegs == kTileThreads, "one row per thread");
+    const int nseg = t.seg_end - t.seg_begin;
+    const int me = threadIdx.x & (kTileThreads - 1);
+    const bool own = me < nseg;
+    const int64_t a = t.seg_begin + (own ? me : 0);
+    const int64_t k0 = rptr[a], k1 = rptr[a + 1];
+    const double fa = rf[a];
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; c++) {
+        const int64_t base = t.ent_begin + (int64_t)c * kTileEntries;
+        const int len = (int)max<int64_t>(0, min<int64_t>(kTileEntries, t.ent_end - base));
+        stage_r(prod, me, len, rcol + base, rval + base, x);
+        __syncthreads();
+        const int64_t lo = max(k0, base), hi = own ? min(k1, base + len) : lo;
+        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
+        __syncthreads();
+    }
+    const double ra = fa - acc;
+    if (own) {
+        if (r) r[a] = ra;
+        if (!isfinite(ra)) atomicOr(nonfinite, 1);
+    }
+    double* red = prod;
+    double* mx = prod + kTileThreads;
+    red[me] = own ? ra * ra : 0.0;
+    mx[me] = own ? fabs(ra) : 0.0;
+    __syncthreads();
+    for (int st = kTileThreads / 2; st > 0; st >>= 1) {
+        if (me < st) {
+            red[me] = red[me] + red[me + st];
+            mx[me] = fmax(mx[me], mx[me + st]);
+        }
+        __syncthreads();
+    }
+    sum_sq = red[0];
+    max_abs = mx[0];
+    __syncthreads();
+}
+
 namespace {
 
 // Phase R / phase S kernels over the tiles of one group: one tile per
@@ -192,6 +242,19 @@ __global__ __launch_bounds__(kTileThreads) void k_phase_s(
     __shared__ T prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
     tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
+}
+
+// FP64 residual over all R tiles of a plan, one tile per workgroup: r
+// (may be null) gets r_a; psum/pmax get the per-tile sum of r_a^2 and max |r_a|.
+__global__ __launch_bounds__(kTileThreads) void k_resid_tiles(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+    const double* __restrict__ rval, const double* __restrict__ rf, const double* __restrict__ x,
+    double* __restrict__ r, double* __restrict__ psum, double* __restrict__ pmax, int* __restrict__ nonfinite) {
+    __shared__ double prod[kTileEntries];
+    const Tile t = tiles[blockIdx.x];
+    double s2, mx;
+    tile_resid(t, tile_chunks(t), prod, rptr, rcol, rval, rf, x, r, nonfinite, s2, mx);
+    if (threadIdx.x == 0) { psum[blockIdx.x] = s2; pmax[blockIdx.x] = mx; }
 }
 
 }  // namespace
