@@ -219,9 +219,11 @@ OBK_API obk_status obk_sweep_profile(obk_plan_t plan, double *x_tilde_dev, int64
  *
  * Tunables (0 = default): wgs_per_cu workgroups per compute unit in the
  * persistent launch (default 2, clamped to occupancy); team_work, the entries
- * per sweep one workgroup of a system's team should carry (default 262144);
- * max_team, the largest team (default 16); tiles_per_wg, how many tiles of
- * 256 rows (columns) a workgroup keeps in flight (default 4).  obk_batch_tune times candidate
+ * per sweep one workgroup of a system's team should carry (default: the
+ * batch's average per workgroup; a system above it is split over a team of
+ * workgroups on one XCD, and a workgroup joins at most one team); max_team,
+ * the largest team (default 16); tiles_per_wg, how many tiles (of up to 512
+ * rows or columns) a workgroup keeps in flight (default 4).  obk_batch_tune times candidate
  * settings on the given plans and returns the fastest.
  */
 typedef struct obk_batch_s *obk_batch_t;

@@ -362,7 +362,7 @@ obk_status obk_batch_tune(const obk_plan_t* plans, int count, obk_batch_opts* be
         for (int sub : {1, 2, 4}) {
             for (int per_cu : {1, 2, 4, 8}) {
                 if (sub * per_cu > 16) continue;
-                for (int64_t tw : {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 30}) {
+                for (int64_t tw : {int64_t(0), int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 30}) {
                     obk_batch_opts o{per_cu, tw, 16, sub};
                     obk_batch_s* B = obk_batch_new();
                     struct Del { obk_batch_s* b; ~Del() { obk_batch_delete(b); } } del{B};

@@ -37,6 +37,12 @@ void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
 namespace {
 
 constexpr long kSpinLimit = 1L << 22;
+// Merged tiles of the batched sweep: up to kBatchQ * 256 segments (kBatchQ
+// per thread) and kBatchChunk entries; FP32 stages them in one chunk of 16
+// entries per thread, FP64 (twice the registers per value) in two of 8.
+constexpr int kBatchQ = 2;
+constexpr int kBatchChunk = kTileThreads * 16;
+template <class T> constexpr int batch_e() { return sizeof(T) == 4 ? 16 : 8; }
 
 template <class T> struct BatchSys {
     const Tile* rtiles;
@@ -132,14 +138,15 @@ __device__ __forceinline__ void team_phase(const BatchSys<T>& S, int32_t g, int3
         mt.seg_end = ok ? tb.seg_end : 0;
         mt.ent_begin = ok ? tb.ent_begin : 0;
         mt.ent_end = ok ? tb.ent_end : 0;
-        if ((threadIdx.x & (kTileThreads - 1)) == 0) chunks[sb] = tile_chunks(mt);
+        constexpr int E = batch_e<T>();
+        if ((threadIdx.x & (kTileThreads - 1)) == 0) chunks[sb] = tile_chunks<E>(mt);
         __syncthreads();
         int nchunks = 0;
         for (int b = 0; b < SUB; b++) nchunks = max(nchunks, chunks[b]);
         if (kR)
-            tile_phase_r<T>(mt, nchunks, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
+            tile_phase_r<T, kBatchQ, E>(mt, nchunks, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
         else
-            tile_phase_s<T>(mt, nchunks, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
+            tile_phase_s<T, kBatchQ, E>(mt, nchunks, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
     }
 }
 
@@ -149,8 +156,9 @@ __global__ __launch_bounds__(kTileThreads * SUB) void k_batch_sweeps(const Batch
                                                                      const TeamTask* __restrict__ tasks,
                                                                      const uint8_t* __restrict__ active, int sweeps,
                                                                      int* err, uint64_t* __restrict__ trace) {
-    __shared__ T prod_all[SUB * kTileEntries];
-    T* prod = prod_all + (threadIdx.x / kTileThreads) * kTileEntries;
+    constexpr int chunk = kTileThreads * batch_e<T>();
+    __shared__ T prod_all[SUB * chunk];
+    T* prod = prod_all + (threadIdx.x / kTileThreads) * chunk;
     const int32_t t0 = task_ptr[blockIdx.x], t1 = task_ptr[blockIdx.x + 1];
     if (trace && threadIdx.x == 0) trace[2 * blockIdx.x] = wall_clock64();
     for (int32_t ti = t0; ti < t1; ti++) {
@@ -256,16 +264,52 @@ __global__ void k_batch_permute_out(int64_t n, const int32_t* __restrict__ p, co
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-template <class T> BatchSys<T> sys_view(obk_plan_s& P, uint32_t* bar, int team);
-template <> BatchSys<float> sys_view<float>(obk_plan_s& P, uint32_t* bar, int team) {
-    return BatchSys<float>{P.rtiles.get(), P.stiles.get(), P.d_rtile_ptr.get(), P.d_stile_ptr.get(), P.rptr.get(),
-                           P.rcol.get(), P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sptr.get(), P.srow.get(),
-                           P.sval32.get(), P.tcol.get(), P.d32.get(), P.w32.get(), P.ngroups, team, bar};
+// Tiles of the batched sweep for one system: rt/st (device) with per-group
+// offsets rp/sp (device, G + 1 each).
+struct TileView {
+    const Tile* rt;
+    const Tile* st;
+    const int32_t* rp;
+    const int32_t* sp;
+};
+
+template <class T> BatchSys<T> sys_view(obk_plan_s& P, const TileView& tv, uint32_t* bar, int team);
+template <> BatchSys<float> sys_view<float>(obk_plan_s& P, const TileView& tv, uint32_t* bar, int team) {
+    return BatchSys<float>{tv.rt, tv.st, tv.rp, tv.sp, P.rptr.get(), P.rcol.get(), P.rval32.get(), P.b32.get(),
+                           P.rinv32.get(), P.sptr.get(), P.srow.get(), P.sval32.get(), P.tcol.get(), P.d32.get(),
+                           P.w32.get(), P.ngroups, team, bar};
 }
-template <> BatchSys<double> sys_view<double>(obk_plan_s& P, uint32_t* bar, int team) {
-    return BatchSys<double>{P.rtiles.get(), P.stiles.get(), P.d_rtile_ptr.get(), P.d_stile_ptr.get(), P.rptr.get(),
-                            P.rcol.get(), P.rval.get(), P.rf.get(), P.rinv.get(), P.sptr.get(), P.srow.get(),
-                            P.sval.get(), P.tcol.get(), P.x.get(), P.w.get(), P.ngroups, team, bar};
+template <> BatchSys<double> sys_view<double>(obk_plan_s& P, const TileView& tv, uint32_t* bar, int team) {
+    return BatchSys<double>{tv.rt, tv.st, tv.rp, tv.sp, P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(),
+                            P.rinv.get(), P.sptr.get(), P.srow.get(), P.sval.get(), P.tcol.get(), P.x.get(),
+                            P.w.get(), P.ngroups, team, bar};
+}
+
+// Join consecutive tiles of one group while the result keeps at most
+// kBatchQ * 256 segments and kBatchChunk entries (a tile already over the
+// entry bound stays alone); appends to out, and the group offsets (relative
+// to the first tile appended) to optr.
+void merge_tiles(const std::vector<Tile>& in, const std::vector<int32_t>& ptr, int32_t G, std::vector<Tile>& out,
+                 std::vector<int32_t>& optr) {
+    const size_t base = out.size();
+    optr.push_back(0);
+    for (int32_t g = 0; g < G; g++) {
+        int32_t k = ptr[g];
+        while (k < ptr[g + 1]) {
+            Tile m = in[k++];
+            while (k < ptr[g + 1]) {
+                const Tile& nx = in[k];
+                const int64_t segs = (int64_t)nx.seg_end - m.seg_begin;
+                const int64_t ents = nx.ent_end - m.ent_begin;
+                if (segs > (int64_t)kBatchQ * kTileThreads || ents > kBatchChunk) break;
+                m.seg_end = nx.seg_end;
+                m.ent_end = nx.ent_end;
+                k++;
+            }
+            out.push_back(m);
+        }
+        optr.push_back((int32_t)(out.size() - base));
+    }
 }
 
 }  // namespace
@@ -285,6 +329,7 @@ struct obk_batch_s {
     obk::DevArray<int32_t> task_ptr;
     obk::DevArray<char> tasks, sys_sweep, sys_res;
     obk::DevArray<char> rowblocks, colblocks, resblocks;
+    obk::DevArray<char> mtiles_r, mtiles_s, mptr_r, mptr_s;   // merged sweep tiles
     obk::DevArray<int32_t> rowblk_ptr;
     obk::DevArray<double> psum, pmax;
     obk::DevArray<int> err;
@@ -305,9 +350,11 @@ template <class T> void upload(DevArray<char>& d, const std::vector<T>& h) {
 
 // Team sizing and placement.  Work of a system per sweep ~ its entries in
 // both phases; a system gets ceil(work / team_work) workgroups (at most
-// max_team), all on one XCD (workgroup b runs on XCD b % 8).  Single-workgroup
-// teams are packed onto the least-loaded workgroups.  Each workgroup's task
-// list is ordered by system id.
+// max_team; team_work defaults to the average work per workgroup), all on one
+// XCD (workgroup b runs on XCD b % 8).  A workgroup joins at most one team and
+// runs that task first, so the members of a team start it together and never
+// wait at a team barrier for a member still busy with another system.
+// Single-workgroup systems then go to the least-loaded workgroups.
 void build_schedule(obk_batch_s& B) {
     const int count = (int)B.plans.size();
     int dev = 0, cus = 256;
@@ -325,19 +372,27 @@ void build_schedule(obk_batch_s& B) {
         if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 1>, kTileThreads, 0));
         if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 2>, 2 * kTileThreads, 0));
         if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 4>, 4 * kTileThreads, 0));
+
     }
     per_cu = std::max(1, std::min(per_cu, occ));
     const int nxcd = 8;
     int nwg = std::max(nxcd, cus * per_cu);
     nwg -= nwg % nxcd;
     B.nwg = nwg;
-    const int64_t team_work = B.opts.team_work > 0 ? B.opts.team_work : (1 << 18);
-    const int max_team = std::max(1, std::min(B.opts.max_team > 0 ? B.opts.max_team : 16, nwg / nxcd));
     std::vector<int64_t> work(count);
-    for (int s = 0; s < count; s++) work[s] = 2 * B.plans[s]->nnz + 2 * B.plans[s]->m;
+    int64_t total = 0;
+    for (int s = 0; s < count; s++) {
+        work[s] = 2 * B.plans[s]->nnz + 2 * B.plans[s]->m;
+        total += work[s];
+    }
+    // default: a system gets about work / (average work per workgroup) members
+    const int64_t team_work =
+        B.opts.team_work > 0 ? B.opts.team_work : std::max<int64_t>(1, (total + nwg - 1) / nwg);
+    const int max_team = std::max(1, std::min(B.opts.max_team > 0 ? B.opts.max_team : 16, nwg / nxcd));
     B.team.assign(count, 1);
     std::vector<std::vector<TeamTask>> per_wg(nwg);
     std::vector<int64_t> load(nwg, 0);
+    std::vector<uint8_t> teamed(nwg, 0);     // a workgroup joins at most one team
     // large systems first
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
@@ -345,31 +400,46 @@ void build_schedule(obk_batch_s& B) {
     const int slots = nwg / nxcd;
     for (int s : order) {
         int k = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (work[s] + team_work - 1) / team_work));
-        B.team[s] = k;
-        if (k == 1) {
+        std::vector<int> pick;
+        if (k > 1) {
+            // the XCD with the most free slots (ties: least loaded); the team
+            // shrinks to the free slots there
+            int best_x = -1, best_free = 0;
+            int64_t best_l = INT64_MAX;
+            for (int x = 0; x < nxcd; x++) {
+                int nfree = 0;
+                int64_t l = 0;
+                for (int j = 0; j < slots; j++) {
+                    const int b = x + nxcd * j;
+                    if (!teamed[b]) { nfree++; l += load[b]; }
+                }
+                if (nfree > best_free || (nfree == best_free && nfree > 0 && l < best_l)) {
+                    best_free = nfree; best_l = l; best_x = x;
+                }
+            }
+            k = std::min(k, best_free);
+            if (k > 1) {
+                std::vector<int> ids;
+                for (int j = 0; j < slots; j++) {
+                    const int b = best_x + nxcd * j;
+                    if (!teamed[b]) ids.push_back(b);
+                }
+                std::partial_sort(ids.begin(), ids.begin() + k, ids.end(),
+                                  [&](int a, int b) { return load[a] < load[b]; });
+                pick.assign(ids.begin(), ids.begin() + k);
+            }
+        }
+        if (k > 1) {
+            B.team[s] = k;
+            for (int j = 0; j < k; j++) {
+                per_wg[pick[j]].push_back(TeamTask{s, j});
+                teamed[pick[j]] = 1;
+                load[pick[j]] += (work[s] + k - 1) / k;
+            }
+        } else {
             int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             per_wg[best].push_back(TeamTask{s, 0});
             load[best] += work[s];
-        } else {
-            // the XCD whose k least-loaded slots carry the least total load
-            int best_x = 0;
-            int64_t best_l = INT64_MAX;
-            std::vector<int> pick, best_pick;
-            for (int x = 0; x < nxcd; x++) {
-                pick.clear();
-                std::vector<int> ids(slots);
-                for (int j = 0; j < slots; j++) ids[j] = x + nxcd * j;
-                std::partial_sort(ids.begin(), ids.begin() + k, ids.end(),
-                                  [&](int a, int b) { return load[a] < load[b]; });
-                int64_t l = 0;
-                for (int j = 0; j < k; j++) l = std::max(l, load[ids[j]]);
-                if (l < best_l) { best_l = l; best_x = x; best_pick.assign(ids.begin(), ids.begin() + k); }
-            }
-            (void)best_x;
-            for (int j = 0; j < k; j++) {
-                per_wg[best_pick[j]].push_back(TeamTask{s, j});
-                load[best_pick[j]] = best_l + (work[s] + k - 1) / k;
-            }
         }
     }
     std::vector<int32_t> tptr(nwg + 1, 0);
@@ -388,13 +458,36 @@ void build_schedule(obk_batch_s& B) {
     upload(B.tasks, flat);
     B.bars.alloc(2 * (size_t)std::max(count, 1));
     OBK_HIP(hipMemset(B.bars.get(), 0, 2 * sizeof(uint32_t) * std::max(count, 1)));
+    // merged tiles of every system, R then S, in one array each
+    std::vector<Tile> mr, ms;
+    std::vector<int32_t> mrp, msp;
+    std::vector<size_t> rbase(count), sbase(count), rpbase(count), spbase(count);
+    for (int s = 0; s < count; s++) {
+        obk_plan_s& P = *B.plans[s];
+        rbase[s] = mr.size(); rpbase[s] = mrp.size();
+        merge_tiles(P.h_rtiles, P.h_rtile_ptr, P.ngroups, mr, mrp);
+        sbase[s] = ms.size(); spbase[s] = msp.size();
+        merge_tiles(P.h_stiles, P.h_stile_ptr, P.ngroups, ms, msp);
+    }
+    upload(B.mtiles_r, mr);
+    upload(B.mtiles_s, ms);
+    upload(B.mptr_r, mrp);
+    upload(B.mptr_s, msp);
+    auto view = [&](int s) {
+        return TileView{reinterpret_cast<const Tile*>(B.mtiles_r.get()) + rbase[s],
+                        reinterpret_cast<const Tile*>(B.mtiles_s.get()) + sbase[s],
+                        reinterpret_cast<const int32_t*>(B.mptr_r.get()) + rpbase[s],
+                        reinterpret_cast<const int32_t*>(B.mptr_s.get()) + spbase[s]};
+    };
     if (B.fp32) {
         std::vector<BatchSys<float>> v;
-        for (int s = 0; s < count; s++) v.push_back(sys_view<float>(*B.plans[s], B.bars.get() + 2 * s, B.team[s]));
+        for (int s = 0; s < count; s++)
+            v.push_back(sys_view<float>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
         upload(B.sys_sweep, v);
     } else {
         std::vector<BatchSys<double>> v;
-        for (int s = 0; s < count; s++) v.push_back(sys_view<double>(*B.plans[s], B.bars.get() + 2 * s, B.team[s]));
+        for (int s = 0; s < count; s++)
+            v.push_back(sys_view<double>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
         upload(B.sys_sweep, v);
     }
     std::vector<ResSys> rs;

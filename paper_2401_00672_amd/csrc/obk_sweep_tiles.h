@@ -1,47 +1,51 @@
 // Device bodies of the two sweep phases over tiles, shared by the per-group
-// kernels (defined at the end of this file) and the batched team kernel.  T is the arithmetic type (double, or
-// float in the inner sweeps of iterative refinement).
+// kernels (defined at the end of this file) and the batched team kernel.  T
+// is the arithmetic type (double, or float in the inner sweeps of iterative
+// refinement).
 //
 // phase R (one group): for each row a of the tile, from the same x,
 //   w_a = (f_a - sum_k a_ak x_k) * inv_a
 // phase S (one group): for each touched column c of the tile,
 //   x_c = x_c + sum over the group's rows a holding c of w_a a_ac
 //
-// A workgroup of 256*SUB threads works on SUB tiles at once, one per
-// 256-thread sub-block, each with its own LDS slice of kTileEntries values.
-// A tile holds up to kTileSegs rows (columns): thread t owns segments
-// t, t + 256, ... (one segment per thread at kTileSegs = 256, which keeps
-// enough tiles per phase to fill the chip).
-// Entries are staged through LDS in chunks; each row (column) is then reduced
-// by one thread in ascending entry order, so the result does not depend on
-// SUB or on the tile schedule.  Every load that depends only on the tile
-// (row bounds, f, 1/||a||^2, the column owned) is issued before the entry
-// loads, which shortens the chain of dependent memory round trips.  Written
-// in predicated form: every load is issued at an in-range index.  An empty
-// tile {0,0,0,0} may be passed for an idle sub-block (segment 0 must exist).
+// A tile is worked on by one 256-thread sub-block.  Thread t owns segments
+// (rows in R, columns in S) t, t + 256, ..., Q of them; entries are staged
+// through LDS in chunks of 256*E values, E per thread, and each segment is
+// then reduced by its owner in ascending entry order, so the result depends
+// neither on Q, E nor on the tile schedule.  The per-group kernels use plan
+// tiles (Q = 1, E = 8, which keeps enough tiles per phase to fill the chip);
+// the batched kernel, whose parallelism comes from many systems, uses
+// merged tiles (Q = 2, E = 16) to keep twice the loads in flight per round
+// trip.  Every load that depends only on the tile (row bounds, f,
+// 1/||a||^2, the column owned) is issued before the entry loads.  Written in
+// predicated form: every load is issued at an in-range index.  An empty tile
+// {0,0,0,0} may be passed for an idle sub-block (segment 0 must exist).
 #pragma once
 
 #include "obk_internal.h"
 
 namespace obk {
 
+constexpr int kPlanE = kTileEntries / kTileThreads;    // entries per thread for plan tiles
+constexpr int kPlanQ = kTileSegs / kTileThreads;       // segments per thread for plan tiles
+
+template <int E = kPlanE>
 __device__ __forceinline__ int tile_chunks(const Tile& t) {
-    return (int)((t.ent_end - t.ent_begin + kTileEntries - 1) / kTileEntries);
+    constexpr int64_t C = (int64_t)kTileThreads * E;
+    return (int)((t.ent_end - t.ent_begin + C - 1) / C);
 }
 
 // Stage one chunk of products into LDS: prod[q] = val[q] * v[idx[q]] for
 // q < len.  All index and value loads of the thread are issued first, then all
 // gathers, so a chunk costs two dependent memory round trips, not one pair per
 // entry.  Loads are exec-masked (q < len), never issued out of range.
-constexpr int kPerThread = kTileEntries / kTileThreads;
-
-template <class T>
+template <class T, int E = kPlanE>
 __device__ __forceinline__ void stage_r(T* prod, int me, int len, const int32_t* __restrict__ idx,
                                         const T* __restrict__ val, const T* __restrict__ v) {
-    int32_t ix[kPerThread];
-    T va[kPerThread], g[kPerThread];
+    int32_t ix[E];
+    T va[E], g[E];
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         ix[e] = 0;
         va[e] = T(0);
@@ -51,26 +55,26 @@ __device__ __forceinline__ void stage_r(T* prod, int me, int len, const int32_t*
         }
     }
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         g[e] = T(0);
         if (q < len) g[e] = v[ix[e]];
     }
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         if (q < len) prod[q] = va[e] * g[e];
     }
 }
 
 // Same for phase S, where the product is w[row] * val (operand order kept).
-template <class T>
+template <class T, int E = kPlanE>
 __device__ __forceinline__ void stage_s(T* prod, int me, int len, const int32_t* __restrict__ idx,
                                         const T* __restrict__ val, const T* __restrict__ v) {
-    int32_t ix[kPerThread];
-    T va[kPerThread], g[kPerThread];
+    int32_t ix[E];
+    T va[E], g[E];
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         ix[e] = 0;
         va[e] = T(0);
@@ -80,24 +84,24 @@ __device__ __forceinline__ void stage_s(T* prod, int me, int len, const int32_t*
         }
     }
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         g[e] = T(0);
         if (q < len) g[e] = v[ix[e]];
     }
 #pragma unroll
-    for (int e = 0; e < kPerThread; e++) {
+    for (int e = 0; e < E; e++) {
         const int q = me + e * kTileThreads;
         if (q < len) prod[q] = g[e] * va[e];
     }
 }
 
-template <class T>
+template <class T, int Q = kPlanQ, int E = kPlanE>
 __device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod, const int64_t* __restrict__ rptr,
                                              const int32_t* __restrict__ rcol, const T* __restrict__ rval,
                                              const T* __restrict__ rf, const T* __restrict__ rinv,
                                              const T* __restrict__ x, T* __restrict__ w) {
-    constexpr int Q = kTileSegs / kTileThreads;      // rows owned per thread
+    constexpr int64_t C = (int64_t)kTileThreads * E;     // entries per chunk
     const int nseg = t.seg_end - t.seg_begin;
     const int me = threadIdx.x & (kTileThreads - 1);
     bool own[Q];
@@ -115,9 +119,9 @@ __device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod
         acc[q] = T(0);
     }
     for (int c = 0; c < nchunks; c++) {
-        const int64_t base = t.ent_begin + (int64_t)c * kTileEntries;
-        const int len = (int)max<int64_t>(0, min<int64_t>(kTileEntries, t.ent_end - base));
-        stage_r(prod, me, len, rcol + base, rval + base, x);
+        const int64_t base = t.ent_begin + (int64_t)c * C;
+        const int len = (int)max<int64_t>(0, min<int64_t>(C, t.ent_end - base));
+        stage_r<T, E>(prod, me, len, rcol + base, rval + base, x);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; q++) {
@@ -131,12 +135,12 @@ __device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod
         if (own[q]) w[a[q]] = (fa[q] - acc[q]) * ia[q];
 }
 
-template <class T>
+template <class T, int Q = kPlanQ, int E = kPlanE>
 __device__ __forceinline__ void tile_phase_s(const Tile& t, int nchunks, T* prod, const int64_t* __restrict__ sptr,
                                              const int32_t* __restrict__ srow, const T* __restrict__ sval,
                                              const int32_t* __restrict__ tcol, const T* __restrict__ w,
                                              T* __restrict__ x) {
-    constexpr int Q = kTileSegs / kTileThreads;      // columns owned per thread
+    constexpr int64_t C = (int64_t)kTileThreads * E;     // entries per chunk
     const int nseg = t.seg_end - t.seg_begin;
     const int me = threadIdx.x & (kTileThreads - 1);
     bool own[Q];
@@ -155,9 +159,9 @@ __device__ __forceinline__ void tile_phase_s(const Tile& t, int nchunks, T* prod
         acc[q] = T(0);
     }
     for (int c = 0; c < nchunks; c++) {
-        const int64_t base = t.ent_begin + (int64_t)c * kTileEntries;
-        const int len = (int)max<int64_t>(0, min<int64_t>(kTileEntries, t.ent_end - base));
-        stage_s(prod, me, len, srow + base, sval + base, w);
+        const int64_t base = t.ent_begin + (int64_t)c * C;
+        const int len = (int)max<int64_t>(0, min<int64_t>(C, t.ent_end - base));
+        stage_s<T, E>(prod, me, len, srow + base, sval + base, w);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Q; q++) {
