@@ -20,10 +20,10 @@
 // bounded: past the bound the kernel records an error and leaves, and the host
 // reports OBK_E_HIP.
 #include <algorithm>
-#include <cstdio>
-#include <cstdlib>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -338,6 +338,25 @@ struct obk_batch_s {
     bool busy = false;
     obk::DevArray<uint64_t> trace;       // per workgroup start/end (OBK_TRACE=1)
     int sub = 4;                         // tiles in flight per workgroup
+    // captured steps (one per tolerance); OBK_BATCH_EAGER=1 launches eagerly
+    struct StepGraph {
+        double tol = 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<StepGraph> graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graph = true;
+    obk_batch_s() = default;
+    obk_batch_s(const obk_batch_s&) = delete;
+    obk_batch_s& operator=(const obk_batch_s&) = delete;
+    ~obk_batch_s() {
+        for (auto& g : graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
 };
 
 namespace obk {
@@ -599,6 +618,10 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
             if (plans[t] == plans[s]) fail(OBK_E_ARG, "a plan appears twice in a batch");
     }
     B.fp32 = count > 0 && plans[0]->opts.precision == OBK_FP32_IR;
+    {
+        const char* e = std::getenv("OBK_BATCH_EAGER");
+        B.use_graph = !(e && e[0] && e[0] != '0');
+    }
     build_schedule(B);
     if (trace_enabled()) {
         B.trace.alloc(2 * (size_t)B.nwg);
@@ -632,9 +655,11 @@ void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s) {
 // One step for all enabled systems; relres/active (host, may be NULL) receive
 // each system's relative residual at the start of the step and whether the
 // step advanced it.
-void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s) {
+// The kernels of one step: residual, reduction (relative residual, sigma and
+// the active flags), right-hand side and correction reset (FP32 refinement),
+// the persistent sweep launch, and the update.
+static void enqueue_step(obk_batch_s& B, double tol, hipStream_t s) {
     const int count = (int)B.plans.size();
-    if (count == 0) return;
     if (B.n_resblocks)
         k_batch_resid<<<(unsigned)B.n_resblocks, kTileThreads, 0, s>>>((const ResSys*)B.sys_res.get(),
                                                                        (const Block*)B.resblocks.get(), B.psum.get(),
@@ -663,6 +688,40 @@ void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_
         launch_sweeps<double>(B, std::max(1, B.plans[0]->opts.check_every), s);
         ev_record(B, 1, s);
     }
+    OBK_HIP(hipGetLastError());
+}
+
+// The step's kernels captured once per tolerance into a graph on the batch's
+// own capture stream and replayed afterwards (no memset nodes: the flags the
+// kernels read are written by kernels or by host copies outside the graph).
+static hipGraphExec_t step_graph(obk_batch_s& B, double tol) {
+    for (auto& g : B.graphs)
+        if (g.tol == tol && g.exec) return g.exec;
+    if (!B.capture_stream) OBK_HIP(hipStreamCreateWithFlags(&B.capture_stream, hipStreamNonBlocking));
+    obk_batch_s::StepGraph sg;
+    sg.tol = tol;
+    OBK_HIP(hipStreamBeginCapture(B.capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_step(B, tol, B.capture_stream);
+    } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(B.capture_stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+    }
+    OBK_HIP(hipStreamEndCapture(B.capture_stream, &sg.graph));
+    OBK_HIP(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+    B.graphs.push_back(sg);
+    return sg.exec;
+}
+
+void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s) {
+    const int count = (int)B.plans.size();
+    if (count == 0) return;
+    if (B.use_graph && !B.trace.get())
+        OBK_HIP(hipGraphLaunch(step_graph(B, tol), s));
+    else
+        enqueue_step(B, tol, s);
     OBK_HIP(hipGetLastError());
     std::vector<double> rr(count);
     std::vector<uint8_t> act(count);

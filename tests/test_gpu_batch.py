@@ -100,6 +100,40 @@ def test_batch_step_enable_and_results():
         p.free()
 
 
+def test_batch_graph_replays_equal_eager_steps(monkeypatch):
+    """A step is replayed from a captured graph; every replay (with the host's
+    copies and checks in between) must equal the eagerly launched step."""
+    import torch
+    systems = _systems()[:5]
+    plans = [obk.plan_system(s, 0.1, precision=obk.FP32_IR) for s in systems]
+
+    def run(eager):
+        if eager:
+            monkeypatch.setenv("OBK_BATCH_EAGER", "1")
+        else:
+            monkeypatch.delenv("OBK_BATCH_EAGER", raising=False)
+        b = obk.Batch(plans)
+        b.begin()
+        hist = []
+        for _ in range(7):
+            rr, act = b.step(1e-10)
+            hist.append((rr.copy(), act.copy()))
+            torch.cuda.synchronize()
+        xs = [b.result(i) for i in range(len(plans))]
+        b.free()
+        return hist, xs
+
+    _say("[batch] graph vs eager steps")
+    h_graph, x_graph = run(False)
+    h_eager, x_eager = run(True)
+    for (r1, a1), (r2, a2) in zip(h_graph, h_eager):
+        assert np.array_equal(r1, r2) and np.array_equal(a1, a2)
+    for a, b in zip(x_graph, x_eager):
+        assert np.array_equal(a, b)
+    for p in plans:
+        p.free()
+
+
 def test_batch_tune_and_errors():
     systems = _systems()[:4]
     plans = [obk.plan_system(s, 0.1, precision=obk.FP32_IR) for s in systems]
