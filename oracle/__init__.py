@@ -244,6 +244,39 @@ def solve(pl: Plan, sweeps: int, x0: np.ndarray | None = None) -> np.ndarray:
     return unpermute(pl.p, sweep(pl, xt, sweeps))
 
 
+def pad_square(m, n, rp, ci, v, f):
+    """The extended square system of Section 4 for an m x n system.
+
+    m > n (Algorithm 5): A^ = [A, O] with an m x (m - n) zero block, f^ = f;
+    the unknowns become x^ = [x; x2] and x = x^(1:n).
+    m < n (Algorithm 6): A^ = [A; O] with an (n - m) x n zero block,
+    f^ = [f; 0]; x = x^.
+    A zero block adds no entries: [A, O] is the same CSR read as m x m, and
+    [A; O] appends n - m empty rows.  Returns (N, rp^, ci, v, f^), N = max(m, n)."""
+    rp = _c(rp, np.int64)
+    f = _c(f, np.float64)
+    N = max(int(m), int(n))
+    if m < N:
+        rp = np.concatenate([rp, np.full(N - m, rp[-1], dtype=np.int64)])
+        f = np.concatenate([f, np.zeros(N - m)])
+    return N, rp, _c(ci, np.int32), _c(v, np.float64), f
+
+
+def plan_rect(m, n, rp, ci, v, f, delta, **kw) -> Plan:
+    """Plan of the extended square system (Algorithms 5 and 6, first step)."""
+    N, rp2, ci2, v2, f2 = pad_square(m, n, rp, ci, v, f)
+    return plan(N, rp2, ci2, v2, f2, delta, **kw)
+
+
+def solve_rect(pl: Plan, n: int, sweeps: int, x0: np.ndarray | None = None) -> np.ndarray:
+    """Sweeps on the extended system from x^0 = [x0; 0] (x0 default 0); returns
+    x = x^(1:n) (Algorithm 5; for Algorithm 6 n = N and x = x^)."""
+    x0h = np.zeros(pl.n)
+    if x0 is not None:
+        x0h[:n] = x0
+    return solve(pl, sweeps, x0h)[:n]
+
+
 def refine(pl: Plan, inner: int, outer: int, tol: float, x0t: np.ndarray | None = None):
     """O11 iterative refinement schedule in FP64; returns (x~, steps, relres)."""
     x = np.zeros(pl.n) if x0t is None else np.array(x0t, dtype=np.float64, copy=True)

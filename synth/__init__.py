@@ -41,7 +41,7 @@ import scipy.sparse as sp
 __all__ = [
     "System", "seed_for", "random_rows", "stencil", "c1", "c2", "c3",
     "c4_sizes", "c4_system", "c5_sizes", "c5_system", "c5_arrivals",
-    "from_dense", "from_scipy",
+    "from_dense", "from_scipy", "RectSystem", "rect",
 ]
 
 
@@ -63,6 +63,27 @@ class System:
 
     def scipy(self) -> sp.csr_matrix:
         return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+@dataclasses.dataclass
+class RectSystem:
+    """A consistent m x n sparse system (m != n allowed) in CSR form."""
+    m: int
+    n: int
+    row_ptr: np.ndarray      # int64 [m+1]
+    col: np.ndarray          # int32 [nnz], values < n
+    val: np.ndarray          # float64 [nnz]
+    f: np.ndarray            # float64 [m]
+    x_star: np.ndarray       # float64 [n]
+    name: str = ""
+    seed: int = -1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.m, self.n))
 
 
 def seed_for(config: int, index: int = 0) -> int:
@@ -245,3 +266,26 @@ def c5_arrivals(count: int, rate_per_s: float) -> np.ndarray:
     """Poisson arrival times (seconds) at ``rate_per_s``, from seed 5000."""
     rng = np.random.Generator(np.random.PCG64(5000))
     return np.cumsum(rng.exponential(1.0 / rate_per_s, size=count))
+
+
+def rect(m: int, n: int, density: float, index: int = 0) -> RectSystem:
+    """Rectangular family of the non-square experiments (the row, column and
+    density figures of Tables 6 and 8): round(density * m * n) distinct
+    positions uniform over the m x n grid, N(0,1) values, x* ~ N(0,1),
+    f = A x*.  Seed 1000 * 6 + index; draw order: positions, values, x*."""
+    seed = seed_for(6, index)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nnz = int(round(density * m * n))
+    pos = np.sort(rng.choice(m * n, size=nnz, replace=False))
+    rows, cols = pos // n, pos % n
+    vals = rng.standard_normal(nnz)
+    x_star = rng.standard_normal(n)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    f = A @ x_star
+    return RectSystem(m=m, n=n, row_ptr=np.ascontiguousarray(A.indptr, dtype=np.int64),
+                      col=np.ascontiguousarray(A.indices, dtype=np.int32),
+                      val=np.ascontiguousarray(A.data, dtype=np.float64),
+                      f=np.ascontiguousarray(f, dtype=np.float64),
+                      x_star=np.ascontiguousarray(x_star, dtype=np.float64),
+                      name=f"rect-{m}x{n}-d{density}", seed=seed)

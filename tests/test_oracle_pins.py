@@ -486,3 +486,67 @@ def test_validate_rejects_bad_input():
     assert oracle.validate(2, rp, np.array([0, 1, 1], np.int32), np.array([1, np.nan, 1])) == -4
     assert oracle.validate(2, rp, np.array([0, 1, 1], np.int32), np.ones(3), np.array([1, np.inf])) == -4
     assert oracle.validate(2, np.array([0, 3, 2], np.int64), np.array([0, 1, 1], np.int32), np.ones(3)) == -2
+
+
+# ------------------------------------------------------------------ Section 4
+def test_pad_square_matches_dense_extension():
+    """Eqs. 4.1 and 4.3: [A, O] for m > n and [A; O] with f^ = [f; 0] for m < n,
+    checked against dense numpy blocks."""
+    import scipy.sparse as sp
+    for m, n in ((30, 20), (20, 30), (25, 25)):
+        s = synth.rect(m, n, 0.2, index=m)
+        A = s.scipy().toarray()
+        N, rp, ci, v, f = oracle.pad_square(m, n, s.row_ptr, s.col, s.val, s.f)
+        Ah = sp.csr_matrix((v, ci, rp), shape=(N, N)).toarray()
+        if m > n:
+            want, fw = np.hstack([A, np.zeros((m, m - n))]), s.f
+        elif m < n:
+            want, fw = np.vstack([A, np.zeros((n - m, n))]), np.concatenate([s.f, np.zeros(n - m)])
+        else:
+            want, fw = A, s.f
+        assert N == max(m, n)
+        assert np.array_equal(Ah, want) and np.array_equal(f, fw)
+
+
+def test_sobk_recovers_solution_and_leaves_extension_unknowns():
+    """Algorithm 5 on a consistent overdetermined system with full column rank
+    (the 200 x 150, density 0.2 size of Table 6): x^(1:n) -> x*, and the
+    extension unknowns x^(n+1:m), whose columns are zero, never move."""
+    s = synth.rect(200, 150, 0.2)
+    assert np.linalg.matrix_rank(s.scipy().toarray()) == 150
+    pl = oracle.plan_rect(s.m, s.n, s.row_ptr, s.col, s.val, s.f, 0.1)
+    xh = oracle.solve(pl, 400, np.zeros(pl.n))
+    assert np.array_equal(xh[s.n:], np.zeros(s.m - s.n))
+    x = oracle.solve_rect(pl, s.n, 400)
+    assert np.array_equal(x, xh[:s.n])
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) <= 1e-8
+
+
+def test_uobk_converges_to_minimum_norm_solution():
+    """Algorithm 6 on a consistent underdetermined system (the 500 x 2000,
+    density 0.002 size of Table 8): from x0 = 0 the iterate stays in the row
+    space, so it converges to the minimum-norm solution pinv(A) f (Theorem 1),
+    not to the generating x*."""
+    s = synth.rect(500, 2000, 0.002)
+    A = s.scipy().toarray()
+    x_mn = np.linalg.pinv(A) @ s.f
+    pl = oracle.plan_rect(s.m, s.n, s.row_ptr, s.col, s.val, s.f, 0.1)
+    x = oracle.solve_rect(pl, s.n, 2000)
+    assert np.linalg.norm(x - x_mn) / np.linalg.norm(x_mn) <= 1e-10
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) > 0.1
+
+
+def test_extension_rows_are_zero_rows():
+    """The n - m appended rows of [A; O] have no entries: they join no group
+    (zero rows, Q15) and their right-hand side is 0, so the system stays
+    consistent."""
+    s = synth.rect(300, 700, 0.01)
+    pl = oracle.plan_rect(s.m, s.n, s.row_ptr, s.col, s.val, s.f, 0.1)
+    new_of_old = np.empty(pl.n, dtype=np.int64)
+    new_of_old[pl.p] = np.arange(pl.n)
+    ext = new_of_old[s.m:]                          # reordered positions of appended rows
+    assert np.all(pl.group[ext] == -1)
+    assert np.all(pl.f[ext] == 0.0)
+    lens = np.diff(s.row_ptr)
+    real = new_of_old[:s.m][lens > 0]
+    assert np.all(pl.group[real] >= 0)
