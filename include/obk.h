@@ -4,7 +4,8 @@
  * Algorithm via RCM Reordering and Dynamic Grouping for Sparse Linear
  * Systems").
  *
- * The library solves the square sparse system A x = f (eq. 1.1) as follows:
+ * The library solves the sparse system A x = f (eq. 1.1) as follows (an
+ * m x n system with m != n through its extended square system, Section 4):
  *   obk_plan   RCM reordering A~ = P A P^T, f~ = P f (Section 3.2, eqs.
  *              3.1-3.2), squared row norms (denominator of eq. 1.2), the row
  *              cosine table thresholded at delta (Section 3.3, one-row blocks)
@@ -20,7 +21,11 @@
  * Conventions shared by every entry point:
  *  - CSR: int64 row_ptr[n+1] (row_ptr[0] = 0), int32 col[nnz], double
  *    val[nnz].  Rows may be unsorted; a repeated (row, col) is an error;
- *    explicit zeros are kept as structure.  Only square matrices are accepted.
+ *    explicit zeros are kept as structure.  A non-square m x n matrix is
+ *    solved as the extended N x N system, N = max(m, n) (Section 4): for
+ *    m > n, [A, O] with f unchanged and x = x^(1:n) (Algorithm 5); for
+ *    m < n, [A; O] with f^ = [f; 0] and x = x^ (Algorithm 6).  x0 and x
+ *    always hold the caller's n unknowns; the extension unknowns start at 0.
  *  - Memory spaces: obk_csr.on_device says whether the CSR arrays and f are
  *    host or device pointers.  x0 and x of obk_solve live in the same space
  *    as the CSR given to obk_plan.  The caller owns every pointer it passes;
@@ -59,7 +64,7 @@ typedef enum {
     OBK_OK = 0,
     OBK_E_ARG = -1,         /* bad argument (null pointer, negative size, bad option) */
     OBK_E_CSR = -2,         /* malformed CSR: row_ptr not monotone, column out of range, duplicate */
-    OBK_E_NOT_SQUARE = -3,  /* n_rows != n_cols */
+    OBK_E_NOT_SQUARE = -3,  /* reserved (non-square systems are extended, Section 4) */
     OBK_E_NONFINITE = -4,   /* NaN or Inf in val or f */
     OBK_E_NOMEM = -5,       /* device or host allocation failed, or over opts.hbm_budget */
     OBK_E_HIP = -6,         /* a HIP runtime call failed */
@@ -120,9 +125,13 @@ OBK_API obk_status obk_opts_default(obk_opts *opts);
  * near-orthogonal iff |cos(a_i, a_j)| < delta (|cos| = |a_i . a_j| /
  * sqrt(||a_i||^2 ||a_j||^2), computed in FP64 with sums in ascending column
  * order).  opts may be NULL (defaults).  On success *out receives a plan that
- * owns device copies of the reordered, grouped system.
- * Errors: OBK_E_ARG, OBK_E_NOT_SQUARE, OBK_E_CSR, OBK_E_NONFINITE,
- * OBK_E_NOMEM, OBK_E_HIP, OBK_E_INCONSISTENT.
+ * owns device copies of the reordered, grouped system.  For n_rows != n_cols
+ * the plan is that of the extended square system of size max(n_rows,
+ * n_cols) (Section 4, Algorithms 5 and 6): row_ptr and f hold n_rows (+1)
+ * entries, columns must be below n_cols, and the introspection calls below
+ * (perm, groups, stats) describe the extended system.
+ * Errors: OBK_E_ARG, OBK_E_CSR, OBK_E_NONFINITE, OBK_E_NOMEM, OBK_E_HIP,
+ * OBK_E_INCONSISTENT.
  */
 OBK_API obk_status obk_plan(const obk_csr *A, const double *f, double delta, const obk_opts *opts,
                     obk_stream_t stream, obk_plan_t *out);

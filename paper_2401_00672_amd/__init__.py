@@ -157,10 +157,12 @@ def _stream(stream) -> int | None:
 class Plan:
     """A device-resident OBK-RCM plan (reordered, grouped system + workspace)."""
 
-    def __init__(self, handle: int, n: int, nnz: int, on_device: bool, opts: dict | None = None):
+    def __init__(self, handle: int, n: int, nnz: int, on_device: bool, opts: dict | None = None,
+                 n_ext: int | None = None):
         self._opts = dict(opts or {})
         self._h = handle
-        self.n = n
+        self.n = n                                  # unknowns of the caller's system
+        self.n_ext = n if n_ext is None else n_ext  # size of the (extended) square system
         self.nnz = nnz
         self.on_device = on_device
 
@@ -240,12 +242,12 @@ class Plan:
 
     # -- introspection
     def perm(self) -> np.ndarray:
-        p = np.empty(self.n, dtype=np.int32)
+        p = np.empty(self.n_ext, dtype=np.int32)
         _check(lib().obk_plan_perm(self.handle, p.ctypes.data))
         return p
 
     def groups(self):
-        g = np.empty(self.n, dtype=np.int32)
+        g = np.empty(self.n_ext, dtype=np.int32)
         ng = ctypes.c_int32(0)
         _check(lib().obk_plan_groups(self.handle, g.ctypes.data, ctypes.byref(ng)))
         return g, int(ng.value)
@@ -286,8 +288,8 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
         ptrs = (rp.ctypes.data, ci.ctypes.data if nnz else None, v.ctypes.data if nnz else None,
                 ff.ctypes.data)
         st = _stream(stream)
-    csr = _Csr(nrows, nrows if n_cols is None else int(n_cols), nnz, ptrs[0], ptrs[1], ptrs[2],
-               1 if on_device else 0)
+    ncols = nrows if n_cols is None else int(n_cols)
+    csr = _Csr(nrows, ncols, nnz, ptrs[0], ptrs[1], ptrs[2], 1 if on_device else 0)
     opts = _Opts()
     lib().obk_opts_default(ctypes.byref(opts))
     opts.use_rcm = 1 if use_rcm else 0
@@ -299,8 +301,9 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     h = _P()
     _check(lib().obk_plan(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
     del keep
-    return Plan(h.value, nrows, nnz, on_device,
-                {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every)})
+    return Plan(h.value, ncols, nnz, on_device,
+                {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every)},
+                n_ext=max(nrows, ncols))
 
 
 def rcm_host(gptr, gadj) -> np.ndarray:
@@ -328,7 +331,9 @@ def first_fit_host(cptr, cidx, active):
 
 
 def plan_system(s, delta: float, **kw) -> Plan:
-    """obk_plan on a ``synth.System`` (host arrays)."""
+    """obk_plan on a ``synth.System`` or ``synth.RectSystem`` (host arrays)."""
+    if hasattr(s, "m"):
+        return plan(s.row_ptr, s.col, s.val, s.f, delta, n=s.m, n_cols=s.n, **kw)
     return plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)
 
 

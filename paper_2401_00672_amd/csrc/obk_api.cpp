@@ -98,10 +98,10 @@ obk_status obk_plan(const obk_csr* A, const double* f, double delta, const obk_o
     obk_plan_s* P = nullptr;
     obk_status st = guarded([&] {
         if (!A || !out) obk::fail(OBK_E_ARG, "A and out must not be NULL");
-        if (A->n_rows != A->n_cols) obk::fail(OBK_E_NOT_SQUARE, "the method needs a square matrix");
-        if (A->n_rows < 0 || A->nnz < 0) obk::fail(OBK_E_ARG, "negative size");
-        if (A->n_rows >= std::numeric_limits<int32_t>::max() || A->nnz >= std::numeric_limits<int32_t>::max())
-            obk::fail(OBK_E_ARG, "n and nnz must be below 2^31 - 1");
+        if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) obk::fail(OBK_E_ARG, "negative size");
+        if (std::max(A->n_rows, A->n_cols) >= std::numeric_limits<int32_t>::max() ||
+            A->nnz >= std::numeric_limits<int32_t>::max())
+            obk::fail(OBK_E_ARG, "n_rows, n_cols and nnz must be below 2^31 - 1");
         if (A->n_rows > 0 && (!A->row_ptr || !f)) obk::fail(OBK_E_ARG, "row_ptr and f must not be NULL");
         if (A->nnz > 0 && (!A->col || !A->val)) obk::fail(OBK_E_ARG, "col and val must not be NULL");
         if (!(delta > 0.0) || !std::isfinite(delta)) obk::fail(OBK_E_ARG, "delta must be finite and > 0");

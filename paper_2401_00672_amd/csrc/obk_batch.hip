@@ -250,16 +250,32 @@ __global__ void k_batch_cols(const ResSys* __restrict__ sys, const Block* __rest
     else S.d[c] = 0.0f;
 }
 
-__global__ void k_batch_permute_in(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ x0,
-                                   double* __restrict__ xt) {
+// x~ = P [x0; 0] over the extended system (n entries; x0 holds the caller's
+// n_in unknowns, may be null: 0)
+__global__ void k_batch_permute_in(int64_t n, int64_t n_in, const int32_t* __restrict__ p,
+                                   const double* __restrict__ x0, double* __restrict__ xt) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) xt[t] = x0 ? x0[p[t]] : 0.0;
+    const bool have = (x0 != nullptr) & (n_in > 0);     // uniform
+    if (t < n) {
+        const int32_t pt = p[t];
+        const bool mine = pt < n_in;
+        double val = 0.0;
+        if (have) {
+            const double g = x0[mine ? pt : 0];
+            val = mine ? g : 0.0;
+        }
+        xt[t] = val;
+    }
 }
 
-__global__ void k_batch_permute_out(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ xt,
-                                    double* __restrict__ x) {
+// x = (P^T x~)(1 : n_in)
+__global__ void k_batch_permute_out(int64_t n, int64_t n_in, const int32_t* __restrict__ p,
+                                    const double* __restrict__ xt, double* __restrict__ x) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) x[p[t]] = xt[t];
+    if (t < n) {
+        const int32_t pt = p[t];
+        if (pt < n_in) x[pt] = xt[t];
+    }
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
@@ -634,11 +650,11 @@ static void start_one(obk_plan_s& P, const double* x0, hipStream_t s) {
     const double* src = x0;
     DevArray<double> tmp;
     if (src && !P.input_on_device) {
-        tmp.alloc(P.n);
-        OBK_HIP(hipMemcpyAsync(tmp.get(), src, P.n * sizeof(double), hipMemcpyHostToDevice, s));
+        tmp.alloc(P.n_in);
+        OBK_HIP(hipMemcpyAsync(tmp.get(), src, P.n_in * sizeof(double), hipMemcpyHostToDevice, s));
         src = tmp.get();
     }
-    k_batch_permute_in<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), src, P.x.get());
+    k_batch_permute_in<<<nblk(P.n), 256, 0, s>>>(P.n, P.n_in, P.perm.get(), src, P.x.get());
     OBK_HIP(hipGetLastError());
     if (tmp.get()) OBK_HIP(hipStreamSynchronize(s));
 }
@@ -742,10 +758,10 @@ void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s) {
     obk_plan_s& P = *B.plans[index];
     DevArray<double> tmp;
     double* dst = x;
-    if (!P.input_on_device) { tmp.alloc(P.n); dst = tmp.get(); }
-    k_batch_permute_out<<<nblk(P.n), 256, 0, s>>>(P.n, P.perm.get(), P.x.get(), dst);
+    if (!P.input_on_device) { tmp.alloc(P.n_in); dst = tmp.get(); }
+    k_batch_permute_out<<<nblk(P.n), 256, 0, s>>>(P.n, P.n_in, P.perm.get(), P.x.get(), dst);
     OBK_HIP(hipGetLastError());
-    if (!P.input_on_device) OBK_HIP(hipMemcpyAsync(x, tmp.get(), P.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!P.input_on_device) OBK_HIP(hipMemcpyAsync(x, tmp.get(), P.n_in * sizeof(double), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
 }
 

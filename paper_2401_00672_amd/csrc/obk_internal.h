@@ -126,7 +126,8 @@ void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Til
 // --------------------------------------------------------------- the plan
 struct obk_plan_s {
     int device = 0;
-    int64_t n = 0, nnz = 0;
+    int64_t n = 0, nnz = 0;      // n: size of the (extended) square system
+    int64_t n_in = 0, m_in = 0;  // unknowns and equations of the caller's system
     int64_t m = 0;              // rows that take part in a group (nonzero rows)
     int32_t ngroups = 0;
     int64_t bandwidth = 0;

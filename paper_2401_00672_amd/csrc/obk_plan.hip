@@ -31,8 +31,19 @@ __global__ void k_iota_u32(int64_t n, uint32_t* __restrict__ out) {
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
 // ---------------------------------------------------------------- ingest
-__global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           const double* __restrict__ v, const double* __restrict__ f, int* flags) {
+// rows nr..n-1 of the extended system: empty, right-hand side 0
+__global__ void k_extend_rows(int64_t nr, int64_t n, int64_t* __restrict__ rp, double* __restrict__ f) {
+    const int64_t i = nr + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        rp[i + 1] = rp[nr];
+        f[i] = 0.0;
+    }
+}
+
+// n: rows of the (extended) square system; ncols: columns of the caller's matrix
+__global__ void k_validate(int64_t n, int64_t ncols, int64_t nnz, const int64_t* __restrict__ rp,
+                           const int32_t* __restrict__ ci, const double* __restrict__ v,
+                           const double* __restrict__ f, int* flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
     if (i <= n) {
@@ -42,7 +53,7 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ r
         if (i < n && !isfinite(f[i])) bad |= BAD_F;
     }
     if (i < nnz) {
-        if (ci[i] < 0 || (int64_t)ci[i] >= n) bad |= BAD_COL;
+        if (ci[i] < 0 || (int64_t)ci[i] >= ncols) bad |= BAD_COL;
         if (!isfinite(v[i])) bad |= BAD_VAL;
     }
     if (bad) atomicOr(flags, bad);
@@ -449,22 +460,37 @@ struct PlanTrace {
 };
 
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s) {
-    const int64_t n = A.n_rows, nnz = A.nnz;
+    // an m x n system with m != n is solved as its extended square system
+    // (Section 4): [A, O] for m > n, [A; O] with f^ = [f; 0] for m < n
+    const int64_t nr = A.n_rows, nc = A.n_cols, nnz = A.nnz;
+    const int64_t n = std::max(nr, nc);
     const bool dev = A.on_device != 0;
-    P.n = n; P.nnz = nnz; P.delta = delta; P.input_on_device = dev;
+    P.n = n; P.n_in = nc; P.m_in = nr; P.nnz = nnz; P.delta = delta; P.input_on_device = dev;
     OBK_HIP(hipGetDevice(&P.device));
     AllocScope pool(s);
     PlanTrace tr(s);
 
     // ---- a1: ingest and validate (square checked by the caller)
     DevArray<int64_t> rp; DevArray<int32_t> ci; DevArray<double> v, fd;
-    copy_in(rp, A.row_ptr, n + 1, dev, s);
+    rp.alloc(n + 1);
+    fd.alloc(n);
+    if (dev) {
+        OBK_HIP(hipMemcpyAsync(rp.get(), A.row_ptr, (nr + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+        if (nr) OBK_HIP(hipMemcpyAsync(fd.get(), f, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        h2d(rp.get(), A.row_ptr, nr + 1, s);
+        if (nr) h2d(fd.get(), f, nr, s);
+    }
+    if (n > nr) {   // appended empty rows with a zero right-hand side
+        k_extend_rows<<<nblk(n - nr), kT, 0, s>>>(nr, n, rp.get(), fd.get());
+        OBK_HIP(hipGetLastError());
+    }
     copy_in(ci, A.col, nnz, dev, s);
     copy_in(v, A.val, nnz, dev, s);
-    copy_in(fd, f, n, dev, s);
     DevArray<int> flags; flags.alloc(1);
     OBK_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
-    k_validate<<<nblk(std::max(n + 1, nnz)), kT, 0, s>>>(n, nnz, rp.get(), ci.get(), v.get(), fd.get(), flags.get());
+    k_validate<<<nblk(std::max(n + 1, nnz)), kT, 0, s>>>(n, nc, nnz, rp.get(), ci.get(), v.get(), fd.get(),
+                                                          flags.get());
     OBK_HIP(hipGetLastError());
     int hflags = to_host(flags.get(), 1, s)[0];
     if (hflags & BAD_ROWPTR) fail(OBK_E_CSR, "row_ptr is not a monotone offset array from 0 to nnz");

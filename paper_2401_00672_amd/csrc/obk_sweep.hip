@@ -29,16 +29,32 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-__global__ void k_permute_in(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ x0,
+// x~ = P x^0 over the extended system of size n, where x^0 = [x0; 0] and x0
+// (may be null: 0) holds the caller's n_in unknowns
+__global__ void k_permute_in(int64_t n, int64_t n_in, const int32_t* __restrict__ p, const double* __restrict__ x0,
                              double* __restrict__ xt) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) xt[t] = x0 ? x0[p[t]] : 0.0;
+    const bool have = (x0 != nullptr) & (n_in > 0);     // uniform
+    if (t < n) {
+        const int32_t pt = p[t];
+        const bool mine = pt < n_in;
+        double val = 0.0;
+        if (have) {
+            const double g = x0[mine ? pt : 0];
+            val = mine ? g : 0.0;
+        }
+        xt[t] = val;
+    }
 }
 
-__global__ void k_permute_out(int64_t n, const int32_t* __restrict__ p, const double* __restrict__ xt,
-                              double* __restrict__ x) {
+// x = (P^T x~)(1 : n_in): the caller's unknowns of the extended solution
+__global__ void k_permute_out(int64_t n, int64_t n_in, const int32_t* __restrict__ p,
+                              const double* __restrict__ xt, double* __restrict__ x) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) x[p[t]] = xt[t];
+    if (t < n) {
+        const int32_t pt = p[t];
+        if (pt < n_in) x[pt] = xt[t];
+    }
 }
 
 // ordered reduction of the per-tile partials by one block (deterministic; the
@@ -283,12 +299,12 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
     if (x0) {
         if (dev) x0dev = x0;
         else {
-            x0d.alloc(n);
-            OBK_HIP(hipMemcpyAsync(x0d.get(), x0, n * sizeof(double), hipMemcpyHostToDevice, s));
+            x0d.alloc(P.n_in);
+            OBK_HIP(hipMemcpyAsync(x0d.get(), x0, P.n_in * sizeof(double), hipMemcpyHostToDevice, s));
             x0dev = x0d.get();
         }
     }
-    k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), x0dev, P.x.get());
+    k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.n_in, P.perm.get(), x0dev, P.x.get());
     OBK_HIP(hipGetLastError());
     bool nf = false;
     inf.relres0 = relres(P, P.x.get(), s, &nf);
@@ -314,10 +330,10 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
     inf.sweeps = done;
     // x = P^T x~ (Algorithm 4, last step)
     double* xout = x;
-    if (!dev) { xd.alloc(n); xout = xd.get(); }
-    k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), P.x.get(), xout);
+    if (!dev) { xd.alloc(P.n_in); xout = xd.get(); }
+    k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.n_in, P.perm.get(), P.x.get(), xout);
     OBK_HIP(hipGetLastError());
-    if (!dev) OBK_HIP(hipMemcpyAsync(x, xd.get(), n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev) OBK_HIP(hipMemcpyAsync(x, xd.get(), P.n_in * sizeof(double), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
@@ -338,12 +354,12 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     if (x0) {
         if (dev) x0dev = x0;
         else {
-            x0d.alloc(n);
-            OBK_HIP(hipMemcpyAsync(x0d.get(), x0, n * sizeof(double), hipMemcpyHostToDevice, s));
+            x0d.alloc(P.n_in);
+            OBK_HIP(hipMemcpyAsync(x0d.get(), x0, P.n_in * sizeof(double), hipMemcpyHostToDevice, s));
             x0dev = x0d.get();
         }
     }
-    k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), x0dev, P.x.get());
+    k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.n_in, P.perm.get(), x0dev, P.x.get());
     OBK_HIP(hipGetLastError());
     auto residual = [&](double* rho, double* sigma, bool* nonfinite) {
         double r2 = 0, mx = 0;
@@ -379,10 +395,10 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     }
     if (inf.status == OBK_MAXIT && sigma == 0.0) inf.status = OBK_CONVERGED;
     double* xout = x;
-    if (!dev) { xd.alloc(n); xout = xd.get(); }
-    k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.perm.get(), P.x.get(), xout);
+    if (!dev) { xd.alloc(P.n_in); xout = xd.get(); }
+    k_permute_out<<<nblk(n), 256, 0, s>>>(n, P.n_in, P.perm.get(), P.x.get(), xout);
     OBK_HIP(hipGetLastError());
-    if (!dev) OBK_HIP(hipMemcpyAsync(x, xd.get(), n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev) OBK_HIP(hipMemcpyAsync(x, xd.get(), P.n_in * sizeof(double), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;

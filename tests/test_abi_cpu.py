@@ -40,7 +40,7 @@ def test_opts_default_and_free_null():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n_cols=5), -3),               # not square (Section 4: the method needs m = n)
+    (dict(n_cols=-1), -1),              # negative size
     (dict(delta=0.0), -1),              # delta must be > 0
     (dict(delta=float("nan")), -1),
     (dict(precision=7), -1),

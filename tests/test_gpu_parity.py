@@ -258,3 +258,60 @@ def test_fp32_refinement_reaches_1e10(name, maker):
     # dominant systems the error is within a small multiple of that
     assert err_oracle <= 1e-8
     assert err_star <= 1e-8
+
+
+# ------------------------------------------------- non-square (Section 4)
+RECT_CASES = [
+    ("sobk-200x150-d0.2", lambda: synth.rect(200, 150, 0.2), 200),
+    ("uobk-500x2000-d0.002", lambda: synth.rect(500, 2000, 0.002), 200),
+    ("sobk-20000x12000-d1e-4", lambda: synth.rect(20000, 12000, 0.0001), 60),
+    ("uobk-15000x20000-d8e-5", lambda: synth.rect(15000, 20000, 0.00008), 60),
+]
+
+
+@pytest.mark.parametrize("name,maker,K", RECT_CASES, ids=[c[0] for c in RECT_CASES])
+def test_nonsquare_plan_and_sweeps_match_oracle(name, maker, K):
+    """Algorithms 5 and 6: the plan of the extended square system is bit-exact
+    (permutation, groups) and x = x^(1:n) after K FP64 sweeps is within 1e-10
+    of the oracle's (sizes and densities of Tables 6 and 8)."""
+    s = maker()
+    _say(f"[parity] {name}: m={s.m} n={s.n} nnz={s.nnz}")
+    pl_o = oracle.plan_rect(s.m, s.n, s.row_ptr, s.col, s.val, s.f, 0.1)
+    with obk.plan_system(s, 0.1) as P:
+        assert np.array_equal(P.perm(), pl_o.p)
+        g, ng = P.groups()
+        assert ng == pl_o.ngroups and np.array_equal(g, pl_o.group)
+        x, info = P.solve(maxit=K)
+    xo = oracle.solve_rect(pl_o, s.n, K)
+    assert x.shape == (s.n,)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _say(f"[parity] {name}: relerr={rel:.3e} bitwise={np.array_equal(x, xo)}")
+    assert rel <= TOL_X
+
+
+def test_nonsquare_fp32_refinement_and_batch():
+    """FP32 sweeps + FP64 refinement reach 1e-10 on both extensions (x* for the
+    full-column-rank overdetermined system, the minimum-norm solution for the
+    underdetermined one), and a batch mixing them with a square system equals
+    the single solves bit for bit."""
+    systems = [synth.rect(200, 150, 0.2), synth.rect(500, 2000, 0.002), synth.c1(n=3000, companion=True)]
+    _say("[parity] non-square fp32 refinement + batch")
+    plans = [obk.plan_system(s, 0.1, precision=obk.FP32_IR) for s in systems]
+    singles = [p.solve(maxit=200, tol=1e-10) for p in plans]
+    for s, (x, info) in zip(systems, singles):
+        assert info.status == "converged", info
+        assert np.linalg.norm(s.f - s.scipy() @ x) / np.linalg.norm(s.f) <= 1.5e-10
+    # underdetermined: from x0 = 0 every correction is a combination of rows,
+    # so the iterate stays in the row space of A, where the minimum-norm
+    # solution is the only solution.  FP32 corrections are rounded component
+    # by component, which leaves a null-space part of FP32 size that A cannot
+    # see (the FP64 path keeps it at rounding level; see the parity cases)
+    A = systems[1].scipy().toarray()
+    xu = singles[1][0]
+    assert np.linalg.norm(xu - np.linalg.pinv(A) @ (A @ xu)) / np.linalg.norm(xu) <= 1e-6
+    assert np.linalg.norm(singles[0][0] - systems[0].x_star) / np.linalg.norm(systems[0].x_star) <= 1e-8
+    xs, infos = obk.solve_batch(plans, tol=1e-10, maxit=200)
+    for (x1, i1), x2, i2 in zip(singles, xs, infos):
+        assert x2.shape == x1.shape and np.array_equal(x1, x2) and i1.outer_steps == i2.outer_steps
+    for p in plans:
+        p.free()
