@@ -36,7 +36,7 @@ def _kernel_source_sha() -> str:
     """Hash of the sweep kernel sources: counter figures recorded for an older
     kernel are not reported."""
     h = hashlib.sha256()
-    for f in ("obk_sweep_tiles.h", "obk_internal.h"):
+    for f in ("obk_sweep_tiles.h", "obk_tile.h"):
         with open(os.path.join(ROOT, "paper_2401_00672_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/obk.h"
+#include "obk_tile.h"
 
 namespace obk {
 
@@ -106,16 +107,6 @@ int32_t host_first_fit(int64_t n, const int64_t* cptr, const int32_t* cidx, cons
                        int32_t* colour);
 
 // --------------------------------------------------------- sweep schedule
-// A tile is a contiguous range of "segments" (rows of a group in phase R,
-// touched columns of a group in phase S) whose entries are reduced by one
-// workgroup.  seg_begin/seg_end index segments, ent_begin/ent_end entries.
-struct Tile {
-    int32_t seg_begin, seg_end;
-    int64_t ent_begin, ent_end;
-};
-constexpr int kTileThreads = 256;        // threads per tile (one sub-block)
-constexpr int kTileSegs = 256;           // rows (columns) per tile, 1 per thread
-constexpr int kTileEntries = 2048;       // entries staged per chunk (8 per thread)
 // Split segments [0, nseg) with offsets off[nseg+1] into tiles of at most
 // kTileSegs segments and (unless a single segment is longer) at most
 // kTileEntries entries.
