@@ -132,6 +132,13 @@ void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm
             cm[tail++] = s;
         }
         int32_t v = cm[head++];
+        // the queue ahead is known: start fetching the adjacency of a vertex
+        // a few places further on while this one is expanded
+        if (head + 4 < tail) {
+            const int32_t ahead = cm[head + 4];
+            __builtin_prefetch(gadj + gptr[ahead]);
+            __builtin_prefetch(&gptr[cm[head + 8 < tail ? head + 8 : head + 4]]);
+        }
         fresh.clear();
         for (int64_t k = gptr[v]; k < gptr[v + 1]; k++) {
             int32_t u = gadj[k];
