@@ -23,6 +23,19 @@ inline unsigned nblk(int64_t n, int t = kT) { return (unsigned)std::max<int64_t>
 enum : int { BAD_ROWPTR = 1, BAD_COL = 2, BAD_VAL = 4, BAD_F = 8, DUPLICATE = 16 };
 
 // ------------------------------------------------------------- small helpers
+// cptr[i] = ccount[trp[i]] (exclusive count of conflicts before row i's first
+// entry), nconf when row i starts past the last entry (empty trailing rows)
+__global__ void k_row_conflict_ptr(int64_t n, int64_t nnz, int64_t nconf, const int64_t* __restrict__ trp,
+                                   const int64_t* __restrict__ ccount, int64_t* __restrict__ cptr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) {
+        const int64_t k = trp[i];
+        const bool in = k < nnz;
+        const int64_t c = ccount[in ? k : 0];
+        cptr[i] = in ? c : nconf;
+    }
+}
+
 __global__ void k_iota_u32(int64_t n, uint32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (uint32_t)i;
@@ -632,15 +645,14 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
 
     tr.mark("conflicts");
     // ---- a6: first-fit grouping on the host
-    std::vector<int64_t> htrp = to_host(trp.get(), n + 1, s);
-    std::vector<int64_t> hcc = to_host(ccount.get(), nnz, s);
+    // conflict offsets per row: the exclusive count at the row's first entry
+    // (conflicts are emitted in entry order), nconf past the last entry
+    DevArray<int64_t> cptr_rows; cptr_rows.alloc(n + 1);
+    k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), cptr_rows.get());
+    OBK_HIP(hipGetLastError());
+    std::vector<int64_t> hcptr = to_host(cptr_rows.get(), n + 1, s);
     std::vector<int32_t> hcidx = to_host(cidx.get(), nconf, s);
     std::vector<double> hnu = to_host(nu.get(), n, s);
-    std::vector<int64_t> hcptr(n + 1);
-    for (int64_t i = 0; i < n; i++) hcptr[i] = (htrp[i] < nnz) ? hcc[htrp[i]] : nconf;
-    hcptr[n] = nconf;
-    // rows with no entries start where the next row starts
-    for (int64_t i = n - 1; i >= 0; i--) if (htrp[i] == htrp[i + 1]) hcptr[i] = hcptr[i + 1];
     std::vector<uint8_t> active(n);
     for (int64_t i = 0; i < n; i++) active[i] = hnu[i] != 0.0;
     std::vector<int32_t> group(n);
