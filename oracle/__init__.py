@@ -12,6 +12,7 @@ import dataclasses
 import os
 
 import numpy as np
+import scipy.sparse as sp
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -285,3 +286,96 @@ def refine(pl: Plan, inner: int, outer: int, tol: float, x0t: np.ndarray | None 
                              _ptr(pl.group), pl.ngroups, _ptr(x), int(inner), int(outer), float(tol),
                              ctypes.byref(rho))
     return x, int(steps), float(rho.value)
+
+
+# ------------------------------------------------- block mode (Algorithm 4)
+@dataclasses.dataclass
+class BlockPlan:
+    """Paper-literal block form of Algorithm 4 (k uniform row blocks)."""
+    n: int
+    p: np.ndarray          # RCM permutation, new -> old
+    rp: np.ndarray         # reordered CSR
+    ci: np.ndarray
+    v: np.ndarray
+    f: np.ndarray
+    bptr: np.ndarray       # block row ranges, k + 1
+    cos: np.ndarray        # k x k table of |cos| between block centroids
+    pairs: list            # Oclass: (tau1, tau2) in the order formed
+    nclass: list           # Nclass: blocks left unpaired, ascending
+
+
+def block_ranges(m: int, k: int) -> np.ndarray:
+    """Uniform chunking in order (Section 3.3): the first k - 1 blocks take
+    floor(m / k) rows each, the k-th block the rest."""
+    if k < 1 or k > max(m, 1):
+        raise ValueError("need 1 <= k <= m")
+    size = m // k
+    b = np.arange(k + 1, dtype=np.int64) * size
+    b[k] = m
+    return b
+
+
+def block_plan(n, rp, ci, v, f, k, thr) -> BlockPlan:
+    """Algorithm 4, steps 1-4 in block form: RCM, uniform chunking, the cosine
+    table of the block centroids, and the pairing of Section 3.3 (each block
+    not yet in a class takes the first later block not yet in a class whose
+    centroid is near-orthogonal to its own, |cos| < thr; blocks left over form
+    Nclass)."""
+    if validate(n, rp, ci, v, f) != 0:
+        raise ValueError("invalid system")
+    p = rcm(n, rp, ci)
+    trp, tci, tv, tf = permute(n, rp, ci, v, f, p)
+    bptr = block_ranges(n, k)
+    A = sp.csr_matrix((tv, tci, trp), shape=(n, n))
+    cen = np.zeros((k, n))
+    for b in range(k):
+        # the centroid is the mean row of the block (its scale does not enter the cosine)
+        cen[b] = np.asarray(A[bptr[b]:bptr[b + 1]].sum(axis=0)).ravel() / max(bptr[b + 1] - bptr[b], 1)
+    nrm = np.sqrt(np.einsum("ij,ij->i", cen, cen))
+    G = cen @ cen.T
+    cos = np.zeros((k, k))
+    for i in range(k):
+        for j in range(k):
+            if nrm[i] > 0 and nrm[j] > 0:
+                cos[i, j] = abs(G[i, j]) / (nrm[i] * nrm[j])
+    taken = [False] * k
+    pairs = []
+    for i in range(k):
+        if taken[i]:
+            continue
+        for j in range(i + 1, k):
+            if not taken[j] and cos[i, j] < thr:
+                pairs.append((i, j))
+                taken[i] = taken[j] = True
+                break
+    nclass = [i for i in range(k) if not taken[i]]
+    return BlockPlan(n, p, trp, tci, tv, tf, bptr, cos, pairs, nclass)
+
+
+def block_project(bp: BlockPlan, tau: int, x: np.ndarray) -> np.ndarray:
+    """Eq. 1.3 / 3.3: x + pinv(A_tau) (f_tau - A_tau x), with the dense
+    pseudo-inverse of the block."""
+    r0, r1 = int(bp.bptr[tau]), int(bp.bptr[tau + 1])
+    A = sp.csr_matrix((bp.v, bp.ci, bp.rp), shape=(bp.n, bp.n))[r0:r1].toarray()
+    return x + np.linalg.pinv(A) @ (bp.f[r0:r1] - A @ x)
+
+
+def block_sweep(bp: BlockPlan, xt: np.ndarray, sweeps: int) -> np.ndarray:
+    """Sweeps of the block iteration in reordered coordinates: each Oclass
+    pair projected in turn (tau1 then tau2, the two half steps of Algorithm 4),
+    then every Nclass block, in the order formed (deterministic reading of the
+    selection steps)."""
+    x = np.array(xt, dtype=np.float64, copy=True)
+    for _ in range(int(sweeps)):
+        for t1, t2 in bp.pairs:
+            x = block_project(bp, t1, x)
+            x = block_project(bp, t2, x)
+        for t in bp.nclass:
+            x = block_project(bp, t, x)
+    return x
+
+
+def block_solve(bp: BlockPlan, sweeps: int, x0: np.ndarray | None = None) -> np.ndarray:
+    """Block plan + sweeps from x0 (default 0), original ordering."""
+    xt = np.zeros(bp.n) if x0 is None else permute_vec(bp.p, x0)
+    return unpermute(bp.p, block_sweep(bp, xt, sweeps))

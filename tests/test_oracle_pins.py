@@ -550,3 +550,83 @@ def test_extension_rows_are_zero_rows():
     lens = np.diff(s.row_ptr)
     real = new_of_old[:s.m][lens > 0]
     assert np.all(pl.group[real] >= 0)
+
+
+# ------------------------------------------- block mode (Section 3.3, Algorithm 4)
+def test_block_ranges_floor_rule():
+    """The first k - 1 blocks take floor(m / k) rows, the k-th the rest."""
+    assert oracle.block_ranges(10, 3).tolist() == [0, 3, 6, 10]
+    assert oracle.block_ranges(12, 4).tolist() == [0, 3, 6, 9, 12]
+    assert oracle.block_ranges(7, 1).tolist() == [0, 7]
+    assert oracle.block_ranges(5, 5).tolist() == [0, 1, 2, 3, 4, 5]
+
+
+def test_block_projection_lands_on_block_hyperplanes():
+    """Eq. 1.3: after x + pinv(A_tau)(f_tau - A_tau x) on a consistent system,
+    A_tau x = f_tau."""
+    s = synth.c1(n=300, companion=True)
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 5, 0.1)
+    A = sp.csr_matrix((bp.v, bp.ci, bp.rp), shape=(s.n, s.n))
+    x = np.random.default_rng(1).standard_normal(s.n)
+    for tau in range(5):
+        y = oracle.block_project(bp, tau, x)
+        r0, r1 = bp.bptr[tau], bp.bptr[tau + 1]
+        assert np.linalg.norm(A[r0:r1] @ y - bp.f[r0:r1]) <= 1e-10 * np.linalg.norm(bp.f[r0:r1])
+
+
+def test_one_row_blocks_are_sequential_kaczmarz():
+    """k = m: every block is one row, so a block sweep is eq. 1.2 row by row in
+    the order the pairs and Nclass give."""
+    s = synth.c1(n=60)
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, s.n, 0.1)
+    order = [t for pr in bp.pairs for t in pr] + list(bp.nclass)
+    assert sorted(order) == list(range(s.n))
+    x0 = np.random.default_rng(2).standard_normal(s.n)
+    xb = oracle.block_sweep(bp, x0, 2)
+    nu, inv = oracle.norms(s.n, bp.rp, bp.v)
+    xr = oracle.rowwise(s.n, bp.rp, bp.ci, bp.v, bp.f, inv, np.array(order * 2, dtype=np.int32), x0)
+    assert np.linalg.norm(xb - xr) <= 1e-12 * np.linalg.norm(xr)
+
+
+def test_block_pair_rule_hand_cases():
+    """Blocks with disjoint column supports have centroid cosine 0 and pair up
+    in order; blocks of identical dense rows have cosine 1 and all go to
+    Nclass."""
+    n = 12
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, i] = 2.0
+        D[i, (i + 1) % 3 + 3 * (i // 3)] += 0.5     # stays inside each block of 3 rows and 3 columns
+    s = synth.from_dense(D, np.ones(n))
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 4, 0.1)
+    # the RCM order keeps the four 3x3 blocks contiguous, so the chunks are them
+    assert np.allclose(bp.cos - np.eye(4), 0.0)
+    assert bp.pairs == [(0, 1), (2, 3)] and bp.nclass == []
+    E = np.ones((8, 8)) + 7 * np.eye(8)
+    se = synth.from_dense(E, np.ones(8))
+    be = oracle.block_plan(se.n, se.row_ptr, se.col, se.val, se.f, 4, 0.1)
+    assert be.pairs == [] and be.nclass == [0, 1, 2, 3]
+
+
+def test_orthogonal_pair_equals_joint_projection():
+    """For two blocks whose rows are mutually orthogonal, the two half steps of
+    Algorithm 4 equal one projection onto both blocks (eq. 1.3 with the
+    stacked block)."""
+    rng = np.random.default_rng(4)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    A = Q[:20]                                       # 20 orthonormal rows
+    f = A @ rng.standard_normal(40)
+    x = rng.standard_normal(40)
+    A1, A2, f1, f2 = A[:10], A[10:], f[:10], f[10:]
+    y = x + np.linalg.pinv(A1) @ (f1 - A1 @ x)
+    y = y + np.linalg.pinv(A2) @ (f2 - A2 @ y)
+    z = x + np.linalg.pinv(A) @ (f - A @ x)
+    assert np.linalg.norm(y - z) <= 1e-12 * np.linalg.norm(z)
+
+
+def test_block_mode_converges_to_generating_solution():
+    """Theorem 1 for the block iteration: a consistent, well-conditioned system."""
+    s = synth.c1(n=400, companion=True)
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 8, 0.1)
+    x = oracle.block_solve(bp, 60)
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) <= 1e-10
