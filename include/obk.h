@@ -105,6 +105,16 @@ typedef struct {
                                 with f_i != 0; 0 (default): such rows are skipped */
     size_t hbm_budget;       /* 0: unlimited; else obk_plan fails with OBK_E_NOMEM when the
                                 plan's device footprint would exceed it */
+    int block_k;             /* 0 (default): one-row blocks grouped by first fit.  k in
+                                [1, 4096]: block form of Algorithm 4 (Section 3.3), with
+                                k uniform chunks of A~ projected exactly; OBK_FP64 only.
+                                A plan-time option. */
+    int block_wgs;           /* block form: workgroups of the projection launch
+                                (0 = from the block size) */
+    int block_maxit;         /* block form: CG iterations per projection at most
+                                (0 = 4 x block rows + 100) */
+    double block_tol;        /* block form: a projection's CG stops once its residual
+                                norm is <= block_tol x its initial one (default 1e-14) */
 } obk_opts;
 
 typedef struct {
@@ -164,13 +174,40 @@ OBK_API obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts *opts);
 /* p_host[t] = original index of reordered row t (new -> old), n entries. */
 OBK_API obk_status obk_plan_perm(obk_plan_t plan, int32_t *p_host);
 /* group_of_row_host[t] = group of reordered row t (-1 for an all-zero row);
- * *n_groups = number of groups.  Either output may be NULL. */
+ * *n_groups = number of groups.  In the block form (opts.block_k > 0) the
+ * group of a row is its block (zero rows included) and *n_groups = k.
+ * Either output may be NULL. */
 OBK_API obk_status obk_plan_groups(obk_plan_t plan, int32_t *group_of_row_host, int32_t *n_groups);
 /* Device bytes owned by the plan (for admission against an HBM budget). */
 OBK_API obk_status obk_plan_bytes(obk_plan_t plan, size_t *device_bytes);
 /* Sizes: n, nnz, number of groups, bandwidth of A~, number of conflicting pairs. */
 OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int32_t *n_groups,
                           int64_t *bandwidth, int64_t *n_conflicts);
+
+/*
+ * Block form of Algorithm 4 (opts.block_k = k > 0; Section 3.3, eq. 3.3).
+ * Planning: RCM as above; the reordered rows are cut in order into k blocks,
+ * the first k - 1 of floor(n / k) rows and the last of the rest; the centroid
+ * of a block is its mean row and the table C(a, b) = |cos| of the centroids
+ * of blocks a and b (0 when either centroid is zero) is formed in FP64;
+ * pairs are formed in ascending order of a: block a, if not yet paired,
+ * pairs with the least b > a not yet paired with C(a, b) < delta (delta is
+ * the paper's thr); blocks left unpaired form Nclass.  A sweep projects, for
+ * each pair in the order formed, block a then block b, then every Nclass
+ * block in ascending order.  A projection onto block t replaces x~ by
+ * x~ + A_t^+ (f_t - A_t x~); it is computed as x~ + A_t^T y with y from
+ * conjugate gradients on A_t A_t^T y = f_t - A_t x~ (started at 0, stopped
+ * by opts.block_tol / opts.block_maxit; all-zero rows take no part), all
+ * iterations of all projections of a call in one cooperative launch.
+ *
+ * obk_plan_blocks (host outputs, each may be NULL): *k; bptr[k+1] the row
+ * range of each block in reordered rows; partner[k] the block a block is
+ * paired with (-1: Nclass); cos[k*k] the table C, row-major; cg_iters[k] the
+ * CG iterations spent on each block over every sweep run on the plan so far.
+ * Errors: OBK_E_ARG when the plan is not in block form.
+ */
+OBK_API obk_status obk_plan_blocks(obk_plan_t plan, int32_t *k, int64_t *bptr, int32_t *partner, double *cos,
+                                   int64_t *cg_iters);
 
 /*
  * Sweeps on a plan with device-resident iterates, no host synchronisation and

@@ -43,7 +43,8 @@ class _Csr(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("use_rcm", ctypes.c_int), ("precision", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("reject_inconsistent", ctypes.c_int),
-                ("hbm_budget", ctypes.c_size_t)]
+                ("hbm_budget", ctypes.c_size_t), ("block_k", ctypes.c_int), ("block_wgs", ctypes.c_int),
+                ("block_maxit", ctypes.c_int), ("block_tol", ctypes.c_double)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.obk_sweep_device.argtypes = [_P, _P, ctypes.c_int64, _P]
         L.obk_sweep_profile.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(_KernelProfile),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.obk_plan_blocks.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]
         L.obk_plan_set_opts.argtypes = [_P, ctypes.POINTER(_Opts)]
         L.obk_plan_set_opts.restype = ctypes.c_int
         L.obk_last_error.restype = ctypes.c_char_p
@@ -115,7 +117,8 @@ def lib() -> ctypes.CDLL:
         for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
-                     "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune"):
+                     "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
+                     "obk_plan_blocks"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,15 +233,36 @@ class Plan:
                  "bytes": out[i].bytes} for i in range(n.value)]
 
     def set_opts(self, precision: int | None = None, inner_sweeps: int | None = None,
-                 check_every: int | None = None) -> None:
+                 check_every: int | None = None, block_wgs: int | None = None, block_maxit: int | None = None,
+                 block_tol: float | None = None) -> None:
         """obk_plan_set_opts: change solve options without replanning."""
         o = _Opts()
         lib().obk_opts_default(ctypes.byref(o))
-        o.precision = self._opts.get("precision", FP64) if precision is None else int(precision)
-        o.inner_sweeps = self._opts.get("inner_sweeps", 8) if inner_sweeps is None else int(inner_sweeps)
-        o.check_every = self._opts.get("check_every", 1) if check_every is None else int(check_every)
+        new = {"precision": precision, "inner_sweeps": inner_sweeps, "check_every": check_every,
+               "block_wgs": block_wgs, "block_maxit": block_maxit, "block_tol": block_tol}
+        for key, val in new.items():
+            v = self._opts.get(key, getattr(o, key)) if val is None else val
+            setattr(o, key, type(getattr(o, key))(v))
         _check(lib().obk_plan_set_opts(self.handle, ctypes.byref(o)))
-        self._opts.update(precision=o.precision, inner_sweeps=o.inner_sweeps, check_every=o.check_every)
+        self._opts.update({key: getattr(o, key) for key in new})
+
+    def blocks(self) -> dict:
+        """obk_plan_blocks (block form): block row ranges, the |cos| table of
+        the centroids, the Oclass pairs in the order formed, Nclass, and the CG
+        iterations spent per block so far."""
+        k = ctypes.c_int32(0)
+        _check(lib().obk_plan_blocks(self.handle, ctypes.byref(k), None, None, None, None))
+        kk = int(k.value)
+        bptr = np.empty(kk + 1, dtype=np.int64)
+        partner = np.empty(kk, dtype=np.int32)
+        cos = np.empty((kk, kk), dtype=np.float64)
+        iters = np.empty(kk, dtype=np.int64)
+        _check(lib().obk_plan_blocks(self.handle, ctypes.byref(k), bptr.ctypes.data, partner.ctypes.data,
+                                     cos.ctypes.data, iters.ctypes.data))
+        pairs = [(a, int(partner[a])) for a in range(kk) if partner[a] > a]
+        nclass = [a for a in range(kk) if partner[a] < 0]
+        return {"k": kk, "bptr": bptr, "partner": partner, "cos": cos, "pairs": pairs, "nclass": nclass,
+                "cg_iters": iters}
 
     # -- introspection
     def perm(self) -> np.ndarray:
@@ -268,8 +292,11 @@ class Plan:
 
 def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: int | None = None,
          use_rcm: bool = True, precision: int = FP64, inner_sweeps: int = 8, check_every: int = 1,
-         reject_inconsistent: bool = False, hbm_budget: int = 0, stream=None) -> Plan:
-    """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device)."""
+         reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0, block_wgs: int = 0,
+         block_maxit: int = 0, block_tol: float = 1e-14, stream=None) -> Plan:
+    """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device).
+    block_k > 0 selects the block form of Algorithm 4 (k uniform blocks, exact
+    block projections); delta is then the centroid cosine threshold."""
     on_device = _is_torch(row_ptr)
     if on_device:
         nrows = int(row_ptr.numel()) - 1 if n is None else int(n)
@@ -298,11 +325,16 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     opts.check_every = int(check_every)
     opts.reject_inconsistent = 1 if reject_inconsistent else 0
     opts.hbm_budget = int(hbm_budget)
+    opts.block_k = int(block_k)
+    opts.block_wgs = int(block_wgs)
+    opts.block_maxit = int(block_maxit)
+    opts.block_tol = float(block_tol)
     h = _P()
     _check(lib().obk_plan(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
     del keep
     return Plan(h.value, ncols, nnz, on_device,
-                {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every)},
+                {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every),
+                 "block_wgs": int(block_wgs), "block_maxit": int(block_maxit), "block_tol": float(block_tol)},
                 n_ext=max(nrows, ncols))
 
 

@@ -42,7 +42,9 @@ size_t obk_plan_s::device_bytes() const {
            tcol.bytes() + sptr.bytes() + srow.bytes() + sval.bytes() + rtiles.bytes() + stiles.bytes() +
            d_rtile_ptr.bytes() + d_stile_ptr.bytes() +
            x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
-           b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes();
+           b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes() + d_bptr.bytes() + d_btptr.bytes() +
+           d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
+           biters.bytes();
 }
 
 namespace {
@@ -67,6 +69,13 @@ template <class F> obk_status guarded(F&& body) {
 
 hipStream_t as_hip(obk_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
+void check_block_opts(const obk_opts& o) {
+    if (o.block_k < 0 || o.block_k > 4096) obk::fail(OBK_E_ARG, "block_k must be in [0, 4096]");
+    if (o.block_k > 0 && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "the block form runs in OBK_FP64 only");
+    if (o.block_wgs < 0 || o.block_maxit < 0) obk::fail(OBK_E_ARG, "block_wgs and block_maxit must be >= 0");
+    if (!(o.block_tol >= 0.0) || !std::isfinite(o.block_tol)) obk::fail(OBK_E_ARG, "block_tol must be finite and >= 0");
+}
+
 // RAII marker for the one-solve-at-a-time rule
 struct BusyGuard {
     obk_plan_s* p;
@@ -89,6 +98,10 @@ obk_status obk_opts_default(obk_opts* opts) {
     opts->check_every = 1;
     opts->reject_inconsistent = 0;
     opts->hbm_budget = 0;
+    opts->block_k = 0;
+    opts->block_wgs = 0;
+    opts->block_maxit = 0;
+    opts->block_tol = 1e-14;
     return OBK_OK;
 }
 
@@ -110,6 +123,8 @@ obk_status obk_plan(const obk_csr* A, const double* f, double delta, const obk_o
         if (opts) o = *opts;
         if (o.precision != OBK_FP64 && o.precision != OBK_FP32_IR) obk::fail(OBK_E_ARG, "unknown precision");
         if (o.inner_sweeps < 1 || o.check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
+        check_block_opts(o);
+        if (o.block_k > std::max(A->n_rows, A->n_cols)) obk::fail(OBK_E_ARG, "block_k exceeds the number of rows");
         P = new obk_plan_s();
         P->opts = o;
         obk::build_plan(*P, *A, f, delta, as_hip(stream));
@@ -145,12 +160,18 @@ obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts* opts) {
         if (!plan || !opts) obk::fail(OBK_E_ARG, "NULL argument");
         if (opts->precision != OBK_FP64 && opts->precision != OBK_FP32_IR) obk::fail(OBK_E_ARG, "unknown precision");
         if (opts->inner_sweeps < 1 || opts->check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
+        obk_opts o = *opts;
+        o.block_k = plan->opts.block_k;   // a plan-time option
+        check_block_opts(o);
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
         plan->opts.precision = opts->precision;
         plan->opts.inner_sweeps = opts->inner_sweeps;
         plan->opts.check_every = opts->check_every;
         plan->opts.hbm_budget = opts->hbm_budget;
+        plan->opts.block_wgs = opts->block_wgs;
+        plan->opts.block_maxit = opts->block_maxit;
+        plan->opts.block_tol = opts->block_tol;
         if (plan->has_fp32()) obk::ensure_fp32(*plan, nullptr);
     });
 }
@@ -196,6 +217,23 @@ obk_status obk_plan_groups(obk_plan_t plan, int32_t* group_of_row_host, int32_t*
         if (group_of_row_host && plan->n)
             std::memcpy(group_of_row_host, plan->h_group.data(), plan->n * sizeof(int32_t));
         if (n_groups) *n_groups = plan->ngroups;
+    });
+}
+
+obk_status obk_plan_blocks(obk_plan_t plan, int32_t* k, int64_t* bptr, int32_t* partner, double* cos,
+                           int64_t* cg_iters) {
+    return guarded([&] {
+        if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
+        if (!plan->block_form()) obk::fail(OBK_E_ARG, "the plan is not in block form");
+        const int32_t K = plan->opts.block_k;
+        if (k) *k = K;
+        if (bptr) std::memcpy(bptr, plan->h_bptr.data(), (K + 1) * sizeof(int64_t));
+        if (partner) std::memcpy(partner, plan->h_partner.data(), K * sizeof(int32_t));
+        if (cos) std::memcpy(cos, plan->h_bcos.data(), (size_t)K * K * sizeof(double));
+        if (cg_iters) {
+            OBK_HIP(hipSetDevice(plan->device));
+            OBK_HIP(hipMemcpy(cg_iters, plan->biters.get(), K * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
     });
 }
 

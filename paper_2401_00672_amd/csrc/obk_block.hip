@@ -1,0 +1,449 @@
+// Block form of Algorithm 4 (Section 3.3): k uniform chunks of the reordered
+// system, the |cos| table of their centroids, the pairing into Oclass and
+// Nclass, and sweeps of exact block projections (eq. 3.3).
+//
+// Planning (block_setup; the shared stages have already kept the reordered
+// rows in order, m = n, and built the per-block CSC with rows ascending):
+//   * every per-block column segment is summed in ascending row order: these
+//     are the block's column sums, its centroid times its row count (a scale
+//     the cosine does not see);
+//   * for every pair of blocks whose touched-column ranges intersect, one
+//     workgroup forms the dot product of their column sums by looking up each
+//     column of one block in the sorted column list of the other; all other
+//     pairs share no column and their cosine is exactly 0;
+//   * the host forms |cos| and pairs the blocks.
+//
+// Sweeps (k_block_sweeps): one cooperative launch of G workgroups runs every
+// projection of the call.  Projection onto block t (rows R, touched columns
+// S): res = f_R - A_R x~ (all-zero rows: 0), then conjugate gradients on
+// A_R A_R^T y = res in the form that moves x~ itself (x~ += alpha A_R^T d):
+//   phase A (columns of S)  u = A_R^T (res + beta p)              |u|^2
+//   -- grid barrier --      alpha = |res|^2 / |u|^2
+//   phase B (columns of S)  x~ += alpha u
+//           (rows of R)     p = res + beta p; res -= alpha A_R u   |res|^2
+//   -- grid barrier --      beta = |res_new|^2 / |res|^2
+// (p holds the previous direction; u = A_R^T d with d = res + beta p is the
+// current one, so alpha = |res|^2 / d^T A_R A_R^T d = |res|^2 / |u|^2.)
+// Rows and column segments of a block are cut into G contiguous ranges, one
+// per workgroup; each row and each column is reduced sequentially in
+// ascending index order.  Every workgroup reduces the G partial sums itself
+// in one fixed order, so all of them take the same decisions with no further
+// synchronisation, and a solve is bitwise repeatable for a given G.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "obk_internal.h"
+
+namespace obk {
+
+namespace {
+
+constexpr int kBT = 1024;             // threads per workgroup of the projection launch
+constexpr long kBlockSpin = 1L << 22; // bound on one barrier wait (polls)
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+// Sum over the workgroup in a fixed order (butterfly within each wave, then
+// the wave sums in ascending order); every thread gets the same value.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* lds) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    __syncthreads();                       // lds is free again
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; i++) t = t + lds[i];
+    return t;
+}
+
+// Barrier over the whole (co-resident) grid on a monotonic arrival counter:
+// at its e-th barrier a workgroup adds 1 and waits until the counter reaches
+// e G.  Every wave fences at agent scope on both sides (its own stores out
+// before the arrival, the others' stores in after the wait); wave 0 waits,
+// in wave-uniform control flow.  Returns false when the wait timed out or
+// another workgroup reported a timeout: the caller then leaves the kernel,
+// so every workgroup exits after at most one bound.
+__device__ __forceinline__ bool grid_barrier(uint64_t* bar, int* err, int* lds_flag, uint64_t& episode) {
+    if (gridDim.x == 1) {
+        __syncthreads();
+        return true;
+    }
+    episode++;
+    const uint64_t target = episode * gridDim.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) >> 6;
+    if (wave == 0) {
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(bar, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t cur = 0;
+        int bad = 0;
+        long spins = 0;
+#pragma clang loop unroll(disable)
+        do {
+            __builtin_amdgcn_s_sleep(1);
+            cur = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            spins++;
+        } while ((cur < target) & (bad == 0) & (spins <= kBlockSpin));
+        const int ok = cur >= target ? 1 : 0;
+        if (threadIdx.x == 0) {
+            if (!ok) atomicOr(err, 1);
+            *lds_flag = ok;
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *lds_flag != 0;
+}
+
+struct BlockArgs {
+    const int64_t* rptr;      // reordered CSR (rows in order), [n+1]
+    const int32_t* rcol;
+    const double* rval;
+    const double* rf;
+    const double* rinv;       // 0 marks an all-zero row
+    const int64_t* bptr;      // rows of block b: [bptr[b], bptr[b+1])
+    const int64_t* btptr;     // column segments of block b: [btptr[b], btptr[b+1])
+    const int32_t* tcol;
+    const int64_t* sptr;
+    const int32_t* srow;
+    const double* sval;
+    const int32_t* order;     // blocks in projection order
+    double* x;
+    double* res;
+    double* p;
+    double* u;
+    double* part;             // [4 G] partial sums: |u|^2, |res|^2 in the loop, |res_0|^2 (two)
+    uint64_t* bar;            // arrival counter (zero at launch)
+    int* err;
+    int64_t* iters;           // CG iterations per block, accumulated
+    int64_t sweeps;
+    int32_t k;
+    int32_t maxit;            // 0: 4 rows + 100
+    double tol2;              // squared relative stopping tolerance
+};
+
+__global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
+    __shared__ double lds[kBT / 64];
+    __shared__ int flag;
+    uint64_t episode = 0;
+    const int64_t G = gridDim.x, w = blockIdx.x;
+    const int t = threadIdx.x;
+    // Each reduction reads, after a barrier, partials written before it; a
+    // workgroup may already write the next partials while a slower one still
+    // reads, so consecutive reductions never share a buffer: the loop
+    // alternates pu and pr, and the start of a projection alternates between
+    // two buffers of its own (it can follow a reduction of either kind, or
+    // the start of the previous projection).
+    double* pu = a.part;
+    double* pr = a.part + G;
+    for (int64_t sw = 0; sw < a.sweeps; sw++) {
+        for (int32_t j = 0; j < a.k; j++) {
+            double* p0 = a.part + (2 + ((sw * a.k + j) & 1)) * G;
+            const int32_t b = a.order[j];
+            const int64_t r0 = a.bptr[b], nb = a.bptr[b + 1] - r0;
+            const int64_t s0 = a.btptr[b], ns = a.btptr[b + 1] - s0;
+            const int64_t ra = r0 + nb * w / G, rb = r0 + nb * (w + 1) / G;
+            const int64_t sa = s0 + ns * w / G, sb = s0 + ns * (w + 1) / G;
+            // res = f_R - A_R x~, p = 0
+            double acc = 0.0;
+            for (int64_t i = ra + t; i < rb; i += kBT) {
+                double r = 0.0;
+                if (a.rinv[i] != 0.0) {
+                    double d = 0.0;
+                    const int64_t e1 = a.rptr[i + 1];
+                    for (int64_t e = a.rptr[i]; e < e1; e++) d = d + a.rval[e] * a.x[a.rcol[e]];
+                    r = a.rf[i] - d;
+                }
+                a.res[i] = r;
+                a.p[i] = 0.0;
+                acc = acc + r * r;
+            }
+            acc = wg_sum<kBT>(acc, lds);
+            if (t == 0) p0[w] = acc;
+            if (!grid_barrier(a.bar, a.err, &flag, episode)) return;
+            double rr = wg_sum<kBT>(t < G ? p0[t] : 0.0, lds);
+            const double rr0 = rr;
+            const int64_t cap = a.maxit > 0 ? a.maxit : 4 * nb + 100;
+            double beta = 0.0;
+            int64_t it = 0;
+            while (rr0 > 0.0 && rr > a.tol2 * rr0 && it < cap) {
+                // phase A: u = A_R^T (res + beta p) on the touched columns
+                acc = 0.0;
+                for (int64_t q = sa + t; q < sb; q += kBT) {
+                    double s = 0.0;
+                    const int64_t e1 = a.sptr[q + 1];
+                    for (int64_t e = a.sptr[q]; e < e1; e++) {
+                        const int32_t i = a.srow[e];
+                        s = s + a.sval[e] * (a.res[i] + beta * a.p[i]);
+                    }
+                    a.u[a.tcol[q]] = s;
+                    acc = acc + s * s;
+                }
+                acc = wg_sum<kBT>(acc, lds);
+                if (t == 0) pu[w] = acc;
+                if (!grid_barrier(a.bar, a.err, &flag, episode)) return;
+                const double uu = wg_sum<kBT>(t < G ? pu[t] : 0.0, lds);
+                if (!(uu > 0.0)) break;
+                const double alpha = rr / uu;
+                // phase B: x~ += alpha u; p = res + beta p; res -= alpha A_R u
+                for (int64_t q = sa + t; q < sb; q += kBT) {
+                    const int32_t c = a.tcol[q];
+                    a.x[c] = a.x[c] + alpha * a.u[c];
+                }
+                acc = 0.0;
+                for (int64_t i = ra + t; i < rb; i += kBT) {
+                    if (a.rinv[i] == 0.0) continue;
+                    const double ri = a.res[i];
+                    a.p[i] = ri + beta * a.p[i];
+                    double d = 0.0;
+                    const int64_t e1 = a.rptr[i + 1];
+                    for (int64_t e = a.rptr[i]; e < e1; e++) d = d + a.rval[e] * a.u[a.rcol[e]];
+                    const double rn = ri - alpha * d;
+                    a.res[i] = rn;
+                    acc = acc + rn * rn;
+                }
+                acc = wg_sum<kBT>(acc, lds);
+                if (t == 0) pr[w] = acc;
+                if (!grid_barrier(a.bar, a.err, &flag, episode)) return;
+                const double rn2 = wg_sum<kBT>(t < G ? pr[t] : 0.0, lds);
+                beta = rn2 / rr;
+                rr = rn2;
+                it++;
+            }
+            if (w == 0 && t == 0) a.iters[b] += it;
+        }
+    }
+}
+
+// sum of each column segment, ascending rows
+__global__ void k_seg_sums(int64_t T, const int64_t* __restrict__ sptr, const double* __restrict__ sval,
+                           double* __restrict__ ssum) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T) return;
+    double s = 0.0;
+    for (int64_t e = sptr[q]; e < sptr[q + 1]; e++) s = s + sval[e];
+    ssum[q] = s;
+}
+
+// first and last touched column of each block (lo > hi: no column)
+__global__ void k_block_col_range(int32_t k, const int64_t* __restrict__ btptr, const int32_t* __restrict__ tcol,
+                                  int32_t* __restrict__ lohi) {
+    const int32_t b = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= k) return;
+    const int64_t q0 = btptr[b], q1 = btptr[b + 1];
+    lohi[2 * b] = q1 > q0 ? tcol[q0] : 1;
+    lohi[2 * b + 1] = q1 > q0 ? tcol[q1 - 1] : 0;
+}
+
+// Gram entry of the column sums of blocks (pairs[2p], pairs[2p+1]); one
+// workgroup per pair; the columns of each block's segment list ascend.
+__global__ __launch_bounds__(256) void k_block_gram(const int32_t* __restrict__ pairs,
+                                                    const int64_t* __restrict__ btptr,
+                                                    const int32_t* __restrict__ tcol,
+                                                    const double* __restrict__ ssum, double* __restrict__ gram) {
+    __shared__ double lds[4];
+    const int32_t ba = pairs[2 * blockIdx.x], bb = pairs[2 * blockIdx.x + 1];
+    const int64_t a0 = btptr[ba], a1 = btptr[ba + 1], b0 = btptr[bb], b1 = btptr[bb + 1];
+    double acc = 0.0;
+    for (int64_t q = a0 + threadIdx.x; q < a1; q += blockDim.x) {
+        const int32_t c = tcol[q];
+        int64_t lo = b0, hi = b1;          // first position with tcol >= c
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (tcol[mid] < c) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < b1 && tcol[lo] == c) acc = acc + ssum[q] * ssum[lo];
+    }
+    acc = wg_sum<256>(acc, lds);
+    if (threadIdx.x == 0) gram[blockIdx.x] = acc;
+}
+
+template <class T> std::vector<T> dev_to_host(const T* d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) {
+        OBK_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipStreamSynchronize(s));
+    }
+    return h;
+}
+
+template <class T> void host_to_dev(DevArray<T>& d, const std::vector<T>& h, hipStream_t s) {
+    d.alloc(h.size());
+    if (!h.empty()) {
+        OBK_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        OBK_HIP(hipStreamSynchronize(s));
+    }
+}
+
+int32_t block_grid(const obk_plan_s& P) {
+    int dev = 0, cus = 256;
+    OBK_HIP(hipGetDevice(&dev));
+    OBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int32_t cap = std::max(1, std::min(kBT, std::max(1, P.block_occ) * cus));
+    if (P.opts.block_wgs > 0) return std::min(P.opts.block_wgs, cap);
+    int64_t rows = 0;
+    for (size_t b = 0; b + 1 < P.h_bptr.size(); b++) rows = std::max(rows, P.h_bptr[b + 1] - P.h_bptr[b]);
+    // about two rows per thread
+    return (int32_t)std::min<int64_t>(cap, std::max<int64_t>(1, (rows + 2 * kBT - 1) / (2 * kBT)));
+}
+
+}  // namespace
+
+// Block ranges, centroid cosines, pairing and the projection workspace.
+void block_setup(obk_plan_s& P, hipStream_t s) {
+    const int32_t K = P.opts.block_k;
+    const int64_t n = P.n;
+    const int64_t T = P.h_tptr[K];
+    host_to_dev(P.d_bptr, P.h_bptr, s);
+    host_to_dev(P.d_btptr, P.h_tptr, s);
+    // column sums per segment, column range per block
+    DevArray<double> ssum; ssum.alloc(T);
+    if (T) {
+        k_seg_sums<<<nblk(T), 256, 0, s>>>(T, P.sptr.get(), P.sval.get(), ssum.get());
+        OBK_HIP(hipGetLastError());
+    }
+    DevArray<int32_t> lohi; lohi.alloc(2 * (size_t)K);
+    k_block_col_range<<<nblk(K), 256, 0, s>>>(K, P.d_btptr.get(), P.tcol.get(), lohi.get());
+    OBK_HIP(hipGetLastError());
+    std::vector<int32_t> hl = dev_to_host(lohi.get(), 2 * (size_t)K, s);
+    // pairs of blocks that can share a column (a <= b)
+    std::vector<int32_t> pairs;
+    for (int32_t a = 0; a < K; a++) {
+        if (hl[2 * a] > hl[2 * a + 1]) continue;
+        for (int32_t b = a; b < K; b++)
+            if (hl[2 * b] <= hl[2 * b + 1] && hl[2 * b] <= hl[2 * a + 1] && hl[2 * a] <= hl[2 * b + 1]) {
+                pairs.push_back(a);
+                pairs.push_back(b);
+            }
+    }
+    const int64_t np = (int64_t)pairs.size() / 2;
+    std::vector<double> gram;
+    if (np) {
+        DevArray<int32_t> dpairs; host_to_dev(dpairs, pairs, s);
+        DevArray<double> dgram; dgram.alloc(np);
+        k_block_gram<<<(unsigned)np, 256, 0, s>>>(dpairs.get(), P.d_btptr.get(), P.tcol.get(), ssum.get(),
+                                                 dgram.get());
+        OBK_HIP(hipGetLastError());
+        gram = dev_to_host(dgram.get(), np, s);
+    }
+    std::vector<double> diag(K, 0.0);
+    for (int64_t q = 0; q < np; q++)
+        if (pairs[2 * q] == pairs[2 * q + 1]) diag[pairs[2 * q]] = gram[q];
+    P.h_bcos.assign((size_t)K * K, 0.0);
+    for (int64_t q = 0; q < np; q++) {
+        const int32_t a = pairs[2 * q], b = pairs[2 * q + 1];
+        if (diag[a] > 0.0 && diag[b] > 0.0) {
+            const double c = std::fabs(gram[q]) / (std::sqrt(diag[a]) * std::sqrt(diag[b]));
+            P.h_bcos[(size_t)a * K + b] = c;
+            P.h_bcos[(size_t)b * K + a] = c;
+        }
+    }
+    // pairing: a block not yet paired takes the least later free block with
+    // |cos| below the threshold; the rest form Nclass
+    P.h_partner.assign(K, -1);
+    P.h_border.clear();
+    for (int32_t a = 0; a < K; a++) {
+        if (P.h_partner[a] >= 0) continue;
+        for (int32_t b = a + 1; b < K; b++)
+            if (P.h_partner[b] < 0 && P.h_bcos[(size_t)a * K + b] < P.delta) {
+                P.h_partner[a] = b;
+                P.h_partner[b] = a;
+                P.h_border.push_back(a);
+                P.h_border.push_back(b);
+                break;
+            }
+    }
+    for (int32_t a = 0; a < K; a++)
+        if (P.h_partner[a] < 0) P.h_border.push_back(a);
+    host_to_dev(P.d_border, P.h_border, s);
+    // projection workspace
+    P.bres.alloc(n); P.bp.alloc(n); P.bu.alloc(n);
+    P.bpart.alloc(4 * kBT);
+    P.bbar.alloc(1);
+    P.berr.alloc(1);
+    P.biters.alloc(K);
+    OBK_HIP(hipMemsetAsync(P.bu.get(), 0, std::max<int64_t>(n, 1) * sizeof(double), s));
+    OBK_HIP(hipMemsetAsync(P.biters.get(), 0, K * sizeof(int64_t), s));
+    OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&P.block_occ, k_block_sweeps, kBT, 0));
+    if (P.block_occ < 1) fail(OBK_E_HIP, "the block projection kernel cannot be resident");
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+// `sweeps` block sweeps on x (device, reordered coordinates); synchronises
+// the stream to check the launch's barrier flag.  ms (may be null) receives
+// the launch's event time.
+void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float* ms) {
+    if (sweeps <= 0 || P.opts.block_k <= 0) return;
+    const int32_t G = block_grid(P);
+    BlockArgs a{};
+    a.rptr = P.rptr.get(); a.rcol = P.rcol.get(); a.rval = P.rval.get(); a.rf = P.rf.get(); a.rinv = P.rinv.get();
+    a.bptr = P.d_bptr.get(); a.btptr = P.d_btptr.get();
+    a.tcol = P.tcol.get(); a.sptr = P.sptr.get(); a.srow = P.srow.get(); a.sval = P.sval.get();
+    a.order = P.d_border.get();
+    a.x = x; a.res = P.bres.get(); a.p = P.bp.get(); a.u = P.bu.get();
+    a.part = P.bpart.get(); a.bar = P.bbar.get(); a.err = P.berr.get(); a.iters = P.biters.get();
+    a.sweeps = sweeps;
+    a.k = P.opts.block_k;
+    a.maxit = std::max(0, P.opts.block_maxit);
+    a.tol2 = P.opts.block_tol * P.opts.block_tol;
+    OBK_HIP(hipMemsetAsync(P.bbar.get(), 0, sizeof(uint64_t), s));
+    OBK_HIP(hipMemsetAsync(P.berr.get(), 0, sizeof(int), s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        OBK_HIP(hipEventCreate(&e0));
+        OBK_HIP(hipEventCreate(&e1));
+        OBK_HIP(hipEventRecord(e0, s));
+    }
+    void* args[] = {&a};
+    hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps), dim3(G), dim3(kBT),
+                                               args, 0, s);
+    if (ms) OBK_HIP(hipEventRecord(e1, s));
+    auto* h = static_cast<int*>(pinned_stage(sizeof(int)));
+    *h = 0;
+    if (le == hipSuccess) le = hipMemcpyAsync(h, P.berr.get(), sizeof(int), hipMemcpyDeviceToHost, s);
+    const hipError_t se = hipStreamSynchronize(s);
+    if (ms && le == hipSuccess && se == hipSuccess) (void)hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    check_hip(le, "hipLaunchCooperativeKernel(k_block_sweeps)");
+    check_hip(se, "hipStreamSynchronize");
+    if (*h) fail(OBK_E_HIP, "a grid barrier of the block projection launch timed out");
+}
+
+// Event time and algorithmic bytes of block sweeps (formula in obk.h).
+int32_t profile_block(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
+                      int32_t max_out) {
+    const int32_t K = P.opts.block_k;
+    std::vector<int64_t> it0 = dev_to_host(P.biters.get(), K, s);
+    float ms = 0;
+    block_sweeps(P, x, sweeps, s, &ms);
+    std::vector<int64_t> it1 = dev_to_host(P.biters.get(), K, s);
+    std::vector<int64_t> rp = dev_to_host(P.rptr.get(), P.n + 1, s);
+    const double sv = 8, so = 4;
+    double bytes = 0;
+    for (int32_t b = 0; b < K; b++) {
+        const double nb = (double)(P.h_bptr[b + 1] - P.h_bptr[b]);
+        const double eb = (double)(rp[P.h_bptr[b + 1]] - rp[P.h_bptr[b]]);
+        const double tb = (double)(P.h_tptr[b + 1] - P.h_tptr[b]);
+        const double start = eb * (sv + so) + nb * (so + 3 * sv) + tb * sv;
+        const double iter = 2 * eb * (sv + so) + nb * (so + 6 * sv) + tb * (3 * so + 5 * sv);
+        bytes += (double)sweeps * start + (double)(it1[b] - it0[b]) * iter;
+    }
+    if (max_out < 1) return 0;
+    std::memset(&out[0], 0, sizeof(out[0]));
+    std::strncpy(out[0].name, "k_block_sweeps", sizeof(out[0].name) - 1);
+    out[0].launches = 1;
+    out[0].seconds = ms * 1e-3;
+    out[0].bytes = bytes;
+    return 1;
+}
+
+}  // namespace obk

@@ -114,6 +114,18 @@ void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Til
 
 }  // namespace obk
 
+struct obk_plan_s;
+namespace obk {
+// Centroid cosines, pairing and projection workspace of a block-form plan
+// (after the shared plan stages).
+void block_setup(obk_plan_s& P, hipStream_t s);
+// `sweeps` block sweeps on x (device, reordered); synchronises the stream.
+// ms (may be null) receives the launch's event time in milliseconds.
+void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float* ms);
+int32_t profile_block(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
+                      int32_t max_out);
+}  // namespace obk
+
 // --------------------------------------------------------------- the plan
 struct obk_plan_s {
     int device = 0;
@@ -169,6 +181,21 @@ struct obk_plan_s {
     obk::DevArray<float> w32;          // group weights [m]
     obk::DevArray<double> r64;         // FP64 residual, group-major [m]
 
+    // block form (opts.block_k > 0): groups are the k blocks, rows stay in
+    // reordered order (m = n) and the per-group CSC is the per-block CSC
+    std::vector<int64_t> h_bptr;       // block b = rows [bptr[b], bptr[b+1])  [k+1]
+    std::vector<double> h_bcos;        // |cos| of the block centroids, row-major [k*k]
+    std::vector<int32_t> h_partner;    // paired block (-1: Nclass) [k]
+    std::vector<int32_t> h_border;     // blocks in projection order of a sweep [k]
+    obk::DevArray<int64_t> d_bptr, d_btptr;   // row and segment ranges per block [k+1]
+    obk::DevArray<int32_t> d_border;
+    obk::DevArray<double> bres, bp, bu;       // CG residual and direction [n], A_t^T p [n]
+    obk::DevArray<double> bpart;              // per-workgroup partial sums
+    obk::DevArray<uint64_t> bbar;             // grid barrier arrival counter [1]
+    obk::DevArray<int> berr;                  // [1]: a barrier wait timed out
+    obk::DevArray<int64_t> biters;            // CG iterations per block [k]
+    int block_occ = 0;                        // resident workgroups per CU of the projection launch
+
     // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
     // count and element size; replayed on the caller's stream
     struct SweepGraph {
@@ -187,4 +214,5 @@ struct obk_plan_s {
     ~obk_plan_s();
     size_t device_bytes() const;
     bool has_fp32() const { return opts.precision == OBK_FP32_IR; }
+    bool block_form() const { return opts.block_k > 0; }
 };

@@ -632,35 +632,55 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());
         OBK_HIP(hipGetLastError());
     }
-    DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
-    k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                                crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
-    OBK_HIP(hipGetLastError());
-    int64_t nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
-    P.nconflicts = nconf;
-    DevArray<int32_t> cidx; cidx.alloc(nconf);
-    k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                               crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get());
-    OBK_HIP(hipGetLastError());
-
-    tr.mark("conflicts");
-    // ---- a6: first-fit grouping on the host
-    // conflict offsets per row: the exclusive count at the row's first entry
-    // (conflicts are emitted in entry order), nconf past the last entry
-    DevArray<int64_t> cptr_rows; cptr_rows.alloc(n + 1);
-    k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), cptr_rows.get());
-    OBK_HIP(hipGetLastError());
-    std::vector<int64_t> hcptr = to_host(cptr_rows.get(), n + 1, s);
-    std::vector<int32_t> hcidx = to_host(cidx.get(), nconf, s);
-    std::vector<double> hnu = to_host(nu.get(), n, s);
-    std::vector<uint8_t> active(n);
-    for (int64_t i = 0; i < n; i++) active[i] = hnu[i] != 0.0;
     std::vector<int32_t> group(n);
-    P.ngroups = host_first_fit(n, hcptr.data(), hcidx.data(), active.data(), group.data());
-    P.h_group = group;
-    ccount = DevArray<int64_t>(); cidx = DevArray<int32_t>();
+    if (P.block_form()) {
+        // ---- block form: k uniform chunks in order (Section 3.3), the first
+        // k - 1 of floor(n / k) rows, the last of the rest; every row, zero or
+        // not, belongs to its block, and the residual tiles cover all rows
+        const int32_t K = P.opts.block_k;
+        if (K > n) fail(OBK_E_ARG, "block_k exceeds the number of rows");
+        P.h_bptr.assign(K + 1, 0);
+        for (int32_t b = 0; b <= K; b++) P.h_bptr[b] = (int64_t)b * (n / K);
+        P.h_bptr[K] = n;
+        for (int32_t b = 0; b < K; b++)
+            for (int64_t i = P.h_bptr[b]; i < P.h_bptr[b + 1]; i++) group[i] = b;
+        P.ngroups = K;
+        P.nconflicts = 0;
+        P.zero_rows_f2 = 0.0;
+        P.zero_rows_fmax = 0.0;
+        P.h_group = group;
+        tr.mark("conflicts");
+        tr.mark("groups");
+    } else {
+        DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
+        k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                                    crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
+        OBK_HIP(hipGetLastError());
+        int64_t nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
+        P.nconflicts = nconf;
+        DevArray<int32_t> cidx; cidx.alloc(nconf);
+        k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                                   crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get());
+        OBK_HIP(hipGetLastError());
 
-    tr.mark("groups");
+        tr.mark("conflicts");
+        // ---- a6: first-fit grouping on the host
+        // conflict offsets per row: the exclusive count at the row's first entry
+        // (conflicts are emitted in entry order), nconf past the last entry
+        DevArray<int64_t> cptr_rows; cptr_rows.alloc(n + 1);
+        k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), cptr_rows.get());
+        OBK_HIP(hipGetLastError());
+        std::vector<int64_t> hcptr = to_host(cptr_rows.get(), n + 1, s);
+        std::vector<int32_t> hcidx = to_host(cidx.get(), nconf, s);
+        std::vector<double> hnu = to_host(nu.get(), n, s);
+        std::vector<uint8_t> active(n);
+        for (int64_t i = 0; i < n; i++) active[i] = hnu[i] != 0.0;
+        P.ngroups = host_first_fit(n, hcptr.data(), hcidx.data(), active.data(), group.data());
+        P.h_group = group;
+        ccount = DevArray<int64_t>(); cidx = DevArray<int32_t>();
+
+        tr.mark("groups");
+    }
     // ---- a7: group-major relayout
     const int32_t G = P.ngroups;
     std::vector<int64_t> gsize(G + 1, 0);
@@ -715,16 +735,18 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     int64_t T = scan_exclusive_i64(segflag.get(), segflag.get(), me, s);
     P.tcol.alloc(T); P.sptr.alloc(T + 1); P.srow.alloc(me); P.sval.alloc(me);
     DevArray<int64_t> segs_g; segs_g.alloc(std::max(G, 1));
+    OBK_HIP(hipMemsetAsync(segs_g.get(), 0xFF, std::max(G, 1) * sizeof(int64_t), s));   // -1: no segment
     k_seg_emit<<<nblk(me), kT, 0, s>>>(me, gkey.get(), gidx.get(), ccol.get(), crow.get(), cval.get(), dpos.get(),
                                         segflag.get(), P.tcol.get(), P.sptr.get(), P.srow.get(), P.sval.get(),
                                         segs_g.get());
     OBK_HIP(hipGetLastError());
     k_set_i64<<<1, 1, 0, s>>>(P.sptr.get() + T, me);
     std::vector<int64_t> hfirst = to_host(segs_g.get(), std::max(G, 1), s);
-    // every group has at least one row with a nonzero entry, hence a segment
+    // every group has at least one row with a nonzero entry, hence a segment;
+    // a block of the block form may have none (its range is then empty)
     P.h_tptr.assign(G + 1, 0);
-    for (int32_t g = 0; g < G; g++) P.h_tptr[g] = hfirst[g];
     P.h_tptr[G] = T;
+    for (int32_t g = G - 1; g >= 0; g--) P.h_tptr[g] = hfirst[g] >= 0 ? hfirst[g] : P.h_tptr[g + 1];
     for (int32_t g = 0; g < G; g++)
         if (P.h_tptr[g] > P.h_tptr[g + 1] || P.h_tptr[g] < 0)
             fail(OBK_E_HIP, "inconsistent per-group column segments");
@@ -747,6 +769,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
     tr.mark("tiles");
+    if (P.block_form()) block_setup(P, s);
     // ---- FP32 copies for the refinement mode
     if (P.has_fp32()) ensure_fp32(P, s);
 

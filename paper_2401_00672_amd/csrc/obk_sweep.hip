@@ -158,6 +158,7 @@ static void run_sweeps(obk_plan_s& P, const T* rval, const T* rf, const T* rinv,
 
 // enqueue `sweeps` sweeps on x (device, reordered coordinates)
 void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
+    if (P.block_form()) return block_sweeps(P, x, sweeps, s, nullptr);
     run_sweeps<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), x, P.w.get(), sweeps, s);
 }
 
@@ -165,6 +166,7 @@ void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
 // of event time and algorithmic bytes (formulas in obk.h).
 int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
                        int32_t max_out) {
+    if (P.block_form()) return profile_block(P, x, sweeps, s, out, max_out);
     const int32_t G = P.ngroups;
     struct Launch { int kind; double bytes; };
     std::vector<Launch> plan_launches;

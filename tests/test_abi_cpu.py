@@ -35,6 +35,7 @@ def test_opts_default_and_free_null():
     assert L.obk_opts_default(o) == 0
     assert (o.use_rcm, o.precision, o.inner_sweeps, o.check_every, o.reject_inconsistent, o.hbm_budget) == \
         (1, 0, 8, 1, 0, 0)
+    assert (o.block_k, o.block_wgs, o.block_maxit, o.block_tol) == (0, 0, 0, 1e-14)
     L.obk_free(None)
     assert L.obk_opts_default(None) == -1
 
@@ -45,6 +46,12 @@ def test_opts_default_and_free_null():
     (dict(delta=float("nan")), -1),
     (dict(precision=7), -1),
     (dict(check_every=0), -1),
+    (dict(block_k=-1), -1),             # block form: k in [1, 4096], at most the rows
+    (dict(block_k=4097), -1),
+    (dict(block_k=7), -1),              # 6 rows
+    (dict(block_k=2, precision=1), -1), # block form is FP64 only
+    (dict(block_k=2, block_tol=-1.0), -1),
+    (dict(block_k=2, block_maxit=-3), -1),
 ])
 def test_plan_rejects_bad_arguments_before_any_gpu_work(kw, code):
     s = synth.c1(n=6)
