@@ -44,7 +44,7 @@ size_t obk_plan_s::device_bytes() const {
            x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
            b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes() + d_bptr.bytes() + d_btptr.bytes() +
            d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
-           biters.bytes();
+           biters.bytes() + blseg.bytes() + d_bfit.bytes();
 }
 
 namespace {

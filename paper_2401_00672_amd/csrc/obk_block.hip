@@ -123,13 +123,108 @@ struct BlockArgs {
     uint64_t* bar;            // arrival counter (zero at launch)
     int* err;
     int64_t* iters;           // CG iterations per block, accumulated
+    const int32_t* lseg;      // per CSR entry: its column's index in the block's segment list
+    const int32_t* fit;       // per block: 1 if it is projected from LDS
     int64_t sweeps;
+    int32_t lds_path;         // 1: single-workgroup launch with dynamic LDS for the fitting blocks
     int32_t k;
     int32_t maxit;            // 0: 4 rows + 100
     double tol2;              // squared relative stopping tolerance
 };
 
+// Dynamic LDS bytes of a block projected from LDS (nb rows, ns touched
+// columns, eb entries): entry values of the CSR and CSC copies, res, p, u and
+// the touched x in FP64; row and segment offsets in int32; local column and
+// row indices in uint16.
+__host__ __device__ inline int64_t lds_bytes_for(int64_t nb, int64_t ns, int64_t eb) {
+    return 8 * (2 * eb + 2 * nb + 2 * ns) + 4 * (nb + ns + 2) + 4 * eb;
+}
+
+// One projection by a single workgroup with the block resident in LDS: the
+// block's CSR and CSC (local indices), res, p, u and the touched entries of
+// x~ are staged once; the CG iterations then touch no global memory; x~ is
+// written back at the end.  Same operations in the same order as the
+// global-memory form with one workgroup.  Returns the CG iterations.
+__device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, double* lds) {
+    const int t = threadIdx.x;
+    const int64_t r0 = a.bptr[b], nb = a.bptr[b + 1] - r0;
+    const int64_t s0 = a.btptr[b], ns = a.btptr[b + 1] - s0;
+    const int64_t e0 = a.rptr[r0], eb = a.rptr[r0 + nb] - e0;
+    const int64_t q0 = a.sptr[s0];
+    double* rv = dyn;
+    double* sv = rv + eb;
+    double* res = sv + eb;
+    double* pv = res + nb;
+    double* u = pv + nb;
+    double* xs = u + ns;
+    int32_t* roff = reinterpret_cast<int32_t*>(xs + ns);
+    int32_t* soff = roff + nb + 1;
+    uint16_t* lcol = reinterpret_cast<uint16_t*>(soff + ns + 1);
+    uint16_t* lrow = lcol + eb;
+    for (int64_t i = t; i <= nb; i += kBT) roff[i] = (int32_t)(a.rptr[r0 + i] - e0);
+    for (int64_t q = t; q <= ns; q += kBT) soff[q] = (int32_t)(a.sptr[s0 + q] - q0);
+    for (int64_t e = t; e < eb; e += kBT) {
+        rv[e] = a.rval[e0 + e];
+        lcol[e] = (uint16_t)a.lseg[e0 + e];
+        sv[e] = a.sval[q0 + e];
+        lrow[e] = (uint16_t)(a.srow[q0 + e] - r0);
+    }
+    for (int64_t q = t; q < ns; q += kBT) xs[q] = a.x[a.tcol[s0 + q]];
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t i = t; i < nb; i += kBT) {
+        double r = 0.0;
+        if (a.rinv[r0 + i] != 0.0) {
+            double d = 0.0;
+            for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * xs[lcol[e]];
+            r = a.rf[r0 + i] - d;
+        }
+        res[i] = r;
+        pv[i] = 0.0;
+        acc = acc + r * r;
+    }
+    double rr = wg_sum<kBT>(acc, lds);
+    const double rr0 = rr;
+    const int64_t cap = a.maxit > 0 ? a.maxit : 4 * nb + 100;
+    double beta = 0.0;
+    int64_t it = 0;
+    while (rr0 > 0.0 && rr > a.tol2 * rr0 && it < cap) {
+        acc = 0.0;
+        for (int64_t q = t; q < ns; q += kBT) {
+            double sum = 0.0;
+            for (int32_t e = soff[q]; e < soff[q + 1]; e++) {
+                const int i = lrow[e];
+                sum = sum + sv[e] * (res[i] + beta * pv[i]);
+            }
+            u[q] = sum;
+            acc = acc + sum * sum;
+        }
+        const double uu = wg_sum<kBT>(acc, lds);
+        if (!(uu > 0.0)) break;
+        const double alpha = rr / uu;
+        for (int64_t q = t; q < ns; q += kBT) xs[q] = xs[q] + alpha * u[q];
+        acc = 0.0;
+        for (int64_t i = t; i < nb; i += kBT) {
+            const double ri = res[i];
+            pv[i] = ri + beta * pv[i];
+            double d = 0.0;
+            for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * u[lcol[e]];
+            const double rn = ri - alpha * d;
+            res[i] = rn;
+            acc = acc + rn * rn;
+        }
+        const double rn2 = wg_sum<kBT>(acc, lds);
+        beta = rn2 / rr;
+        rr = rn2;
+        it++;
+    }
+    for (int64_t q = t; q < ns; q += kBT) a.x[a.tcol[s0 + q]] = xs[q];
+    __syncthreads();
+    return it;
+}
+
 __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
+    extern __shared__ double dyn[];
     __shared__ double lds[kBT / 64];
     __shared__ int flag;
     uint64_t episode = 0;
@@ -147,6 +242,11 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
         for (int32_t j = 0; j < a.k; j++) {
             double* p0 = a.part + (2 + ((sw * a.k + j) & 1)) * G;
             const int32_t b = a.order[j];
+            if (a.lds_path && a.fit[b]) {
+                const int64_t it = project_lds(a, b, dyn, lds);
+                if (t == 0) a.iters[b] += it;
+                continue;
+            }
             const int64_t r0 = a.bptr[b], nb = a.bptr[b + 1] - r0;
             const int64_t s0 = a.btptr[b], ns = a.btptr[b + 1] - s0;
             const int64_t ra = r0 + nb * w / G, rb = r0 + nb * (w + 1) / G;
@@ -219,6 +319,32 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
             }
             if (w == 0 && t == 0) a.iters[b] += it;
         }
+    }
+}
+
+// local index of each CSR entry's column in its block's (ascending) segment list
+__global__ void k_block_local_seg(int64_t n, int32_t k, const int64_t* __restrict__ bptr,
+                                  const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                  const int64_t* __restrict__ btptr, const int32_t* __restrict__ tcol,
+                                  int32_t* __restrict__ lseg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = k;                // block b: bptr[b] <= i < bptr[b+1]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (bptr[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const int64_t q0 = btptr[lo], q1 = btptr[lo + 1];
+    for (int64_t e = rptr[i]; e < rptr[i + 1]; e++) {
+        const int32_t c = rcol[e];
+        int64_t a = q0, z = q1;
+        while (a < z) {
+            const int64_t mid = a + ((z - a) >> 1);
+            if (tcol[mid] < c) a = mid + 1;
+            else z = mid;
+        }
+        lseg[e] = (int32_t)(a - q0);
     }
 }
 
@@ -364,6 +490,37 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
     for (int32_t a = 0; a < K; a++)
         if (P.h_partner[a] < 0) P.h_border.push_back(a);
     host_to_dev(P.d_border, P.h_border, s);
+    // blocks small enough to be projected from LDS by a one-workgroup launch
+    {
+        const int64_t nnz_act = P.rcol.count;
+        P.blseg.alloc(nnz_act);
+        if (n) {
+            k_block_local_seg<<<nblk(n), 256, 0, s>>>(n, K, P.d_bptr.get(), P.rptr.get(), P.rcol.get(),
+                                                     P.d_btptr.get(), P.tcol.get(), P.blseg.get());
+            OBK_HIP(hipGetLastError());
+        }
+        int dev = 0, max_lds = 0;
+        OBK_HIP(hipGetDevice(&dev));
+        OBK_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const int64_t budget = (int64_t)max_lds - 1024;      // room for the kernel's static LDS
+        std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
+        P.h_bfit.assign(K, 0);
+        P.block_lds = 0;
+        for (int32_t b = 0; b < K; b++) {
+            const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b];
+            const int64_t ns = P.h_tptr[b + 1] - P.h_tptr[b];
+            const int64_t eb = rp[P.h_bptr[b + 1]] - rp[P.h_bptr[b]];
+            const int64_t bytes = lds_bytes_for(nb, ns, eb);
+            if (nb <= 65535 && ns <= 65535 && bytes <= budget) {
+                P.h_bfit[b] = 1;
+                P.block_lds = std::max(P.block_lds, bytes);
+            }
+        }
+        host_to_dev(P.d_bfit, P.h_bfit, s);
+        if (P.block_lds > 0)
+            OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_sweeps),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.block_lds));
+    }
     // projection workspace
     P.bres.alloc(n); P.bp.alloc(n); P.bu.alloc(n);
     P.bpart.alloc(4 * kBT);
@@ -394,6 +551,10 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     a.k = P.opts.block_k;
     a.maxit = std::max(0, P.opts.block_maxit);
     a.tol2 = P.opts.block_tol * P.opts.block_tol;
+    a.lseg = P.blseg.get();
+    a.fit = P.d_bfit.get();
+    a.lds_path = (G == 1 && P.block_lds > 0) ? 1 : 0;
+    const unsigned shmem = a.lds_path ? (unsigned)P.block_lds : 0u;
     OBK_HIP(hipMemsetAsync(P.bbar.get(), 0, sizeof(uint64_t), s));
     OBK_HIP(hipMemsetAsync(P.berr.get(), 0, sizeof(int), s));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -404,7 +565,7 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     }
     void* args[] = {&a};
     hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps), dim3(G), dim3(kBT),
-                                               args, 0, s);
+                                               args, shmem, s);
     if (ms) OBK_HIP(hipEventRecord(e1, s));
     auto* h = static_cast<int*>(pinned_stage(sizeof(int)));
     *h = 0;

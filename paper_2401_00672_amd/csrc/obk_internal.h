@@ -194,6 +194,10 @@ struct obk_plan_s {
     obk::DevArray<uint64_t> bbar;             // grid barrier arrival counter [1]
     obk::DevArray<int> berr;                  // [1]: a barrier wait timed out
     obk::DevArray<int64_t> biters;            // CG iterations per block [k]
+    obk::DevArray<int32_t> blseg;             // per CSR entry: local index of its column in its block
+    obk::DevArray<int32_t> d_bfit;            // per block: projected from LDS in one-workgroup launches
+    std::vector<int32_t> h_bfit;
+    int64_t block_lds = 0;                    // dynamic LDS bytes of a one-workgroup launch (0: none fits)
     int block_occ = 0;                        // resident workgroups per CU of the projection launch
 
     // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
