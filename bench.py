@@ -192,7 +192,7 @@ def bench_block(args) -> dict:
     s = synth.c2(grid=grid)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = obk.plan_system(s, thr, block_k=k)
+    P = obk.plan_system(s, thr, block_k=k, block_wgs=args.block_wgs)
     plan_s = time.perf_counter() - t0
     info = P.blocks()
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
@@ -225,6 +225,7 @@ def bench_block(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"block-form-stencil-{grid}x{grid}-symperm-rcm-k{k}-thr{thr}-fp64-sweep",
                    "n": s.n, "nnz": s.nnz, "k": k, "pairs": len(info["pairs"]), "nclass": len(info["nclass"]),
+                   "workgroups": args.block_wgs or "auto",
                    "cg_iterations_per_sweep": iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": prof["name"],
@@ -483,6 +484,7 @@ def main() -> int:
     ap.add_argument("--block-grid", type=int, default=128, help="block: stencil grid side")
     ap.add_argument("--block-k", type=int, default=16, help="block: number of blocks")
     ap.add_argument("--block-thr", type=float, default=0.02, help="block: centroid cosine threshold")
+    ap.add_argument("--block-wgs", type=int, default=0, help="block: workgroups of the projection launch (0: auto)")
     ap.add_argument("--systems", type=int, default=512)
     ap.add_argument("--inner", type=int, default=8)
     ap.add_argument("--check-every", type=int, default=5)

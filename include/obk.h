@@ -198,7 +198,8 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  * x~ + A_t^+ (f_t - A_t x~); it is computed as x~ + A_t^T y with y from
  * conjugate gradients on A_t A_t^T y = f_t - A_t x~ (started at 0, stopped
  * by opts.block_tol / opts.block_maxit; all-zero rows take no part), all
- * iterations of all projections of a call in one cooperative launch.
+ * iterations of all projections of a call in one launch (cooperative when
+ * it spans several workgroups).
  *
  * obk_plan_blocks (host outputs, each may be NULL): *k; bptr[k+1] the row
  * range of each block in reordered rows; partner[k] the block a block is

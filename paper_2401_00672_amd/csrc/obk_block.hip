@@ -13,8 +13,8 @@
 //     pairs share no column and their cosine is exactly 0;
 //   * the host forms |cos| and pairs the blocks.
 //
-// Sweeps (k_block_sweeps): one cooperative launch of G workgroups runs every
-// projection of the call.  Projection onto block t (rows R, touched columns
+// Sweeps (k_block_sweeps): one launch of G workgroups (cooperative for
+// G > 1) runs every projection of the call.  Projection onto block t (rows R, touched columns
 // S): res = f_R - A_R x~ (all-zero rows: 0), then conjugate gradients on
 // A_R A_R^T y = res in the form that moves x~ itself (x~ += alpha A_R^T d):
 //   phase A (columns of S)  u = A_R^T (res + beta p)              |u|^2
@@ -29,6 +29,7 @@
 // ascending index order.  Every workgroup reduces the G partial sums itself
 // in one fixed order, so all of them take the same decisions with no further
 // synchronisation, and a solve is bitwise repeatable for a given G.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,6 +61,25 @@ __device__ __forceinline__ double wg_sum(double v, double* lds) {
 #pragma unroll
     for (int i = 0; i < NT / 64; i++) t = t + lds[i];
     return t;
+}
+
+// sum over e in [e0, e1) of val[e] * gather(idx[e]), accumulated in
+// ascending e; four entries at a time have their loads issued together.
+template <class I, class F>
+__device__ __forceinline__ double dot_seq(int64_t e0, int64_t e1, const double* val, const I* idx, F gather) {
+    double s = 0.0;
+    int64_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+        const double g0 = gather(idx[e]), g1 = gather(idx[e + 1]), g2 = gather(idx[e + 2]),
+                     g3 = gather(idx[e + 3]);
+        s = s + v0 * g0;
+        s = s + v1 * g1;
+        s = s + v2 * g2;
+        s = s + v3 * g3;
+    }
+    for (; e < e1; e++) s = s + val[e] * gather(idx[e]);
+    return s;
 }
 
 // Barrier over the whole (co-resident) grid on a monotonic arrival counter:
@@ -180,22 +200,21 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
             r = a.rf[r0 + i] - d;
         }
         res[i] = r;
-        pv[i] = 0.0;
+        pv[i] = r + 0.0 * 0.0;     // the first direction, res + beta p with beta = 0, p = 0
         acc = acc + r * r;
     }
     double rr = wg_sum<kBT>(acc, lds);
     const double rr0 = rr;
     const int64_t cap = a.maxit > 0 ? a.maxit : 4 * nb + 100;
-    double beta = 0.0;
     int64_t it = 0;
+    // pv holds the current direction d = res + beta p, formed once per row
+    // after beta is known (the global-memory form forms the same value at
+    // every use), so phase A gathers one vector
     while (rr0 > 0.0 && rr > a.tol2 * rr0 && it < cap) {
         acc = 0.0;
         for (int64_t q = t; q < ns; q += kBT) {
             double sum = 0.0;
-            for (int32_t e = soff[q]; e < soff[q + 1]; e++) {
-                const int i = lrow[e];
-                sum = sum + sv[e] * (res[i] + beta * pv[i]);
-            }
+            for (int32_t e = soff[q]; e < soff[q + 1]; e++) sum = sum + sv[e] * pv[lrow[e]];
             u[q] = sum;
             acc = acc + sum * sum;
         }
@@ -205,18 +224,18 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
         for (int64_t q = t; q < ns; q += kBT) xs[q] = xs[q] + alpha * u[q];
         acc = 0.0;
         for (int64_t i = t; i < nb; i += kBT) {
-            const double ri = res[i];
-            pv[i] = ri + beta * pv[i];
             double d = 0.0;
             for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * u[lcol[e]];
-            const double rn = ri - alpha * d;
+            const double rn = res[i] - alpha * d;
             res[i] = rn;
             acc = acc + rn * rn;
         }
         const double rn2 = wg_sum<kBT>(acc, lds);
-        beta = rn2 / rr;
+        const double beta = rn2 / rr;
         rr = rn2;
         it++;
+        for (int64_t i = t; i < nb; i += kBT) pv[i] = res[i] + beta * pv[i];
+        __syncthreads();
     }
     for (int64_t q = t; q < ns; q += kBT) a.x[a.tcol[s0 + q]] = xs[q];
     __syncthreads();
@@ -256,9 +275,8 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
             for (int64_t i = ra + t; i < rb; i += kBT) {
                 double r = 0.0;
                 if (a.rinv[i] != 0.0) {
-                    double d = 0.0;
-                    const int64_t e1 = a.rptr[i + 1];
-                    for (int64_t e = a.rptr[i]; e < e1; e++) d = d + a.rval[e] * a.x[a.rcol[e]];
+                    const double d = dot_seq(a.rptr[i], a.rptr[i + 1], a.rval, a.rcol,
+                                             [&](int32_t c) { return a.x[c]; });
                     r = a.rf[i] - d;
                 }
                 a.res[i] = r;
@@ -277,12 +295,8 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
                 // phase A: u = A_R^T (res + beta p) on the touched columns
                 acc = 0.0;
                 for (int64_t q = sa + t; q < sb; q += kBT) {
-                    double s = 0.0;
-                    const int64_t e1 = a.sptr[q + 1];
-                    for (int64_t e = a.sptr[q]; e < e1; e++) {
-                        const int32_t i = a.srow[e];
-                        s = s + a.sval[e] * (a.res[i] + beta * a.p[i]);
-                    }
+                    const double s = dot_seq(a.sptr[q], a.sptr[q + 1], a.sval, a.srow,
+                                             [&](int32_t i) { return a.res[i] + beta * a.p[i]; });
                     a.u[a.tcol[q]] = s;
                     acc = acc + s * s;
                 }
@@ -302,9 +316,8 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
                     if (a.rinv[i] == 0.0) continue;
                     const double ri = a.res[i];
                     a.p[i] = ri + beta * a.p[i];
-                    double d = 0.0;
-                    const int64_t e1 = a.rptr[i + 1];
-                    for (int64_t e = a.rptr[i]; e < e1; e++) d = d + a.rval[e] * a.u[a.rcol[e]];
+                    const double d = dot_seq(a.rptr[i], a.rptr[i + 1], a.rval, a.rcol,
+                                             [&](int32_t c) { return a.u[c]; });
                     const double rn = ri - alpha * d;
                     a.res[i] = rn;
                     acc = acc + rn * rn;
@@ -561,12 +574,20 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     if (ms) {
         OBK_HIP(hipEventCreate(&e0));
         OBK_HIP(hipEventCreate(&e1));
-        OBK_HIP(hipEventRecord(e0, s));
     }
-    void* args[] = {&a};
-    hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps), dim3(G), dim3(kBT),
-                                               args, shmem, s);
-    if (ms) OBK_HIP(hipEventRecord(e1, s));
+    hipError_t le = hipSuccess;
+    if (G == 1) {
+        // one workgroup needs no co-residency guarantee: a plain launch, with
+        // the events on its own dispatch packet
+        hipExtLaunchKernelGGL(k_block_sweeps, dim3(1), dim3(kBT), shmem, s, e0, e1, 0, a);
+        le = hipGetLastError();
+    } else {
+        void* args[] = {&a};
+        if (ms) OBK_HIP(hipEventRecord(e0, s));
+        le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps), dim3(G), dim3(kBT), args,
+                                        shmem, s);
+        if (ms) OBK_HIP(hipEventRecord(e1, s));
+    }
     auto* h = static_cast<int*>(pinned_stage(sizeof(int)));
     *h = 0;
     if (le == hipSuccess) le = hipMemcpyAsync(h, P.berr.get(), sizeof(int), hipMemcpyDeviceToHost, s);
@@ -574,7 +595,7 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     if (ms && le == hipSuccess && se == hipSuccess) (void)hipEventElapsedTime(ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    check_hip(le, "hipLaunchCooperativeKernel(k_block_sweeps)");
+    check_hip(le, "launch of k_block_sweeps");
     check_hip(se, "hipStreamSynchronize");
     if (*h) fail(OBK_E_HIP, "a grid barrier of the block projection launch timed out");
 }
