@@ -379,3 +379,42 @@ def block_solve(bp: BlockPlan, sweeps: int, x0: np.ndarray | None = None) -> np.
     """Block plan + sweeps from x0 (default 0), original ordering."""
     xt = np.zeros(bp.n) if x0 is None else permute_vec(bp.p, x0)
     return unpermute(bp.p, block_sweep(bp, xt, sweeps))
+
+
+# ------------------------------------------ block-count criteria (Section 3.6)
+def block_zn_nn(cos: np.ndarray) -> tuple[float, float]:
+    """Definitions 1 and 2 on a k x k cosine table C: the orthogonality
+    proportion zn = n1 / k^2 (n1 = entries of C exactly zero) and the
+    non-orthogonality severity nn = n2 * nm / k^2 (n2 = nonzero entries, nm
+    their mean), i.e. the sum of the nonzero entries over k^2."""
+    C = np.asarray(cos, dtype=np.float64)
+    k = C.shape[0]
+    num = k * k
+    nz = C[C != 0.0]
+    n1 = num - nz.size
+    nm = nz.mean() if nz.size else 0.0
+    return n1 / num, nz.size * nm / num
+
+
+def select_block_k(scores) -> int:
+    """The block count that maximises zn and minimises nn (Section 3.6), read
+    as: the largest zn, then among those the least nn, then the least k.
+    scores: iterable of (k, zn, nn)."""
+    best = None
+    for k, zn, nn in scores:
+        key = (-zn, nn, k)
+        if best is None or key < best[0]:
+            best = (key, k)
+    if best is None:
+        raise ValueError("no candidate block counts")
+    return int(best[1])
+
+
+def block_k_scores(n, rp, ci, v, f, thr, candidates):
+    """(k, zn, nn) of the block plan for every candidate k."""
+    out = []
+    for k in candidates:
+        bp = block_plan(n, rp, ci, v, f, int(k), thr)
+        zn, nn = block_zn_nn(bp.cos)
+        out.append((int(k), zn, nn))
+    return out

@@ -630,3 +630,50 @@ def test_block_mode_converges_to_generating_solution():
     bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 8, 0.1)
     x = oracle.block_solve(bp, 60)
     assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) <= 1e-10
+
+
+# ------------------------------------------ block-count criteria (Section 3.6)
+def test_zn_nn_of_disjoint_blocks():
+    """Definitions 1-2 on the block-diagonal hand case: C = I_4 gives
+    n1 = 12 zero entries of 16 (zn = 0.75) and four nonzero entries of
+    mean 1 (nn = 4 / 16)."""
+    n = 12
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, i] = 2.0
+        D[i, (i + 1) % 3 + 3 * (i // 3)] += 0.5
+    s = synth.from_dense(D, np.ones(n))
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 4, 0.1)
+    zn, nn = oracle.block_zn_nn(bp.cos)
+    assert zn == pytest.approx(0.75, abs=1e-15)
+    assert nn == pytest.approx(0.25, abs=1e-12)
+
+
+def test_zn_nn_of_a_dense_matrix_and_of_a_band():
+    """A dense matrix of equal positive rows has no zero cosine (zn = 0) and
+    every cosine 1 (nn = 1).  A tridiagonal matrix cut into k blocks has
+    nonzero cosines only between a block and itself or a neighbour:
+    n2 = 3k - 2, so zn = 1 - (3k - 2) / k^2."""
+    E = np.ones((8, 8))
+    se = synth.from_dense(E, np.ones(8))
+    zn, nn = oracle.block_zn_nn(oracle.block_plan(se.n, se.row_ptr, se.col, se.val, se.f, 4, 0.1).cos)
+    assert zn == 0.0 and nn == pytest.approx(1.0, abs=1e-12)
+    n = 60
+    T = sp.diags([np.full(n - 1, -1.0), np.full(n, 4.0), np.full(n - 1, -1.0)], [-1, 0, 1]).tocsr()
+    st = synth.from_scipy(T, np.ones(n))
+    for k in (3, 5, 6, 10):
+        bp = oracle.block_plan(st.n, st.row_ptr, st.col, st.val, st.f, k, 0.1)
+        zn, nn = oracle.block_zn_nn(bp.cos)
+        assert zn == pytest.approx(1.0 - (3 * k - 2) / k ** 2, abs=1e-15), k
+        off = np.array([bp.cos[b, b + 1] for b in range(k - 1)])
+        assert np.all(off > 0) and nn == pytest.approx((np.trace(bp.cos) + 2 * off.sum()) / k ** 2, abs=1e-15)
+
+
+def test_block_k_selection_rule():
+    """Largest zn first, then least nn, then least k; one candidate that is
+    best on both criteria is always chosen (the muu example of Section 3.6)."""
+    assert oracle.select_block_k([(2, 0.5, 0.10), (3, 0.4, 0.05), (4, 0.5, 0.20)]) == 2
+    assert oracle.select_block_k([(2, 0.5, 0.30), (3, 0.5, 0.20), (4, 0.5, 0.20)]) == 3
+    assert oracle.select_block_k([(5, 0.1, 0.9), (2, 0.7, 0.1), (9, 0.6, 0.05)]) == 2
+    with pytest.raises(ValueError):
+        oracle.select_block_k([])
