@@ -235,9 +235,15 @@ def bench_block(args) -> dict:
         "us_per_cg_iteration": ms * 1e3 / max(iters, 1),
         "plan_seconds": plan_s,
     }
+    zn, nn = P.block_zn_nn()
+    P.free()
+    # block-count criteria of Section 3.6 over the paper's range k < 20
+    t1 = time.perf_counter()
+    best, scores = obk.select_block_k(s, thr, list(range(2, 20)))
+    res["k_selection"] = {"candidates": "2..19", "chosen": best, "seconds": time.perf_counter() - t1,
+                          "benched_k_zn": zn, "benched_k_nn": nn}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_block(s, k, thr, args.cpu_budget)
-    P.free()
     return res
 
 

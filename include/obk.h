@@ -211,6 +211,25 @@ OBK_API obk_status obk_plan_blocks(obk_plan_t plan, int32_t *k, int64_t *bptr, i
                                    int64_t *cg_iters);
 
 /*
+ * Block-count criteria of Section 3.6 (Definitions 1 and 2) for the block
+ * form.  From the k x k table C of a block-form plan: the orthogonality
+ * proportion zn = (entries of C exactly 0) / k^2 and the non-orthogonality
+ * severity nn = (number of nonzero entries x their mean) / k^2.
+ * obk_block_zn_nn reads them from a plan (OBK_E_ARG if it is not in block
+ * form).  obk_block_select_k plans A once per candidate k (as obk_plan with
+ * opts->block_k = k and delta = thr; opts may be NULL), writes zn[i] and
+ * nn[i] of candidate i (host arrays of n_candidates, each may be NULL) and
+ * *best_k: the candidate of largest zn, then least nn, then least k -- the
+ * paper asks for the k that maximises zn and minimises nn.  Each plan is
+ * freed before the next is built.  Errors: as obk_plan; OBK_E_ARG for an
+ * empty candidate list or a candidate outside [1, 4096].
+ */
+OBK_API obk_status obk_block_zn_nn(obk_plan_t plan, double *zn, double *nn);
+OBK_API obk_status obk_block_select_k(const obk_csr *A, const double *f, double thr, const int32_t *candidates,
+                                      int32_t n_candidates, const obk_opts *opts, obk_stream_t stream,
+                                      int32_t *best_k, double *zn, double *nn);
+
+/*
  * Sweeps on a plan with device-resident iterates, no host synchronisation and
  * no residual (the form a benchmark or a batched driver times): x~ (device,
  * reordered coordinates, n entries) is updated in place by `sweeps` sweeps.

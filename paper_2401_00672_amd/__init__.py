@@ -98,6 +98,9 @@ def lib() -> ctypes.CDLL:
         L.obk_sweep_profile.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(_KernelProfile),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_blocks.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]
+        L.obk_block_zn_nn.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.obk_block_select_k.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, _P, ctypes.c_int32,
+                                         ctypes.POINTER(_Opts), _P, ctypes.POINTER(ctypes.c_int32), _P, _P]
         L.obk_plan_set_opts.argtypes = [_P, ctypes.POINTER(_Opts)]
         L.obk_plan_set_opts.restype = ctypes.c_int
         L.obk_last_error.restype = ctypes.c_char_p
@@ -118,7 +121,7 @@ def lib() -> ctypes.CDLL:
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
-                     "obk_plan_blocks"):
+                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -276,6 +279,12 @@ class Plan:
         _check(lib().obk_plan_groups(self.handle, g.ctypes.data, ctypes.byref(ng)))
         return g, int(ng.value)
 
+    def block_zn_nn(self) -> tuple[float, float]:
+        """obk_block_zn_nn: Definitions 1-2 on the plan's centroid cosine table."""
+        zn, nn = ctypes.c_double(), ctypes.c_double()
+        _check(lib().obk_block_zn_nn(self.handle, ctypes.byref(zn), ctypes.byref(nn)))
+        return zn.value, nn.value
+
     def device_bytes(self) -> int:
         b = ctypes.c_size_t(0)
         _check(lib().obk_plan_bytes(self.handle, ctypes.byref(b)))
@@ -336,6 +345,28 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
                 {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every),
                  "block_wgs": int(block_wgs), "block_maxit": int(block_maxit), "block_tol": float(block_tol)},
                 n_ext=max(nrows, ncols))
+
+
+def select_block_k(s, thr: float, candidates, stream=None):
+    """obk_block_select_k on a ``synth.System`` (host arrays): the block count
+    of largest zn, then least nn, among `candidates` (Section 3.6).  Returns
+    (best_k, [(k, zn, nn), ...])."""
+    rp, ci, v, ff = _host(s.row_ptr, np.int64), _host(s.col, np.int32), _host(s.val, np.float64), \
+        _host(s.f, np.float64)
+    nrows = s.m if hasattr(s, "m") else len(rp) - 1
+    ncols = s.n
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    csr = _Csr(nrows, ncols, len(ci), rp.ctypes.data, ci.ctypes.data if len(ci) else None,
+               v.ctypes.data if len(ci) else None, 0)
+    opts = _Opts()
+    lib().obk_opts_default(ctypes.byref(opts))
+    zn = np.zeros(len(cand))
+    nn = np.zeros(len(cand))
+    best = ctypes.c_int32(0)
+    _check(lib().obk_block_select_k(ctypes.byref(csr), ff.ctypes.data, float(thr), cand.ctypes.data, len(cand),
+                                    ctypes.byref(opts), _stream(stream), ctypes.byref(best), zn.ctypes.data,
+                                    nn.ctypes.data))
+    return int(best.value), [(int(k), float(a), float(b)) for k, a, b in zip(cand, zn, nn)]
 
 
 def rcm_host(gptr, gadj) -> np.ndarray:

@@ -69,6 +69,21 @@ template <class F> obk_status guarded(F&& body) {
 
 hipStream_t as_hip(obk_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Definitions 1 and 2 on the plan's centroid cosine table
+void block_criteria(const obk_plan_s& P, double* zn, double* nn) {
+    const size_t num = P.h_bcos.size();
+    size_t n2 = 0;
+    double sum = 0.0;
+    for (double c : P.h_bcos)
+        if (c != 0.0) {
+            n2++;
+            sum += c;
+        }
+    const double nm = n2 ? sum / (double)n2 : 0.0;
+    if (zn) *zn = num ? (double)(num - n2) / (double)num : 0.0;
+    if (nn) *nn = num ? (double)n2 * nm / (double)num : 0.0;
+}
+
 void check_block_opts(const obk_opts& o) {
     if (o.block_k < 0 || o.block_k > 4096) obk::fail(OBK_E_ARG, "block_k must be in [0, 4096]");
     if (o.block_k > 0 && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "the block form runs in OBK_FP64 only");
@@ -234,6 +249,48 @@ obk_status obk_plan_blocks(obk_plan_t plan, int32_t* k, int64_t* bptr, int32_t* 
             OBK_HIP(hipSetDevice(plan->device));
             OBK_HIP(hipMemcpy(cg_iters, plan->biters.get(), K * sizeof(int64_t), hipMemcpyDeviceToHost));
         }
+    });
+}
+
+obk_status obk_block_zn_nn(obk_plan_t plan, double* zn, double* nn) {
+    return guarded([&] {
+        if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
+        if (!plan->block_form()) obk::fail(OBK_E_ARG, "the plan is not in block form");
+        block_criteria(*plan, zn, nn);
+    });
+}
+
+obk_status obk_block_select_k(const obk_csr* A, const double* f, double thr, const int32_t* candidates,
+                              int32_t n_candidates, const obk_opts* opts, obk_stream_t stream, int32_t* best_k,
+                              double* zn, double* nn) {
+    return guarded([&] {
+        if (!best_k) obk::fail(OBK_E_ARG, "best_k must not be NULL");
+        if (n_candidates < 1 || !candidates) obk::fail(OBK_E_ARG, "no candidate block counts");
+        for (int32_t i = 0; i < n_candidates; i++)
+            if (candidates[i] < 1 || candidates[i] > 4096) obk::fail(OBK_E_ARG, "a candidate is outside [1, 4096]");
+        obk_opts o;
+        obk_opts_default(&o);
+        if (opts) o = *opts;
+        double bz = 0.0, bn = 0.0;
+        int32_t bk = -1;
+        for (int32_t i = 0; i < n_candidates; i++) {
+            o.block_k = candidates[i];
+            obk_plan_t P = nullptr;
+            const obk_status st = obk_plan(A, f, thr, &o, stream, &P);
+            if (st != OBK_OK) obk::fail(st, obk::last_error_cstr());
+            double z = 0.0, q = 0.0;
+            block_criteria(*P, &z, &q);
+            obk_free(P);
+            if (zn) zn[i] = z;
+            if (nn) nn[i] = q;
+            const int32_t k = candidates[i];
+            if (bk < 0 || z > bz || (z == bz && (q < bn || (q == bn && k < bk)))) {
+                bk = k;
+                bz = z;
+                bn = q;
+            }
+        }
+        *best_k = bk;
     });
 }
 

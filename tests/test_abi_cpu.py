@@ -123,3 +123,11 @@ def test_host_stage_argument_errors():
     assert obk.lib().obk_rcm_host(-1, None, None, None) == -1
     assert obk.lib().obk_first_fit_host(3, None, None, None, None, None) == -1
     assert obk.rcm_host(np.zeros(1, np.int64), np.zeros(0, np.int32)).size == 0
+
+
+def test_block_select_k_rejects_bad_candidates_before_any_gpu_work():
+    s = synth.c1(n=6)
+    for cands in ([], [0], [4097], [2, -1]):
+        with pytest.raises(obk.ObkError) as ei:
+            obk.select_block_k(s, 0.1, cands)
+        assert ei.value.code == -1

@@ -226,3 +226,25 @@ def test_block_form_rejected_by_batch():
         assert ei.value.code == -1
         with pytest.raises(obk.ObkError):
             P.set_opts(precision=obk.FP32_IR)
+
+
+@pytest.mark.parametrize("name,maker,thr", [
+    ("stencil24", lambda: synth.c2(grid=24), 0.02),
+    ("c1-companion-600", lambda: synth.c1(n=600, companion=True), 0.02),
+    ("c1-500", lambda: synth.c1(n=500), 0.1),
+])
+def test_block_count_selection_matches_oracle(name, maker, thr):
+    """Section 3.6: zn and nn of every candidate k, and the chosen k, equal the
+    oracle's (zn exactly: it counts exact zeros of the cosine table)."""
+    s = maker()
+    cands = list(range(2, 20))
+    want = oracle.block_k_scores(s.n, s.row_ptr, s.col, s.val, s.f, thr, cands)
+    k_o = oracle.select_block_k(want)
+    k, got = obk.select_block_k(s, thr, cands)
+    _say(f"[block] {name}: chosen k {k} (oracle {k_o}); zn/nn {[(a, round(b, 4), round(c, 4)) for a, b, c in got]}")
+    for (ka, za, na), (kb, zb, nb) in zip(got, want):
+        assert ka == kb and za == zb and abs(na - nb) <= 1e-12
+    assert k == k_o
+    with obk.plan_system(s, thr, block_k=k) as P:
+        zn, nn = P.block_zn_nn()
+    assert (zn, nn) == next((z, q) for kk, z, q in got if kk == k)
