@@ -66,6 +66,18 @@ def lib():
         L.orc_unpermute.argtypes = [_i64, _p, _p, _p]
         L.orc_permute_vec.restype = None
         L.orc_permute_vec.argtypes = [_i64, _p, _p, _p]
+        L.orc_norms_z.restype = None
+        L.orc_norms_z.argtypes = [_i64, _p, _p, _p, _p, _p]
+        L.orc_cosine_z.restype = _f64
+        L.orc_cosine_z.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
+        L.orc_conflicts_z.restype = _i64
+        L.orc_conflicts_z.argtypes = [_i64, _p, _p, _p, _p, _p, _f64, _p, _p]
+        L.orc_sweep_z.restype = ctypes.c_int
+        L.orc_sweep_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _p, _p, _i64]
+        L.orc_rowwise_z.restype = None
+        L.orc_rowwise_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p]
+        L.orc_relres_z.restype = _f64
+        L.orc_relres_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p]
         L.orc_refine.restype = _i64
         L.orc_refine.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64, _i64, _f64, _p]
         _lib = L
@@ -418,3 +430,101 @@ def block_k_scores(n, rp, ci, v, f, thr, candidates):
         zn, nn = block_zn_nn(bp.cos)
         out.append((int(k), zn, nn))
     return out
+
+
+
+# ----------------------------------------------------- complex systems (kim1)
+@dataclasses.dataclass
+class ComplexPlan:
+    """Plan of a complex system: the real plan's steps with the complex norm and
+    cosine (orc_*_z in the C file); values in separate real/imaginary arrays."""
+    n: int
+    p: np.ndarray
+    rp: np.ndarray
+    ci: np.ndarray
+    vr: np.ndarray
+    vi: np.ndarray
+    fr: np.ndarray
+    fi: np.ndarray
+    nu: np.ndarray
+    inv: np.ndarray
+    group: np.ndarray
+    ngroups: int
+
+
+def norms_complex(n, rp, vr, vi):
+    nu = np.empty(n)
+    inv = np.empty(n)
+    lib().orc_norms_z(n, _ptr(_c(rp, np.int64)), _ptr(_c(vr, np.float64)), _ptr(_c(vi, np.float64)),
+                      _ptr(nu), _ptr(inv))
+    return nu, inv
+
+
+def cosine_complex(i, j, rp, ci, vr, vi, nu) -> float:
+    """|a_i^H a_j| / (||a_i|| ||a_j||) over the common columns."""
+    return float(lib().orc_cosine_z(int(i), int(j), _ptr(rp), _ptr(ci), _ptr(vr), _ptr(vi), _ptr(nu)))
+
+
+def plan_complex(n, rp, ci, vz, fz, delta, *, use_rcm: bool = True) -> ComplexPlan:
+    """Algorithm 4, first four steps, over C: RCM on the pattern (as for real
+    systems), the same symmetric permutation of the real and imaginary parts,
+    complex norms and cosines, first-fit grouping."""
+    vz = np.asarray(vz, dtype=np.complex128)
+    fz = np.asarray(fz, dtype=np.complex128)
+    vr, vi = _c(vz.real, np.float64), _c(vz.imag, np.float64)
+    fr, fi = _c(fz.real, np.float64), _c(fz.imag, np.float64)
+    if validate(n, rp, ci, vr, fr) != 0 or validate(n, rp, ci, vi, fi) != 0:
+        raise ValueError("invalid system")
+    p = rcm(n, rp, ci) if use_rcm else np.arange(n, dtype=np.int32)
+    trp, tci, tvr, tfr = permute(n, rp, ci, vr, fr, p)
+    _, _, tvi, tfi = permute(n, rp, ci, vi, fi, p)
+    nu, inv = norms_complex(n, trp, tvr, tvi)
+    cptr = np.zeros(n + 1, dtype=np.int64)
+    total = lib().orc_conflicts_z(n, _ptr(trp), _ptr(tci), _ptr(tvr), _ptr(tvi), _ptr(nu), float(delta),
+                                  _ptr(cptr), None)
+    cidx = np.zeros(max(int(total), 1), dtype=np.int32)
+    lib().orc_conflicts_z(n, _ptr(trp), _ptr(tci), _ptr(tvr), _ptr(tvi), _ptr(nu), float(delta), _ptr(cptr),
+                          _ptr(cidx))
+    group, ng = groups(n, nu, cptr, cidx[:total])
+    return ComplexPlan(n, p, trp, tci, tvr, tvi, tfr, tfi, nu, inv, group, ng)
+
+
+def sweep_complex(pl: ComplexPlan, xt: np.ndarray, sweeps: int) -> np.ndarray:
+    """O8 over C on a reordered complex iterate."""
+    xr = np.array(np.real(xt), dtype=np.float64, copy=True)
+    xi = np.array(np.imag(xt), dtype=np.float64, copy=True)
+    rc = lib().orc_sweep_z(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.vr), _ptr(pl.vi), _ptr(pl.fr), _ptr(pl.fi),
+                           _ptr(pl.inv), _ptr(pl.group), pl.ngroups, _ptr(xr), _ptr(xi), int(sweeps))
+    if rc != 0:
+        raise RuntimeError(f"orc_sweep_z failed: {rc}")
+    return xr + 1j * xi
+
+
+def rowwise_complex(pl: ComplexPlan, rows, xt: np.ndarray) -> np.ndarray:
+    xr = np.array(np.real(xt), dtype=np.float64, copy=True)
+    xi = np.array(np.imag(xt), dtype=np.float64, copy=True)
+    rows = _c(rows, np.int32)
+    lib().orc_rowwise_z(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.vr), _ptr(pl.vi), _ptr(pl.fr), _ptr(pl.fi),
+                        _ptr(pl.inv), _ptr(rows), len(rows), _ptr(xr), _ptr(xi))
+    return xr + 1j * xi
+
+
+def relres_complex(n, rp, ci, vz, fz, xz) -> float:
+    vz, fz, xz = (np.asarray(a, dtype=np.complex128) for a in (vz, fz, xz))
+    return float(lib().orc_relres_z(n, _ptr(_c(rp, np.int64)), _ptr(_c(ci, np.int32)), _ptr(_c(vz.real, np.float64)),
+                                    _ptr(_c(vz.imag, np.float64)), _ptr(_c(fz.real, np.float64)),
+                                    _ptr(_c(fz.imag, np.float64)), _ptr(_c(xz.real, np.float64)),
+                                    _ptr(_c(xz.imag, np.float64))))
+
+
+def solve_complex(pl: ComplexPlan, sweeps: int, x0: np.ndarray | None = None) -> np.ndarray:
+    """Plan + sweeps from x0 (default 0), original ordering."""
+    xt = np.zeros(pl.n, dtype=np.complex128) if x0 is None else np.asarray(x0, dtype=np.complex128)[pl.p]
+    xt = sweep_complex(pl, xt, sweeps)
+    x = np.empty(pl.n, dtype=np.complex128)
+    x[pl.p] = xt
+    return x
+
+
+def plan_system_complex(s, delta, **kw) -> ComplexPlan:
+    return plan_complex(s.n, s.row_ptr, s.col, s.val, s.f, delta, **kw)

@@ -516,3 +516,196 @@ int64_t orc_refine(int64_t n, const int64_t *rp, const int32_t *ci, const double
     free(r); free(d);
     return steps;
 }
+
+/* ------------------------------------------------------------- complex ----
+ * The complex case: the paper solves the complex matrix kim1 with the same
+ * algorithm (its discussion of Table 4).  Entries are held as separate real
+ * (vr) and imaginary (vi) arrays on the pattern of O4.  Over C:
+ *   row norm        nu_i = sum_k (re a_ik^2 + im a_ik^2), ascending k;
+ *   row cosine      d = a_i^H a_j = sum over common columns, ascending, of
+ *                   conj(a_ic) a_jc, i.e. with a = a_ic, b = a_jc:
+ *                     re d = re d + (re a re b + im a im b),
+ *                     im d = im d + (re a im b - im a re b);
+ *                   cos_ij = sqrt(re d^2 + im d^2) / sqrt(nu_i nu_j);
+ *   row projection  eq. (1.2) over C: x = x + (f_i - a_i x) / nu_i a_i^H, with
+ *                     a_i x = sum_k a_ik x_k (ascending k),
+ *                     re += re a re x - im a im x, im += re a im x + im a re x,
+ *                   and the update of x_c adding w conj(a_ic):
+ *                     re += re w re a + im w im a, im += im w re a - re w im a.
+ * The group sweep is O8 with these operations; each sum is accumulated in
+ * the order given.                                                          */
+void orc_norms_z(int64_t n, const int64_t *rp, const double *vr, const double *vi, double *nu, double *inv)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + (vr[k] * vr[k] + vi[k] * vi[k]);
+        nu[i] = s;
+        inv[i] = (s != 0.0) ? 1.0 / s : 0.0;
+    }
+}
+
+double orc_cosine_z(int64_t i, int64_t j, const int64_t *rp, const int32_t *ci, const double *vr,
+                    const double *vi, const double *nu)
+{
+    double dr = 0.0, di = 0.0;
+    int shared = 0;
+    int64_t a = rp[i], b = rp[j];
+    while (a < rp[i + 1] && b < rp[j + 1]) {
+        if (ci[a] < ci[b]) a++;
+        else if (ci[a] > ci[b]) b++;
+        else {
+            dr = dr + (vr[a] * vr[b] + vi[a] * vi[b]);
+            di = di + (vr[a] * vi[b] - vi[a] * vr[b]);
+            shared = 1;
+            a++;
+            b++;
+        }
+    }
+    if (!shared || nu[i] == 0.0 || nu[j] == 0.0) return 0.0;
+    return sqrt(dr * dr + di * di) / sqrt(nu[i] * nu[j]);
+}
+
+int64_t orc_conflicts_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *vr, const double *vi,
+                        const double *nu, double delta, int64_t *cptr, int32_t *cidx)
+{
+    int64_t nnz = rp[n];
+    int64_t *cp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *cr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!cp || !cr || !fill || !mark || !cand) {
+        free(cp); free(cr); free(fill); free(mark); free(cand); return ORC_E_NOMEM;
+    }
+    for (int64_t k = 0; k < nnz; k++) cp[ci[k] + 1]++;
+    for (int64_t c = 0; c < n; c++) cp[c + 1] += cp[c];
+    for (int64_t c = 0; c < n; c++) fill[c] = cp[c];
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) cr[fill[ci[k]]++] = (int32_t)i;
+    for (int64_t j = 0; j < n; j++) mark[j] = -1;
+    int64_t total = 0;
+    cptr[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t ncand = 0;
+        if (nu[i] != 0.0) {
+            for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                int32_t c = ci[k];
+                for (int64_t t = cp[c]; t < cp[c + 1]; t++) {
+                    int32_t j = cr[t];
+                    if (j < i && mark[j] != i) { mark[j] = i; cand[ncand++] = j; }
+                }
+            }
+        }
+        qsort(cand, (size_t)ncand, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < ncand; t++) {
+            int32_t j = cand[t];
+            if (nu[j] == 0.0) continue;
+            if (orc_cosine_z(i, j, rp, ci, vr, vi, nu) >= delta) {
+                if (cidx) cidx[total] = j;
+                total++;
+            }
+        }
+        cptr[i + 1] = total;
+    }
+    free(cp); free(cr); free(fill); free(mark); free(cand);
+    return total;
+}
+
+int orc_sweep_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *vr, const double *vi,
+                const double *fr, const double *fi, const double *inv, const int32_t *group, int32_t ngroups,
+                double *xr, double *xi, int64_t sweeps)
+{
+    int64_t *gp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
+    int32_t *gr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ngroups + 1));
+    double *wr = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *wi = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *tr = (double *)calloc((size_t)n + 1, sizeof(double));
+    double *ti = (double *)calloc((size_t)n + 1, sizeof(double));
+    char *touched = (char *)calloc((size_t)n + 1, 1);
+    int32_t *tlist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!gp || !gr || !fill || !wr || !wi || !tr || !ti || !touched || !tlist) {
+        free(gp); free(gr); free(fill); free(wr); free(wi); free(tr); free(ti); free(touched); free(tlist);
+        return ORC_E_NOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) gp[group[i] + 1]++;
+    for (int32_t g = 0; g < ngroups; g++) gp[g + 1] += gp[g];
+    for (int32_t g = 0; g < ngroups; g++) fill[g] = gp[g];
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) gr[fill[group[i]]++] = (int32_t)i;
+    for (int64_t it = 0; it < sweeps; it++) {
+        for (int32_t g = 0; g < ngroups; g++) {
+            for (int64_t a = gp[g]; a < gp[g + 1]; a++) {
+                int32_t i = gr[a];
+                double sr = 0.0, si = 0.0;
+                for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                    int32_t c = ci[k];
+                    sr = sr + (vr[k] * xr[c] - vi[k] * xi[c]);
+                    si = si + (vr[k] * xi[c] + vi[k] * xr[c]);
+                }
+                wr[i] = (fr[i] - sr) * inv[i];
+                wi[i] = (fi[i] - si) * inv[i];
+            }
+            int64_t nt = 0;
+            for (int64_t a = gp[g]; a < gp[g + 1]; a++) {
+                int32_t i = gr[a];
+                for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                    int32_t c = ci[k];
+                    if (!touched[c]) { touched[c] = 1; tr[c] = 0.0; ti[c] = 0.0; tlist[nt++] = c; }
+                    tr[c] = tr[c] + (wr[i] * vr[k] + wi[i] * vi[k]);
+                    ti[c] = ti[c] + (wi[i] * vr[k] - wr[i] * vi[k]);
+                }
+            }
+            for (int64_t a = 0; a < nt; a++) {
+                int32_t c = tlist[a];
+                xr[c] = xr[c] + tr[c];
+                xi[c] = xi[c] + ti[c];
+                touched[c] = 0;
+            }
+        }
+    }
+    free(gp); free(gr); free(fill); free(wr); free(wi); free(tr); free(ti); free(touched); free(tlist);
+    return ORC_OK;
+}
+
+/* Sequential complex row projections in a given order (eq. 1.2 over C). */
+void orc_rowwise_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *vr, const double *vi,
+                   const double *fr, const double *fi, const double *inv, const int32_t *rows, int64_t nrows,
+                   double *xr, double *xi)
+{
+    (void)n;
+    for (int64_t a = 0; a < nrows; a++) {
+        int32_t i = rows[a];
+        double sr = 0.0, si = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t c = ci[k];
+            sr = sr + (vr[k] * xr[c] - vi[k] * xi[c]);
+            si = si + (vr[k] * xi[c] + vi[k] * xr[c]);
+        }
+        double wr = (fr[i] - sr) * inv[i], wi = (fi[i] - si) * inv[i];
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t c = ci[k];
+            xr[c] = xr[c] + (wr * vr[k] + wi * vi[k]);
+            xi[c] = xi[c] + (wi * vr[k] - wr * vi[k]);
+        }
+    }
+}
+
+/* Complex residual norm ratio ||f - A x|| / ||f|| (sums of |.|^2, ascending). */
+double orc_relres_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *vr, const double *vi,
+                    const double *fr, const double *fi, const double *xr, const double *xi)
+{
+    double res2 = 0.0, rhs2 = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+            int32_t c = ci[k];
+            sr = sr + (vr[k] * xr[c] - vi[k] * xi[c]);
+            si = si + (vr[k] * xi[c] + vi[k] * xr[c]);
+        }
+        double er = fr[i] - sr, ei = fi[i] - si;
+        res2 = res2 + (er * er + ei * ei);
+        rhs2 = rhs2 + (fr[i] * fr[i] + fi[i] * fi[i]);
+    }
+    if (rhs2 == 0.0) return res2 == 0.0 ? 0.0 : -1.0;
+    return sqrt(res2) / sqrt(rhs2);
+}

@@ -20,6 +20,9 @@ not available here; the families below stand in for them:
 * ``c5``        serving requests, n log-uniform in [500, 5e5], 4..16 nnz/row.
 * ``companion=True`` replaces the diagonal by U(1,2) + sum_j |a_ij| (row
   diagonal dominance), keeping pattern, off-diagonal values and seeds.
+* ``c1z``, ``c2z`` complex counterparts of ``c1`` and ``c2`` (the paper also
+  solves the complex matrix kim1): same patterns, complex values, complex
+  x*; ``c2z(grid=196)`` has kim1's order (38,416 rows against 38,415).
 
 Conventions: ``numpy.random.Generator(PCG64(seed))`` with
 ``seed = 1000*config + system_index``.  Draw order per system: per-row nnz
@@ -41,7 +44,7 @@ import scipy.sparse as sp
 __all__ = [
     "System", "seed_for", "random_rows", "stencil", "c1", "c2", "c3",
     "c4_sizes", "c4_system", "c5_sizes", "c5_system", "c5_arrivals",
-    "from_dense", "from_scipy", "RectSystem", "rect",
+    "from_dense", "from_scipy", "RectSystem", "rect", "ComplexSystem", "c1z", "c2z",
 ]
 
 
@@ -289,3 +292,96 @@ def rect(m: int, n: int, density: float, index: int = 0) -> RectSystem:
                       f=np.ascontiguousarray(f, dtype=np.float64),
                       x_star=np.ascontiguousarray(x_star, dtype=np.float64),
                       name=f"rect-{m}x{n}-d{density}", seed=seed)
+
+
+# ------------------------------------------------------------ complex systems
+@dataclasses.dataclass
+class ComplexSystem:
+    """A square sparse complex system in CSR form with its generating solution."""
+    n: int
+    row_ptr: np.ndarray      # int64 [n+1]
+    col: np.ndarray          # int32 [nnz]
+    val: np.ndarray          # complex128 [nnz]
+    f: np.ndarray            # complex128 [n]
+    x_star: np.ndarray       # complex128 [n]
+    name: str = ""
+    seed: int = -1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.size)
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def _pack_z(A, x_star, name: str, seed: int) -> ComplexSystem:
+    A = sp.csr_matrix(A, dtype=np.complex128)
+    A.sum_duplicates()
+    A.sort_indices()
+    f = A @ x_star
+    return ComplexSystem(n=A.shape[0],
+                         row_ptr=np.ascontiguousarray(A.indptr, dtype=np.int64),
+                         col=np.ascontiguousarray(A.indices, dtype=np.int32),
+                         val=np.ascontiguousarray(A.data, dtype=np.complex128),
+                         f=np.ascontiguousarray(f, dtype=np.complex128),
+                         x_star=np.ascontiguousarray(x_star, dtype=np.complex128), name=name, seed=seed)
+
+
+def c1z(index: int = 0, *, n: int = 2000, companion: bool = False) -> ComplexSystem:
+    """Complex counterpart of c1: 4 off-diagonals per row at distinct uniform
+    columns with N(0,1) + i N(0,1) values, a diagonal of modulus U(1,2) (plus
+    sum_j |a_ij| for the companion) and phase U(0, 2 pi), then a random
+    symmetric permutation.  Seed 1000 * 7 + index; draw order: columns,
+    off-diagonal real parts, imaginary parts, diagonal moduli, phases,
+    permutation, x* real parts, imaginary parts."""
+    seed = seed_for(7, index)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = np.full(n, 4, dtype=np.int64)
+    cols, mask = _distinct_offdiag_columns(rng, n, k)
+    off_re = rng.standard_normal(size=cols.shape)
+    off_im = rng.standard_normal(size=cols.shape)
+    mod = rng.uniform(1.0, 2.0, size=n)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n)
+    rr = np.repeat(np.arange(n, dtype=np.int64), k)
+    vv = off_re[mask] + 1j * off_im[mask]
+    if companion:
+        mod = mod + np.bincount(rr, weights=np.abs(vv), minlength=n)
+    diag = mod * np.exp(1j * phase)
+    A = sp.csr_matrix((np.concatenate([vv, diag]),
+                       (np.concatenate([rr, np.arange(n)]), np.concatenate([cols[mask], np.arange(n)]))),
+                      shape=(n, n), dtype=np.complex128)
+    perm = rng.permutation(n)
+    A = A[perm][:, perm]
+    x_star = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return _pack_z(A, x_star, f"c1z-n{n}" + ("-companion" if companion else ""), seed)
+
+
+def c2z(index: int = 0, *, grid: int = 1024) -> ComplexSystem:
+    """Complex counterpart of c2: the 5-point stencil pattern with -1 + 0.25 i g
+    (g ~ N(0,1)) to each neighbour and 4 + U(0, 0.1) + i U(-0.5, 0.5) on the
+    diagonal, under a random symmetric permutation.  Seed 1000 * 8 + index;
+    draw order: neighbour imaginary parts, diagonal real parts, diagonal
+    imaginary parts, permutation, x* real parts, imaginary parts."""
+    seed = seed_for(8, index)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = grid * grid
+    idx = np.arange(n, dtype=np.int64).reshape(grid, grid)
+    rows, cols = [], []
+    for dr, dc in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        r0, r1 = max(0, -dr), grid - max(0, dr)
+        c0, c1 = max(0, -dc), grid - max(0, dc)
+        rows.append(idx[r0:r1, c0:c1].ravel())
+        cols.append(idx[r0 + dr:r1 + dr, c0 + dc:c1 + dc].ravel())
+    rr = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    off = -1.0 + 0.25j * rng.standard_normal(rr.size)
+    dre = 4.0 + rng.uniform(0.0, 0.1, size=n)
+    dim = rng.uniform(-0.5, 0.5, size=n)
+    A = sp.csr_matrix((np.concatenate([off, dre + 1j * dim]),
+                       (np.concatenate([rr, np.arange(n)]), np.concatenate([cc, np.arange(n)]))),
+                      shape=(n, n), dtype=np.complex128)
+    perm = rng.permutation(n)
+    A = A[perm][:, perm]
+    x_star = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return _pack_z(A, x_star, f"c2z-grid{grid}", seed)

@@ -37,6 +37,15 @@ MUTANTS = [
     ("unpermute_wrong_direction", "for (int64_t t = 0; t < n; t++) x[p[t]] = xt[t];",
      "for (int64_t t = 0; t < n; t++) x[t] = xt[p[t]];"),
     ("refine_unscaled", "x[i] = x[i] + sigma * d[i];", "x[i] = x[i] + d[i];"),
+    ("z_cosine_no_conjugate", "di = di + (vr[a] * vi[b] - vi[a] * vr[b]);",
+     "di = di + (vr[a] * vi[b] + vi[a] * vr[b]);"),
+    ("z_norm_real_part_only", "s = s + (vr[k] * vr[k] + vi[k] * vi[k]);", "s = s + vr[k] * vr[k];"),
+    ("z_update_no_conjugate", "ti[c] = ti[c] + (wi[i] * vr[k] - wr[i] * vi[k]);",
+     "ti[c] = ti[c] + (wi[i] * vr[k] + wr[i] * vi[k]);"),
+    ("z_product_sign", "sr = sr + (vr[k] * xr[c] - vi[k] * xi[c]);\n"
+     "                    si = si + (vr[k] * xi[c] + vi[k] * xr[c]);\n                }\n                wr[i]",
+     "sr = sr + (vr[k] * xr[c] + vi[k] * xi[c]);\n"
+     "                    si = si + (vr[k] * xi[c] + vi[k] * xr[c]);\n                }\n                wr[i]"),
 ]
 
 

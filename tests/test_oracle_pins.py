@@ -677,3 +677,86 @@ def test_block_k_selection_rule():
     assert oracle.select_block_k([(5, 0.1, 0.9), (2, 0.7, 0.1), (9, 0.6, 0.05)]) == 2
     with pytest.raises(ValueError):
         oracle.select_block_k([])
+
+
+
+# ------------------------------------------------ complex systems (kim1 case)
+def _as_complex(s):
+    return synth.ComplexSystem(s.n, s.row_ptr, s.col, s.val.astype(np.complex128), s.f.astype(np.complex128),
+                               s.x_star.astype(np.complex128), s.name + "-as-complex", s.seed)
+
+
+def test_complex_oracle_on_a_real_system_is_the_real_oracle():
+    """Imaginary parts 0: every complex operation reduces exactly to its real
+    counterpart, so the permutation, the groups and the iterate equal the
+    (separately pinned) real oracle's bit for bit."""
+    s = synth.c1(n=300)
+    pr = oracle.plan_system(s, 0.1)
+    pz = oracle.plan_system_complex(_as_complex(s), 0.1)
+    assert np.array_equal(pr.p, pz.p) and np.array_equal(pr.group, pz.group) and pr.ngroups == pz.ngroups
+    xr = oracle.solve(pr, 5)
+    xz = oracle.solve_complex(pz, 5)
+    assert np.array_equal(xz.real, xr) and not np.any(xz.imag)
+
+
+def test_complex_cosine_is_the_hermitian_cosine():
+    """|a_i^H a_j| / (||a_i|| ||a_j||), against numpy's conjugating dot."""
+    s = synth.c1z(n=200)
+    pz = oracle.plan_system_complex(s, 0.1)
+    A = sp.csr_matrix((pz.vr + 1j * pz.vi, pz.ci, pz.rp), shape=(s.n, s.n)).toarray()
+    rng = np.random.default_rng(3)
+    checked = 0
+    for _ in range(400):
+        i, j = rng.integers(0, s.n, 2)
+        if i == j or not np.any((A[i] != 0) & (A[j] != 0)):
+            continue
+        want = abs(np.vdot(A[i], A[j])) / (np.linalg.norm(A[i]) * np.linalg.norm(A[j]))
+        assert oracle.cosine_complex(i, j, pz.rp, pz.ci, pz.vr, pz.vi, pz.nu) == pytest.approx(want, rel=1e-13)
+        checked += 1
+    assert checked > 20
+    assert np.allclose(pz.nu, np.sum(np.abs(A) ** 2, axis=1), rtol=1e-14)
+
+
+def test_complex_orthogonal_group_step_is_the_pseudo_inverse_projection():
+    """Rows of a unitary (DFT) matrix are mutually orthogonal: they form one
+    group, and one sweep is x + pinv(A)(f - A x) over C (eq. 1.3)."""
+    m = 16
+    F = np.exp(-2j * np.pi * np.outer(np.arange(m), np.arange(m)) / m) / np.sqrt(m)
+    A = F[:8] * np.array([1.0, 2.0, 0.5, 3.0, 1.5, 1.0, 0.25, 2.5])[:, None]
+    A = np.vstack([A, np.zeros((m - 8, m))])       # square, with zero rows
+    xs = np.random.default_rng(5).standard_normal(m) + 1j * np.random.default_rng(6).standard_normal(m)
+    S = sp.csr_matrix(A)
+    S.sort_indices()
+    z = synth.ComplexSystem(m, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.astype(np.complex128),
+                            S @ xs, xs, "dft", -1)
+    pz = oracle.plan_system_complex(z, 0.1, use_rcm=False)
+    assert pz.ngroups == 1
+    x0 = np.random.default_rng(7).standard_normal(m) + 0j
+    x1 = oracle.solve_complex(pz, 1, x0)
+    want = x0 + np.linalg.pinv(A) @ (z.f - A @ x0)
+    assert np.linalg.norm(x1 - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_complex_projection_is_phase_invariant():
+    """Scaling row i and f_i by e^{i theta} leaves the hyperplane, hence every
+    projection, unchanged (a missing conjugate in the update breaks this)."""
+    s = synth.c1z(n=200, companion=True)
+    rng = np.random.default_rng(8)
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, s.n))
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    t = synth.ComplexSystem(s.n, s.row_ptr, s.col, s.val * ph[rows], s.f * ph, s.x_star, "phased", -1)
+    pa = oracle.plan_system_complex(s, 0.1)
+    pb = oracle.plan_system_complex(t, 0.1)
+    assert np.array_equal(pa.group, pb.group)
+    xa = oracle.solve_complex(pa, 4)
+    xb = oracle.solve_complex(pb, 4)
+    assert np.linalg.norm(xa - xb) <= 1e-12 * np.linalg.norm(xa)
+
+
+def test_complex_sweep_converges_to_generating_solution():
+    """Theorem 1 over C on a consistent, well-conditioned complex system."""
+    s = synth.c1z(n=400, companion=True)
+    pz = oracle.plan_system_complex(s, 0.1)
+    x = oracle.solve_complex(pz, 80)
+    assert np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star) <= 1e-10
+    assert oracle.relres_complex(s.n, s.row_ptr, s.col, s.val, s.f, x) <= 1e-10
