@@ -147,6 +147,23 @@ OBK_API obk_status obk_plan(const obk_csr *A, const double *f, double delta, con
                     obk_stream_t stream, obk_plan_t *out);
 
 /*
+ * Complex systems.  The paper applies Algorithm 4 unchanged to a complex
+ * matrix (kim1, in its discussion of Table 4); over C the row norm is
+ * sum_k |a_ik|^2, the cosine of rows i, j is |a_i^H a_j| / (||a_i|| ||a_j||)
+ * (the Hermitian inner product; |.| makes the order of the conjugation
+ * immaterial), and the row projection of eq. 1.2 is
+ * x + (f_i - a_i x) / ||a_i||^2 a_i^H.  obk_plan_complex takes the same CSR
+ * as obk_plan except that A->val holds 2 nnz doubles and f 2 n_rows doubles,
+ * each entry as (re, im); a plan built by it takes complex x0 and x in
+ * obk_solve (2 n_cols doubles, interleaved) and complex x~ in
+ * obk_sweep_device / obk_sweep_profile (2 n doubles).  Every sum runs in
+ * ascending index order, as for real systems.  OBK_FP64 only; not in block
+ * form; not batched.  Errors as obk_plan.
+ */
+OBK_API obk_status obk_plan_complex(const obk_csr *A, const double *f, double delta, const obk_opts *opts,
+                                    obk_stream_t stream, obk_plan_t *out);
+
+/*
  * Run sweeps from x0 (NULL: x0 = 0, the paper's start, Section 3.5) and write
  * the result in the original ordering to x.  With tol > 0 the relative
  * residual ||f - A x|| / ||f|| is checked every opts.check_every sweeps (each

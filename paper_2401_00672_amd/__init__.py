@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.obk_sweep_profile.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(_KernelProfile),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_blocks.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]
+        L.obk_plan_complex.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
+                                       ctypes.POINTER(_P)]
         L.obk_block_zn_nn.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.obk_block_select_k.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, _P, ctypes.c_int32,
                                          ctypes.POINTER(_Opts), _P, ctypes.POINTER(ctypes.c_int32), _P, _P]
@@ -121,7 +123,7 @@ def lib() -> ctypes.CDLL:
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
-                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k"):
+                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k", "obk_plan_complex"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,7 +140,8 @@ def _is_torch(a: Any) -> bool:
 
 def _dev_ptr(t, dtype_name: str) -> int:
     import torch
-    want = {"int64": torch.int64, "int32": torch.int32, "float64": torch.float64}[dtype_name]
+    want = {"int64": torch.int64, "int32": torch.int32, "float64": torch.float64,
+            "complex128": torch.complex128}[dtype_name]
     if not t.is_cuda or t.dtype != want or not t.is_contiguous():
         raise ObkError(-1, f"expected a contiguous CUDA tensor of {dtype_name}")
     return t.data_ptr()
@@ -164,8 +167,9 @@ class Plan:
     """A device-resident OBK-RCM plan (reordered, grouped system + workspace)."""
 
     def __init__(self, handle: int, n: int, nnz: int, on_device: bool, opts: dict | None = None,
-                 n_ext: int | None = None):
+                 n_ext: int | None = None, cplx: bool = False):
         self._opts = dict(opts or {})
+        self.cplx = cplx                            # complex system: x0, x, x~ are complex128
         self._h = handle
         self.n = n                                  # unknowns of the caller's system
         self.n_ext = n if n_ext is None else n_ext  # size of the (extended) square system
@@ -203,14 +207,16 @@ class Plan:
         info = _Info()
         if self.on_device:
             import torch
-            x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
-            px = _dev_ptr(x, "float64")
-            p0 = None if x0 is None else _dev_ptr(x0, "float64")
+            tname = "complex128" if self.cplx else "float64"
+            x = out if out is not None else torch.empty(self.n, dtype=getattr(torch, tname), device="cuda")
+            px = _dev_ptr(x, tname)
+            p0 = None if x0 is None else _dev_ptr(x0, tname)
             st = _stream(stream) or torch.cuda.current_stream().cuda_stream
         else:
-            x = out if out is not None else np.empty(self.n, dtype=np.float64)
+            dt = np.complex128 if self.cplx else np.float64
+            x = out if out is not None else np.empty(self.n, dtype=dt)
             px = x.ctypes.data
-            x0h = None if x0 is None else _host(x0, np.float64)
+            x0h = None if x0 is None else _host(x0, dt)
             p0 = None if x0h is None else x0h.ctypes.data
             st = _stream(stream)
         _check(lib().obk_solve(self.handle, p0, float(tol), int(maxit), px, ctypes.byref(info), st))
@@ -221,7 +227,8 @@ class Plan:
         """Enqueue `sweeps` sweeps on a device iterate in reordered coordinates."""
         import torch
         st = _stream(stream) or torch.cuda.current_stream().cuda_stream
-        _check(lib().obk_sweep_device(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st))
+        _check(lib().obk_sweep_device(self.handle, _dev_ptr(x_tilde, "complex128" if self.cplx else "float64"),
+                                      int(sweeps), st))
 
     def sweep_profile(self, x_tilde, sweeps: int, stream=None) -> list[dict]:
         """obk_sweep_profile: eager FP64 sweeps with HIP events around every
@@ -230,8 +237,8 @@ class Plan:
         st = _stream(stream) or torch.cuda.current_stream().cuda_stream
         out = (_KernelProfile * 8)()
         n = ctypes.c_int32()
-        _check(lib().obk_sweep_profile(self.handle, _dev_ptr(x_tilde, "float64"), int(sweeps), st, out, 8,
-                                       ctypes.byref(n)))
+        _check(lib().obk_sweep_profile(self.handle, _dev_ptr(x_tilde, "complex128" if self.cplx else "float64"),
+                                       int(sweeps), st, out, 8, ctypes.byref(n)))
         return [{"name": out[i].name.decode(), "launches": out[i].launches, "seconds": out[i].seconds,
                  "bytes": out[i].bytes} for i in range(n.value)]
 
@@ -299,10 +306,16 @@ class Plan:
                 "conflicts": nc.value}
 
 
+def plan_complex(row_ptr, col, val, f, delta: float, **kw) -> Plan:
+    """obk_plan_complex on a complex CSR system (host numpy or device torch
+    arrays; val and f complex128)."""
+    return plan(row_ptr, col, val, f, delta, _complex=True, **kw)
+
+
 def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: int | None = None,
          use_rcm: bool = True, precision: int = FP64, inner_sweeps: int = 8, check_every: int = 1,
          reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0, block_wgs: int = 0,
-         block_maxit: int = 0, block_tol: float = 1e-14, stream=None) -> Plan:
+         block_maxit: int = 0, block_tol: float = 1e-14, stream=None, _complex: bool = False) -> Plan:
     """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device).
     block_k > 0 selects the block form of Algorithm 4 (k uniform blocks, exact
     block projections); delta is then the centroid cosine threshold."""
@@ -311,13 +324,13 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
         nrows = int(row_ptr.numel()) - 1 if n is None else int(n)
         nnz = int(col.numel())
         keep = (row_ptr, col, val, f)
-        ptrs = (_dev_ptr(row_ptr, "int64"), _dev_ptr(col, "int32"), _dev_ptr(val, "float64"),
-                _dev_ptr(f, "float64"))
+        vt = "complex128" if _complex else "float64"
+        ptrs = (_dev_ptr(row_ptr, "int64"), _dev_ptr(col, "int32"), _dev_ptr(val, vt), _dev_ptr(f, vt))
         import torch
         st = _stream(stream) or torch.cuda.current_stream().cuda_stream
     else:
-        rp, ci, v, ff = _host(row_ptr, np.int64), _host(col, np.int32), _host(val, np.float64), \
-            _host(f, np.float64)
+        vt = np.complex128 if _complex else np.float64
+        rp, ci, v, ff = _host(row_ptr, np.int64), _host(col, np.int32), _host(val, vt), _host(f, vt)
         nrows = len(rp) - 1 if n is None else int(n)
         nnz = len(ci)
         keep = (rp, ci, v, ff)
@@ -339,12 +352,13 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     opts.block_maxit = int(block_maxit)
     opts.block_tol = float(block_tol)
     h = _P()
-    _check(lib().obk_plan(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
+    entry = lib().obk_plan_complex if _complex else lib().obk_plan
+    _check(entry(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
     del keep
     return Plan(h.value, ncols, nnz, on_device,
                 {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every),
                  "block_wgs": int(block_wgs), "block_maxit": int(block_maxit), "block_tol": float(block_tol)},
-                n_ext=max(nrows, ncols))
+                n_ext=max(nrows, ncols), cplx=bool(_complex))
 
 
 def select_block_k(s, thr: float, candidates, stream=None):
@@ -397,6 +411,8 @@ def plan_system(s, delta: float, **kw) -> Plan:
     """obk_plan on a ``synth.System`` or ``synth.RectSystem`` (host arrays)."""
     if hasattr(s, "m"):
         return plan(s.row_ptr, s.col, s.val, s.f, delta, n=s.m, n_cols=s.n, **kw)
+    if np.iscomplexobj(s.val):
+        return plan_complex(s.row_ptr, s.col, s.val, s.f, delta, **kw)
     return plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)
 
 

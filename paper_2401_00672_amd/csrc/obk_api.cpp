@@ -44,7 +44,7 @@ size_t obk_plan_s::device_bytes() const {
            x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
            b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes() + d_bptr.bytes() + d_btptr.bytes() +
            d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
-           biters.bytes() + blseg.bytes() + d_bfit.bytes();
+           biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes();
 }
 
 namespace {
@@ -120,8 +120,21 @@ obk_status obk_opts_default(obk_opts* opts) {
     return OBK_OK;
 }
 
+static obk_status plan_impl(const obk_csr* A, const double* f, double delta, const obk_opts* opts,
+                            obk_stream_t stream, obk_plan_t* out, bool cplx);
+
 obk_status obk_plan(const obk_csr* A, const double* f, double delta, const obk_opts* opts, obk_stream_t stream,
                     obk_plan_t* out) {
+    return plan_impl(A, f, delta, opts, stream, out, false);
+}
+
+obk_status obk_plan_complex(const obk_csr* A, const double* f, double delta, const obk_opts* opts,
+                            obk_stream_t stream, obk_plan_t* out) {
+    return plan_impl(A, f, delta, opts, stream, out, true);
+}
+
+static obk_status plan_impl(const obk_csr* A, const double* f, double delta, const obk_opts* opts,
+                            obk_stream_t stream, obk_plan_t* out, bool cplx) {
     if (out) *out = nullptr;
     obk_plan_s* P = nullptr;
     obk_status st = guarded([&] {
@@ -140,8 +153,11 @@ obk_status obk_plan(const obk_csr* A, const double* f, double delta, const obk_o
         if (o.inner_sweeps < 1 || o.check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
         check_block_opts(o);
         if (o.block_k > std::max(A->n_rows, A->n_cols)) obk::fail(OBK_E_ARG, "block_k exceeds the number of rows");
+        if (cplx && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "complex systems run in OBK_FP64 only");
+        if (cplx && o.block_k > 0) obk::fail(OBK_E_ARG, "the block form takes real systems only");
         P = new obk_plan_s();
         P->opts = o;
+        P->cplx = cplx;
         obk::build_plan(*P, *A, f, delta, as_hip(stream));
     });
     if (st != OBK_OK) {
@@ -163,7 +179,9 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
         if (maxit < 0 || std::isnan(tol)) obk::fail(OBK_E_ARG, "maxit must be >= 0 and tol a number");
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
-        if (plan->opts.precision == OBK_FP32_IR)
+        if (plan->cplx)
+            obk::solve_complex(*plan, x0, tol, maxit, x, info, as_hip(stream));
+        else if (plan->opts.precision == OBK_FP32_IR)
             obk::solve_fp32_ir(*plan, x0, tol, maxit, x, info, as_hip(stream));
         else
             obk::solve_fp64(*plan, x0, tol, maxit, x, info, as_hip(stream));
@@ -178,6 +196,7 @@ obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts* opts) {
         obk_opts o = *opts;
         o.block_k = plan->opts.block_k;   // a plan-time option
         check_block_opts(o);
+        if (plan->cplx && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "complex systems run in OBK_FP64 only");
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
         plan->opts.precision = opts->precision;
@@ -196,7 +215,8 @@ obk_status obk_sweep_device(obk_plan_t plan, double* x_tilde_dev, int64_t sweeps
         if (!plan || !x_tilde_dev) obk::fail(OBK_E_ARG, "plan and x_tilde_dev must not be NULL");
         if (sweeps < 0) obk::fail(OBK_E_ARG, "sweeps must be >= 0");
         OBK_HIP(hipSetDevice(plan->device));
-        obk::enqueue_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream));
+        if (plan->cplx) obk::enqueue_sweeps_z(*plan, x_tilde_dev, sweeps, as_hip(stream));
+        else obk::enqueue_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream));
     });
 }
 
@@ -208,7 +228,8 @@ obk_status obk_sweep_profile(obk_plan_t plan, double* x_tilde_dev, int64_t sweep
         if (max_out < 1) obk::fail(OBK_E_ARG, "max_out must be >= 1");
         OBK_HIP(hipSetDevice(plan->device));
         BusyGuard busy(plan);
-        *n_out = obk::profile_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out);
+        *n_out = plan->cplx ? obk::profile_sweeps_z(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out)
+                            : obk::profile_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out);
     });
 }
 

@@ -629,6 +629,7 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
         if (!plans[s]) fail(OBK_E_ARG, "NULL plan in batch");
         if (plans[s]->device != B.device) fail(OBK_E_ARG, "plans of a batch must live on the current device");
         if (plans[s]->block_form()) fail(OBK_E_ARG, "plans in block form cannot be batched");
+        if (plans[s]->cplx) fail(OBK_E_ARG, "complex plans cannot be batched");
         if (s > 0 && plans[s]->opts.precision != plans[0]->opts.precision)
             fail(OBK_E_ARG, "plans of a batch must share one precision");
         for (int t = 0; t < s; t++)

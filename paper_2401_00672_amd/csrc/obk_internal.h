@@ -116,6 +116,28 @@ void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Til
 
 struct obk_plan_s;
 namespace obk {
+// Complex systems: plan-stage helpers (values as separate real and imaginary
+// arrays) and the solve on a complex plan (interleaved values).
+void z_split(const double* in, int64_t n, double* re, double* im, hipStream_t s);
+void z_fill_zero(double* p, int64_t n, hipStream_t s);
+void z_finite(const double* a, int64_t n, int* flags, int bit, hipStream_t s);
+void z_gather_i32(int64_t n, const int32_t* idx, const double* src, double* dst, hipStream_t s);
+void z_gather_u32(int64_t n, const uint32_t* idx, const double* src, double* dst, hipStream_t s);
+void z_norms(int64_t n, const int64_t* trp, const double* tv, const double* tvi, double* nu, double* inv,
+             hipStream_t s);
+void z_conflicts(bool fill, int64_t nnz, const int64_t* trp, const int32_t* tci, const double* tv, const double* tvi,
+                 const int32_t* trow, const int64_t* cptr, const int32_t* crow, const double* nu, double delta,
+                 int64_t* count, const int64_t* out_pos, int32_t* out_idx, hipStream_t s);
+void z_relayout(int64_t m, const int32_t* grow, const int64_t* trp, const double* tv, const double* tvi,
+                const double* tf, const double* tfi, const int64_t* rptr, double* rvalz, double* rfz,
+                hipStream_t s);
+void z_pack(int64_t n, const double* re, const double* im, double* out, hipStream_t s);
+void solve_complex(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
+                   hipStream_t s);
+void enqueue_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
+                         int32_t max_out);
+
 // Centroid cosines, pairing and projection workspace of a block-form plan
 // (after the shared plan stages).
 void block_setup(obk_plan_s& P, hipStream_t s);
@@ -137,6 +159,7 @@ struct obk_plan_s {
     int64_t nconflicts = 0;
     obk_opts opts{};
     double delta = 0;
+    bool cplx = false;           // complex system: values, f~, x~, w interleaved (re, im)
     bool input_on_device = false;
     bool busy = false;
 
@@ -180,6 +203,12 @@ struct obk_plan_s {
     obk::DevArray<float> d32;          // correction, reordered [n]
     obk::DevArray<float> w32;          // group weights [m]
     obk::DevArray<double> r64;         // FP64 residual, group-major [m]
+
+    // complex plans: interleaved values of the group-major CSR and the
+    // per-group CSC, and f~ (rval, sval, rf stay empty)
+    obk::DevArray<double> rvalz;       // [2 nnz]
+    obk::DevArray<double> svalz;       // [2 nnz]
+    obk::DevArray<double> rfz;         // [2 m]
 
     // block form (opts.block_k > 0): groups are the k blocks, rows stay in
     // reordered order (m = n) and the per-group CSC is the per-block CSC

@@ -484,27 +484,51 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     PlanTrace tr(s);
 
     // ---- a1: ingest and validate (square checked by the caller)
-    DevArray<int64_t> rp; DevArray<int32_t> ci; DevArray<double> v, fd;
+    // complex systems: values and f arrive interleaved (re, im) and travel
+    // through the structural stages as separate real and imaginary arrays
+    const bool cplx = P.cplx;
+    DevArray<int64_t> rp; DevArray<int32_t> ci; DevArray<double> v, fd, v_im, fd_im;
     rp.alloc(n + 1);
     fd.alloc(n);
+    if (cplx) fd_im.alloc(n);
+    if (cplx) {
+        DevArray<double> fz;
+        copy_in(fz, f, 2 * nr, dev, s);
+        z_split(fz.get(), nr, fd.get(), fd_im.get(), s);
+        z_fill_zero(fd_im.get() + nr, n - nr, s);
+        sync_for_free(s);
+    }
     if (dev) {
         OBK_HIP(hipMemcpyAsync(rp.get(), A.row_ptr, (nr + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-        if (nr) OBK_HIP(hipMemcpyAsync(fd.get(), f, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (nr && !cplx) OBK_HIP(hipMemcpyAsync(fd.get(), f, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
         h2d(rp.get(), A.row_ptr, nr + 1, s);
-        if (nr) h2d(fd.get(), f, nr, s);
+        if (nr && !cplx) h2d(fd.get(), f, nr, s);
     }
     if (n > nr) {   // appended empty rows with a zero right-hand side
         k_extend_rows<<<nblk(n - nr), kT, 0, s>>>(nr, n, rp.get(), fd.get());
         OBK_HIP(hipGetLastError());
     }
     copy_in(ci, A.col, nnz, dev, s);
-    copy_in(v, A.val, nnz, dev, s);
+    if (cplx) {
+        DevArray<double> vz;
+        copy_in(vz, A.val, 2 * nnz, dev, s);
+        v.alloc(nnz);
+        v_im.alloc(nnz);
+        z_split(vz.get(), nnz, v.get(), v_im.get(), s);
+        sync_for_free(s);
+    } else {
+        copy_in(v, A.val, nnz, dev, s);
+    }
     DevArray<int> flags; flags.alloc(1);
     OBK_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int), s));
     k_validate<<<nblk(std::max(n + 1, nnz)), kT, 0, s>>>(n, nc, nnz, rp.get(), ci.get(), v.get(), fd.get(),
                                                           flags.get());
     OBK_HIP(hipGetLastError());
+    if (cplx) {
+        z_finite(v_im.get(), nnz, flags.get(), BAD_VAL, s);
+        z_finite(fd_im.get(), n, flags.get(), BAD_F, s);
+    }
     int hflags = to_host(flags.get(), 1, s)[0];
     if (hflags & BAD_ROWPTR) fail(OBK_E_CSR, "row_ptr is not a monotone offset array from 0 to nnz");
     if (hflags & BAD_COL) fail(OBK_E_CSR, "column index out of range");
@@ -583,6 +607,13 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     k_perm_finish<<<nblk(nnz), kT, 0, s>>>(nnz, entry.get(), ci.get(), q.get(), v.get(), trow.get(), tci.get(),
                                            tv.get(), flags.get(), bw.get());
     OBK_HIP(hipGetLastError());
+    DevArray<double> tv_im, tf_im;
+    if (cplx) {
+        tv_im.alloc(nnz);
+        tf_im.alloc(n);
+        z_gather_u32(nnz, entry.get(), v_im.get(), tv_im.get(), s);
+        z_gather_i32(n, P.perm.get(), fd_im.get(), tf_im.get(), s);
+    }
     k_dup_check<<<nblk(nnz), kT, 0, s>>>(nnz, trow.get(), tci.get(), flags.get());
     OBK_HIP(hipGetLastError());
     hflags = to_host(flags.get(), 1, s)[0];
@@ -590,16 +621,25 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     P.bandwidth = (int64_t)to_host(bw.get(), 1, s)[0];
     // free what the rest of the plan no longer needs
     rp = DevArray<int64_t>(); ci = DevArray<int32_t>(); v = DevArray<double>(); fd = DevArray<double>();
+    v_im = DevArray<double>(); fd_im = DevArray<double>();
     row = DevArray<int32_t>(); kcol = DevArray<uint32_t>(); krow = DevArray<uint32_t>();
     entry = DevArray<uint32_t>();
 
     tr.mark("permute");
     // ---- a4: row norms
     DevArray<double> nu, inv; nu.alloc(n); inv.alloc(n);
-    k_norms<<<nblk(n), kT, 0, s>>>(n, trp.get(), tv.get(), nu.get(), inv.get());
-    OBK_HIP(hipGetLastError());
+    if (cplx) {
+        z_norms(n, trp.get(), tv.get(), tv_im.get(), nu.get(), inv.get(), s);
+    } else {
+        k_norms<<<nblk(n), kT, 0, s>>>(n, trp.get(), tv.get(), nu.get(), inv.get());
+        OBK_HIP(hipGetLastError());
+    }
     P.fnorm2 = sum_squares(tf.get(), nu.get(), n, false, s);
     P.zero_rows_f2 = sum_squares(tf.get(), nu.get(), n, true, s);
+    if (cplx) {   // |f_i|^2 = re^2 + im^2: the two parts summed apart, then added
+        P.fnorm2 = P.fnorm2 + sum_squares(tf_im.get(), nu.get(), n, false, s);
+        P.zero_rows_f2 = P.zero_rows_f2 + sum_squares(tf_im.get(), nu.get(), n, true, s);
+    }
     {
         std::vector<double> hf = to_host(tf.get(), n, s), hn = to_host(nu.get(), n, s);
         double mx = 0.0;
@@ -632,6 +672,11 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());
         OBK_HIP(hipGetLastError());
     }
+    DevArray<double> cval_im;
+    if (cplx) {
+        cval_im.alloc(nnz);
+        z_gather_u32(nnz, order.get(), tv_im.get(), cval_im.get(), s);
+    }
     std::vector<int32_t> group(n);
     if (P.block_form()) {
         // ---- block form: k uniform chunks in order (Section 3.3), the first
@@ -653,15 +698,26 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         tr.mark("groups");
     } else {
         DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
-        k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                                    crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
-        OBK_HIP(hipGetLastError());
+        if (cplx) {
+            z_conflicts(false, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
+                        nu.get(), delta, ccount.get(), nullptr, nullptr, s);
+        } else {
+            k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                                        crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
+            OBK_HIP(hipGetLastError());
+        }
         int64_t nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
         P.nconflicts = nconf;
         DevArray<int32_t> cidx; cidx.alloc(nconf);
-        k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                                   crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get());
-        OBK_HIP(hipGetLastError());
+        if (cplx) {
+            z_conflicts(true, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
+                        nu.get(), delta, nullptr, ccount.get(), cidx.get(), s);
+        } else {
+            k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
+                                                       crow.get(), nu.get(), delta, nullptr, ccount.get(),
+                                                       cidx.get());
+            OBK_HIP(hipGetLastError());
+        }
 
         tr.mark("conflicts");
         // ---- a6: first-fit grouping on the host
@@ -715,6 +771,15 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     k_gm_gather<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), tci.get(), tv.get(), tf.get(), inv.get(),
                                         P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.rinv.get());
     OBK_HIP(hipGetLastError());
+    if (cplx) {   // interleaved values and f~; the real-only arrays are dropped
+        P.rvalz.alloc(2 * nnz_act);
+        P.rfz.alloc(2 * m);
+        z_relayout(m, dgrow.get(), trp.get(), tv.get(), tv_im.get(), tf.get(), tf_im.get(), P.rptr.get(),
+                   P.rvalz.get(), P.rfz.get(), s);
+        sync_for_free(s);
+        P.rval = DevArray<double>();
+        P.rf = DevArray<double>();
+    }
 
     tr.mark("relayout");
     // per-group CSC: CSC entries of active rows, stable-sorted by group
@@ -741,6 +806,14 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
                                         segs_g.get());
     OBK_HIP(hipGetLastError());
     k_set_i64<<<1, 1, 0, s>>>(P.sptr.get() + T, me);
+    if (cplx) {
+        DevArray<double> sval_im; sval_im.alloc(me);
+        z_gather_u32(me, gidx.get(), cval_im.get(), sval_im.get(), s);
+        P.svalz.alloc(2 * me);
+        z_pack(me, P.sval.get(), sval_im.get(), P.svalz.get(), s);
+        sync_for_free(s);
+        P.sval = DevArray<double>();
+    }
     std::vector<int64_t> hfirst = to_host(segs_g.get(), std::max(G, 1), s);
     // every group has at least one row with a nonzero entry, hence a segment;
     // a block of the block form may have none (its range is then empty)
@@ -774,8 +847,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     if (P.has_fp32()) ensure_fp32(P, s);
 
     // ---- workspace
-    P.x.alloc(n);
-    P.w.alloc(m);
+    P.x.alloc(cplx ? 2 * n : n);
+    P.w.alloc(cplx ? 2 * m : m);
     P.red.alloc(2 * std::max<size_t>(P.h_rtiles.size(), 1) + 16);   // residual partials per R tile
     OBK_HIP(hipStreamSynchronize(s));
     tr.mark("fp32_workspace");

@@ -131,3 +131,11 @@ def test_block_select_k_rejects_bad_candidates_before_any_gpu_work():
         with pytest.raises(obk.ObkError) as ei:
             obk.select_block_k(s, 0.1, cands)
         assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("kw", [dict(precision=1), dict(block_k=2)])
+def test_complex_plan_rejects_fp32_and_block_form_before_any_gpu_work(kw):
+    s = synth.c1z(n=6)
+    with pytest.raises(obk.ObkError) as ei:
+        obk.plan_complex(s.row_ptr, s.col, s.val, s.f, 0.1, **kw)
+    assert ei.value.code == -1
