@@ -247,6 +247,91 @@ def bench_block(args) -> dict:
     return res
 
 
+def cpu_baseline_complex(system, delta: float, budget_s: float = 12.0) -> dict:
+    """The oracle's complex path timed on the host: plan once, then complex
+    sweeps until the time budget is used (single thread)."""
+    import oracle
+    t0 = time.perf_counter()
+    pl = oracle.plan_system_complex(system, delta)
+    plan_s = time.perf_counter() - t0
+    x = np.zeros(system.n, dtype=np.complex128)
+    done, t1 = 0, time.perf_counter()
+    while True:
+        x = oracle.sweep_complex(pl, x, 1)
+        done += 1
+        el = time.perf_counter() - t1
+        if el >= budget_s or done >= 2000:
+            break
+    return {"value": done / el, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} complex FP64 sweeps of the full workload after a {plan_s:.1f} s oracle plan "
+                      f"({el:.1f} s of sweeps, one thread)"}
+
+
+def bench_complex(args) -> dict:
+    """Complex counterpart of the default line (the paper's kim1 case): the
+    1024x1024 stencil pattern with complex values under a random symmetric
+    permutation, delta = 0.1, complex FP64 sweeps."""
+    import torch
+    import synth
+    import paper_2401_00672_amd as obk
+    grid = args.grid
+    s = synth.c2z(grid=grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = obk.plan_system(s, args.delta)
+    plan_s = time.perf_counter() - t0
+    st = P.stats()
+    g, ng = P.groups()
+    m = int((g >= 0).sum())
+    x = torch.zeros(s.n, dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    if args.warmup > 0:
+        P.sweep_device(x, args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    P.sweep_device(x, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    B = sweep_bytes(s.n, m, s.nnz, sv=16, sx=16)
+    prof = P.sweep_profile(x, args.profile_sweeps)
+    dom = max(prof, key=lambda k: k["seconds"])
+    dom_avg_s = dom["seconds"] / dom["launches"]
+    dom_bytes = dom["bytes"] / dom["launches"]
+    achieved = dom_bytes / dom_avg_s / 1e9
+    res = {
+        "metric": "sweeps/s + GB/s vs HBM peak",
+        "value": 1000.0 / ms,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"complex-stencil-{grid}x{grid}-symperm-rcm-delta{args.delta}-fp64-sweep",
+                   "n": s.n, "nnz": s.nnz, "groups": ng, "bandwidth_after_rcm": st["bandwidth"],
+                   "algorithmic_bytes_per_sweep": B},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["name"],
+                     "avg_launch_us": dom_avg_s * 1e6, "algorithmic_bytes_per_launch": dom_bytes,
+                     "launches_profiled": dom["launches"], "traffic_unit": "bytes/launch"},
+        "sweep_effective": {"formula_bytes_per_sweep": B, "achieved_gbs": B / (ms * 1e-3) / 1e9,
+                            "frac": B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernels": [{"name": k["name"], "launches": k["launches"], "avg_us": k["seconds"] / k["launches"] * 1e6,
+                     "gbs": k["bytes"] / k["seconds"] / 1e9} for k in prof],
+        "plan_seconds": plan_s,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_complex(s, args.delta, args.cpu_budget)
+    P.free()
+    return res
+
+
 def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -484,9 +569,10 @@ def main() -> int:
                     help="eager sweeps timed per launch for the dominant-kernel roofline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "block"],
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5", "block", "complex"],
                     help="c2: 1024^2 stencil sweeps (default line); c3: 2M-row FP32+IR; c4: 512 batched systems; "
-                         "c5: continuous-batching server; block: block form of Algorithm 4")
+                         "c5: continuous-batching server; block: block form of Algorithm 4; "
+                         "complex: complex counterpart of c2")
     ap.add_argument("--block-grid", type=int, default=128, help="block: stencil grid side")
     ap.add_argument("--block-k", type=int, default=16, help="block: number of blocks")
     ap.add_argument("--block-thr", type=float, default=0.02, help="block: centroid cosine threshold")
@@ -518,6 +604,8 @@ def main() -> int:
         res = bench_serving(args)
     elif args.config == "block":
         res = bench_block(args)
+    elif args.config == "complex":
+        res = bench_complex(args)
     else:
         res = bench_stencil(args)
     print(json.dumps(res), flush=True)

@@ -17,8 +17,11 @@
 //            (d = a_i^H a_j), |cos| = sqrt(re d^2 + im d^2) / sqrt(nu_i nu_j)
 //   phase R  re s += re a re x - im a im x,  im s += re a im x + im a re x,
 //            w = (f - s) / ||a||^2
-//   phase S  re t += re w re a + im w im a,  im t += im w re a - re w im a
-//            (t = sum of w conj(a)), x_c += t
+//   phase S  t = sum of w conj(a), x_c += t, with conj(a) stored in the
+//            per-group CSC and w conj(a) formed as the plain product:
+//            re = re w re a - im w (-im a), im = re w (-im a) + im w re a,
+//            which equals re w re a + im w im a and im w re a - re w im a
+//            bit for bit (negation is exact and a two-term sum commutes)
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -29,8 +32,25 @@
 #include <vector>
 
 #include "obk_internal.h"
+#include "obk_sweep_tiles.h"
 
 namespace obk {
+
+// Complex FP64 value with exactly the component operations listed above; the
+// tile bodies of the real sweep run on it unchanged (the per-group CSC of a
+// complex plan holds conj(a), so phase S's product w * conj(a) is the plain
+// product).
+struct alignas(16) zdouble {
+    double re, im;
+    zdouble() = default;
+    __host__ __device__ constexpr zdouble(double r) : re(r), im(0.0) {}
+    __host__ __device__ constexpr zdouble(double r, double i) : re(r), im(i) {}
+};
+__device__ __forceinline__ zdouble operator*(zdouble a, zdouble b) {
+    return zdouble(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+__device__ __forceinline__ zdouble operator+(zdouble a, zdouble b) { return zdouble(a.re + b.re, a.im + b.im); }
+__device__ __forceinline__ zdouble operator-(zdouble a, zdouble b) { return zdouble(a.re - b.re, a.im - b.im); }
 
 namespace {
 
@@ -138,57 +158,58 @@ __global__ void k_gm_gather_z(int64_t m, const int32_t* __restrict__ grow, const
     rfz[a] = make_double2(tf[t], tfi[t]);
 }
 
-__global__ void k_pack(int64_t n, const double* __restrict__ re, const double* __restrict__ im,
+__global__ void k_pack(int64_t n, const double* __restrict__ re, const double* __restrict__ im, double sign,
                        double2* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = make_double2(re[i], im[i]);
+    if (i < n) out[i] = make_double2(re[i], sign * im[i]);
 }
 
 // ----------------------------------------------------------- sweep kernels
-// Phase R over one tile of rows (one thread per row, ascending entries):
-// w_a = (f_a - a_a x~) / ||a_a||^2.
+// Phase R over one tile of rows: the real tile body (entries staged through
+// LDS, each row summed by its owner in ascending entry order) on complex
+// values, with the real scale 1/||a||^2: w_a = (f_a - a_a x~) / ||a_a||^2.
 __global__ __launch_bounds__(kZT) void k_phase_r_z(const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr,
                                                    const int32_t* __restrict__ rcol,
-                                                   const double2* __restrict__ rval,
-                                                   const double2* __restrict__ rf, const double* __restrict__ rinv,
-                                                   const double2* __restrict__ x, double2* __restrict__ w) {
+                                                   const zdouble* __restrict__ rval,
+                                                   const zdouble* __restrict__ rf, const double* __restrict__ rinv,
+                                                   const zdouble* __restrict__ x, zdouble* __restrict__ w) {
+    __shared__ zdouble prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    const int64_t a = t.seg_begin + threadIdx.x;
-    if (a >= t.seg_end) return;
-    double sr = 0.0, si = 0.0;
-    const int64_t e1 = rptr[a + 1];
-    for (int64_t e = rptr[a]; e < e1; e++) {
-        const double2 v = rval[e];
-        const double2 xv = x[rcol[e]];
-        sr = sr + (v.x * xv.x - v.y * xv.y);
-        si = si + (v.x * xv.y + v.y * xv.x);
+    constexpr int64_t C = kTileEntries;
+    const int nchunks = tile_chunks(t);
+    const int nseg = t.seg_end - t.seg_begin;
+    const int me = threadIdx.x;
+    const bool own = me < nseg;
+    const int64_t a = t.seg_begin + (own ? me : 0);
+    const int64_t k0 = rptr[a], k1 = rptr[a + 1];
+    const zdouble fa = rf[a];
+    const double ia = rinv[a];
+    zdouble acc(0.0);
+    for (int c = 0; c < nchunks; c++) {
+        const int64_t base = t.ent_begin + (int64_t)c * C;
+        const int len = (int)max<int64_t>(0, min<int64_t>(C, t.ent_end - base));
+        stage_r<zdouble>(prod, me, len, rcol + base, rval + base, x);
+        __syncthreads();
+        const int64_t lo = max(k0, base), hi = own ? min(k1, base + len) : lo;
+        for (int64_t k = lo; k < hi; k++) acc = acc + prod[k - base];
+        __syncthreads();
     }
-    const double2 f = rf[a];
-    const double inv = rinv[a];
-    w[a] = make_double2((f.x - sr) * inv, (f.y - si) * inv);
+    if (own) {
+        const zdouble d = fa - acc;
+        w[a] = zdouble(d.re * ia, d.im * ia);
+    }
 }
 
 // Phase S over one tile of touched columns: x~_c += sum over the group's rows
-// (ascending) of w_a conj(a_ac).
+// (ascending) of w_a conj(a_ac), the generic tile body on conj(a).
 __global__ __launch_bounds__(kZT) void k_phase_s_z(const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr,
                                                    const int32_t* __restrict__ srow,
-                                                   const double2* __restrict__ sval,
-                                                   const int32_t* __restrict__ tcol, const double2* __restrict__ w,
-                                                   double2* __restrict__ x) {
+                                                   const zdouble* __restrict__ sval_conj,
+                                                   const int32_t* __restrict__ tcol, const zdouble* __restrict__ w,
+                                                   zdouble* __restrict__ x) {
+    __shared__ zdouble prod[kTileEntries];
     const Tile t = tiles[blockIdx.x];
-    const int64_t q = t.seg_begin + threadIdx.x;
-    if (q >= t.seg_end) return;
-    double tr = 0.0, ti = 0.0;
-    const int64_t e1 = sptr[q + 1];
-    for (int64_t e = sptr[q]; e < e1; e++) {
-        const double2 v = sval[e];
-        const double2 wv = w[srow[e]];
-        tr = tr + (wv.x * v.x + wv.y * v.y);
-        ti = ti + (wv.y * v.x - wv.x * v.y);
-    }
-    const int32_t c = tcol[q];
-    const double2 xv = x[c];
-    x[c] = make_double2(xv.x + tr, xv.y + ti);
+    tile_phase_s<zdouble>(t, tile_chunks(t), prod, sptr, srow, sval_conj, tcol, w, x);
 }
 
 // FP64 residual over one tile of rows: sum of |r_a|^2 in a fixed tree order
@@ -326,19 +347,19 @@ void z_relayout(int64_t m, const int32_t* grow, const int64_t* trp, const double
     OBK_HIP(hipGetLastError());
 }
 
-void z_pack(int64_t n, const double* re, const double* im, double* out, hipStream_t s) {
+void z_pack(int64_t n, const double* re, const double* im, bool conjugate, double* out, hipStream_t s) {
     if (n <= 0) return;
-    k_pack<<<nblk(n), 256, 0, s>>>(n, re, im, reinterpret_cast<double2*>(out));
+    k_pack<<<nblk(n), 256, 0, s>>>(n, re, im, conjugate ? -1.0 : 1.0, reinterpret_cast<double2*>(out));
     OBK_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ sweeps
 static void enqueue_sweeps_zt(const obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
-    const double2* rv = reinterpret_cast<const double2*>(P.rvalz.get());
-    const double2* rf = reinterpret_cast<const double2*>(P.rfz.get());
-    const double2* sv = reinterpret_cast<const double2*>(P.svalz.get());
-    double2* xz = reinterpret_cast<double2*>(x);
-    double2* wz = reinterpret_cast<double2*>(P.w.get());
+    const zdouble* rv = reinterpret_cast<const zdouble*>(P.rvalz.get());
+    const zdouble* rf = reinterpret_cast<const zdouble*>(P.rfz.get());
+    const zdouble* sv = reinterpret_cast<const zdouble*>(P.svalz.get());
+    zdouble* xz = reinterpret_cast<zdouble*>(x);
+    zdouble* wz = reinterpret_cast<zdouble*>(P.w.get());
     for (int64_t it = 0; it < sweeps; it++) {
         for (int32_t g = 0; g < P.ngroups; g++) {
             const int32_t r0 = P.h_rtile_ptr[g], r1 = P.h_rtile_ptr[g + 1];
@@ -411,11 +432,11 @@ int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s
         // S: values and row ids; offset, id, x~ read and write per touched column; w once per row
         sbytes[g] = eg * (sv + so) + tg * (2 * so + 2 * sv) + ng * sv;
     }
-    const double2* rv = reinterpret_cast<const double2*>(P.rvalz.get());
-    const double2* rf = reinterpret_cast<const double2*>(P.rfz.get());
-    const double2* svz = reinterpret_cast<const double2*>(P.svalz.get());
-    double2* xz = reinterpret_cast<double2*>(x);
-    double2* wz = reinterpret_cast<double2*>(P.w.get());
+    const zdouble* rv = reinterpret_cast<const zdouble*>(P.rvalz.get());
+    const zdouble* rf = reinterpret_cast<const zdouble*>(P.rfz.get());
+    const zdouble* svz = reinterpret_cast<const zdouble*>(P.svalz.get());
+    zdouble* xz = reinterpret_cast<zdouble*>(x);
+    zdouble* wz = reinterpret_cast<zdouble*>(P.w.get());
     struct L { int kind; double bytes; hipEvent_t a, b; };
     std::vector<L> ls;
     struct Guard {
@@ -434,7 +455,7 @@ int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s
                 hipExtLaunchKernelGGL(k_phase_r_z, dim3(r1 - r0), dim3(kZT), 0, s, l.a, l.b, 0,
                                       (const Tile*)(P.rtiles.get() + r0), (const int64_t*)P.rptr.get(),
                                       (const int32_t*)P.rcol.get(), rv, rf, (const double*)P.rinv.get(),
-                                      (const double2*)xz, wz);
+                                      (const zdouble*)xz, wz);
             }
             if (s1 > s0) {
                 L l{1, sbytes[g], nullptr, nullptr};
@@ -444,7 +465,7 @@ int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s
                 hipExtLaunchKernelGGL(k_phase_s_z, dim3(s1 - s0), dim3(kZT), 0, s, l.a, l.b, 0,
                                       (const Tile*)(P.stiles.get() + s0), (const int64_t*)P.sptr.get(),
                                       (const int32_t*)P.srow.get(), svz, (const int32_t*)P.tcol.get(),
-                                      (const double2*)wz, xz);
+                                      (const zdouble*)wz, xz);
             }
         }
     OBK_HIP(hipGetLastError());

@@ -131,7 +131,7 @@ void z_conflicts(bool fill, int64_t nnz, const int64_t* trp, const int32_t* tci,
 void z_relayout(int64_t m, const int32_t* grow, const int64_t* trp, const double* tv, const double* tvi,
                 const double* tf, const double* tfi, const int64_t* rptr, double* rvalz, double* rfz,
                 hipStream_t s);
-void z_pack(int64_t n, const double* re, const double* im, double* out, hipStream_t s);
+void z_pack(int64_t n, const double* re, const double* im, bool conjugate, double* out, hipStream_t s);
 void solve_complex(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                    hipStream_t s);
 void enqueue_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
@@ -207,7 +207,7 @@ struct obk_plan_s {
     // complex plans: interleaved values of the group-major CSR and the
     // per-group CSC, and f~ (rval, sval, rf stay empty)
     obk::DevArray<double> rvalz;       // [2 nnz]
-    obk::DevArray<double> svalz;       // [2 nnz]
+    obk::DevArray<double> svalz;       // [2 nnz], conj(a): phase S adds w conj(a)
     obk::DevArray<double> rfz;         // [2 m]
 
     // block form (opts.block_k > 0): groups are the k blocks, rows stay in

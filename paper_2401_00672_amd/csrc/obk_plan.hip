@@ -810,7 +810,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         DevArray<double> sval_im; sval_im.alloc(me);
         z_gather_u32(me, gidx.get(), cval_im.get(), sval_im.get(), s);
         P.svalz.alloc(2 * me);
-        z_pack(me, P.sval.get(), sval_im.get(), P.svalz.get(), s);
+        z_pack(me, P.sval.get(), sval_im.get(), true, P.svalz.get(), s);   // conj(a)
         sync_for_free(s);
         P.sval = DevArray<double>();
     }
