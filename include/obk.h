@@ -253,7 +253,9 @@ OBK_API obk_status obk_block_select_k(const obk_csr *A, const double *f, double 
  * Enqueued on stream; returns without waiting.  The sweeps are replayed from
  * graphs captured on first use for this x~ pointer (the plan keeps them until
  * obk_free).  Sweeps on one plan share its workspace: calls on the same plan
- * must be ordered (one stream, or explicit synchronisation).
+ * must be ordered (one stream, or explicit synchronisation).  In the block
+ * form all sweeps run in one launch (not from a graph) and the call
+ * synchronises the stream to check that launch's barrier flag.
  */
 OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_t sweeps,
                             obk_stream_t stream);
@@ -273,6 +275,14 @@ OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_
  *   phase S: e_g (s + 4) + t_g (8 + 2 s) + n_g s
  *            (values and row ids; column offset, column id, x read and
  *            written per touched column; w read once per row)
+ * Complex plans report k_phase_r_z / k_phase_s_z with the same formulas and
+ * s = 16 for values, f~, w and x~ (1/||a||^2 stays 8 bytes).  Block-form
+ * plans report one kernel, k_block_sweeps, timed over the whole launch of
+ * `sweeps` sweeps; its bytes are, per CG iteration on block b (n_b rows, e_b
+ * entries, t_b touched columns, s = 8, offsets 4 bytes),
+ *   2 e_b (s + 4) + n_b (4 + 6 s) + t_b (12 + 5 s),
+ * summed over the iterations the launch ran, plus e_b (s + 4) + n_b (4 + 3 s)
+ * + t_b s for the residual that starts each projection.
  * Synchronises the stream.  *n_out receives the number of kernels reported
  * (at most max_out).  sweeps must be in [1, 4096].
  */
