@@ -160,6 +160,44 @@ __host__ __device__ inline int64_t lds_bytes_for(int64_t nb, int64_t ns, int64_t
     return 8 * (2 * eb + 2 * nb + 2 * ns) + 4 * (nb + ns + 2) + 4 * eb;
 }
 
+// The local indices of up to C entries of one row or column segment, held in
+// registers for a whole projection (entries past C are read from LDS), so
+// that a dot's gathers can be issued without first loading the indices.
+template <int C>
+struct RegCache {
+    int e0, n, hi;          // first entry, cached count, end of the segment
+    int idx[C];
+};
+
+template <int C>
+__device__ __forceinline__ void cache_load(RegCache<C>& c, int e0, int e1, const uint16_t* idx) {
+    c.e0 = e0;
+    c.n = min(e1 - e0, C);
+    c.hi = e1;
+#pragma unroll
+    for (int k = 0; k < C; k++) c.idx[k] = (k < c.n) ? (int)idx[e0 + k] : 0;
+}
+
+// sum over the segment's entries, ascending, of val * vec[idx]; the value
+// loads and gathers of the cached entries are issued together
+template <int C, class F>
+__device__ __forceinline__ double cache_dot(const RegCache<C>& c, const double* val, const uint16_t* idx, F vec) {
+    double g[C], v[C];
+#pragma unroll
+    for (int k = 0; k < C; k++) {
+        g[k] = (k < c.n) ? vec(c.idx[k]) : 0.0;
+        v[k] = (k < c.n) ? val[c.e0 + k] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; k++)
+        if (k < c.n) s = s + v[k] * g[k];
+    for (int e = c.e0 + c.n; e < c.hi; e++) s = s + val[e] * vec(idx[e]);
+    return s;
+}
+
+constexpr int kCache = 6;
+
 // One projection by a single workgroup with the block resident in LDS: the
 // block's CSR and CSC (local indices), res, p, u and the touched entries of
 // x~ are staged once; the CG iterations then touch no global memory; x~ is
@@ -191,16 +229,32 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
     }
     for (int64_t q = t; q < ns; q += kBT) xs[q] = a.x[a.tcol[s0 + q]];
     __syncthreads();
+    // registers hold the indices of the first owned row and the first two owned segments
+    const int64_t qa = t, qb = t + kBT;
+    RegCache<kCache> rc, sca, scb;
+    cache_load(rc, t < nb ? roff[t] : 0, t < nb ? roff[t + 1] : 0, lcol);
+    cache_load(sca, qa < ns ? soff[qa] : 0, qa < ns ? soff[qa + 1] : 0, lrow);
+    cache_load(scb, qb < ns ? soff[qb] : 0, qb < ns ? soff[qb + 1] : 0, lrow);
+    auto gx = [&](int c) { return xs[c]; };
+    auto gu = [&](int c) { return u[c]; };
+    auto gp = [&](int i) { return pv[i]; };
     double acc = 0.0;
-    for (int64_t i = t; i < nb; i += kBT) {
-        double r = 0.0;
-        if (a.rinv[r0 + i] != 0.0) {
-            double d = 0.0;
-            for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * xs[lcol[e]];
-            r = a.rf[r0 + i] - d;
-        }
+    // the residual of each owned row (the first from its cached indices);
+    // all-zero rows take no part; the first direction is res + beta p with
+    // beta = 0, p = 0
+    if (t < nb) {
+        const double d = cache_dot(rc, rv, lcol, gx);
+        const double r = (a.rinv[r0 + t] != 0.0) ? a.rf[r0 + t] - d : 0.0;
+        res[t] = r;
+        pv[t] = r + 0.0 * 0.0;
+        acc = acc + r * r;
+    }
+    for (int64_t i = t + kBT; i < nb; i += kBT) {
+        double d = 0.0;
+        for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * xs[lcol[e]];
+        const double r = (a.rinv[r0 + i] != 0.0) ? a.rf[r0 + i] - d : 0.0;
         res[i] = r;
-        pv[i] = r + 0.0 * 0.0;     // the first direction, res + beta p with beta = 0, p = 0
+        pv[i] = r + 0.0 * 0.0;
         acc = acc + r * r;
     }
     double rr = wg_sum<kBT>(acc, lds);
@@ -212,7 +266,17 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
     // every use), so phase A gathers one vector
     while (rr0 > 0.0 && rr > a.tol2 * rr0 && it < cap) {
         acc = 0.0;
-        for (int64_t q = t; q < ns; q += kBT) {
+        if (qa < ns) {
+            const double sum = cache_dot(sca, sv, lrow, gp);
+            u[qa] = sum;
+            acc = acc + sum * sum;
+        }
+        if (qb < ns) {
+            const double sum = cache_dot(scb, sv, lrow, gp);
+            u[qb] = sum;
+            acc = acc + sum * sum;
+        }
+        for (int64_t q = t + 2 * kBT; q < ns; q += kBT) {
             double sum = 0.0;
             for (int32_t e = soff[q]; e < soff[q + 1]; e++) sum = sum + sv[e] * pv[lrow[e]];
             u[q] = sum;
@@ -223,7 +287,12 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
         const double alpha = rr / uu;
         for (int64_t q = t; q < ns; q += kBT) xs[q] = xs[q] + alpha * u[q];
         acc = 0.0;
-        for (int64_t i = t; i < nb; i += kBT) {
+        if (t < nb) {
+            const double rn = res[t] - alpha * cache_dot(rc, rv, lcol, gu);
+            res[t] = rn;
+            acc = acc + rn * rn;
+        }
+        for (int64_t i = t + kBT; i < nb; i += kBT) {
             double d = 0.0;
             for (int32_t e = roff[i]; e < roff[i + 1]; e++) d = d + rv[e] * u[lcol[e]];
             const double rn = res[i] - alpha * d;
