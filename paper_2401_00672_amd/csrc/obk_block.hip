@@ -48,12 +48,41 @@ constexpr long kBlockSpin = 1L << 22; // bound on one barrier wait (polls)
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-// Sum over the workgroup in a fixed order (butterfly within each wave, then
-// the wave sums in ascending order); every thread gets the same value.
+// A double moved across lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over a wave in a fixed order, the same value in every lane: pairs
+// within quads (lanes i, i^1, then i, i^2), quads within half rows (lane i
+// with 7 - i), half rows within rows of 16 (i with 15 - i) -- each step adds
+// two values in an order that commutes, so all lanes of a row agree -- then
+// the four row sums in ascending order.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = v + dpp_f64<0xB1>(v);       // quad_perm [1,0,3,2]
+    v = v + dpp_f64<0x4E>(v);       // quad_perm [2,3,0,1]
+    v = v + dpp_f64<0x141>(v);      // row_half_mirror
+    v = v + dpp_f64<0x140>(v);      // row_mirror
+    return ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
+}
+
+// Sum over the workgroup in a fixed order (each wave's sum, then the wave
+// sums in ascending order); every thread gets the same value.  Called by
+// every thread of the workgroup.
 template <int NT>
 __device__ __forceinline__ double wg_sum(double v, double* lds) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    v = wave_sum(v);
     __syncthreads();                       // lds is free again
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
