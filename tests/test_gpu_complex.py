@@ -12,6 +12,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 import synth
@@ -128,3 +129,34 @@ def test_complex_device_inputs_sweep_device_and_profile():
             P.set_opts(precision=obk.FP32_IR)
     finally:
         P.free()
+
+
+@pytest.mark.parametrize("m,n", [(120, 200), (260, 150)])
+def test_complex_non_square_systems(m, n):
+    """Section 4 over C: the complex plan of an m x n system is that of the
+    extended square system ([A; O] with f^ = [f; 0], or [A, O]); x = x^(1:n)."""
+    rng = np.random.default_rng(m + n)
+    nnz = int(0.05 * m * n)
+    pos = np.sort(rng.choice(m * n, size=nnz, replace=False))
+    rows, cols = pos // n, pos % n
+    vals = rng.standard_normal(nnz) + 1j * rng.standard_normal(nnz)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    xs = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    f = A @ xs
+    N = max(m, n)
+    rp_ext = np.concatenate([A.indptr, np.full(N - m, A.indptr[-1])]).astype(np.int64)
+    f_ext = np.concatenate([f, np.zeros(N - m, dtype=np.complex128)])
+    ext = synth.ComplexSystem(N, rp_ext, A.indices.astype(np.int32), A.data.astype(np.complex128), f_ext,
+                              np.zeros(N, dtype=np.complex128))
+    po = oracle.plan_system_complex(ext, 0.1)
+    x_o = oracle.solve_complex(po, 6)[:n]
+    P = obk.plan_complex(A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, f, 0.1, n=m, n_cols=n)
+    try:
+        assert np.array_equal(P.perm(), po.p)
+        assert np.array_equal(P.groups()[0], po.group)
+        x, _ = P.solve(maxit=6)
+    finally:
+        P.free()
+    _say(f"[complex] {m}x{n}: err {_rel(x, x_o):.3e}, bitwise {np.array_equal(x, x_o)}")
+    assert x.shape == (n,) and _rel(x, x_o) <= TOL_X
