@@ -616,11 +616,13 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
         const int64_t budget = (int64_t)max_lds - 1024;      // room for the kernel's static LDS
         std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
         P.h_bfit.assign(K, 0);
+        P.h_bnnz.assign(K, 0);
         P.block_lds = 0;
         for (int32_t b = 0; b < K; b++) {
             const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b];
             const int64_t ns = P.h_tptr[b + 1] - P.h_tptr[b];
             const int64_t eb = rp[P.h_bptr[b + 1]] - rp[P.h_bptr[b]];
+            P.h_bnnz[b] = eb;
             const int64_t bytes = lds_bytes_for(nb, ns, eb);
             if (nb <= 65535 && ns <= 65535 && bytes <= budget) {
                 P.h_bfit[b] = 1;
@@ -706,12 +708,11 @@ int32_t profile_block(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, o
     float ms = 0;
     block_sweeps(P, x, sweeps, s, &ms);
     std::vector<int64_t> it1 = dev_to_host(P.biters.get(), K, s);
-    std::vector<int64_t> rp = dev_to_host(P.rptr.get(), P.n + 1, s);
     const double sv = 8, so = 4;
     double bytes = 0;
     for (int32_t b = 0; b < K; b++) {
         const double nb = (double)(P.h_bptr[b + 1] - P.h_bptr[b]);
-        const double eb = (double)(rp[P.h_bptr[b + 1]] - rp[P.h_bptr[b]]);
+        const double eb = (double)P.h_bnnz[b];
         const double tb = (double)(P.h_tptr[b + 1] - P.h_tptr[b]);
         const double start = eb * (sv + so) + nb * (so + 3 * sv) + tb * sv;
         const double iter = 2 * eb * (sv + so) + nb * (so + 6 * sv) + tb * (3 * so + 5 * sv);

@@ -216,6 +216,7 @@ struct obk_plan_s {
     std::vector<double> h_bcos;        // |cos| of the block centroids, row-major [k*k]
     std::vector<int32_t> h_partner;    // paired block (-1: Nclass) [k]
     std::vector<int32_t> h_border;     // blocks in projection order of a sweep [k]
+    std::vector<int64_t> h_bnnz;       // entries of each block [k]
     obk::DevArray<int64_t> d_bptr, d_btptr;   // row and segment ranges per block [k+1]
     obk::DevArray<int32_t> d_border;
     obk::DevArray<double> bres, bp, bu;       // CG residual and direction [n], A_t^T p [n]
