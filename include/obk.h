@@ -247,6 +247,26 @@ OBK_API obk_status obk_block_select_k(const obk_csr *A, const double *f, double 
                                       int32_t *best_k, double *zn, double *nn);
 
 /*
+ * Threshold selection of Section 3.7 (Table 5), per real system: the paper fixes
+ * thr by comparing run times over candidate values; here, for each
+ * candidate delta, A is planned (as obk_plan with that delta and opts, NULL:
+ * defaults) and solved from x0 = 0 to tol (at most maxit sweeps, or
+ * refinement steps in OBK_FP32_IR), and the time of plan plus solve (host
+ * wall clock) is recorded.  *best_delta is the converged candidate with the
+ * least time (no candidate converged: the least final relative residual).
+ * Per candidate i (host arrays, each may be NULL): seconds[i], sweeps[i]
+ * (obk_info.sweeps), relres[i].  Each plan is freed before the next is
+ * built; the solutions are discarded.  The choice depends on timing and so
+ * may differ between runs when candidates are close.  Errors: as obk_plan
+ * and obk_solve; OBK_E_ARG for an empty list, a candidate that is not
+ * finite and > 0, tol <= 0 or maxit < 1.
+ */
+OBK_API obk_status obk_select_delta(const obk_csr *A, const double *f, const double *candidates,
+                                    int32_t n_candidates, double tol, int64_t maxit, const obk_opts *opts,
+                                    obk_stream_t stream, double *best_delta, double *seconds, int64_t *sweeps,
+                                    double *relres);
+
+/*
  * Sweeps on a plan with device-resident iterates, no host synchronisation and
  * no residual (the form a benchmark or a batched driver times): x~ (device,
  * reordered coordinates, n entries) is updated in place by `sweeps` sweeps.

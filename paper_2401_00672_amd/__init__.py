@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.obk_block_zn_nn.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.obk_block_select_k.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, _P, ctypes.c_int32,
                                          ctypes.POINTER(_Opts), _P, ctypes.POINTER(ctypes.c_int32), _P, _P]
+        L.obk_select_delta.argtypes = [ctypes.POINTER(_Csr), _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                       ctypes.POINTER(_Opts), _P, ctypes.POINTER(ctypes.c_double), _P, _P, _P]
         L.obk_plan_set_opts.argtypes = [_P, ctypes.POINTER(_Opts)]
         L.obk_plan_set_opts.restype = ctypes.c_int
         L.obk_last_error.restype = ctypes.c_char_p
@@ -123,7 +125,8 @@ def lib() -> ctypes.CDLL:
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
-                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k", "obk_plan_complex"):
+                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k", "obk_plan_complex",
+                     "obk_select_delta"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -381,6 +384,32 @@ def select_block_k(s, thr: float, candidates, stream=None):
                                     ctypes.byref(opts), _stream(stream), ctypes.byref(best), zn.ctypes.data,
                                     nn.ctypes.data))
     return int(best.value), [(int(k), float(a), float(b)) for k, a, b in zip(cand, zn, nn)]
+
+
+def select_delta(s, candidates=(0.5, 0.2, 0.1, 0.05, 0.02, 0.01), tol: float = 1e-8, maxit: int = 1000,
+                 stream=None, **opt_kw):
+    """obk_select_delta on a real ``synth.System`` (host arrays): plan and
+    solve to `tol` for each candidate threshold (default: the six values of
+    Table 5) and return (best_delta, [(delta, seconds, sweeps, relres), ...]).
+    opt_kw sets obk_opts fields (e.g. block_k=8 for the block form)."""
+    rp, ci, v, ff = _host(s.row_ptr, np.int64), _host(s.col, np.int32), _host(s.val, np.float64), \
+        _host(s.f, np.float64)
+    nrows = s.m if hasattr(s, "m") else len(rp) - 1
+    csr = _Csr(nrows, s.n, len(ci), rp.ctypes.data, ci.ctypes.data if len(ci) else None,
+               v.ctypes.data if len(ci) else None, 0)
+    opts = _Opts()
+    lib().obk_opts_default(ctypes.byref(opts))
+    for key, val in opt_kw.items():
+        setattr(opts, key, type(getattr(opts, key))(val))
+    cand = np.ascontiguousarray(candidates, dtype=np.float64)
+    sec = np.zeros(len(cand))
+    swp = np.zeros(len(cand), dtype=np.int64)
+    rel = np.zeros(len(cand))
+    best = ctypes.c_double(0.0)
+    _check(lib().obk_select_delta(ctypes.byref(csr), ff.ctypes.data, cand.ctypes.data, len(cand), float(tol),
+                                  int(maxit), ctypes.byref(opts), _stream(stream), ctypes.byref(best),
+                                  sec.ctypes.data, swp.ctypes.data, rel.ctypes.data))
+    return float(best.value), [(float(d), float(t), int(k), float(r)) for d, t, k, r in zip(cand, sec, swp, rel)]
 
 
 def rcm_host(gptr, gadj) -> np.ndarray:

@@ -315,6 +315,59 @@ obk_status obk_block_select_k(const obk_csr* A, const double* f, double thr, con
     });
 }
 
+obk_status obk_select_delta(const obk_csr* A, const double* f, const double* candidates, int32_t n_candidates,
+                            double tol, int64_t maxit, const obk_opts* opts, obk_stream_t stream, double* best_delta,
+                            double* seconds, int64_t* sweeps, double* relres) {
+    return guarded([&] {
+        if (!A || !best_delta) obk::fail(OBK_E_ARG, "A and best_delta must not be NULL");
+        if (n_candidates < 1 || !candidates) obk::fail(OBK_E_ARG, "no candidate thresholds");
+        for (int32_t i = 0; i < n_candidates; i++)
+            if (!(candidates[i] > 0.0) || !std::isfinite(candidates[i]))
+                obk::fail(OBK_E_ARG, "a candidate threshold is not finite and > 0");
+        if (!(tol > 0.0) || maxit < 1) obk::fail(OBK_E_ARG, "tol must be > 0 and maxit >= 1");
+        const int64_t n_x = A->n_cols;
+        // solution buffer in the input's memory space
+        obk::DevArray<double> xd;
+        std::vector<double> xh;
+        double* x = nullptr;
+        if (A->on_device) {
+            xd.alloc((size_t)n_x);
+            x = xd.get();
+        } else {
+            xh.assign((size_t)std::max<int64_t>(n_x, 1), 0.0);
+            x = xh.data();
+        }
+        int32_t best = -1;
+        double best_s = 0.0, best_r = 0.0;
+        bool best_conv = false;
+        for (int32_t i = 0; i < n_candidates; i++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            obk_plan_t P = nullptr;
+            obk_status st = obk_plan(A, f, candidates[i], opts, stream, &P);
+            if (st != OBK_OK) obk::fail(st, obk::last_error_cstr());
+            obk_info info{};
+            st = obk_solve(P, nullptr, tol, maxit, x, &info, stream);
+            const std::string msg = st != OBK_OK ? obk::last_error_cstr() : "";
+            obk_free(P);
+            if (st != OBK_OK) obk::fail(st, msg);
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (seconds) seconds[i] = sec;
+            if (sweeps) sweeps[i] = info.sweeps;
+            if (relres) relres[i] = info.relres;
+            const bool conv = info.status == OBK_CONVERGED;
+            const bool better = best < 0 || (conv && !best_conv) ||
+                                (conv == best_conv && (conv ? sec < best_s : info.relres < best_r));
+            if (better) {
+                best = i;
+                best_s = sec;
+                best_r = info.relres;
+                best_conv = conv;
+            }
+        }
+        *best_delta = candidates[best];
+    });
+}
+
 obk_status obk_plan_bytes(obk_plan_t plan, size_t* device_bytes) {
     return guarded([&] {
         if (!plan || !device_bytes) obk::fail(OBK_E_ARG, "NULL argument");

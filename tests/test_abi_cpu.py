@@ -139,3 +139,12 @@ def test_complex_plan_rejects_fp32_and_block_form_before_any_gpu_work(kw):
     with pytest.raises(obk.ObkError) as ei:
         obk.plan_complex(s.row_ptr, s.col, s.val, s.f, 0.1, **kw)
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("cands,tol,maxit", [([], 1e-8, 10), ([0.1, 0.0], 1e-8, 10), ([0.1, float("nan")], 1e-8, 10),
+                                             ([0.1], 0.0, 10), ([0.1], 1e-8, 0)])
+def test_select_delta_rejects_bad_arguments_before_any_gpu_work(cands, tol, maxit):
+    s = synth.c1(n=6)
+    with pytest.raises(obk.ObkError) as ei:
+        obk.select_delta(s, cands, tol=tol, maxit=maxit)
+    assert ei.value.code == -1

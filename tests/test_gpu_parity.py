@@ -315,3 +315,24 @@ def test_nonsquare_fp32_refinement_and_batch():
         assert x2.shape == x1.shape and np.array_equal(x1, x2) and i1.outer_steps == i2.outer_steps
     for p in plans:
         p.free()
+
+
+
+def test_threshold_selection_per_system():
+    """Section 3.7 per system: every candidate of Table 5 is planned and
+    solved to tol; the reported sweep counts are those of direct solves with
+    each threshold, and the choice is the fastest converged candidate."""
+    s = synth.c1(n=3000, companion=True)
+    cands = (0.5, 0.2, 0.1, 0.05, 0.02, 0.01)
+    best, rows = obk.select_delta(s, cands, tol=1e-8, maxit=500)
+    _say(f"[select-delta] {rows} -> {best}")
+    assert [r[0] for r in rows] == list(cands)
+    for d, sec, sweeps, rel in rows:
+        with obk.plan_system(s, d) as P:
+            _, info = P.solve(maxit=500, tol=1e-8)
+        assert info.sweeps == sweeps and (info.status == "converged") == (rel <= 1e-8)
+    # at 0.5 the group steps are far from orthogonal and the iteration
+    # diverges (the oracle too); the other five converge
+    assert rows[0][3] > 1e-8 and all(r[3] <= 1e-8 for r in rows[1:])
+    conv = [r for r in rows if r[3] <= 1e-8]
+    assert best == min(conv, key=lambda r: r[1])[0]
