@@ -32,17 +32,21 @@ def sweep_bytes(n: int, m: int, nnz: int, touched: int | None = None, sv: int = 
     return nnz * (sv + 4) + m * (4 + sv + sv) + 2 * n * sx
 
 
-def _kernel_source_sha() -> str:
+REAL_SWEEP_SOURCES = ("obk_sweep_tiles.h", "obk_tile.h")
+COMPLEX_SWEEP_SOURCES = ("obk_complex.hip", "obk_sweep_tiles.h", "obk_tile.h")
+
+
+def _kernel_source_sha(files=REAL_SWEEP_SOURCES) -> str:
     """Hash of the sweep kernel sources: counter figures recorded for an older
     kernel are not reported."""
     h = hashlib.sha256()
-    for f in ("obk_sweep_tiles.h", "obk_tile.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2401_00672_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def kernel_traffic(kernel: str, workload: str):
+def kernel_traffic(kernel: str, workload: str, files=REAL_SWEEP_SOURCES):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
     None when no summary matches the current kernel source."""
@@ -55,7 +59,7 @@ def kernel_traffic(kernel: str, workload: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != _kernel_source_sha() or kv.get("kernel") != kernel:
+    if kv.get("kernel_source_sha256_16") != _kernel_source_sha(files) or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -317,8 +321,9 @@ def bench_complex(args) -> dict:
                    "n": s.n, "nnz": s.nnz, "groups": ng, "bandwidth_after_rcm": st["bandwidth"],
                    "algorithmic_bytes_per_sweep": B},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom["name"],
-                     "avg_launch_us": dom_avg_s * 1e6, "algorithmic_bytes_per_launch": dom_bytes,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": kernel_traffic(dom["name"], "complex_stencil", COMPLEX_SWEEP_SOURCES),
+                     "kernel": dom["name"], "avg_launch_us": dom_avg_s * 1e6, "algorithmic_bytes_per_launch": dom_bytes,
                      "launches_profiled": dom["launches"], "traffic_unit": "bytes/launch"},
         "sweep_effective": {"formula_bytes_per_sweep": B, "achieved_gbs": B / (ms * 1e-3) / 1e9,
                             "frac": B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
