@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kZT) void k_phase_r_z(const Tile* __restrict__ tile
                                                    const zdouble* __restrict__ rf, const double* __restrict__ rinv,
                                                    const zdouble* __restrict__ x, zdouble* __restrict__ w) {
     __shared__ zdouble prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     constexpr int64_t C = kTileEntries;
     const int nchunks = tile_chunks(t);
     const int nseg = t.seg_end - t.seg_begin;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kZT) void k_phase_s_z(const Tile* __restrict__ tile
                                                    const int32_t* __restrict__ tcol, const zdouble* __restrict__ w,
                                                    zdouble* __restrict__ x) {
     __shared__ zdouble prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     tile_phase_s<zdouble>(t, tile_chunks(t), prod, sptr, srow, sval_conj, tcol, w, x);
 }
 

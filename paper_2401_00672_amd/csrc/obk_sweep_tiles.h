@@ -225,6 +225,15 @@ __device__ __forceinline__ void tile_resid(const Tile& t, int nchunks, double* p
     __syncthreads();
 }
 
+// Tile of workgroup b when workgroups are dealt to the 8 XCDs in turn
+// (b -> XCD b % 8): XCD x takes one contiguous run of the tiles, so tiles
+// that share a window of x (or w) share that XCD's L2.  A bijection on
+// [0, n) for any n.
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
+    const int32_t q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+    return x * q + min(x, r) + j;
+}
+
 namespace {
 
 // Phase R / phase S kernels over the tiles of one group: one tile per
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(kTileThreads) void k_phase_r(
     const T* __restrict__ rval, const T* __restrict__ rf, const T* __restrict__ rinv, const T* __restrict__ x,
     T* __restrict__ w) {
     __shared__ T prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
 }
 
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kTileThreads) void k_phase_s(
     const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr, const int32_t* __restrict__ srow,
     const T* __restrict__ sval, const int32_t* __restrict__ tcol, const T* __restrict__ w, T* __restrict__ x) {
     __shared__ T prod[kTileEntries];
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
 }
 
