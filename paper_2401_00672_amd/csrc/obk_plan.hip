@@ -756,6 +756,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         int64_t me_est = nnz;
         size_t est = (size_t)(m + 1) * 8 + (size_t)nnz * 12 + (size_t)m * 24 + (size_t)nnz * 12 +
                      (size_t)std::min<int64_t>(me_est, (int64_t)G * n + 1) * 12 + (size_t)n * 12;
+        if (cplx) est += (size_t)nnz * 16 + (size_t)m * 16 + (size_t)n * 8;   // imaginary parts, x~ and w
+        if (P.block_form()) est += (size_t)n * 24 + (size_t)nnz * 4;         // CG vectors, local indices
         if (P.opts.hbm_budget && est > P.opts.hbm_budget)
             fail(OBK_E_NOMEM, "plan footprint " + std::to_string(est) + " B exceeds hbm_budget");
     }

@@ -248,3 +248,20 @@ def test_block_count_selection_matches_oracle(name, maker, thr):
     with obk.plan_system(s, thr, block_k=k) as P:
         zn, nn = P.block_zn_nn()
     assert (zn, nn) == next((z, q) for kk, z, q in got if kk == k)
+
+
+def test_block_form_iteration_cap_and_budget():
+    """block_maxit caps every projection's CG iterations (the result is then
+    an approximate projection, still repeatable); an HBM budget below the
+    plan's footprint is refused."""
+    s = synth.c2(grid=32)
+    k = 4
+    with obk.plan_system(s, 0.02, block_k=k, block_maxit=3) as P:
+        x1, _ = P.solve(maxit=2)
+        it = P.blocks()["cg_iters"]
+        x2, _ = P.solve(maxit=2)
+        assert np.array_equal(x1, x2)
+    assert all(0 < v <= 3 * 2 for v in it), it      # 2 sweeps x at most 3 iterations
+    with pytest.raises(obk.ObkError) as ei:
+        obk.plan_system(s, 0.02, block_k=k, hbm_budget=1 << 16)
+    assert ei.value.code == -5
