@@ -148,3 +148,19 @@ def test_select_delta_rejects_bad_arguments_before_any_gpu_work(cands, tol, maxi
     with pytest.raises(obk.ObkError) as ei:
         obk.select_delta(s, cands, tol=tol, maxit=maxit)
     assert ei.value.code == -1
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/obk.h is a C ABI: it compiles as C99 with -pedantic next to
+    <math.h> (no C++ or torch types leak into it)."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not installed")
+    src = tmp_path / "use_obk.c"
+    src.write_text('#include <math.h>\n#include "obk.h"\n'
+                   'int main(void) { obk_opts o; obk_opts_default(&o); return o.block_k + (int)cos(0.0) - 1; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "use_obk.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
