@@ -97,7 +97,12 @@ typedef struct {
 } obk_csr;
 
 typedef struct {
-    int use_rcm;             /* 1 (default): reverse Cuthill-McKee; 0: identity ordering */
+    int use_rcm;             /* 0: identity ordering.  1 (default), 2, 3: reverse
+                                Cuthill-McKee, the same order from three engines: 1 picks
+                                (the device level-synchronous form for graphs of at least
+                                16384 vertices, handing over to the host loop once its
+                                levels stay narrow; the host loop below that), 2 the device
+                                form at any size and to the end, 3 the host loop */
     int precision;           /* OBK_FP64 (default) or OBK_FP32_IR */
     int inner_sweeps;        /* OBK_FP32_IR: FP32 sweeps per refinement step (default 8) */
     int check_every;         /* sweeps between residual checks when tol > 0 (default 1) */

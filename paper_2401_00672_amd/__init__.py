@@ -316,12 +316,15 @@ def plan_complex(row_ptr, col, val, f, delta: float, **kw) -> Plan:
 
 
 def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: int | None = None,
-         use_rcm: bool = True, precision: int = FP64, inner_sweeps: int = 8, check_every: int = 1,
-         reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0, block_wgs: int = 0,
-         block_maxit: int = 0, block_tol: float = 1e-14, stream=None, _complex: bool = False) -> Plan:
+         use_rcm: bool = True, rcm_engine: str = "auto", precision: int = FP64, inner_sweeps: int = 8,
+         check_every: int = 1, reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0,
+         block_wgs: int = 0, block_maxit: int = 0, block_tol: float = 1e-14, stream=None,
+         _complex: bool = False) -> Plan:
     """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device).
     block_k > 0 selects the block form of Algorithm 4 (k uniform blocks, exact
-    block projections); delta is then the centroid cosine threshold."""
+    block projections); delta is then the centroid cosine threshold.
+    rcm_engine ("auto", "device" or "host") picks how the reverse Cuthill-McKee
+    order is formed; the order is the same."""
     on_device = _is_torch(row_ptr)
     if on_device:
         nrows = int(row_ptr.numel()) - 1 if n is None else int(n)
@@ -344,7 +347,10 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     csr = _Csr(nrows, ncols, nnz, ptrs[0], ptrs[1], ptrs[2], 1 if on_device else 0)
     opts = _Opts()
     lib().obk_opts_default(ctypes.byref(opts))
-    opts.use_rcm = 1 if use_rcm else 0
+    engines = {"auto": 1, "device": 2, "host": 3}
+    if rcm_engine not in engines:
+        raise ValueError(f"rcm_engine must be one of {sorted(engines)}")
+    opts.use_rcm = engines[rcm_engine] if use_rcm else 0
     opts.precision = int(precision)
     opts.inner_sweeps = int(inner_sweeps)
     opts.check_every = int(check_every)

@@ -151,6 +151,7 @@ static obk_status plan_impl(const obk_csr* A, const double* f, double delta, con
         if (opts) o = *opts;
         if (o.precision != OBK_FP64 && o.precision != OBK_FP32_IR) obk::fail(OBK_E_ARG, "unknown precision");
         if (o.inner_sweeps < 1 || o.check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
+        if (o.use_rcm < 0 || o.use_rcm > 3) obk::fail(OBK_E_ARG, "use_rcm must be 0, 1, 2 or 3");
         check_block_opts(o);
         if (o.block_k > std::max(A->n_rows, A->n_cols)) obk::fail(OBK_E_ARG, "block_k exceeds the number of rows");
         if (cplx && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "complex systems run in OBK_FP64 only");

@@ -101,7 +101,8 @@ void DevMem::release() {
 // --------------------------------------------------------------------- RCM
 // Section 3.2 names reverse Cuthill-McKee without a tie-break; this file
 // fixes one (stated in obk.h and below) so that the order is unique.
-void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm) {
+void host_cm_resume(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* cm, uint8_t* seen, int64_t head,
+                    int64_t tail) {
     if (n <= 0) return;
     // Degrees once; neighbours are then ordered by the 64-bit key
     // (degree << 32 | index), which is the (degree, index) order.
@@ -119,11 +120,11 @@ void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm
     std::vector<int32_t> by_degree(n);
     for (int64_t v = 0; v < n; v++) by_degree[bucket[deg[v]]++] = (int32_t)v;
 
-    std::vector<uint8_t> seen(n, 0);
-    std::vector<int32_t> cm(n);          // Cuthill-McKee sequence, doubles as the FIFO
+    // cm is the Cuthill-McKee sequence and doubles as the FIFO: [head, tail)
+    // are the vertices appended but not yet expanded
     std::vector<uint64_t> fresh;
     fresh.reserve(256);
-    int64_t head = 0, tail = 0, next_start = 0;
+    int64_t next_start = 0;
     while (tail < n) {
         if (head == tail) {               // new component
             while (seen[by_degree[next_start]]) next_start++;
@@ -159,6 +160,13 @@ void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm
         }
         for (uint64_t key : fresh) cm[tail++] = (int32_t)(key & 0xffffffffu);
     }
+}
+
+void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm) {
+    if (n <= 0) return;
+    std::vector<int32_t> cm(n);
+    std::vector<uint8_t> seen(n, 0);
+    host_cm_resume(n, gptr, gadj, cm.data(), seen.data(), 0, 0);
     for (int64_t t = 0; t < n; t++) perm[t] = cm[n - 1 - t];
 }
 

@@ -100,6 +100,20 @@ int bits_for(uint64_t max_value);
 // unvisited neighbours by ascending (degree, index); reverse the whole
 // Cuthill-McKee sequence.  perm[t] = old index of new position t.
 void host_rcm(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* perm);
+// The same Cuthill-McKee sequence (not reversed) continued from a state of
+// the search: cm[0, tail) appended so far, seen[] their flags, cm[head, tail)
+// not yet expanded.  (0, 0) with no vertex seen starts it.
+void host_cm_resume(int64_t n, const int64_t* gptr, const int32_t* gadj, int32_t* cm, uint8_t* seen, int64_t head,
+                    int64_t tail);
+// The reverse Cuthill-McKee order of the same graph formed on the device, one
+// breadth-first level per step (adj, deg: device adjacency in row order and
+// degrees).  With give_up, once at least 4 levels are done, they hold fewer
+// than kDeviceRcmMinWidth vertices each on average and the last one is less
+// than twice the one before, the host loop finishes the search from the
+// device's state.  perm is host memory.
+constexpr int64_t kDeviceRcmMinWidth = 2048;
+constexpr int64_t kDeviceRcmMinN = 16384;     // use_rcm = 1: smaller graphs go to the host loop
+void device_rcm(int64_t n, const int32_t* adj, const int32_t* deg, bool give_up, hipStream_t s, int32_t* perm);
 // First-fit colouring in row order: row i takes the least colour not used
 // by any conflicting row j < i (conflict lists cptr[n+1], cidx).  Rows with
 // active[i] == 0 get colour -1.  Returns the number of colours.

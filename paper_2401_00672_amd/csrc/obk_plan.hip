@@ -561,11 +561,18 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         OBK_HIP(hipMemsetAsync(deg.get(), 0, n * sizeof(int32_t), s));
         k_unique_emit<<<nblk(m2), kT, 0, s>>>(m2, ra.get(), cb.get(), uflag.get(), adj.get(), deg.get());
         OBK_HIP(hipGetLastError());
-        std::vector<int32_t> hdeg = to_host(deg.get(), n, s);
-        std::vector<int32_t> hadj = to_host(adj.get(), mu, s);
-        std::vector<int64_t> gptr(n + 1, 0);
-        for (int64_t i = 0; i < n; i++) gptr[i + 1] = gptr[i] + hdeg[i];
-        host_rcm(n, gptr.data(), hadj.data(), perm.data());
+        tr.mark("rcm_graph");
+        const int mode = P.opts.use_rcm;
+        if (mode == 2 || (mode == 1 && n >= kDeviceRcmMinN)) {
+            device_rcm(n, adj.get(), deg.get(), mode == 1, s, perm.data());
+        } else {
+            std::vector<int32_t> hdeg = to_host(deg.get(), n, s);
+            std::vector<int32_t> hadj = to_host(adj.get(), mu, s);
+            std::vector<int64_t> gptr(n + 1, 0);
+            for (int64_t i = 0; i < n; i++) gptr[i + 1] = gptr[i] + hdeg[i];
+            tr.mark("rcm_copy");
+            host_rcm(n, gptr.data(), hadj.data(), perm.data());
+        }
     } else {
         for (int64_t t = 0; t < n; t++) perm[t] = (int32_t)t;
     }

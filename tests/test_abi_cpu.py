@@ -4,6 +4,8 @@ first-fit grouping) are bit-exact with the oracle's independent code."""
 import os
 import re
 
+import ctypes
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -60,6 +62,21 @@ def test_plan_rejects_bad_arguments_before_any_gpu_work(kw, code):
         obk.plan(s.row_ptr, s.col, s.val, s.f, delta, **kw)
     assert ei.value.code == code
     assert obk.lib().obk_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("use_rcm", [-1, 4])
+def test_plan_rejects_unknown_rcm_engine_before_any_gpu_work(use_rcm):
+    s = synth.c1(n=6)
+    csr = obk._Csr(s.n, s.n, s.nnz, s.row_ptr.ctypes.data, s.col.ctypes.data, s.val.ctypes.data, 0)
+    o = obk._Opts()
+    obk.lib().obk_opts_default(ctypes.byref(o))
+    o.use_rcm = use_rcm
+    h = ctypes.c_void_p()
+    rc = obk.lib().obk_plan(ctypes.byref(csr), s.f.ctypes.data, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert "use_rcm" in obk.lib().obk_last_error().decode()
+    with pytest.raises(ValueError):
+        obk.plan(s.row_ptr, s.col, s.val, s.f, 0.1, rcm_engine="gpu")
 
 
 def _graph(s):

@@ -98,6 +98,46 @@ def test_plan_and_sweeps_match_oracle(name, maker, delta, K):
     assert rel <= TOL_X
 
 
+def _components():
+    """Components of several sizes and widths plus degree-0 vertices
+    (diagonal-only rows), with rows and columns shuffled so that the
+    components interleave in index order."""
+    rng = np.random.default_rng(21)
+    parts = [sp.random(k, k, density=d, random_state=int(rng.integers(1 << 30)))
+             for k, d in [(3000, 0.002), (500, 0.01), (40, 0.1), (2, 1.0)]]
+    A = (sp.block_diag(parts + [sp.csr_matrix((25, 25))]) + sp.eye(3567)).tocsr()
+    q = rng.permutation(A.shape[0])
+    A = A[q][:, q].tocsr()
+    A.sort_indices()
+    return synth.from_scipy(A, rng.standard_normal(A.shape[0]), name="components")
+
+
+RCM_CASES = [
+    ("c1", lambda: synth.c1()),
+    ("stencil30-narrow-levels", lambda: synth.c2(grid=30)),
+    ("stencil160-hands-over", lambda: synth.c2(grid=160)),
+    ("c3-family-n20000", lambda: synth.c3(n=20000)),
+    ("c4-family-n7001", lambda: synth.c4_system(5, n=7001)),
+    ("components-and-isolated", _components),
+    ("arrow", _arrow),
+    ("identity", lambda: synth.from_dense(np.eye(33), f=np.arange(33.0))),
+    ("n1", lambda: synth.from_dense(np.array([[2.0]]), f=np.array([6.0]))),
+]
+
+
+@pytest.mark.parametrize("name,maker", RCM_CASES, ids=[c[0] for c in RCM_CASES])
+def test_rcm_engines_match_oracle(name, maker):
+    """The device level-synchronous order, the host loop and the automatic
+    choice (device first, host loop resuming once the levels stay narrow)
+    all give the oracle's permutation bit for bit."""
+    s = maker()
+    _say(f"[parity] rcm engines {name}: n={s.n} nnz={s.nnz}")
+    p_o = oracle.rcm(s.n, s.row_ptr, s.col)
+    for engine in ("device", "host", "auto"):
+        with obk.plan_system(s, 0.1, rcm_engine=engine) as P:
+            assert np.array_equal(P.perm(), p_o), f"{engine} engine"
+
+
 def test_full_size_stencil_parity():
     """The 1024x1024 stencil (1,048,576 rows) at its full size: bit-exact plan,
     x after 3 sweeps within 1e-10."""
