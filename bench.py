@@ -428,7 +428,8 @@ def bench_serving(args) -> dict:
     _log(f"[c5] generated {count} requests in {time.perf_counter() - t0:.1f} s "
          f"(mean n {sizes.mean():.0f}, total nnz {sum(s.nnz for s in systems)})")
     budget = int(args.budget_gib * (1 << 30))
-    be = LibobkBackend(delta=args.delta, inner_sweeps=args.inner, planners=args.planners)
+    be = LibobkBackend(delta=args.delta, inner_sweeps=args.inner, planners=args.planners,
+                       rcm_engine=args.rcm_engine)
     warm = Server(be, budget, tol=1e-10, planners=args.planners)
     warm.run([Request(0, 0.0, systems[0])])
     torch.cuda.synchronize()
@@ -480,7 +481,7 @@ def bench_serving(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"serving-{count}-requests-n-loguniform-500-5e5-4to16nnz-companion-poisson",
                    "requests": count, "arrival_rate_per_s": rate, "budget_bytes": budget,
-                   "planners": args.planners, "inner_sweeps": args.inner},
+                   "planners": args.planners, "inner_sweeps": args.inner, "rcm_engine": args.rcm_engine},
         "latency_s": lat,
         "converged": conv,
         "worst_sampled_relres": worst,
@@ -590,6 +591,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=512, help="c5: requests in the sample")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: device-memory admission budget")
     ap.add_argument("--planners", type=int, default=4, help="c5: planner threads")
+    ap.add_argument("--rcm-engine", default="host", choices=["auto", "device", "host"],
+                    help="c5: how each request's plan forms its RCM order")
     ap.add_argument("--max-steps", type=int, default=200, help="c5: refinement steps before a request gives up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (counter calibration) and exit")
