@@ -186,9 +186,10 @@ def bench_block(args) -> dict:
     """Block form of Algorithm 4 on a banded system of the paper's size class:
     a 5-point stencil under a random symmetric permutation, k uniform blocks
     after RCM, thr = 0.02 (the paper's global threshold).  A timed step is one
-    sweep (every Oclass pair, then Nclass), each block projected exactly by
-    in-kernel conjugate gradients; all sweeps of the timed region run in one
-    cooperative launch."""
+    sweep (every Oclass pair, then Nclass), each block projected exactly:
+    from its banded Cholesky factor of A_t A_t^T (--block-solver direct, the
+    default) or by in-kernel conjugate gradients (--block-solver cg); all
+    sweeps of the timed region run in one launch."""
     import torch
     import synth
     import paper_2401_00672_amd as obk
@@ -196,7 +197,7 @@ def bench_block(args) -> dict:
     s = synth.c2(grid=grid)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = obk.plan_system(s, thr, block_k=k, block_wgs=args.block_wgs)
+    P = obk.plan_system(s, thr, block_k=k, block_wgs=args.block_wgs, block_solver=args.block_solver)
     plan_s = time.perf_counter() - t0
     info = P.blocks()
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
@@ -229,14 +230,16 @@ def bench_block(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"block-form-stencil-{grid}x{grid}-symperm-rcm-k{k}-thr{thr}-fp64-sweep",
                    "n": s.n, "nnz": s.nnz, "k": k, "pairs": len(info["pairs"]), "nclass": len(info["nclass"]),
-                   "workgroups": args.block_wgs or "auto",
+                   "workgroups": args.block_wgs or "auto", "solver": args.block_solver,
+                   "direct_blocks": int(info["direct"].sum()),
+                   "factor_bandwidth_max": int(info["factor_bandwidth"].max()),
                    "cg_iterations_per_sweep": iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": prof["name"],
                      "avg_launch_us": prof["seconds"] / prof["launches"] * 1e6,
                      "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"],
                      "sweeps_per_launch": args.profile_sweeps, "traffic_unit": "bytes/launch"},
-        "us_per_cg_iteration": ms * 1e3 / max(iters, 1),
+        "us_per_cg_iteration": ms * 1e3 / iters if iters > 0 else None,
         "plan_seconds": plan_s,
     }
     zn, nn = P.block_zn_nn()
@@ -583,6 +586,8 @@ def main() -> int:
     ap.add_argument("--block-k", type=int, default=16, help="block: number of blocks")
     ap.add_argument("--block-thr", type=float, default=0.02, help="block: centroid cosine threshold")
     ap.add_argument("--block-wgs", type=int, default=0, help="block: workgroups of the projection launch (0: auto)")
+    ap.add_argument("--block-solver", default="direct", choices=["direct", "cg"],
+                    help="block: projections from banded Cholesky factors, or by conjugate gradients")
     ap.add_argument("--systems", type=int, default=512)
     ap.add_argument("--inner", type=int, default=8)
     ap.add_argument("--check-every", type=int, default=5)

@@ -120,6 +120,11 @@ typedef struct {
                                 (0 = 4 x block rows + 100) */
     double block_tol;        /* block form: a projection's CG stops once its residual
                                 norm is <= block_tol x its initial one (default 1e-14) */
+    int block_solver;        /* block form: 0 (default): blocks with a banded Cholesky
+                                factor of A_t A_t^T (formed at plan time; full row rank to
+                                a pivot test, band within limits) are projected exactly
+                                from it in one-workgroup launches, the others by CG;
+                                1: CG for every block.  A plan-time option. */
 } obk_opts;
 
 typedef struct {
@@ -223,6 +228,15 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  * iterations of all projections of a call in one launch (cooperative when
  * it spans several workgroups).
  *
+ * Direct projections (opts.block_solver = 0): y solves A_t A_t^T y =
+ * f_t - A_t x~ by a forward and a backward banded triangular solve with the
+ * block's Cholesky factor (formed on the host at plan time, in FP64, from the
+ * pairwise row products accumulated in ascending column order).  A block
+ * whose pivots fall below 1e-8 of their diagonal (rank deficient to working
+ * accuracy), whose band would exceed 2^26 entries, or with more than 8192
+ * rows keeps CG, and so does every block of a launch over several
+ * workgroups.  All-zero rows take no part (their y is 0).
+ *
  * obk_plan_blocks (host outputs, each may be NULL): *k; bptr[k+1] the row
  * range of each block in reordered rows; partner[k] the block a block is
  * paired with (-1: Nclass); cos[k*k] the table C, row-major; cg_iters[k] the
@@ -231,6 +245,13 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  */
 OBK_API obk_status obk_plan_blocks(obk_plan_t plan, int32_t *k, int64_t *bptr, int32_t *partner, double *cos,
                                    int64_t *cg_iters);
+/*
+ * Per block of a block-form plan (host outputs, each may be NULL): direct[k]
+ * 1 when the block is projected from its Cholesky factor, bandwidth[k] that
+ * factor's bandwidth (-1 without one).  Errors: OBK_E_ARG when the plan is
+ * not in block form.
+ */
+OBK_API obk_status obk_plan_block_solvers(obk_plan_t plan, int32_t *direct, int64_t *bandwidth);
 
 /*
  * Block-count criteria of Section 3.6 (Definitions 1 and 2) for the block

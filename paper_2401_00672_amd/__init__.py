@@ -44,7 +44,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("use_rcm", ctypes.c_int), ("precision", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("reject_inconsistent", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t), ("block_k", ctypes.c_int), ("block_wgs", ctypes.c_int),
-                ("block_maxit", ctypes.c_int), ("block_tol", ctypes.c_double)]
+                ("block_maxit", ctypes.c_int), ("block_tol", ctypes.c_double), ("block_solver", ctypes.c_int)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         L.obk_sweep_profile.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.POINTER(_KernelProfile),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_blocks.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P]
+        L.obk_plan_block_solvers.argtypes = [_P, _P, _P]
         L.obk_plan_complex.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
                                        ctypes.POINTER(_P)]
         L.obk_block_zn_nn.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -125,7 +126,8 @@ def lib() -> ctypes.CDLL:
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
                      "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
-                     "obk_plan_blocks", "obk_block_zn_nn", "obk_block_select_k", "obk_plan_complex",
+                     "obk_plan_blocks", "obk_plan_block_solvers", "obk_block_zn_nn", "obk_block_select_k",
+                     "obk_plan_complex",
                      "obk_select_delta"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -274,8 +276,11 @@ class Plan:
                                      cos.ctypes.data, iters.ctypes.data))
         pairs = [(a, int(partner[a])) for a in range(kk) if partner[a] > a]
         nclass = [a for a in range(kk) if partner[a] < 0]
+        direct = np.empty(kk, dtype=np.int32)
+        bw = np.empty(kk, dtype=np.int64)
+        _check(lib().obk_plan_block_solvers(self.handle, direct.ctypes.data, bw.ctypes.data))
         return {"k": kk, "bptr": bptr, "partner": partner, "cos": cos, "pairs": pairs, "nclass": nclass,
-                "cg_iters": iters}
+                "cg_iters": iters, "direct": direct.astype(bool), "factor_bandwidth": bw}
 
     # -- introspection
     def perm(self) -> np.ndarray:
@@ -318,8 +323,8 @@ def plan_complex(row_ptr, col, val, f, delta: float, **kw) -> Plan:
 def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: int | None = None,
          use_rcm: bool = True, rcm_engine: str = "auto", precision: int = FP64, inner_sweeps: int = 8,
          check_every: int = 1, reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0,
-         block_wgs: int = 0, block_maxit: int = 0, block_tol: float = 1e-14, stream=None,
-         _complex: bool = False) -> Plan:
+         block_wgs: int = 0, block_maxit: int = 0, block_tol: float = 1e-14, block_solver: str = "direct",
+         stream=None, _complex: bool = False) -> Plan:
     """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device).
     block_k > 0 selects the block form of Algorithm 4 (k uniform blocks, exact
     block projections); delta is then the centroid cosine threshold.
@@ -360,6 +365,10 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     opts.block_wgs = int(block_wgs)
     opts.block_maxit = int(block_maxit)
     opts.block_tol = float(block_tol)
+    solvers = {"direct": 0, "cg": 1}
+    if block_solver not in solvers:
+        raise ValueError(f"block_solver must be one of {sorted(solvers)}")
+    opts.block_solver = solvers[block_solver]
     h = _P()
     entry = lib().obk_plan_complex if _complex else lib().obk_plan
     _check(entry(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))

@@ -44,7 +44,8 @@ size_t obk_plan_s::device_bytes() const {
            x.bytes() + w.bytes() + red.bytes() + rval32.bytes() + rinv32.bytes() + sval32.bytes() +
            b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes() + d_bptr.bytes() + d_btptr.bytes() +
            d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
-           biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes();
+           biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes() +
+           d_bdirect.bytes() + d_bbw.bytes() + d_boff.bytes() + lfc.bytes() + lfr.bytes() + ldinv.bytes();
 }
 
 namespace {
@@ -89,6 +90,7 @@ void check_block_opts(const obk_opts& o) {
     if (o.block_k > 0 && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "the block form runs in OBK_FP64 only");
     if (o.block_wgs < 0 || o.block_maxit < 0) obk::fail(OBK_E_ARG, "block_wgs and block_maxit must be >= 0");
     if (!(o.block_tol >= 0.0) || !std::isfinite(o.block_tol)) obk::fail(OBK_E_ARG, "block_tol must be finite and >= 0");
+    if (o.block_solver != 0 && o.block_solver != 1) obk::fail(OBK_E_ARG, "block_solver must be 0 or 1");
 }
 
 // RAII marker for the one-solve-at-a-time rule
@@ -117,6 +119,7 @@ obk_status obk_opts_default(obk_opts* opts) {
     opts->block_wgs = 0;
     opts->block_maxit = 0;
     opts->block_tol = 1e-14;
+    opts->block_solver = 0;
     return OBK_OK;
 }
 
@@ -270,6 +273,19 @@ obk_status obk_plan_blocks(obk_plan_t plan, int32_t* k, int64_t* bptr, int32_t* 
         if (cg_iters) {
             OBK_HIP(hipSetDevice(plan->device));
             OBK_HIP(hipMemcpy(cg_iters, plan->biters.get(), K * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+obk_status obk_plan_block_solvers(obk_plan_t plan, int32_t* direct, int64_t* bandwidth) {
+    return guarded([&] {
+        if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
+        if (!plan->block_form()) obk::fail(OBK_E_ARG, "the plan is not in block form");
+        const int32_t K = plan->opts.block_k;
+        for (int32_t b = 0; b < K; b++) {
+            const bool d = b < (int32_t)plan->h_bdirect.size() && plan->h_bdirect[b];
+            if (direct) direct[b] = d ? 1 : 0;
+            if (bandwidth) bandwidth[b] = d ? plan->h_bbw[b] : -1;
         }
     });
 }

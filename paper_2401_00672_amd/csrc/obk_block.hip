@@ -33,8 +33,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "obk_internal.h"
@@ -174,6 +176,12 @@ struct BlockArgs {
     int64_t* iters;           // CG iterations per block, accumulated
     const int32_t* lseg;      // per CSR entry: its column's index in the block's segment list
     const int32_t* fit;       // per block: 1 if it is projected from LDS
+    const int32_t* direct;    // per block: 1 if it is projected from its Cholesky factor
+    const int32_t* dbw;       // per block: the factor's bandwidth
+    const int64_t* doff;      // per block: offset of the factor in lfc / lfr
+    const double* lfc;        // factors by columns: [off + c (bw+1) + d] = L[c+d][c]
+    const double* lfr;        // factors by rows: [off + i (bw+1) + bw - (i-j)] = L[i][j]
+    const double* ldinv;      // 1 / L[i][i] per row [n]
     int64_t sweeps;
     int32_t lds_path;         // 1: single-workgroup launch with dynamic LDS for the fitting blocks
     int32_t k;
@@ -340,6 +348,244 @@ __device__ int64_t project_lds(const BlockArgs& a, int32_t b, double* dyn, doubl
     return it;
 }
 
+// Dynamic LDS bytes of a direct projection of a block of nb rows: y, and
+// two buffers for the diagonal block of a panel and its inverse pivots.
+constexpr int kPanel = 64;
+// a panel's diagonal block, rows padded to 65 doubles so that lane k reading
+// row k stays off the other lanes' banks, then 1 / L[k][k]
+constexpr int kDStride = kPanel + 1;
+constexpr int kDiagBuf = kPanel * kDStride + kPanel;
+__host__ __device__ inline int64_t direct_lds_for(int64_t nb) { return 8 * (nb + 2 * kDiagBuf); }
+
+// One exact projection by a single workgroup from the block's banded
+// Cholesky factor L (L L^T = A_t A_t^T):
+//   r = f_t - A_t x~  ->  L z = r  ->  L^T y = z  ->  x~ += A_t^T y
+// The triangular solves go by panels of 64 rows: the panel's diagonal block
+// is staged in LDS and solved by wave 0 lane by lane (lane k holds row k;
+// step c broadcasts the finished value of row c), then the rows of the band
+// beyond the panel are updated, four threads to a row (16 panel columns
+// each, the four partial sums added in lane order).  Neither the factor
+// entries of that update nor the next panel's diagonal block depend on the
+// solve, so every thread loads them into registers before wave 0 starts and
+// the solve hides their latency; the diagonal blocks alternate between two
+// LDS buffers.  y lives in LDS throughout.
+constexpr int kPart = 4;                       // threads per updated row
+constexpr int kPartCols = kPanel / kPart;      // panel columns per thread
+constexpr int kStagePer = kPanel * kPanel / kBT;
+constexpr int64_t kRowsPerPass = kBT / kPart;  // updated rows per pass
+
+// Factor entries of the update of row j (this thread's 16 panel columns);
+// lfac(j, c) gives the entry's index, or -1 outside the band.
+template <class F>
+__device__ __forceinline__ void band_load(double (&lv)[kPartCols], int j, bool row_ok, int pw,
+                                          const double* __restrict__ Lf, F lfac) {
+    const int part = threadIdx.x % kPart;
+#pragma unroll
+    for (int u = 0; u < kPartCols; u++) {
+        const int c = part * kPartCols + u;
+        const int k = (row_ok && c < pw) ? lfac(j, c) : -1;
+        const double l = Lf[k >= 0 ? k : 0];
+        lv[u] = k >= 0 ? l : 0.0;
+    }
+}
+
+// z[j] -= sum over the panel columns c of L(j, c) z[p0 + c]; the four lanes
+// of a row call it together
+__device__ __forceinline__ void band_apply(const double (&lv)[kPartCols], double* z, int p0, int pw, int j,
+                                           bool row_ok) {
+    const int part = threadIdx.x % kPart;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPartCols; u++) {
+        const int c = part * kPartCols + u;
+        acc = acc + lv[u] * z[p0 + (c < pw ? c : 0)];
+    }
+    const double a1 = __shfl_down(acc, 1, kPart);
+    const double a2 = __shfl_down(acc, 2, kPart);
+    const double a3 = __shfl_down(acc, 3, kPart);
+    if (row_ok && part == 0) z[j] = z[j] - (((acc + a1) + a2) + a3);
+}
+
+// The diagonal block D[k][c] (64 x 64) of the panel at row p0 (pw rows) and
+// its inverse pivots: lfac(k, c) gives the entry's index, or -1 for a zero.
+template <class F>
+__device__ __forceinline__ void stage_load(double (&v)[kStagePer], double& dv, const double* __restrict__ Lf,
+                                           const double* __restrict__ dinv, int p0, int pw, F lfac) {
+#pragma unroll
+    for (int u = 0; u < kStagePer; u++) {
+        const int q = threadIdx.x + u * kBT;
+        const int k = lfac(q / kPanel, q % kPanel);
+        const double l = Lf[k >= 0 ? k : 0];
+        v[u] = k >= 0 ? l : 0.0;
+    }
+    const int k = (int)threadIdx.x;
+    const double d = dinv[p0 + (k < pw ? k : 0)];
+    dv = k < pw ? d : 0.0;
+}
+__device__ __forceinline__ void stage_store(double* D, const double (&v)[kStagePer], double dv) {
+#pragma unroll
+    for (int u = 0; u < kStagePer; u++) {
+        const int q = threadIdx.x + u * kBT;
+        D[(q / kPanel) * kDStride + q % kPanel] = v[u];
+    }
+    if (threadIdx.x < kPanel) D[kPanel * kDStride + threadIdx.x] = dv;
+}
+
+__device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
+    static_assert(kPanel * kPanel % kBT == 0 && kPanel == 64, "panel of one wave");
+    const int t = threadIdx.x;
+    // in-block indices fit 32 bits: a block has at most 8192 rows and 2^24 band entries
+    const int64_t r0 = a.bptr[b];
+    const int nb = (int)(a.bptr[b + 1] - r0);
+    const int64_t s0 = a.btptr[b];
+    const int ns = (int)(a.btptr[b + 1] - s0);
+    const int bw = a.dbw[b], W = bw + 1;
+    const double* Lc = a.lfc + a.doff[b];
+    const double* Lr = a.lfr + a.doff[b];
+    const double* dinv = a.ldinv + r0;
+    double* z = dyn;
+    double* Dbuf[2] = {dyn + nb, dyn + nb + kDiagBuf};
+    const int np = (nb + kPanel - 1) / kPanel;
+    double sv[kStagePer], lv[kPartCols], sd = 0.0;
+    // D[k][c] = L[p0+k][p0+c] for c <= k (rows of the band): forward panels
+    auto fwd_diag = [=](int p0, int pw) {
+        return [=](int k, int c) -> int { return (k < pw && c <= k && k - c <= bw) ? (p0 + k) * W + bw - (k - c) : -1; };
+    };
+    // D[k][c] = L[p0+c][p0+k] for c >= k (columns of the band): backward panels
+    auto bwd_diag = [=](int p0, int pw) {
+        return [=](int k, int c) -> int { return (c < pw && c >= k && c - k <= bw) ? (p0 + k) * W + (c - k) : -1; };
+    };
+    // r = f_t - A_t x~ (all-zero rows: 0); the first diagonal block meanwhile
+    stage_load(sv, sd, Lr, dinv, 0, min(kPanel, nb), fwd_diag(0, min(kPanel, nb)));
+    for (int i = t; i < nb; i += kBT) {
+        double r = 0.0;
+        if (a.rinv[r0 + i] != 0.0) {
+            const double d = dot_seq(a.rptr[r0 + i], a.rptr[r0 + i + 1], a.rval, a.rcol,
+                                     [&](int32_t c) { return a.x[c]; });
+            r = a.rf[r0 + i] - d;
+        }
+        z[i] = r;
+    }
+    stage_store(Dbuf[0], sv, sd);
+    __syncthreads();
+    // L z = r, panels from the top
+    for (int ip = 0; ip < np; ip++) {
+        const int p0 = ip * kPanel;
+        const int pw = min(kPanel, nb - p0);
+        const double* D = Dbuf[ip & 1];
+        // rows below the panel that the band reaches: [p0 + pw, je)
+        const int je = min(nb, p0 + pw + bw);
+        auto below = [=](int j, int c) -> int {
+            const int d = j - (p0 + c);
+            return d <= bw ? (p0 + c) * W + d : -1;
+        };
+        const int j0 = p0 + pw + t / kPart;
+        band_load(lv, j0, j0 < je, pw, Lc, below);
+        if (ip + 1 < np) {
+            const int q0 = p0 + kPanel, qw = min(kPanel, nb - q0);
+            stage_load(sv, sd, Lr, dinv, q0, qw, fwd_diag(q0, qw));
+        }
+        if (t < kPanel) {
+            // reads LDS only: the prefetches above stay in flight
+            double v = t < pw ? z[p0 + t] : 0.0;
+            const double di = D[kPanel * kDStride + t];
+            for (int c0 = 0; c0 < pw; c0 += 8) {
+                double dr[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) dr[u] = D[t * kDStride + c0 + u];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int c = c0 + u;
+                    if (c < pw) {
+                        const double zc = readlane_f64(v * di, c);
+                        const double upd = v - dr[u] * zc;
+                        v = (t == c) ? zc : ((t > c) ? upd : v);
+                    }
+                }
+            }
+            if (t < pw) z[p0 + t] = v;
+        }
+        __syncthreads();
+        band_apply(lv, z, p0, pw, j0, j0 < je);
+        for (int jp = p0 + pw + (int)kRowsPerPass; jp < je; jp += (int)kRowsPerPass) {   // bands over 256 rows
+            const int j = jp + t / kPart;
+            band_load(lv, j, j < je, pw, Lc, below);
+            band_apply(lv, z, p0, pw, j, j < je);
+        }
+        if (ip + 1 < np) stage_store(Dbuf[(ip + 1) & 1], sv, sd);
+        __syncthreads();
+    }
+    // L^T y = z, panels from the bottom
+    {
+        const int p0 = (np - 1) * kPanel;
+        stage_load(sv, sd, Lc, dinv, p0, nb - p0, bwd_diag(p0, nb - p0));
+        stage_store(Dbuf[0], sv, sd);
+        __syncthreads();
+    }
+    for (int ip = np - 1; ip >= 0; ip--) {
+        const int p0 = ip * kPanel;
+        const int pw = min(kPanel, nb - p0);
+        const double* D = Dbuf[(np - 1 - ip) & 1];
+        // rows above the panel that the band reaches: [jb, p0)
+        const int jb = max(0, p0 - bw);
+        auto above = [=](int j, int c) -> int {
+            const int d = (p0 + c) - j;
+            return d <= bw ? (p0 + c) * W + bw - d : -1;
+        };
+        const int j0 = jb + t / kPart;
+        band_load(lv, j0, j0 < p0, pw, Lr, above);
+        if (ip > 0) stage_load(sv, sd, Lc, dinv, p0 - kPanel, kPanel, bwd_diag(p0 - kPanel, kPanel));
+        if (t < kPanel) {
+            double v = t < pw ? z[p0 + t] : 0.0;
+            const double di = D[kPanel * kDStride + t];
+            for (int c1 = pw; c1 > 0; c1 -= 8) {
+                double dr[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) dr[u] = D[t * kDStride + max(c1 - 1 - u, 0)];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int c = c1 - 1 - u;
+                    if (c >= 0) {
+                        const double yc = readlane_f64(v * di, c);
+                        const double upd = v - dr[u] * yc;
+                        v = (t == c) ? yc : ((t < c) ? upd : v);
+                    }
+                }
+            }
+            if (t < pw) z[p0 + t] = v;
+        }
+        __syncthreads();
+        band_apply(lv, z, p0, pw, j0, j0 < p0);
+        for (int jp = jb + (int)kRowsPerPass; jp < p0; jp += (int)kRowsPerPass) {
+            const int j = jp + t / kPart;
+            band_load(lv, j, j < p0, pw, Lr, above);
+            band_apply(lv, z, p0, pw, j, j < p0);
+        }
+        if (ip > 0) stage_store(Dbuf[(np - ip) & 1], sv, sd);
+        __syncthreads();
+    }
+    // x~ += A_t^T y on the touched columns, rows in ascending order
+    for (int q = t; q < ns; q += kBT) {
+        const int64_t sg = s0 + q;
+        double acc = 0.0;
+        for (int64_t e = a.sptr[sg]; e < a.sptr[sg + 1]; e++) acc = acc + a.sval[e] * z[a.srow[e] - r0];
+        const int32_t c = a.tcol[sg];
+        a.x[c] = a.x[c] + acc;
+    }
+    __syncthreads();
+}
+
+// Every projection of a call from the blocks' factors, one workgroup.
+__global__ __launch_bounds__(kBT) void k_block_direct(BlockArgs a) {
+    extern __shared__ double dyn[];
+    for (int64_t sw = 0; sw < a.sweeps; sw++)
+        for (int32_t j = 0; j < a.k; j++) project_direct(a, a.order[j], dyn);
+}
+
+// kMix = 1: blocks with a factor are projected from it (one-workgroup
+// launches), the rest by CG; kMix = 0: CG for all (kept apart so that the CG
+// forms keep their registers).
+template <int kMix>
 __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
     extern __shared__ double dyn[];
     __shared__ double lds[kBT / 64];
@@ -359,6 +605,10 @@ __global__ __launch_bounds__(kBT) void k_block_sweeps(BlockArgs a) {
         for (int32_t j = 0; j < a.k; j++) {
             double* p0 = a.part + (2 + ((sw * a.k + j) & 1)) * G;
             const int32_t b = a.order[j];
+            if (kMix == 1 && a.lds_path && a.direct[b]) {
+                project_direct(a, b, dyn);
+                continue;
+            }
             if (a.lds_path && a.fit[b]) {
                 const int64_t it = project_lds(a, b, dyn, lds);
                 if (t == 0) a.iters[b] += it;
@@ -532,6 +782,18 @@ int32_t block_grid(const obk_plan_s& P) {
     return (int32_t)std::min<int64_t>(cap, std::max<int64_t>(1, (rows + 2 * kBT - 1) / (2 * kBT)));
 }
 
+// The projection kernel of a launch of G workgroups: the factors serve
+// one-workgroup launches only.
+struct BlockKernel { const void* fn; const char* name; };
+BlockKernel block_kernel(const obk_plan_s& P, int32_t G) {
+    int32_t nd = 0;
+    for (int32_t d : P.h_bdirect) nd += d;
+    if (G == 1 && nd > 0 && nd == P.opts.block_k)
+        return {reinterpret_cast<const void*>(k_block_direct), "k_block_direct"};
+    if (G == 1 && nd > 0) return {reinterpret_cast<const void*>(k_block_sweeps<1>), "k_block_sweeps"};
+    return {reinterpret_cast<const void*>(k_block_sweeps<0>), "k_block_sweeps"};
+}
+
 }  // namespace
 
 // Block ranges, centroid cosines, pairing and the projection workspace.
@@ -631,7 +893,7 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
         }
         host_to_dev(P.d_bfit, P.h_bfit, s);
         if (P.block_lds > 0)
-            OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_sweeps),
+            OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_sweeps<0>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.block_lds));
     }
     // projection workspace
@@ -642,9 +904,147 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
     P.biters.alloc(K);
     OBK_HIP(hipMemsetAsync(P.bu.get(), 0, std::max<int64_t>(n, 1) * sizeof(double), s));
     OBK_HIP(hipMemsetAsync(P.biters.get(), 0, K * sizeof(int64_t), s));
-    OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&P.block_occ, k_block_sweeps, kBT, 0));
+    OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&P.block_occ, k_block_sweeps<0>, kBT, 0));
     if (P.block_occ < 1) fail(OBK_E_HIP, "the block projection kernel cannot be resident");
     OBK_HIP(hipStreamSynchronize(s));
+}
+
+// Banded Cholesky factor of B B^T for the rows [r0, r0 + nb) of the
+// reordered CSR: Gram entries accumulated over the columns in ascending
+// order, then L row by row.  Returns the bandwidth, or -1 when the block is
+// rank deficient to the pivot test, too wide, or too large.  All-zero rows
+// (rinv 0) get a unit diagonal: they are decoupled and their y is 0.
+constexpr int64_t kDirectMaxRows = 8192;
+constexpr int64_t kDirectMaxBand = int64_t(1) << 24;     // band entries per block
+constexpr int64_t kDirectMaxTotal = int64_t(1) << 27;    // band entries per plan
+constexpr double kPivotTol = 1e-8;
+
+static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                            const std::vector<double>& va, const std::vector<double>& rinv,
+                            std::vector<double>& L) {
+    if (nb <= 0 || nb > kDirectMaxRows) return -1;
+    struct Ent { int32_t c, i; double v; };
+    std::vector<Ent> es;
+    es.reserve((size_t)(rp[r0 + nb] - rp[r0]));
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t k = rp[r0 + i]; k < rp[r0 + i + 1]; k++) es.push_back({ci[k], (int32_t)i, va[k]});
+    std::sort(es.begin(), es.end(), [](const Ent& x, const Ent& y) { return x.c != y.c ? x.c < y.c : x.i < y.i; });
+    int64_t bw = 0;
+    for (size_t a = 0; a < es.size();) {
+        size_t e = a;
+        while (e < es.size() && es[e].c == es[a].c) e++;
+        bw = std::max<int64_t>(bw, es[e - 1].i - es[a].i);
+        a = e;
+    }
+    const int64_t W = bw + 1;
+    if (nb * W > kDirectMaxBand) return -1;
+    L.assign((size_t)(nb * W), 0.0);
+    auto at = [&](int64_t i, int64_t j) -> double& { return L[(size_t)(i * W + bw - (i - j))]; };
+    for (size_t a = 0; a < es.size();) {
+        size_t e = a;
+        while (e < es.size() && es[e].c == es[a].c) e++;
+        for (size_t p = a; p < e; p++)
+            for (size_t q = a; q <= p; q++) at(es[p].i, es[q].i) += es[p].v * es[q].v;
+        a = e;
+    }
+    for (int64_t i = 0; i < nb; i++)
+        if (rinv[r0 + i] == 0.0) at(i, i) = 1.0;
+    for (int64_t i = 0; i < nb; i++) {
+        const int64_t jlo = std::max<int64_t>(0, i - bw);
+        const double gii = at(i, i);
+        for (int64_t j = jlo; j <= i; j++) {
+            double sum = at(i, j);
+            for (int64_t k = std::max<int64_t>(jlo, j - bw); k < j; k++) sum -= at(i, k) * at(j, k);
+            if (j < i) {
+                at(i, j) = sum / at(j, j);
+            } else {
+                if (!(sum > kPivotTol * gii)) return -1;
+                at(i, i) = std::sqrt(sum);
+            }
+        }
+    }
+    return bw;
+}
+
+void block_factor(obk_plan_s& P, hipStream_t s) {
+    const int32_t K = P.opts.block_k;
+    P.h_bdirect.assign(K, 0);
+    P.h_bbw.assign(K, -1);
+    P.direct_lds = 0;
+    std::vector<std::vector<double>> fac(K);
+    if (P.opts.block_solver == 0 && K > 0) {
+        const int64_t n = P.n;
+        const std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
+        const std::vector<int32_t> ci = dev_to_host(P.rcol.get(), rp[n], s);
+        const std::vector<double> va = dev_to_host(P.rval.get(), rp[n], s);
+        const std::vector<double> ri = dev_to_host(P.rinv.get(), n, s);
+        std::atomic<int32_t> next{0};
+        std::atomic<bool> failed{false};
+        auto worker = [&] {
+            for (int32_t b; (b = next.fetch_add(1)) < K;) {
+                try {
+                    P.h_bbw[b] = factor_block(P.h_bptr[b], P.h_bptr[b + 1] - P.h_bptr[b], rp, ci, va, ri, fac[b]);
+                } catch (...) {
+                    failed = true;
+                }
+            }
+        };
+        const int nt = (int)std::max(1u, std::min<unsigned>(16u, std::min<unsigned>(
+                                               (unsigned)K, std::thread::hardware_concurrency())));
+        std::vector<std::thread> pool;
+        for (int i = 1; i < nt; i++) pool.emplace_back(worker);
+        worker();
+        for (auto& th : pool) th.join();
+        if (failed) fail(OBK_E_NOMEM, "host memory for the block factors");
+    }
+    // blocks in order until the plan-wide limit; the device footprint must
+    // stay within hbm_budget
+    std::vector<int64_t> off(K, 0);
+    int64_t total = 0;
+    for (int32_t b = 0; b < K; b++) {
+        const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b];
+        if (P.h_bbw[b] < 0 || total + nb * (P.h_bbw[b] + 1) > kDirectMaxTotal) {
+            P.h_bbw[b] = -1;
+            continue;
+        }
+        off[b] = total;
+        total += nb * (P.h_bbw[b] + 1);
+        P.h_bdirect[b] = 1;
+    }
+    const size_t extra = (size_t)(2 * total + P.n) * sizeof(double);
+    if (total > 0 && P.opts.hbm_budget && P.device_bytes() + extra > P.opts.hbm_budget) {
+        P.h_bdirect.assign(K, 0);
+        P.h_bbw.assign(K, -1);
+        total = 0;
+    }
+    std::vector<int32_t> hbw(K, 0);
+    for (int32_t b = 0; b < K; b++) hbw[b] = (int32_t)std::max<int64_t>(0, P.h_bbw[b]);
+    host_to_dev(P.d_bdirect, P.h_bdirect, s);
+    host_to_dev(P.d_bbw, hbw, s);
+    host_to_dev(P.d_boff, off, s);
+    std::vector<double> lc((size_t)total), lr((size_t)total), dinv((size_t)P.n, 0.0);
+    for (int32_t b = 0; b < K; b++) {
+        if (!P.h_bdirect[b]) continue;
+        const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b], bw = P.h_bbw[b], W = bw + 1;
+        const std::vector<double>& L = fac[b];
+        std::copy(L.begin(), L.end(), lr.begin() + off[b]);
+        for (int64_t c = 0; c < nb; c++) {
+            for (int64_t d = 0; d <= bw; d++)
+                lc[(size_t)(off[b] + c * W + d)] = c + d < nb ? L[(size_t)((c + d) * W + bw - d)] : 0.0;
+            dinv[(size_t)(P.h_bptr[b] + c)] = 1.0 / L[(size_t)(c * W + bw)];
+        }
+        P.direct_lds = std::max(P.direct_lds, direct_lds_for(nb));
+    }
+    host_to_dev(P.lfc, lc, s);
+    host_to_dev(P.lfr, lr, s);
+    host_to_dev(P.ldinv, dinv, s);
+    const int64_t shmem = std::max(P.block_lds, P.direct_lds);
+    if (P.direct_lds > 0) {
+        OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_sweeps<1>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_direct),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.direct_lds));
+    }
 }
 
 // `sweeps` block sweeps on x (device, reordered coordinates); synchronises
@@ -666,8 +1066,17 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     a.tol2 = P.opts.block_tol * P.opts.block_tol;
     a.lseg = P.blseg.get();
     a.fit = P.d_bfit.get();
-    a.lds_path = (G == 1 && P.block_lds > 0) ? 1 : 0;
-    const unsigned shmem = a.lds_path ? (unsigned)P.block_lds : 0u;
+    a.direct = P.d_bdirect.get();
+    a.dbw = P.d_bbw.get();
+    a.doff = P.d_boff.get();
+    a.lfc = P.lfc.get();
+    a.lfr = P.lfr.get();
+    a.ldinv = P.ldinv.get();
+    const int64_t lds_need = std::max(P.block_lds, P.direct_lds);
+    a.lds_path = (G == 1 && lds_need > 0) ? 1 : 0;
+    const BlockKernel kern = block_kernel(P, G);
+    const unsigned shmem = kern.fn == reinterpret_cast<const void*>(k_block_direct) ? (unsigned)P.direct_lds
+                           : a.lds_path ? (unsigned)lds_need : 0u;
     OBK_HIP(hipMemsetAsync(P.bbar.get(), 0, sizeof(uint64_t), s));
     OBK_HIP(hipMemsetAsync(P.berr.get(), 0, sizeof(int), s));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -679,12 +1088,17 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     if (G == 1) {
         // one workgroup needs no co-residency guarantee: a plain launch, with
         // the events on its own dispatch packet
-        hipExtLaunchKernelGGL(k_block_sweeps, dim3(1), dim3(kBT), shmem, s, e0, e1, 0, a);
+        if (kern.fn == reinterpret_cast<const void*>(k_block_direct))
+            hipExtLaunchKernelGGL(k_block_direct, dim3(1), dim3(kBT), shmem, s, e0, e1, 0, a);
+        else if (kern.fn == reinterpret_cast<const void*>(k_block_sweeps<1>))
+            hipExtLaunchKernelGGL(k_block_sweeps<1>, dim3(1), dim3(kBT), shmem, s, e0, e1, 0, a);
+        else
+            hipExtLaunchKernelGGL(k_block_sweeps<0>, dim3(1), dim3(kBT), shmem, s, e0, e1, 0, a);
         le = hipGetLastError();
     } else {
         void* args[] = {&a};
         if (ms) OBK_HIP(hipEventRecord(e0, s));
-        le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps), dim3(G), dim3(kBT), args,
+        le = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_block_sweeps<0>), dim3(G), dim3(kBT), args,
                                         shmem, s);
         if (ms) OBK_HIP(hipEventRecord(e1, s));
     }
@@ -695,7 +1109,7 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     if (ms && le == hipSuccess && se == hipSuccess) (void)hipEventElapsedTime(ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    check_hip(le, "launch of k_block_sweeps");
+    check_hip(le, kern.name);
     check_hip(se, "hipStreamSynchronize");
     if (*h) fail(OBK_E_HIP, "a grid barrier of the block projection launch timed out");
 }
@@ -710,17 +1124,25 @@ int32_t profile_block(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, o
     std::vector<int64_t> it1 = dev_to_host(P.biters.get(), K, s);
     const double sv = 8, so = 4;
     double bytes = 0;
+    const bool one_wg = block_grid(P) == 1;
     for (int32_t b = 0; b < K; b++) {
         const double nb = (double)(P.h_bptr[b + 1] - P.h_bptr[b]);
         const double eb = (double)P.h_bnnz[b];
         const double tb = (double)(P.h_tptr[b + 1] - P.h_tptr[b]);
+        if (one_wg && b < (int32_t)P.h_bdirect.size() && P.h_bdirect[b]) {
+            // residual; the band and 1/L[i][i] once per triangular solve; x~ += A_t^T y
+            const double band = nb * (double)(P.h_bbw[b] + 1);
+            bytes += (double)sweeps * (eb * (sv + so) + nb * (so + 2 * sv) + tb * sv + 2 * band * sv +
+                                       2 * nb * sv + eb * (sv + so) + tb * (2 * so + 2 * sv));
+            continue;
+        }
         const double start = eb * (sv + so) + nb * (so + 3 * sv) + tb * sv;
         const double iter = 2 * eb * (sv + so) + nb * (so + 6 * sv) + tb * (3 * so + 5 * sv);
         bytes += (double)sweeps * start + (double)(it1[b] - it0[b]) * iter;
     }
     if (max_out < 1) return 0;
     std::memset(&out[0], 0, sizeof(out[0]));
-    std::strncpy(out[0].name, "k_block_sweeps", sizeof(out[0].name) - 1);
+    std::strncpy(out[0].name, block_kernel(P, block_grid(P)).name, sizeof(out[0].name) - 1);
     out[0].launches = 1;
     out[0].seconds = ms * 1e-3;
     out[0].bytes = bytes;

@@ -155,6 +155,9 @@ int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s
 // Centroid cosines, pairing and projection workspace of a block-form plan
 // (after the shared plan stages).
 void block_setup(obk_plan_s& P, hipStream_t s);
+// Banded Cholesky factors of A_t A_t^T for the blocks that have one (full row
+// rank to the pivot test, band within the size limits); sets h_bdirect.
+void block_factor(obk_plan_s& P, hipStream_t s);
 // `sweeps` block sweeps on x (device, reordered); synchronises the stream.
 // ms (may be null) receives the launch's event time in milliseconds.
 void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float* ms);
@@ -243,6 +246,17 @@ struct obk_plan_s {
     std::vector<int32_t> h_bfit;
     int64_t block_lds = 0;                    // dynamic LDS bytes of a one-workgroup launch (0: none fits)
     int block_occ = 0;                        // resident workgroups per CU of the projection launch
+    // direct projections (opts.block_solver = 0): banded Cholesky factor L of
+    // A_t A_t^T per block, bandwidth bw_b, stored twice: by columns,
+    // lfc[off_b + c (bw_b+1) + d] = L[c+d][c], and by rows,
+    // lfr[off_b + i (bw_b+1) + bw_b - (i-j)] = L[i][j] (zero outside the band);
+    // ldinv[row] = 1 / L[i][i]
+    std::vector<int32_t> h_bdirect;           // per block: 1 when projected from its factor [k]
+    std::vector<int64_t> h_bbw;               // per block: factor bandwidth, -1 without one [k]
+    obk::DevArray<int32_t> d_bdirect, d_bbw;
+    obk::DevArray<int64_t> d_boff;            // per block: offset of its factor in lfc / lfr
+    obk::DevArray<double> lfc, lfr, ldinv;
+    int64_t direct_lds = 0;                   // dynamic LDS bytes of a direct projection (0: none)
 
     // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
     // count and element size; replayed on the caller's stream

@@ -851,7 +851,10 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
     tr.mark("tiles");
-    if (P.block_form()) block_setup(P, s);
+    if (P.block_form()) {
+        block_setup(P, s);
+        block_factor(P, s);
+    }
     // ---- FP32 copies for the refinement mode
     if (P.has_fp32()) ensure_fp32(P, s);
 

@@ -79,6 +79,22 @@ def test_plan_rejects_unknown_rcm_engine_before_any_gpu_work(use_rcm):
         obk.plan(s.row_ptr, s.col, s.val, s.f, 0.1, rcm_engine="gpu")
 
 
+@pytest.mark.parametrize("solver", [-1, 2])
+def test_plan_rejects_unknown_block_solver_before_any_gpu_work(solver):
+    s = synth.c1(n=6)
+    csr = obk._Csr(s.n, s.n, s.nnz, s.row_ptr.ctypes.data, s.col.ctypes.data, s.val.ctypes.data, 0)
+    o = obk._Opts()
+    obk.lib().obk_opts_default(ctypes.byref(o))
+    assert o.block_solver == 0
+    o.block_k, o.block_solver = 2, solver
+    h = ctypes.c_void_p()
+    rc = obk.lib().obk_plan(ctypes.byref(csr), s.f.ctypes.data, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert "block_solver" in obk.lib().obk_last_error().decode()
+    with pytest.raises(ValueError):
+        obk.plan(s.row_ptr, s.col, s.val, s.f, 0.1, block_k=2, block_solver="lu")
+
+
 def _graph(s):
     A = s.scipy()
     G = ((A + A.T) != 0).astype(np.int8).tolil()

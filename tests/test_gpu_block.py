@@ -71,23 +71,70 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("solver", ["direct", "cg"])
 @pytest.mark.parametrize("name,maker,k,thr,sweeps", CASES, ids=[c[0] for c in CASES])
-def test_block_form_matches_oracle(name, maker, k, thr, sweeps):
+def test_block_form_matches_oracle(name, maker, k, thr, sweeps, solver):
     s = maker()
-    _say(f"[block] {name}: n={s.n} nnz={s.nnz} k={k} thr={thr} sweeps={sweeps}")
+    _say(f"[block] {name} ({solver}): n={s.n} nnz={s.nnz} k={k} thr={thr} sweeps={sweeps}")
     bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, thr)
     x_o = oracle.block_solve(bp, sweeps)
-    with obk.plan_system(s, thr, block_k=k) as P:
-        _check_plan(P, bp, k)
+    with obk.plan_system(s, thr, block_k=k, block_solver=solver) as P:
+        info_b = _check_plan(P, bp, k)
         x, info = P.solve(maxit=sweeps)
-        it = P.blocks()["cg_iters"]
+        b = P.blocks()
+        it, direct = b["cg_iters"], b["direct"]
         err = _rel(x, x_o)
-        _say(f"[block] {name}: |x - x_oracle| / |x_oracle| = {err:.3e}, CG iterations per block {it.tolist()}")
+        _say(f"[block] {name} ({solver}): |x - x_oracle| / |x_oracle| = {err:.3e}, direct blocks "
+             f"{int(direct.sum())}/{k} (bandwidths {b['factor_bandwidth'].tolist()}), CG iterations {it.tolist()}")
         assert info.sweeps == sweeps
         assert err <= TOL_X
+        if solver == "cg":
+            assert not direct.any()
+        else:
+            assert direct.all()               # these blocks have full row rank
+            assert not it.any()
         # bitwise repeatable
         x2, _ = P.solve(maxit=sweeps)
         assert np.array_equal(x, x2)
+
+
+def test_block_form_direct_at_block_size_1024():
+    """Blocks of 1024 rows of a stencil (factor bandwidth about twice the
+    grid side): the direct projections reproduce the oracle's pseudo-inverse
+    projections and agree with the CG ones."""
+    s = synth.c2(grid=64)
+    k, thr, sweeps = 4, 0.02, 2
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, thr)
+    x_o = oracle.block_solve(bp, sweeps)
+    with obk.plan_system(s, thr, block_k=k) as P:
+        x, _ = P.solve(maxit=sweeps)
+        b = P.blocks()
+    with obk.plan_system(s, thr, block_k=k, block_solver="cg") as P:
+        x_cg, _ = P.solve(maxit=sweeps)
+    _say(f"[block] stencil64 k=4 direct: err {_rel(x, x_o):.3e}, vs CG {_rel(x, x_cg):.3e}, "
+         f"bandwidths {b['factor_bandwidth'].tolist()}")
+    assert b["direct"].all() and (b["factor_bandwidth"] > 64).all()
+    assert _rel(x, x_o) <= TOL_X and _rel(x, x_cg) <= TOL_X
+
+
+def test_block_form_rank_deficient_block_keeps_cg():
+    """A block with two identical rows has no Cholesky factor (the pivot
+    test fails): it is projected by CG, and the least-norm projection is
+    still the oracle's."""
+    base = synth.c1(n=300, companion=True)
+    A = base.scipy().tolil()
+    A[7, :] = A[3, :]
+    A = A.tocsr()
+    A.sort_indices()
+    s = synth.from_scipy(A, base.x_star, name="dup-row")
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, 1, 0.02)
+    x_o = oracle.block_solve(bp, 1)
+    with obk.plan_system(s, 0.02, block_k=1) as P:
+        x, _ = P.solve(maxit=1)
+        b = P.blocks()
+    _say(f"[block] duplicated row, k=1: direct {b['direct'].tolist()}, err {_rel(x, x_o):.3e}")
+    assert not b["direct"].any() and b["cg_iters"].sum() > 0
+    assert _rel(x, x_o) <= TOL_X
 
 
 def test_block_form_single_block_is_the_least_norm_solution():
@@ -136,10 +183,12 @@ def test_block_form_underdetermined():
     assert _rel(x, x_o) <= TOL_X
 
 
-def test_block_form_all_zero_blocks():
+@pytest.mark.parametrize("solver", ["direct", "cg"])
+def test_block_form_all_zero_blocks(solver):
     """Isolated unknowns (an empty row and an empty column each) come last in
     the RCM order, so the last blocks hold only zero rows: their centroid is
-    0, their cosine with every block is 0 and their projection is empty."""
+    0, their cosine with every block is 0 and their projection is empty
+    (no CG iteration; a unit factor and y = 0 in the direct form)."""
     base = synth.c1(n=300, companion=True)
     A = sp.bmat([[base.scipy(), None], [None, sp.csr_matrix((100, 100))]]).tocsr()
     xs = np.concatenate([base.x_star, np.zeros(100)])
@@ -149,12 +198,15 @@ def test_block_form_all_zero_blocks():
     x_o = oracle.block_solve(bp, sweeps)
     zero_blocks = [b for b in range(k) if not np.any(bp.cos[b] > 0)]
     assert zero_blocks == [6, 7]
-    with obk.plan_system(s, thr, block_k=k) as P:
+    with obk.plan_system(s, thr, block_k=k, block_solver=solver) as P:
         _check_plan(P, bp, k)
         x, _ = P.solve(maxit=sweeps)
-        it = P.blocks()["cg_iters"]
-    _say(f"[block] zero blocks {zero_blocks}: CG iterations {it.tolist()}, err {_rel(x, x_o):.3e}")
-    assert all(it[b] == 0 for b in zero_blocks) and all(it[b] > 0 for b in range(6))
+        it, direct = P.blocks()["cg_iters"], P.blocks()["direct"]
+    _say(f"[block] zero blocks {zero_blocks} ({solver}): CG iterations {it.tolist()}, err {_rel(x, x_o):.3e}")
+    if solver == "cg":
+        assert all(it[b] == 0 for b in zero_blocks) and all(it[b] > 0 for b in range(6))
+    else:
+        assert direct.all() and not it.any()
     assert _rel(x, x_o) <= TOL_X
 
 
@@ -197,15 +249,17 @@ def test_block_form_tolerance_stops_and_converges():
     assert info.sweeps == want
 
 
-def test_block_form_sweep_device_and_profile():
+@pytest.mark.parametrize("solver", ["direct", "cg"])
+def test_block_form_sweep_device_and_profile(solver):
     """Device-resident sweeps and the per-kernel profile of the block form
-    (one cooperative launch; bytes from the CG iteration counts)."""
+    (one launch; bytes from the factor bands, or from the CG iteration
+    counts)."""
     import torch
     s = synth.c2(grid=48)
     k, thr, sweeps = 8, 0.02, 2
     bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, thr)
     xt_o = oracle.block_sweep(bp, np.zeros(s.n), sweeps)
-    with obk.plan_system(s, thr, block_k=k) as P:
+    with obk.plan_system(s, thr, block_k=k, block_solver=solver) as P:
         xt = torch.zeros(s.n, dtype=torch.float64, device="cuda")
         P.sweep_device(xt, sweeps)
         torch.cuda.synchronize()
@@ -213,9 +267,12 @@ def test_block_form_sweep_device_and_profile():
         it0 = P.blocks()["cg_iters"].sum()
         prof = P.sweep_profile(xt, 1)
         it1 = P.blocks()["cg_iters"].sum()
-    _say(f"[block] profile {prof}, CG iterations {it1 - it0}")
-    assert len(prof) == 1 and prof[0]["name"] == "k_block_sweeps"
-    assert prof[0]["seconds"] > 0 and prof[0]["bytes"] > 0 and it1 > it0
+    _say(f"[block] profile ({solver}) {prof}, CG iterations {it1 - it0}")
+    assert len(prof) == 1 and prof[0]["seconds"] > 0 and prof[0]["bytes"] > 0
+    if solver == "cg":
+        assert prof[0]["name"] == "k_block_sweeps" and it1 > it0
+    else:
+        assert prof[0]["name"] == "k_block_direct" and it1 == it0
 
 
 def test_block_form_rejected_by_batch():
@@ -256,7 +313,7 @@ def test_block_form_iteration_cap_and_budget():
     plan's footprint is refused."""
     s = synth.c2(grid=32)
     k = 4
-    with obk.plan_system(s, 0.02, block_k=k, block_maxit=3) as P:
+    with obk.plan_system(s, 0.02, block_k=k, block_maxit=3, block_solver="cg") as P:
         x1, _ = P.solve(maxit=2)
         it = P.blocks()["cg_iters"]
         x2, _ = P.solve(maxit=2)
