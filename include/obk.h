@@ -230,8 +230,11 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  *
  * Direct projections (opts.block_solver = 0): y solves A_t A_t^T y =
  * f_t - A_t x~ by a forward and a backward banded triangular solve with the
- * block's Cholesky factor (formed on the host at plan time, in FP64, from the
- * pairwise row products accumulated in ascending column order).  A block
+ * block's Cholesky factor, formed on the host at plan time in FP64 from the
+ * pairwise row products (accumulated in ascending column order) with the
+ * block's rows in the reverse Cuthill-McKee order of its own Gram graph
+ * (two rows adjacent when they share a column), which keeps the band
+ * narrow.  A block
  * whose pivots fall below 1e-8 of their diagonal (rank deficient to working
  * accuracy), whose band would exceed 2^26 entries, or with more than 8192
  * rows keeps CG, and so does every block of a launch over several
@@ -321,6 +324,12 @@ OBK_API obk_status obk_sweep_device(obk_plan_t plan, double *x_tilde_dev, int64_
  *   phase S: e_g (s + 4) + t_g (8 + 2 s) + n_g s
  *            (values and row ids; column offset, column id, x read and
  *            written per touched column; w read once per row)
+ * Block-form plans whose blocks are all projected from their factors (one
+ * workgroup) report k_block_direct; its bytes per projection of block b
+ * (n_b rows, e_b entries, t_b touched columns, factor bandwidth w_b, s = 8)
+ * are e_b (s + 4) + n_b (4 + 2 s) + t_b s for the residual, 2 s n_b (w_b + 1)
+ * + 2 s n_b for the band and the inverse pivots (once per triangular solve),
+ * and e_b (s + 4) + t_b (8 + 2 s) for x~ += A_t^T y.
  * Complex plans report k_phase_r_z / k_phase_s_z with the same formulas and
  * s = 16 for values, f~, w and x~ (1/||a||^2 stays 8 bytes).  Block-form
  * plans report one kernel, k_block_sweeps, timed over the whole launch of

@@ -45,7 +45,8 @@ size_t obk_plan_s::device_bytes() const {
            b32.bytes() + d32.bytes() + w32.bytes() + r64.bytes() + d_bptr.bytes() + d_btptr.bytes() +
            d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
            biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes() +
-           d_bdirect.bytes() + d_bbw.bytes() + d_boff.bytes() + lfc.bytes() + lfr.bytes() + ldinv.bytes();
+           d_bdirect.bytes() + d_bbw.bytes() + d_boff.bytes() + lfc.bytes() + lfr.bytes() + ldinv.bytes() +
+           d_lperm.bytes() + d_lpos.bytes();
 }
 
 namespace {

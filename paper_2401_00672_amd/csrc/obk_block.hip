@@ -181,7 +181,9 @@ struct BlockArgs {
     const int64_t* doff;      // per block: offset of the factor in lfc / lfr
     const double* lfc;        // factors by columns: [off + c (bw+1) + d] = L[c+d][c]
     const double* lfr;        // factors by rows: [off + i (bw+1) + bw - (i-j)] = L[i][j]
-    const double* ldinv;      // 1 / L[i][i] per row [n]
+    const double* ldinv;      // 1 / L[k][k] per factor position [n]
+    const int32_t* lperm;     // per factor position k of a block: its block row [n]
+    const int32_t* lpos;      // per block row: its factor position [n]
     int64_t sweeps;
     int32_t lds_path;         // 1: single-workgroup launch with dynamic LDS for the fitting blocks
     int32_t k;
@@ -455,16 +457,16 @@ __device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
     auto bwd_diag = [=](int p0, int pw) {
         return [=](int k, int c) -> int { return (c < pw && c >= k && c - k <= bw) ? (p0 + k) * W + (c - k) : -1; };
     };
-    // r = f_t - A_t x~ (all-zero rows: 0); the first diagonal block meanwhile
+    // r = f_t - A_t x~ in factor order (all-zero rows: 0); the first diagonal block meanwhile
     stage_load(sv, sd, Lr, dinv, 0, min(kPanel, nb), fwd_diag(0, min(kPanel, nb)));
-    for (int i = t; i < nb; i += kBT) {
+    for (int k = t; k < nb; k += kBT) {
+        const int64_t i = r0 + a.lperm[r0 + k];
         double r = 0.0;
-        if (a.rinv[r0 + i] != 0.0) {
-            const double d = dot_seq(a.rptr[r0 + i], a.rptr[r0 + i + 1], a.rval, a.rcol,
-                                     [&](int32_t c) { return a.x[c]; });
-            r = a.rf[r0 + i] - d;
+        if (a.rinv[i] != 0.0) {
+            const double d = dot_seq(a.rptr[i], a.rptr[i + 1], a.rval, a.rcol, [&](int32_t c) { return a.x[c]; });
+            r = a.rf[i] - d;
         }
-        z[i] = r;
+        z[k] = r;
     }
     stage_store(Dbuf[0], sv, sd);
     __syncthreads();
@@ -568,7 +570,7 @@ __device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
     for (int q = t; q < ns; q += kBT) {
         const int64_t sg = s0 + q;
         double acc = 0.0;
-        for (int64_t e = a.sptr[sg]; e < a.sptr[sg + 1]; e++) acc = acc + a.sval[e] * z[a.srow[e] - r0];
+        for (int64_t e = a.sptr[sg]; e < a.sptr[sg + 1]; e++) acc = acc + a.sval[e] * z[a.lpos[a.srow[e]]];
         const int32_t c = a.tcol[sg];
         a.x[c] = a.x[c] + acc;
     }
@@ -910,10 +912,15 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
 }
 
 // Banded Cholesky factor of B B^T for the rows [r0, r0 + nb) of the
-// reordered CSR: Gram entries accumulated over the columns in ascending
-// order, then L row by row.  Returns the bandwidth, or -1 when the block is
-// rank deficient to the pivot test, too wide, or too large.  All-zero rows
-// (rinv 0) get a unit diagonal: they are decoupled and their y is 0.
+// reordered CSR.  The rows are first put in the reverse Cuthill-McKee order
+// of the block's own Gram graph (two rows adjacent when they share a
+// column): the block's rows follow the global order, which for a band of
+// the matrix runs across the block, while the local order runs along it and
+// keeps the factor's band narrow.  perm[k] is the block row at position k.
+// Gram entries are accumulated over the columns in ascending order, then L
+// row by row.  Returns the bandwidth, or -1 when the block is rank deficient
+// to the pivot test, too wide, or too large.  All-zero rows (rinv 0) get a
+// unit diagonal: they are decoupled and their y is 0.
 constexpr int64_t kDirectMaxRows = 8192;
 constexpr int64_t kDirectMaxBand = int64_t(1) << 24;     // band entries per block
 constexpr int64_t kDirectMaxTotal = int64_t(1) << 27;    // band entries per plan
@@ -921,14 +928,40 @@ constexpr double kPivotTol = 1e-8;
 
 static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
                             const std::vector<double>& va, const std::vector<double>& rinv,
-                            std::vector<double>& L) {
+                            std::vector<double>& L, std::vector<int32_t>& perm) {
     if (nb <= 0 || nb > kDirectMaxRows) return -1;
     struct Ent { int32_t c, i; double v; };
     std::vector<Ent> es;
     es.reserve((size_t)(rp[r0 + nb] - rp[r0]));
     for (int64_t i = 0; i < nb; i++)
         for (int64_t k = rp[r0 + i]; k < rp[r0 + i + 1]; k++) es.push_back({ci[k], (int32_t)i, va[k]});
-    std::sort(es.begin(), es.end(), [](const Ent& x, const Ent& y) { return x.c != y.c ? x.c < y.c : x.i < y.i; });
+    auto by_col = [](const Ent& x, const Ent& y) { return x.c != y.c ? x.c < y.c : x.i < y.i; };
+    std::sort(es.begin(), es.end(), by_col);
+    // the Gram graph and its reverse Cuthill-McKee order
+    std::vector<uint64_t> edges;
+    for (size_t a = 0; a < es.size();) {
+        size_t e = a;
+        while (e < es.size() && es[e].c == es[a].c) e++;
+        for (size_t p = a; p < e; p++)
+            for (size_t q = a; q < e; q++)
+                if (p != q) edges.push_back(((uint64_t)(uint32_t)es[p].i << 32) | (uint32_t)es[q].i);
+        a = e;
+    }
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    std::vector<int64_t> gptr(nb + 1, 0);
+    std::vector<int32_t> gadj(edges.size());
+    for (size_t q = 0; q < edges.size(); q++) {
+        gptr[(edges[q] >> 32) + 1]++;
+        gadj[q] = (int32_t)(edges[q] & 0xffffffffu);
+    }
+    for (int64_t i = 0; i < nb; i++) gptr[i + 1] += gptr[i];
+    perm.assign((size_t)nb, 0);
+    host_rcm(nb, gptr.data(), gadj.data(), perm.data());
+    std::vector<int32_t> pos((size_t)nb);
+    for (int64_t k = 0; k < nb; k++) pos[perm[k]] = (int32_t)k;
+    for (Ent& e : es) e.i = pos[e.i];
+    std::sort(es.begin(), es.end(), by_col);
     int64_t bw = 0;
     for (size_t a = 0; a < es.size();) {
         size_t e = a;
@@ -947,8 +980,8 @@ static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& 
             for (size_t q = a; q <= p; q++) at(es[p].i, es[q].i) += es[p].v * es[q].v;
         a = e;
     }
-    for (int64_t i = 0; i < nb; i++)
-        if (rinv[r0 + i] == 0.0) at(i, i) = 1.0;
+    for (int64_t k = 0; k < nb; k++)
+        if (rinv[r0 + perm[k]] == 0.0) at(k, k) = 1.0;
     for (int64_t i = 0; i < nb; i++) {
         const int64_t jlo = std::max<int64_t>(0, i - bw);
         const double gii = at(i, i);
@@ -972,6 +1005,7 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
     P.h_bbw.assign(K, -1);
     P.direct_lds = 0;
     std::vector<std::vector<double>> fac(K);
+    std::vector<std::vector<int32_t>> perms(K);
     if (P.opts.block_solver == 0 && K > 0) {
         const int64_t n = P.n;
         const std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
@@ -983,7 +1017,8 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
         auto worker = [&] {
             for (int32_t b; (b = next.fetch_add(1)) < K;) {
                 try {
-                    P.h_bbw[b] = factor_block(P.h_bptr[b], P.h_bptr[b + 1] - P.h_bptr[b], rp, ci, va, ri, fac[b]);
+                    P.h_bbw[b] = factor_block(P.h_bptr[b], P.h_bptr[b + 1] - P.h_bptr[b], rp, ci, va, ri, fac[b],
+                                              perms[b]);
                 } catch (...) {
                     failed = true;
                 }
@@ -1011,7 +1046,7 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
         total += nb * (P.h_bbw[b] + 1);
         P.h_bdirect[b] = 1;
     }
-    const size_t extra = (size_t)(2 * total + P.n) * sizeof(double);
+    const size_t extra = (size_t)(2 * total + P.n) * sizeof(double) + (size_t)(2 * P.n) * sizeof(int32_t);
     if (total > 0 && P.opts.hbm_budget && P.device_bytes() + extra > P.opts.hbm_budget) {
         P.h_bdirect.assign(K, 0);
         P.h_bbw.assign(K, -1);
@@ -1023,6 +1058,7 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
     host_to_dev(P.d_bbw, hbw, s);
     host_to_dev(P.d_boff, off, s);
     std::vector<double> lc((size_t)total), lr((size_t)total), dinv((size_t)P.n, 0.0);
+    std::vector<int32_t> hperm((size_t)P.n, 0), hpos((size_t)P.n, 0);
     for (int32_t b = 0; b < K; b++) {
         if (!P.h_bdirect[b]) continue;
         const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b], bw = P.h_bbw[b], W = bw + 1;
@@ -1032,12 +1068,16 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
             for (int64_t d = 0; d <= bw; d++)
                 lc[(size_t)(off[b] + c * W + d)] = c + d < nb ? L[(size_t)((c + d) * W + bw - d)] : 0.0;
             dinv[(size_t)(P.h_bptr[b] + c)] = 1.0 / L[(size_t)(c * W + bw)];
+            hperm[(size_t)(P.h_bptr[b] + c)] = perms[b][c];
+            hpos[(size_t)(P.h_bptr[b] + perms[b][c])] = (int32_t)c;
         }
         P.direct_lds = std::max(P.direct_lds, direct_lds_for(nb));
     }
     host_to_dev(P.lfc, lc, s);
     host_to_dev(P.lfr, lr, s);
     host_to_dev(P.ldinv, dinv, s);
+    host_to_dev(P.d_lperm, hperm, s);
+    host_to_dev(P.d_lpos, hpos, s);
     const int64_t shmem = std::max(P.block_lds, P.direct_lds);
     if (P.direct_lds > 0) {
         OBK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_block_sweeps<1>),
@@ -1072,6 +1112,8 @@ void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float
     a.lfc = P.lfc.get();
     a.lfr = P.lfr.get();
     a.ldinv = P.ldinv.get();
+    a.lperm = P.d_lperm.get();
+    a.lpos = P.d_lpos.get();
     const int64_t lds_need = std::max(P.block_lds, P.direct_lds);
     a.lds_path = (G == 1 && lds_need > 0) ? 1 : 0;
     const BlockKernel kern = block_kernel(P, G);

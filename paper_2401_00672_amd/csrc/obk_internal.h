@@ -247,7 +247,8 @@ struct obk_plan_s {
     int64_t block_lds = 0;                    // dynamic LDS bytes of a one-workgroup launch (0: none fits)
     int block_occ = 0;                        // resident workgroups per CU of the projection launch
     // direct projections (opts.block_solver = 0): banded Cholesky factor L of
-    // A_t A_t^T per block, bandwidth bw_b, stored twice: by columns,
+    // P A_t A_t^T P^T per block (P: the reverse Cuthill-McKee order of the
+    // block's Gram graph), bandwidth bw_b, stored twice: by columns,
     // lfc[off_b + c (bw_b+1) + d] = L[c+d][c], and by rows,
     // lfr[off_b + i (bw_b+1) + bw_b - (i-j)] = L[i][j] (zero outside the band);
     // ldinv[row] = 1 / L[i][i]
@@ -256,6 +257,7 @@ struct obk_plan_s {
     obk::DevArray<int32_t> d_bdirect, d_bbw;
     obk::DevArray<int64_t> d_boff;            // per block: offset of its factor in lfc / lfr
     obk::DevArray<double> lfc, lfr, ldinv;
+    obk::DevArray<int32_t> d_lperm, d_lpos;   // factor order of each block's rows, and its inverse [n]
     int64_t direct_lds = 0;                   // dynamic LDS bytes of a direct projection (0: none)
 
     // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
