@@ -433,43 +433,120 @@ __device__ __forceinline__ void stage_store(double* D, const double (&v)[kStageP
     if (threadIdx.x < kPanel) D[kPanel * kDStride + threadIdx.x] = dv;
 }
 
-__device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
-    static_assert(kPanel * kPanel % kBT == 0 && kPanel == 64, "panel of one wave");
-    const int t = threadIdx.x;
-    // in-block indices fit 32 bits: a block has at most 8192 rows and 2^24 band entries
-    const int64_t r0 = a.bptr[b];
-    const int nb = (int)(a.bptr[b + 1] - r0);
-    const int64_t s0 = a.btptr[b];
-    const int ns = (int)(a.btptr[b + 1] - s0);
-    const int bw = a.dbw[b], W = bw + 1;
-    const double* Lc = a.lfc + a.doff[b];
-    const double* Lr = a.lfr + a.doff[b];
-    const double* dinv = a.ldinv + r0;
-    double* z = dyn;
-    double* Dbuf[2] = {dyn + nb, dyn + nb + kDiagBuf};
+// Triangular solve with a band narrower than a wave (bw < 64), in place on
+// z (LDS): forward L z = r (kFwd) or backward L^T y = z.  Wave 0 keeps the
+// 64 rows at and after the current one (before it, backward) in a circular
+// window: row j lives in lane j mod 64.  Step k takes row k's finished value
+// (times 1 / L[k][k]) from its lane, updates the rows of the band with one
+// FMA each, and the lane takes the row 64 further on.  The other waves copy
+// the band, 64 rows at a time, into the LDS buffer wave 0 is not reading.
+template <bool kFwd>
+__device__ __forceinline__ void window_solve(double* z, int nb, int bw, const double* __restrict__ Lf,
+                                             const double* __restrict__ dinv, double* buf0, double* buf1) {
+    const int t = threadIdx.x, W = bw + 1;
+    const int nch = (nb + kPanel - 1) / kPanel;
+    // chunk ci covers rows [cb, ce): ascending chunks forward, descending backward
+    auto range = [&](int ci, int& cb, int& ce) {
+        if (kFwd) { cb = ci * kPanel; ce = min(nb, cb + kPanel); }
+        else { ce = nb - ci * kPanel; cb = max(0, ce - kPanel); }
+    };
+    // copy a chunk's band rows (at most 64 x 64 values) and inverse pivots:
+    // every load of the thread is issued before its stores
+    constexpr int kPer = (kPanel * kPanel + (kBT - kPanel) - 1) / (kBT - kPanel);
+    auto stage = [&](int ci, double* B, int first, int stride) {
+        int cb, ce;
+        range(ci, cb, ce);
+        const int len = (ce - cb) * W;
+        double v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int q = first + u * stride;
+            v[u] = Lf[cb * W + (q < len ? q : 0)];
+        }
+        const double dv = dinv[cb + (first < ce - cb ? first : 0)];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int q = first + u * stride;
+            if (q < len) B[q] = v[u];
+        }
+        if (first < ce - cb) B[kPanel * kPanel + first] = dv;
+    };
+    // wave 0 is the solving wave; the test is wave-uniform by construction
+    const bool solver = (__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6) == 0;
+    double w = 0.0;
+    if (solver) {
+        const int j = kFwd ? t : (nb - 1) - ((nb - 1 - t) & (kPanel - 1));
+        w = (j >= 0 && j < nb) ? z[j] : 0.0;
+    }
+    stage(0, buf0, t, kBT);
+    __syncthreads();
+    for (int ci = 0; ci < nch; ci++) {
+        double* B = (ci & 1) ? buf1 : buf0;
+        if (!solver) {
+            if (ci + 1 < nch) stage(ci + 1, (ci & 1) ? buf0 : buf1, t - kPanel, kBT - kPanel);
+        } else {
+            int cb, ce;
+            range(ci, cb, ce);
+            const int cw = ce - cb;
+            // this lane's row is finished at step my_s (if my_s < cw); it then
+            // takes the row 64 further on, whose right-hand side is read now,
+            // off the chain of dependent steps
+            const int my_s = kFwd ? ((t - cb) & (kPanel - 1)) : ((ce - 1 - t) & (kPanel - 1));
+            const int my_k = kFwd ? cb + my_s : ce - 1 - my_s;
+            const int nxt = kFwd ? my_k + kPanel : my_k - kPanel;
+            const double nv = z[(my_s < cw && nxt >= 0 && nxt < nb) ? nxt : 0];
+            const double nval = (my_s < cw && nxt >= 0 && nxt < nb) ? nv : 0.0;
+            double fin = 0.0;
+            for (int s0 = 0; s0 < cw; s0 += 8) {
+                double lv[8], dv[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int st = s0 + u;
+                    const int kk = st < cw ? (kFwd ? st : cw - 1 - st) : 0;
+                    const int k = cb + kk;
+                    const int d = kFwd ? ((t - k) & (kPanel - 1)) : ((k - t) & (kPanel - 1));
+                    const bool ok = st < cw && d >= 1 && d <= bw;
+                    const double x = B[ok ? kk * W + (kFwd ? d : bw - d) : 0];
+                    lv[u] = ok ? x : 0.0;
+                    dv[u] = B[kPanel * kPanel + kk];
+                }
+                auto step = [&](int u) {
+                    const int st = s0 + u;
+                    const int k = cb + (kFwd ? st : cw - 1 - st);
+                    const int src = k & (kPanel - 1);
+                    const double zk = readlane_f64(w, src) * dv[u];
+                    w = __builtin_fma(-lv[u], zk, w);
+                    fin = (t == src) ? zk : fin;
+                    w = (t == src) ? nval : w;
+                };
+                if (s0 + 8 <= cw) {
+#pragma unroll
+                    for (int u = 0; u < 8; u++) step(u);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        if (u < cw - s0) step(u);
+                }
+            }
+            if (my_s < cw) z[my_k] = fin;
+        }
+        __syncthreads();
+    }
+}
+
+// The triangular solves by panels of 64 rows (any bandwidth), in place on z.
+__device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const double* __restrict__ Lc,
+                                             const double* __restrict__ Lr, const double* __restrict__ dinv,
+                                             double* const (&Dbuf)[2], double (&sv)[kStagePer],
+                                             double (&lv)[kPartCols], double& sd) {
+    const int t = threadIdx.x, W = bw + 1;
     const int np = (nb + kPanel - 1) / kPanel;
-    double sv[kStagePer], lv[kPartCols], sd = 0.0;
-    // D[k][c] = L[p0+k][p0+c] for c <= k (rows of the band): forward panels
     auto fwd_diag = [=](int p0, int pw) {
         return [=](int k, int c) -> int { return (k < pw && c <= k && k - c <= bw) ? (p0 + k) * W + bw - (k - c) : -1; };
     };
-    // D[k][c] = L[p0+c][p0+k] for c >= k (columns of the band): backward panels
     auto bwd_diag = [=](int p0, int pw) {
         return [=](int k, int c) -> int { return (c < pw && c >= k && c - k <= bw) ? (p0 + k) * W + (c - k) : -1; };
     };
-    // r = f_t - A_t x~ in factor order (all-zero rows: 0); the first diagonal block meanwhile
-    stage_load(sv, sd, Lr, dinv, 0, min(kPanel, nb), fwd_diag(0, min(kPanel, nb)));
-    for (int k = t; k < nb; k += kBT) {
-        const int64_t i = r0 + a.lperm[r0 + k];
-        double r = 0.0;
-        if (a.rinv[i] != 0.0) {
-            const double d = dot_seq(a.rptr[i], a.rptr[i + 1], a.rval, a.rcol, [&](int32_t c) { return a.x[c]; });
-            r = a.rf[i] - d;
-        }
-        z[k] = r;
-    }
-    stage_store(Dbuf[0], sv, sd);
-    __syncthreads();
     // L z = r, panels from the top
     for (int ip = 0; ip < np; ip++) {
         const int p0 = ip * kPanel;
@@ -565,6 +642,49 @@ __device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
         }
         if (ip > 0) stage_store(Dbuf[(np - ip) & 1], sv, sd);
         __syncthreads();
+    }
+}
+
+__device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
+    static_assert(kPanel * kPanel % kBT == 0 && kPanel == 64, "panel of one wave");
+    const int t = threadIdx.x;
+    // in-block indices fit 32 bits: a block has at most 8192 rows and 2^24 band entries
+    const int64_t r0 = a.bptr[b];
+    const int nb = (int)(a.bptr[b + 1] - r0);
+    const int64_t s0 = a.btptr[b];
+    const int ns = (int)(a.btptr[b + 1] - s0);
+    const int bw = a.dbw[b], W = bw + 1;
+    const double* Lc = a.lfc + a.doff[b];
+    const double* Lr = a.lfr + a.doff[b];
+    const double* dinv = a.ldinv + r0;
+    double* z = dyn;
+    double* Dbuf[2] = {dyn + nb, dyn + nb + kDiagBuf};
+    double sv[kStagePer], lv[kPartCols], sd = 0.0;
+    const bool narrow = bw < kPanel;
+    // r = f_t - A_t x~ in factor order (all-zero rows: 0); for the panel
+    // solves, the first diagonal block meanwhile
+    if (!narrow) {
+        const int pw = min(kPanel, nb);
+        stage_load(sv, sd, Lr, dinv, 0, pw, [=](int k, int c) -> int {
+            return (k < pw && c <= k && k - c <= bw) ? k * W + bw - (k - c) : -1;
+        });
+    }
+    for (int k = t; k < nb; k += kBT) {
+        const int64_t i = r0 + a.lperm[r0 + k];
+        double r = 0.0;
+        if (a.rinv[i] != 0.0) {
+            const double d = dot_seq(a.rptr[i], a.rptr[i + 1], a.rval, a.rcol, [&](int32_t c) { return a.x[c]; });
+            r = a.rf[i] - d;
+        }
+        z[k] = r;
+    }
+    if (!narrow) stage_store(Dbuf[0], sv, sd);
+    __syncthreads();
+    if (narrow) {
+        window_solve<true>(z, nb, bw, Lc, dinv, Dbuf[0], Dbuf[1]);
+        window_solve<false>(z, nb, bw, Lr, dinv, Dbuf[0], Dbuf[1]);
+    } else {
+        panel_solves(z, nb, bw, Lc, Lr, dinv, Dbuf, sv, lv, sd);
     }
     // x~ += A_t^T y on the touched columns, rows in ascending order
     for (int q = t; q < ns; q += kBT) {
