@@ -71,6 +71,10 @@ CASES = [
 ]
 
 
+WIDE_BAND = {"c1-companion-600/k1", "c1-companion-600/k3"}
+NARROW_BAND = {"c1-601/k6-ragged", "stencil24/k6", "stencil24/k16", "c1-40/k40-rows"}
+
+
 @pytest.mark.parametrize("solver", ["direct", "cg"])
 @pytest.mark.parametrize("name,maker,k,thr,sweeps", CASES, ids=[c[0] for c in CASES])
 def test_block_form_matches_oracle(name, maker, k, thr, sweeps, solver):
@@ -93,6 +97,12 @@ def test_block_form_matches_oracle(name, maker, k, thr, sweeps, solver):
         else:
             assert direct.all()               # these blocks have full row rank
             assert not it.any()
+            # both triangular-solve forms are exercised: one-wave window for
+            # bands under 64, panels for wider ones
+            if name in WIDE_BAND:
+                assert (b["factor_bandwidth"] >= 64).all()
+            if name in NARROW_BAND:
+                assert (b["factor_bandwidth"] < 64).all()
         # bitwise repeatable
         x2, _ = P.solve(maxit=sweeps)
         assert np.array_equal(x, x2)
