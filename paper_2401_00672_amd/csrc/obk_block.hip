@@ -36,6 +36,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -433,16 +434,16 @@ __device__ __forceinline__ void stage_store(double* D, const double (&v)[kStageP
     if (threadIdx.x < kPanel) D[kPanel * kDStride + threadIdx.x] = dv;
 }
 
-// Triangular solve with a band narrower than a wave (bw < 64), in place on
-// z (LDS): forward L z = r (kFwd) or backward L^T y = z.  Wave 0 keeps the
+// Unit triangular solve with a band narrower than a wave (bw < 64), in place
+// on z (LDS): forward U z = r (kFwd) or backward U^T y = z.  Wave 0 keeps the
 // 64 rows at and after the current one (before it, backward) in a circular
-// window: row j lives in lane j mod 64.  Step k takes row k's finished value
-// (times 1 / L[k][k]) from its lane, updates the rows of the band with one
-// FMA each, and the lane takes the row 64 further on.  The other waves copy
-// the band, 64 rows at a time, into the LDS buffer wave 0 is not reading.
+// window: row j lives in lane j mod 64.  Step k broadcasts row k's finished
+// value from its lane, updates the rows of the band with one FMA each, and
+// the lane takes the row 64 further on.  The other waves copy the band, 64
+// rows at a time, into the LDS buffer wave 0 is not reading.
 template <bool kFwd>
 __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const double* __restrict__ Lf,
-                                             const double* __restrict__ dinv, double* buf0, double* buf1) {
+                                             double* buf0, double* buf1) {
     const int t = threadIdx.x, W = bw + 1;
     const int nch = (nb + kPanel - 1) / kPanel;
     // chunk ci covers rows [cb, ce): ascending chunks forward, descending backward
@@ -463,13 +464,11 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
             const int q = first + u * stride;
             v[u] = Lf[cb * W + (q < len ? q : 0)];
         }
-        const double dv = dinv[cb + (first < ce - cb ? first : 0)];
 #pragma unroll
         for (int u = 0; u < kPer; u++) {
             const int q = first + u * stride;
             if (q < len) B[q] = v[u];
         }
-        if (first < ce - cb) B[kPanel * kPanel + first] = dv;
     };
     // wave 0 is the solving wave; the test is wave-uniform by construction
     const bool solver = (__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6) == 0;
@@ -497,8 +496,12 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
             const double nv = z[(my_s < cw && nxt >= 0 && nxt < nb) ? nxt : 0];
             const double nval = (my_s < cw && nxt >= 0 && nxt < nb) ? nv : 0.0;
             double fin = 0.0;
+            // a lane that finishes a row gets its first update for the next
+            // row 64 - bw steps later, so for bw <= 56 the lanes finished in
+            // a group of 8 steps take their next rows together after it
+            const bool grouped = bw <= kPanel - 8;
             for (int s0 = 0; s0 < cw; s0 += 8) {
-                double lv[8], dv[8];
+                double lv[8];
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
                     const int st = s0 + u;
@@ -508,24 +511,26 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
                     const bool ok = st < cw && d >= 1 && d <= bw;
                     const double x = B[ok ? kk * W + (kFwd ? d : bw - d) : 0];
                     lv[u] = ok ? x : 0.0;
-                    dv[u] = B[kPanel * kPanel + kk];
                 }
-                auto step = [&](int u) {
+                // the unit diagonal: row k's value is final when it is broadcast
+                auto step = [&](int u, bool replace) {
                     const int st = s0 + u;
                     const int k = cb + (kFwd ? st : cw - 1 - st);
                     const int src = k & (kPanel - 1);
-                    const double zk = readlane_f64(w, src) * dv[u];
+                    const double zk = readlane_f64(w, src);
                     w = __builtin_fma(-lv[u], zk, w);
                     fin = (t == src) ? zk : fin;
-                    w = (t == src) ? nval : w;
+                    if (replace) w = (t == src) ? nval : w;
                 };
-                if (s0 + 8 <= cw) {
+                if (s0 + 8 <= cw && grouped) {
 #pragma unroll
-                    for (int u = 0; u < 8; u++) step(u);
+                    for (int u = 0; u < 8; u++) step(u, false);
+                    const bool mine = my_s >= s0 && my_s < s0 + 8;
+                    w = mine ? nval : w;
                 } else {
 #pragma unroll
                     for (int u = 0; u < 8; u++)
-                        if (u < cw - s0) step(u);
+                        if (u < cw - s0) step(u, true);
                 }
             }
             if (my_s < cw) z[my_k] = fin;
@@ -567,7 +572,6 @@ __device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const do
         if (t < kPanel) {
             // reads LDS only: the prefetches above stay in flight
             double v = t < pw ? z[p0 + t] : 0.0;
-            const double di = D[kPanel * kDStride + t];
             for (int c0 = 0; c0 < pw; c0 += 8) {
                 double dr[8];
 #pragma unroll
@@ -576,7 +580,7 @@ __device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const do
                 for (int u = 0; u < 8; u++) {
                     const int c = c0 + u;
                     if (c < pw) {
-                        const double zc = readlane_f64(v * di, c);
+                        const double zc = readlane_f64(v, c);
                         const double upd = v - dr[u] * zc;
                         v = (t == c) ? zc : ((t > c) ? upd : v);
                     }
@@ -594,7 +598,10 @@ __device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const do
         if (ip + 1 < np) stage_store(Dbuf[(ip + 1) & 1], sv, sd);
         __syncthreads();
     }
-    // L^T y = z, panels from the bottom
+    // D^-1 between the two unit triangular solves
+    for (int k = t; k < nb; k += kBT) z[k] = z[k] * dinv[k];
+    __syncthreads();
+    // U^T y = z, panels from the bottom
     {
         const int p0 = (np - 1) * kPanel;
         stage_load(sv, sd, Lc, dinv, p0, nb - p0, bwd_diag(p0, nb - p0));
@@ -616,7 +623,6 @@ __device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const do
         if (ip > 0) stage_load(sv, sd, Lc, dinv, p0 - kPanel, kPanel, bwd_diag(p0 - kPanel, kPanel));
         if (t < kPanel) {
             double v = t < pw ? z[p0 + t] : 0.0;
-            const double di = D[kPanel * kDStride + t];
             for (int c1 = pw; c1 > 0; c1 -= 8) {
                 double dr[8];
 #pragma unroll
@@ -625,7 +631,7 @@ __device__ __forceinline__ void panel_solves(double* z, int nb, int bw, const do
                 for (int u = 0; u < 8; u++) {
                     const int c = c1 - 1 - u;
                     if (c >= 0) {
-                        const double yc = readlane_f64(v * di, c);
+                        const double yc = readlane_f64(v, c);
                         const double upd = v - dr[u] * yc;
                         v = (t == c) ? yc : ((t < c) ? upd : v);
                     }
@@ -681,8 +687,10 @@ __device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
     if (!narrow) stage_store(Dbuf[0], sv, sd);
     __syncthreads();
     if (narrow) {
-        window_solve<true>(z, nb, bw, Lc, dinv, Dbuf[0], Dbuf[1]);
-        window_solve<false>(z, nb, bw, Lr, dinv, Dbuf[0], Dbuf[1]);
+        window_solve<true>(z, nb, bw, Lc, Dbuf[0], Dbuf[1]);
+        for (int k = t; k < nb; k += kBT) z[k] = z[k] * dinv[k];    // D^-1
+        __syncthreads();
+        window_solve<false>(z, nb, bw, Lr, Dbuf[0], Dbuf[1]);
     } else {
         panel_solves(z, nb, bw, Lc, Lr, dinv, Dbuf, sv, lv, sd);
     }
@@ -1147,7 +1155,13 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
         const int nt = (int)std::max(1u, std::min<unsigned>(16u, std::min<unsigned>(
                                                (unsigned)K, std::thread::hardware_concurrency())));
         std::vector<std::thread> pool;
-        for (int i = 1; i < nt; i++) pool.emplace_back(worker);
+        for (int i = 1; i < nt; i++) {
+            try {
+                pool.emplace_back(worker);
+            } catch (const std::system_error&) {
+                break;     // fewer helper threads; the calling thread takes the rest
+            }
+        }
         worker();
         for (auto& th : pool) th.join();
         if (failed) fail(OBK_E_NOMEM, "host memory for the block factors");
@@ -1182,12 +1196,19 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
     for (int32_t b = 0; b < K; b++) {
         if (!P.h_bdirect[b]) continue;
         const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b], bw = P.h_bbw[b], W = bw + 1;
-        const std::vector<double>& L = fac[b];
+        // the unit lower factor U = L diag(1 / L[j][j]) (so that A_t A_t^T =
+        // U D U^T with D = diag(L[j][j]^2)) and D^-1
+        std::vector<double>& L = fac[b];
+        std::vector<double> piv((size_t)nb);
+        for (int64_t c = 0; c < nb; c++) piv[c] = L[(size_t)(c * W + bw)];
+        for (int64_t i = 0; i < nb; i++)
+            for (int64_t d = 1; d <= bw && d <= i; d++) L[(size_t)(i * W + bw - d)] /= piv[i - d];
+        for (int64_t i = 0; i < nb; i++) L[(size_t)(i * W + bw)] = 1.0;
         std::copy(L.begin(), L.end(), lr.begin() + off[b]);
         for (int64_t c = 0; c < nb; c++) {
             for (int64_t d = 0; d <= bw; d++)
                 lc[(size_t)(off[b] + c * W + d)] = c + d < nb ? L[(size_t)((c + d) * W + bw - d)] : 0.0;
-            dinv[(size_t)(P.h_bptr[b] + c)] = 1.0 / L[(size_t)(c * W + bw)];
+            dinv[(size_t)(P.h_bptr[b] + c)] = 1.0 / (piv[c] * piv[c]);
             hperm[(size_t)(P.h_bptr[b] + c)] = perms[b][c];
             hpos[(size_t)(P.h_bptr[b] + perms[b][c])] = (int32_t)c;
         }
