@@ -11,9 +11,17 @@
 //     workgroup forms the dot product of their column sums by looking up each
 //     column of one block in the sorted column list of the other; all other
 //     pairs share no column and their cosine is exactly 0;
-//   * the host forms |cos| and pairs the blocks.
+//   * the host forms |cos| and pairs the blocks;
+//   * (block_factor) for each block, the host puts its rows in the reverse
+//     Cuthill-McKee order of its Gram graph and forms the banded Cholesky
+//     factor of A_t A_t^T in the unit-diagonal form U D U^T, when the block
+//     has full row rank to the pivot test and a band within the limits.
 //
-// Sweeps (k_block_sweeps): one launch of G workgroups (cooperative for
+// Sweeps with factors (k_block_direct, or k_block_sweeps<1> when only some
+// blocks have one): a projection is r = f_t - A_t x~, U z = r, z *= D^-1,
+// U^T y = z, x~ += A_t^T y, by one workgroup (project_direct).
+//
+// Sweeps by CG (k_block_sweeps): one launch of G workgroups (cooperative for
 // G > 1) runs every projection of the call.  Projection onto block t (rows R, touched columns
 // S): res = f_R - A_R x~ (all-zero rows: 0), then conjugate gradients on
 // A_R A_R^T y = res in the form that moves x~ itself (x~ += alpha A_R^T d):
