@@ -129,6 +129,34 @@ def test_block_form_direct_at_block_size_1024():
     assert _rel(x, x_o) <= TOL_X and _rel(x, x_cg) <= TOL_X
 
 
+def test_block_form_mixed_direct_and_cg_blocks():
+    """Rows 3 and 7 made identical land in one of three blocks (RCM
+    positions 227 and 204 of 300): that block keeps CG, the other two are
+    projected from their factors in the same launch, and the iterate is the
+    oracle's."""
+    base = synth.c1(n=300, companion=True)
+    A = base.scipy().tolil()
+    A[7, :] = A[3, :]
+    A = A.tocsr()
+    A.sort_indices()
+    s = synth.from_scipy(A, base.x_star, name="dup-row")
+    k, sweeps = 3, 3
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, 0.02)
+    x_o = oracle.block_solve(bp, sweeps)
+    with obk.plan_system(s, 0.02, block_k=k) as P:
+        x, _ = P.solve(maxit=sweeps)
+        x2, _ = P.solve(maxit=sweeps)
+        b = P.blocks()
+        import torch
+        prof = P.sweep_profile(torch.zeros(s.n, dtype=torch.float64, device="cuda"), 1)
+    _say(f"[block] mixed: direct {b['direct'].tolist()}, CG iterations {b['cg_iters'].tolist()}, "
+         f"err {_rel(x, x_o):.3e}, kernel {prof[0]['name']}")
+    assert b["direct"].tolist() == [True, True, False]
+    assert b["cg_iters"][2] > 0 and b["cg_iters"][0] == 0 and b["cg_iters"][1] == 0
+    assert prof[0]["name"] == "k_block_sweeps"
+    assert _rel(x, x_o) <= TOL_X and np.array_equal(x, x2)
+
+
 def test_block_form_rank_deficient_block_keeps_cg():
     """A block with two identical rows has no Cholesky factor (the pivot
     test fails): it is projected by CG, and the least-norm projection is
