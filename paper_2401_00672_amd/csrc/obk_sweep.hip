@@ -94,19 +94,48 @@ __global__ void k_update_x(int64_t n, double sigma, const float* __restrict__ d,
 
 }  // namespace
 
+// The tiles [t0, t1) of a phase as a kernel argument list in workgroup order
+// (empty when the phase has more than kInlineTiles tiles and reads them from
+// the tile array).
+static TileList tile_list(const std::vector<Tile>& tiles, int32_t t0, int32_t t1, int32_t& inl) {
+    TileList tl;
+    std::memset(&tl, 0, sizeof(tl));
+    inl = (t1 - t0 <= kInlineTiles) ? 1 : 0;
+    if (inl)
+        for (int32_t b = 0; b < t1 - t0; b++) tl.t[b] = tiles[t0 + xcd_tile(b, t1 - t0)];
+    return tl;
+}
+
 template <class T>
 static void enqueue_sweeps_t(const obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval,
                              T* x, T* w, int64_t sweeps, hipStream_t s) {
+    const int32_t G = P.ngroups;
+    std::vector<TileList> rl(G), sl(G);
+    std::vector<int32_t> rin(G), sin(G);
+    for (int32_t g = 0; g < G; g++) {
+        rl[g] = tile_list(P.h_rtiles, P.h_rtile_ptr[g], P.h_rtile_ptr[g + 1], rin[g]);
+        sl[g] = tile_list(P.h_stiles, P.h_stile_ptr[g], P.h_stile_ptr[g + 1], sin[g]);
+    }
     for (int64_t it = 0; it < sweeps; it++) {
-        for (int32_t g = 0; g < P.ngroups; g++) {
+        for (int32_t g = 0; g < G; g++) {
             const int32_t r0 = P.h_rtile_ptr[g], r1 = P.h_rtile_ptr[g + 1];
             const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
-            if (r1 > r0)
-                k_phase_r<T><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, P.rptr.get(), P.rcol.get(), rval, rf,
-                                                     rinv, x, w);
-            if (s1 > s0)
-                k_phase_s<T><<<s1 - s0, kT, 0, s>>>(P.stiles.get() + s0, P.sptr.get(), P.srow.get(), sval,
-                                                     P.tcol.get(), w, x);
+            if (r1 > r0) {
+                if (rin[g])
+                    k_phase_r<T, true><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, rl[g], P.rptr.get(), P.rcol.get(),
+                                                               rval, rf, rinv, x, w);
+                else
+                    k_phase_r<T, false><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, rl[g], P.rptr.get(),
+                                                                P.rcol.get(), rval, rf, rinv, x, w);
+            }
+            if (s1 > s0) {
+                if (sin[g])
+                    k_phase_s<T, true><<<s1 - s0, kT, 0, s>>>(P.stiles.get() + s0, sl[g], P.sptr.get(), P.srow.get(),
+                                                               sval, P.tcol.get(), w, x);
+                else
+                    k_phase_s<T, false><<<s1 - s0, kT, 0, s>>>(P.stiles.get() + s0, sl[g], P.sptr.get(),
+                                                                P.srow.get(), sval, P.tcol.get(), w, x);
+            }
         }
     }
     OBK_HIP(hipGetLastError());
@@ -198,17 +227,21 @@ int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, 
             const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
             // the events ride on the kernel's own dispatch packet: they time the
             // kernel, not the packets around it
+            int32_t rin = 0, sin = 0;
+            const TileList rl = tile_list(P.h_rtiles, r0, r1, rin), sl = tile_list(P.h_stiles, s0, s1, sin);
             if (r1 > r0) {
-                hipExtLaunchKernelGGL(k_phase_r<double>, dim3(r1 - r0), dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
-                                      (const Tile*)(P.rtiles.get() + r0), (const int64_t*)P.rptr.get(),
+                hipExtLaunchKernelGGL(rin ? k_phase_r<double, true> : k_phase_r<double, false>, dim3(r1 - r0),
+                                      dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
+                                      (const Tile*)(P.rtiles.get() + r0), rl, (const int64_t*)P.rptr.get(),
                                       (const int32_t*)P.rcol.get(), (const double*)P.rval.get(),
                                       (const double*)P.rf.get(), (const double*)P.rinv.get(), (const double*)x,
                                       P.w.get());
                 k++, li++;
             }
             if (s1 > s0) {
-                hipExtLaunchKernelGGL(k_phase_s<double>, dim3(s1 - s0), dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
-                                      (const Tile*)(P.stiles.get() + s0), (const int64_t*)P.sptr.get(),
+                hipExtLaunchKernelGGL(sin ? k_phase_s<double, true> : k_phase_s<double, false>, dim3(s1 - s0),
+                                      dim3(kT), 0, s, ev[2 * k], ev[2 * k + 1], 0,
+                                      (const Tile*)(P.stiles.get() + s0), sl, (const int64_t*)P.sptr.get(),
                                       (const int32_t*)P.srow.get(), (const double*)P.sval.get(),
                                       (const int32_t*)P.tcol.get(), (const double*)P.w.get(), x);
                 k++, li++;

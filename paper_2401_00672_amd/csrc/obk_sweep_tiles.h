@@ -229,31 +229,44 @@ __device__ __forceinline__ void tile_resid(const Tile& t, int nchunks, double* p
 // (b -> XCD b % 8): XCD x takes one contiguous run of the tiles, so tiles
 // that share a window of x (or w) share that XCD's L2.  A bijection on
 // [0, n) for any n.
-__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
+__host__ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
     const int32_t q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
     return x * q + min(x, r) + j;
 }
 
+// A phase of at most kInlineTiles tiles carries its tile list in the kernel
+// arguments, already in the order of xcd_tile: workgroup b reads entry b at
+// kernel start together with the other arguments, one dependent load sooner
+// than through the tile array (whose index needs the grid size, itself an
+// argument), which shortens the latency-bound phases of small groups.
+constexpr int kInlineTiles = 32;
+struct TileList {
+    Tile t[kInlineTiles];
+};
+
 namespace {
 
 // Phase R / phase S kernels over the tiles of one group: one tile per
-// 256-thread workgroup.
-template <class T>
+// 256-thread workgroup, from tiles[] or, for kInl, from tl.
+// (kInl: the tile list is in the arguments; the two instances differ only in
+// where the tile is read, so neither carries the other's load.)
+template <class T, bool kInl>
 __global__ __launch_bounds__(kTileThreads) void k_phase_r(
-    const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
-    const T* __restrict__ rval, const T* __restrict__ rf, const T* __restrict__ rinv, const T* __restrict__ x,
-    T* __restrict__ w) {
+    const Tile* __restrict__ tiles, TileList tl, const int64_t* __restrict__ rptr,
+    const int32_t* __restrict__ rcol, const T* __restrict__ rval, const T* __restrict__ rf,
+    const T* __restrict__ rinv, const T* __restrict__ x, T* __restrict__ w) {
     __shared__ T prod[kTileEntries];
-    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const Tile t = kInl ? tl.t[blockIdx.x] : tiles[xcd_tile(blockIdx.x, gridDim.x)];
     tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
 }
 
-template <class T>
+template <class T, bool kInl>
 __global__ __launch_bounds__(kTileThreads) void k_phase_s(
-    const Tile* __restrict__ tiles, const int64_t* __restrict__ sptr, const int32_t* __restrict__ srow,
-    const T* __restrict__ sval, const int32_t* __restrict__ tcol, const T* __restrict__ w, T* __restrict__ x) {
+    const Tile* __restrict__ tiles, TileList tl, const int64_t* __restrict__ sptr,
+    const int32_t* __restrict__ srow, const T* __restrict__ sval, const int32_t* __restrict__ tcol,
+    const T* __restrict__ w, T* __restrict__ x) {
     __shared__ T prod[kTileEntries];
-    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const Tile t = kInl ? tl.t[blockIdx.x] : tiles[xcd_tile(blockIdx.x, gridDim.x)];
     tile_phase_s<T>(t, tile_chunks(t), prod, sptr, srow, sval, tcol, w, x);
 }
 
