@@ -508,8 +508,7 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
             // row 64 - bw steps later, so for bw <= 56 the lanes finished in
             // a group of 8 steps take their next rows together after it
             const bool grouped = bw <= kPanel - 8;
-            for (int s0 = 0; s0 < cw; s0 += 8) {
-                double lv[8];
+            auto load_group = [&](int s0, double (&lv)[8]) {
 #pragma unroll
                 for (int u = 0; u < 8; u++) {
                     const int st = s0 + u;
@@ -520,7 +519,12 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
                     const double x = B[ok ? kk * W + (kFwd ? d : bw - d) : 0];
                     lv[u] = ok ? x : 0.0;
                 }
-                // the unit diagonal: row k's value is final when it is broadcast
+            };
+            double lv[8], ln[8];
+            load_group(0, lv);
+            for (int s0 = 0; s0 < cw; s0 += 8) {
+                // the next group's band entries are read while this group's steps run
+                load_group(s0 + 8, ln);
                 auto step = [&](int u, bool replace) {
                     const int st = s0 + u;
                     const int k = cb + (kFwd ? st : cw - 1 - st);
@@ -540,6 +544,8 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
                     for (int u = 0; u < 8; u++)
                         if (u < cw - s0) step(u, true);
                 }
+#pragma unroll
+                for (int u = 0; u < 8; u++) lv[u] = ln[u];
             }
             if (my_s < cw) z[my_k] = fin;
         }
