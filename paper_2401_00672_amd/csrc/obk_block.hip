@@ -451,7 +451,7 @@ __device__ __forceinline__ void stage_store(double* D, const double (&v)[kStageP
 // rows at a time, into the LDS buffer wave 0 is not reading.
 template <bool kFwd>
 __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const double* __restrict__ Lf,
-                                             double* buf0, double* buf1) {
+                                             const double* __restrict__ dinv, double* buf0, double* buf1) {
     const int t = threadIdx.x, W = bw + 1;
     const int nch = (nb + kPanel - 1) / kPanel;
     // chunk ci covers rows [cb, ce): ascending chunks forward, descending backward
@@ -503,6 +503,9 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
             const int nxt = kFwd ? my_k + kPanel : my_k - kPanel;
             const double nv = z[(my_s < cw && nxt >= 0 && nxt < nb) ? nxt : 0];
             const double nval = (my_s < cw && nxt >= 0 && nxt < nb) ? nv : 0.0;
+            // forward: the finished value is stored already scaled by D^-1,
+            // the right-hand side of the backward solve
+            const double dk = kFwd ? dinv[(my_s < cw) ? my_k : 0] : 1.0;
             double fin = 0.0;
             // a lane that finishes a row gets its first update for the next
             // row 64 - bw steps later, so for bw <= 56 the lanes finished in
@@ -547,7 +550,7 @@ __device__ __forceinline__ void window_solve(double* z, int nb, int bw, const do
 #pragma unroll
                 for (int u = 0; u < 8; u++) lv[u] = ln[u];
             }
-            if (my_s < cw) z[my_k] = fin;
+            if (my_s < cw) z[my_k] = kFwd ? fin * dk : fin;
         }
         __syncthreads();
     }
@@ -701,10 +704,8 @@ __device__ void project_direct(const BlockArgs& a, int32_t b, double* dyn) {
     if (!narrow) stage_store(Dbuf[0], sv, sd);
     __syncthreads();
     if (narrow) {
-        window_solve<true>(z, nb, bw, Lc, Dbuf[0], Dbuf[1]);
-        for (int k = t; k < nb; k += kBT) z[k] = z[k] * dinv[k];    // D^-1
-        __syncthreads();
-        window_solve<false>(z, nb, bw, Lr, Dbuf[0], Dbuf[1]);
+        window_solve<true>(z, nb, bw, Lc, dinv, Dbuf[0], Dbuf[1]);     // stores D^-1 z
+        window_solve<false>(z, nb, bw, Lr, dinv, Dbuf[0], Dbuf[1]);
     } else {
         panel_solves(z, nb, bw, Lc, Lr, dinv, Dbuf, sv, lv, sd);
     }
