@@ -236,9 +236,9 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  * (two rows adjacent when they share a column), which keeps the band
  * narrow.  A block
  * whose pivots fall below 1e-8 of their diagonal (rank deficient to working
- * accuracy), whose band would exceed 2^26 entries, or with more than 8192
- * rows keeps CG, and so does every block of a launch over several
- * workgroups.  All-zero rows take no part (their y is 0).
+ * accuracy), whose band or whose count of row pairs sharing a column would
+ * exceed 2^24, or with more than 8192 rows keeps CG, and so does every block
+ * of a launch over several workgroups.  All-zero rows take no part (their y is 0).
  *
  * obk_plan_blocks (host outputs, each may be NULL): *k; bptr[k+1] the row
  * range of each block in reordered rows; partner[k] the block a block is

@@ -1080,6 +1080,16 @@ static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& 
         for (int64_t k = rp[r0 + i]; k < rp[r0 + i + 1]; k++) es.push_back({ci[k], (int32_t)i, va[k]});
     auto by_col = [](const Ent& x, const Ent& y) { return x.c != y.c ? x.c < y.c : x.i < y.i; };
     std::sort(es.begin(), es.end(), by_col);
+    // a column with c entries in the block gives c^2 row pairs: a block with
+    // dense columns keeps CG rather than building a large Gram graph
+    int64_t pairs = 0;
+    for (size_t a = 0; a < es.size();) {
+        size_t e = a;
+        while (e < es.size() && es[e].c == es[a].c) e++;
+        pairs += (int64_t)(e - a) * (int64_t)(e - a);
+        a = e;
+    }
+    if (pairs > kDirectMaxBand) return -1;
     // the Gram graph and its reverse Cuthill-McKee order
     std::vector<uint64_t> edges;
     for (size_t a = 0; a < es.size();) {

@@ -157,6 +157,28 @@ def test_block_form_mixed_direct_and_cg_blocks():
     assert _rel(x, x_o) <= TOL_X and np.array_equal(x, x2)
 
 
+def test_block_form_dense_column_keeps_cg():
+    """A single 4,200-row block whose first column is dense has 4,200^2 row
+    pairs sharing that column, over the 2^24 limit of the factor's Gram
+    graph: the block keeps CG, and one projection onto the whole consistent
+    system still lands on its minimum-norm solution."""
+    n = 4200
+    rng = np.random.default_rng(23)
+    A = sp.lil_matrix((n, n))
+    A.setdiag(rng.uniform(1, 2, n) + n ** 0.5)
+    A[0, :] = rng.standard_normal(n)
+    A[:, 0] = rng.standard_normal((n, 1))
+    A[0, 0] = n
+    s = synth.from_scipy(A.tocsr(), rng.standard_normal(n), name="arrow-4200")
+    with obk.plan_system(s, 0.02, block_k=1) as P:
+        x, info = P.solve(maxit=1)
+        b = P.blocks()
+    _say(f"[block] dense column: direct {b['direct'].tolist()}, CG iterations {b['cg_iters'].tolist()}, "
+         f"relres {info.relres:.3e}, |x - x*| / |x*| = {_rel(x, s.x_star):.3e}")
+    assert not b["direct"].any() and b["cg_iters"][0] > 0
+    assert info.relres <= 1e-11 and _rel(x, s.x_star) <= 1e-10
+
+
 def test_block_form_rank_deficient_block_keeps_cg():
     """A block with two identical rows has no Cholesky factor (the pivot
     test fails): it is projected by CG, and the least-norm projection is
