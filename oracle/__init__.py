@@ -78,6 +78,8 @@ def lib():
         L.orc_rowwise_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p]
         L.orc_relres_z.restype = _f64
         L.orc_relres_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_solve_tol.restype = ctypes.c_int
+        L.orc_solve_tol.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _f64, _i64, _i64, _p, _p]
         L.orc_refine.restype = _i64
         L.orc_refine.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64, _i64, _f64, _p]
         _lib = L
@@ -288,6 +290,35 @@ def solve_rect(pl: Plan, n: int, sweeps: int, x0: np.ndarray | None = None) -> n
     if x0 is not None:
         x0h[:n] = x0
     return solve(pl, sweeps, x0h)[:n]
+
+
+SOLVE_STATUS = {0: "converged", 1: "maxit", 2: "diverged", 3: "nonfinite"}
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    sweeps: int
+    checks: int
+    relres0: float
+    relres: float
+    status: str
+
+
+def solve_tol(pl: Plan, tol: float, maxit: int, check_every: int = 1,
+              x0t: np.ndarray | None = None) -> tuple[np.ndarray, SolveInfo]:
+    """O9: sweeps from x~0 (default 0, Section 3.5) until the relative residual
+    is <= tol, checked every `check_every` sweeps, or `maxit` sweeps are done;
+    DIVERGED when it exceeds 1e3 times its initial value, NONFINITE on NaN or
+    Inf.  tol <= 0 runs exactly maxit sweeps.  Reordered coordinates."""
+    x = np.zeros(pl.n) if x0t is None else np.array(x0t, dtype=np.float64, copy=True)
+    out = np.zeros(2, np.int64)
+    rho = np.zeros(2, np.float64)
+    st = lib().orc_solve_tol(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(pl.f), _ptr(pl.inv),
+                             _ptr(pl.group), pl.ngroups, _ptr(x), float(tol), int(maxit), int(check_every),
+                             _ptr(out), _ptr(rho))
+    if st < 0:
+        raise RuntimeError(f"orc_solve_tol failed: {st}")
+    return x, SolveInfo(int(out[0]), int(out[1]), float(rho[0]), float(rho[1]), SOLVE_STATUS[st])
 
 
 def refine(pl: Plan, inner: int, outer: int, tol: float, x0t: np.ndarray | None = None):

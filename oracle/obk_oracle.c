@@ -517,6 +517,81 @@ int64_t orc_refine(int64_t n, const int64_t *rp, const int32_t *ci, const double
     return steps;
 }
 
+/* --------------------------------------------------------------- O9 -----
+ * Solve to a tolerance (the stopping rule of Section 3.5, read as a relative
+ * residual): from x (x~0 on entry, the iterate on return)
+ *   rho0 = ||f - A x|| / ||f||;
+ *   NONFINITE if some residual entry or the sum of squares is not finite,
+ *   else CONVERGED at once if tol > 0 and rho0 <= tol;
+ *   while fewer than maxit sweeps are done and no outcome is set:
+ *     run c = min(check_every, maxit - done) sweeps (all maxit - done when
+ *     tol <= 0), then, if tol > 0, recompute rho:
+ *       NONFINITE as above, else CONVERGED if rho <= tol, else DIVERGED if
+ *       rho0 > 0 and rho > 1e3 rho0;
+ *   with tol <= 0, rho is computed once after the maxit sweeps.
+ * "Not finite" is read from the residual's sum of squares (a NaN or infinite
+ * entry makes it so).  Each norm is the sqrt of an ascending-index sum of
+ * squares; ||f|| = 0
+ * gives rho = 0 when ||r|| = 0 and +inf otherwise.  out[0] = sweeps done,
+ * out[1] = residual checks after sweeps; rho[0] = rho0, rho[1] = last rho.
+ * Returns the outcome (ORC_CONVERGED ... ORC_NONFINITE) or an error < 0.    */
+#define ORC_CONVERGED 0
+#define ORC_MAXIT 1
+#define ORC_DIVERGED 2
+#define ORC_NONFINITE 3
+
+static double relres_flag(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                          const double *f, const double *x, int *nonfinite)
+{
+    double rr = 0.0, ff = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
+        double ri = f[i] - s;
+        rr = rr + ri * ri;
+        ff = ff + f[i] * f[i];
+    }
+    /* a NaN or infinite residual entry makes the sum NaN or infinite */
+    *nonfinite = !isfinite(rr);
+    if (ff == 0.0) return rr == 0.0 ? 0.0 : INFINITY;
+    return sqrt(rr) / sqrt(ff);
+}
+
+int orc_solve_tol(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                  const double *f, const double *inv, const int32_t *group, int32_t ngroups,
+                  double *x, double tol, int64_t maxit, int64_t check_every, int64_t *out,
+                  double *rho)
+{
+    if (n < 0 || maxit < 0 || check_every < 1 || !out || !rho) return ORC_E_ARG;
+    int bad = 0;
+    double rho0 = relres_flag(n, rp, ci, v, f, x, &bad);
+    double cur = rho0;
+    int status = ORC_MAXIT;
+    int64_t done = 0, checks = 0;
+    if (bad) status = ORC_NONFINITE;
+    else if (tol > 0.0 && rho0 <= tol) status = ORC_CONVERGED;
+    while (done < maxit && status == ORC_MAXIT) {
+        int64_t c = maxit - done;
+        if (tol > 0.0 && check_every < c) c = check_every;
+        int rc = orc_sweep(n, rp, ci, v, f, inv, group, ngroups, x, c);
+        if (rc != ORC_OK) return rc;
+        done += c;
+        if (tol > 0.0) {
+            checks++;
+            cur = relres_flag(n, rp, ci, v, f, x, &bad);
+            if (bad) status = ORC_NONFINITE;
+            else if (cur <= tol) status = ORC_CONVERGED;
+            else if (rho0 > 0.0 && cur > 1e3 * rho0) status = ORC_DIVERGED;
+        }
+    }
+    if (tol <= 0.0) cur = relres_flag(n, rp, ci, v, f, x, &bad);
+    out[0] = done;
+    out[1] = checks;
+    rho[0] = rho0;
+    rho[1] = cur;
+    return status;
+}
+
 /* ------------------------------------------------------------- complex ----
  * The complex case: the paper solves the complex matrix kim1 with the same
  * algorithm (its discussion of Table 4).  Entries are held as separate real

@@ -400,15 +400,10 @@ void enqueue_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
         P.graphs.push_back(sg);
         return sg.exec;
     };
-    if (sweeps >= kChunkZ) {
-        hipGraphExec_t ex = graph_for(kChunkZ);
-        for (int64_t i = 0; i + kChunkZ <= sweeps; i += kChunkZ) OBK_HIP(hipGraphLaunch(ex, s));
-    }
-    const int64_t rest = sweeps % kChunkZ;
-    if (rest) {
-        hipGraphExec_t ex = graph_for(1);
-        for (int64_t i = 0; i < rest; i++) OBK_HIP(hipGraphLaunch(ex, s));
-    }
+    // both graphs are captured on the iterate's first use (see run_sweeps)
+    hipGraphExec_t chunk = graph_for(kChunkZ), one = graph_for(1);
+    for (int64_t i = 0; i + kChunkZ <= sweeps; i += kChunkZ) OBK_HIP(hipGraphLaunch(chunk, s));
+    for (int64_t i = 0; i < sweeps % kChunkZ; i++) OBK_HIP(hipGraphLaunch(one, s));
 }
 
 // Eager complex sweeps with an event pair on every kernel's dispatch packet;

@@ -174,15 +174,12 @@ template <class T>
 static void run_sweeps(obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval, T* x, T* w,
                        int64_t sweeps, hipStream_t s) {
     if (sweeps <= 0 || P.ngroups == 0) return;
-    if (sweeps >= kChunk) {
-        hipGraphExec_t ex = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, kChunk);
-        for (int64_t i = 0; i + kChunk <= sweeps; i += kChunk) OBK_HIP(hipGraphLaunch(ex, s));
-    }
-    const int64_t rest = sweeps % kChunk;
-    if (rest) {
-        hipGraphExec_t ex = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, 1);
-        for (int64_t i = 0; i < rest; i++) OBK_HIP(hipGraphLaunch(ex, s));
-    }
+    // both graphs of this iterate are captured on its first use, so no later
+    // call (whatever its sweep count) captures or instantiates on the host
+    hipGraphExec_t chunk = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, kChunk);
+    hipGraphExec_t one = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, 1);
+    for (int64_t i = 0; i + kChunk <= sweeps; i += kChunk) OBK_HIP(hipGraphLaunch(chunk, s));
+    for (int64_t i = 0; i < sweeps % kChunk; i++) OBK_HIP(hipGraphLaunch(one, s));
 }
 
 // enqueue `sweeps` sweeps on x (device, reordered coordinates)

@@ -6,6 +6,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# The mutation tests run the oracle pins against a planted-mistake copy of the
+# oracle package: OBK_ORACLE_PKG names the folder holding that copy.
+if os.environ.get("OBK_ORACLE_PKG"):
+    sys.path.insert(0, os.environ["OBK_ORACLE_PKG"])
 
 
 def pytest_configure(config):

@@ -15,6 +15,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "obk_oracle.c")
 
+# each pin run is single-threaded, so that parallel mutant runs do not
+# oversubscribe the cores with BLAS threads
+_ONE_THREAD = {"OMP_NUM_THREADS": "1", "OPENBLAS_NUM_THREADS": "1", "MKL_NUM_THREADS": "1"}
+
 # (name, exact text in the source, replacement)
 MUTANTS = [
     ("rcm_not_reversed", "p[t] = order[n - 1 - t];", "p[t] = order[t];"),
@@ -33,10 +37,17 @@ MUTANTS = [
      "                w[i]"),
     ("sweep_drops_update", "x[c] = x[c] + t[c];", "x[c] = t[c];"),
     ("sweep_sequential_within_group", "x[c] = x[c] + t[c];", "x[c] = x[c];"),
-    ("relres_no_sqrt", "return sqrt(rr) / sqrt(ff);", "return rr / ff;"),
+    ("relres_no_sqrt", "? 0.0 : -1.0;\n    return sqrt(rr) / sqrt(ff);", "? 0.0 : -1.0;\n    return rr / ff;"),
     ("unpermute_wrong_direction", "for (int64_t t = 0; t < n; t++) x[p[t]] = xt[t];",
      "for (int64_t t = 0; t < n; t++) x[t] = xt[p[t]];"),
     ("refine_unscaled", "x[i] = x[i] + sigma * d[i];", "x[i] = x[i] + d[i];"),
+    ("stop_ignores_check_every", "if (tol > 0.0 && check_every < c) c = check_every;",
+     "if (tol > 0.0 && 1 < c) c = 1;"),
+    ("stop_divergence_factor", "else if (rho0 > 0.0 && cur > 1e3 * rho0) status = ORC_DIVERGED;",
+     "else if (rho0 > 0.0 && cur > 1e2 * rho0) status = ORC_DIVERGED;"),
+    ("stop_misses_nonfinite", "*nonfinite = !isfinite(rr);", "*nonfinite = 0;"),
+    ("stop_squared_residual", "    if (ff == 0.0) return rr == 0.0 ? 0.0 : INFINITY;\n    return sqrt(rr) / sqrt(ff);",
+     "    if (ff == 0.0) return rr == 0.0 ? 0.0 : INFINITY;\n    return rr / ff;"),
     ("z_cosine_no_conjugate", "di = di + (vr[a] * vi[b] - vi[a] * vr[b]);",
      "di = di + (vr[a] * vi[b] + vi[a] * vr[b]);"),
     ("z_norm_real_part_only", "s = s + (vr[k] * vr[k] + vi[k] * vi[k]);", "s = s + vr[k] * vr[k];"),
@@ -80,8 +91,68 @@ def test_pins_catch_mutant(source, name, old, new, tmp_path):
     csrc.write_text(src)
     subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-shared", "-fPIC", "-o", str(so),
                     str(csrc), "-lm"], check=True)
-    env = dict(os.environ, OBK_ORACLE_LIB=str(so))
+    env = dict(os.environ, OBK_ORACLE_LIB=str(so), **_ONE_THREAD)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+# Mistakes planted in the Python half of the oracle (oracle/__init__.py: the
+# block form, its criteria and the non-square extension).
+PY_MUTANTS = [
+    ("centroid_of_abs_values", "cen[b] = np.asarray(A[bptr[b]:bptr[b + 1]].sum(axis=0))",
+     "cen[b] = np.asarray(abs(A[bptr[b]:bptr[b + 1]]).sum(axis=0))"),
+    ("centroid_is_first_row", "cen[b] = np.asarray(A[bptr[b]:bptr[b + 1]].sum(axis=0))",
+     "cen[b] = np.asarray(A[bptr[b]:bptr[b] + 1].sum(axis=0))"),
+    ("tau2_before_tau1", "            x = block_project(bp, t1, x)\n            x = block_project(bp, t2, x)",
+     "            x = block_project(bp, t2, x)\n            x = block_project(bp, t1, x)"),
+    ("nclass_before_pairs",
+     "        for t1, t2 in bp.pairs:\n            x = block_project(bp, t1, x)\n            x = block_project(bp, t2, x)\n"
+     "        for t in bp.nclass:\n            x = block_project(bp, t, x)",
+     "        for t in bp.nclass:\n            x = block_project(bp, t, x)\n"
+     "        for t1, t2 in bp.pairs:\n            x = block_project(bp, t1, x)\n            x = block_project(bp, t2, x)"),
+    ("block_projection_sign", "return x + np.linalg.pinv(A) @ (bp.f[r0:r1] - A @ x)",
+     "return x - np.linalg.pinv(A) @ (bp.f[r0:r1] - A @ x)"),
+    ("chunks_ceil", "size = m // k", "size = -(-m // k)"),
+    ("zn_counts_nonzeros", "return n1 / num, nz.size * nm / num", "return nz.size / num, nz.size * nm / num"),
+    ("nn_mean_only", "return n1 / num, nz.size * nm / num", "return n1 / num, nm / num"),
+    ("select_least_zn", "key = (-zn, nn, k)", "key = (zn, nn, k)"),
+    ("pad_rhs_ones", "f = np.concatenate([f, np.zeros(N - m)])", "f = np.concatenate([f, np.ones(N - m)])"),
+    ("stop_status_names_swapped", 'SOLVE_STATUS = {0: "converged", 1: "maxit", 2: "diverged", 3: "nonfinite"}',
+     'SOLVE_STATUS = {0: "converged", 1: "diverged", 2: "maxit", 3: "nonfinite"}'),
+]
+
+
+@pytest.fixture(scope="module")
+def py_source():
+    with open(os.path.join(ROOT, "oracle", "__init__.py")) as fh:
+        return fh.read()
+
+
+def _run_pins_on_copy(tmp_path, init_text):
+    import shutil
+    import oracle
+    oracle.lib()                        # builds liboracle.so if it is missing
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("build.py", "obk_oracle.c", "liboracle.so"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "__init__.py").write_text(init_text)
+    env = dict(os.environ, OBK_ORACLE_PKG=str(tmp_path), **_ONE_THREAD)
+    env.pop("OBK_ORACLE_LIB", None)
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          env=env, cwd=ROOT, capture_output=True, text=True, timeout=300)
+
+
+def test_python_mutant_harness_imports_the_copy(py_source, tmp_path):
+    """Control: the pins import the planted copy, not the package in the tree."""
+    r = _run_pins_on_copy(tmp_path, py_source + '\nraise ImportError("planted copy loaded")\n')
+    assert r.returncode != 0 and "planted copy loaded" in r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("name,old,new", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_pins_catch_python_mutant(py_source, name, old, new, tmp_path):
+    r = _run_pins_on_copy(tmp_path, _apply(py_source, old, new, name))
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

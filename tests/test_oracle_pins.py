@@ -466,6 +466,83 @@ def test_relres_against_scipy():
                                np.linalg.norm(r) / np.linalg.norm(s.f), rtol=1e-13)
 
 
+# ------------------------------------------------- O9: the stopping rule
+def _two_row_case():
+    """A = [[1, 1], [0, 1]], x* = (1, 1), f = (2, 1).  RCM reverses the two
+    vertices, so A~ = [[1, 0], [1, 1]], f~ = (1, 2), x~* = (1, 1); the rows'
+    cosine is 1/sqrt(2) >= 0.1, so each row is its own group, row (1, 0)
+    first.  Worked by hand from x~ = 0: the first projection sets x~_0 = 1,
+    the second moves x~ along (1, 1) onto x~_0 + x~_1 = 2, and after every
+    sweep the error lies along (1, -1) with the residual of row 0 equal to
+    -(x~_0 - 1) and that of row 1 zero.  Sweep 1 ends at (3/2, 1/2), sweep 2
+    at (5/4, 3/4): each sweep halves the error (alternating projections onto
+    two lines at 45 degrees, |cos|^2 = 1/2), so ||r_k|| = 2^-k exactly
+    (dyadic values) and relres_k = 2^-k / sqrt(5)."""
+    return synth.from_dense(np.array([[1.0, 1.0], [0.0, 1.0]]), f=np.array([2.0, 1.0]))
+
+
+def test_stop_rule_two_row_hand_case():
+    """Section 3.5's stopping rule read as relres <= tol: 2^-k / sqrt(5) <= 1e-10
+    first at k = 33 (2^-32 / sqrt(5) = 1.04e-10); checked every 5 sweeps it
+    stops at 35; with maxit = 20 it stops there, unconverged; tol <= 0 runs
+    exactly maxit sweeps."""
+    pl = oracle.plan_system(_two_row_case(), 0.1)
+    assert pl.p.tolist() == [1, 0] and pl.group.tolist() == [0, 1]
+    for every, k in ((1, 33), (5, 35)):
+        x, inf = oracle.solve_tol(pl, 1e-10, 100, every)
+        assert (inf.status, inf.sweeps, inf.checks) == ("converged", k, k // every)
+        assert inf.relres0 == 1.0
+        assert inf.relres == pytest.approx(2.0 ** -k / np.sqrt(5.0), rel=1e-14)
+        assert np.array_equal(x, np.array([1.0 + 2.0 ** -k, 1.0 - 2.0 ** -k]))
+    x, inf = oracle.solve_tol(pl, 1e-10, 20, 1)
+    assert (inf.status, inf.sweeps) == ("maxit", 20)
+    assert inf.relres == pytest.approx(2.0 ** -20 / np.sqrt(5.0), rel=1e-14)
+    x, inf = oracle.solve_tol(pl, 0.0, 7, 3)
+    assert (inf.status, inf.sweeps, inf.checks) == ("maxit", 7, 0)
+    assert inf.relres == pytest.approx(2.0 ** -7 / np.sqrt(5.0), rel=1e-14)
+
+
+def test_stop_rule_divergence_and_nonfinite_hand_case():
+    """Three identical rows (1, 1, 1), f = (3, 3, 3), delta = 2: no pair
+    reaches |cos| = 1 >= 2, so one group projects all three rows from the
+    same iterate.  With s = sum x, each w_i = (3 - s) / 3 and x_c grows by
+    3 w, so s becomes 9 - 2 s: s = 0, 9, -9, 27, ... and every residual entry
+    is 3 (-2)^k, relres_k = 2^k.  The rule declares divergence at the first
+    check with relres > 1e3: sweep 10 (1024) when checked every sweep, sweep 12
+    (4096) when checked every 4.  Checked only after 1100 sweeps, the values
+    have overflowed (3 * 2^1100 > DBL_MAX): NONFINITE.  A NaN start is
+    NONFINITE before any sweep."""
+    s = synth.from_dense(np.ones((3, 3)), f=np.full(3, 3.0))
+    pl = oracle.plan_system(s, 2.0)
+    assert pl.ngroups == 1
+    for every, k in ((1, 10), (4, 12)):
+        _, inf = oracle.solve_tol(pl, 1e-10, 100, every)
+        assert (inf.status, inf.sweeps, inf.relres) == ("diverged", k, 2.0 ** k)
+    _, inf = oracle.solve_tol(pl, 1e-10, 2000, 1100)
+    assert (inf.status, inf.sweeps, inf.checks) == ("nonfinite", 1100, 1)
+    x0 = np.array([0.0, np.nan, 0.0])
+    _, inf = oracle.solve_tol(pl, 1e-10, 50, 1, x0t=x0)
+    assert (inf.status, inf.sweeps) == ("nonfinite", 0)
+
+
+def test_stop_rule_residual_against_scipy():
+    """The relative residual the rule reports equals ||f - A x|| / ||f|| formed
+    by scipy in original coordinates from the returned iterate, and the
+    iterate of a tol <= 0 run is the plain K-sweep iterate."""
+    s = synth.c1(n=800, companion=True)
+    pl = oracle.plan_system(s, 0.1)
+    xt, inf = oracle.solve_tol(pl, 1e-6, 500, 3)
+    assert inf.status == "converged" and inf.sweeps % 3 == 0
+    x = oracle.unpermute(pl.p, xt)
+    ref = np.linalg.norm(s.f - s.scipy() @ x) / np.linalg.norm(s.f)
+    assert inf.relres == pytest.approx(ref, rel=1e-12)
+    assert ref <= 1e-6
+    _, prev = oracle.solve_tol(pl, 0.0, inf.sweeps - 3, 1)
+    assert prev.relres > 1e-6          # not converged at the previous check
+    xk, _ = oracle.solve_tol(pl, 0.0, 17, 1)
+    assert np.array_equal(xk, oracle.sweep(pl, np.zeros(s.n), 17))
+
+
 def test_refinement_reaches_tolerance():
     """Iterative refinement around the sweep reaches relative residual 1e-10."""
     s = synth.c1(companion=True)
@@ -606,6 +683,60 @@ def test_block_pair_rule_hand_cases():
     se = synth.from_dense(E, np.ones(8))
     be = oracle.block_plan(se.n, se.row_ptr, se.col, se.val, se.f, 4, 0.1)
     assert be.pairs == [] and be.nclass == [0, 1, 2, 3]
+
+
+def _tridiag_blocks(n=40, k=5):
+    T = sp.diags([np.full(n - 1, -1.0), np.full(n, 4.0), np.full(n - 1, -1.0)], [-1, 0, 1]).tocsr()
+    return synth.from_scipy(T, np.linspace(-1.0, 1.0, n)), k
+
+
+def test_block_centroid_cosines_hand_worked():
+    """Centroid cosines of Section 3.3 (Algorithm 4, step 3) on tridiag(-1, 4, -1)
+    with n = 40 cut into k = 5 blocks of s = 8 rows.  RCM reverses the path,
+    which leaves this matrix unchanged.  The row sum of an inner block is -1
+    at the column before the block, 3 at its first and last columns, 2 at the
+    s - 2 columns between and -1 at the column after: squared norm
+    1 + 9 + 4 (s - 2) + 9 + 1 = 4 s + 12 = 44; the first and last blocks lack
+    one outer -1: 4 s + 11 = 43.  Neighbouring sums overlap at two columns
+    with products 3 (-1) each: G = -6 (-6 / s^2 for the mean rows; the scale
+    cancels).  Blocks two apart share no column.  Hence |cos| = 6 / sqrt(43 * 44)
+    for the pairs (0, 1) and (3, 4), 6 / 44 = 3 / 22 for (1, 2) and (2, 3),
+    0 beyond, 1 on the diagonal."""
+    s, k = _tridiag_blocks()
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, 0.1)
+    want = np.eye(k)
+    edge, inner = 6.0 / np.sqrt(43.0 * 44.0), 3.0 / 22.0
+    for a, b, c in ((0, 1, edge), (1, 2, inner), (2, 3, inner), (3, 4, edge)):
+        want[a, b] = want[b, a] = c
+    assert np.abs(bp.cos - want).max() <= 1e-15
+    # pair rule on these values: at thr = 0.1 the neighbours (|cos| ~ 0.14)
+    # conflict, so 0 pairs with 2 and 1 with 3; at thr = 0.2 neighbours pair
+    assert bp.pairs == [(0, 2), (1, 3)] and bp.nclass == [4]
+    bp2 = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, 0.2)
+    assert bp2.pairs == [(0, 1), (2, 3)] and bp2.nclass == [4]
+
+
+def test_block_sweep_order_is_pairs_then_nclass():
+    """Algorithm 4's order: each pair's tau1 then tau2 (in the order the pairs
+    were formed), then the Nclass blocks.  The blocks of the thr = 0.2 plan
+    overlap their neighbours, so the projections do not commute and the order
+    shows; the expected iterate is formed with dense numpy pseudo-inverses
+    in that order."""
+    s, k = _tridiag_blocks()
+    bp = oracle.block_plan(s.n, s.row_ptr, s.col, s.val, s.f, k, 0.2)
+    A = sp.csr_matrix((bp.v, bp.ci, bp.rp), shape=(s.n, s.n)).toarray()
+    x = np.random.default_rng(9).standard_normal(s.n)
+    want = x.copy()
+    for t in (0, 1, 2, 3, 4):
+        r0, r1 = bp.bptr[t], bp.bptr[t + 1]
+        want = want + np.linalg.pinv(A[r0:r1]) @ (bp.f[r0:r1] - A[r0:r1] @ want)
+    got = oracle.block_sweep(bp, x, 1)
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    other = x.copy()
+    for t in (4, 1, 0, 3, 2):                        # a different order lands elsewhere
+        r0, r1 = bp.bptr[t], bp.bptr[t + 1]
+        other = other + np.linalg.pinv(A[r0:r1]) @ (bp.f[r0:r1] - A[r0:r1] @ other)
+    assert np.linalg.norm(other - want) > 1e-6 * np.linalg.norm(want)
 
 
 def test_orthogonal_pair_equals_joint_projection():
