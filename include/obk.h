@@ -125,6 +125,39 @@ typedef struct {
                                 a pivot test, band within limits) are projected exactly
                                 from it in one-workgroup launches, the others by CG;
                                 1: CG for every block.  A plan-time option. */
+    int sweep_kernel;        /* FP64 sweeps of real one-row-block plans: 0 (default): the
+                                banded engine when the reordered band is narrow enough for
+                                every slab's windows to fit in LDS, else the per-group phase
+                                kernels; 1: the per-group phase kernels; 2: the banded
+                                engine, OBK_E_ARG when it does not apply.  Both give the
+                                same iterate bit for bit.  A plan-time option. */
+    double omega;            /* relaxation of every row step: w_i = omega (f_i - a_i x) /
+                                ||a_i||^2 (eq. 1.2 scaled); default 1.0, the paper's step
+                                (bit for bit: multiplying by 1.0 is exact); must lie in
+                                (0, 2).  Not in the block form.  A plan-time option (kept
+                                by obk_plan_set_opts). */
+    int max_group;           /* 0 (default): maximal groups (first fit, the hot path);
+                                2: the paper's literal class rule of Section 3.3 -- each
+                                row pairs with the first later unpaired row it is
+                                near-orthogonal to, the two projected one after the other
+                                (Algorithm 4, the tau1 and tau2 steps), unpaired rows
+                                (Nclass) one by one after all pairs.  This is the block form
+                                with k = n one-row blocks, so it needs n <= 4096 and
+                                OBK_FP64; other values: OBK_E_ARG.  A plan-time option. */
+    int deterministic;       /* 1 (default) or 0.  Every kernel of the library reduces in
+                                a fixed order (no floating-point atomics), so results are
+                                repeatable bit for bit either way; 0 is accepted and runs
+                                the same kernels. */
+    void *(*alloc)(size_t bytes, void *ctx);   /* device memory for the plan and the
+                                temporaries of planning and solving (NULL: the HIP runtime,
+                                stream-ordered during planning).  alloc returns NULL on
+                                failure (then OBK_E_NOMEM); alloc and dealloc are both set
+                                or both NULL.  A block returned by alloc goes back through
+                                dealloc once no queued work uses it (temporaries after a
+                                synchronisation of the call's stream, plan memory in
+                                obk_free). */
+    void (*dealloc)(void *ptr, void *ctx);
+    void *ctx;               /* passed to alloc and dealloc */
 } obk_opts;
 
 typedef struct {
@@ -207,6 +240,11 @@ OBK_API obk_status obk_plan_perm(obk_plan_t plan, int32_t *p_host);
 OBK_API obk_status obk_plan_groups(obk_plan_t plan, int32_t *group_of_row_host, int32_t *n_groups);
 /* Device bytes owned by the plan (for admission against an HBM budget). */
 OBK_API obk_status obk_plan_bytes(obk_plan_t plan, size_t *device_bytes);
+/* Which kernels run the plan's FP64 sweeps (opts.sweep_kernel): *engine = 2
+ * for the banded engine, with *slabs its workgroups (each owning a
+ * contiguous range of the reordered unknowns), or 1 for the per-group phase
+ * kernels (*slabs = 0).  Either output may be NULL. */
+OBK_API obk_status obk_plan_engine(obk_plan_t plan, int32_t *engine, int32_t *slabs);
 /* Sizes: n, nnz, number of groups, bandwidth of A~, number of conflicting pairs. */
 OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int32_t *n_groups,
                           int64_t *bandwidth, int64_t *n_conflicts);
@@ -237,8 +275,12 @@ OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int
  * narrow.  A block
  * whose pivots fall below 1e-8 of their diagonal (rank deficient to working
  * accuracy), whose band or whose count of row pairs sharing a column would
- * exceed 2^24, or with more than 8192 rows keeps CG, and so does every block
- * of a launch over several workgroups.  All-zero rows take no part (their y is 0).
+ * exceed 2^24, or with more than 8192 rows keeps CG, and so do the blocks
+ * past the plan-wide limits (2^27 band entries and 2^36 factorisation steps
+ * of rows x band^2, applied in block order before any block is factored)
+ * and every block of a launch over several workgroups (factors are built
+ * only when the plan's launch is one workgroup).  All-zero rows take no part
+ * (their y is 0).
  *
  * obk_plan_blocks (host outputs, each may be NULL): *k; bptr[k+1] the row
  * range of each block in reordered rows; partner[k] the block a block is
@@ -432,6 +474,27 @@ OBK_API obk_status obk_batch_tune(const obk_plan_t *plans, int count, obk_batch_
  * Errors: OBK_E_ARG for NULL pointers or negative n.
  */
 OBK_API obk_status obk_rcm_host(int64_t n, const int64_t *gptr, const int32_t *gadj, int32_t *perm);
+/*
+ * obk_banded_emulate_host: the banded engine's plan-time layout for exactly
+ * `slabs` slabs and its sweep, run on the host (no device): for the
+ * reordered system rp[n+1], col, val (rows sorted by column), f~, inv =
+ * 1/||a_i||^2, group[n] (-1: a row in no group) and ngroups, `sweeps`
+ * sweeps of eq. 3.3 (groups in ascending order, all rows of a group from the
+ * same iterate, each row step relaxed by omega as in obk_opts) update x
+ * (reordered coordinates, n entries) in place.  Each
+ * slab owns a contiguous range of the unknowns; a slab's rows, and the rows
+ * touching its window columns, must lie within its neighbours' ranges.
+ * stats (may be NULL, 4 entries): the slab count (0 when that count does not
+ * apply; then OBK_E_ARG), the (slab, group, phase) pieces whose data the
+ * layout keeps in LDS for a whole launch and those it streams every sweep,
+ * and the LDS bytes per workgroup (a budget of 159 KiB is assumed).  The
+ * iterate equals the device engine's and the group-phase kernels' bit for
+ * bit.
+ */
+OBK_API obk_status obk_banded_emulate_host(int64_t n, const int64_t *rp, const int32_t *col, const double *val,
+                                           const double *f, const double *inv, const int32_t *group,
+                                           int32_t ngroups, int32_t slabs, int64_t sweeps, double omega,
+                                           double *x, int64_t *stats);
 OBK_API obk_status obk_first_fit_host(int64_t n, const int64_t *cptr, const int32_t *cidx,
                                       const uint8_t *active, int32_t *group, int32_t *n_groups);
 

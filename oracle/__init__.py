@@ -57,7 +57,7 @@ def lib():
         L.orc_pairs.restype = ctypes.c_int
         L.orc_pairs.argtypes = [_i64, _p, _p, _p, _p, _f64, _p]
         L.orc_sweep.restype = ctypes.c_int
-        L.orc_sweep.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64]
+        L.orc_sweep.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _f64, _p, _i64]
         L.orc_rowwise.restype = None
         L.orc_rowwise.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i64, _p]
         L.orc_relres.restype = _f64
@@ -73,15 +73,25 @@ def lib():
         L.orc_conflicts_z.restype = _i64
         L.orc_conflicts_z.argtypes = [_i64, _p, _p, _p, _p, _p, _f64, _p, _p]
         L.orc_sweep_z.restype = ctypes.c_int
-        L.orc_sweep_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _p, _p, _i64]
+        L.orc_sweep_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _f64, _p, _p, _i64]
         L.orc_rowwise_z.restype = None
         L.orc_rowwise_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p]
         L.orc_relres_z.restype = _f64
         L.orc_relres_z.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_mt_prepare.restype = _p
+        L.orc_mt_prepare.argtypes = [_i64, _p, _p, _p, _p, _i32]
+        L.orc_mt_sweep.restype = ctypes.c_int
+        L.orc_mt_sweep.argtypes = [_p, _p, _p, _p, _p, _p, _f64, _p, _i64]
+        L.orc_mt_free.restype = None
+        L.orc_mt_free.argtypes = [_p]
         L.orc_solve_tol.restype = ctypes.c_int
-        L.orc_solve_tol.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _f64, _i64, _i64, _p, _p]
+        L.orc_solve_tol.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _f64, _p, _f64, _i64, _i64, _p, _p]
         L.orc_refine.restype = _i64
-        L.orc_refine.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _p, _i64, _i64, _f64, _p]
+        L.orc_refine.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _i32, _f64, _p, _i64, _i64, _f64, _p]
         _lib = L
     return _lib
 
@@ -190,9 +200,10 @@ class Plan:
     cidx: np.ndarray
     group: np.ndarray      # group of each reordered row (-1: zero row)
     ngroups: int
+    omega: float = 1.0     # relaxation of every row step (the paper's step: 1)
 
 
-def plan(n, rp, ci, v, f, delta, *, use_rcm: bool = True) -> Plan:
+def plan(n, rp, ci, v, f, delta, *, use_rcm: bool = True, omega: float = 1.0) -> Plan:
     """Algorithm 4, first four steps, with one-row blocks: RCM, reorder,
     norms, cosine conflicts, grouping."""
     if validate(n, rp, ci, v, f) != 0:
@@ -202,7 +213,7 @@ def plan(n, rp, ci, v, f, delta, *, use_rcm: bool = True) -> Plan:
     nu, inv = norms(n, trp, tv)
     cptr, cidx = conflicts(n, trp, tci, tv, nu, delta)
     g, ng = groups(n, nu, cptr, cidx)
-    return Plan(n, p, trp, tci, tv, tf, nu, inv, cptr, cidx, g, ng)
+    return Plan(n, p, trp, tci, tv, tf, nu, inv, cptr, cidx, g, ng, float(omega))
 
 
 def plan_system(s, delta, **kw) -> Plan:
@@ -214,10 +225,51 @@ def sweep(pl: Plan, xt: np.ndarray, sweeps: int, f: np.ndarray | None = None) ->
     x = np.array(xt, dtype=np.float64, copy=True)
     ff = pl.f if f is None else _c(f, np.float64)
     rc = lib().orc_sweep(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(ff), _ptr(pl.inv),
-                         _ptr(pl.group), pl.ngroups, _ptr(x), int(sweeps))
+                         _ptr(pl.group), pl.ngroups, pl.omega, _ptr(x), int(sweeps))
     if rc != 0:
         raise RuntimeError(f"orc_sweep failed: {rc}")
     return x
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's row-parallel loops (conflicts, ThreadedSweep)."""
+    lib().orc_set_threads(int(t))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+class ThreadedSweep:
+    """O8 on several threads: phase (i) over the rows of a group, phase (ii)
+    over its touched columns, each column's sum in ascending row order --
+    the same operations as `sweep`, so the iterate is the same bit for bit
+    (checked by the CPU tests).  Used for timing on all cores and for the
+    full-size checks."""
+
+    def __init__(self, pl: Plan):
+        self.pl = pl
+        self._h = lib().orc_mt_prepare(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(pl.group), pl.ngroups)
+        if not self._h:
+            raise MemoryError("orc_mt_prepare failed")
+
+    def sweep(self, x: np.ndarray, sweeps: int, f: np.ndarray | None = None) -> np.ndarray:
+        """`sweeps` sweeps in place on x (float64, contiguous); returns x."""
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+        ff = self.pl.f if f is None else _c(f, np.float64)
+        rc = lib().orc_mt_sweep(self._h, _ptr(self.pl.rp), _ptr(self.pl.ci), _ptr(self.pl.v), _ptr(ff),
+                                _ptr(self.pl.inv), self.pl.omega, _ptr(x), int(sweeps))
+        if rc != 0:
+            raise RuntimeError(f"orc_mt_sweep failed: {rc}")
+        return x
+
+    def close(self) -> None:
+        if self._h:
+            lib().orc_mt_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def rowwise(n, rp, ci, v, f, inv, rows, x):
@@ -314,8 +366,8 @@ def solve_tol(pl: Plan, tol: float, maxit: int, check_every: int = 1,
     out = np.zeros(2, np.int64)
     rho = np.zeros(2, np.float64)
     st = lib().orc_solve_tol(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(pl.f), _ptr(pl.inv),
-                             _ptr(pl.group), pl.ngroups, _ptr(x), float(tol), int(maxit), int(check_every),
-                             _ptr(out), _ptr(rho))
+                             _ptr(pl.group), pl.ngroups, pl.omega, _ptr(x), float(tol), int(maxit),
+                             int(check_every), _ptr(out), _ptr(rho))
     if st < 0:
         raise RuntimeError(f"orc_solve_tol failed: {st}")
     return x, SolveInfo(int(out[0]), int(out[1]), float(rho[0]), float(rho[1]), SOLVE_STATUS[st])
@@ -326,7 +378,7 @@ def refine(pl: Plan, inner: int, outer: int, tol: float, x0t: np.ndarray | None 
     x = np.zeros(pl.n) if x0t is None else np.array(x0t, dtype=np.float64, copy=True)
     rho = ctypes.c_double(0.0)
     steps = lib().orc_refine(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.v), _ptr(pl.f), _ptr(pl.inv),
-                             _ptr(pl.group), pl.ngroups, _ptr(x), int(inner), int(outer), float(tol),
+                             _ptr(pl.group), pl.ngroups, pl.omega, _ptr(x), int(inner), int(outer), float(tol),
                              ctypes.byref(rho))
     return x, int(steps), float(rho.value)
 
@@ -481,6 +533,7 @@ class ComplexPlan:
     inv: np.ndarray
     group: np.ndarray
     ngroups: int
+    omega: float = 1.0
 
 
 def norms_complex(n, rp, vr, vi):
@@ -496,7 +549,7 @@ def cosine_complex(i, j, rp, ci, vr, vi, nu) -> float:
     return float(lib().orc_cosine_z(int(i), int(j), _ptr(rp), _ptr(ci), _ptr(vr), _ptr(vi), _ptr(nu)))
 
 
-def plan_complex(n, rp, ci, vz, fz, delta, *, use_rcm: bool = True) -> ComplexPlan:
+def plan_complex(n, rp, ci, vz, fz, delta, *, use_rcm: bool = True, omega: float = 1.0) -> ComplexPlan:
     """Algorithm 4, first four steps, over C: RCM on the pattern (as for real
     systems), the same symmetric permutation of the real and imaginary parts,
     complex norms and cosines, first-fit grouping."""
@@ -517,7 +570,7 @@ def plan_complex(n, rp, ci, vz, fz, delta, *, use_rcm: bool = True) -> ComplexPl
     lib().orc_conflicts_z(n, _ptr(trp), _ptr(tci), _ptr(tvr), _ptr(tvi), _ptr(nu), float(delta), _ptr(cptr),
                           _ptr(cidx))
     group, ng = groups(n, nu, cptr, cidx[:total])
-    return ComplexPlan(n, p, trp, tci, tvr, tvi, tfr, tfi, nu, inv, group, ng)
+    return ComplexPlan(n, p, trp, tci, tvr, tvi, tfr, tfi, nu, inv, group, ng, float(omega))
 
 
 def sweep_complex(pl: ComplexPlan, xt: np.ndarray, sweeps: int) -> np.ndarray:
@@ -525,7 +578,7 @@ def sweep_complex(pl: ComplexPlan, xt: np.ndarray, sweeps: int) -> np.ndarray:
     xr = np.array(np.real(xt), dtype=np.float64, copy=True)
     xi = np.array(np.imag(xt), dtype=np.float64, copy=True)
     rc = lib().orc_sweep_z(pl.n, _ptr(pl.rp), _ptr(pl.ci), _ptr(pl.vr), _ptr(pl.vi), _ptr(pl.fr), _ptr(pl.fi),
-                           _ptr(pl.inv), _ptr(pl.group), pl.ngroups, _ptr(xr), _ptr(xi), int(sweeps))
+                           _ptr(pl.inv), _ptr(pl.group), pl.ngroups, pl.omega, _ptr(xr), _ptr(xi), int(sweeps))
     if rc != 0:
         raise RuntimeError(f"orc_sweep_z failed: {rc}")
     return xr + 1j * xi

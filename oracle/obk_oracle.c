@@ -33,8 +33,31 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the row-parallel loops (conflicts, the threaded sweep); 1
+ * without OpenMP.  Only the CPU timing baseline changes it.                 */
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define ORC_OK 0
 #define ORC_E_ARG (-1)
@@ -273,6 +296,37 @@ static int cmp_i32(const void *x, const void *y)
     return (a > b) - (a < b);
 }
 
+/* The conflicts of one row i: the rows j < i sharing a column with it, in
+ * ascending order, whose cosine reaches delta.  Writes them to out (may be
+ * NULL) and returns their count.  mark[] / cand[] are scratch of n entries
+ * (mark[j] != i on entry for every j).                                      */
+static int64_t row_conflicts(int64_t i, const int64_t *rp, const int32_t *ci, const double *v,
+                             const double *nu, double delta, const int64_t *cp, const int32_t *cr,
+                             int64_t *mark, int32_t *cand, int32_t *out)
+{
+    int64_t ncand = 0, cnt = 0;
+    if (nu[i] == 0.0) return 0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+        int32_t c = ci[k];
+        for (int64_t t = cp[c]; t < cp[c + 1]; t++) {
+            int32_t j = cr[t];
+            if (j < i && mark[j] != i) { mark[j] = i; cand[ncand++] = j; }
+        }
+    }
+    qsort(cand, (size_t)ncand, sizeof(int32_t), cmp_i32);
+    for (int64_t t = 0; t < ncand; t++) {
+        int32_t j = cand[t];
+        if (nu[j] == 0.0) continue;
+        if (orc_cosine(i, j, rp, ci, v, nu) >= delta) {
+            if (out) out[cnt] = j;
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
+/* Rows are independent, so the count and fill passes may run on several
+ * threads (OpenMP when built with it); each row's list is the same.          */
 int64_t orc_conflicts(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                       const double *nu, double delta, int64_t *cptr, int32_t *cidx)
 {
@@ -281,44 +335,42 @@ int64_t orc_conflicts(int64_t n, const int64_t *rp, const int32_t *ci, const dou
     int64_t *cp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     int32_t *cr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
     int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
-    int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
-    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    if (!cp || !cr || !fill || !mark || !cand) {
-        free(cp); free(cr); free(fill); free(mark); free(cand); return ORC_E_NOMEM;
-    }
+    if (!cp || !cr || !fill) { free(cp); free(cr); free(fill); return ORC_E_NOMEM; }
     for (int64_t k = 0; k < nnz; k++) cp[ci[k] + 1]++;
     for (int64_t c = 0; c < n; c++) cp[c + 1] += cp[c];
     for (int64_t c = 0; c < n; c++) fill[c] = cp[c];
     for (int64_t i = 0; i < n; i++)
         for (int64_t k = rp[i]; k < rp[i + 1]; k++) cr[fill[ci[k]]++] = (int32_t)i;
-    for (int64_t j = 0; j < n; j++) mark[j] = -1;
 
-    int64_t total = 0;
-    cptr[0] = 0;
-    for (int64_t i = 0; i < n; i++) {
-        int64_t ncand = 0;
-        if (nu[i] != 0.0) {
-            for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
-                int32_t c = ci[k];
-                for (int64_t t = cp[c]; t < cp[c + 1]; t++) {
-                    int32_t j = cr[t];
-                    if (j < i && mark[j] != i) { mark[j] = i; cand[ncand++] = j; }
+    /* counts per row (cptr[i + 1]), then offsets; with cidx, the lists */
+    int failed = 0;
+    for (int pass = 0; pass < (cidx ? 2 : 1); pass++) {
+        #pragma omp parallel
+        {
+            int64_t *mark = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+            int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+            if (!mark || !cand) {
+                #pragma omp atomic write
+                failed = 1;
+            } else {
+                for (int64_t j = 0; j < n; j++) mark[j] = -1;
+                #pragma omp for schedule(dynamic, 1024)
+                for (int64_t i = 0; i < n; i++) {
+                    if (pass == 0) cptr[i + 1] = row_conflicts(i, rp, ci, v, nu, delta, cp, cr, mark, cand, NULL);
+                    else (void)row_conflicts(i, rp, ci, v, nu, delta, cp, cr, mark, cand, cidx + cptr[i]);
                 }
             }
+            free(mark);
+            free(cand);
         }
-        qsort(cand, (size_t)ncand, sizeof(int32_t), cmp_i32);
-        for (int64_t t = 0; t < ncand; t++) {
-            int32_t j = cand[t];
-            if (nu[j] == 0.0) continue;
-            if (orc_cosine(i, j, rp, ci, v, nu) >= delta) {
-                if (cidx) cidx[total] = j;
-                total++;
-            }
+        if (failed) break;
+        if (pass == 0) {
+            cptr[0] = 0;
+            for (int64_t i = 0; i < n; i++) cptr[i + 1] += cptr[i];
         }
-        cptr[i + 1] = total;
     }
-    free(cp); free(cr); free(fill); free(mark); free(cand);
-    return total;
+    free(cp); free(cr); free(fill);
+    return failed ? ORC_E_NOMEM : cptr[n];
 }
 
 /* ---------------------------------------------------------------- O7 ----
@@ -374,16 +426,18 @@ int orc_pairs(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
  * One OBK sweep (eq. 3.3 with one-row blocks; eq. 1.2 per row).
  * For g = 0 .. ngroups-1:
  *   (i)  for every row i of group g, from the same iterate x:
- *          s = sum_k a_ik x_k (ascending k);  w_i = (f_i - s) * inv_i
+ *          s = sum_k a_ik x_k (ascending k);  w_i = ((f_i - s) * inv_i) * omega
  *   (ii) for every column c touched by group g:
  *          t = sum over rows i of group g holding c, ascending i, of w_i a_ic;
  *          x_c = x_c + t
  * For exactly orthogonal rows this is the pseudo-inverse projection of eq.
  * (1.3); for near-orthogonal rows it defines the step.  `sweeps` sweeps run.
- * T = double (FP64).                                                         */
+ * omega is a relaxation of every row step; the paper's step is omega = 1
+ * (multiplying by 1.0 is exact, so that case is the unrelaxed step bit for
+ * bit).  T = double (FP64).                                                  */
 int orc_sweep(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
               const double *f, const double *inv, const int32_t *group, int32_t ngroups,
-              double *x, int64_t sweeps)
+              double omega, double *x, int64_t sweeps)
 {
     /* rows of each group in ascending order */
     int64_t *gp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
@@ -409,7 +463,7 @@ int orc_sweep(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                 int32_t i = gr[a];
                 double s = 0.0;
                 for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
-                w[i] = (f[i] - s) * inv[i];
+                w[i] = ((f[i] - s) * inv[i]) * omega;
             }
             /* (ii) per touched column, the sum over the group's rows in
              * ascending row order, then one update of x_c */
@@ -430,6 +484,130 @@ int orc_sweep(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
         }
     }
     free(gp); free(gr); free(fill); free(w); free(t); free(touched); free(tlist);
+    return ORC_OK;
+}
+
+/* The same sweep on several threads (OpenMP), for the CPU timing baseline
+ * and the full-size checks: phase (i) over the rows of a group, phase (ii)
+ * over the columns it touches, each column summing its group's entries in
+ * ascending row order before the one update of x_c -- the arithmetic of
+ * orc_sweep, operation for operation, so the iterates are equal bit for bit.
+ * orc_mt_prepare lays out, per group, the touched columns and their entries
+ * (row, value) by ascending row; orc_mt_sweep runs sweeps; orc_mt_free.    */
+typedef struct {
+    int64_t n;
+    int32_t ngroups;
+    int64_t *gp;       /* rows of group g: gr[gp[g] .. gp[g+1]) */
+    int32_t *gr;
+    int64_t *tp;       /* touched columns of group g: tc[tp[g] .. tp[g+1]) */
+    int32_t *tc;
+    int64_t *ep;       /* entries of touched column t: [ep[t], ep[t+1]) */
+    int32_t *er;       /* row of each entry */
+    double *ev;        /* value of each entry */
+    double *w;
+} orc_mt;
+
+void orc_mt_free(orc_mt *h)
+{
+    if (!h) return;
+    free(h->gp); free(h->gr); free(h->tp); free(h->tc); free(h->ep); free(h->er); free(h->ev); free(h->w);
+    free(h);
+}
+
+orc_mt *orc_mt_prepare(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                       const int32_t *group, int32_t ngroups)
+{
+    orc_mt *h = (orc_mt *)calloc(1, sizeof(orc_mt));
+    if (!h) return NULL;
+    int64_t nnz = rp[n];
+    h->n = n;
+    h->ngroups = ngroups;
+    h->gp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
+    h->gr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    h->tp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
+    h->tc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    h->ep = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz + 2));
+    h->er = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    h->ev = (double *)malloc(sizeof(double) * (size_t)(nnz + 1));
+    h->w = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *slot = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!h->gp || !h->gr || !h->tp || !h->tc || !h->ep || !h->er || !h->ev || !h->w || !cnt || !slot) {
+        free(cnt); free(slot); orc_mt_free(h); return NULL;
+    }
+    for (int64_t i = 0; i < n; i++) if (group[i] >= 0) h->gp[group[i] + 1]++;
+    for (int32_t g = 0; g < ngroups; g++) h->gp[g + 1] += h->gp[g];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ngroups + 1));
+        if (!fill) { free(cnt); free(slot); orc_mt_free(h); return NULL; }
+        for (int32_t g = 0; g < ngroups; g++) fill[g] = h->gp[g];
+        for (int64_t i = 0; i < n; i++) if (group[i] >= 0) h->gr[fill[group[i]]++] = (int32_t)i;
+        free(fill);
+    }
+    /* per group: entries counted per column, touched columns ascending,
+     * then filled by ascending row */
+    int64_t nt = 0, ne = 0;
+    for (int32_t g = 0; g < ngroups; g++) {
+        h->tp[g] = nt;
+        for (int64_t a = h->gp[g]; a < h->gp[g + 1]; a++) {
+            int32_t i = h->gr[a];
+            for (int64_t k = rp[i]; k < rp[i + 1]; k++) cnt[ci[k]]++;
+        }
+        int64_t t0 = nt;
+        for (int64_t a = h->gp[g]; a < h->gp[g + 1]; a++) {
+            int32_t i = h->gr[a];
+            for (int64_t k = rp[i]; k < rp[i + 1]; k++)
+                if (cnt[ci[k]] > 0 && slot[ci[k]] != -1 - (int64_t)g) {
+                    slot[ci[k]] = -1 - (int64_t)g;
+                    h->tc[nt++] = ci[k];
+                }
+        }
+        qsort(h->tc + t0, (size_t)(nt - t0), sizeof(int32_t), cmp_i32);
+        for (int64_t t = t0; t < nt; t++) {
+            int32_t c = h->tc[t];
+            h->ep[t] = ne;
+            slot[c] = ne;
+            ne += cnt[c];
+            cnt[c] = 0;
+        }
+        for (int64_t a = h->gp[g]; a < h->gp[g + 1]; a++) {
+            int32_t i = h->gr[a];
+            for (int64_t k = rp[i]; k < rp[i + 1]; k++) {
+                int64_t e = slot[ci[k]]++;
+                h->er[e] = i;
+                h->ev[e] = v[k];
+            }
+        }
+        for (int64_t t = t0; t < nt; t++) slot[h->tc[t]] = 0;
+    }
+    h->tp[ngroups] = nt;
+    h->ep[nt] = ne;
+    free(cnt); free(slot);
+    return h;
+}
+
+int orc_mt_sweep(const orc_mt *h, const int64_t *rp, const int32_t *ci, const double *v,
+                 const double *f, const double *inv, double omega, double *x, int64_t sweeps)
+{
+    if (!h) return ORC_E_ARG;
+    double *w = h->w;
+    for (int64_t it = 0; it < sweeps; it++) {
+        for (int32_t g = 0; g < h->ngroups; g++) {
+            #pragma omp parallel for schedule(static)
+            for (int64_t a = h->gp[g]; a < h->gp[g + 1]; a++) {
+                int32_t i = h->gr[a];
+                double s = 0.0;
+                for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];
+                w[i] = ((f[i] - s) * inv[i]) * omega;
+            }
+            #pragma omp parallel for schedule(static)
+            for (int64_t t = h->tp[g]; t < h->tp[g + 1]; t++) {
+                double tt = 0.0;
+                for (int64_t e = h->ep[t]; e < h->ep[t + 1]; e++) tt = tt + w[h->er[e]] * h->ev[e];
+                x[h->tc[t]] = x[h->tc[t]] + tt;
+            }
+        }
+    }
     return ORC_OK;
 }
 
@@ -495,7 +673,7 @@ void orc_permute_vec(int64_t n, const int32_t *p, const double *x, double *xt)
  * Returns the number of outer steps taken; *relres gets the last residual.  */
 int64_t orc_refine(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                    const double *f, const double *inv, const int32_t *group, int32_t ngroups,
-                   double *x, int64_t inner, int64_t outer, double tol, double *relres)
+                   double omega, double *x, int64_t inner, int64_t outer, double tol, double *relres)
 {
     double *r = (double *)malloc(sizeof(double) * (size_t)(n + 1));
     double *d = (double *)malloc(sizeof(double) * (size_t)(n + 1));
@@ -507,7 +685,7 @@ int64_t orc_refine(int64_t n, const int64_t *rp, const int32_t *ci, const double
         for (int64_t i = 0; i < n; i++) if (fabs(r[i]) > sigma) sigma = fabs(r[i]);
         if (sigma == 0.0) break;
         for (int64_t i = 0; i < n; i++) { r[i] = r[i] / sigma; d[i] = 0.0; }
-        orc_sweep(n, rp, ci, v, r, inv, group, ngroups, d, inner);
+        orc_sweep(n, rp, ci, v, r, inv, group, ngroups, omega, d, inner);
         for (int64_t i = 0; i < n; i++) x[i] = x[i] + sigma * d[i];
         steps++;
         rho = orc_relres(n, rp, ci, v, f, x, r);
@@ -559,7 +737,7 @@ static double relres_flag(int64_t n, const int64_t *rp, const int32_t *ci, const
 
 int orc_solve_tol(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
                   const double *f, const double *inv, const int32_t *group, int32_t ngroups,
-                  double *x, double tol, int64_t maxit, int64_t check_every, int64_t *out,
+                  double omega, double *x, double tol, int64_t maxit, int64_t check_every, int64_t *out,
                   double *rho)
 {
     if (n < 0 || maxit < 0 || check_every < 1 || !out || !rho) return ORC_E_ARG;
@@ -573,7 +751,7 @@ int orc_solve_tol(int64_t n, const int64_t *rp, const int32_t *ci, const double 
     while (done < maxit && status == ORC_MAXIT) {
         int64_t c = maxit - done;
         if (tol > 0.0 && check_every < c) c = check_every;
-        int rc = orc_sweep(n, rp, ci, v, f, inv, group, ngroups, x, c);
+        int rc = orc_sweep(n, rp, ci, v, f, inv, group, ngroups, omega, x, c);
         if (rc != ORC_OK) return rc;
         done += c;
         if (tol > 0.0) {
@@ -688,7 +866,7 @@ int64_t orc_conflicts_z(int64_t n, const int64_t *rp, const int32_t *ci, const d
 
 int orc_sweep_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *vr, const double *vi,
                 const double *fr, const double *fi, const double *inv, const int32_t *group, int32_t ngroups,
-                double *xr, double *xi, int64_t sweeps)
+                double omega, double *xr, double *xi, int64_t sweeps)
 {
     int64_t *gp = (int64_t *)calloc((size_t)ngroups + 1, sizeof(int64_t));
     int32_t *gr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
@@ -717,8 +895,8 @@ int orc_sweep_z(int64_t n, const int64_t *rp, const int32_t *ci, const double *v
                     sr = sr + (vr[k] * xr[c] - vi[k] * xi[c]);
                     si = si + (vr[k] * xi[c] + vi[k] * xr[c]);
                 }
-                wr[i] = (fr[i] - sr) * inv[i];
-                wi[i] = (fi[i] - si) * inv[i];
+                wr[i] = ((fr[i] - sr) * inv[i]) * omega;
+                wi[i] = ((fi[i] - si) * inv[i]) * omega;
             }
             int64_t nt = 0;
             for (int64_t a = gp[g]; a < gp[g + 1]; a++) {

@@ -44,7 +44,15 @@ class _Opts(ctypes.Structure):
     _fields_ = [("use_rcm", ctypes.c_int), ("precision", ctypes.c_int), ("inner_sweeps", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("reject_inconsistent", ctypes.c_int),
                 ("hbm_budget", ctypes.c_size_t), ("block_k", ctypes.c_int), ("block_wgs", ctypes.c_int),
-                ("block_maxit", ctypes.c_int), ("block_tol", ctypes.c_double), ("block_solver", ctypes.c_int)]
+                ("block_maxit", ctypes.c_int), ("block_tol", ctypes.c_double), ("block_solver", ctypes.c_int),
+                ("sweep_kernel", ctypes.c_int), ("omega", ctypes.c_double), ("max_group", ctypes.c_int),
+                ("deterministic", ctypes.c_int), ("alloc", ctypes.c_void_p), ("dealloc", ctypes.c_void_p),
+                ("ctx", ctypes.c_void_p)]
+
+
+# obk_opts.alloc / dealloc: the caller's device allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class _BatchOpts(ctypes.Structure):
@@ -84,6 +92,9 @@ def lib() -> ctypes.CDLL:
                                "python paper_2401_00672_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         L.obk_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+        L.obk_plan_engine.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.obk_banded_emulate_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int64, ctypes.c_double, _P, _P]
         L.obk_plan.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
                                ctypes.POINTER(_P)]
         L.obk_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.POINTER(_Info), _P]
@@ -305,6 +316,13 @@ class Plan:
         _check(lib().obk_plan_bytes(self.handle, ctypes.byref(b)))
         return int(b.value)
 
+    def engine(self) -> dict:
+        """obk_plan_engine: which kernels run the FP64 sweeps ("banded" with its
+        slab count, or "phases")."""
+        e, sl = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().obk_plan_engine(self.handle, ctypes.byref(e), ctypes.byref(sl)))
+        return {"engine": "banded" if e.value == 2 else "phases", "slabs": sl.value}
+
     def stats(self) -> dict:
         n, nnz, bw, nc = (ctypes.c_int64() for _ in range(4))
         ng = ctypes.c_int32()
@@ -324,12 +342,15 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
          use_rcm: bool = True, rcm_engine: str = "auto", precision: int = FP64, inner_sweeps: int = 8,
          check_every: int = 1, reject_inconsistent: bool = False, hbm_budget: int = 0, block_k: int = 0,
          block_wgs: int = 0, block_maxit: int = 0, block_tol: float = 1e-14, block_solver: str = "direct",
-         stream=None, _complex: bool = False) -> Plan:
+         sweep_kernel: str = "auto", omega: float = 1.0, max_group: int = 0, deterministic: bool = True,
+         allocator=None, stream=None, _complex: bool = False) -> Plan:
     """obk_plan on a CSR system: numpy arrays (host) or torch CUDA tensors (device).
     block_k > 0 selects the block form of Algorithm 4 (k uniform blocks, exact
     block projections); delta is then the centroid cosine threshold.
     rcm_engine ("auto", "device" or "host") picks how the reverse Cuthill-McKee
-    order is formed; the order is the same."""
+    order is formed; the order is the same.  allocator: an object with
+    alloc(nbytes) -> device pointer (int, 0 on failure) and dealloc(ptr), used
+    for the plan's device memory (obk_opts.alloc / dealloc)."""
     on_device = _is_torch(row_ptr)
     if on_device:
         nrows = int(row_ptr.numel()) - 1 if n is None else int(n)
@@ -369,14 +390,29 @@ def plan(row_ptr, col, val, f, delta: float, *, n: int | None = None, n_cols: in
     if block_solver not in solvers:
         raise ValueError(f"block_solver must be one of {sorted(solvers)}")
     opts.block_solver = solvers[block_solver]
+    kernels = {"auto": 0, "phases": 1, "banded": 2}
+    if sweep_kernel not in kernels:
+        raise ValueError(f"sweep_kernel must be one of {sorted(kernels)}")
+    opts.sweep_kernel = kernels[sweep_kernel]
+    opts.omega = float(omega)
+    opts.max_group = int(max_group)
+    opts.deterministic = 1 if deterministic else 0
+    callbacks = None
+    if allocator is not None:
+        callbacks = (ALLOC_FN(lambda nbytes, ctx: allocator.alloc(int(nbytes)) or None),
+                     DEALLOC_FN(lambda ptr, ctx: allocator.dealloc(ptr)))
+        opts.alloc = ctypes.cast(callbacks[0], ctypes.c_void_p)
+        opts.dealloc = ctypes.cast(callbacks[1], ctypes.c_void_p)
     h = _P()
     entry = lib().obk_plan_complex if _complex else lib().obk_plan
     _check(entry(ctypes.byref(csr), ptrs[3], float(delta), ctypes.byref(opts), st, ctypes.byref(h)))
     del keep
-    return Plan(h.value, ncols, nnz, on_device,
+    plan_obj = Plan(h.value, ncols, nnz, on_device,
                 {"precision": int(precision), "inner_sweeps": int(inner_sweeps), "check_every": int(check_every),
                  "block_wgs": int(block_wgs), "block_maxit": int(block_maxit), "block_tol": float(block_tol)},
                 n_ext=max(nrows, ncols), cplx=bool(_complex))
+    plan_obj._callbacks = callbacks     # the allocator callbacks live as long as the plan
+    return plan_obj
 
 
 def select_block_k(s, thr: float, candidates, stream=None):
@@ -436,6 +472,21 @@ def rcm_host(gptr, gadj) -> np.ndarray:
     _check(lib().obk_rcm_host(n, gptr.ctypes.data, gadj.ctypes.data if gadj.size else None,
                               perm.ctypes.data if n else None))
     return perm
+
+
+def banded_emulate_host(rp, ci, v, f, inv, group, ngroups: int, slabs: int, sweeps: int, x,
+                        omega: float = 1.0) -> tuple[np.ndarray, dict]:
+    """obk_banded_emulate_host: the banded engine's layout for `slabs` slabs and
+    its sweeps run on the host; returns (x after the sweeps, layout stats)."""
+    rp, ci, v = _host(rp, np.int64), _host(ci, np.int32), _host(v, np.float64)
+    f, inv, group = _host(f, np.float64), _host(inv, np.float64), _host(group, np.int32)
+    xo = np.array(x, dtype=np.float64, copy=True)
+    st = np.zeros(4, np.int64)
+    n = len(rp) - 1
+    _check(lib().obk_banded_emulate_host(n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, f.ctypes.data,
+                                         inv.ctypes.data, group.ctypes.data, int(ngroups), int(slabs), int(sweeps),
+                                         float(omega), xo.ctypes.data, st.ctypes.data))
+    return xo, {"slabs": int(st[0]), "cached": int(st[1]), "streamed": int(st[2]), "lds_bytes": int(st[3])}
 
 
 def first_fit_host(cptr, cidx, active):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libobk.so")
 SOURCES = ["obk_api.cpp", "obk_host.cpp", "obk_sort.hip", "obk_plan.hip", "obk_sweep.hip", "obk_batch.hip",
-           "obk_block.hip", "obk_complex.hip", "obk_rcm.hip"]
+           "obk_block.hip", "obk_complex.hip", "obk_rcm.hip", "obk_slab.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

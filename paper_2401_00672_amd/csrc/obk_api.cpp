@@ -46,7 +46,9 @@ size_t obk_plan_s::device_bytes() const {
            d_border.bytes() + bres.bytes() + bp.bytes() + bu.bytes() + bpart.bytes() + bbar.bytes() + berr.bytes() +
            biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes() +
            d_bdirect.bytes() + d_bbw.bytes() + d_boff.bytes() + lfc.bytes() + lfr.bytes() + ldinv.bytes() +
-           d_lperm.bytes() + d_lpos.bytes();
+           d_lperm.bytes() + d_lpos.bytes() + sl_desc.bytes() + sl_grp.bytes() + sl_round.bytes() +
+           sl_tgt.bytes() + sl_len.bytes() + sl_idx.bytes() + sl_f.bytes() + sl_inv.bytes() + sl_val.bytes() +
+           sl_xbuf.bytes() + sl_flags.bytes() + sl_err.bytes();
 }
 
 namespace {
@@ -92,6 +94,18 @@ void check_block_opts(const obk_opts& o) {
     if (o.block_wgs < 0 || o.block_maxit < 0) obk::fail(OBK_E_ARG, "block_wgs and block_maxit must be >= 0");
     if (!(o.block_tol >= 0.0) || !std::isfinite(o.block_tol)) obk::fail(OBK_E_ARG, "block_tol must be finite and >= 0");
     if (o.block_solver != 0 && o.block_solver != 1) obk::fail(OBK_E_ARG, "block_solver must be 0 or 1");
+    if (o.sweep_kernel < 0 || o.sweep_kernel > 2) obk::fail(OBK_E_ARG, "sweep_kernel must be 0, 1 or 2");
+}
+
+// the fields every entry point that takes an obk_opts checks the same way
+void check_common_opts(const obk_opts& o) {
+    if (!(o.omega > 0.0 && o.omega < 2.0)) obk::fail(OBK_E_ARG, "omega must lie in (0, 2)");
+    if (o.max_group != 0 && o.max_group != 2) obk::fail(OBK_E_ARG, "max_group must be 0 or 2");
+    if (o.deterministic != 0 && o.deterministic != 1) obk::fail(OBK_E_ARG, "deterministic must be 0 or 1");
+    if ((o.alloc == nullptr) != (o.dealloc == nullptr))
+        obk::fail(OBK_E_ARG, "alloc and dealloc must both be set or both be NULL");
+    if (o.block_k > 0 && o.omega != 1.0) obk::fail(OBK_E_ARG, "the block form takes no relaxation (omega = 1)");
+    if (o.block_k > 0 && o.sweep_kernel == 2) obk::fail(OBK_E_ARG, "the banded engine runs one-row-block plans only");
 }
 
 // RAII marker for the one-solve-at-a-time rule
@@ -121,6 +135,13 @@ obk_status obk_opts_default(obk_opts* opts) {
     opts->block_maxit = 0;
     opts->block_tol = 1e-14;
     opts->block_solver = 0;
+    opts->sweep_kernel = 0;
+    opts->omega = 1.0;
+    opts->max_group = 0;
+    opts->deterministic = 1;
+    opts->alloc = nullptr;
+    opts->dealloc = nullptr;
+    opts->ctx = nullptr;
     return OBK_OK;
 }
 
@@ -156,13 +177,23 @@ static obk_status plan_impl(const obk_csr* A, const double* f, double delta, con
         if (o.precision != OBK_FP64 && o.precision != OBK_FP32_IR) obk::fail(OBK_E_ARG, "unknown precision");
         if (o.inner_sweeps < 1 || o.check_every < 1) obk::fail(OBK_E_ARG, "inner_sweeps and check_every must be >= 1");
         if (o.use_rcm < 0 || o.use_rcm > 3) obk::fail(OBK_E_ARG, "use_rcm must be 0, 1, 2 or 3");
+        if (o.max_group == 2) {
+            // the paper's pair rule: the block form with one-row blocks
+            const int64_t N = std::max(A->n_rows, A->n_cols);
+            if (o.block_k != 0) obk::fail(OBK_E_ARG, "max_group = 2 is the block form with k = n; leave block_k 0");
+            if (N > 4096 || N < 1) obk::fail(OBK_E_ARG, "max_group = 2 needs 1 <= n <= 4096 (k = n blocks)");
+            o.block_k = (int)N;
+        }
         check_block_opts(o);
+        check_common_opts(o);
         if (o.block_k > std::max(A->n_rows, A->n_cols)) obk::fail(OBK_E_ARG, "block_k exceeds the number of rows");
         if (cplx && o.precision != OBK_FP64) obk::fail(OBK_E_ARG, "complex systems run in OBK_FP64 only");
         if (cplx && o.block_k > 0) obk::fail(OBK_E_ARG, "the block form takes real systems only");
+        if (cplx && o.sweep_kernel == 2) obk::fail(OBK_E_ARG, "the banded engine runs real systems only");
         P = new obk_plan_s();
         P->opts = o;
         P->cplx = cplx;
+        obk::UserAllocScope ua(o.alloc, o.dealloc, o.ctx, as_hip(stream));
         obk::build_plan(*P, *A, f, delta, as_hip(stream));
     });
     if (st != OBK_OK) {
@@ -184,6 +215,7 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
         if (maxit < 0 || std::isnan(tol)) obk::fail(OBK_E_ARG, "maxit must be >= 0 and tol a number");
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
+        obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, as_hip(stream));
         if (plan->cplx)
             obk::solve_complex(*plan, x0, tol, maxit, x, info, as_hip(stream));
         else if (plan->opts.precision == OBK_FP32_IR)
@@ -211,6 +243,7 @@ obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts* opts) {
         plan->opts.block_wgs = opts->block_wgs;
         plan->opts.block_maxit = opts->block_maxit;
         plan->opts.block_tol = opts->block_tol;
+        obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, nullptr);
         if (plan->has_fp32()) obk::ensure_fp32(*plan, nullptr);
     });
 }
@@ -219,7 +252,9 @@ obk_status obk_sweep_device(obk_plan_t plan, double* x_tilde_dev, int64_t sweeps
     return guarded([&] {
         if (!plan || !x_tilde_dev) obk::fail(OBK_E_ARG, "plan and x_tilde_dev must not be NULL");
         if (sweeps < 0) obk::fail(OBK_E_ARG, "sweeps must be >= 0");
+        BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
+        obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, as_hip(stream));
         if (plan->cplx) obk::enqueue_sweeps_z(*plan, x_tilde_dev, sweeps, as_hip(stream));
         else obk::enqueue_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream));
     });
@@ -233,6 +268,7 @@ obk_status obk_sweep_profile(obk_plan_t plan, double* x_tilde_dev, int64_t sweep
         if (max_out < 1) obk::fail(OBK_E_ARG, "max_out must be >= 1");
         OBK_HIP(hipSetDevice(plan->device));
         BusyGuard busy(plan);
+        obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, as_hip(stream));
         *n_out = plan->cplx ? obk::profile_sweeps_z(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out)
                             : obk::profile_sweeps(*plan, x_tilde_dev, sweeps, as_hip(stream), out, max_out);
     });
@@ -402,6 +438,14 @@ obk_status obk_plan_stats(obk_plan_t plan, int64_t* n, int64_t* nnz, int32_t* n_
         if (n_groups) *n_groups = plan->ngroups;
         if (bandwidth) *bandwidth = plan->bandwidth;
         if (n_conflicts) *n_conflicts = plan->nconflicts;
+    });
+}
+
+obk_status obk_plan_engine(obk_plan_t plan, int32_t* engine, int32_t* slabs) {
+    return guarded([&] {
+        if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
+        if (engine) *engine = plan->slab_S > 0 ? 2 : 1;
+        if (slabs) *slabs = plan->slab_S;
     });
 }
 

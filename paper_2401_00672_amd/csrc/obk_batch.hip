@@ -63,6 +63,7 @@ template <class T> struct BatchSys {
     int32_t ngroups;
     int32_t team;
     uint32_t* bar;           // [0] arrivals, [1] generation
+    T omega;                 // relaxation of the row steps
 };
 
 struct TeamTask {
@@ -89,9 +90,14 @@ struct ResSys {              // FP64 arrays for residual, scaling and update
     double fnorm2, zero_f2, zero_fmax;
 };
 
-__device__ __forceinline__ void team_barrier(uint32_t* bar, int team, int* err) {
+// Barrier of a system's team; false (for every thread of the workgroup) when
+// the wait timed out, after which the launch is abandoned: the workgroup
+// leaves, its teammates time out in turn, and the host reports the error flag.
+__device__ __forceinline__ bool team_barrier(uint32_t* bar, int team, int* err) {
+    __shared__ int timed_out;
     __syncthreads();
     if (team > 1) {
+        if (threadIdx.x == 0) timed_out = 0;
         if (threadIdx.x == 0) {
             const uint32_t gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t arrived =
@@ -109,12 +115,17 @@ __device__ __forceinline__ void team_barrier(uint32_t* bar, int team, int* err) 
                     cur = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     spins++;
                 } while ((cur == gen) & (spins <= kSpinLimit));
-                if (cur == gen) atomicOr(err, 1);
+                if (cur == gen) {
+                    atomicOr(err, 1);
+                    timed_out = 1;
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
+        return timed_out == 0;
     }
+    return true;
 }
 
 // Tiles of one phase handled by team member `rank`: r0 + rank + j * team for
@@ -144,7 +155,7 @@ __device__ __forceinline__ void team_phase(const BatchSys<T>& S, int32_t g, int3
         int nchunks = 0;
         for (int b = 0; b < SUB; b++) nchunks = max(nchunks, chunks[b]);
         if (kR)
-            tile_phase_r<T, kBatchQ, E>(mt, nchunks, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w);
+            tile_phase_r<T, kBatchQ, E>(mt, nchunks, prod, S.rptr, S.rcol, S.rval, S.rf, S.rinv, S.x, S.w, S.omega);
         else
             tile_phase_s<T, kBatchQ, E>(mt, nchunks, prod, S.sptr, S.srow, S.sval, S.tcol, S.w, S.x);
     }
@@ -168,9 +179,9 @@ __global__ __launch_bounds__(kTileThreads * SUB) void k_batch_sweeps(const Batch
         for (int sw = 0; sw < sweeps; sw++) {
             for (int32_t g = 0; g < S.ngroups; g++) {
                 team_phase<T, SUB, true>(S, g, tk.rank, prod);
-                team_barrier(S.bar, S.team, err);
+                if (!team_barrier(S.bar, S.team, err)) return;
                 team_phase<T, SUB, false>(S, g, tk.rank, prod);
-                team_barrier(S.bar, S.team, err);
+                if (!team_barrier(S.bar, S.team, err)) return;
             }
         }
     }
@@ -293,12 +304,12 @@ template <class T> BatchSys<T> sys_view(obk_plan_s& P, const TileView& tv, uint3
 template <> BatchSys<float> sys_view<float>(obk_plan_s& P, const TileView& tv, uint32_t* bar, int team) {
     return BatchSys<float>{tv.rt, tv.st, tv.rp, tv.sp, P.rptr.get(), P.rcol.get(), P.rval32.get(), P.b32.get(),
                            P.rinv32.get(), P.sptr.get(), P.srow.get(), P.sval32.get(), P.tcol.get(), P.d32.get(),
-                           P.w32.get(), P.ngroups, team, bar};
+                           P.w32.get(), P.ngroups, team, bar, (float)P.opts.omega};
 }
 template <> BatchSys<double> sys_view<double>(obk_plan_s& P, const TileView& tv, uint32_t* bar, int team) {
     return BatchSys<double>{tv.rt, tv.st, tv.rp, tv.sp, P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(),
                             P.rinv.get(), P.sptr.get(), P.srow.get(), P.sval.get(), P.tcol.get(), P.x.get(),
-                            P.w.get(), P.ngroups, team, bar};
+                            P.w.get(), P.ngroups, team, bar, P.opts.omega};
 }
 
 // Join consecutive tiles of one group while the result keeps at most

@@ -1067,14 +1067,23 @@ void block_setup(obk_plan_s& P, hipStream_t s) {
 constexpr int64_t kDirectMaxRows = 8192;
 constexpr int64_t kDirectMaxBand = int64_t(1) << 24;     // band entries per block
 constexpr int64_t kDirectMaxTotal = int64_t(1) << 27;    // band entries per plan
+constexpr int64_t kDirectMaxWork = int64_t(1) << 36;     // factorisation work (rows x band^2) per plan
 constexpr double kPivotTol = 1e-8;
 
-static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
-                            const std::vector<double>& va, const std::vector<double>& rinv,
-                            std::vector<double>& L, std::vector<int32_t>& perm) {
+// A block's entries (column, row within the block, value), sorted by
+// (column, row) in the block's factor order once block_order has run.
+struct FactorEnt { int32_t c, i; double v; };
+
+// First stage of a block's factor: the reverse Cuthill-McKee order of its
+// Gram graph (rows adjacent when they share a column) and the bandwidth of
+// A_t A_t^T in that order; -1 when the block has too many rows, or its
+// columns give too many row pairs, or the band would be too large (the block
+// keeps CG).  Cheap next to the factorisation, so the plan-wide limits can
+// be applied before any block is factored.
+static int64_t block_order(int64_t r0, int64_t nb, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                           const std::vector<double>& va, std::vector<FactorEnt>& es, std::vector<int32_t>& perm) {
     if (nb <= 0 || nb > kDirectMaxRows) return -1;
-    struct Ent { int32_t c, i; double v; };
-    std::vector<Ent> es;
+    using Ent = FactorEnt;
     es.reserve((size_t)(rp[r0 + nb] - rp[r0]));
     for (int64_t i = 0; i < nb; i++)
         for (int64_t k = rp[r0 + i]; k < rp[r0 + i + 1]; k++) es.push_back({ci[k], (int32_t)i, va[k]});
@@ -1122,8 +1131,16 @@ static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& 
         bw = std::max<int64_t>(bw, es[e - 1].i - es[a].i);
         a = e;
     }
+    if (nb * (bw + 1) > kDirectMaxBand) return -1;
+    return bw;
+}
+
+// Second stage: the banded Cholesky factor of A_t A_t^T in the block's order
+// (row products accumulated in ascending column order); false when a pivot
+// falls below kPivotTol of its diagonal (rank deficient to working accuracy).
+static bool factor_block(int64_t r0, int64_t nb, int64_t bw, const std::vector<FactorEnt>& es,
+                         const std::vector<double>& rinv, const std::vector<int32_t>& perm, std::vector<double>& L) {
     const int64_t W = bw + 1;
-    if (nb * W > kDirectMaxBand) return -1;
     L.assign((size_t)(nb * W), 0.0);
     auto at = [&](int64_t i, int64_t j) -> double& { return L[(size_t)(i * W + bw - (i - j))]; };
     for (size_t a = 0; a < es.size();) {
@@ -1144,12 +1161,12 @@ static int64_t factor_block(int64_t r0, int64_t nb, const std::vector<int64_t>& 
             if (j < i) {
                 at(i, j) = sum / at(j, j);
             } else {
-                if (!(sum > kPivotTol * gii)) return -1;
+                if (!(sum > kPivotTol * gii)) return false;
                 at(i, i) = std::sqrt(sum);
             }
         }
     }
-    return bw;
+    return true;
 }
 
 void block_factor(obk_plan_s& P, hipStream_t s) {
@@ -1159,19 +1176,17 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
     P.direct_lds = 0;
     std::vector<std::vector<double>> fac(K);
     std::vector<std::vector<int32_t>> perms(K);
-    if (P.opts.block_solver == 0 && K > 0) {
-        const int64_t n = P.n;
-        const std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
-        const std::vector<int32_t> ci = dev_to_host(P.rcol.get(), rp[n], s);
-        const std::vector<double> va = dev_to_host(P.rval.get(), rp[n], s);
-        const std::vector<double> ri = dev_to_host(P.rinv.get(), n, s);
+    std::vector<std::vector<FactorEnt>> ents(K);
+    // factors serve one-workgroup launches only: a plan whose launch spans
+    // several workgroups keeps CG for every block and builds none
+    const bool want = P.opts.block_solver == 0 && K > 0 && block_grid(P) == 1;
+    auto parallel = [&](auto&& body) {
         std::atomic<int32_t> next{0};
         std::atomic<bool> failed{false};
         auto worker = [&] {
             for (int32_t b; (b = next.fetch_add(1)) < K;) {
                 try {
-                    P.h_bbw[b] = factor_block(P.h_bptr[b], P.h_bptr[b + 1] - P.h_bptr[b], rp, ci, va, ri, fac[b],
-                                              perms[b]);
+                    body(b);
                 } catch (...) {
                     failed = true;
                 }
@@ -1190,17 +1205,49 @@ void block_factor(obk_plan_s& P, hipStream_t s) {
         worker();
         for (auto& th : pool) th.join();
         if (failed) fail(OBK_E_NOMEM, "host memory for the block factors");
+    };
+    if (want) {
+        const int64_t n = P.n;
+        const std::vector<int64_t> rp = dev_to_host(P.rptr.get(), n + 1, s);
+        const std::vector<int32_t> ci = dev_to_host(P.rcol.get(), rp[n], s);
+        const std::vector<double> va = dev_to_host(P.rval.get(), rp[n], s);
+        const std::vector<double> ri = dev_to_host(P.rinv.get(), n, s);
+        // 1. orders and bands of every block
+        parallel([&](int32_t b) {
+            P.h_bbw[b] = block_order(P.h_bptr[b], P.h_bptr[b + 1] - P.h_bptr[b], rp, ci, va, ents[b], perms[b]);
+        });
+        // 2. the plan-wide limits, in block order, before any factorisation:
+        // the band storage and the factorisation work (rows x band^2)
+        int64_t band_total = 0, work_total = 0;
+        for (int32_t b = 0; b < K; b++) {
+            const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b], bw = P.h_bbw[b];
+            if (bw < 0) continue;
+            const int64_t work = nb * (bw + 1) * (bw + 1);
+            if (band_total + nb * (bw + 1) > kDirectMaxTotal || work_total + work > kDirectMaxWork) {
+                P.h_bbw[b] = -1;
+                std::vector<FactorEnt>().swap(ents[b]);
+                continue;
+            }
+            band_total += nb * (bw + 1);
+            work_total += work;
+        }
+        // 3. factors of the blocks still in; a failed pivot test releases its factor
+        parallel([&](int32_t b) {
+            if (P.h_bbw[b] < 0) return;
+            const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b];
+            if (!factor_block(P.h_bptr[b], nb, P.h_bbw[b], ents[b], ri, perms[b], fac[b])) {
+                P.h_bbw[b] = -1;
+                std::vector<double>().swap(fac[b]);
+            }
+            std::vector<FactorEnt>().swap(ents[b]);
+        });
     }
-    // blocks in order until the plan-wide limit; the device footprint must
-    // stay within hbm_budget
+    // the device footprint must stay within hbm_budget
     std::vector<int64_t> off(K, 0);
     int64_t total = 0;
     for (int32_t b = 0; b < K; b++) {
         const int64_t nb = P.h_bptr[b + 1] - P.h_bptr[b];
-        if (P.h_bbw[b] < 0 || total + nb * (P.h_bbw[b] + 1) > kDirectMaxTotal) {
-            P.h_bbw[b] = -1;
-            continue;
-        }
+        if (P.h_bbw[b] < 0) continue;
         off[b] = total;
         total += nb * (P.h_bbw[b] + 1);
         P.h_bdirect[b] = 1;

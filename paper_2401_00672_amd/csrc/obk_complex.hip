@@ -167,12 +167,13 @@ __global__ void k_pack(int64_t n, const double* __restrict__ re, const double* _
 // ----------------------------------------------------------- sweep kernels
 // Phase R over one tile of rows: the real tile body (entries staged through
 // LDS, each row summed by its owner in ascending entry order) on complex
-// values, with the real scale 1/||a||^2: w_a = (f_a - a_a x~) / ||a_a||^2.
+// values, with the real scale 1/||a||^2: w_a = ((f_a - a_a x~) / ||a_a||^2) omega.
 __global__ __launch_bounds__(kZT) void k_phase_r_z(const Tile* __restrict__ tiles, const int64_t* __restrict__ rptr,
                                                    const int32_t* __restrict__ rcol,
                                                    const zdouble* __restrict__ rval,
                                                    const zdouble* __restrict__ rf, const double* __restrict__ rinv,
-                                                   const zdouble* __restrict__ x, zdouble* __restrict__ w) {
+                                                   const zdouble* __restrict__ x, zdouble* __restrict__ w,
+                                                   double omega) {
     __shared__ zdouble prod[kTileEntries];
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     constexpr int64_t C = kTileEntries;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kZT) void k_phase_r_z(const Tile* __restrict__ tile
     }
     if (own) {
         const zdouble d = fa - acc;
-        w[a] = zdouble(d.re * ia, d.im * ia);
+        w[a] = zdouble((d.re * ia) * omega, (d.im * ia) * omega);
     }
 }
 
@@ -366,7 +367,7 @@ static void enqueue_sweeps_zt(const obk_plan_s& P, double* x, int64_t sweeps, hi
             const int32_t s0 = P.h_stile_ptr[g], s1 = P.h_stile_ptr[g + 1];
             if (r1 > r0)
                 k_phase_r_z<<<r1 - r0, kZT, 0, s>>>(P.rtiles.get() + r0, P.rptr.get(), P.rcol.get(), rv, rf,
-                                                    P.rinv.get(), xz, wz);
+                                                    P.rinv.get(), xz, wz, P.opts.omega);
             if (s1 > s0)
                 k_phase_s_z<<<s1 - s0, kZT, 0, s>>>(P.stiles.get() + s0, P.sptr.get(), P.srow.get(), sv,
                                                     P.tcol.get(), wz, xz);
@@ -450,7 +451,7 @@ int32_t profile_sweeps_z(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s
                 hipExtLaunchKernelGGL(k_phase_r_z, dim3(r1 - r0), dim3(kZT), 0, s, l.a, l.b, 0,
                                       (const Tile*)(P.rtiles.get() + r0), (const int64_t*)P.rptr.get(),
                                       (const int32_t*)P.rcol.get(), rv, rf, (const double*)P.rinv.get(),
-                                      (const zdouble*)xz, wz);
+                                      (const zdouble*)xz, wz, P.opts.omega);
             }
             if (s1 > s0) {
                 L l{1, sbytes[g], nullptr, nullptr};

@@ -32,7 +32,29 @@ void check_hip(hipError_t e, const char* what) {
 namespace {
 thread_local hipStream_t g_alloc_stream = nullptr;
 thread_local bool g_alloc_scoped = false;
+thread_local void* (*g_user_alloc)(size_t, void*) = nullptr;
+thread_local void (*g_user_dealloc)(void*, void*) = nullptr;
+thread_local void* g_user_ctx = nullptr;
+thread_local hipStream_t g_user_stream = nullptr;
 }  // namespace
+
+UserAllocScope::UserAllocScope(void* (*alloc)(size_t, void*), void (*dealloc)(void*, void*), void* ctx,
+                               hipStream_t s)
+    : prev_alloc(g_user_alloc), prev_dealloc(g_user_dealloc), prev_ctx(g_user_ctx), prev_stream(g_user_stream) {
+    if (alloc) {
+        g_user_alloc = alloc;
+        g_user_dealloc = dealloc;
+        g_user_ctx = ctx;
+        g_user_stream = s;
+    }
+}
+
+UserAllocScope::~UserAllocScope() {
+    g_user_alloc = prev_alloc;
+    g_user_dealloc = prev_dealloc;
+    g_user_ctx = prev_ctx;
+    g_user_stream = prev_stream;
+}
 
 AllocScope::AllocScope(hipStream_t s) : prev_stream(g_alloc_stream), prev_on(g_alloc_scoped) {
     g_alloc_stream = s;
@@ -75,6 +97,16 @@ void DevMem::alloc(size_t b) {
     release();
     if (b == 0) b = 16;
     void* p = nullptr;
+    if (g_user_alloc) {
+        p = g_user_alloc(b, g_user_ctx);
+        if (!p) fail(OBK_E_NOMEM, "the caller's allocator returned NULL for " + std::to_string(b) + " bytes");
+        ptr = p;
+        bytes = b;
+        pooled = false;
+        dealloc = g_user_dealloc;
+        ctx = g_user_ctx;
+        return;
+    }
     const bool use_pool = g_alloc_scoped;
     hipError_t e = use_pool ? hipMallocAsync(&p, b, g_alloc_stream) : hipMalloc(&p, b);
     if (e != hipSuccess) {
@@ -87,7 +119,11 @@ void DevMem::alloc(size_t b) {
 }
 
 void DevMem::release() {
-    if (ptr) {
+    if (ptr && dealloc) {
+        // a temporary released during a call: no queued work may still use it
+        if (g_user_alloc) (void)hipStreamSynchronize(g_user_stream);
+        dealloc(ptr, ctx);
+    } else if (ptr) {
         if (pooled)
             (void)hipFreeAsync(ptr, g_alloc_scoped ? g_alloc_stream : nullptr);
         else
@@ -96,6 +132,8 @@ void DevMem::release() {
     ptr = nullptr;
     bytes = 0;
     pooled = false;
+    dealloc = nullptr;
+    ctx = nullptr;
 }
 
 // --------------------------------------------------------------------- RCM

@@ -49,21 +49,36 @@ void sync_for_free(hipStream_t s);
 // until the thread ends); every user completes its copy before returning.
 void* pinned_stage(size_t bytes);
 
+// While a UserAllocScope is active on the calling thread, buffers come from
+// the caller's allocator (obk_opts.alloc / dealloc / ctx) instead; each
+// buffer keeps its dealloc, and a temporary released while the scope is
+// active first waits for the scope's stream.
+struct UserAllocScope {
+    void* (*prev_alloc)(size_t, void*);
+    void (*prev_dealloc)(void*, void*);
+    void* prev_ctx;
+    hipStream_t prev_stream;
+    UserAllocScope(void* (*alloc)(size_t, void*), void (*dealloc)(void*, void*), void* ctx, hipStream_t s);
+    ~UserAllocScope();
+};
+
 struct DevMem {
     void* ptr = nullptr;
     size_t bytes = 0;
     bool pooled = false;
+    void (*dealloc)(void*, void*) = nullptr;   // the caller's deallocator, when it came from alloc
+    void* ctx = nullptr;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
-    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes), pooled(o.pooled) {
-        o.ptr = nullptr; o.bytes = 0; o.pooled = false;
+    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes), pooled(o.pooled), dealloc(o.dealloc), ctx(o.ctx) {
+        o.ptr = nullptr; o.bytes = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
     }
     DevMem& operator=(DevMem&& o) noexcept {
         if (this != &o) {
             release();
-            ptr = o.ptr; bytes = o.bytes; pooled = o.pooled;
-            o.ptr = nullptr; o.bytes = 0; o.pooled = false;
+            ptr = o.ptr; bytes = o.bytes; pooled = o.pooled; dealloc = o.dealloc; ctx = o.ctx;
+            o.ptr = nullptr; o.bytes = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
         }
         return *this;
     }
@@ -163,6 +178,40 @@ void block_factor(obk_plan_s& P, hipStream_t s);
 void block_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, float* ms);
 int32_t profile_block(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
                       int32_t max_out);
+// Banded sweep engine (obk_slab.hip): one persistent launch in which each
+// workgroup owns a contiguous slab of the reordered unknowns.
+struct SlabPhase {           // one phase (R or S) of one group on one slab
+    int64_t item_off;        // first item in the item arrays
+    int32_t count;           // items (rows in R, touched window columns in S)
+    int32_t round0, nrounds; // rounds in the round table
+    int32_t ents;            // entries of all its rounds (ELL, padding included)
+    int32_t cache;           // byte offset of its copy in the LDS cache, -1: streamed
+    int32_t pad;
+};
+struct SlabRound {           // items [r * QT, ...) of a phase, entry-major
+    int64_t ent_off;         // first entry of the round
+    int32_t K;               // entries per item in the round (its longest item)
+    int32_t pad;
+};
+struct SlabGroup {           // one group on one slab
+    SlabPhase r, s;
+    int32_t lo_cnt, own_cnt, hi_cnt;   // w window: [lower halo | own rows | upper halo]
+    int32_t pre_cnt, suf_cnt;          // own rows published to slab k-1 (first) and k+1 (last)
+    int32_t pad;
+};
+struct SlabDesc {            // one slab
+    int32_t xlo, xcount;     // x window: reordered columns [xlo, xlo + xcount)
+    int32_t own_lo, own_cnt; // own columns: window positions [own_lo, own_lo + own_cnt)
+    int32_t round_first, round_count;   // the slab's rounds (contiguous in the round table)
+    int32_t cache_bytes;     // bytes of its phases copied to LDS at launch start
+    int32_t pad;
+};
+constexpr int32_t kSlabMaxGroups = 64;
+void slab_setup(obk_plan_s& P, const std::vector<int64_t>& hrptr, const std::vector<int32_t>& grow,
+                const std::vector<int32_t>& pos, hipStream_t s);
+void slab_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+double slab_profile(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
+void slab_check(obk_plan_s& P, hipStream_t s);
 }  // namespace obk
 
 // --------------------------------------------------------------- the plan
@@ -259,6 +308,22 @@ struct obk_plan_s {
     obk::DevArray<double> lfc, lfr, ldinv;
     obk::DevArray<int32_t> d_lperm, d_lpos;   // factor order of each block's rows, and its inverse [n]
     int64_t direct_lds = 0;                   // dynamic LDS bytes of a direct projection (0: none)
+
+    // banded sweep engine (slab_S > 0 when it runs the FP64 sweeps)
+    int32_t slab_S = 0;                       // slabs (workgroups) of the launch
+    int64_t slab_xmax = 0, slab_wmax = 0;     // largest x and w windows (LDS doubles)
+    int64_t slab_cap = 0;                     // exchange buffer doubles per (slab, side, parity)
+    int64_t slab_lds = 0;                     // dynamic LDS bytes
+    int64_t slab_meta_off = 0, slab_cache_off = 0;   // LDS byte offsets of descriptors and cached phases
+    double slab_bytes_per_sweep = 0;          // bytes one sweep streams (items, entries, exchange)
+    double slab_bytes_per_launch = 0;         // bytes read once per launch (windows, cached phases)
+    obk::DevArray<obk::SlabDesc> sl_desc;
+    obk::DevArray<obk::SlabGroup> sl_grp;
+    obk::DevArray<obk::SlabRound> sl_round;
+    obk::DevArray<uint16_t> sl_tgt, sl_len, sl_idx;
+    obk::DevArray<double> sl_f, sl_inv, sl_val, sl_xbuf;
+    obk::DevArray<uint32_t> sl_flags;
+    obk::DevArray<int> sl_err;
 
     // captured sweep sequences (hipGraph), keyed by iterate pointer, sweep
     // count and element size; replayed on the caller's stream

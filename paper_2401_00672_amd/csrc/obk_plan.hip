@@ -851,6 +851,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
     tr.mark("tiles");
+    if (!cplx && !P.block_form()) slab_setup(P, hrptr, grow, pos_of_row, s);
+    tr.mark("banded_engine");
     if (P.block_form()) {
         block_setup(P, s);
         block_factor(P, s);

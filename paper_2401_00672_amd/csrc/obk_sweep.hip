@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 
 #include <chrono>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -107,8 +108,11 @@ static TileList tile_list(const std::vector<Tile>& tiles, int32_t t0, int32_t t1
 }
 
 template <class T>
-static void enqueue_sweeps_t(const obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval,
+static void enqueue_sweeps_t(obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval,
                              T* x, T* w, int64_t sweeps, hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (P.slab_S > 0) return slab_sweeps(P, x, sweeps, s);     // the banded engine, one launch
+    }
     const int32_t G = P.ngroups;
     std::vector<TileList> rl(G), sl(G);
     std::vector<int32_t> rin(G), sin(G);
@@ -123,10 +127,10 @@ static void enqueue_sweeps_t(const obk_plan_s& P, const T* rval, const T* rf, co
             if (r1 > r0) {
                 if (rin[g])
                     k_phase_r<T, true><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, rl[g], P.rptr.get(), P.rcol.get(),
-                                                               rval, rf, rinv, x, w);
+                                                               rval, rf, rinv, x, w, (T)P.opts.omega);
                 else
                     k_phase_r<T, false><<<r1 - r0, kT, 0, s>>>(P.rtiles.get() + r0, rl[g], P.rptr.get(),
-                                                                P.rcol.get(), rval, rf, rinv, x, w);
+                                                                P.rcol.get(), rval, rf, rinv, x, w, (T)P.opts.omega);
             }
             if (s1 > s0) {
                 if (sin[g])
@@ -193,6 +197,16 @@ void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s) {
 int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
                        int32_t max_out) {
     if (P.block_form()) return profile_block(P, x, sweeps, s, out, max_out);
+    if (P.slab_S > 0) {
+        if (max_out < 1) return 0;
+        obk_kernel_profile& o = out[0];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, "k_slab_sweeps", sizeof(o.name) - 1);
+        o.launches = 1;
+        o.seconds = slab_profile(P, x, sweeps, s);
+        o.bytes = P.slab_bytes_per_sweep * (double)sweeps + P.slab_bytes_per_launch;
+        return 1;
+    }
     const int32_t G = P.ngroups;
     struct Launch { int kind; double bytes; };
     std::vector<Launch> plan_launches;
@@ -232,7 +246,7 @@ int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, 
                                       (const Tile*)(P.rtiles.get() + r0), rl, (const int64_t*)P.rptr.get(),
                                       (const int32_t*)P.rcol.get(), (const double*)P.rval.get(),
                                       (const double*)P.rf.get(), (const double*)P.rinv.get(), (const double*)x,
-                                      P.w.get());
+                                      P.w.get(), P.opts.omega);
                 k++, li++;
             }
             if (s1 > s0) {
@@ -308,7 +322,8 @@ static void resid_tiles(const obk_plan_s& P, const double* x, double* r, hipStre
 }
 
 // relative residual ||f~ - A~ x|| / ||f~|| (synchronises the stream); sets *nonfinite
-double relres(const obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
+double relres(obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
+    slab_check(P, s);
     double r2 = 0, mx = 0;
     bool nf = false;
     resid_tiles(P, x, nullptr, s, &r2, &mx, &nf);

@@ -4,7 +4,7 @@
 // refinement).
 //
 // phase R (one group): for each row a of the tile, from the same x,
-//   w_a = (f_a - sum_k a_ak x_k) * inv_a
+//   w_a = ((f_a - sum_k a_ak x_k) * inv_a) * omega   (omega = 1: the paper's step)
 // phase S (one group): for each touched column c of the tile,
 //   x_c = x_c + sum over the group's rows a holding c of w_a a_ac
 //
@@ -100,7 +100,7 @@ template <class T, int Q = kPlanQ, int E = kPlanE>
 __device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod, const int64_t* __restrict__ rptr,
                                              const int32_t* __restrict__ rcol, const T* __restrict__ rval,
                                              const T* __restrict__ rf, const T* __restrict__ rinv,
-                                             const T* __restrict__ x, T* __restrict__ w) {
+                                             const T* __restrict__ x, T* __restrict__ w, T omega) {
     constexpr int64_t C = (int64_t)kTileThreads * E;     // entries per chunk
     const int nseg = t.seg_end - t.seg_begin;
     const int me = threadIdx.x & (kTileThreads - 1);
@@ -132,7 +132,7 @@ __device__ __forceinline__ void tile_phase_r(const Tile& t, int nchunks, T* prod
     }
 #pragma unroll
     for (int q = 0; q < Q; q++)
-        if (own[q]) w[a[q]] = (fa[q] - acc[q]) * ia[q];
+        if (own[q]) w[a[q]] = ((fa[q] - acc[q]) * ia[q]) * omega;
 }
 
 template <class T, int Q = kPlanQ, int E = kPlanE>
@@ -254,10 +254,10 @@ template <class T, bool kInl>
 __global__ __launch_bounds__(kTileThreads) void k_phase_r(
     const Tile* __restrict__ tiles, TileList tl, const int64_t* __restrict__ rptr,
     const int32_t* __restrict__ rcol, const T* __restrict__ rval, const T* __restrict__ rf,
-    const T* __restrict__ rinv, const T* __restrict__ x, T* __restrict__ w) {
+    const T* __restrict__ rinv, const T* __restrict__ x, T* __restrict__ w, T omega) {
     __shared__ T prod[kTileEntries];
     const Tile t = kInl ? tl.t[blockIdx.x] : tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w);
+    tile_phase_r<T>(t, tile_chunks(t), prod, rptr, rcol, rval, rf, rinv, x, w, omega);
 }
 
 template <class T, bool kInl>

@@ -17,7 +17,15 @@ persistent launch, then the FP64 update):
   which live in their plans) and only the newcomers are started from x0 = 0;
 * **retiring** -- a member whose relative residual reached ``tol`` (or that hit
   ``max_steps``) leaves at the step boundary; its solution is copied to the
-  host and its plan freed.
+  host.  Its slot in the batch object is disabled (``obk_batch_enable``)
+  rather than rebuilt; its plan stays allocated while the batch object
+  refers to it and is freed when the batch is next rebuilt -- when requests
+  join, when disabled slots outnumber the live ones, or when the head of the
+  queue waits for memory that retired plans hold;
+* **failure and cancellation** -- a request whose plan fails (a malformed
+  system, memory) gets a ``failed`` result and returns its budget; ``cancel``
+  (from any thread) withdraws a request that is waiting, planning or being
+  solved, with a ``cancelled`` result, and leaves the others' work as it is.
 
 Latency is measured from a request's arrival to its solution being on the
 host.  The backend is pluggable so that the scheduling logic can be tested on
@@ -29,6 +37,7 @@ import collections
 import concurrent.futures as cf
 import dataclasses
 import queue
+import threading
 import time
 
 import numpy as np
@@ -50,7 +59,8 @@ class Result:
     finished: float
     steps: int
     relres: float
-    status: str             # "converged" | "maxit" | "rejected"
+    status: str             # "converged" | "maxit" | "rejected" | "failed" | "cancelled"
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -102,6 +112,9 @@ class LibobkBackend:
     def make_batch(self, plans):
         return self.obk.Batch(plans, self.batch_opts)
 
+    def enable(self, batch, enabled) -> None:
+        batch.enable(np.asarray(enabled, dtype=np.int32), stream=self.stream.cuda_stream)
+
     def start(self, batch, i: int) -> None:
         batch.start(i, stream=self.stream.cuda_stream)
 
@@ -125,6 +138,7 @@ class _Member:
     nbytes: int
     admitted: float
     steps: int = 0
+    live: bool = True       # False once retired (its slot in the batch is disabled)
 
 
 class Server:
@@ -140,7 +154,19 @@ class Server:
         self.clock = clock
         self.idle_wait = idle_wait
         self.stats = {"steps": 0, "rebuilds": 0, "peak_bytes": 0, "peak_members": 0, "step_seconds": 0.0,
-                      "rebuild_seconds": 0.0}
+                      "rebuild_seconds": 0.0, "failed": 0, "cancelled": 0}
+        self._cancel_lock = threading.Lock()
+        self._cancel: set[int] = set()
+
+    def cancel(self, rid: int) -> None:
+        """Withdraw request `rid` (thread-safe): it is dropped at the next loop
+        turn with a ``cancelled`` result, whatever stage it is in."""
+        with self._cancel_lock:
+            self._cancel.add(int(rid))
+
+    def _cancelled(self) -> set[int]:
+        with self._cancel_lock:
+            return set(self._cancel)
 
     def run(self, requests) -> list[Result]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -148,78 +174,113 @@ class Server:
         t0 = self.clock()
         now = lambda: self.clock() - t0          # noqa: E731
         results: dict[int, Result] = {}
-        members: list[_Member] = []
+        members: list[_Member] = []              # the batch's slots, in batch order
         joining: list[_Member] = []
         planning: dict[cf.Future, tuple[Request, int, float]] = {}
         used = 0
         batch = None
         pool = cf.ThreadPoolExecutor(max_workers=max(1, self.planners))
+
+        def finish(r: Request, admitted: float, status: str, x=None, steps=0, relres=float("nan"), err=""):
+            results[r.rid] = Result(r.rid, x, r.arrival, admitted, now(), steps, relres, status, err)
+            if status in ("failed", "cancelled"):
+                self.stats[status] += 1
+
         try:
             while len(results) < len(reqs):
                 t = now()
+                gone = self._cancelled()
+                # 0. cancellations: waiting requests leave the queue at once
+                if gone and any(r.rid in gone for r in pending):
+                    for r in [r for r in pending if r.rid in gone]:
+                        finish(r, t, "cancelled")
+                    pending = collections.deque(r for r in pending if r.rid not in gone)
                 # 1. admission: FIFO, the head blocks when it does not fit
+                blocked = False
                 while pending and pending[0].arrival <= t:
                     r = pending[0]
                     est = footprint_estimate(r.system.n, r.system.nnz)
                     if est > self.budget:
                         pending.popleft()
-                        results[r.rid] = Result(r.rid, None, r.arrival, t, now(), 0, float("nan"), "rejected")
+                        finish(r, t, "rejected")
                         continue
                     if used + est > self.budget:
+                        blocked = True
                         break
                     pending.popleft()
                     used += est
                     planning[pool.submit(self.backend.plan, r.system)] = (r, est, t)
-                # 2. planned requests join at this step boundary
+                # 2. planned requests join at this step boundary (a failed or
+                # cancelled one returns its budget)
                 for fut in [f for f in planning if f.done()]:
                     r, est, ta = planning.pop(fut)
-                    plan = fut.result()
+                    try:
+                        plan = fut.result()
+                    except Exception as e:               # noqa: BLE001 -- reported per request
+                        used -= est
+                        finish(r, ta, "failed", err=str(e))
+                        continue
+                    if r.rid in gone:
+                        self.backend.free_plan(plan)
+                        used -= est
+                        finish(r, ta, "cancelled")
+                        continue
                     nb = self.backend.plan_bytes(plan)
                     used += nb - est
                     joining.append(_Member(r, plan, nb, ta))
                 self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
-                if joining:
+                # cancelled members retire like finished ones, without a result
+                if gone and any(m.live and m.req.rid in gone for m in members):
+                    for m in members:
+                        if m.live and m.req.rid in gone:
+                            m.live = False
+                            finish(m.req, m.admitted, "cancelled", steps=m.steps)
+                    self.backend.enable(batch, [1 if m.live else 0 for m in members])
+                live = [m for m in members if m.live]
+                retired_held = len(members) - len(live)
+                if joining or (retired_held and (len(live) < retired_held or blocked)):
+                    # rebuild over the live members and the newcomers; the
+                    # retired members' plans are freed once no batch refers to them
                     tb = self.clock()
                     if batch is not None:
                         self.backend.free_batch(batch)
-                    first_new = len(members)
-                    members.extend(joining)
+                        batch = None
+                    for m in members:
+                        if not m.live:
+                            self.backend.free_plan(m.plan)
+                            used -= m.nbytes
+                    first_new = len(live)
+                    members = live + joining
                     joining = []
-                    batch = self.backend.make_batch([m.plan for m in members])
-                    for i in range(first_new, len(members)):
-                        self.backend.start(batch, i)
-                    self.stats["rebuilds"] += 1
+                    if members:
+                        batch = self.backend.make_batch([m.plan for m in members])
+                        for i in range(first_new, len(members)):
+                            self.backend.start(batch, i)
+                        self.stats["rebuilds"] += 1
                     self.stats["rebuild_seconds"] += self.clock() - tb
-                self.stats["peak_members"] = max(self.stats["peak_members"], len(members))
+                live_count = sum(1 for m in members if m.live)
+                self.stats["peak_members"] = max(self.stats["peak_members"], live_count)
                 # 3. one batched step, then retire the finished members
-                if members:
+                if live_count:
                     ts = self.clock()
                     relres, active = self.backend.step(batch, self.tol)
                     self.stats["step_seconds"] += self.clock() - ts
                     self.stats["steps"] += 1
-                    keep = []
+                    retired = False
                     for i, m in enumerate(members):
+                        if not m.live:
+                            continue
                         if active[i]:
                             m.steps += 1
-                        done = (not active[i]) or m.steps >= self.max_steps
-                        if not done:
-                            keep.append(m)
+                        if active[i] and m.steps < self.max_steps:
                             continue
                         x = self.backend.result(batch, i)
                         status = "converged" if relres[i] <= self.tol and not active[i] else "maxit"
-                        results[m.req.rid] = Result(m.req.rid, x, m.req.arrival, m.admitted, now(), m.steps,
-                                                    float(relres[i]), status)
-                        self.backend.free_plan(m.plan)
-                        used -= m.nbytes
-                    if len(keep) != len(members):
-                        self.backend.free_batch(batch)
-                        batch = None
-                        members = keep
-                        if members:
-                            tb = self.clock()
-                            batch = self.backend.make_batch([m.plan for m in members])
-                            self.stats["rebuilds"] += 1
-                            self.stats["rebuild_seconds"] += self.clock() - tb
+                        finish(m.req, m.admitted, status, x, m.steps, float(relres[i]))
+                        m.live = False
+                        retired = True
+                    if retired and any(m.live for m in members):
+                        self.backend.enable(batch, [1 if m.live else 0 for m in members])
                     continue
                 # 4. idle: wait for a plan or the next arrival
                 wait = self.idle_wait
@@ -233,6 +294,15 @@ class Server:
             pool.shutdown(wait=True)
             if batch is not None:
                 self.backend.free_batch(batch)
+            # plans still held (retired members of the last batch, or all of
+            # them when the loop ends early on an error elsewhere)
+            for m in members + joining:
+                self.backend.free_plan(m.plan)
+            for fut in planning:
+                try:
+                    self.backend.free_plan(fut.result())
+                except Exception:                        # noqa: BLE001 -- its error was the request's
+                    pass
         return [results[r.rid] for r in reqs]
 
 

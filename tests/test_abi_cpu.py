@@ -38,6 +38,8 @@ def test_opts_default_and_free_null():
     assert (o.use_rcm, o.precision, o.inner_sweeps, o.check_every, o.reject_inconsistent, o.hbm_budget) == \
         (1, 0, 8, 1, 0, 0)
     assert (o.block_k, o.block_wgs, o.block_maxit, o.block_tol) == (0, 0, 0, 1e-14)
+    assert (o.sweep_kernel, o.omega, o.max_group, o.deterministic) == (0, 1.0, 0, 1)
+    assert (o.alloc, o.dealloc, o.ctx) == (None, None, None)
     L.obk_free(None)
     assert L.obk_opts_default(None) == -1
 
@@ -54,6 +56,13 @@ def test_opts_default_and_free_null():
     (dict(block_k=2, precision=1), -1), # block form is FP64 only
     (dict(block_k=2, block_tol=-1.0), -1),
     (dict(block_k=2, block_maxit=-3), -1),
+    (dict(omega=0.0), -1),              # relaxation in (0, 2)
+    (dict(omega=2.0), -1),
+    (dict(omega=float("nan")), -1),
+    (dict(block_k=2, omega=0.5), -1),   # the block form takes no relaxation
+    (dict(max_group=3), -1),            # 0 (first fit) or 2 (the paper's pairs)
+    (dict(max_group=2, block_k=2), -1),
+    (dict(sweep_kernel="banded", block_k=2), -1),
 ])
 def test_plan_rejects_bad_arguments_before_any_gpu_work(kw, code):
     s = synth.c1(n=6)
@@ -197,3 +206,33 @@ def test_header_is_plain_c(tmp_path):
                         os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "use_obk.o")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def _opts_plan_rc(**fields):
+    """obk_plan on a 6-row host system with raw option fields; returns the
+    status (the options are checked before any device work)."""
+    s = synth.c1(n=6)
+    csr = obk._Csr(s.n, s.n, s.nnz, s.row_ptr.ctypes.data, s.col.ctypes.data, s.val.ctypes.data, 0)
+    o = obk._Opts()
+    obk.lib().obk_opts_default(ctypes.byref(o))
+    for k, v in fields.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    rc = obk.lib().obk_plan(ctypes.byref(csr), s.f.ctypes.data, 0.1, ctypes.byref(o), None, ctypes.byref(h))
+    assert not h.value
+    return rc
+
+
+def test_plan_rejects_bad_option_fields_before_any_gpu_work():
+    """deterministic takes 0 or 1; alloc and dealloc come together; a pair
+    rule (max_group = 2) beyond 4096 rows is refused; sweep_kernel is 0..2."""
+    keep = obk.ALLOC_FN(lambda n, ctx: None)
+    assert _opts_plan_rc(deterministic=2) == -1
+    assert "deterministic" in obk.lib().obk_last_error().decode()
+    assert _opts_plan_rc(alloc=ctypes.cast(keep, ctypes.c_void_p)) == -1
+    assert "alloc and dealloc" in obk.lib().obk_last_error().decode()
+    assert _opts_plan_rc(sweep_kernel=3) == -1
+    s = synth.c1(n=5000)
+    with pytest.raises(obk.ObkError) as ei:
+        obk.plan(s.row_ptr, s.col, s.val, s.f, 0.1, max_group=2)
+    assert ei.value.code == -1 and "4096" in str(ei.value)

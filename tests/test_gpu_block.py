@@ -4,12 +4,14 @@ projections) against the oracle's block form (through the C ABI).
 Bar: the RCM permutation, the block ranges, the Oclass pairs (in the order
 formed) and Nclass are exact; the |cos| table of the block centroids agrees
 to 1e-12 absolute (both FP64; the two sides sum in different orders); the
-iterate after K sweeps is within 1e-9 relative (2-norm) of the oracle's.
+iterate after K sweeps is within 1e-10 of the oracle's, relative in the
+2-norm and element-wise (max |difference| over max |oracle entry|).
 The oracle projects with the dense pseudo-inverse; the library runs
 conjugate gradients on A_t A_t^T y = r to a relative residual of 1e-14 per
 projection, so each projection carries an error of about 1e-14 times the
 condition number of the block; over K k projections on these well
-conditioned blocks that stays below 1e-11, and 1e-9 leaves room.
+conditioned blocks that stays below 1e-11 (observed at most a few 1e-15
+for the direct projections).
 """
 import sys
 
@@ -23,7 +25,7 @@ import paper_2401_00672_amd as obk
 
 pytestmark = pytest.mark.gpu
 
-TOL_X = 1e-9
+TOL_X = 1e-10
 TOL_COS = 1e-12
 
 
@@ -40,8 +42,11 @@ def _need_gpu():
 
 
 def _rel(a, b):
+    """The larger of the 2-norm relative error and the element-wise one."""
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    return max(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0),
+               (np.abs(a - b).max() if b.size else 0.0) / (mb if mb > 0 else 1.0))
 
 
 def _check_plan(P, bp, k):

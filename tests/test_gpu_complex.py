@@ -36,7 +36,9 @@ def _need_gpu():
 
 
 def _rel(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    """The larger of the 2-norm relative error and the element-wise one."""
+    return max(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300),
+               np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 CASES = [

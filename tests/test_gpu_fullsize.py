@@ -1,15 +1,14 @@
-"""Parity at the benchmark sizes, where the whole oracle plan is too slow to run.
+"""Parity at the benchmark sizes.
 
 Scattered 2,000,000-row system (12 nnz/row):
-  * the RCM permutation is bit-exact against the oracle's RCM, run in full;
-  * the grouping is checked row by row on a random sample with the oracle's
-    own cosine (O6): no sampled row shares a group with a row it conflicts
-    with, and a sampled row of group c has, for every c' < c, an earlier
-    conflicting row in group c' (which, with the first property, is exactly
-    first-fit at that row);
+  * the whole oracle plan (its conflict pass runs on all cores): the RCM
+    permutation and every row's group are bit-exact;
+  * x after 2 FP64 sweeps equals the oracle's element-wise (threaded oracle
+    sweep, the same operations as the plain one);
   * FP64 sweeps never increase ||x - x*|| (the group step is non-expansive on
     a consistent system), and FP32 sweeps + FP64 refinement bring the
-    row-dominant companion to relative residual 1e-10 (checked on the host).
+    row-dominant companion to relative residual 1e-10 (checked on the host),
+    with its error against the oracle's FP64 refinement stated.
 
 512 batched systems, in the launch configuration the benchmark times (tuned):
   every system's batched result equals its single solve bit for bit, and the
@@ -19,7 +18,6 @@ import sys
 
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import oracle
 import synth
@@ -40,51 +38,52 @@ def _need_gpu():
     torch.cuda.init()
 
 
-def _check_first_fit_sample(n, trp, tci, tv, nu, group, delta, rows):
-    A = sp.csr_matrix((tv, tci, trp), shape=(n, n))
-    C = A.tocsc()
-    for i in rows:
-        gi = int(group[i])
-        if nu[i] == 0.0:
-            assert gi == -1
-            continue
-        cols = tci[trp[i]:trp[i + 1]]
-        cand = np.unique(np.concatenate([C.indices[C.indptr[c]:C.indptr[c + 1]] for c in cols]))
-        cand = cand[cand != i]
-        conf = [int(j) for j in cand
-                if nu[j] != 0.0 and oracle.cosine(i, j, trp, tci, tv, nu) >= delta]
-        assert all(int(group[j]) != gi for j in conf), f"row {i} shares group {gi} with a conflicting row"
-        earlier = {int(group[j]) for j in conf if j < i}
-        assert set(range(gi)) <= earlier, f"row {i}: group {gi} is not the first free one"
-
-
 @pytest.mark.timeout(900)
 def test_scattered_2m_full_size():
+    """The whole oracle plan (RCM, conflicts on all cores, first fit) of the
+    2,000,000-row system against the GPU's: permutation and groups bit-exact;
+    the iterate after 2 FP64 sweeps against the oracle's (threaded sweep,
+    the same operations) element-wise; FP32 sweeps + FP64 refinement on the
+    companion to relative residual 1e-10, with its error against the oracle's
+    FP64 run of the same refinement schedule."""
     s = synth.c3()
     n = s.n
-    _say(f"[full] scattered n={n} nnz={s.nnz}: oracle RCM")
-    p_o = oracle.rcm(n, s.row_ptr, s.col)
-    trp, tci, tv, tf = oracle.permute(n, s.row_ptr, s.col, s.val, s.f, p_o)
-    nu, _ = oracle.norms(n, trp, tv)
+    _say(f"[full] scattered n={n} nnz={s.nnz}: oracle plan on {oracle.max_threads()} threads")
+    pl = oracle.plan_system(s, 0.1)
+    _say(f"[full] scattered: oracle {pl.ngroups} groups, {pl.cidx.size} conflicts")
     with obk.plan_system(s, 0.1) as P:
-        assert np.array_equal(P.perm(), p_o)
+        assert np.array_equal(P.perm(), pl.p), "RCM permutation differs"
         g, ng = P.groups()
-        assert ng == int(g.max()) + 1
-        rows = np.random.default_rng(7).choice(n, 2000, replace=False)
-        _say(f"[full] scattered: {ng} groups, first-fit check on {len(rows)} sampled rows")
-        _check_first_fit_sample(n, trp, tci, tv, nu, g, 0.1, rows)
+        assert ng == pl.ngroups and np.array_equal(g, pl.group), "group assignment differs"
+        assert P.stats()["conflicts"] == pl.cidx.size
+        x2, _ = P.solve(maxit=2)
         errs = []
         for k in range(1, 5):
             x, _ = P.solve(maxit=k)
             errs.append(np.linalg.norm(x - s.x_star))
         _say(f"[full] scattered: ||x_k - x*|| = {['%.6e' % e for e in errs]}")
         assert all(b <= a for a, b in zip(errs, errs[1:]))
+    ts = oracle.ThreadedSweep(pl)
+    xo = oracle.unpermute(pl.p, ts.sweep(np.zeros(n), 2))
+    ts.close()
+    dev = np.abs(x2 - xo).max()
+    _say(f"[full] scattered: 2 sweeps, max |x_gpu - x_oracle| = {dev:.3e} (max |x| {np.abs(xo).max():.3e}), "
+         f"bitwise={np.array_equal(x2, xo)}")
+    assert dev <= 1e-10 * np.abs(xo).max()
     sc = synth.c3(companion=True)
     with obk.plan_system(sc, 0.1, precision=obk.FP32_IR, inner_sweeps=8) as P:
         x, info = P.solve(maxit=100, tol=1e-10)
     rel = np.linalg.norm(sc.f - sc.scipy() @ x) / np.linalg.norm(sc.f)
-    _say(f"[full] scattered companion fp32-ir: {info.status} steps={info.outer_steps} relres={rel:.3e}")
+    _say(f"[full] scattered companion fp32-ir: {info.status} steps={info.outer_steps} relres={rel:.3e}; "
+         f"oracle FP64 refinement")
     assert info.status == "converged" and rel <= 1.5e-10
+    plc = oracle.plan_system(sc, 0.1)
+    xt64, steps64, rho64 = oracle.refine(plc, 8, 100, 1e-10)
+    x64 = oracle.unpermute(plc.p, xt64)
+    err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+    _say(f"[full] scattered companion: oracle FP64 refinement {steps64} steps relres {rho64:.3e}; "
+         f"error of the FP32+IR result vs the FP64 oracle {err:.3e}")
+    assert err <= 1e-8
 
 
 @pytest.mark.timeout(900)

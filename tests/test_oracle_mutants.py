@@ -31,10 +31,14 @@ MUTANTS = [
      "if (orc_cosine(i, j, rp, ci, v, nu) > delta) {"),
     ("firstfit_skips_zero", "int32_t g = 0;\n        while (used[g]) g++;",
      "int32_t g = 1;\n        while (used[g]) g++;"),
-    ("sweep_sign", "w[i] = (f[i] - s) * inv[i];", "w[i] = (s - f[i]) * inv[i];"),
+    ("sweep_sign", "w[i] = ((f[i] - s) * inv[i]) * omega;\n            }\n            /* (ii)",
+     "w[i] = ((s - f[i]) * inv[i]) * omega;\n            }\n            /* (ii)"),
+    ("sweep_omega_dropped", "w[i] = ((f[i] - s) * inv[i]) * omega;\n            }\n            /* (ii)",
+     "w[i] = ((f[i] - s) * inv[i]);\n            }\n            /* (ii)"),
     ("sweep_gathers_wrong_x", "for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[ci[k]];\n"
-     "                w[i]", "for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[i];\n"
-     "                w[i]"),
+     "                w[i] = ((f[i] - s) * inv[i]) * omega;\n            }\n            /* (ii)",
+     "for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = s + v[k] * x[i];\n"
+     "                w[i] = ((f[i] - s) * inv[i]) * omega;\n            }\n            /* (ii)"),
     ("sweep_drops_update", "x[c] = x[c] + t[c];", "x[c] = t[c];"),
     ("sweep_sequential_within_group", "x[c] = x[c] + t[c];", "x[c] = x[c];"),
     ("relres_no_sqrt", "? 0.0 : -1.0;\n    return sqrt(rr) / sqrt(ff);", "? 0.0 : -1.0;\n    return rr / ff;"),
@@ -74,9 +78,10 @@ def source():
 def _sequential_patch(src):
     # within a group, apply each row's update at once (the mistake of running
     # the class rows one after another from the latest iterate)
-    old = "                w[i] = (f[i] - s) * inv[i];"
-    new = ("                w[i] = (f[i] - s) * inv[i];\n"
-           "                for (int64_t k = rp[i]; k < rp[i + 1]; k++) x[ci[k]] = x[ci[k]] + w[i] * v[k];")
+    old = "                w[i] = ((f[i] - s) * inv[i]) * omega;\n            }\n            /* (ii)"
+    new = ("                w[i] = ((f[i] - s) * inv[i]) * omega;\n"
+           "                for (int64_t k = rp[i]; k < rp[i + 1]; k++) x[ci[k]] = x[ci[k]] + w[i] * v[k];"
+           "\n            }\n            /* (ii)")
     src = _apply(src, old, new, "seq")
     return src
 

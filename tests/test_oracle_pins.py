@@ -466,6 +466,47 @@ def test_relres_against_scipy():
                                np.linalg.norm(r) / np.linalg.norm(s.f), rtol=1e-13)
 
 
+# ------------------------------------------------- relaxation (omega)
+def test_relaxed_step_on_the_identity():
+    """With omega, each row step moves omega times the projection: on the
+    identity (one group) one sweep from 0 gives x = omega f exactly (one
+    rounding per entry), and omega = 1 is the unrelaxed step of eq. 1.2."""
+    f = np.arange(1.0, 34.0) / 7.0
+    s = synth.from_dense(np.eye(33), f=f)
+    for om in (0.5, 1.3, 1.0):
+        pl = oracle.plan_system(s, 0.1, omega=om)
+        assert pl.ngroups == 1
+        x = oracle.sweep(pl, np.zeros(33), 1)
+        assert np.array_equal(x, om * pl.f)
+
+
+def test_relaxed_single_group_step_is_relaxed_cimmino():
+    """delta > 1 puts every row in one group: one sweep is the relaxed
+    simultaneous step x + omega A^T D^-1 (f - A x), D = diag(||a_i||^2),
+    formed here with dense numpy."""
+    s = synth.c1(n=80)
+    for om in (0.6, 1.7):
+        pl = oracle.plan_system(s, 1.5, omega=om)
+        assert pl.ngroups == 1
+        A = sp.csr_matrix((pl.v, pl.ci, pl.rp), shape=(s.n, s.n)).toarray()
+        x0 = np.random.default_rng(8).standard_normal(s.n)
+        want = x0 + om * (A.T @ ((pl.f - A @ x0) / np.einsum("ij,ij->i", A, A)))
+        got = oracle.sweep(pl, x0, 1)
+        assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+
+
+def test_relaxed_orthonormal_group_scales_the_residual():
+    """For one group of orthonormal rows the relaxed step leaves the residual
+    (1 - omega) r: ||r_1|| = |1 - omega| ||r_0||."""
+    rng = np.random.default_rng(12)
+    Q, _ = np.linalg.qr(rng.standard_normal((24, 24)))
+    s = synth.from_dense(Q, x_star=rng.standard_normal(24))
+    for om in (0.25, 1.5):
+        pl = oracle.plan_system(s, 1.5, omega=om)
+        x1, inf = oracle.solve_tol(pl, 0.0, 1, 1)
+        assert inf.relres == pytest.approx(abs(1.0 - om) * inf.relres0, rel=1e-10)
+
+
 # ------------------------------------------------- O9: the stopping rule
 def _two_row_case():
     """A = [[1, 1], [0, 1]], x* = (1, 1), f = (2, 1).  RCM reverses the two

@@ -31,17 +31,22 @@ class _Plan:
 class _Batch:
     def __init__(self, plans):
         self.plans = list(plans)
+        self.enabled = [True] * len(self.plans)
         self.freed = False
 
 
 class FakeBackend:
     """relres after k steps = 10**-k; converged when k >= need."""
 
-    def __init__(self, plan_bytes_factor=1.0):
+    def __init__(self, plan_bytes_factor=1.0, fail=()):
         self.live_plans = set()
         self.factor = plan_bytes_factor
+        self.fail = set(fail)           # systems (by id) whose plan raises
+        self.batches = []
 
     def plan(self, system):
+        if id(system) in self.fail:
+            raise RuntimeError("OBK_E_CSR: malformed system")
         p = _Plan(system)
         self.live_plans.add(p)
         return p
@@ -51,7 +56,13 @@ class FakeBackend:
 
     def make_batch(self, plans):
         assert all(not p.freed for p in plans)
-        return _Batch(plans)
+        b = _Batch(plans)
+        self.batches.append(b)
+        return b
+
+    def enable(self, batch, enabled):
+        assert not batch.freed
+        batch.enabled = [bool(e) for e in enabled]
 
     def start(self, batch, i):
         assert batch.plans[i].k is None, "a member was started twice"
@@ -60,10 +71,13 @@ class FakeBackend:
     def step(self, batch, tol):
         assert not batch.freed
         rr, act = [], []
-        for p in batch.plans:
+        for p, en in zip(batch.plans, batch.enabled):
+            # like the library's step, every member's residual is read: its
+            # plan must still exist, enabled or not
+            assert not p.freed, "a batch step read a freed plan"
             assert p.k is not None, "stepped a member that was never started"
             r = 10.0 ** (-min(p.k, p.s.need))
-            a = r > tol
+            a = en and r > tol
             rr.append(r)
             act.append(a)
             if a:
@@ -79,6 +93,7 @@ class FakeBackend:
 
     def free_plan(self, plan):
         assert not plan.freed
+        assert not any(plan in b.plans for b in self.batches if not b.freed), "plan freed under a live batch"
         plan.freed = True
         self.live_plans.discard(plan)
 
@@ -152,3 +167,61 @@ def test_exact_plan_bytes_replace_estimate(factor):
     srv = Server(FakeBackend(plan_bytes_factor=factor), budget_bytes=budget, tol=1e-10, max_steps=3)
     res = srv.run(reqs)
     assert len(res) == 25 and srv.stats["peak_bytes"] <= budget
+
+
+def test_failed_plan_is_reported_and_budget_returned():
+    """A request whose plan raises gets a 'failed' result with the message;
+    its budget comes back and every other request is served."""
+    reqs = _requests(30, seed=5, rate=1e6)
+    bad = {id(reqs[4].system), id(reqs[11].system)}
+    budget = int(max(footprint_estimate(q.system.n, q.system.nnz) for q in reqs) * 3)
+    be = FakeBackend(fail=bad)
+    srv = Server(be, budget_bytes=budget, tol=1e-10, max_steps=12)
+    res = srv.run(reqs)
+    st = {r.rid: r for r in res}
+    assert st[4].status == "failed" and "malformed" in st[4].error and st[11].status == "failed"
+    assert all(r.status in ("converged", "maxit") for r in res if r.rid not in (4, 11))
+    assert srv.stats["failed"] == 2 and not be.live_plans
+
+
+def test_cancellation_leaves_the_others_unchanged():
+    """Cancelling a request mid-flight (queued, planning or being solved)
+    withdraws it with a 'cancelled' result; every other request's result is
+    the one it gets without the cancellation."""
+    reqs = _requests(24, seed=6, rate=1e6)
+    for q in reqs:
+        q.system.need = 14                            # long enough to be caught mid-solve
+    ref = Server(FakeBackend(), budget_bytes=1 << 40, tol=1e-10, max_steps=20).run(reqs)
+
+    class _Cancelling(FakeBackend):
+        def step(self, batch, tol):
+            out = super().step(batch, tol)
+            self.steps = getattr(self, "steps", 0) + 1
+            if self.steps == 3:
+                srv.cancel(5)                         # a member being solved
+                srv.cancel(23)                        # the last one, still queued or planning
+            return out
+
+    be = _Cancelling()
+    srv = Server(be, budget_bytes=1 << 40, tol=1e-10, max_steps=20)
+    res = srv.run(reqs)
+    got = {r.rid: r for r in res}
+    assert got[5].status == "cancelled" and got[23].status == "cancelled"
+    for a in ref:
+        if a.rid in (5, 23):
+            continue
+        b = got[a.rid]
+        assert (b.status, b.steps) == (a.status, a.steps) and np.array_equal(b.x, a.x)
+    assert not be.live_plans and srv.stats["cancelled"] == 2
+
+
+def test_retired_members_are_disabled_not_rebuilt():
+    """Retiring a member disables its slot; the batch is rebuilt only when
+    members join or retired slots outnumber the live ones."""
+    reqs = _requests(40, seed=7, rate=1e6)
+    be = FakeBackend()
+    srv = Server(be, budget_bytes=1 << 40, tol=1e-10, max_steps=30)
+    res = srv.run(reqs)
+    assert all(r.status in ("converged", "maxit") for r in res)
+    retirements = sum(1 for r in res)
+    assert srv.stats["rebuilds"] < retirements
