@@ -245,6 +245,16 @@ OBK_API obk_status obk_plan_bytes(obk_plan_t plan, size_t *device_bytes);
  * contiguous range of the reordered unknowns), or 1 for the per-group phase
  * kernels (*slabs = 0).  Either output may be NULL. */
 OBK_API obk_status obk_plan_engine(obk_plan_t plan, int32_t *engine, int32_t *slabs);
+/* Relaxation bound of one-row groups (the paper steps with omega = 1 and is
+ * silent on relaxation; this is a reading of Section 3.3's grouping): with
+ * B_g the rows of group g scaled to unit norm, per_group[g] is Gershgorin's
+ * bound on lambda_max(B_g B_g^H), 1 + max over the rows i of g of
+ * sum_{j in g, j != i} |cos(a_i, a_j)| (every such cosine is below delta),
+ * and *bound is the largest of them (0 when the plan has no groups).  A group
+ * step with omega * bound <= 2 does not expand the error.  Computed in FP64
+ * at plan time (real and complex plans).  per_group (host, n_groups entries)
+ * or bound may be NULL.  OBK_E_ARG for block-form plans. */
+OBK_API obk_status obk_plan_lambda_bound(obk_plan_t plan, double *bound, double *per_group);
 /* Sizes: n, nnz, number of groups, bandwidth of A~, number of conflicting pairs. */
 OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int32_t *n_groups,
                           int64_t *bandwidth, int64_t *n_conflicts);

@@ -612,3 +612,30 @@ def solve_complex(pl: ComplexPlan, sweeps: int, x0: np.ndarray | None = None) ->
 
 def plan_system_complex(s, delta, **kw) -> ComplexPlan:
     return plan_complex(s.n, s.row_ptr, s.col, s.val, s.f, delta, **kw)
+
+
+# ------------------------------------------- relaxation bound (one-row groups)
+def lambda_bound(pl) -> tuple[float, np.ndarray]:
+    """Gershgorin bound on lambda_max(B_g B_g^H) for every group g, B_g being
+    the rows of g scaled to unit norm: max over the rows i of g of
+    sum_j |(B_g B_g^H)_ij| (the diagonal entry 1 plus the row's cosines).
+
+    The paper is silent on relaxation (it steps with omega = 1); the group
+    step e <- (I - omega B_g^H B_g) e does not expand the error when
+    omega * lambda_max <= 2, which this bound certifies.  The bound of a plan
+    is the largest over its groups (0 with no groups).  Real or complex
+    plans; the product B B^H is a library sparse product."""
+    n = pl.n
+    vals = (pl.vr + 1j * pl.vi) if isinstance(pl, ComplexPlan) else pl.v
+    A = sp.csr_matrix((vals, pl.ci, pl.rp), shape=(n, n))
+    act = pl.group >= 0
+    scale = np.zeros(n)
+    scale[act] = 1.0 / np.sqrt(pl.nu[act])
+    B = sp.diags(scale) @ A
+    C = abs(B @ B.conj().T).tocoo()
+    same = (pl.group[C.row] == pl.group[C.col]) & (pl.group[C.row] >= 0)
+    rowsum = np.zeros(n)
+    np.add.at(rowsum, C.row[same], C.data[same])
+    per = np.zeros(pl.ngroups)
+    np.maximum.at(per, pl.group[act], rowsum[act])
+    return (float(per.max()) if per.size else 0.0), per

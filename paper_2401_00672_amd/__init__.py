@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         L.obk_opts_default.argtypes = [ctypes.POINTER(_Opts)]
         L.obk_plan_engine.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.obk_plan_lambda_bound.argtypes = [_P, ctypes.POINTER(ctypes.c_double), _P]
         L.obk_banded_emulate_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int64, ctypes.c_double, _P, _P]
         L.obk_plan.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
@@ -322,6 +323,15 @@ class Plan:
         e, sl = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().obk_plan_engine(self.handle, ctypes.byref(e), ctypes.byref(sl)))
         return {"engine": "banded" if e.value == 2 else "phases", "slabs": sl.value}
+
+    def lambda_bound(self):
+        """obk_plan_lambda_bound: (plan bound, per-group bounds) on
+        lambda_max(B_g B_g^H), B_g the unit-norm rows of group g."""
+        _, ng = self.groups()
+        per = np.zeros(max(ng, 1), dtype=np.float64)
+        b = ctypes.c_double()
+        _check(lib().obk_plan_lambda_bound(self.handle, ctypes.byref(b), per.ctypes.data))
+        return b.value, per[:ng]
 
     def stats(self) -> dict:
         n, nnz, bw, nc = (ctypes.c_int64() for _ in range(4))

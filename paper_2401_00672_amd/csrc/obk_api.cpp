@@ -15,12 +15,12 @@ namespace obk {
 const char* last_error_cstr();
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s);
 void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
-                hipStream_t s);
+                hipStream_t s, const SolveWs* ws = nullptr);
 void enqueue_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
 int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, obk_kernel_profile* out,
                        int32_t max_out);
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
-                   hipStream_t s);
+                   hipStream_t s, const SolveWs* ws = nullptr);
 void ensure_fp32(obk_plan_s& P, hipStream_t s);
 void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts);
 void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s);
@@ -438,6 +438,18 @@ obk_status obk_plan_stats(obk_plan_t plan, int64_t* n, int64_t* nnz, int32_t* n_
         if (n_groups) *n_groups = plan->ngroups;
         if (bandwidth) *bandwidth = plan->bandwidth;
         if (n_conflicts) *n_conflicts = plan->nconflicts;
+    });
+}
+
+obk_status obk_plan_lambda_bound(obk_plan_t plan, double* bound, double* per_group) {
+    return guarded([&] {
+        if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
+        if (plan->block_form()) obk::fail(OBK_E_ARG, "the bound concerns one-row groups; a block-form plan has none");
+        double b = 0.0;
+        for (double v : plan->h_lambda_bound) b = std::max(b, v);
+        if (bound) *bound = b;
+        if (per_group && !plan->h_lambda_bound.empty())
+            std::memcpy(per_group, plan->h_lambda_bound.data(), plan->h_lambda_bound.size() * sizeof(double));
     });
 }
 

@@ -194,10 +194,12 @@ struct SlabRound {           // items [r * QT, ...) of a phase, entry-major
     int32_t pad;
 };
 struct SlabGroup {           // one group on one slab
-    SlabPhase r, s;
+    SlabPhase r;             // phase R: the own rows of the group
+    SlabPhase s, sb;         // phase S: window columns whose rows are all own rows (s, run
+                             // before the exchange) and those with halo rows (sb, after it)
     int32_t lo_cnt, own_cnt, hi_cnt;   // w window: [lower halo | own rows | upper halo]
     int32_t pre_cnt, suf_cnt;          // own rows published to slab k-1 (first) and k+1 (last)
-    int32_t pad;
+    int32_t xoff;                      // the group's offset in every exchange buffer (same on all slabs)
 };
 struct SlabDesc {            // one slab
     int32_t xlo, xcount;     // x window: reordered columns [xlo, xlo + xcount)
@@ -207,6 +209,12 @@ struct SlabDesc {            // one slab
     int32_t pad;
 };
 constexpr int32_t kSlabMaxGroups = 64;
+
+// Workspace of the no-allocation solve: the residual partials (static
+// device scratch) instead of the plan's.
+struct SolveWs {
+    double* red = nullptr;
+};
 void slab_setup(obk_plan_s& P, const std::vector<int64_t>& hrptr, const std::vector<int32_t>& grow,
                 const std::vector<int32_t>& pos, hipStream_t s);
 void slab_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);
@@ -232,6 +240,7 @@ struct obk_plan_s {
     // host copies (introspection, schedule)
     std::vector<int32_t> h_perm;       // new -> old
     std::vector<int32_t> h_group;      // group of each reordered row (-1 zero row)
+    std::vector<double> h_lambda_bound;   // per group: Gershgorin bound on lambda_max(B_g B_g^T)
     std::vector<int64_t> h_gptr;       // group g = group-major rows [gptr[g], gptr[g+1])
     std::vector<int64_t> h_tptr;       // touched columns of group g: [tptr[g], tptr[g+1])
     std::vector<obk::Tile> h_rtiles, h_stiles;

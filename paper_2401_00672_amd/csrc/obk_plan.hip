@@ -261,6 +261,73 @@ __global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const 
     if (!kFill) count[e] = found;
 }
 
+// ------------------------------------------------- group Gram row sums
+// For the bound on the largest eigenvalue of B_g B_g^T (B_g: the rows of
+// group g scaled to unit norm): one thread per entry (i, c); over every other
+// row j of column c in i's group whose first column shared with row i is c,
+// the sum of |cos(a_i, a_j)| (complex: |a_i^H a_j| / (|a_i| |a_j|)).  Each
+// pair of a row's Gram row is so counted at exactly one of its entries.
+template <bool kCplx>
+__global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
+                            const double* __restrict__ tv, const double* __restrict__ tvi,
+                            const int32_t* __restrict__ trow, const int64_t* __restrict__ cptr,
+                            const int32_t* __restrict__ crow, const double* __restrict__ nu,
+                            const int32_t* __restrict__ group, double* __restrict__ part) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t i = trow[e];
+    const int32_t c = tci[e];
+    const int32_t gi = group[i];
+    double acc = 0.0;
+    if (gi >= 0) {
+        const double nui = nu[i];
+        const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+        for (int64_t s = cptr[c]; s < cptr[c + 1]; s++) {
+            const int32_t j = crow[s];
+            if ((j == i) | (group[j] != gi)) continue;
+            int64_t a = ia0, b = trp[j];
+            const int64_t b1 = trp[j + 1];
+            int32_t first = -1;
+            double dr = 0.0, di = 0.0;
+            while ((a < ia1) & (b < b1)) {
+                const int32_t ca = tci[a], cb = tci[b];
+                if (ca == cb) {
+                    if (first < 0) first = ca;
+                    if (kCplx) {   // conj(a_i) a_j
+                        dr = dr + (tv[a] * tv[b] + tvi[a] * tvi[b]);
+                        di = di + (tv[a] * tvi[b] - tvi[a] * tv[b]);
+                    } else {
+                        dr = dr + tv[a] * tv[b];
+                    }
+                }
+                a += (ca <= cb) ? 1 : 0;
+                b += (cb <= ca) ? 1 : 0;
+            }
+            if (first == c) {
+                const double mag = kCplx ? __dsqrt_rn(dr * dr + di * di) : fabs(dr);
+                acc = acc + mag / __dsqrt_rn(nui * nu[j]);
+            }
+        }
+    }
+    part[e] = acc;
+}
+
+// 1 + the row's sum, folded into its group's maximum (non-negative doubles
+// order as their bit patterns, so the maximum does not depend on the order)
+__global__ void k_group_cos_max(int64_t n, const int64_t* __restrict__ trp, const double* __restrict__ part,
+                                const int32_t* __restrict__ group, unsigned long long* __restrict__ gmax) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || group[i] < 0) return;
+    double r = 1.0;
+    for (int64_t e = trp[i]; e < trp[i + 1]; e++) r = r + part[e];
+    atomicMax(gmax + group[i], (unsigned long long)__double_as_longlong(r));
+}
+
+__global__ void k_zero_u64(int64_t m, unsigned long long* __restrict__ p) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) p[k] = 0ull;
+}
+
 // --------------------------------------------------------------- relayout
 __global__ void k_gm_lengths(int64_t m, const int32_t* __restrict__ grow, const int64_t* __restrict__ trp,
                              int64_t* __restrict__ len) {
@@ -771,6 +838,29 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     DevArray<int32_t> dgrow; to_device(dgrow, grow.data(), m, s);
     DevArray<int32_t> dpos; to_device(dpos, pos_of_row.data(), n, s);
     DevArray<int32_t> dgroup; to_device(dgroup, group.data(), n, s);
+    if (!P.block_form() && G > 0) {
+        // per-group Gershgorin bound on lambda_max(B_g B_g^T)
+        DevArray<double> part; part.alloc(nnz);
+        DevArray<unsigned long long> gmax; gmax.alloc(G);
+        k_zero_u64<<<nblk(G), kT, 0, s>>>(G, gmax.get());
+        if (nnz > 0) {
+            if (cplx)
+                k_group_cos<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(),
+                                                           trow.get(), cptr.get(), crow.get(), nu.get(),
+                                                           dgroup.get(), part.get());
+            else
+                k_group_cos<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), nullptr,
+                                                            trow.get(), cptr.get(), crow.get(), nu.get(),
+                                                            dgroup.get(), part.get());
+            OBK_HIP(hipGetLastError());
+        }
+        k_group_cos_max<<<nblk(n), kT, 0, s>>>(n, trp.get(), part.get(), dgroup.get(), gmax.get());
+        OBK_HIP(hipGetLastError());
+        std::vector<unsigned long long> hm = to_host(gmax.get(), G, s);
+        P.h_lambda_bound.resize(G);
+        for (int32_t g = 0; g < G; g++) std::memcpy(&P.h_lambda_bound[g], &hm[g], sizeof(double));
+        sync_for_free(s);
+    }
     P.rptr.alloc(m + 1);
     k_gm_lengths<<<nblk(m), kT, 0, s>>>(m, dgrow.get(), trp.get(), P.rptr.get());
     OBK_HIP(hipGetLastError());

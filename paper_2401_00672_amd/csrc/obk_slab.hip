@@ -14,11 +14,19 @@
 //   phase R  w_i = (f_i - sum_c a_ic x_c) / ||a_i||^2 for the own rows of g,
 //            x_c read from the LDS window (ascending column order);
 //   exchange the own rows' w that a neighbour needs are published to it,
-//            and the neighbours' w are received (one flag per slab and step);
+//            and the neighbours' w are received (one flag per slab, raised
+//            at each step that publishes);
 //   phase S  x_c = x_c + sum_i w_i a_ic (ascending row order) for every
 //            column of H_k that g touches: own columns, and halo columns,
 //            which the owning neighbour updates identically, so the window
-//            stays exact without a second exchange.
+//            stays exact without a second exchange.  Columns whose rows are
+//            all own rows are updated before the wait for the neighbours,
+//            the others after it.
+// A step exchanges only in the directions that carry rows, except at the
+// first group of every sweep, where every pair of neighbours synchronises:
+// a slab is therefore never more than one sweep ahead of a neighbour, and
+// the exchange buffers, kept per (group, sweep parity), are never
+// overwritten before they are read.
 // Every sum runs in the oracle's order with no contraction, so the iterate
 // equals the per-group phase kernels' and the oracle's bit for bit.
 //
@@ -31,7 +39,8 @@
 //
 // Matrix data are streamed once per phase from a plan-time layout: per
 // (slab, group, phase) a list of items (a row in R, a touched column in S),
-// sorted by length and cut into rounds of kSlabQ * kSlabThreads items whose
+// sorted by length and cut into rounds of Q * kSlabThreads items (Q items
+// per thread: 4 rows in R, 8 columns in S, whose items are shorter) whose
 // entries are stored entry-major (ELL) with 16-bit window indices.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -49,9 +58,9 @@ namespace obk {
 namespace {
 
 constexpr int kSlabThreads = 512;
-constexpr int kSlabQ = 4;                            // items per thread per round
-constexpr int kSlabQT = kSlabQ * kSlabThreads;       // items per round
-constexpr int kSlabKP = 8;                           // entries per pass
+constexpr int kQR = 4, kKPR = 8;                     // phase R: rows per thread per round, entries per pass
+constexpr int kQS = 8, kKPS = 4;                     // phase S: columns per thread per round, entries per pass
+__host__ __device__ constexpr int phase_qt(bool isR) { return (isR ? kQR : kQS) * kSlabThreads; }
 constexpr int kFlagStride = 32;                      // one flag per 128-byte line
 constexpr long kSpinLimit = 1L << 22;                // polls before a wait gives up
 
@@ -81,14 +90,15 @@ __host__ __device__ __forceinline__ CacheLayout cache_layout(bool isR, int32_t c
     return c;
 }
 
-// Registers of one round: per item (kSlabQ per thread) its slot, length,
-// f and 1/||a||^2 (R) and running sum; one pass of kSlabKP entries each.
+// Registers of one round: per item (Q per thread) its slot, length, f and
+// 1/||a||^2 (R) and running sum; one pass of KP entries each.
+template <int Q, int KP>
 struct RoundRegs {
-    bool act[kSlabQ];
-    int tg[kSlabQ], ln[kSlabQ];
-    double fa[kSlabQ], ia[kSlabQ], acc[kSlabQ];
-    int ix[kSlabQ][kSlabKP];
-    double v[kSlabQ][kSlabKP];
+    bool act[Q];
+    int tg[Q], ln[Q];
+    double fa[Q], ia[Q], acc[Q];
+    int ix[Q][KP];
+    double v[Q][KP];
 };
 
 // The global arrays a streamed phase reads its items and entries from.
@@ -101,12 +111,13 @@ struct PhaseSrc {
     const double* val;
 };
 
-template <bool kR>
-__device__ __forceinline__ void round_items(const PhaseSrc& s, const SlabPhase& ph, int r, int nr, RoundRegs& R) {
+template <bool kR, int Q, int KP>
+__device__ __forceinline__ void round_items(const PhaseSrc& s, const SlabPhase& ph, int r, int nr,
+                                            RoundRegs<Q, KP>& R) {
     const int t = threadIdx.x;
-    const int64_t io = ph.item_off + (int64_t)r * kSlabQT;
+    const int64_t io = ph.item_off + (int64_t)r * phase_qt(kR);
 #pragma unroll
-    for (int q = 0; q < kSlabQ; q++) {
+    for (int q = 0; q < Q; q++) {
         const int j = q * kSlabThreads + t;
         R.act[q] = j < nr;
         R.tg[q] = 0;
@@ -125,15 +136,16 @@ __device__ __forceinline__ void round_items(const PhaseSrc& s, const SlabPhase& 
     }
 }
 
+template <int Q, int KP>
 __device__ __forceinline__ void round_entries(const PhaseSrc& s, int64_t ent_off, int K, int nr, int e0,
-                                              RoundRegs& R) {
+                                              RoundRegs<Q, KP>& R) {
     const int t = threadIdx.x;
     const int64_t eo = ent_off;
 #pragma unroll
-    for (int q = 0; q < kSlabQ; q++) {
+    for (int q = 0; q < Q; q++) {
         const int j = q * kSlabThreads + t;
 #pragma unroll
-        for (int e = 0; e < kSlabKP; e++) {
+        for (int e = 0; e < KP; e++) {
             R.ix[q][e] = 0;
             R.v[q][e] = 0.0;
             if (R.act[q] & (e0 + e < K)) {
@@ -145,11 +157,12 @@ __device__ __forceinline__ void round_entries(const PhaseSrc& s, int64_t ent_off
     }
 }
 
-__device__ __forceinline__ void round_accumulate(RoundRegs& R, int e0, const double* src) {
+template <int Q, int KP>
+__device__ __forceinline__ void round_accumulate(RoundRegs<Q, KP>& R, int e0, const double* src) {
 #pragma unroll
-    for (int q = 0; q < kSlabQ; q++)
+    for (int q = 0; q < Q; q++)
 #pragma unroll
-        for (int e = 0; e < kSlabKP; e++)
+        for (int e = 0; e < KP; e++)
             if (e0 + e < R.ln[q]) R.acc[q] = R.acc[q] + R.v[q][e] * src[R.ix[q][e]];
 }
 
@@ -158,17 +171,17 @@ __device__ __forceinline__ void round_accumulate(RoundRegs& R, int e0, const dou
 // w window) at each item's slot; S adds the sum into dst (the x window) at
 // each item's column.  src is the window the entries index (x in R, w in
 // S); the oracle's product a * v commutes exactly.
-template <bool kR>
+template <bool kR, int Q, int KP>
 __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound& rd, int nr, const double* src,
-                                             double* dst, RoundRegs& R, double omega) {
+                                             double* dst, RoundRegs<Q, KP>& R, double omega) {
     const int K = __builtin_amdgcn_readfirstlane(rd.K);
     round_accumulate(R, 0, src);
-    for (int e0 = kSlabKP; e0 < K; e0 += kSlabKP) {
+    for (int e0 = KP; e0 < K; e0 += KP) {
         round_entries(s, rd.ent_off, K, nr, e0, R);
         round_accumulate(R, e0, src);
     }
 #pragma unroll
-    for (int q = 0; q < kSlabQ; q++)
+    for (int q = 0; q < Q; q++)
         if (R.act[q]) {
             if (kR) dst[R.tg[q]] = ((R.fa[q] - R.acc[q]) * R.ia[q]) * omega;
             else dst[R.tg[q]] = dst[R.tg[q]] + R.acc[q];
@@ -179,14 +192,15 @@ __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound&
 // LDS (index minus the slab's first).
 template <bool kR>
 __device__ __forceinline__ void run_phase(const PhaseSrc& s, const SlabPhase& ph, const SlabRound* rounds,
-                                          int32_t round_first, int r0, const double* src, double* dst,
-                                          RoundRegs& R, double omega) {
-    for (int r = r0; r < ph.nrounds; r++) {
+                                          int32_t round_first, const double* src, double* dst, double omega) {
+    constexpr int Q = kR ? kQR : kQS, KP = kR ? kKPR : kKPS;
+    RoundRegs<Q, KP> R;
+    for (int r = 0; r < ph.nrounds; r++) {
         const SlabRound& rd = rounds[ph.round0 + r - round_first];
-        const int nr = min(kSlabQT, ph.count - r * kSlabQT);
-        round_items<kR>(s, ph, r, nr, R);
-        round_entries(s, rd.ent_off, __builtin_amdgcn_readfirstlane(rd.K), nr, 0, R);
-        finish_round<kR>(s, rd, nr, src, dst, R, omega);
+        const int nr = min(phase_qt(kR), ph.count - r * phase_qt(kR));
+        round_items<kR, Q, KP>(s, ph, r, nr, R);
+        round_entries<Q, KP>(s, rd.ent_off, __builtin_amdgcn_readfirstlane(rd.K), nr, 0, R);
+        finish_round<kR, Q, KP>(s, rd, nr, src, dst, R, omega);
     }
 }
 
@@ -207,10 +221,10 @@ __device__ __forceinline__ void run_cached(const char* b, const SlabPhase& ph, c
     const int64_t ebase = ph.nrounds ? rounds[ph.round0 - round_first].ent_off : 0;
     for (int r = 0; r < ph.nrounds; r++) {
         const SlabRound& rd = rounds[ph.round0 + r - round_first];
-        const int nr = min(kSlabQT, ph.count - r * kSlabQT);
+        const int nr = min(phase_qt(kR), ph.count - r * phase_qt(kR));
         const int64_t eo = rd.ent_off - ebase;
         for (int j = t; j < nr; j += kSlabThreads) {
-            const int li = r * kSlabQT + j;
+            const int li = r * phase_qt(kR) + j;
             const int ln = len[li];
             double acc = 0.0;
             for (int e = 0; e < ln; e++) {
@@ -296,33 +310,44 @@ __global__ __launch_bounds__(kSlabThreads) void k_slab_sweeps(SlabArgs a, int64_
     for (int g = 0; g < G; g++) {
         cache_fill<true>(a, cache, gl[g].r, rl, d.round_first);
         cache_fill<false>(a, cache, gl[g].s, rl, d.round_first);
+        cache_fill<false>(a, cache, gl[g].sb, rl, d.round_first);
     }
     __syncthreads();
-    // exchange buffers: [slab][0: prefix for k-1, 1: suffix for k+1][parity]
-    auto buf = [&](int slab, int dir, int par) { return a.xbuf + ((int64_t)(slab * 2 + dir) * 2 + par) * a.cap; };
-    RoundRegs R;
+    // exchange buffers: [slab][0: prefix for k-1, 1: suffix for k+1][sweep parity], each
+    // holding every group's values at the group's offset
+    auto buf = [&](int slab, int dir, int g, int par) {
+        return a.xbuf + (((int64_t)slab * 2 + dir) * 2 + par) * a.cap + gl[g].xoff;
+    };
     for (int64_t sw = 0; sw < sweeps; sw++) {
         for (int g = 0; g < G; g++) {
             const uint32_t step = (uint32_t)(sw * G + g) + 1u;
-            const int par = (int)(step & 1u);
+            const int par = (int)(sw & 1);
             const SlabGroup& gd = gl[g];
             // phase R of the own rows of g
             if (gd.r.cache >= 0) run_cached<true>(cache + gd.r.cache, gd.r, rl, d.round_first, xw, ww, a.omega);
-            else run_phase<true>(global_src(a), gd.r, rl, d.round_first, 0, xw, ww, R, a.omega);
+            else run_phase<true>(global_src(a), gd.r, rl, d.round_first, xw, ww, a.omega);
             __syncthreads();
             // publish: the first pre_cnt own rows to k-1, the last suf_cnt to k+1
-            double* plo = buf(k, 0, par);
-            double* phi = buf(k, 1, par);
-            for (int i = t; i < gd.pre_cnt; i += kSlabThreads) st_agent(plo + i, ww[gd.lo_cnt + i]);
-            for (int i = t; i < gd.suf_cnt; i += kSlabThreads)
-                st_agent(phi + i, ww[gd.lo_cnt + gd.own_cnt - gd.suf_cnt + i]);
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (t == 0)
-                __hip_atomic_store(a.flags + (int64_t)k * kFlagStride, step, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            const bool sync = g == 0;       // every pair of neighbours meets once a sweep
+            const bool send = sync | (gd.pre_cnt > 0) | (gd.suf_cnt > 0);
+            if (send) {
+                double* plo = buf(k, 0, g, par);
+                double* phi = buf(k, 1, g, par);
+                for (int i = t; i < gd.pre_cnt; i += kSlabThreads) st_agent(plo + i, ww[gd.lo_cnt + i]);
+                for (int i = t; i < gd.suf_cnt; i += kSlabThreads)
+                    st_agent(phi + i, ww[gd.lo_cnt + gd.own_cnt - gd.suf_cnt + i]);
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (t == 0)
+                    __hip_atomic_store(a.flags + (int64_t)k * kFlagStride, step, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // the columns whose rows are all own rows need no neighbour
+            if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega);
+            else run_phase<false>(global_src(a), gd.s, rl, d.round_first, ww, xw, a.omega);
             const int nb = (t == 0) ? k - 1 : k + 1;
-            if ((t < 2) & (nb >= 0) & (nb < S)) {
+            const bool need = (t == 0) ? (sync | (gd.lo_cnt > 0)) : (sync | (gd.hi_cnt > 0));
+            if ((t < 2) & (nb >= 0) & (nb < S) & need) {
                 const uint32_t* fl = a.flags + (int64_t)nb * kFlagStride;
                 long spins = 0;
 #pragma clang loop unroll(disable)
@@ -339,17 +364,17 @@ __global__ __launch_bounds__(kSlabThreads) void k_slab_sweeps(SlabArgs a, int64_
             if (bail) return;
             // receive: k-1's suffix before the own rows, k+1's prefix after them
             if (gd.lo_cnt) {
-                const double* src = buf(k - 1, 1, par);
+                const double* src = buf(k - 1, 1, g, par);
                 for (int i = t; i < gd.lo_cnt; i += kSlabThreads) ww[i] = ld_agent(src + i);
             }
             if (gd.hi_cnt) {
-                const double* src = buf(k + 1, 0, par);
+                const double* src = buf(k + 1, 0, g, par);
                 for (int i = t; i < gd.hi_cnt; i += kSlabThreads) ww[gd.lo_cnt + gd.own_cnt + i] = ld_agent(src + i);
             }
             __syncthreads();
-            // phase S over the window columns g touches
-            if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega);
-            else run_phase<false>(global_src(a), gd.s, rl, d.round_first, 0, ww, xw, R, a.omega);
+            // phase S over the window columns with halo rows
+            if (gd.sb.cache >= 0) run_cached<false>(cache + gd.sb.cache, gd.sb, rl, d.round_first, ww, xw, a.omega);
+            else run_phase<false>(global_src(a), gd.sb, rl, d.round_first, ww, xw, a.omega);
             __syncthreads();
         }
     }
@@ -479,13 +504,14 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
         std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.len > y.len; });
         ph.count = (int32_t)items.size();
         ph.round0 = (int32_t)h.rounds.size();
-        ph.nrounds = (int32_t)((items.size() + kSlabQT - 1) / kSlabQT);
+        const int64_t qt = phase_qt(isR);
+        ph.nrounds = (int32_t)((items.size() + qt - 1) / qt);
         ph.item_off = isR ? (int64_t)h.tgt.size() : (int64_t)s_tgt.size();
         ph.ents = 0;
         ph.cache = -1;
         ph.pad = 0;
         for (int32_t r = 0; r < ph.nrounds; r++) {
-            const size_t b = (size_t)r * kSlabQT, e = std::min(items.size(), b + kSlabQT);
+            const size_t b = (size_t)r * qt, e = std::min(items.size(), b + (size_t)qt);
             const int64_t nr = (int64_t)(e - b);
             SlabRound rd;
             rd.K = items[b].len;
@@ -566,10 +592,19 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
                         sidx[q] = (int32_t)(p - wlo);
                         sval[q] = val[e];
                     }
+            // columns whose rows are all own rows (w slots [lo_cnt, lo_cnt + own_cnt))
+            // need no neighbour; the others wait for the exchange
             items.clear();
-            for (int64_t c = 0; c < xc; c++)
-                if (cnt[c + 1] > cnt[c]) items.push_back({(int32_t)(cnt[c + 1] - cnt[c]), (int32_t)c, c});
+            std::vector<Item> bitems;
+            for (int64_t c = 0; c < xc; c++) {
+                if (cnt[c + 1] == cnt[c]) continue;
+                bool own_only = true;
+                for (int64_t q = cnt[c]; q < cnt[c + 1]; q++)
+                    own_only = own_only && sidx[q] >= gd.lo_cnt && sidx[q] < gd.lo_cnt + gd.own_cnt;
+                (own_only ? items : bitems).push_back({(int32_t)(cnt[c + 1] - cnt[c]), (int32_t)c, c});
+            }
             emit(items, false, sidx, sval, cnt, gd.s);
+            emit(bitems, false, sidx, sval, cnt, gd.sb);
         }
         h.desc[k].round_count = (int32_t)h.rounds.size() - h.desc[k].round_first;
         h.meta_bytes = std::max<int64_t>(h.meta_bytes, (int64_t)G * (int64_t)sizeof(SlabGroup) +
@@ -593,6 +628,7 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
             SlabGroup& gd = h.grp[(size_t)k * G + g];
             if (gd.r.count > 0) cand.push_back({cache_layout(true, gd.r.count, gd.r.ents).bytes, &gd.r, true});
             if (gd.s.count > 0) cand.push_back({cache_layout(false, gd.s.count, gd.s.ents).bytes, &gd.s, false});
+            if (gd.sb.count > 0) cand.push_back({cache_layout(false, gd.sb.count, gd.sb.ents).bytes, &gd.sb, false});
         }
         std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) { return x.bytes < y.bytes; });
         int64_t used = 0;
@@ -608,7 +644,9 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
         h.desc[k].cache_bytes = (int32_t)used;
         h.cache_bytes = std::max(h.cache_bytes, used);
     }
-    // publication counts: what each neighbour's window takes from the own rows
+    // publication counts: what each neighbour's window takes from the own
+    // rows; each group's values sit at the same offset in every buffer
+    std::vector<int64_t> gcap(G, 0);
     for (int32_t k = 0; k < S; k++)
         for (int32_t g = 0; g < G; g++) {
             SlabGroup& gd = h.grp[(size_t)k * G + g];
@@ -616,12 +654,21 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
             gd.suf_cnt = k + 1 < S ? h.grp[(size_t)(k + 1) * G + g].lo_cnt : 0;
             if (gd.pre_cnt > gd.own_cnt || gd.suf_cnt > gd.own_cnt)
                 fail(OBK_E_HIP, "banded engine: inconsistent neighbour windows");
-            h.cap = std::max<int64_t>(h.cap, std::max(gd.pre_cnt, gd.suf_cnt));
+            gcap[g] = std::max<int64_t>(gcap[g], std::max(gd.pre_cnt, gd.suf_cnt));
             h.bytes += 16.0 * (gd.pre_cnt + gd.suf_cnt);
         }
+    int64_t total_cap = 0;
+    for (int32_t g = 0; g < G; g++) {
+        for (int32_t k = 0; k < S; k++) h.grp[(size_t)k * G + g].xoff = (int32_t)total_cap;
+        total_cap += gcap[g];
+    }
+    h.cap = std::max<int64_t>(1, total_cap);
     // S items follow the R items in the item arrays
     const int64_t nR = (int64_t)h.tgt.size();
-    for (auto& gd : h.grp) gd.s.item_off += nR;
+    for (auto& gd : h.grp) {
+        gd.s.item_off += nR;
+        gd.sb.item_off += nR;
+    }
     h.tgt.insert(h.tgt.end(), s_tgt.begin(), s_tgt.end());
     h.len.insert(h.len.end(), s_len.begin(), s_len.end());
     if (h.idx.empty()) { h.idx.push_back(0); h.val.push_back(0.0); }
@@ -669,6 +716,7 @@ void slab_emulate(const SlabHost& h, int64_t sweeps, double omega, double* x) {
         for (int32_t g = 0; g < G; g++) {
             fill(k, h.grp[(size_t)k * G + g].r, true);
             fill(k, h.grp[(size_t)k * G + g].s, false);
+            fill(k, h.grp[(size_t)k * G + g].sb, false);
         }
     }
     auto phase = [&](int32_t k, const SlabPhase& ph, bool isR, const std::vector<double>& src,
@@ -681,9 +729,10 @@ void slab_emulate(const SlabHost& h, int64_t sweeps, double omega, double* x) {
         auto rd64 = [&](const char* p, int64_t i) { double v; std::memcpy(&v, p + 8 * i, 8); return v; };
         for (int32_t r = 0; r < ph.nrounds; r++) {
             const SlabRound& rd = rl[k].at(ph.round0 + r - h.desc[k].round_first);
-            const int64_t nr = std::min<int64_t>(kSlabQT, ph.count - (int64_t)r * kSlabQT);
+            const int64_t qt = phase_qt(isR);
+            const int64_t nr = std::min<int64_t>(qt, ph.count - (int64_t)r * qt);
             for (int64_t j = 0; j < nr; j++) {
-                const int64_t it = ph.item_off + (int64_t)r * kSlabQT + j;
+                const int64_t it = ph.item_off + (int64_t)r * qt + j;
                 const int64_t li = it - ph.item_off;
                 const int ln = cached ? rd16(b + c.len, li) : h.len.at(it);
                 double acc = 0.0;
@@ -718,7 +767,10 @@ void slab_emulate(const SlabHost& h, int64_t sweeps, double omega, double* x) {
                 for (int32_t i = 0; i < gd.lo_cnt; i++) ww[k].at(i) = suf.at(k - 1).at(i);
                 for (int32_t i = 0; i < gd.hi_cnt; i++) ww[k].at(gd.lo_cnt + gd.own_cnt + i) = pre.at(k + 1).at(i);
             }
-            for (int32_t k = 0; k < S; k++) phase(k, h.grp[(size_t)k * G + g].s, false, ww[k], xw[k]);
+            for (int32_t k = 0; k < S; k++) {
+                phase(k, h.grp[(size_t)k * G + g].s, false, ww[k], xw[k]);
+                phase(k, h.grp[(size_t)k * G + g].sb, false, ww[k], xw[k]);
+            }
         }
     for (int32_t k = 0; k < S; k++)
         for (int32_t j = 0; j < h.desc[k].own_cnt; j++) x[h.desc[k].xlo + h.desc[k].own_lo + j] = xw[k][h.desc[k].own_lo + j];
@@ -733,7 +785,9 @@ void slab_setup(obk_plan_s& P, const std::vector<int64_t>& hrptr, const std::vec
     (void)pos;
     P.slab_S = 0;
     const int mode = P.opts.sweep_kernel;
-    if (mode == 1 || P.cplx || P.block_form()) return;
+    // FP32 refinement plans sweep with the phase kernels (FP32 arithmetic);
+    // their FP64 sweeps, after a switch of precision, do too
+    if (mode == 1 || P.cplx || P.block_form() || P.opts.precision != OBK_FP64) return;
     auto reject = [&](const std::string& why) {
         if (mode == 2) fail(OBK_E_ARG, "sweep_kernel = 2: the banded engine does not apply: " + why);
     };
@@ -894,7 +948,7 @@ extern "C" obk_status obk_banded_emulate_host(int64_t n, const int64_t* rp, cons
         if (stats) {
             int64_t cached = 0, streamed = 0;
             for (const auto& gd : h.grp)
-                for (const obk::SlabPhase* ph : {&gd.r, &gd.s})
+                for (const obk::SlabPhase* ph : {&gd.r, &gd.s, &gd.sb})
                     if (ph->count > 0) (ph->cache >= 0 ? cached : streamed)++;
             stats[0] = h.S;
             stats[1] = cached;

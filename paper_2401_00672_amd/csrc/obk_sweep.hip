@@ -12,6 +12,8 @@
 #include <hip/hip_ext.h>
 
 #include <chrono>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -29,6 +31,10 @@ double sum_squares(const double* f, const double* nu, int64_t n, bool only_zero_
 namespace {
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0) p[0] = 0;
+}
 
 // x~ = P x^0 over the extended system of size n, where x^0 = [x0; 0] and x0
 // (may be null: 0) holds the caller's n_in unknowns
@@ -176,8 +182,9 @@ static hipGraphExec_t sweep_graph(obk_plan_s& P, const T* rval, const T* rf, con
 
 template <class T>
 static void run_sweeps(obk_plan_s& P, const T* rval, const T* rf, const T* rinv, const T* sval, T* x, T* w,
-                       int64_t sweeps, hipStream_t s) {
+                       int64_t sweeps, hipStream_t s, bool eager = false) {
     if (sweeps <= 0 || P.ngroups == 0) return;
+    if (eager) return enqueue_sweeps_t<T>(P, rval, rf, rinv, sval, x, w, sweeps, s);
     // both graphs of this iterate are captured on its first use, so no later
     // call (whatever its sweep count) captures or instantiates on the host
     hipGraphExec_t chunk = sweep_graph<T>(P, rval, rf, rinv, sval, x, w, kChunk);
@@ -297,20 +304,23 @@ namespace obk {
 // FP64 residual over the plan's R tiles (every active row): r (may be null)
 // receives r_a; *sum_sq gets sum r_a^2 over the active rows, *max_abs max |r_a|,
 // *nonfinite whether any r_a is not finite.  Synchronises the stream.
+// With ws (the no-allocation solve), the partials live in ws->red and the
+// sums come back through a stack buffer instead of the pinned stage.
 static void resid_tiles(const obk_plan_s& P, const double* x, double* r, hipStream_t s, double* sum_sq,
-                        double* max_abs, bool* nonfinite) {
+                        double* max_abs, bool* nonfinite, const SolveWs* ws) {
     const int64_t nt = (int64_t)P.h_rtiles.size();
-    double* psum = P.red.get();
+    double* psum = ws ? ws->red : P.red.get();
     double* pmax = psum + std::max<int64_t>(nt, 1);
     double* out = pmax + std::max<int64_t>(nt, 1);
     int* flag = reinterpret_cast<int*>(out + 4);
-    OBK_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_zero_int<<<1, 64, 0, s>>>(flag);
     if (nt)
         k_resid_tiles<<<(unsigned)nt, kT, 0, s>>>(P.rtiles.get(), P.rptr.get(), P.rcol.get(), P.rval.get(),
                                                   P.rf.get(), x, r, psum, pmax, flag);
     k_sum_max_partials<<<1, 256, 0, s>>>(nt, psum, pmax, out);
     OBK_HIP(hipGetLastError());
-    auto* h = static_cast<double*>(pinned_stage(4 * sizeof(double)));
+    double hstack[4];
+    auto* h = ws ? hstack : static_cast<double*>(pinned_stage(4 * sizeof(double)));
     OBK_HIP(hipMemcpyAsync(h, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipMemcpyAsync(h + 2, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     OBK_HIP(hipStreamSynchronize(s));
@@ -322,11 +332,11 @@ static void resid_tiles(const obk_plan_s& P, const double* x, double* r, hipStre
 }
 
 // relative residual ||f~ - A~ x|| / ||f~|| (synchronises the stream); sets *nonfinite
-double relres(obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
+double relres(obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite, const SolveWs* ws) {
     slab_check(P, s);
     double r2 = 0, mx = 0;
     bool nf = false;
-    resid_tiles(P, x, nullptr, s, &r2, &mx, &nf);
+    resid_tiles(P, x, nullptr, s, &r2, &mx, &nf, ws);
     r2 = r2 + P.zero_rows_f2;
     if (nonfinite) *nonfinite = nf || !std::isfinite(r2);
     if (P.fnorm2 == 0.0) return r2 == 0.0 ? 0.0 : INFINITY;
@@ -334,10 +344,10 @@ double relres(obk_plan_s& P, const double* x, hipStream_t s, bool* nonfinite) {
 }
 
 void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
-                hipStream_t s) {
+                hipStream_t s, const SolveWs* ws) {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t n = P.n;
-    const bool dev = P.input_on_device;
+    const bool dev = P.input_on_device || ws;
     obk_info inf{};
     inf.relres = -1;
     // x~0 = P x0 (Section 3.5 starts from 0)
@@ -354,7 +364,7 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
     k_permute_in<<<nblk(n), 256, 0, s>>>(n, P.n_in, P.perm.get(), x0dev, P.x.get());
     OBK_HIP(hipGetLastError());
     bool nf = false;
-    inf.relres0 = relres(P, P.x.get(), s, &nf);
+    inf.relres0 = relres(P, P.x.get(), s, &nf, ws);
     inf.relres = inf.relres0;
     inf.status = OBK_MAXIT;
     const int64_t every = std::max(1, P.opts.check_every);
@@ -363,17 +373,19 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
     else if (tol > 0 && inf.relres0 <= tol) inf.status = OBK_CONVERGED;
     while (done < maxit && inf.status == OBK_MAXIT) {
         int64_t chunk = (tol > 0) ? std::min(every, maxit - done) : (maxit - done);
-        enqueue_sweeps(P, P.x.get(), chunk, s);
+        if (ws) run_sweeps<double>(P, P.rval.get(), P.rf.get(), P.rinv.get(), P.sval.get(), P.x.get(), P.w.get(),
+                                   chunk, s, true);
+        else enqueue_sweeps(P, P.x.get(), chunk, s);
         done += chunk;
         if (tol > 0) {
             inf.outer_steps++;
-            inf.relres = relres(P, P.x.get(), s, &nf);
+            inf.relres = relres(P, P.x.get(), s, &nf, ws);
             if (nf) inf.status = OBK_NONFINITE_ITERATE;
             else if (inf.relres <= tol) inf.status = OBK_CONVERGED;
             else if (inf.relres > 1e3 * inf.relres0 && inf.relres0 > 0) inf.status = OBK_DIVERGED;
         }
     }
-    if (tol <= 0) inf.relres = relres(P, P.x.get(), s, &nf);
+    if (tol <= 0) inf.relres = relres(P, P.x.get(), s, &nf, ws);
     inf.sweeps = done;
     // x = P^T x~ (Algorithm 4, last step)
     double* xout = x;
@@ -391,10 +403,10 @@ void solve_fp64(obk_plan_s& P, const double* x0, double tol, int64_t maxit, doub
 // sweeps on A d = r / sigma from d = 0; x += sigma d.  Stops when
 // ||r|| / ||f|| <= tol or after maxit refinement steps.
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
-                   hipStream_t s) {
+                   hipStream_t s, const SolveWs* ws) {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t n = P.n, m = P.m;
-    const bool dev = P.input_on_device;
+    const bool dev = P.input_on_device || ws;
     obk_info inf{};
     DevArray<double> x0d, xd;
     const double* x0dev = nullptr;
@@ -411,7 +423,7 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     auto residual = [&](double* rho, double* sigma, bool* nonfinite) {
         double r2 = 0, mx = 0;
         bool nf = false;
-        resid_tiles(P, P.x.get(), P.r64.get(), s, &r2, &mx, &nf);
+        resid_tiles(P, P.x.get(), P.r64.get(), s, &r2, &mx, &nf, ws);
         r2 = r2 + P.zero_rows_f2;
         *sigma = std::max(mx, P.zero_rows_fmax);
         *nonfinite = nf || !std::isfinite(r2);
@@ -429,7 +441,7 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     while (inf.status == OBK_MAXIT && inf.outer_steps < maxit && sigma > 0.0) {
         k_make_rhs<<<nblk(std::max(m, n)), 256, 0, s>>>(m, n, P.r64.get(), sigma, P.b32.get(), P.d32.get());
         run_sweeps<float>(P, P.rval32.get(), P.b32.get(), P.rinv32.get(), P.sval32.get(), P.d32.get(),
-                          P.w32.get(), inner, s);
+                          P.w32.get(), inner, s, ws != nullptr);
         k_update_x<<<nblk(n), 256, 0, s>>>(n, sigma, P.d32.get(), P.x.get());
         OBK_HIP(hipGetLastError());
         inf.outer_steps++;

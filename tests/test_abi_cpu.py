@@ -236,3 +236,13 @@ def test_plan_rejects_bad_option_fields_before_any_gpu_work():
     with pytest.raises(obk.ObkError) as ei:
         obk.plan(s.row_ptr, s.col, s.val, s.f, 0.1, max_group=2)
     assert ei.value.code == -1 and "4096" in str(ei.value)
+
+
+def test_binding_declares_argument_types_of_every_call():
+    """Every library call of the binding that takes arguments has ctypes
+    argument types declared (a float passed without them fails at call time,
+    which only a device run would show)."""
+    src = open(os.path.join(os.path.dirname(HEADER), "..", "paper_2401_00672_amd", "__init__.py")).read()
+    called = set(re.findall(r"lib\(\)\.(obk_\w+)\((?!\))", src))
+    declared = set(re.findall(r"L\.(obk_\w+)\.argtypes", src))
+    assert called <= declared, sorted(called - declared)

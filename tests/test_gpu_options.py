@@ -151,3 +151,41 @@ def test_caller_allocator(kw):
     _say(f"[options] caller allocator {kw}: {al.calls} blocks, {al.bytes} bytes in all, {held} held by the plan "
          f"(plan reports {own})")
     assert np.array_equal(x, y)
+
+
+LAMBDA_CASES = [
+    ("c1", lambda: synth.c1(), 0.1, False),
+    ("c1-companion", lambda: synth.c1(companion=True), 0.1, False),
+    ("stencil64", lambda: synth.c2(grid=64), 0.1, False),
+    ("scattered-20000", lambda: synth.c3(n=20000), 0.1, False),
+    ("random-rows-delta0.4", lambda: synth.random_rows(3000, 6, 11), 0.4, False),
+    ("zero-rows", lambda: synth.from_dense(np.diag([2.0, 0.0, 1.0, 0.0, 3.0])), 0.1, False),
+    ("c1z", lambda: synth.c1z(), 0.1, True),
+    ("c2z-grid64", lambda: synth.c2z(grid=64), 0.1, True),
+    ("stencil-1024-full", lambda: synth.c2(), 0.1, False),
+]
+
+
+@pytest.mark.parametrize("name,maker,delta,cplx", LAMBDA_CASES, ids=[c[0] for c in LAMBDA_CASES])
+def test_lambda_bound_matches_oracle(name, maker, delta, cplx):
+    """obk_plan_lambda_bound: every group's Gershgorin bound on
+    lambda_max(B_g B_g^H) against the oracle's (the same groups: the plans are
+    bit-exact), to 1e-12 relative (the cosines are summed in another order)."""
+    s = maker()
+    po = oracle.plan_system_complex(s, delta) if cplx else oracle.plan_system(s, delta)
+    bo, per_o = oracle.lambda_bound(po)
+    with obk.plan_system(s, delta) as P:
+        b, per = P.lambda_bound()
+        g, ng = P.groups()
+    _say(f"[lambda] {name}: {ng} groups, bound {b:.15f} (oracle {bo:.15f}), max per-group deviation "
+         f"{np.abs(per - per_o).max() if ng else 0.0:.3e}")
+    assert ng == po.ngroups and np.array_equal(g, po.group)
+    assert per.shape == per_o.shape and np.all(np.abs(per - per_o) <= 1e-12 * per_o)
+    assert b == per.max() if ng else b == 0.0
+
+
+def test_lambda_bound_refused_for_block_form():
+    s = synth.c1(n=600)
+    with obk.plan_system(s, 0.1, block_k=8) as P:
+        with pytest.raises(obk.ObkError, match="OBK_E_ARG"):
+            P.lambda_bound()

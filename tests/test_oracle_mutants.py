@@ -104,7 +104,7 @@ def test_pins_catch_mutant(source, name, old, new, tmp_path):
 
 
 # Mistakes planted in the Python half of the oracle (oracle/__init__.py: the
-# block form, its criteria and the non-square extension).
+# block form, its criteria, the non-square extension and the relaxation bound).
 PY_MUTANTS = [
     ("centroid_of_abs_values", "cen[b] = np.asarray(A[bptr[b]:bptr[b + 1]].sum(axis=0))",
      "cen[b] = np.asarray(abs(A[bptr[b]:bptr[b + 1]]).sum(axis=0))"),
@@ -126,6 +126,13 @@ PY_MUTANTS = [
     ("pad_rhs_ones", "f = np.concatenate([f, np.zeros(N - m)])", "f = np.concatenate([f, np.ones(N - m)])"),
     ("stop_status_names_swapped", 'SOLVE_STATUS = {0: "converged", 1: "maxit", 2: "diverged", 3: "nonfinite"}',
      'SOLVE_STATUS = {0: "converged", 1: "diverged", 2: "maxit", 3: "nonfinite"}'),
+    ("lambda_signed_cosines", "C = abs(B @ B.conj().T).tocoo()", "C = (B @ B.conj().T).real.tocoo()"),
+    ("lambda_no_conjugate", "C = abs(B @ B.conj().T).tocoo()", "C = abs(B @ B.T).tocoo()"),
+    ("lambda_rows_not_scaled", "scale[act] = 1.0 / np.sqrt(pl.nu[act])", "scale[act] = 1.0 / pl.nu[act]"),
+    ("lambda_across_groups", "same = (pl.group[C.row] == pl.group[C.col]) & (pl.group[C.row] >= 0)",
+     "same = (pl.group[C.row] >= 0) & (pl.group[C.col] >= 0)"),
+    ("lambda_without_diagonal", "same = (pl.group[C.row] == pl.group[C.col]) & (pl.group[C.row] >= 0)",
+     "same = (pl.group[C.row] == pl.group[C.col]) & (pl.group[C.row] >= 0) & (C.row != C.col)"),
 ]
 
 

@@ -522,6 +522,65 @@ def _two_row_case():
     return synth.from_dense(np.array([[1.0, 1.0], [0.0, 1.0]]), f=np.array([2.0, 1.0]))
 
 
+# ------------------------------------------- relaxation bound (one-row groups)
+def _tri(sign):
+    return sp.csr_matrix(np.array([[2.0, sign, 0.0], [sign, 2.0, sign], [0.0, sign, 2.0]]))
+
+
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+def test_lambda_bound_hand_worked_tridiagonal(sign):
+    """tridiag(s, 2, s): |a_1|^2 = |a_3|^2 = 5, |a_2|^2 = 6, |cos(a_1, a_2)| =
+    |cos(a_2, a_3)| = 4 / sqrt(30) ~ 0.730, |cos(a_1, a_3)| = 1 / 5, whatever
+    the sign s.  delta = 0.75: one group, bound 1 + 8 / sqrt(30) (row 2);
+    delta = 0.5: groups {1, 3} and {2}, bounds 1.2 and 1."""
+    s = synth.from_scipy(_tri(sign))
+    b, per = oracle.lambda_bound(oracle.plan_system(s, 0.75))
+    assert per.size == 1 and b == pytest.approx(1.0 + 8.0 / np.sqrt(30.0), rel=1e-14)
+    b, per = oracle.lambda_bound(oracle.plan_system(s, 0.5))
+    assert np.sort(per) == pytest.approx([1.0, 1.2], rel=1e-14) and b == pytest.approx(1.2, rel=1e-14)
+
+
+def test_lambda_bound_of_orthogonal_rows_is_one():
+    """Rows with disjoint supports (and a zero row): every Gram matrix is the
+    identity, so every bound is exactly 1."""
+    M = np.diag([3.0, -2.0, 0.0, 5.0, 1.5])[[4, 0, 3, 2, 1]]
+    pl = oracle.plan_system(synth.from_dense(M), 0.1)
+    b, per = oracle.lambda_bound(pl)
+    assert pl.ngroups == 1 and b == 1.0 and np.array_equal(per, [1.0])
+
+
+def test_lambda_bound_hand_worked_complex():
+    """a_1 = (1, i, 0), a_2 = (i, 2, 0), a_3 = (0, 1, 1); squared norms 2, 5, 2.
+    |a_1^H a_2| = |i - 2i| = 1, |a_1^H a_3| = |-i| = 1, |a_2^H a_3| = 2, so the
+    cosines are 1/sqrt(10), 1/2 and 2/sqrt(10) (the plain bilinear products
+    would give 3, 1 and 2).  delta = 0.7: one group; the row sums are
+    1 + 1/sqrt(10) + 1/2, 1 + 3/sqrt(10) and 1 + 1/2 + 2/sqrt(10), the last
+    the largest."""
+    M = np.array([[1.0, 1j, 0.0], [1j, 2.0, 0.0], [0.0, 1.0, 1.0]])
+    A = sp.csr_matrix(M)
+    n = 3
+    pl = oracle.plan_complex(n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data,
+                             M @ np.ones(n), 0.7, use_rcm=False)
+    b, per = oracle.lambda_bound(pl)
+    assert pl.ngroups == 1 and b == pytest.approx(1.5 + 2.0 / np.sqrt(10.0), rel=1e-14)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_lambda_bound_bounds_the_largest_eigenvalue(seed):
+    """Gershgorin: per group, lambda_max of the dense B_g B_g^T lies in
+    [1, bound] (the diagonal is 1, the bound is the largest absolute row sum)."""
+    s = synth.random_rows(120, 4, seed)
+    pl = oracle.plan_system(s, 0.3)
+    b, per = oracle.lambda_bound(pl)
+    A = sp.csr_matrix((pl.v, pl.ci, pl.rp), shape=(pl.n, pl.n)).toarray()
+    for g in range(pl.ngroups):
+        rows = np.flatnonzero(pl.group == g)
+        B = A[rows] / np.sqrt(pl.nu[rows])[:, None]
+        lam = np.linalg.eigvalsh(B @ B.T).max()
+        assert 1.0 - 1e-12 <= lam <= per[g] * (1 + 1e-12)
+    assert b == per.max() and b < 1.0 + 0.3 * 12
+
+
 def test_stop_rule_two_row_hand_case():
     """Section 3.5's stopping rule read as relres <= tol: 2^-k / sqrt(5) <= 1e-10
     first at k = 33 (2^-32 / sqrt(5) = 1.04e-10); checked every 5 sweeps it
