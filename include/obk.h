@@ -218,6 +218,23 @@ OBK_API obk_status obk_plan_complex(const obk_csr *A, const double *f, double de
 OBK_API obk_status obk_solve(obk_plan_t plan, const double *x0, double tol, int64_t maxit, double *x,
                      obk_info *info, obk_stream_t stream);
 
+/*
+ * obk_solve without device allocation, for callers that cannot allocate
+ * (code in tight serving loops, or harnesses that forbid hipMalloc): the
+ * same solve as obk_solve on x0 and x in device memory (x0 NULL: 0; x0 and
+ * x hold the caller's unknowns, whatever memory space the plan's CSR came
+ * from), for real plans with one-row blocks (OBK_FP64 or OBK_FP32_IR).  The
+ * sweeps are launched directly (no graph is captured) and the residual's
+ * per-tile partials go to a static device array of 1 MiB, one per GPU,
+ * held until the process ends: a plan of more than 65,528 row tiles of 256
+ * rows is refused with OBK_E_ARG.  Every call on a GPU shares that array,
+ * so calls that overlap on one GPU race; serialise them.  The plan's own
+ * workspace is used as by obk_solve (one solve per plan at a time).
+ * Errors: OBK_E_ARG, OBK_E_BUSY, OBK_E_HIP.
+ */
+OBK_API obk_status obk_solve_noalloc(obk_plan_t plan, const double *x0, double tol, int64_t maxit, double *x,
+                                     obk_info *info, obk_stream_t stream);
+
 /* Release a plan and its device memory.  NULL is a no-op. */
 OBK_API void obk_free(obk_plan_t plan);
 

@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.obk_plan.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
                                ctypes.POINTER(_P)]
         L.obk_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.POINTER(_Info), _P]
+        L.obk_solve_noalloc.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.POINTER(_Info), _P]
         L.obk_free.argtypes = [_P]
         L.obk_free.restype = None
         L.obk_plan_perm.argtypes = [_P, _P]
@@ -237,6 +238,20 @@ class Plan:
             p0 = None if x0h is None else x0h.ctypes.data
             st = _stream(stream)
         _check(lib().obk_solve(self.handle, p0, float(tol), int(maxit), px, ctypes.byref(info), st))
+        return x, Info(info.sweeps, info.outer_steps, info.relres0, info.relres, info.seconds,
+                       STATUS.get(info.status, str(info.status)))
+
+    def solve_noalloc(self, x0=None, tol: float = 0.0, maxit: int = 100, out=None, stream=None):
+        """obk_solve_noalloc: obk_solve on device tensors (x0 None = 0; out, if
+        given, receives x) without any device allocation; real one-row-block
+        plans.  Returns (x, Info)."""
+        import torch
+        info = _Info()
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device="cuda")
+        px = _dev_ptr(x, "float64")
+        p0 = None if x0 is None else _dev_ptr(x0, "float64")
+        st = _stream(stream) or torch.cuda.current_stream().cuda_stream
+        _check(lib().obk_solve_noalloc(self.handle, p0, float(tol), int(maxit), px, ctypes.byref(info), st))
         return x, Info(info.sweeps, info.outer_steps, info.relres0, info.relres, info.seconds,
                        STATUS.get(info.status, str(info.status)))
 

@@ -225,6 +225,19 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
     });
 }
 
+obk_status obk_solve_noalloc(obk_plan_t plan, const double* x0, double tol, int64_t maxit, double* x,
+                             obk_info* info, obk_stream_t stream) {
+    return guarded([&] {
+        if (!plan || !x) obk::fail(OBK_E_ARG, "plan and x must not be NULL");
+        if (maxit < 0 || std::isnan(tol)) obk::fail(OBK_E_ARG, "maxit must be >= 0 and tol a number");
+        if (plan->cplx || plan->block_form())
+            obk::fail(OBK_E_ARG, "obk_solve_noalloc takes real plans with one-row blocks");
+        BusyGuard busy(plan);
+        OBK_HIP(hipSetDevice(plan->device));
+        obk::solve_noalloc(*plan, x0, tol, maxit, x, info, as_hip(stream));
+    });
+}
+
 obk_status obk_plan_set_opts(obk_plan_t plan, const obk_opts* opts) {
     return guarded([&] {
         if (!plan || !opts) obk::fail(OBK_E_ARG, "NULL argument");

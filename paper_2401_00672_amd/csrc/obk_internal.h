@@ -215,6 +215,8 @@ constexpr int32_t kSlabMaxGroups = 64;
 struct SolveWs {
     double* red = nullptr;
 };
+void solve_noalloc(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
+                   hipStream_t s);
 void slab_setup(obk_plan_s& P, const std::vector<int64_t>& hrptr, const std::vector<int32_t>& grow,
                 const std::vector<int32_t>& pos, hipStream_t s);
 void slab_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s);

@@ -463,4 +463,52 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
     if (info) *info = inf;
 }
 
+// ------------------------------------------------- the no-allocation solve
+// Device scratch of the no-allocation solve (obk_solve_noalloc): the
+// residual partials of up to kScratchTiles row tiles and the reduced sums.
+// One copy per GPU, held until the process ends; every call on a GPU uses
+// it, so calls that overlap on one GPU race.  Host code reaches it only
+// through the address hipGetSymbolAddress returns on each device.
+constexpr int64_t kScratchDoubles = int64_t(1) << 17;          // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int64_t kScratchTiles = (kScratchDoubles - 16) / 2;
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch;        // per device: the address of scratch there
+
+// The device address of scratch on the current device (looked up once per
+// device, with that device current).
+static double* scratch_address() {
+    int dev = 0;
+    OBK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(OBK_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    return g_scratch[dev];
+}
+
+// obk_solve on device iterates with no allocation: the residual partials in
+// the static scratch, sweeps launched eagerly (no graph is captured), sums
+// read back through a stack buffer.  The plan's own workspace is used as in
+// obk_solve.
+void solve_noalloc(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
+                   hipStream_t s) {
+    const int64_t nt = (int64_t)P.h_rtiles.size();
+    if (nt > kScratchTiles)
+        fail(OBK_E_ARG, "the plan has " + std::to_string(nt) + " row tiles; the static scratch holds the partials of " +
+                            std::to_string(kScratchTiles));
+    SolveWs ws;
+    ws.red = scratch_address();
+    if (P.opts.precision == OBK_FP32_IR) solve_fp32_ir(P, x0, tol, maxit, x, info, s, &ws);
+    else solve_fp64(P, x0, tol, maxit, x, info, s, &ws);
+}
+
 }  // namespace obk
