@@ -112,9 +112,10 @@ def bench_stencil(args) -> dict:
     s = synth.c2(grid=grid)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = obk.plan_system(s, args.delta)
+    P = obk.plan_system(s, args.delta, sweep_kernel=args.sweep_kernel)
     plan_s = time.perf_counter() - t0
     st = P.stats()
+    eng = P.engine()
     g, ng = P.groups()
     m = int((g >= 0).sum())
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
@@ -153,7 +154,7 @@ def bench_stencil(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"stencil-{grid}x{grid}-symperm-rcm-delta{args.delta}-fp64-sweep",
                    "n": s.n, "nnz": s.nnz, "groups": ng, "bandwidth_after_rcm": st["bandwidth"],
-                   "algorithmic_bytes_per_sweep": B},
+                   "algorithmic_bytes_per_sweep": B, "engine": eng},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "+".join(k["name"] for k in prof), "unit_of_work": "one sweep",
@@ -625,6 +626,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--grid", type=int, default=1024)
     ap.add_argument("--delta", type=float, default=0.1)
+    ap.add_argument("--sweep-kernel", default="auto", choices=["auto", "phases", "banded"],
+                    help="c2: which kernels run the sweeps")
     ap.add_argument("--profile-sweeps", type=int, default=20,
                     help="eager sweeps timed per launch for the dominant-kernel roofline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
