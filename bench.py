@@ -33,6 +33,7 @@ def sweep_bytes(n: int, m: int, nnz: int, touched: int | None = None, sv: int = 
 
 
 REAL_SWEEP_SOURCES = ("obk_sweep_tiles.h", "obk_tile.h")
+BANDED_SOURCES = ("obk_slab.hip",)
 COMPLEX_SWEEP_SOURCES = ("obk_complex.hip", "obk_sweep_tiles.h", "obk_tile.h")
 
 
@@ -46,10 +47,11 @@ def _kernel_source_sha(files=REAL_SWEEP_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_traffic(kernel: str, workload: str, files=REAL_SWEEP_SOURCES):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
-    None when no summary matches the current kernel source."""
+def kernel_traffic(kernel: str, workload: str, files=REAL_SWEEP_SOURCES, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes per launch (or per sweep, key "hbm_bytes_per_sweep") of
+    `kernel` from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a plain copy), or None when no summary
+    matches the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -62,7 +64,7 @@ def kernel_traffic(kernel: str, workload: str, files=REAL_SWEEP_SOURCES):
     if kv.get("kernel_source_sha256_16") != _kernel_source_sha(files) or kv.get("kernel") != kernel:
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -138,7 +140,11 @@ def bench_stencil(args) -> dict:
     sweep_kernel_s = sum(k["seconds"] for k in prof) / args.profile_sweeps
     launches_per_sweep = sum(k["launches"] for k in prof) / args.profile_sweeps
     achieved = B / sweep_kernel_s / 1e9
-    traffic = kernel_traffic("+".join(k["name"] for k in prof), "stencil")
+    if eng["engine"] == "banded":
+        # one launch runs every sweep of a call: the summary is per sweep
+        traffic = kernel_traffic("k_slab_sweeps", "stencil_banded", BANDED_SOURCES, "hbm_bytes_per_sweep")
+    else:
+        traffic = kernel_traffic("+".join(k["name"] for k in prof), "stencil")
     res = {
         "metric": "sweeps/s + GB/s vs HBM peak",
         "value": 1000.0 / ms,
@@ -160,7 +166,7 @@ def bench_stencil(args) -> dict:
                      "kernel": "+".join(k["name"] for k in prof), "unit_of_work": "one sweep",
                      "algorithmic_bytes_per_sweep": B, "kernel_us_per_sweep": sweep_kernel_s * 1e6,
                      "launches_per_sweep": launches_per_sweep, "sweeps_profiled": args.profile_sweeps,
-                     "traffic_unit": "bytes/sweep"},
+                     "traffic_unit": "bytes/sweep" if eng["engine"] == "banded" else "bytes/launch"},
         "sweep_effective": {"formula_bytes_per_sweep": B, "achieved_gbs": sweep_gbs,
                             "frac": sweep_gbs / HBM_PEAK_GBS},
         # per kernel, with the implementation's own bytes per launch (A is read

@@ -313,14 +313,45 @@ __global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const 
 }
 
 // 1 + the row's sum, folded into its group's maximum (non-negative doubles
-// order as their bit patterns, so the maximum does not depend on the order)
-__global__ void k_group_cos_max(int64_t n, const int64_t* __restrict__ trp, const double* __restrict__ part,
-                                const int32_t* __restrict__ group, unsigned long long* __restrict__ gmax) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || group[i] < 0) return;
-    double r = 1.0;
-    for (int64_t e = trp[i]; e < trp[i + 1]; e++) r = r + part[e];
-    atomicMax(gmax + group[i], (unsigned long long)__double_as_longlong(r));
+// order as their bit patterns, so the maximum does not depend on the order).
+// One thread per group-major row: a block whose rows all belong to one group
+// (all but the blocks at group boundaries) reduces in LDS and folds once.
+constexpr int kCosMaxThreads = 256;
+__global__ void __launch_bounds__(kCosMaxThreads)
+k_group_cos_max(int64_t m, const int32_t* __restrict__ grow, const int64_t* __restrict__ trp,
+                const double* __restrict__ part, const int32_t* __restrict__ group,
+                unsigned long long* __restrict__ gmax) {
+    __shared__ unsigned long long red[kCosMaxThreads];
+    __shared__ int g0, uniform;
+    const int t = threadIdx.x;
+    const int64_t a = (int64_t)blockIdx.x * kCosMaxThreads + t;
+    const bool valid = a < m;
+    int32_t g = -1;
+    unsigned long long r = 0ull;
+    if (valid) {
+        const int32_t i = grow[a];
+        g = group[i];
+        double s = 1.0;
+        for (int64_t e = trp[i]; e < trp[i + 1]; e++) s = s + part[e];
+        r = (unsigned long long)__double_as_longlong(s);
+    }
+    if (t == 0) {
+        g0 = g;
+        uniform = 1;
+    }
+    __syncthreads();
+    if (valid && g != g0) uniform = 0;
+    red[t] = r;
+    __syncthreads();
+    if (!uniform) {
+        if (valid) atomicMax(gmax + g, r);
+        return;
+    }
+    for (int w = kCosMaxThreads / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] = red[t] > red[t + w] ? red[t] : red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) atomicMax(gmax + g0, red[0]);
 }
 
 __global__ void k_zero_u64(int64_t m, unsigned long long* __restrict__ p) {
@@ -854,7 +885,9 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
                                                             dgroup.get(), part.get());
             OBK_HIP(hipGetLastError());
         }
-        k_group_cos_max<<<nblk(n), kT, 0, s>>>(n, trp.get(), part.get(), dgroup.get(), gmax.get());
+        if (m > 0)
+            k_group_cos_max<<<(unsigned)((m + kCosMaxThreads - 1) / kCosMaxThreads), kCosMaxThreads, 0, s>>>(
+                m, dgrow.get(), trp.get(), part.get(), dgroup.get(), gmax.get());
         OBK_HIP(hipGetLastError());
         std::vector<unsigned long long> hm = to_host(gmax.get(), G, s);
         P.h_lambda_bound.resize(G);
