@@ -47,7 +47,7 @@ size_t obk_plan_s::device_bytes() const {
            biters.bytes() + blseg.bytes() + d_bfit.bytes() + rvalz.bytes() + svalz.bytes() + rfz.bytes() +
            d_bdirect.bytes() + d_bbw.bytes() + d_boff.bytes() + lfc.bytes() + lfr.bytes() + ldinv.bytes() +
            d_lperm.bytes() + d_lpos.bytes() + sl_desc.bytes() + sl_grp.bytes() + sl_round.bytes() +
-           sl_tgt.bytes() + sl_len.bytes() + sl_idx.bytes() + sl_f.bytes() + sl_inv.bytes() + sl_val.bytes() +
+           sl_tgt.bytes() + sl_len.bytes() + sl_idx.bytes() + sl_f.bytes() + sl_val.bytes() +
            sl_xbuf.bytes() + sl_flags.bytes() + sl_err.bytes();
 }
 

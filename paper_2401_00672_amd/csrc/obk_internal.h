@@ -332,7 +332,7 @@ struct obk_plan_s {
     obk::DevArray<obk::SlabGroup> sl_grp;
     obk::DevArray<obk::SlabRound> sl_round;
     obk::DevArray<uint16_t> sl_tgt, sl_len, sl_idx;
-    obk::DevArray<double> sl_f, sl_inv, sl_val, sl_xbuf;
+    obk::DevArray<double> sl_f, sl_val, sl_xbuf;
     obk::DevArray<uint32_t> sl_flags;
     obk::DevArray<int> sl_err;
 

@@ -39,8 +39,8 @@
 //
 // Matrix data are streamed once per phase from a plan-time layout: per
 // (slab, group, phase) a list of items (a row in R, a touched column in S),
-// sorted by length and cut into rounds of Q * kSlabThreads items (Q items
-// per thread: 4 rows in R, 8 columns in S, whose items are shorter) whose
+// sorted by length and cut into rounds of Q * 448 items (Q items per
+// computing thread: 5 rows in R, 9 columns in S, whose items are shorter) whose
 // entries are stored entry-major (ELL) with 16-bit window indices.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -58,9 +58,13 @@ namespace obk {
 namespace {
 
 constexpr int kSlabThreads = 512;
-constexpr int kQR = 4, kKPR = 8;                     // phase R: rows per thread per round, entries per pass
-constexpr int kQS = 8, kKPS = 4;                     // phase S: columns per thread per round, entries per pass
-__host__ __device__ constexpr int phase_qt(bool isR) { return (isR ? kQR : kQS) * kSlabThreads; }
+// Wave 0 of a workgroup runs the neighbour exchange (publish, wait,
+// receive) while the other waves sweep the interior columns; those waves run
+// every phase.
+constexpr int kCommThreads = 64, kCompThreads = kSlabThreads - kCommThreads;
+constexpr int kQR = 5, kKPR = 6;                     // phase R: rows per thread per round, entries per pass
+constexpr int kQS = 9, kKPS = 4;                     // phase S: columns per thread per round, entries per pass
+__host__ __device__ constexpr int phase_qt(bool isR) { return (isR ? kQR : kQS) * kCompThreads; }
 constexpr int kFlagStride = 32;                      // one flag per 128-byte line
 constexpr long kSpinLimit = 1L << 22;                // polls before a wait gives up
 
@@ -72,17 +76,15 @@ __device__ __forceinline__ double ld_agent(const double* p) {
 }
 
 // Byte layout of a phase copied to the LDS cache (offsets from its block,
-// doubles first so that every array stays aligned): f and 1/||a||^2 per item
-// (R only), the entry values, then the 16-bit item targets, lengths and
-// entry indices.
+// doubles first so that every array stays aligned): f per item (R only), the
+// entry values, then the 16-bit item targets, lengths and entry indices.
 struct CacheLayout {
-    int32_t f, inv, val, tgt, len, idx, bytes;
+    int32_t f, val, tgt, len, idx, bytes;
 };
 __host__ __device__ __forceinline__ CacheLayout cache_layout(bool isR, int32_t count, int32_t ents) {
     CacheLayout c;
     c.f = 0;
-    c.inv = isR ? 8 * count : 0;
-    c.val = isR ? 16 * count : 0;
+    c.val = isR ? 8 * count : 0;
     c.tgt = c.val + 8 * ents;
     c.len = c.tgt + 2 * count;
     c.idx = c.len + 2 * count;
@@ -91,12 +93,13 @@ __host__ __device__ __forceinline__ CacheLayout cache_layout(bool isR, int32_t c
 }
 
 // Registers of one round: per item (Q per thread) its slot, length, f and
-// 1/||a||^2 (R) and running sum; one pass of KP entries each.
+// ||a||^2 (R, summed from the row's entries) and running sum; one pass of
+// KP entries each.
 template <int Q, int KP>
 struct RoundRegs {
     bool act[Q];
     int tg[Q], ln[Q];
-    double fa[Q], ia[Q], acc[Q];
+    double fa[Q], nu[Q], acc[Q];
     int ix[Q][KP];
     double v[Q][KP];
 };
@@ -106,7 +109,6 @@ struct PhaseSrc {
     const uint16_t* tgt;
     const uint16_t* len;
     const double* f;
-    const double* inv;
     const uint16_t* idx;
     const double* val;
 };
@@ -114,24 +116,21 @@ struct PhaseSrc {
 template <bool kR, int Q, int KP>
 __device__ __forceinline__ void round_items(const PhaseSrc& s, const SlabPhase& ph, int r, int nr,
                                             RoundRegs<Q, KP>& R) {
-    const int t = threadIdx.x;
+    const int t = (int)threadIdx.x - kCommThreads;
     const int64_t io = ph.item_off + (int64_t)r * phase_qt(kR);
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        const int j = q * kSlabThreads + t;
+        const int j = q * kCompThreads + t;
         R.act[q] = j < nr;
         R.tg[q] = 0;
         R.ln[q] = 0;
         R.fa[q] = 0.0;
-        R.ia[q] = 0.0;
+        R.nu[q] = 0.0;
         R.acc[q] = 0.0;
         if (R.act[q]) {
             R.tg[q] = s.tgt[io + j];
             R.ln[q] = s.len[io + j];
-            if (kR) {
-                R.fa[q] = s.f[io + j];
-                R.ia[q] = s.inv[io + j];
-            }
+            if (kR) R.fa[q] = s.f[io + j];
         }
     }
 }
@@ -139,11 +138,11 @@ __device__ __forceinline__ void round_items(const PhaseSrc& s, const SlabPhase& 
 template <int Q, int KP>
 __device__ __forceinline__ void round_entries(const PhaseSrc& s, int64_t ent_off, int K, int nr, int e0,
                                               RoundRegs<Q, KP>& R) {
-    const int t = threadIdx.x;
+    const int t = (int)threadIdx.x - kCommThreads;
     const int64_t eo = ent_off;
 #pragma unroll
     for (int q = 0; q < Q; q++) {
-        const int j = q * kSlabThreads + t;
+        const int j = q * kCompThreads + t;
 #pragma unroll
         for (int e = 0; e < KP; e++) {
             R.ix[q][e] = 0;
@@ -157,13 +156,18 @@ __device__ __forceinline__ void round_entries(const PhaseSrc& s, int64_t ent_off
     }
 }
 
-template <int Q, int KP>
+// Phase R also sums each row's ||a||^2 from its entries, in the same order
+// as the plan's norms (ascending column, no contraction).
+template <bool kR, int Q, int KP>
 __device__ __forceinline__ void round_accumulate(RoundRegs<Q, KP>& R, int e0, const double* src) {
 #pragma unroll
     for (int q = 0; q < Q; q++)
 #pragma unroll
         for (int e = 0; e < KP; e++)
-            if (e0 + e < R.ln[q]) R.acc[q] = R.acc[q] + R.v[q][e] * src[R.ix[q][e]];
+            if (e0 + e < R.ln[q]) {
+                R.acc[q] = R.acc[q] + R.v[q][e] * src[R.ix[q][e]];
+                if (kR) R.nu[q] = R.nu[q] + R.v[q][e] * R.v[q][e];
+            }
 }
 
 // The rest of round r once its items and first entry pass are in R: the
@@ -175,20 +179,21 @@ template <bool kR, int Q, int KP>
 __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound& rd, int nr, const double* src,
                                              double* dst, RoundRegs<Q, KP>& R, double omega) {
     const int K = __builtin_amdgcn_readfirstlane(rd.K);
-    round_accumulate(R, 0, src);
+    round_accumulate<kR>(R, 0, src);
     for (int e0 = KP; e0 < K; e0 += KP) {
         round_entries(s, rd.ent_off, K, nr, e0, R);
-        round_accumulate(R, e0, src);
+        round_accumulate<kR>(R, e0, src);
     }
 #pragma unroll
     for (int q = 0; q < Q; q++)
         if (R.act[q]) {
-            if (kR) dst[R.tg[q]] = ((R.fa[q] - R.acc[q]) * R.ia[q]) * omega;
+            if (kR) dst[R.tg[q]] = ((R.fa[q] - R.acc[q]) * (1.0 / R.nu[q])) * omega;
             else dst[R.tg[q]] = dst[R.tg[q]] + R.acc[q];
         }
 }
 
-// Rounds [r0, nrounds) of a streamed phase.  rounds are the slab's rounds in
+// Rounds [r0, nrounds) of a streamed phase (run by the computing threads,
+// t >= kCommThreads).  rounds are the slab's rounds in
 // LDS (index minus the slab's first).
 template <bool kR>
 __device__ __forceinline__ void run_phase(const PhaseSrc& s, const SlabPhase& ph, const SlabRound* rounds,
@@ -214,25 +219,60 @@ __device__ __forceinline__ void run_cached(const char* b, const SlabPhase& ph, c
     const uint16_t* tgt = reinterpret_cast<const uint16_t*>(b + c.tgt);
     const uint16_t* len = reinterpret_cast<const uint16_t*>(b + c.len);
     const double* f = reinterpret_cast<const double*>(b + c.f);
-    const double* inv = reinterpret_cast<const double*>(b + c.inv);
     const uint16_t* idx = reinterpret_cast<const uint16_t*>(b + c.idx);
     const double* val = reinterpret_cast<const double*>(b + c.val);
-    const int t = threadIdx.x;
+    const int t = (int)threadIdx.x - kCommThreads;
     const int64_t ebase = ph.nrounds ? rounds[ph.round0 - round_first].ent_off : 0;
     for (int r = 0; r < ph.nrounds; r++) {
         const SlabRound& rd = rounds[ph.round0 + r - round_first];
         const int nr = min(phase_qt(kR), ph.count - r * phase_qt(kR));
         const int64_t eo = rd.ent_off - ebase;
-        for (int j = t; j < nr; j += kSlabThreads) {
+        for (int j = t; j < nr; j += kCompThreads) {
             const int li = r * phase_qt(kR) + j;
             const int ln = len[li];
-            double acc = 0.0;
+            double acc = 0.0, nu = 0.0;
             for (int e = 0; e < ln; e++) {
                 const int64_t at = eo + (int64_t)e * nr + j;
-                acc = acc + val[at] * src[idx[at]];
+                const double v = val[at];
+                acc = acc + v * src[idx[at]];
+                if (kR) nu = nu + v * v;
             }
-            if (kR) dst[tgt[li]] = ((f[li] - acc) * inv[li]) * omega;
+            if (kR) dst[tgt[li]] = ((f[li] - acc) * (1.0 / nu)) * omega;
             else dst[tgt[li]] = dst[tgt[li]] + acc;
+        }
+    }
+}
+
+// The communication wave's copies, kCommBatch values per lane in flight:
+// LDS to the exchange buffer (publish) and back (receive).
+constexpr int kCommBatch = 16;
+__device__ __forceinline__ void comm_publish(double* dst, const double* src, int n, int t) {
+    for (int base = 0; base < n; base += kCommBatch * kCommThreads) {
+        double v[kCommBatch];
+#pragma unroll
+        for (int m = 0; m < kCommBatch; m++) {
+            const int i = base + m * kCommThreads + t;
+            v[m] = i < n ? src[i] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < kCommBatch; m++) {
+            const int i = base + m * kCommThreads + t;
+            if (i < n) st_agent(dst + i, v[m]);
+        }
+    }
+}
+__device__ __forceinline__ void comm_receive(double* dst, const double* src, int n, int t) {
+    for (int base = 0; base < n; base += kCommBatch * kCommThreads) {
+        double v[kCommBatch];
+#pragma unroll
+        for (int m = 0; m < kCommBatch; m++) {
+            const int i = base + m * kCommThreads + t;
+            v[m] = i < n ? ld_agent(src + i) : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < kCommBatch; m++) {
+            const int i = base + m * kCommThreads + t;
+            if (i < n) dst[i] = v[m];
         }
     }
 }
@@ -252,7 +292,6 @@ struct SlabArgs {
     const uint16_t* tgt;
     const uint16_t* len;
     const double* f;
-    const double* inv;
     const uint16_t* idx;
     const double* val;
     double* xbuf;
@@ -266,7 +305,7 @@ struct SlabArgs {
 };
 
 __device__ __forceinline__ PhaseSrc global_src(const SlabArgs& a) {
-    return PhaseSrc{a.tgt, a.len, a.f, a.inv, a.idx, a.val};
+    return PhaseSrc{a.tgt, a.len, a.f, a.idx, a.val};
 }
 
 // copy a phase's items and entries into its LDS block
@@ -280,10 +319,7 @@ __device__ __forceinline__ void cache_fill(const SlabArgs& a, char* cache, const
     for (int i = threadIdx.x; i < ph.count; i += kSlabThreads) {
         reinterpret_cast<uint16_t*>(b + c.tgt)[i] = a.tgt[ph.item_off + i];
         reinterpret_cast<uint16_t*>(b + c.len)[i] = a.len[ph.item_off + i];
-        if (kR) {
-            reinterpret_cast<double*>(b + c.f)[i] = a.f[ph.item_off + i];
-            reinterpret_cast<double*>(b + c.inv)[i] = a.inv[ph.item_off + i];
-        }
+        if (kR) reinterpret_cast<double*>(b + c.f)[i] = a.f[ph.item_off + i];
     }
     for (int i = threadIdx.x; i < ph.ents; i += kSlabThreads) {
         reinterpret_cast<uint16_t*>(b + c.idx)[i] = a.idx[e0 + i];
@@ -318,63 +354,75 @@ __global__ __launch_bounds__(kSlabThreads) void k_slab_sweeps(SlabArgs a, int64_
     auto buf = [&](int slab, int dir, int g, int par) {
         return a.xbuf + (((int64_t)slab * 2 + dir) * 2 + par) * a.cap + gl[g].xoff;
     };
+    const bool comp = t >= kCommThreads;
     for (int64_t sw = 0; sw < sweeps; sw++) {
         for (int g = 0; g < G; g++) {
             const uint32_t step = (uint32_t)(sw * G + g) + 1u;
             const int par = (int)(sw & 1);
             const SlabGroup& gd = gl[g];
             // phase R of the own rows of g
-            if (gd.r.cache >= 0) run_cached<true>(cache + gd.r.cache, gd.r, rl, d.round_first, xw, ww, a.omega);
-            else run_phase<true>(global_src(a), gd.r, rl, d.round_first, xw, ww, a.omega);
-            __syncthreads();
-            // publish: the first pre_cnt own rows to k-1, the last suf_cnt to k+1
-            const bool sync = g == 0;       // every pair of neighbours meets once a sweep
-            const bool send = sync | (gd.pre_cnt > 0) | (gd.suf_cnt > 0);
-            if (send) {
-                double* plo = buf(k, 0, g, par);
-                double* phi = buf(k, 1, g, par);
-                for (int i = t; i < gd.pre_cnt; i += kSlabThreads) st_agent(plo + i, ww[gd.lo_cnt + i]);
-                for (int i = t; i < gd.suf_cnt; i += kSlabThreads)
-                    st_agent(phi + i, ww[gd.lo_cnt + gd.own_cnt - gd.suf_cnt + i]);
-                __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
-                if (t == 0)
-                    __hip_atomic_store(a.flags + (int64_t)k * kFlagStride, step, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (comp) {
+                if (gd.r.cache >= 0) run_cached<true>(cache + gd.r.cache, gd.r, rl, d.round_first, xw, ww, a.omega);
+                else run_phase<true>(global_src(a), gd.r, rl, d.round_first, xw, ww, a.omega);
             }
-            // the columns whose rows are all own rows need no neighbour
-            if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega);
-            else run_phase<false>(global_src(a), gd.s, rl, d.round_first, ww, xw, a.omega);
-            const int nb = (t == 0) ? k - 1 : k + 1;
-            const bool need = (t == 0) ? (sync | (gd.lo_cnt > 0)) : (sync | (gd.hi_cnt > 0));
-            if ((t < 2) & (nb >= 0) & (nb < S) & need) {
-                const uint32_t* fl = a.flags + (int64_t)nb * kFlagStride;
-                long spins = 0;
+            __syncthreads();
+            if (!comp) {
+                // wave 0: publish the first pre_cnt own rows to k-1 and the last
+                // suf_cnt to k+1, raise the flag, wait for the neighbours' and
+                // receive k-1's suffix before the own rows and k+1's prefix
+                // after them (every pair of neighbours meets at the first group
+                // of a sweep)
+                const bool sync = g == 0;
+                const bool send = sync | (gd.pre_cnt > 0) | (gd.suf_cnt > 0);
+                if (send) {
+                    double* plo = buf(k, 0, g, par);
+                    double* phi = buf(k, 1, g, par);
+                    comm_publish(plo, ww + gd.lo_cnt, gd.pre_cnt, t);
+                    comm_publish(phi, ww + gd.lo_cnt + gd.own_cnt - gd.suf_cnt, gd.suf_cnt, t);
+                    __builtin_amdgcn_s_waitcnt(0);      // the whole wave's stores are done
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // and stay before the flag
+                    if (t == 0)
+                        __hip_atomic_store(a.flags + (int64_t)k * kFlagStride, step, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+                const int nb = (t == 0) ? k - 1 : k + 1;
+                const bool need = (t == 0) ? (sync | (gd.lo_cnt > 0)) : (sync | (gd.hi_cnt > 0));
+                bool late = false;
+                if ((t < 2) & (nb >= 0) & (nb < S) & need) {
+                    const uint32_t* fl = a.flags + (int64_t)nb * kFlagStride;
+                    long spins = 0;
 #pragma clang loop unroll(disable)
-                while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
-                    if (++spins > kSpinLimit) {
+                    while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
+                        if (++spins > kSpinLimit) {
+                            late = true;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the data loads follow the wait
+                if (__any(late)) {
+                    if (t == 0) {
                         atomicOr(a.err, 1);
                         bail = 1;
-                        break;
                     }
-                    __builtin_amdgcn_s_sleep(1);
+                } else {
+                    if (gd.lo_cnt) comm_receive(ww, buf(k - 1, 1, g, par), gd.lo_cnt, t);
+                    if (gd.hi_cnt) comm_receive(ww + gd.lo_cnt + gd.own_cnt, buf(k + 1, 0, g, par), gd.hi_cnt, t);
                 }
+            } else {
+                // the other waves: the columns whose rows are all own rows,
+                // which need no neighbour
+                if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega);
+                else run_phase<false>(global_src(a), gd.s, rl, d.round_first, ww, xw, a.omega);
             }
             __syncthreads();
             if (bail) return;
-            // receive: k-1's suffix before the own rows, k+1's prefix after them
-            if (gd.lo_cnt) {
-                const double* src = buf(k - 1, 1, g, par);
-                for (int i = t; i < gd.lo_cnt; i += kSlabThreads) ww[i] = ld_agent(src + i);
-            }
-            if (gd.hi_cnt) {
-                const double* src = buf(k + 1, 0, g, par);
-                for (int i = t; i < gd.hi_cnt; i += kSlabThreads) ww[gd.lo_cnt + gd.own_cnt + i] = ld_agent(src + i);
-            }
-            __syncthreads();
             // phase S over the window columns with halo rows
-            if (gd.sb.cache >= 0) run_cached<false>(cache + gd.sb.cache, gd.sb, rl, d.round_first, ww, xw, a.omega);
-            else run_phase<false>(global_src(a), gd.sb, rl, d.round_first, ww, xw, a.omega);
+            if (comp) {
+                if (gd.sb.cache >= 0) run_cached<false>(cache + gd.sb.cache, gd.sb, rl, d.round_first, ww, xw, a.omega);
+                else run_phase<false>(global_src(a), gd.sb, rl, d.round_first, ww, xw, a.omega);
+            }
             __syncthreads();
         }
     }
@@ -536,8 +584,8 @@ SlabHost slab_build(int64_t n, int32_t G, const std::vector<int64_t>& gptr, cons
                 h.tgt.push_back((uint16_t)it.tgt);
                 h.len.push_back((uint16_t)it.len);
                 h.f.push_back(rf[it.src]);
-                h.inv.push_back(rinv[it.src]);
-                h.bytes += 20.0;
+                h.inv.push_back(rinv[it.src]);     // kept on the host for the emulation's check
+                h.bytes += 12.0;
             } else {
                 s_tgt.push_back((uint16_t)it.tgt);
                 s_len.push_back((uint16_t)it.len);
@@ -697,10 +745,7 @@ void slab_emulate(const SlabHost& h, int64_t sweeps, double omega, double* x) {
         for (int32_t i = 0; i < ph.count; i++) {
             std::memcpy(b + c.tgt + 2 * i, &h.tgt[ph.item_off + i], 2);
             std::memcpy(b + c.len + 2 * i, &h.len[ph.item_off + i], 2);
-            if (isR) {
-                std::memcpy(b + c.f + 8 * i, &h.f[ph.item_off + i], 8);
-                std::memcpy(b + c.inv + 8 * i, &h.inv[ph.item_off + i], 8);
-            }
+            if (isR) std::memcpy(b + c.f + 8 * i, &h.f[ph.item_off + i], 8);
         }
         for (int32_t i = 0; i < ph.ents; i++) {
             std::memcpy(b + c.idx + 2 * (int64_t)i, &h.idx[e0 + i], 2);
@@ -735,17 +780,22 @@ void slab_emulate(const SlabHost& h, int64_t sweeps, double omega, double* x) {
                 const int64_t it = ph.item_off + (int64_t)r * qt + j;
                 const int64_t li = it - ph.item_off;
                 const int ln = cached ? rd16(b + c.len, li) : h.len.at(it);
-                double acc = 0.0;
+                double acc = 0.0, nu = 0.0;
                 for (int32_t e = 0; e < ln; e++) {
                     const int64_t at = rd.ent_off + (int64_t)e * nr + j;
                     const double v = cached ? rd64(b + c.val, at - ebase) : h.val.at(at);
                     const int ix = cached ? rd16(b + c.idx, at - ebase) : h.idx.at(at);
                     acc = acc + v * src.at(ix);
+                    nu = nu + v * v;
                 }
                 const int tg = cached ? rd16(b + c.tgt, li) : h.tgt.at(it);
                 if (isR) {
                     const double fa = cached ? rd64(b + c.f, li) : h.f.at(it);
-                    const double ia = cached ? rd64(b + c.inv, li) : h.inv.at(it);
+                    const double ia = 1.0 / nu;
+                    // the engine's 1/||a||^2, formed from the row's entries,
+                    // is the plan's (and the oracle's) bit for bit
+                    if (ia != h.inv.at(it))
+                        fail(OBK_E_ARG, "banded engine: a row's 1/||a||^2 differs from the given one");
                     dst.at(tg) = ((fa - acc) * ia) * omega;
                 } else {
                     dst.at(tg) = dst.at(tg) + acc;
@@ -823,7 +873,6 @@ void slab_setup(obk_plan_s& P, const std::vector<int64_t>& hrptr, const std::vec
     upload(P.sl_tgt, h.tgt, s);
     upload(P.sl_len, h.len, s);
     upload(P.sl_f, h.f, s);
-    upload(P.sl_inv, h.inv, s);
     upload(P.sl_idx, h.idx, s);
     upload(P.sl_val, h.val, s);
     P.sl_xbuf.alloc((size_t)h.S * 4 * h.cap);
@@ -851,7 +900,6 @@ static SlabArgs slab_args(obk_plan_s& P) {
     a.tgt = P.sl_tgt.get();
     a.len = P.sl_len.get();
     a.f = P.sl_f.get();
-    a.inv = P.sl_inv.get();
     a.idx = P.sl_idx.get();
     a.val = P.sl_val.get();
     a.xbuf = P.sl_xbuf.get();
