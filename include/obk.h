@@ -522,6 +522,26 @@ OBK_API obk_status obk_banded_emulate_host(int64_t n, const int64_t *rp, const i
                                            const double *f, const double *inv, const int32_t *group,
                                            int32_t ngroups, int32_t slabs, int64_t sweeps, double omega,
                                            double *x, int64_t *stats);
+/*
+ * obk_validate_layout_host: the plan validator (run inside obk_plan /
+ * obk_plan_complex when the environment sets OBK_VALIDATE=1, with the tiles
+ * too) on a one-row-block layout given as host arrays: gptr[G+1] and
+ * grow[m] (the reordered row of each group-major row; each group's rows
+ * ascending), group_of_row[n] (-1: in no group), the group-major CSR
+ * rptr[m+1], rcol, rval; the per-group column segments tptr[G+1], tcol[T]
+ * (ascending per group), sptr[T+1], srow (group-major rows, ascending per
+ * column) and sval.  Complex (cplx = 1): values are (re, im) pairs and the
+ * column copies hold conj(a).  Checks that every active row is laid out once
+ * in its group, that each entry is owned by exactly one column entry of its
+ * group with the same value, and that no two rows of a group have
+ * |cos| >= delta (Section 3.3).  OBK_E_ARG names the first violation
+ * (obk_last_error); OK when the layout holds.
+ */
+OBK_API obk_status obk_validate_layout_host(int64_t n, int32_t n_groups, const int64_t *gptr, const int32_t *grow,
+                                           const int32_t *group_of_row, const int64_t *rptr, const int32_t *rcol,
+                                           const double *rval, const int64_t *tptr, const int32_t *tcol,
+                                           const int64_t *sptr, const int32_t *srow, const double *sval,
+                                           int32_t cplx, double delta);
 OBK_API obk_status obk_first_fit_host(int64_t n, const int64_t *cptr, const int32_t *cidx,
                                       const uint8_t *active, int32_t *group, int32_t *n_groups);
 

@@ -20,7 +20,9 @@ __all__ = ["ObkError", "Plan", "plan", "plan_system", "rcm_host", "first_fit_hos
            "batch_tune", "Batch", "lib", "LIB_PATH", "STATUS", "FP64", "FP32_IR"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libobk.so")
+# OBK_LIB names another build of the same sources (the sanitizer test loads
+# a host-sanitized build this way)
+LIB_PATH = os.environ.get("OBK_LIB") or os.path.join(HERE, "libobk.so")
 
 FP64, FP32_IR = 0, 1
 STATUS = {0: "converged", 1: "maxit", 2: "diverged", 3: "nonfinite"}
@@ -94,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.obk_opts_default.argtypes = [ctypes.POINTER(_Opts)]
         L.obk_plan_engine.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_lambda_bound.argtypes = [_P, ctypes.POINTER(ctypes.c_double), _P]
+        L.obk_validate_layout_host.argtypes = [ctypes.c_int64, ctypes.c_int32] + [_P] * 11 + [ctypes.c_int32,
+                                                                                           ctypes.c_double]
         L.obk_banded_emulate_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int64, ctypes.c_double, _P, _P]
         L.obk_plan.argtypes = [ctypes.POINTER(_Csr), _P, ctypes.c_double, ctypes.POINTER(_Opts), _P,
@@ -512,6 +516,17 @@ def banded_emulate_host(rp, ci, v, f, inv, group, ngroups: int, slabs: int, swee
                                          inv.ctypes.data, group.ctypes.data, int(ngroups), int(slabs), int(sweeps),
                                          float(omega), xo.ctypes.data, st.ctypes.data))
     return xo, {"slabs": int(st[0]), "cached": int(st[1]), "streamed": int(st[2]), "lds_bytes": int(st[3])}
+
+
+def validate_layout_host(n, gptr, grow, group_of_row, rptr, rcol, rval, tptr, tcol, sptr, srow, sval, delta,
+                         cplx: bool = False) -> None:
+    """obk_validate_layout_host: the plan validator on a layout given as host
+    arrays (raises ObkError OBK_E_ARG naming the first violation)."""
+    arrs = [_host(gptr, np.int64), _host(grow, np.int32), _host(group_of_row, np.int32), _host(rptr, np.int64),
+            _host(rcol, np.int32), _host(rval, np.float64), _host(tptr, np.int64), _host(tcol, np.int32),
+            _host(sptr, np.int64), _host(srow, np.int32), _host(sval, np.float64)]
+    ptrs = [a.ctypes.data if a.size else None for a in arrs]
+    _check(lib().obk_validate_layout_host(int(n), len(arrs[0]) - 1, *ptrs, int(bool(cplx)), float(delta)))
 
 
 def first_fit_host(cptr, cidx, active):

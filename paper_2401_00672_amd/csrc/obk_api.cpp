@@ -482,6 +482,22 @@ obk_status obk_rcm_host(int64_t n, const int64_t* gptr, const int32_t* gadj, int
     });
 }
 
+obk_status obk_validate_layout_host(int64_t n, int32_t n_groups, const int64_t* gptr, const int32_t* grow,
+                                   const int32_t* group_of_row, const int64_t* rptr, const int32_t* rcol,
+                                   const double* rval, const int64_t* tptr, const int32_t* tcol, const int64_t* sptr,
+                                   const int32_t* srow, const double* sval, int32_t cplx, double delta) {
+    return guarded([&] {
+        if (n < 0 || n_groups < 0 || !gptr || !rptr || !tptr || !sptr || (n > 0 && !group_of_row) ||
+            (gptr[n_groups] > 0 && (!grow || !rcol || !rval)) || (tptr[n_groups] > 0 && (!tcol || !srow || !sval)))
+            obk::fail(OBK_E_ARG, "bad argument");
+        obk::LayoutView L;
+        L.n = n; L.ngroups = n_groups; L.gptr = gptr; L.grow = grow; L.group_of_row = group_of_row;
+        L.rptr = rptr; L.rcol = rcol; L.rval = rval; L.tptr = tptr; L.tcol = tcol; L.sptr = sptr; L.srow = srow;
+        L.sval = sval; L.cplx = cplx != 0; L.sval_conj = cplx != 0; L.delta = delta;
+        obk::validate_layout(L);
+    });
+}
+
 obk_status obk_first_fit_host(int64_t n, const int64_t* cptr, const int32_t* cidx, const uint8_t* active,
                               int32_t* group, int32_t* n_groups) {
     return guarded([&] {

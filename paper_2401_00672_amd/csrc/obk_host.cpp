@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -247,6 +248,129 @@ void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Til
         out.push_back(t);
         s = e;
     }
+}
+
+// The plan validator: the group-major layout of a one-row-block plan against
+// its definition (Section 3.3 grouping, eq. 3.3 sweep data).  Throws an Error
+// (OBK_E_ARG) naming the first violation.
+void validate_layout(const LayoutView& L) {
+    auto bad = [](const std::string& why) { fail(OBK_E_ARG, "plan validator: " + why); };
+    const int64_t n = L.n;
+    const int32_t G = L.ngroups;
+    if (G < 0 || !L.gptr || L.gptr[0] != 0) bad("group offsets do not start at 0");
+    for (int32_t g = 0; g < G; g++)
+        if (L.gptr[g + 1] < L.gptr[g]) bad("group offsets decrease at group " + std::to_string(g));
+    const int64_t m = L.gptr[G];
+    // 1. every active row exactly once, in its group, ascending within it
+    std::vector<uint8_t> seen(n, 0);
+    for (int32_t g = 0; g < G; g++)
+        for (int64_t a = L.gptr[g]; a < L.gptr[g + 1]; a++) {
+            const int64_t r = L.grow[a];
+            if (r < 0 || r >= n) bad("group-major row " + std::to_string(a) + " names row " + std::to_string(r));
+            if (L.group_of_row[r] != g)
+                bad("row " + std::to_string(r) + " is laid out in group " + std::to_string(g) + " but belongs to " +
+                    std::to_string(L.group_of_row[r]));
+            if (a > L.gptr[g] && L.grow[a - 1] >= r) bad("rows of group " + std::to_string(g) + " not ascending");
+            if (seen[r]++) bad("row " + std::to_string(r) + " laid out twice");
+        }
+    for (int64_t r = 0; r < n; r++)
+        if (L.group_of_row[r] >= 0 && !seen[r]) bad("active row " + std::to_string(r) + " missing");
+    // 2. rows: columns ascending, in range
+    if (L.rptr[0] != 0) bad("row offsets do not start at 0");
+    for (int64_t a = 0; a < m; a++) {
+        if (L.rptr[a + 1] <= L.rptr[a]) bad("group-major row " + std::to_string(a) + " has no entry");
+        for (int64_t e = L.rptr[a]; e < L.rptr[a + 1]; e++) {
+            if (L.rcol[e] < 0 || L.rcol[e] >= n) bad("column out of range in row " + std::to_string(a));
+            if (e > L.rptr[a] && L.rcol[e] <= L.rcol[e - 1]) bad("columns of row " + std::to_string(a) + " not ascending");
+        }
+    }
+    const int vs = L.cplx ? 2 : 1;
+    auto rv = [&](int64_t e, int part) { return L.rval[vs * e + part]; };
+    // 3. the per-group columns: every entry of a group's rows owned by exactly
+    // one segment entry, with the same value (conjugated where stored so)
+    const int64_t T = L.tptr[G];
+    const int64_t me = L.sptr[T];
+    std::vector<uint8_t> used(me, 0);
+    for (int32_t g = 0; g < G; g++) {
+        const int64_t s0 = L.tptr[g], s1 = L.tptr[g + 1];
+        if (s1 < s0) bad("segment offsets decrease at group " + std::to_string(g));
+        for (int64_t sg = s0; sg < s1; sg++) {
+            if (sg > s0 && L.tcol[sg] <= L.tcol[sg - 1]) bad("columns of group " + std::to_string(g) + " not ascending");
+            for (int64_t k = L.sptr[sg]; k < L.sptr[sg + 1]; k++) {
+                if (L.srow[k] < L.gptr[g] || L.srow[k] >= L.gptr[g + 1])
+                    bad("segment of group " + std::to_string(g) + " holds a row of another group");
+                if (k > L.sptr[sg] && L.srow[k] <= L.srow[k - 1]) bad("rows of a segment not ascending");
+            }
+        }
+        for (int64_t a = L.gptr[g]; a < L.gptr[g + 1]; a++)
+            for (int64_t e = L.rptr[a]; e < L.rptr[a + 1]; e++) {
+                const int32_t c = L.rcol[e];
+                const int32_t* tb = L.tcol + s0;
+                const int32_t* te = L.tcol + s1;
+                const int32_t* it = std::lower_bound(tb, te, c);
+                if (it == te || *it != c)
+                    bad("entry (" + std::to_string(a) + ", " + std::to_string(c) + ") has no column segment");
+                const int64_t sg = s0 + (it - tb);
+                const int32_t* rb = L.srow + L.sptr[sg];
+                const int32_t* re = L.srow + L.sptr[sg + 1];
+                const int32_t* jt = std::lower_bound(rb, re, (int32_t)a);
+                if (jt == re || *jt != a)
+                    bad("entry (" + std::to_string(a) + ", " + std::to_string(c) + ") missing from its column");
+                const int64_t k = L.sptr[sg] + (jt - rb);
+                if (used[k]++) bad("a column entry is owned twice");
+                const double sr = L.sval[vs * k], si = L.cplx ? L.sval[vs * k + 1] : 0.0;
+                const double er = rv(e, 0), ei = L.cplx ? rv(e, 1) : 0.0;
+                if (sr != er || si != (L.sval_conj ? -ei : ei))
+                    bad("entry (" + std::to_string(a) + ", " + std::to_string(c) + ") has another value in its column");
+            }
+    }
+    for (int64_t k = 0; k < me; k++)
+        if (!used[k]) bad("a column entry belongs to no row entry");
+    // 4. no two rows of a group conflict: |cos| < delta for every pair that
+    // shares a column (the others are orthogonal)
+    std::vector<double> nu(m, 0.0);
+    for (int64_t a = 0; a < m; a++)
+        for (int64_t e = L.rptr[a]; e < L.rptr[a + 1]; e++)
+            nu[a] = nu[a] + (rv(e, 0) * rv(e, 0) + (L.cplx ? rv(e, 1) * rv(e, 1) : 0.0));
+    for (int64_t sg = 0; sg < T; sg++)
+        for (int64_t i = L.sptr[sg]; i < L.sptr[sg + 1]; i++)
+            for (int64_t j = i + 1; j < L.sptr[sg + 1]; j++) {
+                const int64_t a = L.srow[i], b = L.srow[j];
+                double dr = 0.0, di = 0.0;
+                int64_t p = L.rptr[a], q = L.rptr[b];
+                while (p < L.rptr[a + 1] && q < L.rptr[b + 1]) {
+                    if (L.rcol[p] == L.rcol[q]) {
+                        dr = dr + (rv(p, 0) * rv(q, 0) + (L.cplx ? rv(p, 1) * rv(q, 1) : 0.0));
+                        if (L.cplx) di = di + (rv(p, 0) * rv(q, 1) - rv(p, 1) * rv(q, 0));
+                        p++, q++;
+                    } else if (L.rcol[p] < L.rcol[q]) {
+                        p++;
+                    } else {
+                        q++;
+                    }
+                }
+                const double cs = std::sqrt(dr * dr + di * di) / std::sqrt(nu[a] * nu[b]);
+                if (!(cs < L.delta))
+                    bad("group-major rows " + std::to_string(a) + " and " + std::to_string(b) +
+                        " share a group with |cos| = " + std::to_string(cs) + " >= delta");
+            }
+    // 5. tiles cover each group's rows (columns) once, in order
+    auto cover = [&](const Tile* tl, const int32_t* tp, const int64_t* seg, const int64_t* off, const char* what) {
+        if (!tl || !tp) return;
+        for (int32_t g = 0; g < G; g++) {
+            int64_t at = seg[g];
+            for (int32_t t = tp[g]; t < tp[g + 1]; t++) {
+                if (tl[t].seg_begin != at || tl[t].seg_end <= tl[t].seg_begin)
+                    bad(std::string(what) + " tiles of group " + std::to_string(g) + " leave a gap or overlap");
+                if (tl[t].ent_begin != off[tl[t].seg_begin] || tl[t].ent_end != off[tl[t].seg_end])
+                    bad(std::string(what) + " tile entry range differs from its segments");
+                at = tl[t].seg_end;
+            }
+            if (at != seg[g + 1]) bad(std::string(what) + " tiles of group " + std::to_string(g) + " stop short");
+        }
+    };
+    cover(L.rtiles, L.rtile_ptr, L.gptr, L.rptr, "row");
+    cover(L.stiles, L.stile_ptr, L.tptr, L.sptr, "column");
 }
 
 }  // namespace obk

@@ -141,6 +141,32 @@ int32_t host_first_fit(int64_t n, const int64_t* cptr, const int32_t* cidx, cons
 // kTileEntries entries.
 void build_tiles(int64_t seg0, int64_t seg1, const int64_t* off, std::vector<Tile>& out);
 
+// The group-major layout of a one-row-block plan, as host arrays, for the
+// plan validator.  rval/sval: one value per entry, or (re, im) pairs when
+// cplx; sval_conj: the column copies hold conj(a).  Tiles may be null.
+struct LayoutView {
+    int64_t n = 0;
+    int32_t ngroups = 0;
+    const int64_t* gptr = nullptr;        // [G+1] group-major rows of each group
+    const int32_t* grow = nullptr;        // [m] reordered row of each group-major row
+    const int32_t* group_of_row = nullptr;   // [n] group of each reordered row (-1: none)
+    const int64_t* rptr = nullptr;        // [m+1]
+    const int32_t* rcol = nullptr;
+    const double* rval = nullptr;
+    const int64_t* tptr = nullptr;        // [G+1] column segments of each group
+    const int32_t* tcol = nullptr;        // [T]
+    const int64_t* sptr = nullptr;        // [T+1]
+    const int32_t* srow = nullptr;        // group-major row of each column entry
+    const double* sval = nullptr;
+    bool cplx = false, sval_conj = false;
+    double delta = 0.0;
+    const Tile* rtiles = nullptr;
+    const int32_t* rtile_ptr = nullptr;   // [G+1]
+    const Tile* stiles = nullptr;
+    const int32_t* stile_ptr = nullptr;   // [G+1]
+};
+void validate_layout(const LayoutView& L);
+
 }  // namespace obk
 
 struct obk_plan_s;

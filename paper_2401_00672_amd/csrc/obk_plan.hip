@@ -974,6 +974,29 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     to_device(P.d_stile_ptr, P.h_stile_ptr.data(), P.h_stile_ptr.size(), s);
 
     tr.mark("tiles");
+    // OBK_VALIDATE=1: check the layout against its definition (host, slow)
+    const char* val_env = std::getenv("OBK_VALIDATE");
+    if (val_env && std::string(val_env) == "1" && !P.block_form()) {
+        const int64_t ne = hrptr[m], me_ = hsptr[T];
+        std::vector<int32_t> hrcol = to_host(P.rcol.get(), ne, s);
+        std::vector<double> hrval = cplx ? to_host(P.rvalz.get(), 2 * ne, s) : to_host(P.rval.get(), ne, s);
+        std::vector<int32_t> htcol = to_host(P.tcol.get(), T, s);
+        std::vector<int32_t> hsrow = to_host(P.srow.get(), me_, s);
+        std::vector<double> hsval = cplx ? to_host(P.svalz.get(), 2 * me_, s) : to_host(P.sval.get(), me_, s);
+        LayoutView L;
+        L.n = n; L.ngroups = G; L.gptr = P.h_gptr.data(); L.grow = grow.data(); L.group_of_row = P.h_group.data();
+        L.rptr = hrptr.data(); L.rcol = hrcol.data(); L.rval = hrval.data();
+        L.tptr = P.h_tptr.data(); L.tcol = htcol.data(); L.sptr = hsptr.data(); L.srow = hsrow.data();
+        L.sval = hsval.data(); L.cplx = cplx; L.sval_conj = cplx; L.delta = delta;
+        L.rtiles = P.h_rtiles.data(); L.rtile_ptr = P.h_rtile_ptr.data();
+        L.stiles = P.h_stiles.data(); L.stile_ptr = P.h_stile_ptr.data();
+        try {
+            validate_layout(L);
+        } catch (const Error& e) {
+            fail(OBK_E_HIP, e.msg);
+        }
+        tr.mark("validate");
+    }
     if (!cplx && !P.block_form()) slab_setup(P, hrptr, grow, pos_of_row, s);
     tr.mark("banded_engine");
     if (P.block_form()) {

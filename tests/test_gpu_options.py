@@ -189,3 +189,16 @@ def test_lambda_bound_refused_for_block_form():
     with obk.plan_system(s, 0.1, block_k=8) as P:
         with pytest.raises(obk.ObkError, match="OBK_E_ARG"):
             P.lambda_bound()
+
+
+def test_plan_validator_passes_on_device_plans(monkeypatch):
+    """OBK_VALIDATE=1: every plan's group-major layout, column segments and
+    tiles are checked on the host against their definition (no two rows of a
+    group with |cos| >= delta, every entry owned once) inside obk_plan."""
+    monkeypatch.setenv("OBK_VALIDATE", "1")
+    cases = [(synth.c1(), 0.1, {}), (synth.c2(grid=64), 0.1, {}), (synth.c3(n=20000), 0.1, {}),
+             (synth.c1(n=3000, companion=True), 0.1, dict(precision=obk.FP32_IR)), (synth.c1z(), 0.1, {}),
+             (synth.random_rows(2000, 6, 12), 0.4, {})]
+    for s, delta, kw in cases:
+        with obk.plan_system(s, delta, **kw) as P:
+            _say(f"[validate] {s.name}: {P.stats()['groups']} groups, layout valid")
