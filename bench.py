@@ -446,9 +446,77 @@ def run_batched(count: int, delta: float, inner: int, check_every: int, oracle_s
     }
 
 
+def _make_request(job):
+    """Worker: one request system of the serving (c5) or batched (c4) family."""
+    import synth
+    kind, i, n = job
+    return synth.c5_system(i, n=n) if kind == "c5" else synth.c4_system(i, n=n, companion=True)
+
+
+def make_requests(kind: str, sizes, workers: int) -> list:
+    """The systems of `sizes`, generated in order by `workers` processes
+    (spawned: none of them touches the GPU)."""
+    import multiprocessing as mp
+    jobs = [(kind, i, int(n)) for i, n in enumerate(sizes)]
+    if workers <= 1 or len(jobs) < 64:
+        return [_make_request(j) for j in jobs]
+    out = []
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for s in pool.imap(_make_request, jobs, chunksize=8):
+            out.append(s)
+            if len(out) % 512 == 0:
+                _log(f"[{kind}] generated {len(out)}/{len(jobs)} requests")
+    return out
+
+
+def _oracle_request(job):
+    """Worker: the oracle's FP64 plan + solve to `tol` of one request, on one
+    thread; returns (seconds, status)."""
+    import oracle
+    kind, i, n, delta, tol, check_every = job
+    oracle.set_threads(1)
+    s = _make_request((kind, i, n))
+    t0 = time.perf_counter()
+    pl = oracle.plan_system(s, delta)
+    _, info = oracle.solve_tol(pl, tol, 200000, check_every)
+    return time.perf_counter() - t0, info.status
+
+
+def cpu_baseline_requests(kind: str, sizes, delta: float, check_every: int, budget_s: float, workers: int) -> dict:
+    """The oracle solving independent requests in parallel, one request per
+    core (FP64 plan + plain FP64 sweeps to relative residual 1e-10, residual
+    checked every `check_every` sweeps): the requests are taken in order in
+    rounds of `workers` until `budget_s` has passed; solves/s over the rounds
+    run."""
+    import multiprocessing as mp
+    done, statuses = 0, []
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_make_request, [(kind, 0, 500)] * workers)           # start the workers
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(sizes) and time.perf_counter() - t0 < budget_s:
+            jobs = [(kind, j, int(sizes[j]), delta, 1e-10, check_every) for j in range(i, min(i + workers, len(sizes)))]
+            for sec, st in pool.map(_oracle_request, jobs, chunksize=1):
+                statuses.append(st)
+            done += len(jobs)
+            i += len(jobs)
+    wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"the first {done} requests of the workload (n {int(min(sizes[:done]))}..{int(max(sizes[:done]))}), "
+                      f"{workers} at a time, one per process on one thread: FP64 oracle plan + sweeps to 1e-10 "
+                      f"({sum(1 for x in statuses if x == 'converged')} converged) in {wall:.1f} s"}
+
+
 def bench_batched(args) -> dict:
     """The batched configuration at its stated size (512 systems)."""
+    import synth
     r = run_batched(args.systems, args.delta, args.inner, args.check_every, 8)
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("[c4] CPU baseline: the oracle on independent systems, one per core")
+        cpu = cpu_baseline_requests("c4", synth.c4_sizes(512)[:args.systems], args.delta, args.check_every,
+                                    args.cpu_budget, min(16, os.cpu_count() or 1))
     return {
         "metric": "solves/s to rel. residual 1e-10",
         "value": r["solves_per_s"],
@@ -462,6 +530,7 @@ def bench_batched(args) -> dict:
                    "tuned": r["tuned"]},
         **{k: r[k] for k in ("converged", "seconds_batched", "baseline_plain_fp64_loop",
                              "speedup_vs_plain_fp64_loop", "error_vs_fp64_oracle", "plan_seconds_total")},
+        "cpu_baseline": cpu,
     }
 
 
@@ -479,9 +548,9 @@ def bench_serving(args) -> dict:
     from paper_2401_00672_amd.serve import LibobkBackend, Request, Server, latency_summary
 
     count = args.requests
-    sizes = synth.c5_sizes(count)
+    sizes = synth.c5_sizes(8192)[:count]
     t0 = time.perf_counter()
-    systems = [synth.c5_system(i, n=int(n)) for i, n in enumerate(sizes)]
+    systems = make_requests("c5", sizes, min(16, os.cpu_count() or 1))
     _log(f"[c5] generated {count} requests in {time.perf_counter() - t0:.1f} s "
          f"(mean n {sizes.mean():.0f}, total nnz {sum(s.nnz for s in systems)})")
     budget = int(args.budget_gib * (1 << 30))
@@ -493,7 +562,8 @@ def bench_serving(args) -> dict:
 
     def serve(arrivals):
         reqs = [Request(i, float(arrivals[i]), systems[i]) for i in range(count)]
-        srv = Server(be, budget, tol=1e-10, max_steps=args.max_steps, planners=args.planners)
+        srv = Server(be, budget, tol=1e-10, max_steps=args.max_steps, planners=args.planners,
+                     progress=lambda k, n: _log(f"[c5] served {k}/{n}"), progress_every=512)
         ts = time.perf_counter()
         res = srv.run(reqs)
         span = time.perf_counter() - ts
@@ -523,12 +593,19 @@ def bench_serving(args) -> dict:
             _, inf = P.solve(maxit=20000, tol=1e-10)
         service.append(time.perf_counter() - tb)
         base_conv += inf.status == "converged"
+        if (i + 1) % 512 == 0:
+            _log(f"[c5] FIFO baseline {i + 1}/{count}")
     free_at, base_lat = 0.0, []
     for a, sv in zip(arrivals, service):
         start = max(a, free_at)
         free_at = start + sv
         base_lat.append(free_at - a)
     base_lat = np.array(base_lat)
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("[c5] CPU baseline: the oracle on independent requests, one per core")
+        cpu = cpu_baseline_requests("c5", sizes, args.delta, args.check_every, args.cpu_budget,
+                                    min(16, os.cpu_count() or 1))
     return {
         "metric": "solves/s and p50/p99 latency to rel. residual 1e-10 (continuous batching)",
         "value": count / makespan,
@@ -548,6 +625,7 @@ def bench_serving(args) -> dict:
                                      "p50_s": float(np.percentile(base_lat, 50)),
                                      "p99_s": float(np.percentile(base_lat, 99)),
                                      "mean_service_s": float(np.mean(service))},
+        "cpu_baseline": cpu,
     }
 
 

@@ -145,7 +145,8 @@ class Server:
     """Continuous batching with FIFO admission under an HBM budget."""
 
     def __init__(self, backend, budget_bytes: int, tol: float = 1e-10, max_steps: int = 200,
-                 planners: int = 2, clock=time.perf_counter, idle_wait: float = 0.002):
+                 planners: int = 2, clock=time.perf_counter, idle_wait: float = 0.002, progress=None,
+                 progress_every: int = 0):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.tol = float(tol)
@@ -153,6 +154,8 @@ class Server:
         self.planners = int(planners)
         self.clock = clock
         self.idle_wait = idle_wait
+        self.progress = progress                 # called with (finished, total) every progress_every results
+        self.progress_every = int(progress_every)
         self.stats = {"steps": 0, "rebuilds": 0, "peak_bytes": 0, "peak_members": 0, "step_seconds": 0.0,
                       "rebuild_seconds": 0.0, "failed": 0, "cancelled": 0}
         self._cancel_lock = threading.Lock()
@@ -185,6 +188,8 @@ class Server:
             results[r.rid] = Result(r.rid, x, r.arrival, admitted, now(), steps, relres, status, err)
             if status in ("failed", "cancelled"):
                 self.stats[status] += 1
+            if self.progress and self.progress_every > 0 and len(results) % self.progress_every == 0:
+                self.progress(len(results), len(reqs))
 
         try:
             while len(results) < len(reqs):
