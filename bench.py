@@ -563,7 +563,8 @@ def bench_serving(args) -> dict:
     def serve(arrivals):
         reqs = [Request(i, float(arrivals[i]), systems[i]) for i in range(count)]
         srv = Server(be, budget, tol=1e-10, max_steps=args.max_steps, planners=args.planners,
-                     progress=lambda k, n: _log(f"[c5] served {k}/{n}"), progress_every=512)
+                     progress=lambda k, n: _log(f"[c5] served {k}/{n}"), progress_every=512,
+                     reuse_batch=not args.c5_new_batch_objects)
         ts = time.perf_counter()
         res = srv.run(reqs)
         span = time.perf_counter() - ts
@@ -615,7 +616,9 @@ def bench_serving(args) -> dict:
         "data": "synthetic",
         "config": {"workload": f"serving-{count}-requests-n-loguniform-500-5e5-4to16nnz-companion-poisson",
                    "requests": count, "arrival_rate_per_s": rate, "budget_bytes": budget,
-                   "planners": args.planners, "inner_sweeps": args.inner, "rcm_engine": args.rcm_engine},
+                   "planners": args.planners, "inner_sweeps": args.inner, "rcm_engine": args.rcm_engine,
+                   "membership": "new batch object per change" if args.c5_new_batch_objects
+                   else "one batch object reset in place"},
         "latency_s": lat,
         "converged": conv,
         "worst_sampled_relres": worst,
@@ -753,6 +756,8 @@ def main() -> int:
     ap.add_argument("--rcm-engine", default="host", choices=["auto", "device", "host"],
                     help="c5: how each request's plan forms its RCM order")
     ap.add_argument("--max-steps", type=int, default=200, help="c5: refinement steps before a request gives up")
+    ap.add_argument("--c5-new-batch-objects", action="store_true",
+                    help="c5: build a new batch object at every change of membership instead of resetting one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()

@@ -237,6 +237,14 @@ OBK_API obk_status obk_solve_noalloc(obk_plan_t plan, const double *x0, double t
 
 /* Release a plan and its device memory.  NULL is a no-op. */
 OBK_API void obk_free(obk_plan_t plan);
+/* Release a plan without waiting for the device (obk_free waits for all of
+ * it): the plan's pool memory goes back in stream order on `stream`
+ * (hipFreeAsync), so the call returns at once.  The caller guarantees that
+ * every piece of work that uses the plan has completed or is queued on
+ * `stream`.  Memory from the caller's allocator (opts.alloc) is handed back
+ * after a synchronisation of `stream`.  NULL is a no-op; OBK_E_BUSY (the plan
+ * is kept) while a solve on the plan runs. */
+OBK_API obk_status obk_free_async(obk_plan_t plan, obk_stream_t stream);
 
 /*
  * Change a plan's solve options (precision, inner_sweeps, check_every) without
@@ -454,6 +462,19 @@ typedef struct {
 /* Build the launch schedule for `count` plans (the handles must outlive the batch). */
 OBK_API obk_status obk_batch_create(const obk_plan_t *plans, int count, const obk_batch_opts *opts,
                                     obk_batch_t *out);
+/* A new member list for an existing batch (continuous batching: members
+ * admitted and retired between steps).  The launch schedule is formed again
+ * for `plans`; the batch's device storage and its captured step graphs are
+ * kept, and reallocated (the graphs then captured again at the next step)
+ * only when the new members need more room than the batch holds.  Members
+ * keep the iterates held in their plans, so a member that stays continues
+ * where it stopped; new members start with obk_batch_start.  Every member is
+ * enabled afterwards.  The descriptor copies run on `stream`, which is
+ * synchronised before the call returns; the handles of earlier members may be
+ * freed after it.  Plans pass the checks of obk_batch_create (OBK_E_ARG, the
+ * batch then keeps its members); OBK_E_BUSY while a step of the batch runs;
+ * after any other failure the batch is left with no members. */
+OBK_API obk_status obk_batch_reset(obk_batch_t batch, const obk_plan_t *plans, int count, obk_stream_t stream);
 /* x~_i = P_i x0_i for every system (x0 NULL, or x0[i] NULL: zeros); re-enables all systems. */
 OBK_API obk_status obk_batch_begin(obk_batch_t batch, const double *const *x0, obk_stream_t stream);
 /* One step for all systems.  relres[i] (host, may be NULL) receives system i's
@@ -463,9 +484,9 @@ OBK_API obk_status obk_batch_step(obk_batch_t batch, double tol, double *relres,
                                   obk_stream_t stream);
 /* x~_index = P x0 for system `index` alone (x0 NULL: zeros) and enable it;
  * the other systems keep their iterates and flags.  Iterates live in each
- * plan's workspace, so a system moved into a new batch object (continuous
- * batching: members admitted and retired between steps) continues from where
- * it stopped, and only newly admitted members need obk_batch_start. */
+ * plan's workspace, so a system carried over by obk_batch_reset (or moved into
+ * a new batch object) continues from where it stopped, and only newly
+ * admitted members need obk_batch_start. */
 OBK_API obk_status obk_batch_start(obk_batch_t batch, int index, const double *x0, obk_stream_t stream);
 /* enabled[i] = 0 removes system i from later steps until obk_batch_begin. */
 OBK_API obk_status obk_batch_enable(obk_batch_t batch, const int32_t *enabled, obk_stream_t stream);

@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
         L.obk_solve_noalloc.argtypes = [_P, _P, ctypes.c_double, ctypes.c_int64, _P, ctypes.POINTER(_Info), _P]
         L.obk_free.argtypes = [_P]
         L.obk_free.restype = None
+        L.obk_free_async.argtypes = [_P, _P]
+        L.obk_free_async.restype = ctypes.c_int
         L.obk_plan_perm.argtypes = [_P, _P]
         L.obk_plan_groups.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int32)]
         L.obk_plan_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
@@ -130,6 +132,7 @@ def lib() -> ctypes.CDLL:
         L.obk_first_fit_host.argtypes = [ctypes.c_int64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]
         L.obk_batch_create.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_P)]
         L.obk_batch_begin.argtypes = [_P, _P, _P]
+        L.obk_batch_reset.argtypes = [_P, _P, ctypes.c_int, _P]
         L.obk_batch_step.argtypes = [_P, ctypes.c_double, _P, _P, _P]
         L.obk_batch_enable.argtypes = [_P, _P, _P]
         L.obk_batch_start.argtypes = [_P, ctypes.c_int, _P, _P]
@@ -141,7 +144,7 @@ def lib() -> ctypes.CDLL:
         L.obk_batch_tune.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_BatchOpts), ctypes.POINTER(ctypes.c_double)]
         for name in ("obk_opts_default", "obk_plan", "obk_solve", "obk_plan_perm", "obk_plan_groups",
                      "obk_plan_bytes", "obk_plan_stats", "obk_sweep_device", "obk_sweep_profile", "obk_rcm_host",
-                     "obk_first_fit_host", "obk_batch_create", "obk_batch_begin", "obk_batch_step",
+                     "obk_first_fit_host", "obk_batch_create", "obk_batch_reset", "obk_batch_begin", "obk_batch_step",
                      "obk_batch_enable", "obk_batch_start", "obk_batch_result", "obk_solve_batch", "obk_batch_tune",
                      "obk_plan_blocks", "obk_plan_block_solvers", "obk_block_zn_nn", "obk_block_select_k",
                      "obk_plan_complex",
@@ -199,9 +202,15 @@ class Plan:
         self.on_device = on_device
 
     # -- lifetime
-    def free(self) -> None:
+    def free(self, stream=None) -> None:
+        """obk_free; with a stream, obk_free_async: the plan's memory goes back
+        in stream order on it (all work using the plan must be done or queued
+        there)."""
         if self._h:
-            lib().obk_free(self._h)
+            if stream is None:
+                lib().obk_free(self._h)
+            else:
+                _check(lib().obk_free_async(self._h, _stream(stream)))
             self._h = None
 
     def __del__(self):
@@ -627,6 +636,17 @@ class Batch:
         _check(lib().obk_batch_create(self._keep, len(self.plans), ctypes.byref(o) if o is not None else None,
                                       ctypes.byref(h)))
         self._h = h.value
+
+    def reset(self, plans, stream=None):
+        """obk_batch_reset: the same batch object over a new member list;
+        members keep their iterates, new ones need start()."""
+        plans = list(plans)
+        keep = _handles(plans)
+        code = lib().obk_batch_reset(self._h, keep, len(plans), _stream(stream))
+        if code not in (0, -1, -7):
+            self.plans, self._keep = [], _handles([])   # the library left the batch empty
+        _check(code)
+        self.plans, self._keep = plans, keep
 
     def begin(self, x0=None, stream=None):
         on_dev = bool(self.plans) and self.plans[0].on_device

@@ -23,6 +23,7 @@ void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, d
                    hipStream_t s, const SolveWs* ws = nullptr);
 void ensure_fp32(obk_plan_s& P, hipStream_t s);
 void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts);
+void batch_reset(obk_batch_s& B, const obk_plan_t* plans, int count, hipStream_t s);
 void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s);
 void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_out, hipStream_t s);
 void batch_result(obk_batch_s& B, int index, double* x, hipStream_t s);
@@ -294,6 +295,21 @@ void obk_free(obk_plan_t plan) {
     delete plan;
 }
 
+obk_status obk_free_async(obk_plan_t plan, obk_stream_t stream) {
+    return guarded([&] {
+        if (!plan) return;
+        OBK_HIP(hipSetDevice(plan->device));
+        if (__atomic_load_n(&plan->busy, __ATOMIC_ACQUIRE)) obk::fail(OBK_E_BUSY, "a solve on this plan is running");
+        hipStream_t s = as_hip(stream);
+        // the caller's deallocator takes blocks back at once: the work queued
+        // on s must be done first
+        if (plan->opts.alloc) OBK_HIP(hipStreamSynchronize(s));
+        // pool blocks go back in stream order on s
+        obk::AllocScope scope(s);
+        delete plan;
+    });
+}
+
 obk_status obk_plan_perm(obk_plan_t plan, int32_t* p_host) {
     return guarded([&] {
         if (!plan || (!p_host && plan->n > 0)) obk::fail(OBK_E_ARG, "NULL argument");
@@ -519,6 +535,21 @@ obk_status obk_batch_create(const obk_plan_t* plans, int count, const obk_batch_
     if (st != OBK_OK) { obk_batch_delete(B); return st; }
     *out = B;
     return OBK_OK;
+}
+
+obk_status obk_batch_reset(obk_batch_t batch, const obk_plan_t* plans, int count, obk_stream_t stream) {
+    return guarded([&] {
+        if (!batch || count < 0 || (count > 0 && !plans)) obk::fail(OBK_E_ARG, "bad argument");
+        bool* busy = obk_batch_busy(batch);
+        if (__atomic_exchange_n(busy, true, __ATOMIC_ACQ_REL)) obk::fail(OBK_E_BUSY, "a step on this batch is running");
+        try {
+            obk::batch_reset(*batch, plans, count, as_hip(stream));
+        } catch (...) {
+            __atomic_store_n(busy, false, __ATOMIC_RELEASE);
+            throw;
+        }
+        __atomic_store_n(busy, false, __ATOMIC_RELEASE);
+    });
 }
 
 obk_status obk_batch_begin(obk_batch_t batch, const double* const* x0, obk_stream_t stream) {

@@ -191,11 +191,13 @@ __global__ __launch_bounds__(kTileThreads * SUB) void k_batch_sweeps(const Batch
 // FP64 residual of one R tile of one system per workgroup (block = {system,
 // tile}); the per-tile partials are those of the single-system solve, so the
 // per-system reduction in k_batch_reduce gives the same relative residual.
-__global__ __launch_bounds__(kTileThreads) void k_batch_resid(const ResSys* __restrict__ sys,
+__global__ __launch_bounds__(kTileThreads) void k_batch_resid(const int64_t* __restrict__ dims,
+                                                              const ResSys* __restrict__ sys,
                                                               const Block* __restrict__ blocks,
                                                               double* __restrict__ psum, double* __restrict__ pmax,
                                                               int* __restrict__ nonfinite) {
     __shared__ double prod[kTileEntries];
+    if ((int64_t)blockIdx.x >= dims[0]) return;
     const Block bk = blocks[blockIdx.x];
     const ResSys S = sys[bk.sys];
     const Tile t = S.rtiles[bk.begin];
@@ -204,7 +206,8 @@ __global__ __launch_bounds__(kTileThreads) void k_batch_resid(const ResSys* __re
     if (threadIdx.x == 0) { psum[blockIdx.x] = s2; pmax[blockIdx.x] = mx; }
 }
 
-__global__ __launch_bounds__(256) void k_batch_reduce(const ResSys* __restrict__ sys,
+__global__ __launch_bounds__(256) void k_batch_reduce(const int64_t* __restrict__ dims,
+                                                      const ResSys* __restrict__ sys,
                                                       const int32_t* __restrict__ blk_ptr,
                                                       const double* __restrict__ psum,
                                                       const double* __restrict__ pmax, double tol,
@@ -213,6 +216,7 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const ResSys* __restrict__
                                                       uint8_t* __restrict__ active) {
     __shared__ double red[256];
     __shared__ double mx[256];
+    if ((int64_t)blockIdx.x >= dims[1]) return;
     const int s = blockIdx.x;
     const int32_t b0 = blk_ptr[s], b1 = blk_ptr[s + 1];
     double acc = 0.0, m = 0.0;
@@ -242,8 +246,10 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const ResSys* __restrict__
     }
 }
 
-__global__ void k_batch_rhs(const ResSys* __restrict__ sys, const Block* __restrict__ rows,
-                            const double* __restrict__ sigma, const uint8_t* __restrict__ active) {
+__global__ void k_batch_rhs(const int64_t* __restrict__ dims, const ResSys* __restrict__ sys,
+                            const Block* __restrict__ rows, const double* __restrict__ sigma,
+                            const uint8_t* __restrict__ active) {
+    if ((int64_t)blockIdx.x >= dims[2]) return;
     const Block bk = rows[blockIdx.x];
     const int64_t a = bk.begin + (int64_t)threadIdx.x;
     if (a >= bk.end || !active[bk.sys]) return;
@@ -251,8 +257,10 @@ __global__ void k_batch_rhs(const ResSys* __restrict__ sys, const Block* __restr
     S.b[a] = (float)(S.r[a] / sigma[bk.sys]);
 }
 
-__global__ void k_batch_cols(const ResSys* __restrict__ sys, const Block* __restrict__ cols,
-                             const double* __restrict__ sigma, const uint8_t* __restrict__ active, int update) {
+__global__ void k_batch_cols(const int64_t* __restrict__ dims, const ResSys* __restrict__ sys,
+                             const Block* __restrict__ cols, const double* __restrict__ sigma,
+                             const uint8_t* __restrict__ active, int update) {
+    if ((int64_t)blockIdx.x >= dims[3]) return;
     const Block bk = cols[blockIdx.x];
     const int64_t c = bk.begin + (int64_t)threadIdx.x;
     if (c >= bk.end || !active[bk.sys]) return;
@@ -361,13 +369,23 @@ struct obk_batch_s {
     obk::DevArray<double> psum, pmax;
     obk::DevArray<int> err;
     int64_t n_rowblocks = 0, n_colblocks = 0, n_resblocks = 0;
+    // Launch grids of the residual, reduction, right-hand-side and column
+    // kernels: at least the block counts of the current members, which the
+    // kernels read from dims (blocks past them return at once), so that a
+    // reset over new members keeps the captured graphs while the grids and
+    // buffers are large enough.  Buffers and grids only grow.
+    int64_t g_res = 0, g_sys = 0, g_rows = 0, g_cols = 0;
+    obk::DevArray<int64_t> dims;         // {residual blocks, systems, row blocks, column blocks}
+    int occ_fp32 = -1, occ = 0;          // occupancy of the sweep kernel, cached per precision
     std::vector<uint8_t> h_enabled;
     bool busy = false;
     obk::DevArray<uint64_t> trace;       // per workgroup start/end (OBK_TRACE=1)
     int sub = 4;                         // tiles in flight per workgroup
-    // captured steps (one per tolerance); OBK_BATCH_EAGER=1 launches eagerly
+    // captured steps (one per tolerance and sweep count); OBK_BATCH_EAGER=1
+    // launches eagerly
     struct StepGraph {
         double tol = 0;
+        int sweeps = 0;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
@@ -377,11 +395,15 @@ struct obk_batch_s {
     obk_batch_s() = default;
     obk_batch_s(const obk_batch_s&) = delete;
     obk_batch_s& operator=(const obk_batch_s&) = delete;
-    ~obk_batch_s() {
+    void drop_graphs() {
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
         }
+        graphs.clear();
+    }
+    ~obk_batch_s() {
+        drop_graphs();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
     }
 };
@@ -389,9 +411,47 @@ struct obk_batch_s {
 namespace obk {
 namespace {
 
-template <class T> void upload(DevArray<char>& d, const std::vector<T>& h) {
-    d.alloc(std::max<size_t>(h.size() * sizeof(T), 1));
-    if (!h.empty()) OBK_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+// OBK_TRACE=1: per-workgroup wall-clock spans of the persistent launch and the
+// event time of the launch, summarised on stderr after each step
+bool trace_enabled() {
+    const char* v = std::getenv("OBK_TRACE");
+    return v && v[0] && v[0] != '0';
+}
+
+// Grow-only device storage: true when d had to be (re)allocated.  A first
+// allocation is exact; a later one takes at least `headroom` times the old
+// size, so that a stream of resets over similar member lists settles.
+template <class T> bool reserve(DevArray<T>& d, size_t n, double headroom) {
+    if (d.get() && d.count >= n) return false;
+    size_t c = std::max<size_t>(n, 1);
+    if (d.get()) c = std::max(c, (size_t)((double)d.count * headroom));
+    d.alloc(c);
+    return true;
+}
+bool grow_grid(int64_t& g, int64_t need, double headroom) {
+    if (need <= g) return false;
+    g = g == 0 ? need : std::max(need, (int64_t)((double)g * headroom));
+    return true;
+}
+template <class T> void put(DevArray<char>& d, const std::vector<T>& h, hipStream_t s) {
+    if (!h.empty()) OBK_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T> void put(DevArray<T>& d, const std::vector<T>& h, hipStream_t s) {
+    if (!h.empty()) OBK_HIP(hipMemcpyAsync(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+int sweep_occupancy(bool fp32, int sub) {
+    int occ = 0;
+    if (fp32) {
+        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 1>, kTileThreads, 0));
+        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 2>, 2 * kTileThreads, 0));
+        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 4>, 4 * kTileThreads, 0));
+    } else {
+        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 1>, kTileThreads, 0));
+        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 2>, 2 * kTileThreads, 0));
+        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 4>, 4 * kTileThreads, 0));
+    }
+    return occ;
 }
 
 // Team sizing and placement.  Work of a system per sweep ~ its entries in
@@ -401,29 +461,27 @@ template <class T> void upload(DevArray<char>& d, const std::vector<T>& h) {
 // runs that task first, so the members of a team start it together and never
 // wait at a team barrier for a member still busy with another system.
 // Single-workgroup systems then go to the least-loaded workgroups.
-void build_schedule(obk_batch_s& B) {
+//
+// The host arrays are formed first, then the device storage is grown where
+// it is too small (which drops the captured step graphs: they hold its
+// addresses and grids), then everything goes over in asynchronous copies on
+// `st`, which is synchronised before returning.  The batch must be idle.
+void build_schedule(obk_batch_s& B, hipStream_t st, double headroom) {
     const int count = (int)B.plans.size();
     int dev = 0, cus = 256;
     OBK_HIP(hipGetDevice(&dev));
     OBK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = B.opts.wgs_per_cu > 0 ? B.opts.wgs_per_cu : 2;
     // every workgroup of the persistent launch must be resident at once
-    const int sub = B.sub;
-    int occ = 0;
-    if (B.fp32) {
-        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 1>, kTileThreads, 0));
-        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 2>, 2 * kTileThreads, 0));
-        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<float, 4>, 4 * kTileThreads, 0));
-    } else {
-        if (sub == 1) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 1>, kTileThreads, 0));
-        if (sub == 2) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 2>, 2 * kTileThreads, 0));
-        if (sub == 4) OBK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweeps<double, 4>, 4 * kTileThreads, 0));
-
+    if (B.occ_fp32 != (int)B.fp32) {
+        B.occ = sweep_occupancy(B.fp32, B.sub);
+        B.occ_fp32 = (int)B.fp32;
     }
-    per_cu = std::max(1, std::min(per_cu, occ));
+    per_cu = std::max(1, std::min(per_cu, B.occ));
     const int nxcd = 8;
     int nwg = std::max(nxcd, cus * per_cu);
     nwg -= nwg % nxcd;
+    bool changed = nwg != B.nwg;
     B.nwg = nwg;
     std::vector<int64_t> work(count);
     int64_t total = 0;
@@ -499,11 +557,6 @@ void build_schedule(obk_batch_s& B) {
         for (auto& t : per_wg[b]) flat.push_back(t);
         tptr[b + 1] = (int32_t)flat.size();
     }
-    B.task_ptr.alloc(nwg + 1);
-    OBK_HIP(hipMemcpy(B.task_ptr.get(), tptr.data(), (nwg + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    upload(B.tasks, flat);
-    B.bars.alloc(2 * (size_t)std::max(count, 1));
-    OBK_HIP(hipMemset(B.bars.get(), 0, 2 * sizeof(uint32_t) * std::max(count, 1)));
     // merged tiles of every system, R then S, in one array each
     std::vector<Tile> mr, ms;
     std::vector<int32_t> mrp, msp;
@@ -515,34 +568,11 @@ void build_schedule(obk_batch_s& B) {
         sbase[s] = ms.size(); spbase[s] = msp.size();
         merge_tiles(P.h_stiles, P.h_stile_ptr, P.ngroups, ms, msp);
     }
-    upload(B.mtiles_r, mr);
-    upload(B.mtiles_s, ms);
-    upload(B.mptr_r, mrp);
-    upload(B.mptr_s, msp);
-    auto view = [&](int s) {
-        return TileView{reinterpret_cast<const Tile*>(B.mtiles_r.get()) + rbase[s],
-                        reinterpret_cast<const Tile*>(B.mtiles_s.get()) + sbase[s],
-                        reinterpret_cast<const int32_t*>(B.mptr_r.get()) + rpbase[s],
-                        reinterpret_cast<const int32_t*>(B.mptr_s.get()) + spbase[s]};
-    };
-    if (B.fp32) {
-        std::vector<BatchSys<float>> v;
-        for (int s = 0; s < count; s++)
-            v.push_back(sys_view<float>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
-        upload(B.sys_sweep, v);
-    } else {
-        std::vector<BatchSys<double>> v;
-        for (int s = 0; s < count; s++)
-            v.push_back(sys_view<double>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
-        upload(B.sys_sweep, v);
-    }
-    std::vector<ResSys> rs;
+    // residual, right-hand-side and column blocks
     std::vector<Block> rows, cols, res;
     std::vector<int32_t> rptr(count + 1, 0);
     for (int s = 0; s < count; s++) {
         obk_plan_s& P = *B.plans[s];
-        rs.push_back(ResSys{P.rtiles.get(), P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(),
-                            P.r64.get(), P.b32.get(), P.d32.get(), P.fnorm2, P.zero_rows_f2, P.zero_rows_fmax});
         for (int64_t a = 0; a < std::max<int64_t>(P.m, 1); a += 256)
             rows.push_back(Block{s, (int32_t)a, (int32_t)std::min<int64_t>(a + 256, P.m)});
         // residual blocks: the system's R tiles in plan order (all groups)
@@ -551,36 +581,88 @@ void build_schedule(obk_batch_s& B) {
         for (int64_t c = 0; c < P.n; c += 256)
             cols.push_back(Block{s, (int32_t)c, (int32_t)std::min<int64_t>(c + 256, P.n)});
     }
-    upload(B.sys_res, rs);
-    upload(B.rowblocks, rows);
-    upload(B.colblocks, cols);
-    upload(B.resblocks, res);
     B.n_rowblocks = (int64_t)rows.size();
     B.n_colblocks = (int64_t)cols.size();
     B.n_resblocks = (int64_t)res.size();
-    B.rowblk_ptr.alloc(count + 1);
-    OBK_HIP(hipMemcpy(B.rowblk_ptr.get(), rptr.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    B.psum.alloc(std::max<int64_t>(B.n_resblocks, 1));
-    B.pmax.alloc(std::max<int64_t>(B.n_resblocks, 1));
-    B.relres.alloc(std::max(count, 1));
-    B.sigma.alloc(std::max(count, 1));
-    B.active.alloc(std::max(count, 1));
-    B.enabled.alloc(std::max(count, 1));
+    changed |= grow_grid(B.g_res, B.n_resblocks, headroom);
+    changed |= grow_grid(B.g_sys, count, headroom);
+    changed |= grow_grid(B.g_rows, B.n_rowblocks, headroom);
+    changed |= grow_grid(B.g_cols, B.n_colblocks, headroom);
+    // device storage (grown where too small)
+    const size_t sysb = B.fp32 ? sizeof(BatchSys<float>) : sizeof(BatchSys<double>);
+    changed |= reserve(B.task_ptr, (size_t)nwg + 1, headroom);
+    changed |= reserve(B.tasks, flat.size() * sizeof(TeamTask), headroom);
+    changed |= reserve(B.bars, 2 * (size_t)std::max(count, 1), headroom);
+    changed |= reserve(B.mtiles_r, mr.size() * sizeof(Tile), headroom);
+    changed |= reserve(B.mtiles_s, ms.size() * sizeof(Tile), headroom);
+    changed |= reserve(B.mptr_r, mrp.size() * sizeof(int32_t), headroom);
+    changed |= reserve(B.mptr_s, msp.size() * sizeof(int32_t), headroom);
+    changed |= reserve(B.sys_sweep, (size_t)count * sysb, headroom);
+    changed |= reserve(B.sys_res, (size_t)count * sizeof(ResSys), headroom);
+    changed |= reserve(B.rowblocks, rows.size() * sizeof(Block), headroom);
+    changed |= reserve(B.colblocks, cols.size() * sizeof(Block), headroom);
+    changed |= reserve(B.resblocks, res.size() * sizeof(Block), headroom);
+    changed |= reserve(B.rowblk_ptr, (size_t)count + 1, headroom);
+    changed |= reserve(B.psum, (size_t)B.g_res, headroom);
+    changed |= reserve(B.pmax, (size_t)B.g_res, headroom);
+    changed |= reserve(B.relres, (size_t)B.g_sys, headroom);
+    changed |= reserve(B.sigma, (size_t)B.g_sys, headroom);
+    changed |= reserve(B.active, (size_t)B.g_sys, headroom);
+    changed |= reserve(B.enabled, (size_t)B.g_sys, headroom);
+    changed |= reserve(B.err, 2, headroom);
+    changed |= reserve(B.dims, 4, headroom);
+    if (changed) B.drop_graphs();
+    // per-system views (device addresses of the merged tiles and barriers)
+    auto view = [&](int s) {
+        return TileView{reinterpret_cast<const Tile*>(B.mtiles_r.get()) + rbase[s],
+                        reinterpret_cast<const Tile*>(B.mtiles_s.get()) + sbase[s],
+                        reinterpret_cast<const int32_t*>(B.mptr_r.get()) + rpbase[s],
+                        reinterpret_cast<const int32_t*>(B.mptr_s.get()) + spbase[s]};
+    };
+    std::vector<BatchSys<float>> v32;
+    std::vector<BatchSys<double>> v64;
+    for (int s = 0; s < count; s++) {
+        if (B.fp32) v32.push_back(sys_view<float>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
+        else v64.push_back(sys_view<double>(*B.plans[s], view(s), B.bars.get() + 2 * s, B.team[s]));
+    }
+    std::vector<ResSys> rs;
+    for (int s = 0; s < count; s++) {
+        obk_plan_s& P = *B.plans[s];
+        rs.push_back(ResSys{P.rtiles.get(), P.rptr.get(), P.rcol.get(), P.rval.get(), P.rf.get(), P.x.get(),
+                            P.r64.get(), P.b32.get(), P.d32.get(), P.fnorm2, P.zero_rows_f2, P.zero_rows_fmax});
+    }
+    const std::vector<int64_t> dims{B.n_resblocks, count, B.n_rowblocks, B.n_colblocks};
     B.h_enabled.assign(count, 1);
-    OBK_HIP(hipMemcpy(B.enabled.get(), B.h_enabled.data(), count, hipMemcpyHostToDevice));
-    B.err.alloc(2);   // [0]: a team barrier timed out; [1]: a residual was not finite (per system in relres)
-    OBK_HIP(hipMemset(B.err.get(), 0, 2 * sizeof(int)));
+    put(B.task_ptr, tptr, st);
+    put(B.tasks, flat, st);
+    put(B.mtiles_r, mr, st);
+    put(B.mtiles_s, ms, st);
+    put(B.mptr_r, mrp, st);
+    put(B.mptr_s, msp, st);
+    if (B.fp32) put(B.sys_sweep, v32, st);
+    else put(B.sys_sweep, v64, st);
+    put(B.sys_res, rs, st);
+    put(B.rowblocks, rows, st);
+    put(B.colblocks, cols, st);
+    put(B.resblocks, res, st);
+    put(B.rowblk_ptr, rptr, st);
+    put(B.enabled, B.h_enabled, st);
+    put(B.dims, dims, st);
+    // team barriers start from zero; [0]: a team barrier timed out, [1]: a
+    // residual was not finite (per system in relres)
+    OBK_HIP(hipMemsetAsync(B.bars.get(), 0, 2 * sizeof(uint32_t) * std::max(count, 1), st));
+    OBK_HIP(hipMemsetAsync(B.err.get(), 0, 2 * sizeof(int), st));
+    if (trace_enabled()) {
+        (void)reserve(B.trace, 2 * (size_t)B.nwg, headroom);     // eager launches only: no graph holds it
+        OBK_HIP(hipMemsetAsync(B.trace.get(), 0, 2 * sizeof(uint64_t) * B.nwg, st));
+    }
+    // the host arrays above must outlive the copies
+    OBK_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace
 
 namespace {
-// OBK_TRACE=1: per-workgroup wall-clock spans of the persistent launch and the
-// event time of the launch, summarised on stderr after each step
-bool trace_enabled() {
-    const char* v = std::getenv("OBK_TRACE");
-    return v && v[0] && v[0] != '0';
-}
 
 hipEvent_t g_ev[2] = {nullptr, nullptr};
 
@@ -630,12 +712,8 @@ void launch_sweeps(obk_batch_s& B, int sweeps, hipStream_t s) {
     OBK_HIP(hipGetLastError());
 }
 
-void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts) {
-    B.plans.assign(plans, plans + count);
-    if (opts) B.opts = *opts;
-    B.sub = B.opts.tiles_per_wg > 0 ? B.opts.tiles_per_wg : 4;
-    if (B.sub != 1 && B.sub != 2 && B.sub != 4) fail(OBK_E_ARG, "tiles_per_wg must be 1, 2 or 4");
-    OBK_HIP(hipGetDevice(&B.device));
+// The checks every member list passes (obk_batch_create and obk_batch_reset).
+static void check_members(const obk_batch_s& B, const obk_plan_t* plans, int count) {
     for (int s = 0; s < count; s++) {
         if (!plans[s]) fail(OBK_E_ARG, "NULL plan in batch");
         if (plans[s]->device != B.device) fail(OBK_E_ARG, "plans of a batch must live on the current device");
@@ -643,18 +721,53 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
         if (plans[s]->cplx) fail(OBK_E_ARG, "complex plans cannot be batched");
         if (s > 0 && plans[s]->opts.precision != plans[0]->opts.precision)
             fail(OBK_E_ARG, "plans of a batch must share one precision");
-        for (int t = 0; t < s; t++)
-            if (plans[t] == plans[s]) fail(OBK_E_ARG, "a plan appears twice in a batch");
     }
+    std::vector<const obk_plan_s*> sorted(plans, plans + count);
+    std::sort(sorted.begin(), sorted.end(), std::less<const obk_plan_s*>());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        fail(OBK_E_ARG, "a plan appears twice in a batch");
+}
+
+void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts) {
+    if (opts) B.opts = *opts;
+    B.sub = B.opts.tiles_per_wg > 0 ? B.opts.tiles_per_wg : 4;
+    if (B.sub != 1 && B.sub != 2 && B.sub != 4) fail(OBK_E_ARG, "tiles_per_wg must be 1, 2 or 4");
+    OBK_HIP(hipGetDevice(&B.device));
+    check_members(B, plans, count);
+    B.plans.assign(plans, plans + count);
     B.fp32 = count > 0 && plans[0]->opts.precision == OBK_FP32_IR;
     {
         const char* e = std::getenv("OBK_BATCH_EAGER");
         B.use_graph = !(e && e[0] && e[0] != '0');
     }
-    build_schedule(B);
-    if (trace_enabled()) {
-        B.trace.alloc(2 * (size_t)B.nwg);
-        OBK_HIP(hipMemset(B.trace.get(), 0, 2 * sizeof(uint64_t) * B.nwg));
+    build_schedule(B, nullptr, 1.0);
+}
+
+// A new member list for an existing batch object (continuous batching): the
+// schedule is formed again, the device storage and the captured step graphs
+// are kept unless the new members outgrow them.  Members keep their iterates
+// (they live in the plans); every member is enabled afterwards.
+void batch_reset(obk_batch_s& B, const obk_plan_t* plans, int count, hipStream_t s) {
+    int dev = 0;
+    OBK_HIP(hipGetDevice(&dev));
+    if (dev != B.device) fail(OBK_E_ARG, "a batch must be reset on the device it was created on");
+    check_members(B, plans, count);
+    const bool fp32 = count > 0 ? plans[0]->opts.precision == OBK_FP32_IR : B.fp32;
+    if (fp32 != B.fp32) {
+        // another kernel instantiation: the captured graphs no longer apply
+        B.drop_graphs();
+        B.fp32 = fp32;
+    }
+    B.plans.assign(plans, plans + count);
+    try {
+        build_schedule(B, s, 1.5);
+    } catch (...) {
+        // a failed reset leaves an empty batch, never one whose descriptors
+        // and member list disagree
+        B.plans.clear();
+        B.h_enabled.clear();
+        B.drop_graphs();
+        throw;
     }
 }
 
@@ -687,48 +800,53 @@ void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s) {
 // The kernels of one step: residual, reduction (relative residual, sigma and
 // the active flags), right-hand side and correction reset (FP32 refinement),
 // the persistent sweep launch, and the update.
+static int step_sweeps(const obk_batch_s& B) {
+    return B.fp32 ? std::max(1, B.plans[0]->opts.inner_sweeps) : std::max(1, B.plans[0]->opts.check_every);
+}
+
 static void enqueue_step(obk_batch_s& B, double tol, hipStream_t s) {
-    const int count = (int)B.plans.size();
-    if (B.n_resblocks)
-        k_batch_resid<<<(unsigned)B.n_resblocks, kTileThreads, 0, s>>>((const ResSys*)B.sys_res.get(),
-                                                                       (const Block*)B.resblocks.get(), B.psum.get(),
-                                                                       B.pmax.get(), B.err.get() + 1);
-    k_batch_reduce<<<count, 256, 0, s>>>((const ResSys*)B.sys_res.get(), B.rowblk_ptr.get(), B.psum.get(),
-                                         B.pmax.get(), tol > 0 ? tol : -1.0, B.enabled.get(), B.relres.get(),
-                                         B.sigma.get(), B.active.get());
+    const int64_t* dims = B.dims.get();
+    const ResSys* rs = (const ResSys*)B.sys_res.get();
+    if (B.g_res)
+        k_batch_resid<<<(unsigned)B.g_res, kTileThreads, 0, s>>>(dims, rs, (const Block*)B.resblocks.get(),
+                                                                 B.psum.get(), B.pmax.get(), B.err.get() + 1);
+    k_batch_reduce<<<(unsigned)B.g_sys, 256, 0, s>>>(dims, rs, B.rowblk_ptr.get(), B.psum.get(), B.pmax.get(),
+                                                     tol > 0 ? tol : -1.0, B.enabled.get(), B.relres.get(),
+                                                     B.sigma.get(), B.active.get());
     OBK_HIP(hipGetLastError());
     if (B.fp32) {
-        k_batch_rhs<<<(unsigned)B.n_rowblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
-                                                            (const Block*)B.rowblocks.get(), B.sigma.get(),
-                                                            B.active.get());
-        if (B.n_colblocks)
-            k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
-                                                                 (const Block*)B.colblocks.get(), B.sigma.get(),
-                                                                 B.active.get(), 0);
+        k_batch_rhs<<<(unsigned)B.g_rows, 256, 0, s>>>(dims, rs, (const Block*)B.rowblocks.get(), B.sigma.get(),
+                                                       B.active.get());
+        if (B.g_cols)
+            k_batch_cols<<<(unsigned)B.g_cols, 256, 0, s>>>(dims, rs, (const Block*)B.colblocks.get(),
+                                                            B.sigma.get(), B.active.get(), 0);
         ev_record(B, 0, s);
-        launch_sweeps<float>(B, std::max(1, B.plans[0]->opts.inner_sweeps), s);
+        launch_sweeps<float>(B, step_sweeps(B), s);
         ev_record(B, 1, s);
-        if (B.n_colblocks)
-            k_batch_cols<<<(unsigned)B.n_colblocks, 256, 0, s>>>((const ResSys*)B.sys_res.get(),
-                                                                 (const Block*)B.colblocks.get(), B.sigma.get(),
-                                                                 B.active.get(), 1);
+        if (B.g_cols)
+            k_batch_cols<<<(unsigned)B.g_cols, 256, 0, s>>>(dims, rs, (const Block*)B.colblocks.get(),
+                                                            B.sigma.get(), B.active.get(), 1);
     } else {
         ev_record(B, 0, s);
-        launch_sweeps<double>(B, std::max(1, B.plans[0]->opts.check_every), s);
+        launch_sweeps<double>(B, step_sweeps(B), s);
         ev_record(B, 1, s);
     }
     OBK_HIP(hipGetLastError());
 }
 
-// The step's kernels captured once per tolerance into a graph on the batch's
-// own capture stream and replayed afterwards (no memset nodes: the flags the
-// kernels read are written by kernels or by host copies outside the graph).
+// The step's kernels captured once per tolerance and sweep count into a graph
+// on the batch's own capture stream and replayed afterwards (no memset nodes:
+// the flags the kernels read are written by kernels or by host copies and
+// fills outside the graph).  The graph holds the batch's device addresses and
+// grids, so it survives a reset until the storage has to grow.
 static hipGraphExec_t step_graph(obk_batch_s& B, double tol) {
+    const int sweeps = step_sweeps(B);
     for (auto& g : B.graphs)
-        if (g.tol == tol && g.exec) return g.exec;
+        if (g.tol == tol && g.sweeps == sweeps && g.exec) return g.exec;
     if (!B.capture_stream) OBK_HIP(hipStreamCreateWithFlags(&B.capture_stream, hipStreamNonBlocking));
     obk_batch_s::StepGraph sg;
     sg.tol = tol;
+    sg.sweeps = sweeps;
     OBK_HIP(hipStreamBeginCapture(B.capture_stream, hipStreamCaptureModeThreadLocal));
     try {
         enqueue_step(B, tol, B.capture_stream);

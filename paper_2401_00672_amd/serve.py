@@ -13,15 +13,17 @@ persistent launch, then the FP64 update):
 * **planning** -- on planner threads, each with its own HIP stream, so plans
   for new arrivals are built while the batch steps;
 * **joining** -- planned requests join at the next step boundary: the batch
-  object is rebuilt over the new member set (members keep their iterates,
-  which live in their plans) and only the newcomers are started from x0 = 0;
+  object is re-formed over the new member set in place (``obk_batch_reset``:
+  its device storage and captured step graph are kept while they are large
+  enough; members keep their iterates, which live in their plans) and only
+  the newcomers are started from x0 = 0;
 * **retiring** -- a member whose relative residual reached ``tol`` (or that hit
   ``max_steps``) leaves at the step boundary; its solution is copied to the
-  host.  Its slot in the batch object is disabled (``obk_batch_enable``)
-  rather than rebuilt; its plan stays allocated while the batch object
-  refers to it and is freed when the batch is next rebuilt -- when requests
-  join, when disabled slots outnumber the live ones, or when the head of the
-  queue waits for memory that retired plans hold;
+  host.  Its slot in the batch object is disabled (``obk_batch_enable``);
+  its plan stays allocated while the batch object refers to it and is freed
+  when the batch is next re-formed -- when requests join, when disabled
+  slots outnumber the live ones, or when the head of the queue waits for
+  memory that retired plans hold;
 * **failure and cancellation** -- a request whose plan fails (a malformed
   system, memory) gets a ``failed`` result and returns its budget; ``cancel``
   (from any thread) withdraws a request that is waiting, planning or being
@@ -112,6 +114,9 @@ class LibobkBackend:
     def make_batch(self, plans):
         return self.obk.Batch(plans, self.batch_opts)
 
+    def reset_batch(self, batch, plans) -> None:
+        batch.reset(plans, stream=self.stream.cuda_stream)
+
     def enable(self, batch, enabled) -> None:
         batch.enable(np.asarray(enabled, dtype=np.int32), stream=self.stream.cuda_stream)
 
@@ -128,7 +133,10 @@ class LibobkBackend:
         batch.free()
 
     def free_plan(self, plan) -> None:
-        plan.free()
+        # its last use (a step, a result copy) was on the server's stream and
+        # has completed: the memory goes back in stream order, without a
+        # wait for the planners' work on the device
+        plan.free(stream=self.stream.cuda_stream)
 
 
 @dataclasses.dataclass
@@ -146,7 +154,7 @@ class Server:
 
     def __init__(self, backend, budget_bytes: int, tol: float = 1e-10, max_steps: int = 200,
                  planners: int = 2, clock=time.perf_counter, idle_wait: float = 0.002, progress=None,
-                 progress_every: int = 0):
+                 progress_every: int = 0, reuse_batch: bool = True):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.tol = float(tol)
@@ -156,8 +164,11 @@ class Server:
         self.idle_wait = idle_wait
         self.progress = progress                 # called with (finished, total) every progress_every results
         self.progress_every = int(progress_every)
+        # True: one batch object re-formed in place when members join
+        # (obk_batch_reset); False: a new batch object each time
+        self.reuse_batch = bool(reuse_batch)
         self.stats = {"steps": 0, "rebuilds": 0, "peak_bytes": 0, "peak_members": 0, "step_seconds": 0.0,
-                      "rebuild_seconds": 0.0, "failed": 0, "cancelled": 0}
+                      "rebuild_seconds": 0.0, "free_seconds": 0.0, "plan_seconds": 0.0, "failed": 0, "cancelled": 0}
         self._cancel_lock = threading.Lock()
         self._cancel: set[int] = set()
 
@@ -166,6 +177,15 @@ class Server:
         turn with a ``cancelled`` result, whatever stage it is in."""
         with self._cancel_lock:
             self._cancel.add(int(rid))
+
+    def _plan(self, system):
+        # on a planner thread: the time it spends is summed in plan_seconds
+        t = time.perf_counter()
+        try:
+            return self.backend.plan(system)
+        finally:
+            with self._cancel_lock:
+                self.stats["plan_seconds"] += time.perf_counter() - t
 
     def _cancelled(self) -> set[int]:
         with self._cancel_lock:
@@ -214,7 +234,7 @@ class Server:
                         break
                     pending.popleft()
                     used += est
-                    planning[pool.submit(self.backend.plan, r.system)] = (r, est, t)
+                    planning[pool.submit(self._plan, r.system)] = (r, est, t)
                 # 2. planned requests join at this step boundary (a failed or
                 # cancelled one returns its budget)
                 for fut in [f for f in planning if f.done()]:
@@ -244,25 +264,32 @@ class Server:
                 live = [m for m in members if m.live]
                 retired_held = len(members) - len(live)
                 if joining or (retired_held and (len(live) < retired_held or blocked)):
-                    # rebuild over the live members and the newcomers; the
-                    # retired members' plans are freed once no batch refers to them
+                    # re-form the batch over the live members and the
+                    # newcomers; the retired members' plans are freed once no
+                    # batch refers to them
                     tb = self.clock()
-                    if batch is not None:
-                        self.backend.free_batch(batch)
-                        batch = None
-                    for m in members:
-                        if not m.live:
-                            self.backend.free_plan(m.plan)
-                            used -= m.nbytes
+                    retired_members = [m for m in members if not m.live]
                     first_new = len(live)
                     members = live + joining
                     joining = []
-                    if members:
-                        batch = self.backend.make_batch([m.plan for m in members])
-                        for i in range(first_new, len(members)):
-                            self.backend.start(batch, i)
-                        self.stats["rebuilds"] += 1
-                    self.stats["rebuild_seconds"] += self.clock() - tb
+                    plans = [m.plan for m in members]
+                    if batch is not None and self.reuse_batch:
+                        self.backend.reset_batch(batch, plans)
+                    else:
+                        if batch is not None:
+                            self.backend.free_batch(batch)
+                            batch = None
+                        if members:
+                            batch = self.backend.make_batch(plans)
+                    for i in range(first_new, len(members)):
+                        self.backend.start(batch, i)
+                    self.stats["rebuilds"] += 1 if members else 0
+                    tf = self.clock()
+                    self.stats["rebuild_seconds"] += tf - tb
+                    for m in retired_members:
+                        self.backend.free_plan(m.plan)
+                        used -= m.nbytes
+                    self.stats["free_seconds"] += self.clock() - tf
                 live_count = sum(1 for m in members if m.live)
                 self.stats["peak_members"] = max(self.stats["peak_members"], live_count)
                 # 3. one batched step, then retire the finished members

@@ -150,3 +150,110 @@ def test_batch_tune_and_errors():
         obk.solve_batch([plans[0], plans[0]], tol=1e-10)
     for p in plans + [p64]:
         p.free()
+
+
+@pytest.mark.parametrize("eager", [False, True], ids=["graph", "eager"])
+def test_batch_reset_members_continue_and_equal_single(monkeypatch, eager):
+    """obk_batch_reset: one batch object re-formed over changing member lists.
+    Members that stay continue from their iterates, new members start from
+    zero, and every system's result equals its solve alone for the number of
+    steps that advanced it -- through growth (new storage, new graph), shrinkage
+    (storage and graph kept), an empty list, a change of precision and a
+    rejected list (the batch keeps its members)."""
+    if eager:
+        monkeypatch.setenv("OBK_BATCH_EAGER", "1")
+    else:
+        monkeypatch.delenv("OBK_BATCH_EAGER", raising=False)
+    systems = _systems()
+    tol = 1e-10
+    plans = [obk.plan_system(s, 0.1, precision=obk.FP32_IR, inner_sweeps=8) for s in systems]
+    steps = [0] * len(plans)
+    results = {}
+    state = {"members": [0, 1, 2]}
+    b = obk.Batch([plans[i] for i in state["members"]])
+    b.begin()
+
+    def run(k):
+        for _ in range(k):
+            rr, act = b.step(tol)
+            for slot, i in enumerate(state["members"]):
+                steps[i] += int(act[slot])
+
+    def reform(new):
+        old = state["members"]
+        for slot, i in enumerate(old):
+            if i not in new:
+                results[i] = b.result(slot)
+        _say(f"[batch] reset {old} -> {new}")
+        b.reset([plans[i] for i in new])
+        for slot, i in enumerate(new):
+            if i not in old:
+                b.start(slot)
+        for i in old:
+            if i not in new:
+                plans[i].free()          # the batch no longer refers to it
+        state["members"] = new
+
+    run(2)
+    reform([1, 3, 2, 7])                  # grows
+    run(3)
+    with pytest.raises(obk.ObkError) as ei:
+        b.reset([plans[3], plans[3]])
+    assert ei.value.code == -1 and len(b.plans) == 4
+    run(1)
+    reform([3, 2])                        # shrinks
+    run(2)
+    reform([])
+    reform([4, 5, 6])
+    for _ in range(60):
+        rr, act = b.step(tol)
+        for slot, i in enumerate(state["members"]):
+            steps[i] += int(act[slot])
+        if not act.any():
+            break
+    reform([])
+    assert sorted(results) == list(range(len(systems)))
+    for i, x in sorted(results.items()):
+        q = obk.plan_system(systems[i], 0.1, precision=obk.FP32_IR, inner_sweeps=8)
+        x1, info = q.solve(maxit=steps[i], tol=tol)
+        q.free()
+        assert info.outer_steps == steps[i], (i, info.outer_steps, steps[i])
+        assert np.array_equal(x1, x), f"system {i} after {steps[i]} steps: reset batch and single differ"
+    # the same object over FP64 plans: another kernel, graphs captured again
+    p64 = [obk.plan_system(systems[i], 0.1, check_every=5) for i in (0, 4)]
+    b.reset(p64)
+    b.start(0)
+    b.start(1)
+    for _ in range(2):
+        b.step(0.0)
+    for slot, p in enumerate(p64):
+        q = obk.plan_system(systems[(0, 4)[slot]], 0.1, check_every=5)
+        x1, info = q.solve(maxit=10)
+        q.free()
+        assert np.array_equal(b.result(slot), x1)
+    b.free()
+    for p in p64:
+        p.free()
+
+
+def test_free_async_returns_memory_in_stream_order():
+    """obk_free_async: a plan released on a stream without a device-wide wait;
+    plans built afterwards (reusing the pool's memory) solve as before."""
+    import torch
+    systems = _systems()[:3]
+    st = torch.cuda.Stream()
+    ref = []
+    for s in systems:
+        p = obk.plan_system(s, 0.1, precision=obk.FP32_IR, inner_sweeps=8)
+        ref.append(p.solve(maxit=100, tol=1e-10)[0])
+        p.free(stream=st.cuda_stream)
+        p.free(stream=st.cuda_stream)          # a freed handle: no-op
+    _say("[batch] free_async")
+    for _ in range(2):
+        for s, x0 in zip(systems, ref):
+            p = obk.plan_system(s, 0.1, precision=obk.FP32_IR, inner_sweeps=8, stream=st.cuda_stream)
+            x, info = p.solve(maxit=100, tol=1e-10, stream=st.cuda_stream)
+            assert info.status == "converged" and np.array_equal(x, x0)
+            p.free(stream=st.cuda_stream)
+    assert obk.lib().obk_free_async(None, None) == 0
+    st.synchronize()

@@ -43,6 +43,7 @@ class FakeBackend:
         self.factor = plan_bytes_factor
         self.fail = set(fail)           # systems (by id) whose plan raises
         self.batches = []
+        self.resets = 0
 
     def plan(self, system):
         if id(system) in self.fail:
@@ -59,6 +60,15 @@ class FakeBackend:
         b = _Batch(plans)
         self.batches.append(b)
         return b
+
+    def reset_batch(self, batch, plans):
+        # like obk_batch_reset: the same object over a new member list, every
+        # member enabled, iterates (in the plans) untouched
+        assert not batch.freed
+        assert all(not p.freed for p in plans)
+        batch.plans = list(plans)
+        batch.enabled = [True] * len(batch.plans)
+        self.resets += 1
 
     def enable(self, batch, enabled):
         assert not batch.freed
@@ -225,3 +235,29 @@ def test_retired_members_are_disabled_not_rebuilt():
     assert all(r.status in ("converged", "maxit") for r in res)
     retirements = sum(1 for r in res)
     assert srv.stats["rebuilds"] < retirements
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_in_place_reset_equals_new_batch_objects(seed):
+    """Re-forming one batch object in place gives every request the same
+    result, step count and status as building a new batch object per change
+    of membership, and frees every plan."""
+    out = []
+    for reuse in (True, False):
+        be = FakeBackend()
+        srv = Server(be, budget_bytes=6 * footprint_estimate(3000, 15000), tol=1e-10, max_steps=30,
+                     reuse_batch=reuse)
+        res = srv.run(_requests(60, seed=seed, rate=3000.0))
+        assert not be.live_plans
+        if reuse:
+            assert be.resets >= 1 and len(be.batches) == 1
+        else:
+            assert be.resets == 0 and len(be.batches) == srv.stats["rebuilds"]
+        out.append({r.rid: r for r in res})
+    a, b = out
+    assert a.keys() == b.keys()
+    for k in a:
+        assert (a[k].status, a[k].steps) == (b[k].status, b[k].steps)
+        assert (a[k].x is None) == (b[k].x is None)
+        if a[k].x is not None:
+            assert np.array_equal(a[k].x, b[k].x)
