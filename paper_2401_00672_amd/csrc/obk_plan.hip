@@ -210,64 +210,253 @@ __global__ void k_csc_fill(int64_t nnz, const uint32_t* __restrict__ order, cons
     if (k < nnz) crow[k] = trow[order[k]];
 }
 
+// CSC position of every CSR entry (the inverse of the CSC order)
+__global__ void k_csc_pos(int64_t nnz, const uint32_t* __restrict__ order, uint32_t* __restrict__ cpos) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) cpos[order[k]] = (uint32_t)k;
+}
+
 // --------------------------------------------------------- cosine pass
-// One thread per entry (i, c) of A~.  For every row j < i stored in column c,
-// the sparse dot a_i . a_j is taken over the common columns in ascending
-// order; the pair is handled only by the entry of its first common column,
-// so each pair is evaluated once.  |cos| = |d| / sqrt(nu_i * nu_j) (Section
-// 3.3, one-row blocks); the pair conflicts iff |cos| >= delta.
-template <bool kFill>
-__global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
-                            const double* __restrict__ tv, const int32_t* __restrict__ trow,
-                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ crow,
-                            const double* __restrict__ nu, double delta, int64_t* __restrict__ count,
-                            const int64_t* __restrict__ out_pos, int32_t* __restrict__ out_idx) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nnz) return;
-    const int32_t i = trow[e];
-    const int32_t c = tci[e];
-    const double nui = nu[i];
-    const int64_t ia0 = trp[i], ia1 = trp[i + 1];
-    const int64_t s0 = cptr[c], s1 = cptr[c + 1];
-    // rows of column c are ascending: those below i are a prefix
-    int64_t s_end = s0;
-    for (int64_t s = s0; s < s1; s++) s_end += (crow[s] < i) ? 1 : 0;
-    if (nui == 0.0) s_end = s0;
-    int64_t found = 0;
-    int64_t wpos = 0;
-    if (kFill) wpos = out_pos[e];
-    for (int64_t s = s0; s < s_end; s++) {
-        const int32_t j = crow[s];
-        const double nuj = nu[j];
-        int64_t a = ia0, b = trp[j];
-        const int64_t b1 = trp[j + 1];
-        int32_t first = -1;
-        double d = 0.0;
-        while ((a < ia1) & (b < b1)) {
-            const int32_t ca = tci[a], cb = tci[b];
-            const double va = tv[a], vb = tv[b];
-            const bool eq = (ca == cb);
-            if (eq) d = d + va * vb;
-            first = (eq & (first < 0)) ? ca : first;
-            a += (ca <= cb) ? 1 : 0;
-            b += (cb <= ca) ? 1 : 0;
-        }
-        const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
-        const bool conflict = (first == c) & (nuj != 0.0) & (cs >= delta);
-        if (kFill && conflict) out_idx[wpos] = j;
-        wpos += conflict ? 1 : 0;
-        found += conflict ? 1 : 0;
+// Sparse rows of the Gram matrix A~ A~^T, one wavefront per row i (Section
+// 3.3, one-row blocks: |cos_ij| = |a_i . a_j| / sqrt(nu_i nu_j)).  The
+// candidates of row i are the rows j of its columns (below i for conflicts,
+// other than i for the group sums), listed entry by entry in ascending column
+// order and, within a column, in ascending row order; the CSC position of
+// entry (i, c) (cpos) gives the rows of column c below i without a search.
+// A row of at most 64 entries and kGramMaxCand candidates (counted with
+// repeats) gathers its candidates into LDS at once (all loads in flight
+// together), then adds a_ic a_jc into an LDS hash table keyed by j, one
+// column after the other, so that every d_ij = a_i . a_j is summed over the
+// common columns in ascending order -- the order of the pairwise dot
+// product.  Other rows take the pairwise path: 64 candidates at a time, one
+// lane each merges rows i and j, and the pair counts at its first common
+// column only.
+//   kGramCount: conflicts (rows j < i, nu_j != 0, |cos_ij| >= delta) per row;
+//   kGramFill:  the conflict lists at row_pos[i] (hash path: ascending j;
+//               pairwise path: in the order the candidates are listed);
+//   kGramCos:   sum over the rows j != i of i's group of |cos_ij| (the
+//               Gershgorin row sums of B_g B_g^T), at part[trp[i]].
+constexpr int kGramWaves = 4;
+constexpr int kGramSlots = 512;
+constexpr int kGramMaxCand = 384;
+enum : int { kGramCount = 0, kGramFill = 1, kGramCos = 2 };
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int d = 32; d > 0; d >>= 1) v = v + __shfl_xor(v, d, 64);
+    return v;
+}
+__device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t* total) {
+    int32_t incl = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
     }
-    if (!kFill) count[e] = found;
+    *total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+// the entry e of [0, ne) whose candidate range [eoff[e], eoff[e + 1]) holds q
+__device__ __forceinline__ int entry_of(const int32_t* eoff, int ne, int32_t q) {
+    int lo = 0, hi = ne;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (eoff[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct GramLds {
+    int32_t key[kGramSlots];
+    double val[kGramSlots];
+    int32_t cj[kGramMaxCand];        // candidate row, -1: not counted; later the conflict list
+    double cp[kGramMaxCand];         // its product a_ic a_jc
+    int32_t eoff[65];                // first candidate of each entry of the chunk
+    int32_t ecol[64];
+    int64_t es0[64];                 // CSC position of the entry's first candidate
+    double ea[64];
+};
+
+template <int kMode>
+__global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
+    int64_t n, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci, const double* __restrict__ tv,
+    const int64_t* __restrict__ cptr, const uint32_t* __restrict__ cpos, const int32_t* __restrict__ crow,
+    const double* __restrict__ cval, const double* __restrict__ nu, double delta, const int32_t* __restrict__ group,
+    int64_t* __restrict__ row_count, const int64_t* __restrict__ row_pos, int32_t* __restrict__ out_idx,
+    double* __restrict__ part) {
+    __shared__ GramLds lds_all[kGramWaves];
+    const int lane = threadIdx.x & 63;
+    GramLds& L = lds_all[threadIdx.x >> 6];
+    const int64_t row = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
+    if (row >= n) return;                    // whole wavefronts; no block barrier follows
+    const int32_t i = (int32_t)row;
+    const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+    const double nui = nu[i];
+    const int32_t gi = (kMode == kGramCos) ? group[i] : 0;
+    const bool idle = (ia0 == ia1) || ((kMode == kGramCos) ? (gi < 0) : (nui == 0.0));
+    if (idle) {
+        if (kMode == kGramCount && lane == 0) row_count[i] = 0;
+        return;                              // kGramCos: part is zero-filled
+    }
+    int64_t found = 0;                       // conflicts so far (pairwise path)
+    int64_t wpos = (kMode == kGramFill) ? row_pos[i] : 0;
+    double acc = 0.0;                        // |cos| sum of this lane (kGramCos)
+    bool first_chunk = true;
+    for (int64_t kb = ia0; kb < ia1; kb += 64) {
+        // this chunk's entries: one lane each
+        const int64_t k = kb + lane;
+        const int ne = (int)min<int64_t>(64, ia1 - kb);
+        int32_t cnt = 0, c = 0;
+        int64_t s0 = 0;
+        double a = 0.0;
+        if (k < ia1) {
+            c = tci[k];
+            a = tv[k];
+            s0 = cptr[c];
+            cnt = (kMode == kGramCos) ? (int32_t)(cptr[c + 1] - s0) : (int32_t)((int64_t)cpos[k] - s0);
+        }
+        int32_t total = 0;
+        const int32_t off = wave_excl_scan(cnt, lane, &total);
+        L.eoff[lane] = off;
+        if (lane == 63) L.eoff[64] = total;
+        L.ecol[lane] = c;
+        L.es0[lane] = s0;
+        L.ea[lane] = a;
+        wave_sync();
+        if (first_chunk && ia1 - ia0 <= 64 && total <= kGramMaxCand) {
+            // ---- hash path: the whole row is this chunk
+            for (int t = lane; t < kGramSlots; t += 64) L.key[t] = -1;
+            for (int32_t q = lane; q < total; q += 64) {
+                const int e = entry_of(L.eoff, ne, q);
+                const int64_t s = L.es0[e] + (q - L.eoff[e]);
+                const int32_t j = crow[s];
+                bool keep = j != i;
+                if (kMode == kGramCos) keep = keep && (group[j] == gi);
+                L.cj[q] = keep ? j : -1;
+                L.cp[q] = L.ea[e] * cval[s];
+            }
+            wave_sync();
+            for (int e = 0; e < ne; e++) {   // columns in ascending order
+                for (int32_t q = L.eoff[e] + lane; q < L.eoff[e + 1]; q += 64) {
+                    const int32_t j = L.cj[q];
+                    if (j < 0) continue;
+                    const double prod = L.cp[q];
+                    uint32_t h = ((uint32_t)j * 0x9E3779B1u) >> (32 - 9);
+                    for (;;) {
+                        const int32_t prev = atomicCAS(&L.key[h], -1, j);
+                        if (prev == -1) { L.val[h] = 0.0 + prod; break; }
+                        if (prev == j) { L.val[h] = L.val[h] + prod; break; }
+                        h = (h + 1) & (kGramSlots - 1);
+                    }
+                }
+                wave_sync();                 // column e's sums land before column e + 1's
+            }
+            if (kMode == kGramCos) {
+                for (int t = lane; t < kGramSlots; t += 64) {
+                    const int32_t j = L.key[t];
+                    if (j >= 0) acc = acc + fabs(L.val[t]) / __dsqrt_rn(nui * nu[j]);
+                }
+                acc = wave_sum_f64(acc);
+                if (lane == 0) part[ia0] = acc;
+                return;
+            }
+            uint32_t mine = 0;               // bit r: slot lane + 64 r conflicts
+            for (int r = 0; r < kGramSlots / 64; r++) {
+                const int t = lane + 64 * r;
+                const int32_t j = L.key[t];
+                bool conf = false;
+                if (j >= 0) {
+                    const double nuj = nu[j];
+                    const double cs = fabs(L.val[t]) / __dsqrt_rn(nui * nuj);
+                    conf = (nuj != 0.0) & (cs >= delta);
+                }
+                mine |= conf ? (1u << r) : 0u;
+            }
+            if (kMode == kGramCount) {
+                const int64_t cntc = wave_sum_i64(__popc(mine));
+                if (lane == 0) row_count[i] = cntc;
+                return;
+            }
+            // compact the conflicts into cj, then place each at its rank (ascending j)
+            int m = 0;
+            for (int r = 0; r < kGramSlots / 64; r++) {
+                const bool bit = (mine >> r) & 1u;
+                const uint64_t bal = __ballot(bit);
+                if (bit) L.cj[m + __popcll(bal & __lanemask_lt())] = L.key[lane + 64 * r];
+                m += __popcll(bal);
+            }
+            wave_sync();
+            for (int t = lane; t < m; t += 64) {
+                const int32_t j = L.cj[t];
+                int rank = 0;
+                for (int u = 0; u < m; u++) rank += L.cj[u] < j ? 1 : 0;
+                out_idx[wpos + rank] = j;
+            }
+            return;
+        }
+        first_chunk = false;
+        // ---- pairwise path: this chunk's candidates, 64 at a time
+        for (int32_t qb = 0; qb < total; qb += 64) {
+            const int32_t q = qb + lane;
+            bool hit = false;
+            int32_t j = -1;
+            if (q < total) {
+                const int e = entry_of(L.eoff, ne, q);
+                const int64_t s = L.es0[e] + (q - L.eoff[e]);
+                const int32_t ce = L.ecol[e];
+                j = crow[s];
+                const bool take = (j != i) && ((kMode == kGramCos) ? (group[j] == gi) : true);
+                if (take) {
+                    int64_t x = ia0, y = trp[j];
+                    const int64_t y1 = trp[j + 1];
+                    int32_t first = -1;
+                    double d = 0.0;
+                    while ((x < ia1) & (y < y1)) {
+                        const int32_t cx = tci[x], cy = tci[y];
+                        if (cx == cy) {
+                            d = d + tv[x] * tv[y];
+                            if (first < 0) first = cx;
+                        }
+                        x += (cx <= cy) ? 1 : 0;
+                        y += (cy <= cx) ? 1 : 0;
+                    }
+                    if (first == ce) {
+                        const double nuj = nu[j];
+                        const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
+                        if (kMode == kGramCos) acc = acc + cs;
+                        else hit = (nuj != 0.0) & (cs >= delta);
+                    }
+                }
+            }
+            if (kMode != kGramCos) {
+                const uint64_t bal = __ballot(hit);
+                if (kMode == kGramFill && hit) out_idx[wpos + __popcll(bal & __lanemask_lt())] = j;
+                wpos += __popcll(bal);
+                found += __popcll(bal);
+            }
+        }
+        wave_sync();                         // the chunk's LDS lists are read before the next chunk's
+    }
+    if (kMode == kGramCount && lane == 0) row_count[i] = found;
+    if (kMode == kGramCos) {
+        acc = wave_sum_f64(acc);
+        if (lane == 0) part[ia0] = acc;
+    }
 }
 
 // ------------------------------------------------- group Gram row sums
-// For the bound on the largest eigenvalue of B_g B_g^T (B_g: the rows of
-// group g scaled to unit norm): one thread per entry (i, c); over every other
-// row j of column c in i's group whose first column shared with row i is c,
-// the sum of |cos(a_i, a_j)| (complex: |a_i^H a_j| / (|a_i| |a_j|)).  Each
+// Complex systems (the real ones take k_row_gram<kGramCos>): one thread per
+// entry (i, c); over every other row j of column c in i's group whose first
+// column shared with row i is c, the sum of |a_i^H a_j| / (|a_i| |a_j|).  Each
 // pair of a row's Gram row is so counted at exactly one of its entries.
-template <bool kCplx>
 __global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
                             const double* __restrict__ tv, const double* __restrict__ tvi,
                             const int32_t* __restrict__ trow, const int64_t* __restrict__ cptr,
@@ -291,22 +480,15 @@ __global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const 
             double dr = 0.0, di = 0.0;
             while ((a < ia1) & (b < b1)) {
                 const int32_t ca = tci[a], cb = tci[b];
-                if (ca == cb) {
+                if (ca == cb) {      // conj(a_i) a_j
                     if (first < 0) first = ca;
-                    if (kCplx) {   // conj(a_i) a_j
-                        dr = dr + (tv[a] * tv[b] + tvi[a] * tvi[b]);
-                        di = di + (tv[a] * tvi[b] - tvi[a] * tv[b]);
-                    } else {
-                        dr = dr + tv[a] * tv[b];
-                    }
+                    dr = dr + (tv[a] * tv[b] + tvi[a] * tvi[b]);
+                    di = di + (tv[a] * tvi[b] - tvi[a] * tv[b]);
                 }
                 a += (ca <= cb) ? 1 : 0;
                 b += (cb <= ca) ? 1 : 0;
             }
-            if (first == c) {
-                const double mag = kCplx ? __dsqrt_rn(dr * dr + di * di) : fabs(dr);
-                acc = acc + mag / __dsqrt_rn(nui * nu[j]);
-            }
+            if (first == c) acc = acc + __dsqrt_rn(dr * dr + di * di) / __dsqrt_rn(nui * nu[j]);
         }
     }
     part[e] = acc;
@@ -760,6 +942,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     DevArray<int32_t> crow; crow.alloc(nnz);
     DevArray<double> cval; cval.alloc(nnz);
     DevArray<uint32_t> order; order.alloc(nnz);
+    DevArray<uint32_t> cpos; cpos.alloc(nnz);
     int64_t csc_total = 0;
     {
         DevArray<uint32_t> ckey; ckey.alloc(nnz);
@@ -775,6 +958,8 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         k_csc_fill<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), trow.get(), crow.get());
         OBK_HIP(hipGetLastError());
         k_gather_f64<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), tv.get(), cval.get());
+        OBK_HIP(hipGetLastError());
+        k_csc_pos<<<nblk(nnz), kT, 0, s>>>(nnz, order.get(), cpos.get());
         OBK_HIP(hipGetLastError());
     }
     DevArray<double> cval_im;
@@ -802,43 +987,53 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         tr.mark("conflicts");
         tr.mark("groups");
     } else {
-        DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
+        // per-row conflict counts, their exclusive scan (the row offsets of
+        // the lists, nconf at [n]), then the lists
+        DevArray<int64_t> rconf; rconf.alloc(n + 1);
+        DevArray<int32_t> cidx;
+        int64_t nconf = 0;
         if (cplx) {
+            DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
             z_conflicts(false, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
                         nu.get(), delta, ccount.get(), nullptr, nullptr, s);
-        } else {
-            k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                                        crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr);
-            OBK_HIP(hipGetLastError());
-        }
-        int64_t nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
-        P.nconflicts = nconf;
-        DevArray<int32_t> cidx; cidx.alloc(nconf);
-        if (cplx) {
+            nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
+            cidx.alloc(nconf);
             z_conflicts(true, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
                         nu.get(), delta, nullptr, ccount.get(), cidx.get(), s);
+            // row offsets: the exclusive count at the row's first entry
+            // (conflicts are emitted in entry order), nconf past the last entry
+            k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), rconf.get());
+            OBK_HIP(hipGetLastError());
+            sync_for_free(s);
         } else {
-            k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(), cptr.get(),
-                                                       crow.get(), nu.get(), delta, nullptr, ccount.get(),
-                                                       cidx.get());
+            const unsigned gb = (unsigned)std::max<int64_t>(1, (n + kGramWaves - 1) / kGramWaves);
+            if (n > 0)
+                k_row_gram<kGramCount><<<gb, kGramWaves * 64, 0, s>>>(n, trp.get(), tci.get(), tv.get(), cptr.get(),
+                                                                      cpos.get(), crow.get(), cval.get(), nu.get(),
+                                                                      delta, nullptr, rconf.get(), nullptr, nullptr,
+                                                                      nullptr);
+            OBK_HIP(hipGetLastError());
+            nconf = scan_exclusive_i64(rconf.get(), rconf.get(), n, s);
+            k_set_i64<<<1, 1, 0, s>>>(rconf.get() + n, nconf);
+            cidx.alloc(nconf);
+            if (n > 0 && nconf > 0)
+                k_row_gram<kGramFill><<<gb, kGramWaves * 64, 0, s>>>(n, trp.get(), tci.get(), tv.get(), cptr.get(),
+                                                                     cpos.get(), crow.get(), cval.get(), nu.get(),
+                                                                     delta, nullptr, nullptr, rconf.get(),
+                                                                     cidx.get(), nullptr);
             OBK_HIP(hipGetLastError());
         }
-
+        P.nconflicts = nconf;
         tr.mark("conflicts");
         // ---- a6: first-fit grouping on the host
-        // conflict offsets per row: the exclusive count at the row's first entry
-        // (conflicts are emitted in entry order), nconf past the last entry
-        DevArray<int64_t> cptr_rows; cptr_rows.alloc(n + 1);
-        k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), cptr_rows.get());
-        OBK_HIP(hipGetLastError());
-        std::vector<int64_t> hcptr = to_host(cptr_rows.get(), n + 1, s);
+        std::vector<int64_t> hcptr = to_host(rconf.get(), n + 1, s);
         std::vector<int32_t> hcidx = to_host(cidx.get(), nconf, s);
         std::vector<double> hnu = to_host(nu.get(), n, s);
         std::vector<uint8_t> active(n);
         for (int64_t i = 0; i < n; i++) active[i] = hnu[i] != 0.0;
         P.ngroups = host_first_fit(n, hcptr.data(), hcidx.data(), active.data(), group.data());
         P.h_group = group;
-        ccount = DevArray<int64_t>(); cidx = DevArray<int32_t>();
+        rconf = DevArray<int64_t>(); cidx = DevArray<int32_t>();
 
         tr.mark("groups");
     }
@@ -875,14 +1070,16 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         DevArray<unsigned long long> gmax; gmax.alloc(G);
         k_zero_u64<<<nblk(G), kT, 0, s>>>(G, gmax.get());
         if (nnz > 0) {
-            if (cplx)
-                k_group_cos<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(),
-                                                           trow.get(), cptr.get(), crow.get(), nu.get(),
-                                                           dgroup.get(), part.get());
-            else
-                k_group_cos<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), nullptr,
-                                                            trow.get(), cptr.get(), crow.get(), nu.get(),
-                                                            dgroup.get(), part.get());
+            if (cplx) {
+                k_group_cos<<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(),
+                                                     cptr.get(), crow.get(), nu.get(), dgroup.get(), part.get());
+            } else {
+                // one sum per row, at the row's first entry; the other entries hold 0
+                OBK_HIP(hipMemsetAsync(part.get(), 0, nnz * sizeof(double), s));
+                k_row_gram<kGramCos><<<(unsigned)((n + kGramWaves - 1) / kGramWaves), kGramWaves * 64, 0, s>>>(
+                    n, trp.get(), tci.get(), tv.get(), cptr.get(), cpos.get(), crow.get(), cval.get(), nu.get(),
+                    delta, dgroup.get(), nullptr, nullptr, nullptr, part.get());
+            }
             OBK_HIP(hipGetLastError());
         }
         if (m > 0)

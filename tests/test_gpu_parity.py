@@ -75,6 +75,9 @@ CASES = [
     ("c3-family-n20000", lambda: synth.c3(n=20000), 0.1, 10),
     ("c4-family-n7001", lambda: synth.c4_system(5, n=7001), 0.1, 10),
     ("arrow-long-row", _arrow, 0.1, 5),
+    # 20 entries per row: rows on both sides of the row Gram kernel's
+    # hash / pairwise switch (candidate rows counted with repeats)
+    ("random-rows-k19-hash-and-pairwise", lambda: synth.random_rows(4000, 19, 5), 0.1, 5),
     ("zero-rows-explicit-zeros", _zero_rows, 0.1, 30),
     ("identity", lambda: synth.from_dense(np.eye(33), f=np.arange(33.0)), 0.1, 1),
     ("n1", lambda: synth.from_dense(np.array([[2.0]]), f=np.array([6.0])), 0.1, 3),
