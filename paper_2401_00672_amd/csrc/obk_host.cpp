@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -57,12 +58,43 @@ UserAllocScope::~UserAllocScope() {
     g_user_stream = prev_stream;
 }
 
-AllocScope::AllocScope(hipStream_t s) : prev_stream(g_alloc_stream), prev_on(g_alloc_scoped) {
+namespace {
+// Buffers released inside the active AllocScope, by size class.
+struct ScopeCache {
+    hipStream_t stream = nullptr;
+    std::multimap<size_t, void*> blocks;
+};
+thread_local ScopeCache* g_scope_cache = nullptr;
+
+// Size classes: multiples of 256 B up to 4 KiB, then four per power of two
+// (at most 25% over the request).
+size_t size_class(size_t b) {
+    if (b <= 4096) return (b + 255) & ~(size_t)255;
+    const size_t p = (size_t)1 << (63 - __builtin_clzll((unsigned long long)b));
+    const size_t step = p / 4;
+    return (b + step - 1) / step * step;
+}
+}  // namespace
+
+AllocScope::AllocScope(hipStream_t s)
+    : prev_stream(g_alloc_stream), prev_on(g_alloc_scoped), prev_cache(g_scope_cache) {
     g_alloc_stream = s;
     g_alloc_scoped = true;
+    // a scope nested on the same stream shares the outer cache; on another
+    // stream it keeps none (a buffer of the outer scope may still be in use there)
+    if (!g_scope_cache || g_scope_cache->stream != s) {
+        g_scope_cache = (prev_cache && static_cast<ScopeCache*>(prev_cache)->stream != s) ? nullptr
+                                                                                         : new ScopeCache();
+        if (g_scope_cache) g_scope_cache->stream = s;
+    }
 }
 
 AllocScope::~AllocScope() {
+    if (g_scope_cache && g_scope_cache != prev_cache) {
+        for (auto& kv : g_scope_cache->blocks) (void)hipFreeAsync(kv.second, g_scope_cache->stream);
+        delete g_scope_cache;
+    }
+    g_scope_cache = static_cast<ScopeCache*>(prev_cache);
     g_alloc_stream = prev_stream;
     g_alloc_scoped = prev_on;
 }
@@ -109,13 +141,27 @@ void DevMem::alloc(size_t b) {
         return;
     }
     const bool use_pool = g_alloc_scoped;
-    hipError_t e = use_pool ? hipMallocAsync(&p, b, g_alloc_stream) : hipMalloc(&p, b);
+    size_t want = b;
+    if (use_pool && g_scope_cache) {
+        want = size_class(b);
+        auto it = g_scope_cache->blocks.find(want);
+        if (it != g_scope_cache->blocks.end()) {
+            ptr = it->second;
+            g_scope_cache->blocks.erase(it);
+            bytes = b;
+            cap = want;
+            pooled = true;
+            return;
+        }
+    }
+    hipError_t e = use_pool ? hipMallocAsync(&p, want, g_alloc_stream) : hipMalloc(&p, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(OBK_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
     }
     ptr = p;
     bytes = b;
+    cap = (use_pool && g_scope_cache) ? want : 0;
     pooled = use_pool;
 }
 
@@ -125,13 +171,16 @@ void DevMem::release() {
         if (g_user_alloc) (void)hipStreamSynchronize(g_user_stream);
         dealloc(ptr, ctx);
     } else if (ptr) {
-        if (pooled)
+        if (pooled && cap && g_alloc_scoped && g_scope_cache && g_scope_cache->stream == g_alloc_stream)
+            g_scope_cache->blocks.emplace(cap, ptr);       // kept for the scope's next request of its class
+        else if (pooled)
             (void)hipFreeAsync(ptr, g_alloc_scoped ? g_alloc_stream : nullptr);
         else
             (void)hipFree(ptr);
     }
     ptr = nullptr;
     bytes = 0;
+    cap = 0;
     pooled = false;
     dealloc = nullptr;
     ctx = nullptr;

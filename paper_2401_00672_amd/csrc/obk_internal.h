@@ -33,10 +33,17 @@ void set_last_error(const std::string& msg);
 // returned with hipFreeAsync: on the scope's stream while it is active, else on
 // the null stream, after the owner has synchronised the device (obk_free
 // does).  Plan building on one thread then never waits for work that other
-// threads run on the device, as a synchronous hipFree may.
+// threads run on the device, as a synchronous hipFree may.  Inside the scope,
+// a released buffer is kept by the scope (by size class) and serves the next
+// request of its class there: all of the scope's work runs on its stream, so
+// the new owner's work is ordered after the old owner's.  The pool's own
+// calls cost tens of microseconds each and serialise across threads; a plan
+// makes over a hundred temporaries.  The scope hands what it keeps back to
+// the pool when it ends.
 struct AllocScope {
     hipStream_t prev_stream;
     bool prev_on;
+    void* prev_cache;
     explicit AllocScope(hipStream_t s);
     ~AllocScope();
 };
@@ -65,20 +72,22 @@ struct UserAllocScope {
 struct DevMem {
     void* ptr = nullptr;
     size_t bytes = 0;
+    size_t cap = 0;          // block size when it came from an AllocScope's size classes
     bool pooled = false;
     void (*dealloc)(void*, void*) = nullptr;   // the caller's deallocator, when it came from alloc
     void* ctx = nullptr;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
-    DevMem(DevMem&& o) noexcept : ptr(o.ptr), bytes(o.bytes), pooled(o.pooled), dealloc(o.dealloc), ctx(o.ctx) {
-        o.ptr = nullptr; o.bytes = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
+    DevMem(DevMem&& o) noexcept
+        : ptr(o.ptr), bytes(o.bytes), cap(o.cap), pooled(o.pooled), dealloc(o.dealloc), ctx(o.ctx) {
+        o.ptr = nullptr; o.bytes = 0; o.cap = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
     }
     DevMem& operator=(DevMem&& o) noexcept {
         if (this != &o) {
             release();
-            ptr = o.ptr; bytes = o.bytes; pooled = o.pooled; dealloc = o.dealloc; ctx = o.ctx;
-            o.ptr = nullptr; o.bytes = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
+            ptr = o.ptr; bytes = o.bytes; cap = o.cap; pooled = o.pooled; dealloc = o.dealloc; ctx = o.ctx;
+            o.ptr = nullptr; o.bytes = 0; o.cap = 0; o.pooled = false; o.dealloc = nullptr; o.ctx = nullptr;
         }
         return *this;
     }
