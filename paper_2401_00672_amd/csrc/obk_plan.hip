@@ -264,12 +264,14 @@ __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t* 
     return incl - v;
 }
 // the entry e of [0, ne) whose candidate range [eoff[e], eoff[e + 1]) holds q
+// (ne <= 64; a fixed number of predicated halvings)
 __device__ __forceinline__ int entry_of(const int32_t* eoff, int ne, int32_t q) {
-    int lo = 0, hi = ne;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (eoff[mid] <= q) lo = mid;
-        else hi = mid;
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int c = lo + step;
+        const bool ok = (c < ne) & (eoff[c < 64 ? c : 64] <= q);
+        lo = ok ? c : lo;
     }
     return lo;
 }
@@ -285,6 +287,8 @@ struct GramLds {
     double ea[64];
 };
 
+// Written in predicated form (loads at clamped in-range indices, conditions
+// combined bitwise, per-row values wave-uniform), like every kernel here.
 template <int kMode>
 __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
     int64_t n, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci, const double* __restrict__ tv,
@@ -294,14 +298,15 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
     double* __restrict__ part) {
     __shared__ GramLds lds_all[kGramWaves];
     const int lane = threadIdx.x & 63;
-    GramLds& L = lds_all[threadIdx.x >> 6];
-    const int64_t row = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    GramLds& L = lds_all[w];
+    const int64_t row = (int64_t)blockIdx.x * kGramWaves + w;
     if (row >= n) return;                    // whole wavefronts; no block barrier follows
     const int32_t i = (int32_t)row;
     const int64_t ia0 = trp[i], ia1 = trp[i + 1];
     const double nui = nu[i];
     const int32_t gi = (kMode == kGramCos) ? group[i] : 0;
-    const bool idle = (ia0 == ia1) || ((kMode == kGramCos) ? (gi < 0) : (nui == 0.0));
+    const bool idle = (ia0 == ia1) | ((kMode == kGramCos) ? (gi < 0) : (nui == 0.0));
     if (idle) {
         if (kMode == kGramCount && lane == 0) row_count[i] = 0;
         return;                              // kGramCos: part is zero-filled
@@ -309,52 +314,66 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
     int64_t found = 0;                       // conflicts so far (pairwise path)
     int64_t wpos = (kMode == kGramFill) ? row_pos[i] : 0;
     double acc = 0.0;                        // |cos| sum of this lane (kGramCos)
-    bool first_chunk = true;
     for (int64_t kb = ia0; kb < ia1; kb += 64) {
         // this chunk's entries: one lane each
-        const int64_t k = kb + lane;
         const int ne = (int)min<int64_t>(64, ia1 - kb);
-        int32_t cnt = 0, c = 0;
-        int64_t s0 = 0;
-        double a = 0.0;
-        if (k < ia1) {
-            c = tci[k];
-            a = tv[k];
-            s0 = cptr[c];
-            cnt = (kMode == kGramCos) ? (int32_t)(cptr[c + 1] - s0) : (int32_t)((int64_t)cpos[k] - s0);
-        }
+        const bool kin = lane < ne;
+        const int64_t k = kb + (kin ? lane : ne - 1);
+        const int32_t c = tci[k];
+        const double a = tv[k];
+        const int64_t s0 = cptr[c];
+        const int64_t s1 = cptr[c + 1];
+        const int64_t pk = (int64_t)cpos[k];
+        const int32_t cnt = kin ? (int32_t)((kMode == kGramCos) ? (s1 - s0) : (pk - s0)) : 0;
         int32_t total = 0;
         const int32_t off = wave_excl_scan(cnt, lane, &total);
+        total = __builtin_amdgcn_readfirstlane(total);
         L.eoff[lane] = off;
         if (lane == 63) L.eoff[64] = total;
         L.ecol[lane] = c;
         L.es0[lane] = s0;
         L.ea[lane] = a;
         wave_sync();
-        if (first_chunk && ia1 - ia0 <= 64 && total <= kGramMaxCand) {
+        if ((kb == ia0) & (ia1 - ia0 <= 64) & (total <= kGramMaxCand)) {
             // ---- hash path: the whole row is this chunk
             for (int t = lane; t < kGramSlots; t += 64) L.key[t] = -1;
-            for (int32_t q = lane; q < total; q += 64) {
-                const int e = entry_of(L.eoff, ne, q);
-                const int64_t s = L.es0[e] + (q - L.eoff[e]);
-                const int32_t j = crow[s];
-                bool keep = j != i;
-                if (kMode == kGramCos) keep = keep && (group[j] == gi);
-                L.cj[q] = keep ? j : -1;
-                L.cp[q] = L.ea[e] * cval[s];
+            for (int32_t qb = 0; qb < total; qb += 64) {
+                const int32_t q = qb + lane;
+                const bool valid = q < total;
+                const int32_t qc = valid ? q : total - 1;
+                const int e = entry_of(L.eoff, ne, qc);
+                const int64_t sp = L.es0[e] + (qc - L.eoff[e]);
+                const int32_t j = crow[sp];
+                const double cv = cval[sp];
+                const int32_t gj = (kMode == kGramCos) ? group[j] : gi;
+                const bool keep = (j != i) & (gj == gi);
+                if (valid) {
+                    L.cj[q] = keep ? j : -1;
+                    L.cp[q] = L.ea[e] * cv;
+                }
             }
             wave_sync();
             for (int e = 0; e < ne; e++) {   // columns in ascending order
-                for (int32_t q = L.eoff[e] + lane; q < L.eoff[e + 1]; q += 64) {
-                    const int32_t j = L.cj[q];
-                    if (j < 0) continue;
-                    const double prod = L.cp[q];
-                    uint32_t h = ((uint32_t)j * 0x9E3779B1u) >> (32 - 9);
-                    for (;;) {
-                        const int32_t prev = atomicCAS(&L.key[h], -1, j);
-                        if (prev == -1) { L.val[h] = 0.0 + prod; break; }
-                        if (prev == j) { L.val[h] = L.val[h] + prod; break; }
-                        h = (h + 1) & (kGramSlots - 1);
+                const int32_t q0 = __builtin_amdgcn_readfirstlane(L.eoff[e]);
+                const int32_t q1 = __builtin_amdgcn_readfirstlane(L.eoff[e + 1]);
+                for (int32_t qb = q0; qb < q1; qb += 64) {
+                    const int32_t q = qb + lane;
+                    const bool valid = q < q1;
+                    const int32_t qc = valid ? q : q1 - 1;
+                    const int32_t j = L.cj[qc];
+                    const double prod = L.cp[qc];
+                    if (valid & (j >= 0)) {
+                        uint32_t h = ((uint32_t)j * 0x9E3779B1u) >> (32 - 9);
+                        bool done = false;
+                        do {
+                            const int32_t prev = atomicCAS(&L.key[h], -1, j);
+                            const bool fresh = prev == -1;
+                            const bool hit = fresh | (prev == j);
+                            const double old = L.val[h];
+                            if (hit) L.val[h] = (fresh ? 0.0 : old) + prod;
+                            done = hit;
+                            h = hit ? h : ((h + 1) & (kGramSlots - 1));
+                        } while (!done);
                     }
                 }
                 wave_sync();                 // column e's sums land before column e + 1's
@@ -362,22 +381,22 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
             if (kMode == kGramCos) {
                 for (int t = lane; t < kGramSlots; t += 64) {
                     const int32_t j = L.key[t];
-                    if (j >= 0) acc = acc + fabs(L.val[t]) / __dsqrt_rn(nui * nu[j]);
+                    const double nuj = nu[j >= 0 ? j : i];
+                    const double term = fabs(L.val[t]) / __dsqrt_rn(nui * nuj);
+                    acc = (j >= 0) ? acc + term : acc;
                 }
                 acc = wave_sum_f64(acc);
                 if (lane == 0) part[ia0] = acc;
                 return;
             }
             uint32_t mine = 0;               // bit r: slot lane + 64 r conflicts
+#pragma unroll
             for (int r = 0; r < kGramSlots / 64; r++) {
                 const int t = lane + 64 * r;
                 const int32_t j = L.key[t];
-                bool conf = false;
-                if (j >= 0) {
-                    const double nuj = nu[j];
-                    const double cs = fabs(L.val[t]) / __dsqrt_rn(nui * nuj);
-                    conf = (nuj != 0.0) & (cs >= delta);
-                }
+                const double nuj = nu[j >= 0 ? j : i];
+                const double cs = fabs(L.val[t]) / __dsqrt_rn(nui * nuj);
+                const bool conf = (j >= 0) & (nuj != 0.0) & (cs >= delta);
                 mine |= conf ? (1u << r) : 0u;
             }
             if (kMode == kGramCount) {
@@ -387,6 +406,7 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
             }
             // compact the conflicts into cj, then place each at its rank (ascending j)
             int m = 0;
+#pragma unroll
             for (int r = 0; r < kGramSlots / 64; r++) {
                 const bool bit = (mine >> r) & 1u;
                 const uint64_t bal = __ballot(bit);
@@ -394,51 +414,49 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
                 m += __popcll(bal);
             }
             wave_sync();
-            for (int t = lane; t < m; t += 64) {
-                const int32_t j = L.cj[t];
+            for (int tb = 0; tb < m; tb += 64) {
+                const int t = tb + lane;
+                const bool valid = t < m;
+                const int32_t j = L.cj[valid ? t : 0];
                 int rank = 0;
                 for (int u = 0; u < m; u++) rank += L.cj[u] < j ? 1 : 0;
-                out_idx[wpos + rank] = j;
+                if (valid) out_idx[wpos + rank] = j;
             }
             return;
         }
-        first_chunk = false;
         // ---- pairwise path: this chunk's candidates, 64 at a time
         for (int32_t qb = 0; qb < total; qb += 64) {
             const int32_t q = qb + lane;
-            bool hit = false;
-            int32_t j = -1;
-            if (q < total) {
-                const int e = entry_of(L.eoff, ne, q);
-                const int64_t s = L.es0[e] + (q - L.eoff[e]);
-                const int32_t ce = L.ecol[e];
-                j = crow[s];
-                const bool take = (j != i) && ((kMode == kGramCos) ? (group[j] == gi) : true);
-                if (take) {
-                    int64_t x = ia0, y = trp[j];
-                    const int64_t y1 = trp[j + 1];
-                    int32_t first = -1;
-                    double d = 0.0;
-                    while ((x < ia1) & (y < y1)) {
-                        const int32_t cx = tci[x], cy = tci[y];
-                        if (cx == cy) {
-                            d = d + tv[x] * tv[y];
-                            if (first < 0) first = cx;
-                        }
-                        x += (cx <= cy) ? 1 : 0;
-                        y += (cy <= cx) ? 1 : 0;
-                    }
-                    if (first == ce) {
-                        const double nuj = nu[j];
-                        const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
-                        if (kMode == kGramCos) acc = acc + cs;
-                        else hit = (nuj != 0.0) & (cs >= delta);
-                    }
-                }
+            const bool valid = q < total;
+            const int32_t qc = valid ? q : total - 1;
+            const int e = entry_of(L.eoff, ne, qc);
+            const int64_t sp = L.es0[e] + (qc - L.eoff[e]);
+            const int32_t ce = L.ecol[e];
+            const int32_t j = crow[sp];
+            const int32_t gj = (kMode == kGramCos) ? group[j] : gi;
+            const bool take = valid & (j != i) & (gj == gi);
+            int64_t x = ia0, y = trp[j];
+            const int64_t y1 = take ? trp[j + 1] : y;
+            int32_t first = -1;
+            double d = 0.0;
+            while ((x < ia1) & (y < y1)) {
+                const int32_t cx = tci[x], cy = tci[y];
+                const double vx = tv[x], vy = tv[y];
+                const bool eq = cx == cy;
+                d = eq ? d + vx * vy : d;
+                first = (eq & (first < 0)) ? cx : first;
+                x += (cx <= cy) ? 1 : 0;
+                y += (cy <= cx) ? 1 : 0;
             }
-            if (kMode != kGramCos) {
+            const double nuj = nu[j];
+            const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
+            const bool counted = take & (first == ce);
+            if (kMode == kGramCos) {
+                acc = counted ? acc + cs : acc;
+            } else {
+                const bool hit = counted & (nuj != 0.0) & (cs >= delta);
                 const uint64_t bal = __ballot(hit);
-                if (kMode == kGramFill && hit) out_idx[wpos + __popcll(bal & __lanemask_lt())] = j;
+                if ((kMode == kGramFill) & hit) out_idx[wpos + __popcll(bal & __lanemask_lt())] = j;
                 wpos += __popcll(bal);
                 found += __popcll(bal);
             }
