@@ -237,13 +237,13 @@ OBK_API obk_status obk_solve_noalloc(obk_plan_t plan, const double *x0, double t
 
 /* Release a plan and its device memory.  NULL is a no-op. */
 OBK_API void obk_free(obk_plan_t plan);
-/* Release a plan without waiting for the device (obk_free waits for all of
- * it): the plan's pool memory goes back in stream order on `stream`
- * (hipFreeAsync), so the call returns at once.  The caller guarantees that
- * every piece of work that uses the plan has completed or is queued on
- * `stream`.  Memory from the caller's allocator (opts.alloc) is handed back
- * after a synchronisation of `stream`.  NULL is a no-op; OBK_E_BUSY (the plan
- * is kept) while a solve on the plan runs. */
+/* Release a plan waiting only for `stream` (obk_free waits for the whole
+ * device): the caller guarantees that every piece of work that uses the plan
+ * has completed or is queued on `stream`.  Once `stream` is idle the plan's
+ * pool memory is kept by the library for later plans (at most 1 GiB in all,
+ * the rest goes back to the pool); memory from the caller's allocator
+ * (opts.alloc) is handed back through dealloc.  NULL is a no-op; OBK_E_BUSY
+ * (the plan is kept) while a solve on the plan runs. */
 OBK_API obk_status obk_free_async(obk_plan_t plan, obk_stream_t stream);
 
 /*

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -62,9 +63,26 @@ namespace {
 // Buffers released inside the active AllocScope, by size class.
 struct ScopeCache {
     hipStream_t stream = nullptr;
+    int device = 0;
     std::multimap<size_t, void*> blocks;
 };
 thread_local ScopeCache* g_scope_cache = nullptr;
+
+// Pool blocks that no queued work uses any more (the stream of their last use
+// was synchronised), by (device, size class), shared by every thread: a
+// scope takes from here before it asks the pool and leaves its blocks here
+// when it ends.  At most kIdleCap bytes are kept; beyond that blocks go back
+// to the pool.
+constexpr size_t kIdleCap = (size_t)1 << 30;
+struct IdleBlocks {
+    std::mutex mu;
+    std::multimap<std::pair<int, size_t>, void*> blocks;
+    size_t bytes = 0;
+};
+IdleBlocks& idle_blocks() {
+    static IdleBlocks* b = new IdleBlocks();   // never destroyed: kept blocks may outlive static destruction
+    return *b;
+}
 
 // Size classes: multiples of 256 B up to 4 KiB, then four per power of two
 // (at most 25% over the request).
@@ -85,14 +103,33 @@ AllocScope::AllocScope(hipStream_t s)
     if (!g_scope_cache || g_scope_cache->stream != s) {
         g_scope_cache = (prev_cache && static_cast<ScopeCache*>(prev_cache)->stream != s) ? nullptr
                                                                                          : new ScopeCache();
-        if (g_scope_cache) g_scope_cache->stream = s;
+        if (g_scope_cache) {
+            g_scope_cache->stream = s;
+            if (hipGetDevice(&g_scope_cache->device) != hipSuccess) (void)hipGetLastError();
+        }
     }
 }
 
 AllocScope::~AllocScope() {
     if (g_scope_cache && g_scope_cache != prev_cache) {
-        for (auto& kv : g_scope_cache->blocks) (void)hipFreeAsync(kv.second, g_scope_cache->stream);
-        delete g_scope_cache;
+        ScopeCache* c = g_scope_cache;
+        if (!c->blocks.empty()) {
+            // once the scope's stream is idle its blocks are free of any queued
+            // use and may serve any later scope, on any stream of the device
+            const bool idle = hipStreamSynchronize(c->stream) == hipSuccess;
+            if (!idle) (void)hipGetLastError();
+            IdleBlocks& ib = idle_blocks();
+            std::lock_guard<std::mutex> lk(ib.mu);
+            for (auto& kv : c->blocks) {
+                if (idle && ib.bytes + kv.first <= kIdleCap) {
+                    ib.blocks.emplace(std::make_pair(c->device, kv.first), kv.second);
+                    ib.bytes += kv.first;
+                } else {
+                    (void)hipFreeAsync(kv.second, c->stream);
+                }
+            }
+        }
+        delete c;
     }
     g_scope_cache = static_cast<ScopeCache*>(prev_cache);
     g_alloc_stream = prev_stream;
@@ -144,10 +181,23 @@ void DevMem::alloc(size_t b) {
     size_t want = b;
     if (use_pool && g_scope_cache) {
         want = size_class(b);
+        void* hit = nullptr;
         auto it = g_scope_cache->blocks.find(want);
         if (it != g_scope_cache->blocks.end()) {
-            ptr = it->second;
+            hit = it->second;
             g_scope_cache->blocks.erase(it);
+        } else {
+            IdleBlocks& ib = idle_blocks();
+            std::lock_guard<std::mutex> lk(ib.mu);
+            auto jt = ib.blocks.find(std::make_pair(g_scope_cache->device, want));
+            if (jt != ib.blocks.end()) {
+                hit = jt->second;
+                ib.blocks.erase(jt);
+                ib.bytes -= want;
+            }
+        }
+        if (hit) {
+            ptr = hit;
             bytes = b;
             cap = want;
             pooled = true;

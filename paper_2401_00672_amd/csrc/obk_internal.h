@@ -38,8 +38,10 @@ void set_last_error(const std::string& msg);
 // request of its class there: all of the scope's work runs on its stream, so
 // the new owner's work is ordered after the old owner's.  The pool's own
 // calls cost tens of microseconds each and serialise across threads; a plan
-// makes over a hundred temporaries.  The scope hands what it keeps back to
-// the pool when it ends.
+// makes over a hundred temporaries.  When the scope ends it synchronises its
+// stream and leaves what it keeps to a process-wide store of idle blocks (at
+// most 1 GiB, by device and size class), from which later scopes on any
+// thread and stream take before they ask the pool.
 struct AllocScope {
     hipStream_t prev_stream;
     bool prev_on;
