@@ -753,7 +753,7 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=512, help="c5: requests in the sample")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="c5: device-memory admission budget")
     ap.add_argument("--planners", type=int, default=4, help="c5: planner threads")
-    ap.add_argument("--rcm-engine", default="host", choices=["auto", "device", "host"],
+    ap.add_argument("--rcm-engine", default="auto", choices=["auto", "device", "host"],
                     help="c5: how each request's plan forms its RCM order")
     ap.add_argument("--max-steps", type=int, default=200, help="c5: refinement steps before a request gives up")
     ap.add_argument("--c5-new-batch-objects", action="store_true",
