@@ -183,6 +183,12 @@ OBK_API obk_status obk_opts_default(obk_opts *opts);
  * n_cols) (Section 4, Algorithms 5 and 6): row_ptr and f hold n_rows (+1)
  * entries, columns must be below n_cols, and the introspection calls below
  * (perm, groups, stats) describe the extended system.
+ * Device memory (without opts.alloc): the plan's buffers and its temporaries
+ * come from the device's stream-ordered pool on `stream`; a temporary released
+ * during planning serves the plan's next request of its size class, and when
+ * planning ends (with `stream` synchronised) those the plan no longer uses are
+ * kept by the library, at most 1 GiB per process, for later plans on any
+ * thread and stream of the device.
  * Errors: OBK_E_ARG, OBK_E_CSR, OBK_E_NONFINITE, OBK_E_NOMEM, OBK_E_HIP,
  * OBK_E_INCONSISTENT.
  */
