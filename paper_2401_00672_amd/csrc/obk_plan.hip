@@ -216,7 +216,112 @@ __global__ void k_csc_pos(int64_t nnz, const uint32_t* __restrict__ order, uint3
     if (k < nnz) cpos[order[k]] = (uint32_t)k;
 }
 
-// --------------------------------------------------------- cosine pass
+// ------------------------------------------ cosine pass, per entry
+// Plans of short rows (fewer than kGramMinRowLen entries per row on
+// average) take these kernels: a wavefront per row would leave most lanes
+// idle, while one thread per entry keeps the device full.
+// One thread per entry (i, c) of A~.  For every row j < i stored in column c,
+// the sparse dot a_i . a_j is taken over the common columns in ascending
+// order; the pair is handled only by the entry of its first common column,
+// so each pair is evaluated once.  |cos| = |d| / sqrt(nu_i * nu_j) (Section
+// 3.3, one-row blocks); the pair conflicts iff |cos| >= delta.
+template <bool kFill>
+__global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
+                            const double* __restrict__ tv, const int32_t* __restrict__ trow,
+                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ crow,
+                            const double* __restrict__ nu, double delta, int64_t* __restrict__ count,
+                            const int64_t* __restrict__ out_pos, int32_t* __restrict__ out_idx) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t i = trow[e];
+    const int32_t c = tci[e];
+    const double nui = nu[i];
+    const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+    const int64_t s0 = cptr[c], s1 = cptr[c + 1];
+    // rows of column c are ascending: those below i are a prefix
+    int64_t s_end = s0;
+    for (int64_t s = s0; s < s1; s++) s_end += (crow[s] < i) ? 1 : 0;
+    if (nui == 0.0) s_end = s0;
+    int64_t found = 0;
+    int64_t wpos = 0;
+    if (kFill) wpos = out_pos[e];
+    for (int64_t s = s0; s < s_end; s++) {
+        const int32_t j = crow[s];
+        const double nuj = nu[j];
+        int64_t a = ia0, b = trp[j];
+        const int64_t b1 = trp[j + 1];
+        int32_t first = -1;
+        double d = 0.0;
+        while ((a < ia1) & (b < b1)) {
+            const int32_t ca = tci[a], cb = tci[b];
+            const double va = tv[a], vb = tv[b];
+            const bool eq = (ca == cb);
+            if (eq) d = d + va * vb;
+            first = (eq & (first < 0)) ? ca : first;
+            a += (ca <= cb) ? 1 : 0;
+            b += (cb <= ca) ? 1 : 0;
+        }
+        const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
+        const bool conflict = (first == c) & (nuj != 0.0) & (cs >= delta);
+        if (kFill && conflict) out_idx[wpos] = j;
+        wpos += conflict ? 1 : 0;
+        found += conflict ? 1 : 0;
+    }
+    if (!kFill) count[e] = found;
+}
+
+// ------------------------------------------------- group Gram row sums
+// For the bound on the largest eigenvalue of B_g B_g^T (B_g: the rows of
+// group g scaled to unit norm): one thread per entry (i, c); over every other
+// row j of column c in i's group whose first column shared with row i is c,
+// the sum of |cos(a_i, a_j)| (complex: |a_i^H a_j| / (|a_i| |a_j|)).  Each
+// pair of a row's Gram row is so counted at exactly one of its entries.
+template <bool kCplx>
+__global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
+                            const double* __restrict__ tv, const double* __restrict__ tvi,
+                            const int32_t* __restrict__ trow, const int64_t* __restrict__ cptr,
+                            const int32_t* __restrict__ crow, const double* __restrict__ nu,
+                            const int32_t* __restrict__ group, double* __restrict__ part) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t i = trow[e];
+    const int32_t c = tci[e];
+    const int32_t gi = group[i];
+    double acc = 0.0;
+    if (gi >= 0) {
+        const double nui = nu[i];
+        const int64_t ia0 = trp[i], ia1 = trp[i + 1];
+        for (int64_t s = cptr[c]; s < cptr[c + 1]; s++) {
+            const int32_t j = crow[s];
+            if ((j == i) | (group[j] != gi)) continue;
+            int64_t a = ia0, b = trp[j];
+            const int64_t b1 = trp[j + 1];
+            int32_t first = -1;
+            double dr = 0.0, di = 0.0;
+            while ((a < ia1) & (b < b1)) {
+                const int32_t ca = tci[a], cb = tci[b];
+                if (ca == cb) {
+                    if (first < 0) first = ca;
+                    if (kCplx) {   // conj(a_i) a_j
+                        dr = dr + (tv[a] * tv[b] + tvi[a] * tvi[b]);
+                        di = di + (tv[a] * tvi[b] - tvi[a] * tv[b]);
+                    } else {
+                        dr = dr + tv[a] * tv[b];
+                    }
+                }
+                a += (ca <= cb) ? 1 : 0;
+                b += (cb <= ca) ? 1 : 0;
+            }
+            if (first == c) {
+                const double mag = kCplx ? __dsqrt_rn(dr * dr + di * di) : fabs(dr);
+                acc = acc + mag / __dsqrt_rn(nui * nu[j]);
+            }
+        }
+    }
+    part[e] = acc;
+}
+
+// ------------------------------------------ cosine pass, per row
 // Sparse rows of the Gram matrix A~ A~^T, one wavefront per row i (Section
 // 3.3, one-row blocks: |cos_ij| = |a_i . a_j| / sqrt(nu_i nu_j)).  The
 // candidates of row i are the rows j of its columns (below i for conflicts,
@@ -237,6 +342,7 @@ __global__ void k_csc_pos(int64_t nnz, const uint32_t* __restrict__ order, uint3
 //   kGramCos:   sum over the rows j != i of i's group of |cos_ij| (the
 //               Gershgorin row sums of B_g B_g^T), at part[trp[i]].
 constexpr int kGramWaves = 4;
+constexpr int kGramMinRowLen = 7;    // plans with fewer entries per row on average: per-entry kernels
 constexpr int kGramSlots = 512;
 constexpr int kGramMaxCand = 384;
 enum : int { kGramCount = 0, kGramFill = 1, kGramCos = 2 };
@@ -468,48 +574,6 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
         acc = wave_sum_f64(acc);
         if (lane == 0) part[ia0] = acc;
     }
-}
-
-// ------------------------------------------------- group Gram row sums
-// Complex systems (the real ones take k_row_gram<kGramCos>): one thread per
-// entry (i, c); over every other row j of column c in i's group whose first
-// column shared with row i is c, the sum of |a_i^H a_j| / (|a_i| |a_j|).  Each
-// pair of a row's Gram row is so counted at exactly one of its entries.
-__global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
-                            const double* __restrict__ tv, const double* __restrict__ tvi,
-                            const int32_t* __restrict__ trow, const int64_t* __restrict__ cptr,
-                            const int32_t* __restrict__ crow, const double* __restrict__ nu,
-                            const int32_t* __restrict__ group, double* __restrict__ part) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nnz) return;
-    const int32_t i = trow[e];
-    const int32_t c = tci[e];
-    const int32_t gi = group[i];
-    double acc = 0.0;
-    if (gi >= 0) {
-        const double nui = nu[i];
-        const int64_t ia0 = trp[i], ia1 = trp[i + 1];
-        for (int64_t s = cptr[c]; s < cptr[c + 1]; s++) {
-            const int32_t j = crow[s];
-            if ((j == i) | (group[j] != gi)) continue;
-            int64_t a = ia0, b = trp[j];
-            const int64_t b1 = trp[j + 1];
-            int32_t first = -1;
-            double dr = 0.0, di = 0.0;
-            while ((a < ia1) & (b < b1)) {
-                const int32_t ca = tci[a], cb = tci[b];
-                if (ca == cb) {      // conj(a_i) a_j
-                    if (first < 0) first = ca;
-                    dr = dr + (tv[a] * tv[b] + tvi[a] * tvi[b]);
-                    di = di + (tv[a] * tvi[b] - tvi[a] * tv[b]);
-                }
-                a += (ca <= cb) ? 1 : 0;
-                b += (cb <= ca) ? 1 : 0;
-            }
-            if (first == c) acc = acc + __dsqrt_rn(dr * dr + di * di) / __dsqrt_rn(nui * nu[j]);
-        }
-    }
-    part[e] = acc;
 }
 
 // 1 + the row's sum, folded into its group's maximum (non-negative doubles
@@ -1006,18 +1070,33 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         tr.mark("groups");
     } else {
         // per-row conflict counts, their exclusive scan (the row offsets of
-        // the lists, nconf at [n]), then the lists
+        // the lists, nconf at [n]), then the lists; plans of short rows take
+        // one thread per entry instead of a wavefront per row
+        const bool per_row_gram = nnz >= (int64_t)kGramMinRowLen * n;
         DevArray<int64_t> rconf; rconf.alloc(n + 1);
         DevArray<int32_t> cidx;
         int64_t nconf = 0;
-        if (cplx) {
+        if (cplx || !per_row_gram) {
+            // one thread per entry: counts per entry, their scan, the lists
             DevArray<int64_t> ccount; ccount.alloc(nnz + 1);
-            z_conflicts(false, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
-                        nu.get(), delta, ccount.get(), nullptr, nullptr, s);
+            if (cplx)
+                z_conflicts(false, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(),
+                            crow.get(), nu.get(), delta, ccount.get(), nullptr, nullptr, s);
+            else if (nnz > 0)
+                k_conflicts<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(),
+                                                            cptr.get(), crow.get(), nu.get(), delta, ccount.get(),
+                                                            nullptr, nullptr);
+            OBK_HIP(hipGetLastError());
             nconf = scan_exclusive_i64(ccount.get(), ccount.get(), nnz, s);
             cidx.alloc(nconf);
-            z_conflicts(true, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(), crow.get(),
-                        nu.get(), delta, nullptr, ccount.get(), cidx.get(), s);
+            if (cplx)
+                z_conflicts(true, nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(), cptr.get(),
+                            crow.get(), nu.get(), delta, nullptr, ccount.get(), cidx.get(), s);
+            else if (nnz > 0)
+                k_conflicts<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), trow.get(),
+                                                           cptr.get(), crow.get(), nu.get(), delta, nullptr,
+                                                           ccount.get(), cidx.get());
+            OBK_HIP(hipGetLastError());
             // row offsets: the exclusive count at the row's first entry
             // (conflicts are emitted in entry order), nconf past the last entry
             k_row_conflict_ptr<<<nblk(n + 1), kT, 0, s>>>(n, nnz, nconf, trp.get(), ccount.get(), rconf.get());
@@ -1089,8 +1168,13 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
         k_zero_u64<<<nblk(G), kT, 0, s>>>(G, gmax.get());
         if (nnz > 0) {
             if (cplx) {
-                k_group_cos<<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(), trow.get(),
-                                                     cptr.get(), crow.get(), nu.get(), dgroup.get(), part.get());
+                k_group_cos<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(),
+                                                           trow.get(), cptr.get(), crow.get(), nu.get(),
+                                                           dgroup.get(), part.get());
+            } else if (nnz < (int64_t)kGramMinRowLen * n) {
+                k_group_cos<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), nullptr,
+                                                            trow.get(), cptr.get(), crow.get(), nu.get(),
+                                                            dgroup.get(), part.get());
             } else {
                 // one sum per row, at the row's first entry; the other entries hold 0
                 OBK_HIP(hipMemsetAsync(part.get(), 0, nnz * sizeof(double), s));

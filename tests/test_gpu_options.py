@@ -153,17 +153,20 @@ def test_caller_allocator(kw):
     assert np.array_equal(x, y)
 
 
-def _arrow_system(n=3000, seed=3):
-    """Diagonal plus one dense row and one dense column: every row shares the
-    dense column with all the others (the row Gram kernel's pairwise path)."""
+def _dense_cross(n=3000, k_off=8, seed=4):
+    """Nine entries per row (so the plan takes the per-row Gram kernel) plus
+    one dense row and one dense column: every row shares the dense column
+    with all the others, more candidates than the kernel's LDS table holds
+    (its pairwise path)."""
     import scipy.sparse as sp
     rng = np.random.default_rng(seed)
-    A = sp.lil_matrix((n, n))
-    A.setdiag(rng.uniform(1, 2, n) + n ** 0.5)
+    A = synth.random_rows(n, k_off, seed).scipy().tolil()
     A[0, :] = rng.standard_normal(n)
     A[:, 0] = rng.standard_normal((n, 1))
     A[0, 0] = n
-    return synth.from_scipy(A.tocsr(), rng.standard_normal(n), name="arrow")
+    A = A.tocsr()
+    A.sort_indices()
+    return synth.from_scipy(A, rng.standard_normal(n), name="dense-cross")
 
 
 LAMBDA_CASES = [
@@ -173,7 +176,7 @@ LAMBDA_CASES = [
     ("scattered-20000", lambda: synth.c3(n=20000), 0.1, False),
     ("random-rows-delta0.4", lambda: synth.random_rows(3000, 6, 11), 0.4, False),
     ("random-rows-k19-hash-and-pairwise", lambda: synth.random_rows(4000, 19, 5), 0.1, False),
-    ("arrow-pairwise", lambda: _arrow_system(), 0.1, False),
+    ("dense-cross-pairwise", lambda: _dense_cross(), 0.1, False),
     ("zero-rows", lambda: synth.from_dense(np.diag([2.0, 0.0, 1.0, 0.0, 3.0])), 0.1, False),
     ("c1z", lambda: synth.c1z(), 0.1, True),
     ("c2z-grid64", lambda: synth.c2z(grid=64), 0.1, True),

@@ -53,6 +53,19 @@ def _arrow(n=3000, seed=3):
     return synth.from_scipy(A.tocsr(), rng.standard_normal(n), name="arrow")
 
 
+def _dense_cross(n=3000, k_off=8, seed=4):
+    """Nine entries per row plus one dense row and one dense column: the
+    per-row Gram kernel, every row with more candidates than its LDS table."""
+    rng = np.random.default_rng(seed)
+    A = synth.random_rows(n, k_off, seed).scipy().tolil()
+    A[0, :] = rng.standard_normal(n)
+    A[:, 0] = rng.standard_normal((n, 1))
+    A[0, 0] = n
+    A = A.tocsr()
+    A.sort_indices()
+    return synth.from_scipy(A, rng.standard_normal(n), name="dense-cross")
+
+
 def _zero_rows():
     s = synth.c1(n=300)
     A = s.scipy().tolil()
@@ -75,9 +88,11 @@ CASES = [
     ("c3-family-n20000", lambda: synth.c3(n=20000), 0.1, 10),
     ("c4-family-n7001", lambda: synth.c4_system(5, n=7001), 0.1, 10),
     ("arrow-long-row", _arrow, 0.1, 5),
-    # 20 entries per row: rows on both sides of the row Gram kernel's
-    # hash / pairwise switch (candidate rows counted with repeats)
+    # 20 entries per row (the per-row Gram kernel): rows on both sides of its
+    # hash / pairwise switch (candidate rows counted with repeats); the short
+    # rows of the other cases take the per-entry kernels
     ("random-rows-k19-hash-and-pairwise", lambda: synth.random_rows(4000, 19, 5), 0.1, 5),
+    ("dense-cross-k8-pairwise", _dense_cross, 0.1, 5),
     ("zero-rows-explicit-zeros", _zero_rows, 0.1, 30),
     ("identity", lambda: synth.from_dense(np.eye(33), f=np.arange(33.0)), 0.1, 1),
     ("n1", lambda: synth.from_dense(np.array([[2.0]]), f=np.array([6.0])), 0.1, 3),
