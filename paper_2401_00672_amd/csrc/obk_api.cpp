@@ -54,22 +54,44 @@ size_t obk_plan_s::device_bytes() const {
 
 namespace {
 
+const char* status_name(obk_status st) {
+    switch (st) {
+        case OBK_OK: return "OBK_OK";
+        case OBK_E_ARG: return "OBK_E_ARG";
+        case OBK_E_CSR: return "OBK_E_CSR";
+        case OBK_E_NOT_SQUARE: return "OBK_E_NOT_SQUARE";
+        case OBK_E_NONFINITE: return "OBK_E_NONFINITE";
+        case OBK_E_NOMEM: return "OBK_E_NOMEM";
+        case OBK_E_HIP: return "OBK_E_HIP";
+        case OBK_E_BUSY: return "OBK_E_BUSY";
+        case OBK_E_INCONSISTENT: return "OBK_E_INCONSISTENT";
+    }
+    return "OBK_E_?";
+}
+
+obk_status failed(obk_status code, const std::string& msg) {
+    obk::set_last_error(msg);
+    obk::log_line(1, "error %s: %s", status_name(code), msg.c_str());
+    return code;
+}
+
 template <class F> obk_status guarded(F&& body) {
     try {
         body();
         obk::set_last_error("");
         return OBK_OK;
     } catch (const obk::Error& e) {
-        obk::set_last_error(e.msg);
         (void)hipGetLastError();
-        return e.code;
+        return failed(e.code, e.msg);
     } catch (const std::bad_alloc&) {
-        obk::set_last_error("host allocation failed");
-        return OBK_E_NOMEM;
+        return failed(OBK_E_NOMEM, "host allocation failed");
     } catch (...) {
-        obk::set_last_error("unexpected internal error");
-        return OBK_E_HIP;
+        return failed(OBK_E_HIP, "unexpected internal error");
     }
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 hipStream_t as_hip(obk_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
@@ -163,6 +185,7 @@ static obk_status plan_impl(const obk_csr* A, const double* f, double delta, con
                             obk_stream_t stream, obk_plan_t* out, bool cplx) {
     if (out) *out = nullptr;
     obk_plan_s* P = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     obk_status st = guarded([&] {
         if (!A || !out) obk::fail(OBK_E_ARG, "A and out must not be NULL");
         if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) obk::fail(OBK_E_ARG, "negative size");
@@ -206,6 +229,9 @@ static obk_status plan_impl(const obk_csr* A, const double* f, double delta, con
         return st;
     }
     *out = P;
+    obk::log_line(2, "plan%s n=%lld nnz=%lld groups=%d conflicts=%lld bytes=%zu block_k=%d %.2f ms",
+                  cplx ? " (complex)" : "", (long long)P->n, (long long)P->nnz, (int)P->ngroups,
+                  (long long)P->nconflicts, P->device_bytes(), P->opts.block_k, 1e3 * seconds_since(t0));
     return OBK_OK;
 }
 
@@ -217,12 +243,17 @@ obk_status obk_solve(obk_plan_t plan, const double* x0, double tol, int64_t maxi
         BusyGuard busy(plan);
         OBK_HIP(hipSetDevice(plan->device));
         obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, as_hip(stream));
+        obk_info local{};
+        obk_info* inf = info ? info : &local;
         if (plan->cplx)
-            obk::solve_complex(*plan, x0, tol, maxit, x, info, as_hip(stream));
+            obk::solve_complex(*plan, x0, tol, maxit, x, inf, as_hip(stream));
         else if (plan->opts.precision == OBK_FP32_IR)
-            obk::solve_fp32_ir(*plan, x0, tol, maxit, x, info, as_hip(stream));
+            obk::solve_fp32_ir(*plan, x0, tol, maxit, x, inf, as_hip(stream));
         else
-            obk::solve_fp64(*plan, x0, tol, maxit, x, info, as_hip(stream));
+            obk::solve_fp64(*plan, x0, tol, maxit, x, inf, as_hip(stream));
+        obk::log_line(2, "solve n=%lld status=%d sweeps=%lld outer_steps=%lld relres0=%.3e relres=%.3e %.3f ms",
+                      (long long)plan->n, inf->status, (long long)inf->sweeps, (long long)inf->outer_steps,
+                      inf->relres0, inf->relres, 1e3 * inf->seconds);
     });
 }
 

@@ -466,7 +466,8 @@ int sweep_occupancy(bool fp32, int sub) {
 // it is too small (which drops the captured step graphs: they hold its
 // addresses and grids), then everything goes over in asynchronous copies on
 // `st`, which is synchronised before returning.  The batch must be idle.
-void build_schedule(obk_batch_s& B, hipStream_t st, double headroom) {
+// Returns whether any storage or launch grid had to grow.
+bool build_schedule(obk_batch_s& B, hipStream_t st, double headroom) {
     const int count = (int)B.plans.size();
     int dev = 0, cus = 256;
     OBK_HIP(hipGetDevice(&dev));
@@ -658,6 +659,7 @@ void build_schedule(obk_batch_s& B, hipStream_t st, double headroom) {
     }
     // the host arrays above must outlive the copies
     OBK_HIP(hipStreamSynchronize(st));
+    return changed;
 }
 
 }  // namespace
@@ -741,6 +743,7 @@ void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_
         B.use_graph = !(e && e[0] && e[0] != '0');
     }
     build_schedule(B, nullptr, 1.0);
+    log_line(2, "batch create systems=%d workgroups=%d %s", count, B.nwg, B.fp32 ? "fp32-ir" : "fp64");
 }
 
 // A new member list for an existing batch object (continuous batching): the
@@ -760,7 +763,9 @@ void batch_reset(obk_batch_s& B, const obk_plan_t* plans, int count, hipStream_t
     }
     B.plans.assign(plans, plans + count);
     try {
-        build_schedule(B, s, 1.5);
+        const bool grown = build_schedule(B, s, 1.5);
+        log_line(2, "batch reset systems=%d workgroups=%d storage %s", count, B.nwg,
+                 grown ? "grown (step graphs captured again)" : "kept");
     } catch (...) {
         // a failed reset leaves an empty batch, never one whose descriptors
         // and member list disagree
@@ -879,6 +884,11 @@ void batch_step(obk_batch_s& B, double tol, double* relres_out, int32_t* active_
     OBK_HIP(hipStreamSynchronize(s));
     if (herr & 1) fail(OBK_E_HIP, "a team barrier of the batched sweep timed out");
     if (B.trace.get()) trace_report(B);
+    if (log_level() >= 3) {
+        int act_n = 0;
+        for (int i = 0; i < count; i++) act_n += act[i] ? 1 : 0;
+        log_line(3, "batch step systems=%d advanced=%d", count, act_n);
+    }
     for (int i = 0; i < count; i++) {
         if (relres_out) relres_out[i] = rr[i];
         if (active_out) active_out[i] = act[i];

@@ -7,6 +7,9 @@
 #include <map>
 #include <mutex>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,6 +25,28 @@ thread_local std::string g_last_error;
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 const char* last_error_cstr() { return g_last_error.c_str(); }
+
+// ----------------------------------------------------------------- logging
+int log_level() {
+    static const int level = [] {
+        const char* v = std::getenv("OBK_LOG");
+        if (!v || !v[0]) return 0;
+        const int l = std::atoi(v);
+        return l < 0 ? 0 : (l > 3 ? 3 : l);
+    }();
+    return level;
+}
+
+void log_line(int level, const char* fmt, ...) {
+    if (log_level() < level) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[obk] %s\n", buf);
+    std::fflush(stderr);
+}
 
 void fail(obk_status code, const std::string& msg) { throw Error{code, msg}; }
 

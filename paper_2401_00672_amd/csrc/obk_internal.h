@@ -23,6 +23,11 @@ struct Error {
 void check_hip(hipError_t e, const char* what);
 #define OBK_HIP(call) ::obk::check_hip((call), #call)
 void set_last_error(const std::string& msg);
+// OBK_LOG (environment, read once): 0 silent (default), 1 every failed call
+// with its status and message, 2 also a line per plan, solve and batch
+// (re)formation, 3 also a line per batched step.  Lines go to stderr.
+int log_level();
+void log_line(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // ------------------------------------------------------- device memory
 // Owning device buffer; all plan memory goes through it so that the plan

@@ -220,3 +220,44 @@ def test_plan_validator_passes_on_device_plans(monkeypatch):
     for s, delta, kw in cases:
         with obk.plan_system(s, delta, **kw) as P:
             _say(f"[validate] {s.name}: {P.stats()['groups']} groups, layout valid")
+
+
+LOG_CHILD = r"""
+import sys
+sys.path.insert(0, {root!r})
+import synth
+import paper_2401_00672_amd as obk
+s = synth.c1(n=600)
+with obk.plan_system(s, 0.1) as P:
+    P.solve(maxit=5)
+plans = [obk.plan_system(synth.c1(n=n), 0.1, precision=obk.FP32_IR) for n in (500, 700, 900)]
+b = obk.Batch(plans[:2])
+b.begin()
+b.step(1e-10)
+b.reset(plans)
+b.start(2)
+b.step(1e-10)
+b.free()
+for p in plans:
+    p.free()
+print("child done", flush=True)
+"""
+
+
+def test_log_levels_name_plans_solves_and_batches():
+    """OBK_LOG=3 prints a line per plan, solve, batch formation and batched
+    step (the level is read once per process, so this runs in a child)."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OBK_LOG="3")
+    _say("[log] child with OBK_LOG=3")
+    r = subprocess.run([sys.executable, "-c", LOG_CHILD.format(root=root)], capture_output=True, text=True,
+                       timeout=300, env=env)
+    assert r.returncode == 0, r.stderr[-3000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[obk]")]
+    kinds = [l.split()[1] + (" " + l.split()[2] if l.split()[1] == "batch" else "") for l in lines]
+    assert kinds.count("plan") == 4 and kinds.count("solve") == 1, lines
+    assert kinds.count("batch create") == 1 and kinds.count("batch reset") == 1, lines
+    assert kinds.count("batch step") == 2, lines
+    assert not any("error" in l for l in lines), lines
