@@ -203,9 +203,9 @@ class Plan:
 
     # -- lifetime
     def free(self, stream=None) -> None:
-        """obk_free; with a stream, obk_free_async: the plan's memory goes back
-        in stream order on it (all work using the plan must be done or queued
-        there)."""
+        """obk_free; with a stream, obk_free_async: waits only for that stream
+        (all work using the plan must be done or queued there), and the
+        library keeps the plan's memory for later plans."""
         if self._h:
             if stream is None:
                 lib().obk_free(self._h)

@@ -133,9 +133,9 @@ class LibobkBackend:
         batch.free()
 
     def free_plan(self, plan) -> None:
-        # its last use (a step, a result copy) was on the server's stream and
-        # has completed: the memory goes back in stream order, without a
-        # wait for the planners' work on the device
+        # its last use (a step, a result copy) was on the server's stream:
+        # the release waits for that stream only, not for the planners' work
+        # on the device, and the library keeps the memory for later plans
         plan.free(stream=self.stream.cuda_stream)
 
 

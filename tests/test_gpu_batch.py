@@ -236,9 +236,10 @@ def test_batch_reset_members_continue_and_equal_single(monkeypatch, eager):
         p.free()
 
 
-def test_free_async_returns_memory_in_stream_order():
-    """obk_free_async: a plan released on a stream without a device-wide wait;
-    plans built afterwards (reusing the pool's memory) solve as before."""
+def test_free_async_releases_on_its_stream_and_memory_is_reused():
+    """obk_free_async: a plan released waiting only for its stream (no
+    device-wide wait); plans built afterwards take the kept blocks and solve
+    as before, bit for bit."""
     import torch
     systems = _systems()[:3]
     st = torch.cuda.Stream()
