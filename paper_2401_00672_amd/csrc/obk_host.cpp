@@ -188,6 +188,84 @@ void* pinned_stage(size_t bytes) {
     return g_stage.p;
 }
 
+namespace {
+// Two events per thread and device mark when each half of the staging buffer
+// is free again (kept until the thread ends, like the buffer).
+struct StageEvents {
+    int device = -1;
+    hipEvent_t e[2] = {nullptr, nullptr};
+};
+thread_local StageEvents g_stage_ev;
+hipEvent_t stage_event(int k) {
+    int dev = 0;
+    OBK_HIP(hipGetDevice(&dev));
+    if (g_stage_ev.device != dev) {
+        g_stage_ev = StageEvents{};
+        g_stage_ev.device = dev;
+    }
+    if (!g_stage_ev.e[k]) OBK_HIP(hipEventCreateWithFlags(&g_stage_ev.e[k], hipEventDisableTiming));
+    return g_stage_ev.e[k];
+}
+constexpr size_t kStageChunk = (size_t)8 << 20;
+}  // namespace
+
+void stage_h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    if (bytes <= kStageChunk) {
+        void* st = pinned_stage(bytes);
+        std::memcpy(st, h, bytes);
+        OBK_HIP(hipMemcpyAsync(d, st, bytes, hipMemcpyHostToDevice, s));
+        OBK_HIP(hipStreamSynchronize(s));     // the stage is reused by the next copy
+        return;
+    }
+    char* st = static_cast<char*>(pinned_stage(2 * kStageChunk));
+    bool busy[2] = {false, false};
+    int k = 0;
+    for (size_t off = 0; off < bytes; off += kStageChunk, k ^= 1) {
+        const size_t len = std::min(kStageChunk, bytes - off);
+        if (busy[k]) OBK_HIP(hipEventSynchronize(stage_event(k)));      // half k's last copy is done
+        std::memcpy(st + k * kStageChunk, static_cast<const char*>(h) + off, len);
+        OBK_HIP(hipMemcpyAsync(static_cast<char*>(d) + off, st + k * kStageChunk, len, hipMemcpyHostToDevice, s));
+        OBK_HIP(hipEventRecord(stage_event(k), s));
+        busy[k] = true;
+    }
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
+void stage_d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
+    if (!bytes) {
+        OBK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    if (bytes <= kStageChunk) {
+        void* st = pinned_stage(bytes);
+        OBK_HIP(hipMemcpyAsync(st, d, bytes, hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipStreamSynchronize(s));
+        std::memcpy(h, st, bytes);
+        return;
+    }
+    char* st = static_cast<char*>(pinned_stage(2 * kStageChunk));
+    size_t pend_off[2] = {0, 0}, pend_len[2] = {0, 0};
+    int k = 0;
+    auto drain = [&](int q) {
+        if (!pend_len[q]) return;
+        OBK_HIP(hipEventSynchronize(stage_event(q)));
+        std::memcpy(static_cast<char*>(h) + pend_off[q], st + q * kStageChunk, pend_len[q]);
+        pend_len[q] = 0;
+    };
+    for (size_t off = 0; off < bytes; off += kStageChunk, k ^= 1) {
+        const size_t len = std::min(kStageChunk, bytes - off);
+        drain(k);                             // half k holds an earlier chunk still to copy out
+        OBK_HIP(hipMemcpyAsync(st + k * kStageChunk, static_cast<const char*>(d) + off, len, hipMemcpyDeviceToHost, s));
+        OBK_HIP(hipEventRecord(stage_event(k), s));
+        pend_off[k] = off;
+        pend_len[k] = len;
+    }
+    drain(k);                                 // the older of the two in flight first
+    drain(k ^ 1);
+    OBK_HIP(hipStreamSynchronize(s));
+}
+
 void DevMem::alloc(size_t b) {
     release();
     if (b == 0) b = 16;

@@ -62,6 +62,12 @@ void sync_for_free(hipStream_t s);
 // Pinned host staging buffer of the calling thread (grown on demand, kept
 // until the thread ends); every user completes its copy before returning.
 void* pinned_stage(size_t bytes);
+// Host <-> device copies through that buffer, in chunks of at most 8 MiB with
+// two in flight (a large array needs no pinned buffer of its own size:
+// pinning hundreds of megabytes costs more than the copy); both return with
+// the copy complete and the stream synchronised.
+void stage_h2d(void* d, const void* h, size_t bytes, hipStream_t s);
+void stage_d2h(void* h, const void* d, size_t bytes, hipStream_t s);
 
 // While a UserAllocScope is active on the calling thread, buffers come from
 // the caller's allocator (obk_opts.alloc / dealloc / ctx) instead; each

@@ -739,11 +739,7 @@ __global__ void k_to_f32(int64_t m, const double* __restrict__ src, float* __res
 // staging buffer, so that concurrent plan builds on several threads do not
 // share the runtime's pageable-copy path.
 template <class T> void h2d(T* d, const T* h, size_t n, hipStream_t s) {
-    if (!n) return;
-    void* st = pinned_stage(n * sizeof(T));
-    std::memcpy(st, h, n * sizeof(T));
-    OBK_HIP(hipMemcpyAsync(d, st, n * sizeof(T), hipMemcpyHostToDevice, s));
-    OBK_HIP(hipStreamSynchronize(s));     // the stage is reused by the next copy
+    stage_h2d(d, h, n * sizeof(T), s);
 }
 template <class T> void to_device(DevArray<T>& d, const T* h, size_t n, hipStream_t s) {
     d.alloc(n);
@@ -759,14 +755,7 @@ template <class T> void copy_in(DevArray<T>& d, const T* src, size_t n, bool on_
 }
 template <class T> std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
     std::vector<T> h(n);
-    if (n) {
-        void* st = pinned_stage(n * sizeof(T));
-        OBK_HIP(hipMemcpyAsync(st, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-        OBK_HIP(hipStreamSynchronize(s));
-        std::memcpy(h.data(), st, n * sizeof(T));
-    } else {
-        OBK_HIP(hipStreamSynchronize(s));
-    }
+    stage_d2h(h.data(), d, n * sizeof(T), s);
     return h;
 }
 

@@ -185,10 +185,7 @@ template <class T> T d2h_one(const T* d, hipStream_t s) {
 
 template <class T> void d2h(T* h, const T* d, size_t n, hipStream_t s) {
     if (!n) return;
-    void* st = pinned_stage(n * sizeof(T));
-    OBK_HIP(hipMemcpyAsync(st, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-    OBK_HIP(hipStreamSynchronize(s));
-    std::memcpy(h, st, n * sizeof(T));
+    stage_d2h(h, d, n * sizeof(T), s);
 }
 
 }  // namespace
