@@ -258,3 +258,33 @@ def test_free_async_releases_on_its_stream_and_memory_is_reused():
             p.free(stream=st.cuda_stream)
     assert obk.lib().obk_free_async(None, None) == 0
     st.synchronize()
+
+
+def test_batch_created_empty_then_reset():
+    """A batch object created with no members steps as a no-op and takes its
+    members later through obk_batch_reset; their results equal solves alone."""
+    systems = _systems()[:2]
+    b = obk.Batch([])
+    rr, act = b.step(1e-10)
+    assert rr.size == 0 and act.size == 0
+    plans = [obk.plan_system(s, 0.1, precision=obk.FP32_IR, inner_sweeps=8) for s in systems]
+    b.reset(plans)
+    b.start(0)
+    b.start(1)
+    steps = [0, 0]
+    for _ in range(60):
+        rr, act = b.step(1e-10)
+        for i in range(2):
+            steps[i] += int(act[i])
+        if not act.any():
+            break
+    _say(f"[batch] empty then reset: steps {steps}")
+    for i, s in enumerate(systems):
+        x = b.result(i)
+        q = obk.plan_system(s, 0.1, precision=obk.FP32_IR, inner_sweeps=8)
+        x1, info = q.solve(maxit=steps[i], tol=1e-10)
+        q.free()
+        assert info.outer_steps == steps[i] and np.array_equal(x, x1)
+    b.free()
+    for p in plans:
+        p.free()
