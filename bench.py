@@ -7,7 +7,7 @@ a timed step is one full sweep over every group.  The iterate stays in HBM
 for the whole timed region.
 
 Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused:
-this build runs on one GPU.
+the library runs one GPU per process, and this benchmark measures one.
 """
 from __future__ import annotations
 
