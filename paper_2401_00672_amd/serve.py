@@ -167,6 +167,9 @@ class Server:
         # True: one batch object re-formed in place when members join
         # (obk_batch_reset); False: a new batch object each time
         self.reuse_batch = bool(reuse_batch)
+        # rebuilds / rebuild_seconds: re-formations of the batch over a new
+        # member list (in place, or a new object with reuse_batch=False);
+        # free_seconds: plan releases; plan_seconds: summed over planner threads
         self.stats = {"steps": 0, "rebuilds": 0, "peak_bytes": 0, "peak_members": 0, "step_seconds": 0.0,
                       "rebuild_seconds": 0.0, "free_seconds": 0.0, "plan_seconds": 0.0, "failed": 0, "cancelled": 0}
         self._cancel_lock = threading.Lock()
