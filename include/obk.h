@@ -282,9 +282,12 @@ OBK_API obk_status obk_plan_engine(obk_plan_t plan, int32_t *engine, int32_t *sl
  * bound on lambda_max(B_g B_g^H), 1 + max over the rows i of g of
  * sum_{j in g, j != i} |cos(a_i, a_j)| (every such cosine is below delta),
  * and *bound is the largest of them (0 when the plan has no groups).  A group
- * step with omega * bound <= 2 does not expand the error.  Computed in FP64
- * at plan time (real and complex plans).  per_group (host, n_groups entries)
- * or bound may be NULL.  OBK_E_ARG for block-form plans. */
+ * step with omega * bound <= 2 does not expand the error.  Computed in FP64:
+ * for complex plans at plan time, for real plans on the first call (from the
+ * group-major rows and column segments the plan keeps; the call then runs
+ * kernels on a stream of its own and returns when they are done; OBK_E_BUSY
+ * while a solve on the plan runs).  per_group (host, n_groups entries) or
+ * bound may be NULL.  OBK_E_ARG for block-form plans. */
 OBK_API obk_status obk_plan_lambda_bound(obk_plan_t plan, double *bound, double *per_group);
 /* Sizes: n, nnz, number of groups, bandwidth of A~, number of conflicting pairs. */
 OBK_API obk_status obk_plan_stats(obk_plan_t plan, int64_t *n, int64_t *nnz, int32_t *n_groups,

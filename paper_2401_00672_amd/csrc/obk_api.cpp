@@ -22,6 +22,7 @@ int32_t profile_sweeps(obk_plan_s& P, double* x, int64_t sweeps, hipStream_t s, 
 void solve_fp32_ir(obk_plan_s& P, const double* x0, double tol, int64_t maxit, double* x, obk_info* info,
                    hipStream_t s, const SolveWs* ws = nullptr);
 void ensure_fp32(obk_plan_s& P, hipStream_t s);
+void lambda_bound_on_request(obk_plan_s& P, hipStream_t s);
 void batch_create(obk_batch_s& B, const obk_plan_t* plans, int count, const obk_batch_opts* opts);
 void batch_reset(obk_batch_s& B, const obk_plan_t* plans, int count, hipStream_t s);
 void batch_begin(obk_batch_s& B, const double* const* x0, hipStream_t s);
@@ -505,6 +506,16 @@ obk_status obk_plan_lambda_bound(obk_plan_t plan, double* bound, double* per_gro
     return guarded([&] {
         if (!plan) obk::fail(OBK_E_ARG, "NULL plan");
         if (plan->block_form()) obk::fail(OBK_E_ARG, "the bound concerns one-row groups; a block-form plan has none");
+        if (!plan->cplx && plan->ngroups > 0 && plan->h_lambda_bound.empty()) {
+            // formed on first request, on a stream of its own
+            BusyGuard busy(plan);
+            OBK_HIP(hipSetDevice(plan->device));
+            hipStream_t s = nullptr;
+            OBK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            struct SD { hipStream_t s; ~SD() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } sd{s};
+            obk::UserAllocScope ua(plan->opts.alloc, plan->opts.dealloc, plan->opts.ctx, s);
+            obk::lambda_bound_on_request(*plan, s);
+        }
         double b = 0.0;
         for (double v : plan->h_lambda_bound) b = std::max(b, v);
         if (bound) *bound = b;

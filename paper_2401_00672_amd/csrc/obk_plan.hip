@@ -276,6 +276,8 @@ __global__ void k_conflicts(int64_t nnz, const int64_t* __restrict__ trp, const 
 // row j of column c in i's group whose first column shared with row i is c,
 // the sum of |cos(a_i, a_j)| (complex: |a_i^H a_j| / (|a_i| |a_j|)).  Each
 // pair of a row's Gram row is so counted at exactly one of its entries.
+// Complex plans form the bound at plan time with it; real plans form theirs
+// on request (k_gm_group_cos below, the same sums over the arrays they keep).
 template <bool kCplx>
 __global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci,
                             const double* __restrict__ tv, const double* __restrict__ tvi,
@@ -338,14 +340,12 @@ __global__ void k_group_cos(int64_t nnz, const int64_t* __restrict__ trp, const 
 // column only.
 //   kGramCount: conflicts (rows j < i, nu_j != 0, |cos_ij| >= delta) per row;
 //   kGramFill:  the conflict lists at row_pos[i] (hash path: ascending j;
-//               pairwise path: in the order the candidates are listed);
-//   kGramCos:   sum over the rows j != i of i's group of |cos_ij| (the
-//               Gershgorin row sums of B_g B_g^T), at part[trp[i]].
+//               pairwise path: in the order the candidates are listed).
 constexpr int kGramWaves = 4;
 constexpr int kGramMinRowLen = 7;    // plans with fewer entries per row on average: per-entry kernels
 constexpr int kGramSlots = 512;
 constexpr int kGramMaxCand = 384;
-enum : int { kGramCount = 0, kGramFill = 1, kGramCos = 2 };
+enum : int { kGramCount = 0, kGramFill = 1 };
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -354,10 +354,6 @@ __device__ __forceinline__ void wave_sync() {
 }
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
     for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_sum_f64(double v) {
-    for (int d = 32; d > 0; d >>= 1) v = v + __shfl_xor(v, d, 64);
     return v;
 }
 __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int lane, int32_t* total) {
@@ -399,9 +395,8 @@ template <int kMode>
 __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
     int64_t n, const int64_t* __restrict__ trp, const int32_t* __restrict__ tci, const double* __restrict__ tv,
     const int64_t* __restrict__ cptr, const uint32_t* __restrict__ cpos, const int32_t* __restrict__ crow,
-    const double* __restrict__ cval, const double* __restrict__ nu, double delta, const int32_t* __restrict__ group,
-    int64_t* __restrict__ row_count, const int64_t* __restrict__ row_pos, int32_t* __restrict__ out_idx,
-    double* __restrict__ part) {
+    const double* __restrict__ cval, const double* __restrict__ nu, double delta, int64_t* __restrict__ row_count,
+    const int64_t* __restrict__ row_pos, int32_t* __restrict__ out_idx) {
     __shared__ GramLds lds_all[kGramWaves];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -411,15 +406,13 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
     const int32_t i = (int32_t)row;
     const int64_t ia0 = trp[i], ia1 = trp[i + 1];
     const double nui = nu[i];
-    const int32_t gi = (kMode == kGramCos) ? group[i] : 0;
-    const bool idle = (ia0 == ia1) | ((kMode == kGramCos) ? (gi < 0) : (nui == 0.0));
+    const bool idle = (ia0 == ia1) | (nui == 0.0);
     if (idle) {
         if (kMode == kGramCount && lane == 0) row_count[i] = 0;
-        return;                              // kGramCos: part is zero-filled
+        return;
     }
     int64_t found = 0;                       // conflicts so far (pairwise path)
     int64_t wpos = (kMode == kGramFill) ? row_pos[i] : 0;
-    double acc = 0.0;                        // |cos| sum of this lane (kGramCos)
     for (int64_t kb = ia0; kb < ia1; kb += 64) {
         // this chunk's entries: one lane each
         const int ne = (int)min<int64_t>(64, ia1 - kb);
@@ -428,9 +421,8 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
         const int32_t c = tci[k];
         const double a = tv[k];
         const int64_t s0 = cptr[c];
-        const int64_t s1 = cptr[c + 1];
         const int64_t pk = (int64_t)cpos[k];
-        const int32_t cnt = kin ? (int32_t)((kMode == kGramCos) ? (s1 - s0) : (pk - s0)) : 0;
+        const int32_t cnt = kin ? (int32_t)(pk - s0) : 0;      // rows of column c below i
         int32_t total = 0;
         const int32_t off = wave_excl_scan(cnt, lane, &total);
         total = __builtin_amdgcn_readfirstlane(total);
@@ -451,8 +443,7 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
                 const int64_t sp = L.es0[e] + (qc - L.eoff[e]);
                 const int32_t j = crow[sp];
                 const double cv = cval[sp];
-                const int32_t gj = (kMode == kGramCos) ? group[j] : gi;
-                const bool keep = (j != i) & (gj == gi);
+                const bool keep = j != i;
                 if (valid) {
                     L.cj[q] = keep ? j : -1;
                     L.cp[q] = L.ea[e] * cv;
@@ -483,17 +474,6 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
                     }
                 }
                 wave_sync();                 // column e's sums land before column e + 1's
-            }
-            if (kMode == kGramCos) {
-                for (int t = lane; t < kGramSlots; t += 64) {
-                    const int32_t j = L.key[t];
-                    const double nuj = nu[j >= 0 ? j : i];
-                    const double term = fabs(L.val[t]) / __dsqrt_rn(nui * nuj);
-                    acc = (j >= 0) ? acc + term : acc;
-                }
-                acc = wave_sum_f64(acc);
-                if (lane == 0) part[ia0] = acc;
-                return;
             }
             uint32_t mine = 0;               // bit r: slot lane + 64 r conflicts
 #pragma unroll
@@ -539,8 +519,7 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
             const int64_t sp = L.es0[e] + (qc - L.eoff[e]);
             const int32_t ce = L.ecol[e];
             const int32_t j = crow[sp];
-            const int32_t gj = (kMode == kGramCos) ? group[j] : gi;
-            const bool take = valid & (j != i) & (gj == gi);
+            const bool take = valid & (j != i);
             int64_t x = ia0, y = trp[j];
             const int64_t y1 = take ? trp[j + 1] : y;
             int32_t first = -1;
@@ -556,24 +535,15 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_row_gram(
             }
             const double nuj = nu[j];
             const double cs = fabs(d) / __dsqrt_rn(nui * nuj);
-            const bool counted = take & (first == ce);
-            if (kMode == kGramCos) {
-                acc = counted ? acc + cs : acc;
-            } else {
-                const bool hit = counted & (nuj != 0.0) & (cs >= delta);
-                const uint64_t bal = __ballot(hit);
-                if ((kMode == kGramFill) & hit) out_idx[wpos + __popcll(bal & __lanemask_lt())] = j;
-                wpos += __popcll(bal);
-                found += __popcll(bal);
-            }
+            const bool hit = take & (first == ce) & (nuj != 0.0) & (cs >= delta);
+            const uint64_t bal = __ballot(hit);
+            if ((kMode == kGramFill) & hit) out_idx[wpos + __popcll(bal & __lanemask_lt())] = j;
+            wpos += __popcll(bal);
+            found += __popcll(bal);
         }
         wave_sync();                         // the chunk's LDS lists are read before the next chunk's
     }
     if (kMode == kGramCount && lane == 0) row_count[i] = found;
-    if (kMode == kGramCos) {
-        acc = wave_sum_f64(acc);
-        if (lane == 0) part[ia0] = acc;
-    }
 }
 
 // 1 + the row's sum, folded into its group's maximum (non-negative doubles
@@ -621,6 +591,81 @@ k_group_cos_max(int64_t m, const int32_t* __restrict__ grow, const int64_t* __re
 __global__ void k_zero_u64(int64_t m, unsigned long long* __restrict__ p) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < m) p[k] = 0ull;
+}
+
+// ------------------------------------------ relaxation bound, on request
+// A real plan forms its per-group Gershgorin bounds when they are first asked
+// for, from the arrays it keeps: the group-major rows (columns ascending) and
+// each group's column segments (rows ascending).  ||a||^2 of a group-major row,
+// summed as the plan's norms are (ascending column, no contraction).
+__global__ void k_gm_norms(int64_t m, const int64_t* __restrict__ rptr, const double* __restrict__ rval,
+                           double* __restrict__ nu) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < m) {
+        double s = 0.0;
+        for (int64_t k = rptr[a]; k < rptr[a + 1]; k++) s = s + rval[k] * rval[k];
+        nu[a] = s;
+    }
+}
+
+// One thread per group-major entry (a, c) of row a in group g: over the other
+// rows j of g's segment of column c whose first column shared with row a is
+// c, the sum of |cos(a_a, a_j)| -- the plan-time per-entry sums, term for term
+// (a group's rows keep their reordered order in its segments).
+__global__ void k_gm_group_cos(int64_t nnz, const int32_t* __restrict__ erow, const int32_t* __restrict__ rgrp,
+                               const int64_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                               const double* __restrict__ rval, const int64_t* __restrict__ tptr,
+                               const int32_t* __restrict__ tcol, const int64_t* __restrict__ sptr,
+                               const int32_t* __restrict__ srow, const double* __restrict__ nu,
+                               double* __restrict__ part) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t a = erow[e];
+    const int32_t g = rgrp[a];
+    const int32_t c = rcol[e];
+    // the segment of column c among the group's (present: row a touches c)
+    int64_t lo = tptr[g], hi = tptr[g + 1];
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        const bool less = tcol[mid] < c;
+        lo = less ? mid + 1 : lo;
+        hi = less ? hi : mid;
+    }
+    const int64_t s0 = sptr[lo], s1 = sptr[lo + 1];
+    const double nua = nu[a];
+    const int64_t a0 = rptr[a], a1 = rptr[a + 1];
+    double acc = 0.0;
+    for (int64_t sp = s0; sp < s1; sp++) {
+        const int32_t j = srow[sp];
+        const bool take = j != a;
+        int64_t x = a0, y = rptr[j];
+        const int64_t y1 = take ? rptr[j + 1] : y;
+        int32_t first = -1;
+        double d = 0.0;
+        while ((x < a1) & (y < y1)) {
+            const int32_t cx = rcol[x], cy = rcol[y];
+            const double vx = rval[x], vy = rval[y];
+            const bool eq = cx == cy;
+            d = eq ? d + vx * vy : d;
+            first = (eq & (first < 0)) ? cx : first;
+            x += (cx <= cy) ? 1 : 0;
+            y += (cy <= cx) ? 1 : 0;
+        }
+        const double cs = fabs(d) / __dsqrt_rn(nua * nu[j]);
+        acc = (take & (first == c)) ? acc + cs : acc;
+    }
+    part[e] = acc;
+}
+
+// 1 + the row's sum of its entries' parts, in entry order
+__global__ void k_gm_rowsum(int64_t m, const int64_t* __restrict__ rptr, const double* __restrict__ part,
+                            double* __restrict__ out) {
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < m) {
+        double s = 1.0;
+        for (int64_t k = rptr[a]; k < rptr[a + 1]; k++) s = s + part[k];
+        out[a] = s;
+    }
 }
 
 // --------------------------------------------------------------- relayout
@@ -822,6 +867,39 @@ struct PlanTrace {
         std::fprintf(stderr, "\n");
     }
 };
+
+// The per-group bounds of a real one-row-group plan, formed on first request
+// (the largest of 1 + row sum over each group's rows).
+void lambda_bound_on_request(obk_plan_s& P, hipStream_t s) {
+    const int32_t G = P.ngroups;
+    const int64_t m = P.m;
+    const int64_t nnz = (int64_t)P.rcol.count;
+    std::vector<double> bound(G, 0.0);
+    if (m > 0) {
+        std::vector<int32_t> rgrp(m);
+        for (int32_t g = 0; g < G; g++)
+            for (int64_t a = P.h_gptr[g]; a < P.h_gptr[g + 1]; a++) rgrp[a] = g;
+        DevArray<int32_t> drgrp; to_device(drgrp, rgrp.data(), m, s);
+        DevArray<int64_t> dtptr; to_device(dtptr, P.h_tptr.data(), (size_t)G + 1, s);
+        DevArray<double> nu; nu.alloc(m);
+        DevArray<double> rowsum; rowsum.alloc(m);
+        DevArray<int32_t> erow; erow.alloc(nnz);
+        DevArray<double> part; part.alloc(nnz);
+        k_gm_norms<<<nblk(m), kT, 0, s>>>(m, P.rptr.get(), P.rval.get(), nu.get());
+        k_row_of<<<nblk(m), kT, 0, s>>>(m, P.rptr.get(), erow.get());
+        OBK_HIP(hipGetLastError());
+        if (nnz > 0)
+            k_gm_group_cos<<<nblk(nnz), kT, 0, s>>>(nnz, erow.get(), drgrp.get(), P.rptr.get(), P.rcol.get(),
+                                                    P.rval.get(), dtptr.get(), P.tcol.get(), P.sptr.get(),
+                                                    P.srow.get(), nu.get(), part.get());
+        k_gm_rowsum<<<nblk(m), kT, 0, s>>>(m, P.rptr.get(), part.get(), rowsum.get());
+        OBK_HIP(hipGetLastError());
+        const std::vector<double> rs = to_host(rowsum.get(), m, s);
+        for (int32_t g = 0; g < G; g++)
+            for (int64_t a = P.h_gptr[g]; a < P.h_gptr[g + 1]; a++) bound[g] = std::max(bound[g], rs[a]);
+    }
+    P.h_lambda_bound = bound;
+}
 
 void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, hipStream_t s) {
     // an m x n system with m != n is solved as its extended square system
@@ -1096,8 +1174,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
             if (n > 0)
                 k_row_gram<kGramCount><<<gb, kGramWaves * 64, 0, s>>>(n, trp.get(), tci.get(), tv.get(), cptr.get(),
                                                                       cpos.get(), crow.get(), cval.get(), nu.get(),
-                                                                      delta, nullptr, rconf.get(), nullptr, nullptr,
-                                                                      nullptr);
+                                                                      delta, rconf.get(), nullptr, nullptr);
             OBK_HIP(hipGetLastError());
             nconf = scan_exclusive_i64(rconf.get(), rconf.get(), n, s);
             k_set_i64<<<1, 1, 0, s>>>(rconf.get() + n, nconf);
@@ -1105,8 +1182,7 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
             if (n > 0 && nconf > 0)
                 k_row_gram<kGramFill><<<gb, kGramWaves * 64, 0, s>>>(n, trp.get(), tci.get(), tv.get(), cptr.get(),
                                                                      cpos.get(), crow.get(), cval.get(), nu.get(),
-                                                                     delta, nullptr, nullptr, rconf.get(),
-                                                                     cidx.get(), nullptr);
+                                                                     delta, nullptr, rconf.get(), cidx.get());
             OBK_HIP(hipGetLastError());
         }
         P.nconflicts = nconf;
@@ -1150,29 +1226,17 @@ void build_plan(obk_plan_s& P, const obk_csr& A, const double* f, double delta, 
     DevArray<int32_t> dgrow; to_device(dgrow, grow.data(), m, s);
     DevArray<int32_t> dpos; to_device(dpos, pos_of_row.data(), n, s);
     DevArray<int32_t> dgroup; to_device(dgroup, group.data(), n, s);
-    if (!P.block_form() && G > 0) {
-        // per-group Gershgorin bound on lambda_max(B_g B_g^T)
+    if (cplx && G > 0) {
+        // per-group Gershgorin bound on lambda_max(B_g B_g^H) (real plans
+        // form theirs on request, from the arrays they keep)
         DevArray<double> part; part.alloc(nnz);
         DevArray<unsigned long long> gmax; gmax.alloc(G);
         k_zero_u64<<<nblk(G), kT, 0, s>>>(G, gmax.get());
-        if (nnz > 0) {
-            if (cplx) {
-                k_group_cos<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(),
-                                                           trow.get(), cptr.get(), crow.get(), nu.get(),
-                                                           dgroup.get(), part.get());
-            } else if (nnz < (int64_t)kGramMinRowLen * n) {
-                k_group_cos<false><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), nullptr,
-                                                            trow.get(), cptr.get(), crow.get(), nu.get(),
-                                                            dgroup.get(), part.get());
-            } else {
-                // one sum per row, at the row's first entry; the other entries hold 0
-                OBK_HIP(hipMemsetAsync(part.get(), 0, nnz * sizeof(double), s));
-                k_row_gram<kGramCos><<<(unsigned)((n + kGramWaves - 1) / kGramWaves), kGramWaves * 64, 0, s>>>(
-                    n, trp.get(), tci.get(), tv.get(), cptr.get(), cpos.get(), crow.get(), cval.get(), nu.get(),
-                    delta, dgroup.get(), nullptr, nullptr, nullptr, part.get());
-            }
-            OBK_HIP(hipGetLastError());
-        }
+        if (nnz > 0)
+            k_group_cos<true><<<nblk(nnz), kT, 0, s>>>(nnz, trp.get(), tci.get(), tv.get(), tv_im.get(),
+                                                       trow.get(), cptr.get(), crow.get(), nu.get(), dgroup.get(),
+                                                       part.get());
+        OBK_HIP(hipGetLastError());
         if (m > 0)
             k_group_cos_max<<<(unsigned)((m + kCosMaxThreads - 1) / kCosMaxThreads), kCosMaxThreads, 0, s>>>(
                 m, dgrow.get(), trp.get(), part.get(), dgroup.get(), gmax.get());
