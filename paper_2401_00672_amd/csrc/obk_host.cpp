@@ -190,7 +190,7 @@ void* pinned_stage(size_t bytes) {
 
 namespace {
 // Two events per thread and device mark when each half of the staging buffer
-// is free again (kept until the thread ends, like the buffer).
+// is free again (created once and never destroyed: two events per thread).
 struct StageEvents {
     int device = -1;
     hipEvent_t e[2] = {nullptr, nullptr};
