@@ -138,8 +138,9 @@ def bench_stencil(args) -> dict:
     B = sweep_bytes(s.n, m, s.nnz)
     sweep_gbs = B / (ms * 1e-3) / 1e9
     # the sweep's kernels, timed per launch with HIP events on the launch
-    # stream (eager sweeps); the roofline unit is one sweep: the survey
-    # formula's bytes over the summed kernel time of one sweep
+    # stream (eager sweeps); the roofline unit is one sweep: the
+    # algorithmic bytes of sweep_bytes() over the summed kernel time of one
+    # sweep
     prof = P.sweep_profile(x, args.profile_sweeps)
     sweep_kernel_s = sum(k["seconds"] for k in prof) / args.profile_sweeps
     launches_per_sweep = sum(k["launches"] for k in prof) / args.profile_sweeps
@@ -174,7 +175,7 @@ def bench_stencil(args) -> dict:
         "sweep_effective": {"formula_bytes_per_sweep": B, "achieved_gbs": sweep_gbs,
                             "frac": sweep_gbs / HBM_PEAK_GBS},
         # per kernel, with the implementation's own bytes per launch (A is read
-        # in both phases, x once per group): not the survey formula
+        # in both phases, x once per group), not the algorithmic bytes
         "kernels": [{"name": k["name"], "launches": k["launches"], "avg_us": k["seconds"] / k["launches"] * 1e6,
                      "implementation_bytes_per_launch": k["bytes"] / k["launches"],
                      "implementation_gbs": k["bytes"] / k["seconds"] / 1e9} for k in prof],
