@@ -723,7 +723,7 @@ def copy_calibration(mib: int = 256, reps: int = 5) -> dict:
             "kib_per_copy": n * 8 / 1024, "reps": reps}
 
 
-def main() -> int:
+def arg_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
@@ -765,7 +765,11 @@ def main() -> int:
                     help="c5: build a new batch object at every change of membership instead of resetting one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 256 MiB device copy (counter calibration) and exit")
-    args = ap.parse_args()
+    return ap
+
+
+def main() -> int:
+    args = arg_parser().parse_args()
     if args.copy_calibration:
         print(json.dumps(copy_calibration()), flush=True)
         return 0
