@@ -104,6 +104,15 @@ struct RoundRegs {
     double v[Q][KP];
 };
 
+// Where phase R also stores the w of the own rows a neighbour's window
+// needs: slots [lo0, lo1) of the w window go to lo[slot - lo0] (for k-1),
+// slots [hi0, hi1) to hi[slot - hi0] (for k+1); empty ranges store nothing.
+struct PubRange {
+    double* lo;
+    double* hi;
+    int lo0, lo1, hi0, hi1;
+};
+
 // The global arrays a streamed phase reads its items and entries from.
 struct PhaseSrc {
     const uint16_t* tgt;
@@ -177,7 +186,7 @@ __device__ __forceinline__ void round_accumulate(RoundRegs<Q, KP>& R, int e0, co
 // S); the oracle's product a * v commutes exactly.
 template <bool kR, int Q, int KP>
 __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound& rd, int nr, const double* src,
-                                             double* dst, RoundRegs<Q, KP>& R, double omega) {
+                                             double* dst, RoundRegs<Q, KP>& R, double omega, const PubRange& pb) {
     const int K = __builtin_amdgcn_readfirstlane(rd.K);
     round_accumulate<kR>(R, 0, src);
     for (int e0 = KP; e0 < K; e0 += KP) {
@@ -187,8 +196,15 @@ __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound&
 #pragma unroll
     for (int q = 0; q < Q; q++)
         if (R.act[q]) {
-            if (kR) dst[R.tg[q]] = ((R.fa[q] - R.acc[q]) * (1.0 / R.nu[q])) * omega;
-            else dst[R.tg[q]] = dst[R.tg[q]] + R.acc[q];
+            if (kR) {
+                const double wv = ((R.fa[q] - R.acc[q]) * (1.0 / R.nu[q])) * omega;
+                const int tg = R.tg[q];
+                dst[tg] = wv;
+                if ((tg >= pb.lo0) & (tg < pb.lo1)) st_agent(pb.lo + (tg - pb.lo0), wv);
+                if ((tg >= pb.hi0) & (tg < pb.hi1)) st_agent(pb.hi + (tg - pb.hi0), wv);
+            } else {
+                dst[R.tg[q]] = dst[R.tg[q]] + R.acc[q];
+            }
         }
 }
 
@@ -197,7 +213,8 @@ __device__ __forceinline__ void finish_round(const PhaseSrc& s, const SlabRound&
 // LDS (index minus the slab's first).
 template <bool kR>
 __device__ __forceinline__ void run_phase(const PhaseSrc& s, const SlabPhase& ph, const SlabRound* rounds,
-                                          int32_t round_first, const double* src, double* dst, double omega) {
+                                          int32_t round_first, const double* src, double* dst, double omega,
+                                          const PubRange& pb) {
     constexpr int Q = kR ? kQR : kQS, KP = kR ? kKPR : kKPS;
     RoundRegs<Q, KP> R;
     for (int r = 0; r < ph.nrounds; r++) {
@@ -205,7 +222,7 @@ __device__ __forceinline__ void run_phase(const PhaseSrc& s, const SlabPhase& ph
         const int nr = min(phase_qt(kR), ph.count - r * phase_qt(kR));
         round_items<kR, Q, KP>(s, ph, r, nr, R);
         round_entries<Q, KP>(s, rd.ent_off, __builtin_amdgcn_readfirstlane(rd.K), nr, 0, R);
-        finish_round<kR, Q, KP>(s, rd, nr, src, dst, R, omega);
+        finish_round<kR, Q, KP>(s, rd, nr, src, dst, R, omega, pb);
     }
 }
 
@@ -214,7 +231,8 @@ __device__ __forceinline__ void run_phase(const PhaseSrc& s, const SlabPhase& ph
 // register arrays are held).
 template <bool kR>
 __device__ __forceinline__ void run_cached(const char* b, const SlabPhase& ph, const SlabRound* rounds,
-                                           int32_t round_first, const double* src, double* dst, double omega) {
+                                           int32_t round_first, const double* src, double* dst, double omega,
+                                           const PubRange& pb) {
     const CacheLayout c = cache_layout(kR, ph.count, ph.ents);
     const uint16_t* tgt = reinterpret_cast<const uint16_t*>(b + c.tgt);
     const uint16_t* len = reinterpret_cast<const uint16_t*>(b + c.len);
@@ -237,30 +255,22 @@ __device__ __forceinline__ void run_cached(const char* b, const SlabPhase& ph, c
                 acc = acc + v * src[idx[at]];
                 if (kR) nu = nu + v * v;
             }
-            if (kR) dst[tgt[li]] = ((f[li] - acc) * (1.0 / nu)) * omega;
-            else dst[tgt[li]] = dst[tgt[li]] + acc;
+            if (kR) {
+                const double wv = ((f[li] - acc) * (1.0 / nu)) * omega;
+                const int tg = tgt[li];
+                dst[tg] = wv;
+                if ((tg >= pb.lo0) & (tg < pb.lo1)) st_agent(pb.lo + (tg - pb.lo0), wv);
+                if ((tg >= pb.hi0) & (tg < pb.hi1)) st_agent(pb.hi + (tg - pb.hi0), wv);
+            } else {
+                dst[tgt[li]] = dst[tgt[li]] + acc;
+            }
         }
     }
 }
 
-// The communication wave's copies, kCommBatch values per lane in flight:
-// LDS to the exchange buffer (publish) and back (receive).
+// The communication wave's copy of a neighbour's published values into the
+// w window, kCommBatch values per lane in flight.
 constexpr int kCommBatch = 16;
-__device__ __forceinline__ void comm_publish(double* dst, const double* src, int n, int t) {
-    for (int base = 0; base < n; base += kCommBatch * kCommThreads) {
-        double v[kCommBatch];
-#pragma unroll
-        for (int m = 0; m < kCommBatch; m++) {
-            const int i = base + m * kCommThreads + t;
-            v[m] = i < n ? src[i] : 0.0;
-        }
-#pragma unroll
-        for (int m = 0; m < kCommBatch; m++) {
-            const int i = base + m * kCommThreads + t;
-            if (i < n) st_agent(dst + i, v[m]);
-        }
-    }
-}
 __device__ __forceinline__ void comm_receive(double* dst, const double* src, int n, int t) {
     for (int base = 0; base < n; base += kCommBatch * kCommThreads) {
         double v[kCommBatch];
@@ -360,27 +370,30 @@ __global__ __launch_bounds__(kSlabThreads) void k_slab_sweeps(SlabArgs a, int64_
             const uint32_t step = (uint32_t)(sw * G + g) + 1u;
             const int par = (int)(sw & 1);
             const SlabGroup& gd = gl[g];
-            // phase R of the own rows of g
+            const bool sync = g == 0;
+            const bool send = sync | (gd.pre_cnt > 0) | (gd.suf_cnt > 0);
+            // phase R of the own rows of g; the first pre_cnt own rows also go
+            // to the buffer k-1 reads and the last suf_cnt to the one k+1
+            // reads, and each wave waits for its stores before the barrier
             if (comp) {
-                if (gd.r.cache >= 0) run_cached<true>(cache + gd.r.cache, gd.r, rl, d.round_first, xw, ww, a.omega);
-                else run_phase<true>(global_src(a), gd.r, rl, d.round_first, xw, ww, a.omega);
+                const int own0 = gd.lo_cnt, own1 = gd.lo_cnt + gd.own_cnt;
+                const PubRange pb{buf(k, 0, g, par), buf(k, 1, g, par), own0, own0 + gd.pre_cnt,
+                                  own1 - gd.suf_cnt, own1};
+                if (gd.r.cache >= 0)
+                    run_cached<true>(cache + gd.r.cache, gd.r, rl, d.round_first, xw, ww, a.omega, pb);
+                else
+                    run_phase<true>(global_src(a), gd.r, rl, d.round_first, xw, ww, a.omega, pb);
+                __builtin_amdgcn_s_waitcnt(0);
             }
             __syncthreads();
             if (!comp) {
-                // wave 0: publish the first pre_cnt own rows to k-1 and the last
-                // suf_cnt to k+1, raise the flag, wait for the neighbours' and
-                // receive k-1's suffix before the own rows and k+1's prefix
-                // after them (every pair of neighbours meets at the first group
-                // of a sweep)
-                const bool sync = g == 0;
-                const bool send = sync | (gd.pre_cnt > 0) | (gd.suf_cnt > 0);
+                // wave 0: the published values are stored and complete (every
+                // computing wave waited for its stores before the barrier):
+                // raise the flag, wait for the neighbours' and receive k-1's
+                // suffix before the own rows and k+1's prefix after them
+                // (every pair of neighbours meets at the first group of a sweep)
                 if (send) {
-                    double* plo = buf(k, 0, g, par);
-                    double* phi = buf(k, 1, g, par);
-                    comm_publish(plo, ww + gd.lo_cnt, gd.pre_cnt, t);
-                    comm_publish(phi, ww + gd.lo_cnt + gd.own_cnt - gd.suf_cnt, gd.suf_cnt, t);
-                    __builtin_amdgcn_s_waitcnt(0);      // the whole wave's stores are done
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // and stay before the flag
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // the flag stays after the barrier
                     if (t == 0)
                         __hip_atomic_store(a.flags + (int64_t)k * kFlagStride, step, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -413,15 +426,15 @@ __global__ __launch_bounds__(kSlabThreads) void k_slab_sweeps(SlabArgs a, int64_
             } else {
                 // the other waves: the columns whose rows are all own rows,
                 // which need no neighbour
-                if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega);
-                else run_phase<false>(global_src(a), gd.s, rl, d.round_first, ww, xw, a.omega);
+                if (gd.s.cache >= 0) run_cached<false>(cache + gd.s.cache, gd.s, rl, d.round_first, ww, xw, a.omega, PubRange{});
+                else run_phase<false>(global_src(a), gd.s, rl, d.round_first, ww, xw, a.omega, PubRange{});
             }
             __syncthreads();
             if (bail) return;
             // phase S over the window columns with halo rows
             if (comp) {
-                if (gd.sb.cache >= 0) run_cached<false>(cache + gd.sb.cache, gd.sb, rl, d.round_first, ww, xw, a.omega);
-                else run_phase<false>(global_src(a), gd.sb, rl, d.round_first, ww, xw, a.omega);
+                if (gd.sb.cache >= 0) run_cached<false>(cache + gd.sb.cache, gd.sb, rl, d.round_first, ww, xw, a.omega, PubRange{});
+                else run_phase<false>(global_src(a), gd.sb, rl, d.round_first, ww, xw, a.omega, PubRange{});
             }
             __syncthreads();
         }
