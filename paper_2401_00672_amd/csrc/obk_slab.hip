@@ -13,9 +13,10 @@
 // A group step is
 //   phase R  w_i = (f_i - sum_c a_ic x_c) / ||a_i||^2 for the own rows of g,
 //            x_c read from the LDS window (ascending column order);
-//   exchange the own rows' w that a neighbour needs are published to it,
-//            and the neighbours' w are received (one flag per slab, raised
-//            at each step that publishes);
+//   exchange the own rows' w that a neighbour needs are published to it
+//            (stored by phase R itself), and the neighbours' w are
+//            received (one flag per slab, raised at each step that
+//            publishes);
 //   phase S  x_c = x_c + sum_i w_i a_ic (ascending row order) for every
 //            column of H_k that g touches: own columns, and halo columns,
 //            which the owning neighbour updates identically, so the window
@@ -58,9 +59,9 @@ namespace obk {
 namespace {
 
 constexpr int kSlabThreads = 512;
-// Wave 0 of a workgroup runs the neighbour exchange (publish, wait,
-// receive) while the other waves sweep the interior columns; those waves run
-// every phase.
+// Wave 0 of a workgroup runs the neighbour exchange (flag, wait, receive)
+// while the other waves sweep the interior columns; those waves run every
+// phase, and phase R publishes the rows the neighbours need.
 constexpr int kCommThreads = 64, kCompThreads = kSlabThreads - kCommThreads;
 constexpr int kQR = 5, kKPR = 6;                     // phase R: rows per thread per round, entries per pass
 constexpr int kQS = 9, kKPS = 4;                     // phase S: columns per thread per round, entries per pass
